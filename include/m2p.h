@@ -1,0 +1,214 @@
+/*
+ * m2p.h -- C ABI of the MI355X (gfx950) two-phase shallow-flow step.
+ *
+ * The library advances the depth-integrated grain-fluid model of MoSES_2PDF
+ * (Ko, Chen, Wong, Tai; model equations in the paper's Appendix A, numerics in
+ * Sect. 2.2) on a DEM grid: minmod-limited reconstruction, central
+ * (Kurganov-Tadmor) fluxes, topography / Coulomb-friction / fluid-friction /
+ * buoyancy / viscous / interphase-drag sources, Mode-I release and Mode-II
+ * inflow boundaries (Sect. 3.1.2, Stage 0), the two-step modified Euler
+ * (Heun) time integrator and a CFL-limited global time step (Sect. 2.2).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns int: 0 = M2P_OK, < 0 = an M2P_E* code.  No C++
+ *    exception crosses the ABI.  m2p_last_error() gives a thread-local text.
+ *  - Units at the ABI are SI (m, s, m/s, kg/m^3, degrees).  The library
+ *    rescales internally (X, Y, b ~ L; h ~ H; v ~ sqrt(g L); t ~ sqrt(L/g)).
+ *  - Host arrays are row-major [ny][nx] (y outer), cell-centred: cell (i, j)
+ *    sits at X = (i + 1/2) dx, Y = (j + 1/2) dy.  They are copied at call
+ *    time and never retained.
+ *  - All device work is enqueued on the HIP stream given at creation (NULL =
+ *    the default stream).  Calls that return host data synchronize that stream.
+ *  - After a device-side error (non-finite value, dt floor) a context is
+ *    poisoned: only m2p_get_*, m2p_get_diag and m2p_destroy are allowed.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef M2P_H
+#define M2P_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define M2P_OK 0
+#define M2P_EINVAL -1      /* bad sizes or values (phi outside [0,1], delta_b outside [0,90), cfl outside (0,1], non-finite DEM, ...) */
+#define M2P_ENOMEM -2      /* device allocation failed */
+#define M2P_EHIP -3        /* a HIP runtime call failed (text in m2p_last_error) */
+#define M2P_ENONFINITE -4  /* the device saw a NaN or Inf in the state or in dt */
+#define M2P_ENEGDEPTH -5   /* reserved: negative thickness handed in */
+#define M2P_EDTFLOOR -6    /* the CFL time step fell below 1e-12 of the grid's gravity-wave time */
+#define M2P_EMAXSTEPS -7   /* m2p_run_to stopped at max_steps before t_end */
+#define M2P_ESTATE -8      /* call order (step before set_state, poisoned context, ...) */
+
+/* arithmetic of the state: FP64, or FP32 state with FP64 time, dt and volume sums */
+#define M2P_FP64 0
+#define M2P_FP32 1
+
+/* boundary mode per side (Sect. 3.1.2: the paper's default is non-reflecting) */
+#define M2P_BC_TRANSMISSIVE 0 /* zero-gradient copy of the edge cell */
+#define M2P_BC_WALL 1         /* mirror, normal momentum of both phases negated */
+
+/* sides, in the order of m2p_params.bc */
+#define M2P_SIDE_W 0
+#define M2P_SIDE_E 1
+#define M2P_SIDE_S 2
+#define M2P_SIDE_N 3
+
+/* m2p_params.flags */
+#define M2P_F_FLUID_PRESSURE_AS_PRINTED 1 /* weight the fluid interphase pressure by phi^f as printed */
+
+/* thickness convention of m2p_set_state */
+#define M2P_DEPTH_NORMAL 0   /* h measured normal to the bed (the paper's h, Sect. 2.1) */
+#define M2P_DEPTH_VERTICAL 1 /* vertical thickness */
+
+/* kernel variants (m2p_set_variant) */
+#define M2P_VARIANT_AUTO 0
+#define M2P_VARIANT_REFERENCE 1 /* one thread per cell, every stencil value from memory */
+#define M2P_VARIANT_TILED 2     /* fused LDS-free column-marching stage kernel */
+
+typedef struct m2p_ctx m2p_ctx;
+
+typedef struct {
+    int32_t nx, ny; /* cells; both >= 4 */
+    double dx, dy;  /* cell size (m) */
+} m2p_grid;
+
+/* Material and numerical parameters (Sect. 3.1.2, Stage 1; Table 1). */
+typedef struct {
+    double delta_b_deg;   /* basal friction angle delta_b, [0, 90) */
+    double c_d;           /* interphase drag coefficient C_d */
+    double inv_n_r;       /* 1 / N_R; 0 switches fluid friction and viscosity off */
+    double theta_b;       /* fluid basal friction coefficient */
+    double rho_s, rho_f;  /* densities; alpha_rho = rho_f / rho_s */
+    double delta_int_deg; /* internal friction angle: recorded, unused by the model */
+    double cfl;           /* CFL number, (0, 1]; the paper uses 0.1 */
+    double L, H;          /* length and thickness scales (m); aspect ratio eps = H / L */
+    double chi;           /* exponent of eps on the centripetal term of the basal pressure */
+    double g;             /* gravity (m/s^2) */
+    double m_dry;         /* desingularisation thickness (m) for velocities and fractions */
+    double a_min;         /* floor of the CFL wave speed (m/s) */
+    int32_t bc[4];        /* M2P_BC_* for W, E, S, N */
+    int32_t flags;        /* M2P_F_* */
+} m2p_params;
+
+/* One Mode-II inflow segment (Sect. 3.1.2, Stage 0; Sect. 4.2): ncells
+ * boundary cells from index i0 along ``side`` receive a prescribed face flux
+ * from a piecewise-linear hydrograph of discharge Q (m^3/s) and solid
+ * fraction over time t (s), nt >= 1 samples, t increasing. */
+typedef struct {
+    int32_t side, i0, ncells, nt;
+    const double *t, *Q, *phi_s;
+} m2p_inflow;
+
+typedef struct {
+    double t;            /* model time (s) */
+    double dt_last;      /* last step (s) */
+    double dt_next;      /* step the next m2p_step will take (s) */
+    double mass_s, mass_f; /* volume of each phase (m^3), FP64 sums */
+    double in_s, in_f;   /* inflow volumes accumulated (m^3) */
+    double out_s, out_f; /* outflow volumes accumulated through non-inflow boundary faces (m^3) */
+    int64_t steps;       /* steps taken */
+    int64_t clamp_count; /* positivity clamps (tentative negative thickness) */
+    int32_t status;      /* device status bits: 1 non-finite, 2 dt floor */
+    int32_t pad;
+} m2p_diag;
+
+/* Version string. */
+const char *m2p_version(void);
+
+/* Text for a status code; thread-local detail of the last failure. */
+const char *m2p_strerror(int code);
+const char *m2p_last_error(void);
+
+/* Number of visible HIP devices (0 when none), without creating a context. */
+int m2p_device_count(int *count);
+
+/* Create a context on the current HIP device: copies the DEM (metres, ny*nx,
+ * host) and optionally a per-cell friction field tan_mu (tan(delta_b) per
+ * cell, ny*nx, host; NULL = uniform delta_b).  prec is M2P_FP64 or M2P_FP32.
+ * hip_stream is a hipStream_t (NULL = default stream).  The context owns all
+ * device memory unless m2p_bind_buffers is used.  Errors: EINVAL, ENOMEM, EHIP. */
+int m2p_create(m2p_ctx **out, const m2p_grid *g, const m2p_params *p, int32_t prec,
+               const double *dem_host, const double *tan_mu_host, void *hip_stream);
+
+/* Destroy; frees what the context owns (never caller-bound buffers). */
+void m2p_destroy(m2p_ctx *c);
+
+/* Bytes of each of the two state buffers (6 fields, row pitch rounded up to
+ * 64 elements) for a grid and precision. */
+int m2p_buffer_bytes(const m2p_grid *g, int32_t prec, size_t *state_bytes);
+
+/* Optional: use caller-owned device buffers (for example torch tensors) as
+ * the two state buffers, each at least m2p_buffer_bytes long and 256-byte
+ * aligned.  Must precede m2p_set_state; the buffers must outlive the context. */
+int m2p_bind_buffers(m2p_ctx *c, void *state_a, void *state_b, size_t bytes);
+
+/* Mode-I release or any state from SI host fields (ny*nx each): thickness h
+ * (depth_kind M2P_DEPTH_NORMAL or M2P_DEPTH_VERTICAL), solid fraction in
+ * [0, 1], horizontal velocities of solid and fluid (NULL = 0).  Resets nothing
+ * else (time, integrals and step count persist).  Errors: EINVAL, EHIP. */
+int m2p_set_state(m2p_ctx *c, int32_t depth_kind, const double *h, const double *phi_s,
+                  const double *vxs, const double *vys, const double *vxf, const double *vyf);
+
+/* Raw conserved state, dimensionless, host FP64 [6][ny][nx]:
+ * (m^s, p^s_X, p^s_Y, m^f, p^f_X, p^f_Y) with m = J_b h (the paper's
+ * J_b h^s, J_b h^f and the momenta q^s, q^f).  get synchronizes. */
+int m2p_set_state_raw(m2p_ctx *c, const double *U);
+int m2p_get_state_raw(m2p_ctx *c, double *U);
+
+/* Model time (s). */
+int m2p_set_time(m2p_ctx *c, double t);
+
+/* Mode-II inflow segments (replaces earlier ones); at most 8; arrays copied. */
+int m2p_set_inflow(m2p_ctx *c, const m2p_inflow *seg, int32_t nseg);
+
+/* Select the stage-kernel variant (M2P_VARIANT_*); results are identical in
+ * FP64.  Tile rows per workgroup for the tiled variant (0 = default). */
+int m2p_set_variant(m2p_ctx *c, int32_t variant, int32_t tile_rows);
+
+/* One time step, enqueued.  If dt_out is not NULL the stream is synchronized
+ * and the step taken (s) is returned (0 once t reached the run_to end time). */
+int m2p_step(m2p_ctx *c, double *dt_out);
+
+/* Enqueue nsteps steps without any host synchronization. */
+int m2p_run(m2p_ctx *c, int64_t nsteps);
+
+/* Advance until t >= t_end (the last step is shortened to land on t_end) or
+ * max_steps steps, checking the device status between chunks.  Returns
+ * M2P_EMAXSTEPS if t_end was not reached. */
+int m2p_run_to(m2p_ctx *c, double t_end, int64_t max_steps, int64_t *steps_done);
+
+/* Output fields of the paper (Sect. 3.1.2, Stage 3), SI, host, ny*nx each,
+ * NULL skips: bed-normal thickness h, solid fraction, v_X, v_Y of the solid
+ * and of the fluid.  Synchronizes. */
+int m2p_get_fields(m2p_ctx *c, double *h, double *phi_s, double *vxs, double *vys, double *vxf,
+                   double *vyf);
+
+/* Diagnostics (FP64 volume sums computed on demand).  Synchronizes. */
+int m2p_get_diag(m2p_ctx *c, m2p_diag *d);
+
+/* Wait for all work of the context. */
+int m2p_synchronize(m2p_ctx *c);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * each kernel of every step while on != 0 (adds one event record per kernel). */
+int m2p_set_profiling(m2p_ctx *c, int32_t on);
+
+/* Synchronize, then return the summed durations (ms) of the stage-1, stage-2
+ * and finalize kernels of the steps timed since the last call, and their
+ * number; resets the sums. */
+int m2p_kernel_times(m2p_ctx *c, double *ms3, int64_t *nsteps);
+
+/* Device pointer of the current state buffer and its row pitch (elements);
+ * field k starts at ptr + k * ny * pitch. */
+int m2p_state_device_ptr(m2p_ctx *c, void **ptr, int64_t *pitch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* M2P_H */

@@ -1,0 +1,721 @@
+// m2p_abi.hip -- the C ABI (include/m2p.h): argument validation, device
+// memory, the padded DEM, scalar state on the device, and the step / run
+// drivers that enqueue the per-precision kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/m2p.h"
+#include "m2p_launch.h"
+
+using namespace m2p;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return M2P_EHIP;
+}
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #x); \
+    } while (0)
+
+size_t round_up(size_t a, size_t m) { return (a + m - 1) / m * m; }
+
+}  // namespace
+
+struct m2p_ctx {
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    int prec = M2P_FP64;
+    size_t esz = 8;
+    m2p_grid g{};
+    m2p_params p{};
+    KParams kp{};
+    Bufs B{};
+    bool own_state = true;
+    bool has_state = false;
+    bool dirty = true;
+    bool poisoned = false;
+    int variant = M2P_VARIANT_AUTO;
+    int rows = 0;
+    size_t state_bytes = 0;
+    void* b = nullptr;
+    void* mu = nullptr;
+    DevScalars* S = nullptr;
+    double* bpart = nullptr;
+    double* tables = nullptr;
+    double* mass_part = nullptr;
+    double* staging = nullptr;  // FP64 field staging [7][ny][nx]
+    double t_end = std::numeric_limits<double>::infinity();
+    // per-kernel HIP-event timing (m2p_set_profiling)
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    double prof_ms[3] = {0, 0, 0};
+    int64_t prof_n = 0;
+};
+
+static hipError_t step_part(m2p_ctx* c, int part)
+{
+    if (c->prec == M2P_FP64) return Launch<double>::step_part(c->kp, c->B, c->stream, c->variant, c->rows, part);
+    return Launch<float>::step_part(c->kp, c->B, c->stream, c->variant, c->rows, part);
+}
+
+static hipError_t do_step(m2p_ctx* c)
+{
+    if (!c->prof) {
+        for (int part = 0; part < 3; part++) {
+            hipError_t e = step_part(c, part);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    while (c->ev.size() < c->ev_used + 4) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        c->ev.push_back(e);
+    }
+    hipEvent_t* e = &c->ev[c->ev_used];
+    c->ev_used += 4;
+    hipError_t r = hipEventRecord(e[0], c->stream);
+    for (int part = 0; part < 3 && r == hipSuccess; part++) {
+        r = step_part(c, part);
+        if (r == hipSuccess) r = hipEventRecord(e[part + 1], c->stream);
+    }
+    return r;
+}
+
+static hipError_t do_init(m2p_ctx* c)
+{
+    if (c->prec == M2P_FP64) return Launch<double>::init(c->kp, c->B, c->stream);
+    return Launch<float>::init(c->kp, c->B, c->stream);
+}
+
+static void refresh_grid(m2p_ctx* c)
+{
+    int nbx, nby;
+    if (c->prec == M2P_FP64)
+        Launch<double>::grid_dims(c->kp, c->variant, c->rows, nbx, nby);
+    else
+        Launch<float>::grid_dims(c->kp, c->variant, c->rows, nbx, nby);
+    c->B.nbx = nbx;
+    c->B.nby = nby;
+}
+
+static int ensure_ready(m2p_ctx* c)
+{
+    if (c->poisoned) return fail(M2P_ESTATE, "context poisoned by an earlier device error");
+    if (!c->has_state) return fail(M2P_ESTATE, "no state: call m2p_set_state first");
+    if (c->dirty) {
+        double tend = c->t_end / c->kp.T;
+        HIPCHK(hipMemcpyAsync(&c->S->t_end, &tend, sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(do_init(c));
+        c->dirty = false;
+    }
+    return M2P_OK;
+}
+
+static int check_status(m2p_ctx* c, const DevScalars& hs)
+{
+    if (hs.status & 1u) {
+        c->poisoned = true;
+        return fail(M2P_ENONFINITE, "non-finite value in the state or in dt");
+    }
+    if (hs.status & 2u) {
+        c->poisoned = true;
+        return fail(M2P_EDTFLOOR, "CFL time step below the floor");
+    }
+    return M2P_OK;
+}
+
+static int read_scalars(m2p_ctx* c, DevScalars* hs)
+{
+    HIPCHK(hipMemcpyAsync(hs, c->S, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return M2P_OK;
+}
+
+extern "C" {
+
+const char* m2p_version(void) { return "m2p 0.1 (gfx950)"; }
+
+const char* m2p_strerror(int code)
+{
+    switch (code) {
+        case M2P_OK: return "ok";
+        case M2P_EINVAL: return "invalid argument";
+        case M2P_ENOMEM: return "out of device memory";
+        case M2P_EHIP: return "HIP runtime error";
+        case M2P_ENONFINITE: return "non-finite value on the device";
+        case M2P_ENEGDEPTH: return "negative thickness";
+        case M2P_EDTFLOOR: return "time step below floor";
+        case M2P_EMAXSTEPS: return "maximum number of steps reached";
+        case M2P_ESTATE: return "invalid call order or poisoned context";
+        default: return "unknown status";
+    }
+}
+
+const char* m2p_last_error(void) { return g_err.c_str(); }
+
+int m2p_device_count(int* count)
+{
+    if (!count) return fail(M2P_EINVAL, "count is NULL");
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    *count = e == hipSuccess ? n : 0;
+    return M2P_OK;
+}
+
+int m2p_buffer_bytes(const m2p_grid* g, int32_t prec, size_t* state_bytes)
+{
+    if (!g || !state_bytes) return fail(M2P_EINVAL, "NULL argument");
+    if (g->nx < 4 || g->ny < 4) return fail(M2P_EINVAL, "grid must be at least 4 x 4");
+    if (prec != M2P_FP64 && prec != M2P_FP32) return fail(M2P_EINVAL, "precision must be M2P_FP64 or M2P_FP32");
+    size_t esz = prec == M2P_FP64 ? 8 : 4;
+    *state_bytes = (size_t)NF * (size_t)g->ny * round_up((size_t)g->nx, 64) * esz;
+    return M2P_OK;
+}
+
+static int validate(const m2p_grid* g, const m2p_params* p, int32_t prec, const double* dem)
+{
+    if (!g || !p || !dem) return fail(M2P_EINVAL, "NULL argument");
+    if (g->nx < 4 || g->ny < 4) return fail(M2P_EINVAL, "grid must be at least 4 x 4");
+    if ((int64_t)g->nx * (int64_t)g->ny > (int64_t)1 << 31) return fail(M2P_EINVAL, "grid too large");
+    if (!(g->dx > 0) || !(g->dy > 0) || !std::isfinite(g->dx) || !std::isfinite(g->dy))
+        return fail(M2P_EINVAL, "dx, dy must be positive");
+    if (prec != M2P_FP64 && prec != M2P_FP32) return fail(M2P_EINVAL, "precision must be M2P_FP64 or M2P_FP32");
+    if (!(p->delta_b_deg >= 0.0 && p->delta_b_deg < 90.0)) return fail(M2P_EINVAL, "delta_b outside [0, 90)");
+    if (!(p->cfl > 0.0 && p->cfl <= 1.0)) return fail(M2P_EINVAL, "cfl outside (0, 1]");
+    if (!(p->rho_s > 0.0) || !(p->rho_f >= 0.0) || !(p->rho_f < p->rho_s))
+        return fail(M2P_EINVAL, "densities must satisfy 0 <= rho_f < rho_s");
+    if (!(p->L > 0.0) || !(p->H > 0.0) || !(p->g > 0.0)) return fail(M2P_EINVAL, "L, H, g must be positive");
+    if (!(p->c_d >= 0.0) || !(p->inv_n_r >= 0.0) || !(p->theta_b >= 0.0) || !(p->m_dry > 0.0) ||
+        !(p->a_min > 0.0) || !std::isfinite(p->chi))
+        return fail(M2P_EINVAL, "c_d, 1/N_R, theta_b >= 0 and m_dry, a_min > 0 required");
+    for (int s = 0; s < 4; s++)
+        if (p->bc[s] != M2P_BC_TRANSMISSIVE && p->bc[s] != M2P_BC_WALL) return fail(M2P_EINVAL, "bad boundary mode");
+    size_t n = (size_t)g->nx * g->ny;
+    for (size_t k = 0; k < n; k++)
+        if (!std::isfinite(dem[k])) return fail(M2P_EINVAL, "non-finite DEM value");
+    return M2P_OK;
+}
+
+int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t prec, const double* dem,
+               const double* tan_mu, void* hip_stream)
+{
+    if (!out) return fail(M2P_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(g, p, prec, dem);
+    if (rc) return rc;
+    const size_t n = (size_t)g->nx * g->ny;
+    if (tan_mu)
+        for (size_t k = 0; k < n; k++)
+            if (!(tan_mu[k] >= 0.0) || !std::isfinite(tan_mu[k])) return fail(M2P_EINVAL, "bad tan_mu value");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(M2P_EHIP, "no HIP device");
+    m2p_ctx* c = new m2p_ctx();
+    HIPCHK(hipGetDevice(&c->dev));
+    c->stream = (hipStream_t)hip_stream;
+    c->prec = prec;
+    c->esz = prec == M2P_FP64 ? 8 : 4;
+    c->g = *g;
+    c->p = *p;
+    KParams& K = c->kp;
+    std::memset(&K, 0, sizeof(K));
+    K.nx = g->nx;
+    K.ny = g->ny;
+    K.pitch = (int)round_up((size_t)g->nx, 64);
+    K.bpitch = (int)(BOFF + round_up((size_t)g->nx + BHALO, 64));
+    for (int s = 0; s < 4; s++) K.bc[s] = p->bc[s];
+    K.flags = p->flags;
+    K.has_mu = tan_mu ? 1 : 0;
+    K.visc = p->inv_n_r != 0.0 ? 1 : 0;
+    K.eps = p->H / p->L;
+    K.alpha = p->rho_f / p->rho_s;
+    K.one_m_alpha = 1.0 - K.alpha;
+    K.dxi = g->dx / p->L;
+    K.deta = g->dy / p->L;
+    K.two_dxi = 2.0 * K.dxi;
+    K.two_deta = 2.0 * K.deta;
+    K.md = p->m_dry / p->H;
+    K.eps_chi = std::pow(K.eps, p->chi);
+    K.tan_d = std::tan(p->delta_b_deg * M_PI / 180.0);
+    K.c_d = p->c_d;
+    K.inv_n_r = p->inv_n_r;
+    K.theta_b = p->theta_b;
+    K.T = std::sqrt(p->L / p->g);
+    K.V = std::sqrt(p->g * p->L);
+    K.H = p->H;
+    K.L = p->L;
+    K.dx = g->dx;
+    K.dy = g->dy;
+    K.cfl = p->cfl;
+    K.a_floor = p->a_min / K.V;
+    K.dt_floor = 1e-12 * std::min(K.dxi, K.deta) / std::sqrt(K.eps);
+
+    // padded DEM (b / L), linear extrapolation: along Y per column, then along X per row
+    const int nx = g->nx, ny = g->ny, bp = K.bpitch;
+    std::vector<double> bd((size_t)(ny + 2 * BHALO) * bp, 0.0);
+    auto B = [&](int i, int j) -> double& { return bd[(size_t)(j + BHALO) * bp + BOFF + i]; };
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) B(i, j) = dem[(size_t)j * nx + i] / p->L;
+    for (int i = 0; i < nx; i++) {
+        double b0 = B(i, 0), b1 = B(i, 1), bn = B(i, ny - 1), bm = B(i, ny - 2);
+        for (int k = 1; k <= BHALO; k++) {
+            B(i, -k) = b0 + (double)(-k) * (b1 - b0);
+            B(i, ny - 1 + k) = bn + (double)k * (bn - bm);
+        }
+    }
+    for (int j = -BHALO; j < ny + BHALO; j++) {
+        double b0 = B(0, j), b1 = B(1, j), bn = B(nx - 1, j), bm = B(nx - 2, j);
+        for (int k = 1; k <= BHALO; k++) {
+            B(-k, j) = b0 + (double)(-k) * (b1 - b0);
+            B(nx - 1 + k, j) = bn + (double)k * (bn - bm);
+        }
+    }
+    auto cleanup = [&](int code) {
+        m2p_destroy(c);
+        return code;
+    };
+    size_t bbytes = bd.size() * c->esz;
+    if (hipMalloc(&c->b, bbytes) != hipSuccess) return cleanup(fail(M2P_ENOMEM, "DEM allocation failed"));
+    if (c->prec == M2P_FP64) {
+        if (hipMemcpy(c->b, bd.data(), bbytes, hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(M2P_EHIP, "DEM copy failed"));
+    } else {
+        std::vector<float> bf(bd.begin(), bd.end());
+        if (hipMemcpy(c->b, bf.data(), bbytes, hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(M2P_EHIP, "DEM copy failed"));
+    }
+    if (tan_mu) {
+        size_t mb = (size_t)ny * K.pitch * c->esz;
+        if (hipMalloc(&c->mu, mb) != hipSuccess) return cleanup(fail(M2P_ENOMEM, "friction field allocation failed"));
+        std::vector<double> md((size_t)ny * K.pitch, 0.0);
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) md[(size_t)j * K.pitch + i] = tan_mu[(size_t)j * nx + i];
+        hipError_t e;
+        if (c->prec == M2P_FP64)
+            e = hipMemcpy(c->mu, md.data(), mb, hipMemcpyHostToDevice);
+        else {
+            std::vector<float> mf(md.begin(), md.end());
+            e = hipMemcpy(c->mu, mf.data(), mb, hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) return cleanup(fail(M2P_EHIP, "friction field copy failed"));
+    }
+    if (hipMalloc(&c->S, sizeof(DevScalars)) != hipSuccess) return cleanup(fail(M2P_ENOMEM, "scalar allocation failed"));
+    DevScalars hs;
+    std::memset(&hs, 0, sizeof(hs));
+    hs.t_end = std::numeric_limits<double>::infinity();
+    if (hipMemcpy(c->S, &hs, sizeof(hs), hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(M2P_EHIP, "scalar init failed"));
+    refresh_grid(c);
+    // boundary partials sized for the smallest tile shape any variant uses
+    int nmax = std::max((nx + 63) / 64, (ny + 3) / 4) + 1;
+    c->B.nmax = nmax;
+    if (hipMalloc(&c->bpart, sizeof(double) * 2 * 4 * 2 * (size_t)nmax) != hipSuccess)
+        return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
+    hipMemset(c->bpart, 0, sizeof(double) * 2 * 4 * 2 * (size_t)nmax);
+    if (hipMalloc(&c->mass_part, sizeof(double) * 2 * kMassBlocks) != hipSuccess)
+        return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
+    if (hipMalloc(&c->staging, sizeof(double) * 7 * n) != hipSuccess)
+        return cleanup(fail(M2P_ENOMEM, "staging allocation failed"));
+    if (hipMalloc(&c->tables, sizeof(double) * 8) != hipSuccess)
+        return cleanup(fail(M2P_ENOMEM, "table allocation failed"));
+    m2p_buffer_bytes(g, prec, &c->state_bytes);
+    c->B.b = c->b;
+    c->B.mu = c->mu;
+    c->B.S = c->S;
+    c->B.bpart = c->bpart;
+    c->B.tables = c->tables;
+    c->B.mass_part = c->mass_part;
+    *out = c;
+    return M2P_OK;
+}
+
+void m2p_destroy(m2p_ctx* c)
+{
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    if (c->own_state) {
+        if (c->B.U) hipFree(c->B.U);
+        if (c->B.Us) hipFree(c->B.Us);
+    }
+    if (c->b) hipFree(c->b);
+    if (c->mu) hipFree(c->mu);
+    if (c->S) hipFree(c->S);
+    if (c->bpart) hipFree(c->bpart);
+    if (c->tables) hipFree(c->tables);
+    if (c->mass_part) hipFree(c->mass_part);
+    if (c->staging) hipFree(c->staging);
+    for (hipEvent_t e : c->ev) hipEventDestroy(e);
+    delete c;
+}
+
+int m2p_bind_buffers(m2p_ctx* c, void* a, void* b, size_t bytes)
+{
+    if (!c || !a || !b) return fail(M2P_EINVAL, "NULL argument");
+    if (c->B.U) return fail(M2P_ESTATE, "buffers already set");
+    if (bytes < c->state_bytes) return fail(M2P_EINVAL, "buffers too small");
+    if (((uintptr_t)a & 255) || ((uintptr_t)b & 255)) return fail(M2P_EINVAL, "buffers must be 256-byte aligned");
+    c->B.U = a;
+    c->B.Us = b;
+    c->own_state = false;
+    HIPCHK(hipMemsetAsync(a, 0, c->state_bytes, c->stream));
+    HIPCHK(hipMemsetAsync(b, 0, c->state_bytes, c->stream));
+    return M2P_OK;
+}
+
+static int ensure_state_buffers(m2p_ctx* c)
+{
+    if (c->B.U) return M2P_OK;
+    if (hipMalloc(&c->B.U, c->state_bytes) != hipSuccess) return fail(M2P_ENOMEM, "state allocation failed");
+    if (hipMalloc(&c->B.Us, c->state_bytes) != hipSuccess) return fail(M2P_ENOMEM, "state allocation failed");
+    c->own_state = true;
+    HIPCHK(hipMemsetAsync(c->B.U, 0, c->state_bytes, c->stream));
+    HIPCHK(hipMemsetAsync(c->B.Us, 0, c->state_bytes, c->stream));
+    return M2P_OK;
+}
+
+int m2p_set_state(m2p_ctx* c, int32_t kind, const double* h, const double* phi, const double* vxs, const double* vys,
+                  const double* vxf, const double* vyf)
+{
+    if (!c || !h || !phi) return fail(M2P_EINVAL, "NULL argument");
+    if (c->poisoned) return fail(M2P_ESTATE, "context poisoned");
+    if (kind != M2P_DEPTH_NORMAL && kind != M2P_DEPTH_VERTICAL) return fail(M2P_EINVAL, "bad depth kind");
+    const size_t n = (size_t)c->g.nx * c->g.ny;
+    for (size_t k = 0; k < n; k++) {
+        if (!(h[k] >= 0.0) || !std::isfinite(h[k])) return fail(M2P_EINVAL, "thickness must be finite and >= 0");
+        if (!(phi[k] >= 0.0 && phi[k] <= 1.0)) return fail(M2P_EINVAL, "solid fraction outside [0, 1]");
+    }
+    const double* v[4] = {vxs, vys, vxf, vyf};
+    for (int q = 0; q < 4; q++)
+        if (v[q])
+            for (size_t k = 0; k < n; k++)
+                if (!std::isfinite(v[q][k])) return fail(M2P_EINVAL, "non-finite velocity");
+    int rc = ensure_state_buffers(c);
+    if (rc) return rc;
+    std::vector<double> f(6 * n, 0.0);
+    std::memcpy(f.data(), h, n * sizeof(double));
+    std::memcpy(f.data() + n, phi, n * sizeof(double));
+    int has_v = 0;
+    for (int q = 0; q < 4; q++)
+        if (v[q]) {
+            std::memcpy(f.data() + (2 + q) * n, v[q], n * sizeof(double));
+            has_v = 1;
+        }
+    HIPCHK(hipMemcpyAsync(c->staging, f.data(), 6 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (c->prec == M2P_FP64) {
+        HIPCHK(Launch<double>::set_state(c->kp, c->B, c->staging, kind == M2P_DEPTH_VERTICAL, has_v, c->stream));
+    } else {
+        HIPCHK(Launch<float>::set_state(c->kp, c->B, c->staging, kind == M2P_DEPTH_VERTICAL, has_v, c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->has_state = true;
+    c->dirty = true;
+    return M2P_OK;
+}
+
+int m2p_set_state_raw(m2p_ctx* c, const double* U)
+{
+    if (!c || !U) return fail(M2P_EINVAL, "NULL argument");
+    if (c->poisoned) return fail(M2P_ESTATE, "context poisoned");
+    int rc = ensure_state_buffers(c);
+    if (rc) return rc;
+    const int nx = c->g.nx, ny = c->g.ny, pitch = c->kp.pitch;
+    const size_t n = (size_t)nx * ny;
+    for (size_t k = 0; k < NF * n; k++)
+        if (!std::isfinite(U[k])) return fail(M2P_EINVAL, "non-finite state value");
+    if (c->prec == M2P_FP64) {
+        std::vector<double> h((size_t)NF * ny * pitch, 0.0);
+        for (int k = 0; k < NF; k++)
+            for (int j = 0; j < ny; j++)
+                std::memcpy(&h[((size_t)k * ny + j) * pitch], &U[k * n + (size_t)j * nx], nx * sizeof(double));
+        HIPCHK(hipMemcpy(c->B.U, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> h((size_t)NF * ny * pitch, 0.0f);
+        for (int k = 0; k < NF; k++)
+            for (int j = 0; j < ny; j++)
+                for (int i = 0; i < nx; i++) h[((size_t)k * ny + j) * pitch + i] = (float)U[k * n + (size_t)j * nx + i];
+        HIPCHK(hipMemcpy(c->B.U, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    c->has_state = true;
+    c->dirty = true;
+    return M2P_OK;
+}
+
+int m2p_get_state_raw(m2p_ctx* c, double* U)
+{
+    if (!c || !U) return fail(M2P_EINVAL, "NULL argument");
+    if (!c->has_state) return fail(M2P_ESTATE, "no state");
+    const int nx = c->g.nx, ny = c->g.ny, pitch = c->kp.pitch;
+    const size_t n = (size_t)nx * ny;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->prec == M2P_FP64) {
+        std::vector<double> h((size_t)NF * ny * pitch);
+        HIPCHK(hipMemcpy(h.data(), c->B.U, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int k = 0; k < NF; k++)
+            for (int j = 0; j < ny; j++)
+                std::memcpy(&U[k * n + (size_t)j * nx], &h[((size_t)k * ny + j) * pitch], nx * sizeof(double));
+    } else {
+        std::vector<float> h((size_t)NF * ny * pitch);
+        HIPCHK(hipMemcpy(h.data(), c->B.U, h.size() * sizeof(float), hipMemcpyDeviceToHost));
+        for (int k = 0; k < NF; k++)
+            for (int j = 0; j < ny; j++)
+                for (int i = 0; i < nx; i++) U[k * n + (size_t)j * nx + i] = h[((size_t)k * ny + j) * pitch + i];
+    }
+    return M2P_OK;
+}
+
+int m2p_set_time(m2p_ctx* c, double t)
+{
+    if (!c || !std::isfinite(t)) return fail(M2P_EINVAL, "bad argument");
+    double tn = t / c->kp.T;
+    HIPCHK(hipMemcpyAsync(&c->S->t, &tn, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->dirty = true;
+    return M2P_OK;
+}
+
+int m2p_set_inflow(m2p_ctx* c, const m2p_inflow* seg, int32_t nseg)
+{
+    if (!c || (nseg > 0 && !seg)) return fail(M2P_EINVAL, "NULL argument");
+    if (nseg < 0 || nseg > MAX_SEG) return fail(M2P_EINVAL, "0..8 inflow segments supported");
+    std::vector<double> tab;
+    KParams& K = c->kp;
+    for (int s = 0; s < nseg; s++) {
+        const m2p_inflow& q = seg[s];
+        int len = q.side < 2 ? c->g.ny : c->g.nx;
+        if (q.side < 0 || q.side > 3 || q.ncells < 1 || q.i0 < 0 || q.i0 + q.ncells > len || q.nt < 1 || !q.t ||
+            !q.Q || !q.phi_s)
+            return fail(M2P_EINVAL, "bad inflow segment");
+        for (int k = 0; k < q.nt; k++) {
+            if (!std::isfinite(q.t[k]) || !(q.Q[k] >= 0.0) || !(q.phi_s[k] >= 0.0 && q.phi_s[k] <= 1.0))
+                return fail(M2P_EINVAL, "bad hydrograph sample");
+            if (k > 0 && !(q.t[k] > q.t[k - 1])) return fail(M2P_EINVAL, "hydrograph times must increase");
+        }
+        K.seg[s].side = q.side;
+        K.seg[s].i0 = q.i0;
+        K.seg[s].ncells = q.ncells;
+        K.seg[s].nt = q.nt;
+        K.seg[s].toff = (int)tab.size();
+        tab.insert(tab.end(), q.t, q.t + q.nt);
+        tab.insert(tab.end(), q.Q, q.Q + q.nt);
+        tab.insert(tab.end(), q.phi_s, q.phi_s + q.nt);
+    }
+    K.nseg = nseg;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->tables) hipFree(c->tables);
+    c->tables = nullptr;
+    size_t nb = std::max<size_t>(tab.size(), 8) * sizeof(double);
+    if (hipMalloc(&c->tables, nb) != hipSuccess) return fail(M2P_ENOMEM, "table allocation failed");
+    if (!tab.empty()) HIPCHK(hipMemcpy(c->tables, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->B.tables = c->tables;
+    c->dirty = true;
+    return M2P_OK;
+}
+
+int m2p_set_variant(m2p_ctx* c, int32_t variant, int32_t rows)
+{
+    if (!c) return fail(M2P_EINVAL, "NULL context");
+    if (variant < M2P_VARIANT_AUTO || variant > M2P_VARIANT_TILED) return fail(M2P_EINVAL, "unknown variant");
+    if (rows < 0 || rows > 4096) return fail(M2P_EINVAL, "tile rows out of range");
+    c->variant = variant;
+    c->rows = rows;
+    refresh_grid(c);
+    if (std::max(c->B.nbx, c->B.nby) > c->B.nmax) return fail(M2P_EINVAL, "tile shape too small for this grid");
+    return M2P_OK;
+}
+
+int m2p_step(m2p_ctx* c, double* dt_out)
+{
+    if (!c) return fail(M2P_EINVAL, "NULL context");
+    int rc = ensure_ready(c);
+    if (rc) return rc;
+    if (!dt_out) {
+        HIPCHK(do_step(c));
+        return M2P_OK;
+    }
+    DevScalars hs;
+    rc = read_scalars(c, &hs);
+    if (rc) return rc;
+    const double dt = hs.dt;
+    HIPCHK(do_step(c));
+    rc = read_scalars(c, &hs);
+    if (rc) return rc;
+    rc = check_status(c, hs);
+    if (rc) return rc;
+    *dt_out = dt * c->kp.T;
+    return M2P_OK;
+}
+
+int m2p_run(m2p_ctx* c, int64_t nsteps)
+{
+    if (!c || nsteps < 0) return fail(M2P_EINVAL, "bad argument");
+    int rc = ensure_ready(c);
+    if (rc) return rc;
+    for (int64_t k = 0; k < nsteps; k++) HIPCHK(do_step(c));
+    return M2P_OK;
+}
+
+int m2p_run_to(m2p_ctx* c, double t_end, int64_t max_steps, int64_t* steps_done)
+{
+    if (!c || !std::isfinite(t_end) || max_steps < 0) return fail(M2P_EINVAL, "bad argument");
+    if (steps_done) *steps_done = 0;
+    c->t_end = t_end;
+    c->dirty = true;
+    int rc = ensure_ready(c);
+    if (rc) return rc;
+    DevScalars hs;
+    rc = read_scalars(c, &hs);
+    if (rc) return rc;
+    const long long s0 = hs.steps;
+    const double tn_end = t_end / c->kp.T;
+    int64_t issued = 0, chunk = 8;
+    rc = M2P_OK;
+    while (hs.t < tn_end) {
+        if (issued >= max_steps) {
+            rc = fail(M2P_EMAXSTEPS, "max_steps reached before t_end");
+            break;
+        }
+        int64_t k = std::min<int64_t>(chunk, max_steps - issued);
+        for (int64_t q = 0; q < k; q++) HIPCHK(do_step(c));
+        issued += k;
+        chunk = std::min<int64_t>(chunk * 2, 1024);
+        rc = read_scalars(c, &hs);
+        if (rc) break;
+        rc = check_status(c, hs);
+        if (rc) break;
+        if (hs.dt == 0.0 && hs.t < tn_end) {
+            rc = fail(M2P_EDTFLOOR, "zero time step before t_end");
+            c->poisoned = true;
+            break;
+        }
+    }
+    if (steps_done) *steps_done = hs.steps - s0;
+    c->t_end = std::numeric_limits<double>::infinity();
+    c->dirty = true;
+    return rc;
+}
+
+int m2p_get_fields(m2p_ctx* c, double* h, double* phi, double* vxs, double* vys, double* vxf, double* vyf)
+{
+    if (!c) return fail(M2P_EINVAL, "NULL context");
+    if (!c->has_state) return fail(M2P_ESTATE, "no state");
+    const size_t n = (size_t)c->g.nx * c->g.ny;
+    if (c->prec == M2P_FP64) {
+        HIPCHK(Launch<double>::get_fields(c->kp, c->B, c->staging, c->stream));
+    } else {
+        HIPCHK(Launch<float>::get_fields(c->kp, c->B, c->staging, c->stream));
+    }
+    std::vector<double> f(6 * n);
+    HIPCHK(hipMemcpyAsync(f.data(), c->staging, 6 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    double* o[6] = {h, phi, vxs, vys, vxf, vyf};
+    for (int q = 0; q < 6; q++)
+        if (o[q]) std::memcpy(o[q], f.data() + q * n, n * sizeof(double));
+    return M2P_OK;
+}
+
+int m2p_get_diag(m2p_ctx* c, m2p_diag* d)
+{
+    if (!c || !d) return fail(M2P_EINVAL, "NULL argument");
+    std::memset(d, 0, sizeof(*d));
+    DevScalars hs;
+    int rc = read_scalars(c, &hs);
+    if (rc) return rc;
+    if (c->has_state) {
+        if (c->prec == M2P_FP64) {
+            HIPCHK(Launch<double>::mass(c->kp, c->B, c->stream));
+        } else {
+            HIPCHK(Launch<float>::mass(c->kp, c->B, c->stream));
+        }
+        std::vector<double> part(2 * kMassBlocks);
+        HIPCHK(hipMemcpyAsync(part.data(), c->mass_part, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        double ms = 0.0, mf = 0.0;
+        for (int q = 0; q < kMassBlocks; q++) {
+            ms += part[2 * q];
+            mf += part[2 * q + 1];
+        }
+        const KParams& K = c->kp;
+        double scale = K.H * K.L * K.L * K.dxi * K.deta;
+        d->mass_s = ms * scale;
+        d->mass_f = mf * scale;
+    }
+    d->t = hs.t * c->kp.T;
+    d->dt_last = hs.dt_last * c->kp.T;
+    d->dt_next = hs.dt * c->kp.T;
+    d->in_s = hs.in_s;
+    d->in_f = hs.in_f;
+    d->out_s = hs.out_s;
+    d->out_f = hs.out_f;
+    d->steps = hs.steps;
+    d->clamp_count = (int64_t)hs.clamps;
+    d->status = (int32_t)hs.status;
+    return M2P_OK;
+}
+
+int m2p_synchronize(m2p_ctx* c)
+{
+    if (!c) return fail(M2P_EINVAL, "NULL context");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return M2P_OK;
+}
+
+int m2p_set_profiling(m2p_ctx* c, int32_t on)
+{
+    if (!c) return fail(M2P_EINVAL, "NULL context");
+    c->prof = on != 0;
+    return M2P_OK;
+}
+
+int m2p_kernel_times(m2p_ctx* c, double* ms, int64_t* nsteps)
+{
+    if (!c || !ms || !nsteps) return fail(M2P_EINVAL, "NULL argument");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t g = 0; g + 4 <= c->ev_used; g += 4) {
+        for (int part = 0; part < 3; part++) {
+            float t = 0.0f;
+            HIPCHK(hipEventElapsedTime(&t, c->ev[g + part], c->ev[g + part + 1]));
+            c->prof_ms[part] += t;
+        }
+        c->prof_n++;
+    }
+    c->ev_used = 0;
+    for (int part = 0; part < 3; part++) ms[part] = c->prof_ms[part];
+    *nsteps = c->prof_n;
+    c->prof_ms[0] = c->prof_ms[1] = c->prof_ms[2] = 0.0;
+    c->prof_n = 0;
+    return M2P_OK;
+}
+
+int m2p_state_device_ptr(m2p_ctx* c, void** ptr, int64_t* pitch)
+{
+    if (!c || !ptr || !pitch) return fail(M2P_EINVAL, "NULL argument");
+    *ptr = c->B.U;
+    *pitch = c->kp.pitch;
+    return M2P_OK;
+}
+
+}  // extern "C"

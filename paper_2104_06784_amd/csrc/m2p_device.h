@@ -1,0 +1,371 @@
+// m2p_device.h -- device arithmetic of one forward-Euler stage of the
+// two-phase depth-integrated shallow-flow model (Appendix A of the paper)
+// with the central scheme of Sect. 2.2.  Templated on the state type T
+// (float or double).  The FP64 build is compiled without FMA contraction and
+// follows the evaluation order written here exactly; the FP32 build lets the
+// compiler contract and use fast reciprocals.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace m2p {
+
+constexpr int NF = 6;        // m^s, p^s_X, p^s_Y, m^f, p^f_X, p^f_Y
+constexpr int MAX_SEG = 8;   // Mode-II inflow segments
+constexpr int BOFF = 64;     // column offset of cell 0 in the padded DEM rows
+constexpr int BHALO = 2;     // ghost rows / columns of the padded DEM
+
+struct SegDesc {
+    int side, i0, ncells, nt, toff;
+};
+
+// Constants of a scenario, all dimensionless.  Passed by value to kernels.
+struct KParams {
+    int nx, ny, pitch, bpitch;
+    int bc[4];
+    int flags, has_mu, nseg, visc;
+    double dxi, deta, two_dxi, two_deta;
+    double eps, alpha, one_m_alpha, md, eps_chi, tan_d;
+    double c_d, inv_n_r, theta_b;
+    double T, V, H, L, dx, dy, cfl, a_floor, dt_floor;
+    SegDesc seg[MAX_SEG];
+};
+
+// Scalars that live on the device across steps (time, dt, reductions).
+struct DevScalars {
+    double t, dt, dt_last, t_end;
+    double in_s, in_f, out_s, out_f;
+    unsigned long long amax_bits[2];  // max speed (xi, eta) of the state, as double bits
+    long long steps;
+    unsigned long long clamps;
+    unsigned int status;
+    unsigned int pad;
+    double inflow[2][MAX_SEG][4];      // per stage: q, m_in, v_in, phi
+};
+
+template <typename T>
+struct Geo {
+    T bX, bY, J, c, nX, nY, nZ, A11, A12, A21, A22;
+};
+
+template <typename T>
+__device__ __forceinline__ T minmod(T a, T b)
+{
+    if (a > T(0) && b > T(0)) return a < b ? a : b;
+    if (a < T(0) && b < T(0)) return a > b ? a : b;
+    return T(0);
+}
+
+// Continuous desingularisation of num / den (Kurganov-Petrova 2007):
+// 2 den num / (den^2 + max(den^2, md^2)).
+template <typename T>
+__device__ __forceinline__ T dsg(T num, T den, T md)
+{
+    T d2 = den * den;
+    T m2 = md * md;
+    return (T(2) * den * num) / (d2 + (d2 > m2 ? d2 : m2));
+}
+
+// Basal geometry from the four DEM neighbours (b / L): tangents
+// (1, 0, b_X), (0, 1, b_Y), unit normal (-b_X, -b_Y, 1)/s, J_b = s, c = n_Z,
+// A = inverse surface metric.
+template <typename T>
+__device__ __forceinline__ Geo<T> geometry(T bE, T bW, T bN, T bS, T two_dxi, T two_deta)
+{
+    Geo<T> g;
+    T bX = (bE - bW) / two_dxi;
+    T bY = (bN - bS) / two_deta;
+    T s = sqrt(T(1) + bX * bX + bY * bY);
+    g.bX = bX;
+    g.bY = bY;
+    g.J = s;
+    g.c = T(1) / s;
+    g.nX = -bX / s;
+    g.nY = -bY / s;
+    g.nZ = T(1) / s;
+    g.A11 = (T(1) + bY * bY) / (s * s);
+    g.A12 = -bX * bY / (s * s);
+    g.A21 = g.A12;
+    g.A22 = (T(1) + bX * bX) / (s * s);
+    return g;
+}
+
+template <typename T>
+struct Consts {
+    T eps, al, oma, md, eps_chi, tan_d, c_d, inv_n_r, theta_b;
+    T dxi, deta, two_dxi, two_deta;
+    __device__ explicit Consts(const KParams& P)
+        : eps(T(P.eps)), al(T(P.alpha)), oma(T(P.one_m_alpha)), md(T(P.md)), eps_chi(T(P.eps_chi)),
+          tan_d(T(P.tan_d)), c_d(T(P.c_d)), inv_n_r(T(P.inv_n_r)), theta_b(T(P.theta_b)),
+          dxi(T(P.dxi)), deta(T(P.deta)), two_dxi(T(P.two_dxi)), two_deta(T(P.two_deta)) {}
+};
+
+// Physical flux of one reconstructed side of a face (flux vectors F, G of
+// Appendix A with the owner cell's geometry), the conserved values entering
+// the numerical diffusion and the phase speeds |v_n| + sqrt(dP/dm).
+template <typename T>
+__device__ __forceinline__ void side_flux(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d,
+                                          T F[NF], T qv[NF], T a[2])
+{
+    T ms = u[0], mf = u[3];
+    T hs = ms / g.J, hf = mf / g.J, h = hs + hf;
+    T vXs = dsg(u[1], ms, K.md), vYs = dsg(u[2], ms, K.md);
+    T vXf = dsg(u[4], mf, K.md), vYf = dsg(u[5], mf, K.md);
+    T Ns = g.c * (T(1) - K.al) * hs / T(2);
+    T pf = g.c * h / T(2);
+    T Ax = d == 0 ? g.A11 : g.A21;
+    T Ay = d == 0 ? g.A12 : g.A22;
+    T Ann = d == 0 ? g.A11 : g.A22;
+    T vns = d == 0 ? vXs : vYs;
+    T vnf = d == 0 ? vXf : vYf;
+    F[0] = ms * vns;
+    F[1] = ms * vXs * vns + K.eps * g.J * h * Ax * Ns;
+    F[2] = ms * vYs * vns + K.eps * g.J * h * Ay * Ns;
+    F[3] = mf * vnf;
+    F[4] = mf * vXf * vnf + K.eps * g.J * h * Ax * pf;
+    F[5] = mf * vYf * vnf + K.eps * g.J * h * Ay * pf;
+    qv[0] = ms;
+    qv[1] = ms * vXs;
+    qv[2] = ms * vYs;
+    qv[3] = mf;
+    qv[4] = mf * vXf;
+    qv[5] = mf * vYf;
+    T cs = K.eps * Ann * g.c * (T(1) - K.al) * (h + hs) / T(2);
+    T cf = K.eps * Ann * g.c * h;
+    a[0] = fabs(vns) + sqrt(cs > T(0) ? cs : T(0));
+    a[1] = fabs(vnf) + sqrt(cf > T(0) ? cf : T(0));
+}
+
+// Phase speeds only (identical arithmetic to side_flux).
+template <typename T>
+__device__ __forceinline__ void side_speed(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d, T a[2])
+{
+    T ms = u[0], mf = u[3];
+    T hs = ms / g.J, hf = mf / g.J, h = hs + hf;
+    T vns = d == 0 ? dsg(u[1], ms, K.md) : dsg(u[2], ms, K.md);
+    T vnf = d == 0 ? dsg(u[4], mf, K.md) : dsg(u[5], mf, K.md);
+    T Ann = d == 0 ? g.A11 : g.A22;
+    T cs = K.eps * Ann * g.c * (T(1) - K.al) * (h + hs) / T(2);
+    T cf = K.eps * Ann * g.c * h;
+    a[0] = fabs(vns) + sqrt(cs > T(0) ? cs : T(0));
+    a[1] = fabs(vnf) + sqrt(cf > T(0) ? cf : T(0));
+}
+
+// Central (Kurganov-Tadmor) flux per phase: (F- + F+)/2 - a/2 (U+ - U-).
+template <typename T>
+__device__ __forceinline__ void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
+                                             const T uR[NF], const Geo<T>& gR, int d, T H[NF])
+{
+    T FL[NF], FR[NF], qL[NF], qR[NF], aL[2], aR[2];
+    side_flux(K, uL, gL, d, FL, qL, aL);
+    side_flux(K, uR, gR, d, FR, qR, aR);
+#pragma unroll
+    for (int ph = 0; ph < 2; ph++) {
+        T a = aL[ph] > aR[ph] ? aL[ph] : aR[ph];
+#pragma unroll
+        for (int k = 3 * ph; k < 3 * ph + 3; k++) H[k] = T(0.5) * (FL[k] + FR[k]) - T(0.5) * a * (qR[k] - qL[k]);
+    }
+}
+
+// Prescribed Mode-II face flux from the critical-depth inflow state
+// (q, m_in, v_in, phi); sgn = +1 on W/S (inward +X/+Y), -1 on E/N.
+template <typename T>
+__device__ __forceinline__ void inflow_flux(const Consts<T>& K, const Geo<T>& g, int d, int sgn, T q, T m_in,
+                                            T v_in, T phi, T H[NF])
+{
+    T h = m_in / g.J, hs = phi * m_in / g.J;
+    T Ns = g.c * (T(1) - K.al) * hs / T(2), pf = g.c * h / T(2);
+    T Ax = d == 0 ? g.A11 : g.A21, Ay = d == 0 ? g.A12 : g.A22;
+    T qs = phi * q, qf = (T(1) - phi) * q;
+    H[0] = T(sgn) * qs;
+    H[3] = T(sgn) * qf;
+    H[1] = K.eps * g.J * h * Ax * Ns + (d == 0 ? qs * v_in : T(0));
+    H[2] = K.eps * g.J * h * Ay * Ns + (d == 1 ? qs * v_in : T(0));
+    H[4] = K.eps * g.J * h * Ax * pf + (d == 0 ? qf * v_in : T(0));
+    H[5] = K.eps * g.J * h * Ay * pf + (d == 1 ? qf * v_in : T(0));
+}
+
+// Viscous flux pieces at one face: J_b h and A_ij averaged over the two
+// cells; normal derivative by the neighbour difference, tangential
+// derivative as the mean of the two cells' central differences.
+// x-face: returns FX = 2 Jh (A11 u_x + A21 u_y), FY = Jh (A12 u_x + A22 u_y + A11 w_x + A21 w_y).
+template <typename T>
+__device__ __forceinline__ void visc_xface(T u0, T w0, T u1, T w1, T un0, T wn0, T us0, T ws0, T un1, T wn1, T us1,
+                                           T ws1, T Jh0, T Jh1, const Geo<T>& ga, const Geo<T>& gb, T dxi, T deta,
+                                           T& FX, T& FY)
+{
+    T dxu = (u1 - u0) / dxi, dxw = (w1 - w0) / dxi;
+    T dyu = T(0.5) * ((un0 - us0) / (T(2) * deta) + (un1 - us1) / (T(2) * deta));
+    T dyw = T(0.5) * ((wn0 - ws0) / (T(2) * deta) + (wn1 - ws1) / (T(2) * deta));
+    T Jh = T(0.5) * (Jh0 + Jh1);
+    T A11 = T(0.5) * (ga.A11 + gb.A11), A12 = T(0.5) * (ga.A12 + gb.A12);
+    T A21 = T(0.5) * (ga.A21 + gb.A21), A22 = T(0.5) * (ga.A22 + gb.A22);
+    FX = T(2) * Jh * (A11 * dxu + A21 * dyu);
+    FY = Jh * (A12 * dxu + A22 * dyu + A11 * dxw + A21 * dyw);
+}
+
+// y-face: GX = Jh (A12 u_x + A22 u_y + A11 w_x + A21 w_y), GY = 2 Jh (A12 w_x + A22 w_y).
+template <typename T>
+__device__ __forceinline__ void visc_yface(T u0, T w0, T u1, T w1, T ue0, T we0, T uw0, T ww0, T ue1, T we1, T uw1,
+                                           T ww1, T Jh0, T Jh1, const Geo<T>& ga, const Geo<T>& gb, T dxi, T deta,
+                                           T& GX, T& GY)
+{
+    T dyu = (u1 - u0) / deta, dyw = (w1 - w0) / deta;
+    T dxu = T(0.5) * ((ue0 - uw0) / (T(2) * dxi) + (ue1 - uw1) / (T(2) * dxi));
+    T dxw = T(0.5) * ((we0 - ww0) / (T(2) * dxi) + (we1 - ww1) / (T(2) * dxi));
+    T Jh = T(0.5) * (Jh0 + Jh1);
+    T A11 = T(0.5) * (ga.A11 + gb.A11), A12 = T(0.5) * (ga.A12 + gb.A12);
+    T A21 = T(0.5) * (ga.A21 + gb.A21), A22 = T(0.5) * (ga.A22 + gb.A22);
+    GX = Jh * (A12 * dxu + A22 * dyu + A11 * dxw + A21 * dyw);
+    GY = T(2) * Jh * (A12 * dxw + A22 * dyw);
+}
+
+// J_b h pbar^f with pbar^f = c h / 2.
+template <typename T>
+__device__ __forceinline__ T fluid_G(T ms, T mf, const Geo<T>& g)
+{
+    T h = (ms + mf) / g.J;
+    return g.J * h * (g.c * h / T(2));
+}
+
+// Source terms at a cell from the stage-input state, except the viscous term
+// and the Coulomb friction (applied as a clamp after the update).
+// dn: dn/dxi (3) then dn/deta (3).  dGx, dGy: central differences of fluid_G.
+// Out: S[ph][a] accumulated in the order s_n, s_f, s_v, s_d (fluid only);
+// kappa_s for the friction clamp; phif for the viscous prefactor.
+template <typename T>
+struct Src {
+    T sn[2][2], sf[2][2], sv[2][2], sd[2];
+    T kappa_s, phif;
+};
+
+template <typename T>
+__device__ __forceinline__ void sources(const Consts<T>& K, int flags, const T u[NF], const Geo<T>& g,
+                                        const T dn[6], T dGx, T dGy, Src<T>& S)
+{
+    T ms = u[0], mf = u[3];
+    T hs = ms / g.J, hf = mf / g.J, h = hs + hf;
+    T mt = ms + mf;
+    T phis = dsg(ms, mt, K.md), phif = dsg(mf, mt, K.md);
+    T v[2][3];
+    v[0][0] = dsg(u[1], ms, K.md);
+    v[0][1] = dsg(u[2], ms, K.md);
+    v[1][0] = dsg(u[4], mf, K.md);
+    v[1][1] = dsg(u[5], mf, K.md);
+#pragma unroll
+    for (int ph = 0; ph < 2; ph++) v[ph][2] = g.bX * v[ph][0] + g.bY * v[ph][1];
+    T kap[2];
+#pragma unroll
+    for (int ph = 0; ph < 2; ph++) {
+        T k = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; a++) k += v[ph][a] * dn[a] * v[ph][0];
+#pragma unroll
+        for (int a = 0; a < 3; a++) k += v[ph][a] * dn[3 + a] * v[ph][1];
+        kap[ph] = k;
+    }
+    T pbs = hs * (g.c * (T(1) - K.al) - K.eps_chi * kap[0]);
+    T pbf = hf * (g.c - K.eps_chi * kap[1]);
+    if (pbs < T(0)) pbs = T(0);
+    if (pbf < T(0)) pbf = T(0);
+    S.sn[0][0] = g.J * pbs * g.nX;
+    S.sn[0][1] = g.J * pbs * g.nY;
+    S.sn[1][0] = g.J * pbf * g.nX;
+    S.sn[1][1] = g.J * pbf * g.nY;
+    T gx = g.A11 * dGx + g.A21 * dGy;
+    T gy = g.A12 * dGx + g.A22 * dGy;
+    S.sf[0][0] = -K.eps * K.al * phis * gx;
+    S.sf[0][1] = -K.eps * K.al * phis * gy;
+    T wf = (flags & 1) ? phif : phis;
+    S.sf[1][0] = K.eps * wf * gx;
+    S.sf[1][1] = K.eps * wf * gy;
+    T Kd = g.J * K.c_d * phis * phif * h;
+    S.sv[0][0] = K.al * Kd * (v[1][0] - v[0][0]);
+    S.sv[0][1] = K.al * Kd * (v[1][1] - v[0][1]);
+    S.sv[1][0] = -Kd * (v[1][0] - v[0][0]);
+    S.sv[1][1] = -Kd * (v[1][1] - v[0][1]);
+    T fr = g.J * phif * h * K.theta_b * K.inv_n_r / K.eps;
+    S.sd[0] = -fr * v[1][0];
+    S.sd[1] = -fr * v[1][1];
+    S.kappa_s = kap[0];
+    S.phif = phif;
+}
+
+// Forward-Euler update of one cell with the face fluxes and sources, then the
+// Coulomb stop-clamp of the solid and positivity.  Returns the number of
+// positivity clamps (tentative negative thickness).
+template <typename T>
+__device__ __forceinline__ int update_cell(const Consts<T>& K, const T u[NF], const Geo<T>& g, const T HXl[NF],
+                                           const T HXr[NF], const T HYb[NF], const T HYt[NF], const Src<T>& S,
+                                           T svx, T svy, T dt, T tmu, T out[NF])
+{
+#pragma unroll
+    for (int k = 0; k < NF; k++) {
+        T dFx = HXr[k] - HXl[k];
+        T dGy = HYt[k] - HYb[k];
+        T r = -dFx / K.dxi - dGy / K.deta;
+        const int ph = k / 3, comp = k % 3;
+        if (comp > 0) {
+            const int a = comp - 1;
+            r += S.sn[ph][a];
+            r += S.sf[ph][a];
+            r += S.sv[ph][a];
+            if (ph == 1) {
+                r += S.sd[a];
+                r += a == 0 ? svx : svy;
+            }
+        }
+        out[k] = u[k] + dt * r;
+    }
+    T hst = out[0] / g.J;
+    T pbt = hst * (g.c * (T(1) - K.al) - K.eps_chi * S.kappa_s);
+    if (pbt < T(0)) pbt = T(0);
+    T F = dt * (g.J * pbt) * tmu;
+    T pX = out[1], pY = out[2];
+    T pZ = g.bX * pX + g.bY * pY;
+    T p3 = sqrt(pX * pX + pY * pY + pZ * pZ);
+    if (p3 <= F) {
+        out[1] = T(0);
+        out[2] = T(0);
+    } else {
+        out[1] = pX * (T(1) - F / p3);
+        out[2] = pY * (T(1) - F / p3);
+    }
+    int clamps = 0;
+#pragma unroll
+    for (int ph = 0; ph < 2; ph++)
+        if (out[3 * ph] <= T(0)) {
+            if (out[3 * ph] < T(0)) clamps++;
+            out[3 * ph] = T(0);
+            out[3 * ph + 1] = T(0);
+            out[3 * ph + 2] = T(0);
+        }
+    return clamps;
+}
+
+// Ghost-cell index map (transmissive: copy the edge cell; wall: mirror with
+// the normal momentum negated).
+__device__ __forceinline__ int map_index(int i, int n, int bc_lo, int bc_hi, int& flip)
+{
+    if (i < 0) {
+        if (bc_lo == 1) {
+            flip ^= 1;
+            return -1 - i;
+        }
+        return 0;
+    }
+    if (i >= n) {
+        if (bc_hi == 1) {
+            flip ^= 1;
+            return 2 * n - 1 - i;
+        }
+        return n - 1;
+    }
+    return i;
+}
+
+// Order-preserving bits of a non-negative double.
+__device__ __forceinline__ unsigned long long speed_bits(double a) { return (unsigned long long)__double_as_longlong(a); }
+
+}  // namespace m2p

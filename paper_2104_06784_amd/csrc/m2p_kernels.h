@@ -1,0 +1,515 @@
+// m2p_kernels.h -- HIP kernels of the step: stage kernels (forward-Euler
+// stage of Sect. 2.2's scheme, fused reconstruction + fluxes + sources +
+// update), the per-step finalize (time, CFL dt, boundary integrals, inflow
+// states), and state conversion / reduction kernels.  Included once per
+// precision by m2p_f64.hip and m2p_f32.hip.
+#pragma once
+
+#include "m2p_device.h"
+#include "m2p_launch.h"
+
+namespace m2p {
+
+// ---------------------------------------------------------------- helpers
+
+template <typename T>
+struct View {
+    const KParams& P;
+    const T* U;
+    const T* b;
+    size_t fs;
+    __device__ View(const KParams& P_, const T* U_, const T* b_) : P(P_), U(U_), b(b_), fs((size_t)P_.ny * P_.pitch) {}
+    // state at any (ii, jj) in [-2, n+1] with the boundary rules applied
+    __device__ __forceinline__ void load(int ii, int jj, T u[NF]) const
+    {
+        int fx = 0, fy = 0;
+        int mi = map_index(ii, P.nx, P.bc[0], P.bc[1], fx);
+        int mj = map_index(jj, P.ny, P.bc[2], P.bc[3], fy);
+        size_t c = (size_t)mj * P.pitch + mi;
+#pragma unroll
+        for (int k = 0; k < NF; k++) u[k] = U[k * fs + c];
+        if (fx) {
+            u[1] = -u[1];
+            u[4] = -u[4];
+        }
+        if (fy) {
+            u[2] = -u[2];
+            u[5] = -u[5];
+        }
+    }
+    __device__ __forceinline__ T bv(int ii, int jj) const { return b[(size_t)(jj + BHALO) * P.bpitch + BOFF + ii]; }
+    __device__ __forceinline__ Geo<T> geo(int ii, int jj, const Consts<T>& K) const
+    {
+        return geometry(bv(ii + 1, jj), bv(ii - 1, jj), bv(ii, jj + 1), bv(ii, jj - 1), K.two_dxi, K.two_deta);
+    }
+};
+
+// inflow segment covering boundary index k of a side, or -1
+__device__ __forceinline__ int inflow_seg_at(const KParams& P, int side, int k)
+{
+    for (int s = 0; s < P.nseg; s++)
+        if (P.seg[s].side == side && k >= P.seg[s].i0 && k < P.seg[s].i0 + P.seg[s].ncells) return s;
+    return -1;
+}
+
+template <typename T>
+__device__ __forceinline__ void reconstruct(const T w[4][NF], T uL[NF], T uR[NF])
+{
+    // cells (a-1, a, a+1, a+2) -> face a+1/2
+#pragma unroll
+    for (int k = 0; k < NF; k++) {
+        T wm = w[0][k], w0 = w[1][k], w1 = w[2][k], w2 = w[3][k];
+        T s0 = minmod(w0 - wm, w1 - w0);
+        T s1 = minmod(w1 - w0, w2 - w1);
+        uL[k] = w0 + T(0.5) * s0;
+        uR[k] = w1 - T(0.5) * s1;
+    }
+}
+
+// Deterministic block reduction (fixed tree) of NV doubles; result in lane 0 of thread 0.
+template <int NV, int NT>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh)
+{
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+#pragma unroll
+    for (int q = 0; q < NV; q++) sh[q * NT + tid] = v[q];
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (tid < s)
+#pragma unroll
+            for (int q = 0; q < NV; q++) sh[q * NT + tid] += sh[q * NT + tid + s];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < NV; q++) v[q] = sh[q * NT];
+}
+
+// -------------------------------------------------- reference stage kernel
+
+// One thread per cell; every stencil value is read from memory.  STAGE 1:
+// U* = E(U^n) at t^n.  STAGE 2: U^{n+1} = (U^n + E(U*)) / 2 at t^n + dt,
+// written over U^n (only the cell's own U^n is read), plus the maximum phase
+// speeds of U^{n+1} for the next CFL step.
+template <typename T, int STAGE>
+__global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restrict__ Uin, T* Un, T* Uout,
+                                                   const T* __restrict__ b, const T* __restrict__ mu,
+                                                   DevScalars* __restrict__ S, double* __restrict__ bpart, int nmax)
+{
+    __shared__ double sh[9 * 256];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const Consts<T> K(P);
+    const View<T> V(P, Uin, b);
+    const bool active = i < P.nx && j < P.ny;
+    double red[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // outflow [side][phase], clamps
+    double ax = 0.0, ay = 0.0;
+    int bad = 0;
+    if (active) {
+        const T dt = T(S->dt);
+        T row[5][NF], col[5][NF];
+        for (int q = 0; q < 5; q++) V.load(i - 2 + q, j, row[q]);
+        for (int q = 0; q < 5; q++) V.load(i, j - 2 + q, col[q]);
+        const Geo<T> gC = V.geo(i, j, K), gW = V.geo(i - 1, j, K), gE = V.geo(i + 1, j, K);
+        const Geo<T> gS = V.geo(i, j - 1, K), gN = V.geo(i, j + 1, K);
+        T HXl[NF], HXr[NF], HYb[NF], HYt[NF], uL[NF], uR[NF];
+        {
+            T w[4][NF];
+            for (int q = 0; q < 4; q++)
+                for (int k = 0; k < NF; k++) w[q][k] = row[q][k];
+            reconstruct(w, uL, uR);
+            central_flux(K, uL, gW, uR, gC, 0, HXl);
+            for (int q = 0; q < 4; q++)
+                for (int k = 0; k < NF; k++) w[q][k] = row[q + 1][k];
+            reconstruct(w, uL, uR);
+            central_flux(K, uL, gC, uR, gE, 0, HXr);
+            for (int q = 0; q < 4; q++)
+                for (int k = 0; k < NF; k++) w[q][k] = col[q][k];
+            reconstruct(w, uL, uR);
+            central_flux(K, uL, gS, uR, gC, 1, HYb);
+            for (int q = 0; q < 4; q++)
+                for (int k = 0; k < NF; k++) w[q][k] = col[q + 1][k];
+            reconstruct(w, uL, uR);
+            central_flux(K, uL, gC, uR, gN, 1, HYt);
+        }
+        // Mode-II faces and outflow through the other boundary faces
+        const double (*inf)[4] = S->inflow[STAGE - 1];
+        if (i == 0) {
+            int s = inflow_seg_at(P, 0, j);
+            if (s >= 0)
+                inflow_flux(K, gC, 0, +1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HXl);
+            else {
+                red[0] = -(double)HXl[0] * P.deta;
+                red[1] = -(double)HXl[3] * P.deta;
+            }
+        }
+        if (i == P.nx - 1) {
+            int s = inflow_seg_at(P, 1, j);
+            if (s >= 0)
+                inflow_flux(K, gC, 0, -1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HXr);
+            else {
+                red[2] = (double)HXr[0] * P.deta;
+                red[3] = (double)HXr[3] * P.deta;
+            }
+        }
+        if (j == 0) {
+            int s = inflow_seg_at(P, 2, i);
+            if (s >= 0)
+                inflow_flux(K, gC, 1, +1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HYb);
+            else {
+                red[4] = -(double)HYb[0] * P.dxi;
+                red[5] = -(double)HYb[3] * P.dxi;
+            }
+        }
+        if (j == P.ny - 1) {
+            int s = inflow_seg_at(P, 3, i);
+            if (s >= 0)
+                inflow_flux(K, gC, 1, -1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HYt);
+            else {
+                red[6] = (double)HYt[0] * P.dxi;
+                red[7] = (double)HYt[3] * P.dxi;
+            }
+        }
+        // sources
+        const T* uC = row[2];
+        T dn[6];
+        dn[0] = (gE.nX - gW.nX) / K.two_dxi;
+        dn[1] = (gE.nY - gW.nY) / K.two_dxi;
+        dn[2] = (gE.nZ - gW.nZ) / K.two_dxi;
+        dn[3] = (gN.nX - gS.nX) / K.two_deta;
+        dn[4] = (gN.nY - gS.nY) / K.two_deta;
+        dn[5] = (gN.nZ - gS.nZ) / K.two_deta;
+        T dGx = (fluid_G(row[3][0], row[3][3], gE) - fluid_G(row[1][0], row[1][3], gW)) / K.two_dxi;
+        T dGy = (fluid_G(col[3][0], col[3][3], gN) - fluid_G(col[1][0], col[1][3], gS)) / K.two_deta;
+        Src<T> Sr;
+        sources(K, P.flags, uC, gC, dn, dGx, dGy, Sr);
+        T svx = T(0), svy = T(0);
+        if (P.visc) {
+            T c9[3][3][NF];
+            for (int dj = -1; dj <= 1; dj++)
+                for (int di = -1; di <= 1; di++) V.load(i + di, j + dj, c9[dj + 1][di + 1]);
+            T u9[3][3], w9[3][3];
+            for (int a = 0; a < 3; a++)
+                for (int c = 0; c < 3; c++) {
+                    u9[a][c] = dsg(c9[a][c][4], c9[a][c][3], K.md);
+                    w9[a][c] = dsg(c9[a][c][5], c9[a][c][3], K.md);
+                }
+            T JhC = uC[0] + uC[3];
+            T JhW = row[1][0] + row[1][3], JhE = row[3][0] + row[3][3];
+            T JhS = col[1][0] + col[1][3], JhN = col[3][0] + col[3][3];
+            T FX0, FY0, FX1, FY1, GX0, GY0, GX1, GY1;
+            // x-faces (i-1 | i) and (i | i+1); index [row dj+1][col di+1]
+            visc_xface(u9[1][0], w9[1][0], u9[1][1], w9[1][1], u9[2][0], w9[2][0], u9[0][0], w9[0][0], u9[2][1],
+                       w9[2][1], u9[0][1], w9[0][1], JhW, JhC, gW, gC, K.dxi, K.deta, FX0, FY0);
+            visc_xface(u9[1][1], w9[1][1], u9[1][2], w9[1][2], u9[2][1], w9[2][1], u9[0][1], w9[0][1], u9[2][2],
+                       w9[2][2], u9[0][2], w9[0][2], JhC, JhE, gC, gE, K.dxi, K.deta, FX1, FY1);
+            // y-faces (j-1 | j) and (j | j+1)
+            visc_yface(u9[0][1], w9[0][1], u9[1][1], w9[1][1], u9[0][2], w9[0][2], u9[0][0], w9[0][0], u9[1][2],
+                       w9[1][2], u9[1][0], w9[1][0], JhS, JhC, gS, gC, K.dxi, K.deta, GX0, GY0);
+            visc_yface(u9[1][1], w9[1][1], u9[2][1], w9[2][1], u9[1][2], w9[1][2], u9[1][0], w9[1][0], u9[2][2],
+                       w9[2][2], u9[2][0], w9[2][0], JhC, JhN, gC, gN, K.dxi, K.deta, GX1, GY1);
+            T SvX = (FX1 - FX0) / K.dxi + (GX1 - GX0) / K.deta;
+            T SvY = (FY1 - FY0) / K.dxi + (GY1 - GY0) / K.deta;
+            svx = K.eps * Sr.phif * K.inv_n_r * SvX;
+            svy = K.eps * Sr.phif * K.inv_n_r * SvY;
+        }
+        const size_t c = (size_t)j * P.pitch + i;
+        const size_t fs = (size_t)P.ny * P.pitch;
+        T tmu = P.has_mu ? mu[c] : K.tan_d;
+        T out[NF];
+        red[8] = (double)update_cell(K, uC, gC, HXl, HXr, HYb, HYt, Sr, svx, svy, dt, tmu, out);
+        if (STAGE == 2) {
+#pragma unroll
+            for (int k = 0; k < NF; k++) out[k] = T(0.5) * (Un[k * fs + c] + out[k]);
+            T a[2];
+            side_speed(K, out, gC, 0, a);
+            ax = (double)(a[0] > a[1] ? a[0] : a[1]);
+            side_speed(K, out, gC, 1, a);
+            ay = (double)(a[0] > a[1] ? a[0] : a[1]);
+        }
+#pragma unroll
+        for (int k = 0; k < NF; k++) {
+            if (!isfinite(out[k])) bad = 1;
+            Uout[k * fs + c] = out[k];
+        }
+    }
+    // block reductions (deterministic)
+    block_sum<9, 256>(red, sh);
+    __syncthreads();
+    double mx[2] = {ax, ay};
+    {
+        const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+        sh[tid] = mx[0];
+        sh[256 + tid] = mx[1];
+        sh[512 + tid] = bad;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s) {
+                sh[tid] = fmax(sh[tid], sh[tid + s]);
+                sh[256 + tid] = fmax(sh[256 + tid], sh[256 + tid + s]);
+                sh[512 + tid] = fmax(sh[512 + tid], sh[512 + tid + s]);
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const int st = STAGE - 1;
+            if (blockIdx.x == 0) {
+                bpart[((st * 4 + 0) * nmax + blockIdx.y) * 2 + 0] = red[0];
+                bpart[((st * 4 + 0) * nmax + blockIdx.y) * 2 + 1] = red[1];
+            }
+            if (blockIdx.x == gridDim.x - 1) {
+                bpart[((st * 4 + 1) * nmax + blockIdx.y) * 2 + 0] = red[2];
+                bpart[((st * 4 + 1) * nmax + blockIdx.y) * 2 + 1] = red[3];
+            }
+            if (blockIdx.y == 0) {
+                bpart[((st * 4 + 2) * nmax + blockIdx.x) * 2 + 0] = red[4];
+                bpart[((st * 4 + 2) * nmax + blockIdx.x) * 2 + 1] = red[5];
+            }
+            if (blockIdx.y == gridDim.y - 1) {
+                bpart[((st * 4 + 3) * nmax + blockIdx.x) * 2 + 0] = red[6];
+                bpart[((st * 4 + 3) * nmax + blockIdx.x) * 2 + 1] = red[7];
+            }
+            if (red[8] > 0.0) atomicAdd(&S->clamps, (unsigned long long)red[8]);
+            if (sh[512] > 0.0) atomicOr(&S->status, 1u);
+            if (STAGE == 2) {
+                atomicMax(&S->amax_bits[0], speed_bits(sh[0]));
+                atomicMax(&S->amax_bits[1], speed_bits(sh[256]));
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------- speeds (init)
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_speeds(KParams P, const T* __restrict__ U, const T* __restrict__ b,
+                                                DevScalars* __restrict__ S)
+{
+    __shared__ double sh[512];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const Consts<T> K(P);
+    const View<T> V(P, U, b);
+    double ax = 0.0, ay = 0.0;
+    if (i < P.nx && j < P.ny) {
+        T u[NF], a[2];
+        V.load(i, j, u);
+        Geo<T> g = V.geo(i, j, K);
+        side_speed(K, u, g, 0, a);
+        ax = (double)(a[0] > a[1] ? a[0] : a[1]);
+        side_speed(K, u, g, 1, a);
+        ay = (double)(a[0] > a[1] ? a[0] : a[1]);
+    }
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    sh[tid] = ax;
+    sh[256 + tid] = ay;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            sh[tid] = fmax(sh[tid], sh[tid + s]);
+            sh[256 + tid] = fmax(sh[256 + tid], sh[256 + tid + s]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        atomicMax(&S->amax_bits[0], speed_bits(sh[0]));
+        atomicMax(&S->amax_bits[1], speed_bits(sh[256]));
+    }
+}
+
+// ------------------------------------------------------------- finalize
+
+__device__ __forceinline__ double interp_table(const double* t, const double* y, int n, double tau)
+{
+    if (tau <= t[0]) return y[0];
+    if (tau >= t[n - 1]) return y[n - 1];
+    int k = 0;
+    while (k + 1 < n && t[k + 1] < tau) k++;
+    double w = (tau - t[k]) / (t[k + 1] - t[k]);
+    return y[k] + w * (y[k + 1] - y[k]);
+}
+
+// Critical-depth inflow state of a segment at dimensionless time tau:
+// q (discharge per unit width), m_in = (q^2/eps)^(1/3), v_in = q / m_in, phi.
+__device__ __forceinline__ void inflow_state(const KParams& P, const double* tables, int s, double tau_nd,
+                                             double out[4])
+{
+    const SegDesc& d = P.seg[s];
+    const double* t = tables + d.toff;
+    const double* Q = t + d.nt;
+    const double* ph = Q + d.nt;
+    double tau = tau_nd * P.T;
+    double Qv = interp_table(t, Q, d.nt, tau);
+    double phv = interp_table(t, ph, d.nt, tau);
+    double w = (d.side < 2) ? P.dy : P.dx;
+    double qs = Qv / ((double)d.ncells * w);
+    double qn = qs / (P.H * P.V);
+    double m = cbrt(qn * qn / P.eps);
+    out[0] = qn;
+    out[1] = m;
+    out[2] = m > 0.0 ? qn / m : 0.0;
+    out[3] = phv;
+}
+
+__device__ __forceinline__ double inflow_rate(const KParams& P, const double* tables, double tau, int ph)
+{
+    double acc = 0.0;
+    for (int s = 0; s < P.nseg; s++) {
+        double st[4];
+        inflow_state(P, tables, s, tau, st);
+        double w = (P.seg[s].side < 2) ? P.deta : P.dxi;
+        acc += (ph == 0 ? st[3] * st[0] : (1.0 - st[3]) * st[0]) * (double)P.seg[s].ncells * w;
+    }
+    return acc;
+}
+
+// Single wavefront.  mode 0: close the step just taken (time, integrals);
+// both modes: next CFL dt from the speed maxima, inflow states of the next
+// step's two stages, reset of the maxima.
+template <typename T>
+__global__ void __launch_bounds__(64) k_finalize(KParams P, DevScalars* S, const double* __restrict__ bpart, int nbx,
+                                                 int nby, int nmax, const double* __restrict__ tables, int mode)
+{
+    __shared__ double part[16];
+    const int tid = threadIdx.x;
+    if (mode == 0 && tid < 16) {
+        // tid = (stage * 4 + side) * 2 + phase
+        const int st = tid >> 3, side = (tid >> 1) & 3, ph = tid & 1;
+        const int n = side < 2 ? nby : nbx;
+        const double* p = bpart + ((size_t)(st * 4 + side) * nmax) * 2 + ph;
+        double acc = 0.0;
+        for (int q = 0; q < n; q++) acc += p[2 * q];
+        part[tid] = acc;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    double t = S->t;
+    if (mode == 0) {
+        const double dt = S->dt;
+        const double vs = P.H * P.L * P.L;  // dimensionless volume -> m^3
+        for (int ph = 0; ph < 2; ph++) {
+            double B1 = 0.0, B2 = 0.0;
+            for (int side = 0; side < 4; side++) {
+                B1 += part[(0 * 4 + side) * 2 + ph];
+                B2 += part[(1 * 4 + side) * 2 + ph];
+            }
+            double out = 0.5 * dt * (B1 + B2);
+            double in = 0.5 * dt * (inflow_rate(P, tables, t, ph) + inflow_rate(P, tables, t + dt, ph));
+            if (ph == 0) {
+                S->out_s += out * vs;
+                S->in_s += in * vs;
+            } else {
+                S->out_f += out * vs;
+                S->in_f += in * vs;
+            }
+        }
+        if (dt > 0.0) {
+            t += dt;
+            S->t = t;
+            S->steps += 1;
+            S->dt_last = dt;
+        }
+    }
+    double ax = __longlong_as_double((long long)S->amax_bits[0]);
+    double ay = __longlong_as_double((long long)S->amax_bits[1]);
+    for (int s = 0; s < P.nseg; s++) {
+        double st[4];
+        inflow_state(P, tables, s, t, st);
+        double a = st[2] + sqrt(P.eps * st[1]);
+        if (P.seg[s].side < 2) {
+            if (a > ax) ax = a;
+        } else if (a > ay)
+            ay = a;
+    }
+    ax = ax > P.a_floor ? ax : P.a_floor;
+    ay = ay > P.a_floor ? ay : P.a_floor;
+    double dtx = P.dxi / ax, dty = P.deta / ay;
+    double dt = P.cfl * (dtx < dty ? dtx : dty);
+    if (!isfinite(dt)) S->status |= 1u;
+    if (dt < P.dt_floor) S->status |= 2u;
+    if (S->t_end - t < dt) dt = S->t_end - t;
+    if (dt < 0.0) dt = 0.0;
+    S->dt = dt;
+    for (int s = 0; s < P.nseg; s++) {
+        inflow_state(P, tables, s, t, S->inflow[0][s]);
+        inflow_state(P, tables, s, t + dt, S->inflow[1][s]);
+    }
+    S->amax_bits[0] = 0ull;
+    S->amax_bits[1] = 0ull;
+}
+
+// ------------------------------------------------- conversions, reductions
+
+// SI fields (device FP64 staging, [7][ny][nx]: h, phi, vxs, vys, vxf, vyf,
+// mask of given velocities unused) -> conserved state.
+template <typename T>
+__global__ void k_set_state(KParams P, const double* __restrict__ f, int vertical, int has_v, T* __restrict__ U,
+                            const T* __restrict__ b)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= P.nx || j >= P.ny) return;
+    const size_t n = (size_t)P.nx * P.ny, c = (size_t)j * P.nx + i, o = (size_t)j * P.pitch + i;
+    const size_t fs = (size_t)P.ny * P.pitch;
+    // geometry in FP64 from the FP64 view of the DEM (b may be float)
+    auto bv = [&](int ii, int jj) { return (double)b[(size_t)(jj + BHALO) * P.bpitch + BOFF + ii]; };
+    Geo<double> g = geometry(bv(i + 1, j), bv(i - 1, j), bv(i, j + 1), bv(i, j - 1), P.two_dxi, P.two_deta);
+    double h = f[c], ph = f[n + c];
+    double hv = vertical ? h / P.H : g.J * h / P.H;
+    double ms = ph * hv, mf = (1.0 - ph) * hv;
+    U[0 * fs + o] = T(ms);
+    U[1 * fs + o] = T(has_v ? ms * f[2 * n + c] / P.V : 0.0);
+    U[2 * fs + o] = T(has_v ? ms * f[3 * n + c] / P.V : 0.0);
+    U[3 * fs + o] = T(mf);
+    U[4 * fs + o] = T(has_v ? mf * f[4 * n + c] / P.V : 0.0);
+    U[5 * fs + o] = T(has_v ? mf * f[5 * n + c] / P.V : 0.0);
+}
+
+// conserved state -> SI output fields [6][ny][nx] (h normal, phi_s, velocities)
+template <typename T>
+__global__ void k_get_fields(KParams P, const T* __restrict__ U, const T* __restrict__ b, double* __restrict__ f)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= P.nx || j >= P.ny) return;
+    const size_t n = (size_t)P.nx * P.ny, c = (size_t)j * P.nx + i, o = (size_t)j * P.pitch + i;
+    const size_t fs = (size_t)P.ny * P.pitch;
+    auto bv = [&](int ii, int jj) { return (double)b[(size_t)(jj + BHALO) * P.bpitch + BOFF + ii]; };
+    Geo<double> g = geometry(bv(i + 1, j), bv(i - 1, j), bv(i, j + 1), bv(i, j - 1), P.two_dxi, P.two_deta);
+    double ms = (double)U[o], mf = (double)U[3 * fs + o], mt = ms + mf;
+    f[c] = mt / g.J * P.H;
+    f[n + c] = dsg(ms, mt, P.md);
+    f[2 * n + c] = dsg((double)U[1 * fs + o], ms, P.md) * P.V;
+    f[3 * n + c] = dsg((double)U[2 * fs + o], ms, P.md) * P.V;
+    f[4 * n + c] = dsg((double)U[4 * fs + o], mf, P.md) * P.V;
+    f[5 * n + c] = dsg((double)U[5 * fs + o], mf, P.md) * P.V;
+}
+
+// FP64 per-block partial volume sums (fixed grid, fixed tree => deterministic).
+template <typename T>
+__global__ void __launch_bounds__(256) k_mass(KParams P, const T* __restrict__ U, double* __restrict__ part)
+{
+    __shared__ double sh[2 * 256];
+    const size_t n = (size_t)P.nx * P.ny, fs = (size_t)P.ny * P.pitch;
+    double a[2] = {0.0, 0.0};
+    for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (size_t)gridDim.x * 256) {
+        size_t j = c / P.nx, i = c - j * P.nx, o = j * P.pitch + i;
+        a[0] += (double)U[o];
+        a[1] += (double)U[3 * fs + o];
+    }
+    sh[threadIdx.x] = a[0];
+    sh[256 + threadIdx.x] = a[1];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sh[threadIdx.x] += sh[threadIdx.x + s];
+            sh[256 + threadIdx.x] += sh[256 + threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sh[0];
+        part[2 * blockIdx.x + 1] = sh[256];
+    }
+}
+
+}  // namespace m2p

@@ -1,0 +1,137 @@
+"""Python wrapper of one scenario context (argument marshalling over the C ABI).
+
+``Sim`` owns an ``m2p_ctx``.  PyTorch, when given, supplies only device memory
+(``bind_torch``) and the HIP stream; the step itself runs in ``libm2p.so``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _abi as A
+
+
+def make_params(p) -> A.Params:
+    return A.Params(p.delta_b_deg, p.c_d, p.inv_n_r, p.theta_b, p.rho_s, p.rho_f, p.delta_int_deg, p.cfl,
+                    p.L, p.H, p.chi, p.g, p.m_dry, p.a_min, (C.c_int32 * 4)(*p.bc), p.flags)
+
+
+class Sim:
+    """One scenario on the GPU.
+
+    ``prob`` is an ``inputs.Problem``; ``precision`` "f64" or "f32" (default:
+    the problem's).  ``stream`` is an optional ``torch.cuda.Stream``.
+    """
+
+    FIELDS = ("h", "phi_s", "vxs", "vys", "vxf", "vyf")
+
+    def __init__(self, prob, precision=None, stream=None, params=None, variant=A.M2P_VARIANT_AUTO,
+                 tile_rows=0, set_state=True):
+        L = A.lib()
+        self.prob = prob
+        self.nx, self.ny = prob.nx, prob.ny
+        prec = precision or prob.precision
+        self.prec = A.M2P_FP64 if prec == "f64" else A.M2P_FP32
+        self._grid = A.Grid(prob.nx, prob.ny, prob.dx, prob.dy)
+        self._params = make_params(prob.params if params is None else params)
+        dem = np.ascontiguousarray(prob.dem, dtype=np.float64)
+        mu = None if prob.tan_mu is None else np.ascontiguousarray(prob.tan_mu, dtype=np.float64)
+        sp = None if stream is None else C.c_void_p(stream.cuda_stream)
+        h = C.c_void_p()
+        A.check(L.m2p_create(C.byref(h), C.byref(self._grid), C.byref(self._params), self.prec,
+                             A.dptr(dem), A.dptr(mu), sp), "m2p_create")
+        self._h = h
+        self._keep = []
+        if variant != A.M2P_VARIANT_AUTO or tile_rows:
+            self.set_variant(variant, tile_rows)
+        if set_state:
+            self.set_state(prob.h_vert, prob.phi_s, vertical=True, vel=prob.vel)
+            if prob.inflows:
+                self.set_inflow(prob.inflows)
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            A.lib().m2p_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    # -- set-up
+    def set_variant(self, variant, tile_rows=0):
+        A.check(A.lib().m2p_set_variant(self._h, variant, tile_rows), "m2p_set_variant")
+
+    def set_state(self, h, phi_s, vertical=True, vel=None):
+        a = [np.ascontiguousarray(x, dtype=np.float64) for x in (h, phi_s)]
+        v = [None] * 4 if vel is None else [np.ascontiguousarray(x, dtype=np.float64) for x in vel]
+        kind = A.M2P_DEPTH_VERTICAL if vertical else A.M2P_DEPTH_NORMAL
+        A.check(A.lib().m2p_set_state(self._h, kind, A.dptr(a[0]), A.dptr(a[1]), *[A.dptr(x) for x in v]),
+                "m2p_set_state")
+
+    def set_state_raw(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.shape == (6, self.ny, self.nx)
+        A.check(A.lib().m2p_set_state_raw(self._h, A.dptr(U)), "m2p_set_state_raw")
+
+    def set_time(self, t):
+        A.check(A.lib().m2p_set_time(self._h, float(t)), "m2p_set_time")
+
+    def set_inflow(self, inflows):
+        arr = (A.Inflow * max(1, len(inflows)))()
+        for k, s in enumerate(inflows):
+            t = np.ascontiguousarray(s.t, dtype=np.float64)
+            Q = np.ascontiguousarray(s.Q, dtype=np.float64)
+            ph = np.ascontiguousarray(s.phi_s, dtype=np.float64)
+            self._keep += [t, Q, ph]
+            arr[k] = A.Inflow(s.side, s.i0, s.ncells, len(t), A.dptr(t), A.dptr(Q), A.dptr(ph))
+        A.check(A.lib().m2p_set_inflow(self._h, arr, len(inflows)), "m2p_set_inflow")
+
+    # -- stepping
+    def step(self) -> float:
+        dt = C.c_double()
+        A.check(A.lib().m2p_step(self._h, C.byref(dt)), "m2p_step")
+        return dt.value
+
+    def run(self, nsteps: int):
+        A.check(A.lib().m2p_run(self._h, int(nsteps)), "m2p_run")
+
+    def run_to(self, t_end: float, max_steps: int = 10 ** 9) -> int:
+        n = C.c_int64()
+        A.check(A.lib().m2p_run_to(self._h, float(t_end), int(max_steps), C.byref(n)), "m2p_run_to")
+        return n.value
+
+    def synchronize(self):
+        A.check(A.lib().m2p_synchronize(self._h), "m2p_synchronize")
+
+    # -- results
+    def state(self) -> np.ndarray:
+        U = np.empty((6, self.ny, self.nx), dtype=np.float64)
+        A.check(A.lib().m2p_get_state_raw(self._h, A.dptr(U)), "m2p_get_state_raw")
+        return U
+
+    def fields(self) -> dict:
+        out = {k: np.empty((self.ny, self.nx), dtype=np.float64) for k in self.FIELDS}
+        A.check(A.lib().m2p_get_fields(self._h, *[A.dptr(out[k]) for k in self.FIELDS]), "m2p_get_fields")
+        return out
+
+    def diag(self) -> dict:
+        d = A.Diag()
+        A.check(A.lib().m2p_get_diag(self._h, C.byref(d)), "m2p_get_diag")
+        return {k: getattr(d, k) for k, _ in A.Diag._fields_ if k != "pad"}
+
+    def set_profiling(self, on: bool):
+        A.check(A.lib().m2p_set_profiling(self._h, 1 if on else 0), "m2p_set_profiling")
+
+    def kernel_times(self):
+        """(ms of stage 1, stage 2, finalize summed over the timed steps, steps)."""
+        ms = (C.c_double * 3)()
+        n = C.c_int64()
+        A.check(A.lib().m2p_kernel_times(self._h, ms, C.byref(n)), "m2p_kernel_times")
+        return list(ms), n.value
+
+    def device_ptr(self):
+        p, pitch = C.c_void_p(), C.c_int64()
+        A.check(A.lib().m2p_state_device_ptr(self._h, C.byref(p), C.byref(pitch)), "m2p_state_device_ptr")
+        return p.value, pitch.value
