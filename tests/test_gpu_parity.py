@@ -217,7 +217,8 @@ def test_max_steps_reported():
 def test_full_size_config3_one_step(precision, tol):
     """Config 3 at its full 4096^2 size, the launch configuration the benchmark
     times: after 20 GPU steps, one more GPU step and one oracle step from the
-    same state must agree (FP64: 1e-12; FP32 state: 2e-5 of each field's max)."""
+    same state must agree (FP64: 1e-12; FP32 state: 2e-5 of each field's max,
+    about 20x the FP32 rounding of the flux terms relative to the momenta)."""
     import oracle
     oracle.set_threads(16)
     prob = I.config3()
@@ -228,6 +229,12 @@ def test_full_size_config3_one_step(precision, tol):
     t0 = g.diag()["t"]
     dtg = g.step()
     Ug = g.state()
+    if precision == "f32":
+        # the FP32 path stores b / L in FP32; give the oracle that same terrain so
+        # the comparison measures the kernel's arithmetic, not DEM quantisation
+        import dataclasses
+        L = prob.params.L
+        prob = dataclasses.replace(prob, dem=(prob.dem / L).astype(np.float32).astype(np.float64) * L)
     o = Ora(prob)
     o.set_state_raw(U0)
     o.set_time(t0)
