@@ -56,6 +56,8 @@ struct m2p_ctx {
     bool poisoned = false;
     int variant = M2P_VARIANT_AUTO;
     int rows = 0;
+    Shape shape{};
+    double* wpart = nullptr;
     size_t state_bytes = 0;
     void* b = nullptr;
     void* mu = nullptr;
@@ -75,8 +77,8 @@ struct m2p_ctx {
 
 static hipError_t step_part(m2p_ctx* c, int part)
 {
-    if (c->prec == M2P_FP64) return Launch<double>::step_part(c->kp, c->B, c->stream, c->variant, c->rows, part);
-    return Launch<float>::step_part(c->kp, c->B, c->stream, c->variant, c->rows, part);
+    if (c->prec == M2P_FP64) return Launch<double>::step_part(c->kp, c->B, c->shape, c->stream, part);
+    return Launch<float>::step_part(c->kp, c->B, c->shape, c->stream, part);
 }
 
 static hipError_t do_step(m2p_ctx* c)
@@ -110,16 +112,47 @@ static hipError_t do_init(m2p_ctx* c)
     return Launch<float>::init(c->kp, c->B, c->stream);
 }
 
-static void refresh_grid(m2p_ctx* c)
+namespace m2p {
+
+// Launch shape: the reference variant uses 64 x 4 blocks; the tiled variant
+// one wavefront per (strip of 60 output columns, R rows), R the largest of
+// 64, 32, 16, 8 that still gives >= 2048 wavefronts (8 per CU), unless fixed.
+Shape make_shape(const KParams& P, int variant, int rows)
 {
-    int nbx, nby;
-    if (c->prec == M2P_FP64)
-        Launch<double>::grid_dims(c->kp, c->variant, c->rows, nbx, nby);
-    else
-        Launch<float>::grid_dims(c->kp, c->variant, c->rows, nbx, nby);
-    c->B.nbx = nbx;
-    c->B.nby = nby;
+    Shape s{};
+    s.variant = variant == M2P_VARIANT_REFERENCE ? 1 : 2;
+    s.nbx = (P.nx + 63) / 64;
+    s.nby = (P.ny + 3) / 4;
+    s.nstrips = (P.nx + 59) / 60;
+    int R = rows;
+    if (R <= 0) {
+        R = 8;
+        for (int cand : {64, 32, 16}) {
+            if ((long long)s.nstrips * ((P.ny + cand - 1) / cand) >= 2048) {
+                R = cand;
+                break;
+            }
+        }
+    }
+    s.R = R;
+    s.nrb = (P.ny + R - 1) / R;
+    if (s.variant == 1) {
+        s.n_we = s.nby;
+        s.n_sn = s.nbx;
+        s.nw = s.nbx * s.nby;
+        s.blocks = s.nbx * s.nby;
+    } else {
+        s.n_we = s.nrb;
+        s.n_sn = s.nstrips;
+        s.nw = s.nstrips * s.nrb;
+        s.blocks = (s.nw + 3) / 4;
+    }
+    return s;
 }
+
+}  // namespace m2p
+
+static void refresh_grid(m2p_ctx* c) { c->shape = make_shape(c->kp, c->variant, c->rows); }
 
 static int ensure_ready(m2p_ctx* c)
 {
@@ -328,12 +361,21 @@ int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t pr
     if (hipMemcpy(c->S, &hs, sizeof(hs), hipMemcpyHostToDevice) != hipSuccess)
         return cleanup(fail(M2P_EHIP, "scalar init failed"));
     refresh_grid(c);
-    // boundary partials sized for the smallest tile shape any variant uses
-    int nmax = std::max((nx + 63) / 64, (ny + 3) / 4) + 1;
-    c->B.nmax = nmax;
-    if (hipMalloc(&c->bpart, sizeof(double) * 2 * 4 * 2 * (size_t)nmax) != hipSuccess)
-        return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
-    hipMemset(c->bpart, 0, sizeof(double) * 2 * 4 * 2 * (size_t)nmax);
+    // partial buffers sized for every launch shape: reference blocks, or tiled
+    // wavefronts with at least 4 rows each
+    {
+        const int nbx = (nx + 63) / 64, nby = (ny + 3) / 4, nstrips = (nx + 59) / 60, nrb = (ny + 3) / 4;
+        const int nmax = std::max(std::max(nbx, nby), std::max(nstrips, nrb)) + 1;
+        const size_t nw = std::max((size_t)nbx * nby, (size_t)nstrips * nrb);
+        c->B.nmax = nmax;
+        c->B.nw_ref = nbx * nby;
+        if (hipMalloc(&c->bpart, sizeof(double) * 2 * 4 * 2 * (size_t)nmax) != hipSuccess)
+            return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
+        hipMemset(c->bpart, 0, sizeof(double) * 2 * 4 * 2 * (size_t)nmax);
+        if (hipMalloc(&c->wpart, sizeof(double) * 2 * 4 * nw) != hipSuccess)
+            return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
+        hipMemset(c->wpart, 0, sizeof(double) * 2 * 4 * nw);
+    }
     if (hipMalloc(&c->mass_part, sizeof(double) * 2 * kMassBlocks) != hipSuccess)
         return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
     if (hipMalloc(&c->staging, sizeof(double) * 7 * n) != hipSuccess)
@@ -345,6 +387,7 @@ int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t pr
     c->B.mu = c->mu;
     c->B.S = c->S;
     c->B.bpart = c->bpart;
+    c->B.wpart = c->wpart;
     c->B.tables = c->tables;
     c->B.mass_part = c->mass_part;
     *out = c;
@@ -364,6 +407,7 @@ void m2p_destroy(m2p_ctx* c)
     if (c->mu) hipFree(c->mu);
     if (c->S) hipFree(c->S);
     if (c->bpart) hipFree(c->bpart);
+    if (c->wpart) hipFree(c->wpart);
     if (c->tables) hipFree(c->tables);
     if (c->mass_part) hipFree(c->mass_part);
     if (c->staging) hipFree(c->staging);
@@ -538,11 +582,11 @@ int m2p_set_variant(m2p_ctx* c, int32_t variant, int32_t rows)
 {
     if (!c) return fail(M2P_EINVAL, "NULL context");
     if (variant < M2P_VARIANT_AUTO || variant > M2P_VARIANT_TILED) return fail(M2P_EINVAL, "unknown variant");
-    if (rows < 0 || rows > 4096) return fail(M2P_EINVAL, "tile rows out of range");
+    if (rows != 0 && (rows < 4 || rows > 4096)) return fail(M2P_EINVAL, "tile rows must be 0 or in [4, 4096]");
+    HIPCHK(hipStreamSynchronize(c->stream));
     c->variant = variant;
     c->rows = rows;
     refresh_grid(c);
-    if (std::max(c->B.nbx, c->B.nby) > c->B.nmax) return fail(M2P_EINVAL, "tile shape too small for this grid");
     return M2P_OK;
 }
 

@@ -36,7 +36,6 @@ struct KParams {
 struct DevScalars {
     double t, dt, dt_last, t_end;
     double in_s, in_f, out_s, out_f;
-    unsigned long long amax_bits[2];  // max speed (xi, eta) of the state, as double bits
     long long steps;
     unsigned long long clamps;
     unsigned int status;
@@ -188,16 +187,15 @@ __device__ __forceinline__ void inflow_flux(const Consts<T>& K, const Geo<T>& g,
 
 // Viscous flux pieces at one face: J_b h and A_ij averaged over the two
 // cells; normal derivative by the neighbour difference, tangential
-// derivative as the mean of the two cells' central differences.
-// x-face: returns FX = 2 Jh (A11 u_x + A21 u_y), FY = Jh (A12 u_x + A22 u_y + A11 w_x + A21 w_y).
+// derivative as the mean of the two cells' central differences (cd*).
+// x-face: FX = 2 Jh (A11 u_x + A21 u_y), FY = Jh (A12 u_x + A22 u_y + A11 w_x + A21 w_y).
 template <typename T>
-__device__ __forceinline__ void visc_xface(T u0, T w0, T u1, T w1, T un0, T wn0, T us0, T ws0, T un1, T wn1, T us1,
-                                           T ws1, T Jh0, T Jh1, const Geo<T>& ga, const Geo<T>& gb, T dxi, T deta,
-                                           T& FX, T& FY)
+__device__ __forceinline__ void visc_xface_c(T u0, T w0, T u1, T w1, T cdyu0, T cdyw0, T cdyu1, T cdyw1, T Jh0,
+                                             T Jh1, const Geo<T>& ga, const Geo<T>& gb, T dxi, T& FX, T& FY)
 {
     T dxu = (u1 - u0) / dxi, dxw = (w1 - w0) / dxi;
-    T dyu = T(0.5) * ((un0 - us0) / (T(2) * deta) + (un1 - us1) / (T(2) * deta));
-    T dyw = T(0.5) * ((wn0 - ws0) / (T(2) * deta) + (wn1 - ws1) / (T(2) * deta));
+    T dyu = T(0.5) * (cdyu0 + cdyu1);
+    T dyw = T(0.5) * (cdyw0 + cdyw1);
     T Jh = T(0.5) * (Jh0 + Jh1);
     T A11 = T(0.5) * (ga.A11 + gb.A11), A12 = T(0.5) * (ga.A12 + gb.A12);
     T A21 = T(0.5) * (ga.A21 + gb.A21), A22 = T(0.5) * (ga.A22 + gb.A22);
@@ -207,18 +205,24 @@ __device__ __forceinline__ void visc_xface(T u0, T w0, T u1, T w1, T un0, T wn0,
 
 // y-face: GX = Jh (A12 u_x + A22 u_y + A11 w_x + A21 w_y), GY = 2 Jh (A12 w_x + A22 w_y).
 template <typename T>
-__device__ __forceinline__ void visc_yface(T u0, T w0, T u1, T w1, T ue0, T we0, T uw0, T ww0, T ue1, T we1, T uw1,
-                                           T ww1, T Jh0, T Jh1, const Geo<T>& ga, const Geo<T>& gb, T dxi, T deta,
-                                           T& GX, T& GY)
+__device__ __forceinline__ void visc_yface_c(T u0, T w0, T u1, T w1, T cdxu0, T cdxw0, T cdxu1, T cdxw1, T Jh0,
+                                             T Jh1, const Geo<T>& ga, const Geo<T>& gb, T deta, T& GX, T& GY)
 {
     T dyu = (u1 - u0) / deta, dyw = (w1 - w0) / deta;
-    T dxu = T(0.5) * ((ue0 - uw0) / (T(2) * dxi) + (ue1 - uw1) / (T(2) * dxi));
-    T dxw = T(0.5) * ((we0 - ww0) / (T(2) * dxi) + (we1 - ww1) / (T(2) * dxi));
+    T dxu = T(0.5) * (cdxu0 + cdxu1);
+    T dxw = T(0.5) * (cdxw0 + cdxw1);
     T Jh = T(0.5) * (Jh0 + Jh1);
     T A11 = T(0.5) * (ga.A11 + gb.A11), A12 = T(0.5) * (ga.A12 + gb.A12);
     T A21 = T(0.5) * (ga.A21 + gb.A21), A22 = T(0.5) * (ga.A22 + gb.A22);
     GX = Jh * (A12 * dxu + A22 * dyu + A11 * dxw + A21 * dyw);
     GY = T(2) * Jh * (A12 * dxw + A22 * dyw);
+}
+
+// central difference of a neighbour pair over 2 h
+template <typename T>
+__device__ __forceinline__ T cdiff(T up, T dn, T h)
+{
+    return (up - dn) / (T(2) * h);
 }
 
 // J_b h pbar^f with pbar^f = c h / 2.
@@ -364,8 +368,5 @@ __device__ __forceinline__ int map_index(int i, int n, int bc_lo, int bc_hi, int
     }
     return i;
 }
-
-// Order-preserving bits of a non-negative double.
-__device__ __forceinline__ unsigned long long speed_bits(double a) { return (unsigned long long)__double_as_longlong(a); }
 
 }  // namespace m2p

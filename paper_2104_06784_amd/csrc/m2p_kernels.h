@@ -93,7 +93,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh)
 template <typename T, int STAGE>
 __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restrict__ Uin, T* Un, T* Uout,
                                                    const T* __restrict__ b, const T* __restrict__ mu,
-                                                   DevScalars* __restrict__ S, double* __restrict__ bpart, int nmax)
+                                                   DevScalars* __restrict__ S, double* __restrict__ bpart,
+                                                   double* __restrict__ wpart, int nmax)
 {
     __shared__ double sh[9 * 256];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -197,16 +198,23 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
             T JhW = row[1][0] + row[1][3], JhE = row[3][0] + row[3][3];
             T JhS = col[1][0] + col[1][3], JhN = col[3][0] + col[3][3];
             T FX0, FY0, FX1, FY1, GX0, GY0, GX1, GY1;
-            // x-faces (i-1 | i) and (i | i+1); index [row dj+1][col di+1]
-            visc_xface(u9[1][0], w9[1][0], u9[1][1], w9[1][1], u9[2][0], w9[2][0], u9[0][0], w9[0][0], u9[2][1],
-                       w9[2][1], u9[0][1], w9[0][1], JhW, JhC, gW, gC, K.dxi, K.deta, FX0, FY0);
-            visc_xface(u9[1][1], w9[1][1], u9[1][2], w9[1][2], u9[2][1], w9[2][1], u9[0][1], w9[0][1], u9[2][2],
-                       w9[2][2], u9[0][2], w9[0][2], JhC, JhE, gC, gE, K.dxi, K.deta, FX1, FY1);
-            // y-faces (j-1 | j) and (j | j+1)
-            visc_yface(u9[0][1], w9[0][1], u9[1][1], w9[1][1], u9[0][2], w9[0][2], u9[0][0], w9[0][0], u9[1][2],
-                       w9[1][2], u9[1][0], w9[1][0], JhS, JhC, gS, gC, K.dxi, K.deta, GX0, GY0);
-            visc_yface(u9[1][1], w9[1][1], u9[2][1], w9[2][1], u9[1][2], w9[1][2], u9[1][0], w9[1][0], u9[2][2],
-                       w9[2][2], u9[2][0], w9[2][0], JhC, JhN, gC, gN, K.dxi, K.deta, GX1, GY1);
+            // central differences: y-differences at columns i-1, i, i+1 (row j),
+            // x-differences at rows j-1, j, j+1 (column i); index [row dj+1][col di+1]
+            T cyu[3], cyw[3], cxu[3], cxw[3];
+            for (int q = 0; q < 3; q++) {
+                cyu[q] = cdiff(u9[2][q], u9[0][q], K.deta);
+                cyw[q] = cdiff(w9[2][q], w9[0][q], K.deta);
+                cxu[q] = cdiff(u9[q][2], u9[q][0], K.dxi);
+                cxw[q] = cdiff(w9[q][2], w9[q][0], K.dxi);
+            }
+            visc_xface_c(u9[1][0], w9[1][0], u9[1][1], w9[1][1], cyu[0], cyw[0], cyu[1], cyw[1], JhW, JhC, gW, gC,
+                         K.dxi, FX0, FY0);
+            visc_xface_c(u9[1][1], w9[1][1], u9[1][2], w9[1][2], cyu[1], cyw[1], cyu[2], cyw[2], JhC, JhE, gC, gE,
+                         K.dxi, FX1, FY1);
+            visc_yface_c(u9[0][1], w9[0][1], u9[1][1], w9[1][1], cxu[0], cxw[0], cxu[1], cxw[1], JhS, JhC, gS, gC,
+                         K.deta, GX0, GY0);
+            visc_yface_c(u9[1][1], w9[1][1], u9[2][1], w9[2][1], cxu[1], cxw[1], cxu[2], cxw[2], JhC, JhN, gC, gN,
+                         K.deta, GX1, GY1);
             T SvX = (FX1 - FX0) / K.dxi + (GX1 - GX0) / K.deta;
             T SvY = (FY1 - FY0) / K.dxi + (GY1 - GY0) / K.deta;
             svx = K.eps * Sr.phif * K.inv_n_r * SvX;
@@ -232,14 +240,13 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
             Uout[k * fs + c] = out[k];
         }
     }
-    // block reductions (deterministic)
+    // block reductions (fixed trees: deterministic)
     block_sum<9, 256>(red, sh);
     __syncthreads();
-    double mx[2] = {ax, ay};
     {
         const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-        sh[tid] = mx[0];
-        sh[256 + tid] = mx[1];
+        sh[tid] = ax;
+        sh[256 + tid] = ay;
         sh[512 + tid] = bad;
         __syncthreads();
         for (int s = 128; s > 0; s >>= 1) {
@@ -252,6 +259,12 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
         }
         if (tid == 0) {
             const int st = STAGE - 1;
+            const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+            double* wp = wpart + ((size_t)st * gridDim.x * gridDim.y + bid) * 4;
+            wp[0] = sh[0];
+            wp[1] = sh[256];
+            wp[2] = red[8];
+            wp[3] = sh[512];
             if (blockIdx.x == 0) {
                 bpart[((st * 4 + 0) * nmax + blockIdx.y) * 2 + 0] = red[0];
                 bpart[((st * 4 + 0) * nmax + blockIdx.y) * 2 + 1] = red[1];
@@ -268,12 +281,6 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
                 bpart[((st * 4 + 3) * nmax + blockIdx.x) * 2 + 0] = red[6];
                 bpart[((st * 4 + 3) * nmax + blockIdx.x) * 2 + 1] = red[7];
             }
-            if (red[8] > 0.0) atomicAdd(&S->clamps, (unsigned long long)red[8]);
-            if (sh[512] > 0.0) atomicOr(&S->status, 1u);
-            if (STAGE == 2) {
-                atomicMax(&S->amax_bits[0], speed_bits(sh[0]));
-                atomicMax(&S->amax_bits[1], speed_bits(sh[256]));
-            }
         }
     }
 }
@@ -282,7 +289,7 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_speeds(KParams P, const T* __restrict__ U, const T* __restrict__ b,
-                                                DevScalars* __restrict__ S)
+                                                double* __restrict__ wpart)
 {
     __shared__ double sh[512];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,8 +318,13 @@ __global__ void __launch_bounds__(256) k_speeds(KParams P, const T* __restrict__
         __syncthreads();
     }
     if (tid == 0) {
-        atomicMax(&S->amax_bits[0], speed_bits(sh[0]));
-        atomicMax(&S->amax_bits[1], speed_bits(sh[256]));
+        // written into the stage-2 slots, which the init finalize reads
+        const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+        double* wp = wpart + ((size_t)gridDim.x * gridDim.y + bid) * 4;
+        wp[0] = sh[0];
+        wp[1] = sh[256];
+        wp[2] = 0.0;
+        wp[3] = 0.0;
     }
 }
 
@@ -366,22 +378,63 @@ __device__ __forceinline__ double inflow_rate(const KParams& P, const double* ta
 // both modes: next CFL dt from the speed maxima, inflow states of the next
 // step's two stages, reset of the maxima.
 template <typename T>
-__global__ void __launch_bounds__(64) k_finalize(KParams P, DevScalars* S, const double* __restrict__ bpart, int nbx,
-                                                 int nby, int nmax, const double* __restrict__ tables, int mode)
+__global__ void __launch_bounds__(256) k_finalize(KParams P, DevScalars* S, const double* __restrict__ bpart,
+                                                  int n_we, int n_sn, int nmax, const double* __restrict__ tables,
+                                                  int mode, const double* __restrict__ wpart, int nw)
 {
+    // Fixed-order reductions (deterministic): boundary outflow partials, 16
+    // threads per (stage, side, phase); per-wave / per-block partials of the
+    // speed maxima, clamp counts and non-finite flags, 256 strided threads.
+    __shared__ double red[4 * 256];
     __shared__ double part[16];
     const int tid = threadIdx.x;
-    if (mode == 0 && tid < 16) {
-        // tid = (stage * 4 + side) * 2 + phase
-        const int st = tid >> 3, side = (tid >> 1) & 3, ph = tid & 1;
-        const int n = side < 2 ? nby : nbx;
+    if (mode == 0) {
+        const int combo = tid >> 4, lane = tid & 15;
+        const int st = combo >> 3, side = (combo >> 1) & 3, ph = combo & 1;
+        const int n = side < 2 ? n_we : n_sn;
         const double* p = bpart + ((size_t)(st * 4 + side) * nmax) * 2 + ph;
         double acc = 0.0;
-        for (int q = 0; q < n; q++) acc += p[2 * q];
-        part[tid] = acc;
+        for (int q = lane; q < n; q += 16) acc += p[2 * q];
+        red[tid] = acc;
+        __syncthreads();
+        for (int w = 8; w > 0; w >>= 1) {
+            if (lane < w) red[tid] += red[tid + w];
+            __syncthreads();
+        }
+        if (lane == 0) part[combo] = red[tid];
+        __syncthreads();
     }
-    __syncthreads();
+    {
+        double ax = 0.0, ay = 0.0, cl = 0.0, bd = 0.0;
+        const double* w2 = wpart + (size_t)nw * 4;  // stage-2 (or speeds) slots
+        for (int q = tid; q < nw; q += 256) {
+            ax = fmax(ax, w2[4 * q]);
+            ay = fmax(ay, w2[4 * q + 1]);
+            cl += w2[4 * q + 2];
+            bd = fmax(bd, w2[4 * q + 3]);
+            if (mode == 0) {
+                cl += wpart[4 * q + 2];
+                bd = fmax(bd, wpart[4 * q + 3]);
+            }
+        }
+        red[tid] = ax;
+        red[256 + tid] = ay;
+        red[512 + tid] = cl;
+        red[768 + tid] = bd;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) {
+                red[tid] = fmax(red[tid], red[tid + w]);
+                red[256 + tid] = fmax(red[256 + tid], red[256 + tid + w]);
+                red[512 + tid] += red[512 + tid + w];
+                red[768 + tid] = fmax(red[768 + tid], red[768 + tid + w]);
+            }
+            __syncthreads();
+        }
+    }
     if (tid != 0) return;
+    if (red[768] > 0.0) S->status |= 1u;
+    S->clamps += (unsigned long long)red[512];
     double t = S->t;
     if (mode == 0) {
         const double dt = S->dt;
@@ -409,8 +462,8 @@ __global__ void __launch_bounds__(64) k_finalize(KParams P, DevScalars* S, const
             S->dt_last = dt;
         }
     }
-    double ax = __longlong_as_double((long long)S->amax_bits[0]);
-    double ay = __longlong_as_double((long long)S->amax_bits[1]);
+    double ax = red[0];
+    double ay = red[256];
     for (int s = 0; s < P.nseg; s++) {
         double st[4];
         inflow_state(P, tables, s, t, st);
@@ -433,8 +486,6 @@ __global__ void __launch_bounds__(64) k_finalize(KParams P, DevScalars* S, const
         inflow_state(P, tables, s, t, S->inflow[0][s]);
         inflow_state(P, tables, s, t + dt, S->inflow[1][s]);
     }
-    S->amax_bits[0] = 0ull;
-    S->amax_bits[1] = 0ull;
 }
 
 // ------------------------------------------------- conversions, reductions

@@ -3,37 +3,38 @@
 #pragma once
 
 #include "m2p_kernels.h"
+#include "m2p_tiled.h"
 
 namespace m2p {
 
 template <>
-void Launch<M2P_REAL>::grid_dims(const KParams& P, int variant, int rows, int& nbx, int& nby)
-{
-    (void)variant;
-    (void)rows;
-    nbx = (P.nx + 63) / 64;
-    nby = (P.ny + 3) / 4;
-}
-
-template <>
-hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, hipStream_t st, int variant, int rows,
-                                       int part)
+hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Shape& sh, hipStream_t st, int part)
 {
     using T = M2P_REAL;
-    (void)variant;
-    (void)rows;
-    dim3 blk(64, 4), grd(B.nbx, B.nby);
     T* U = (T*)B.U;
     T* Us = (T*)B.Us;
     const T* b = (const T*)B.b;
     const T* mu = (const T*)B.mu;
-    if (part == 0)
-        hipLaunchKernelGGL((k_stage_ref<T, 1>), grd, blk, 0, st, P, U, U, Us, b, mu, B.S, B.bpart, B.nmax);
-    else if (part == 1)
-        hipLaunchKernelGGL((k_stage_ref<T, 2>), grd, blk, 0, st, P, Us, U, U, b, mu, B.S, B.bpart, B.nmax);
-    else
-        hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(64), 0, st, P, B.S, B.bpart, B.nbx, B.nby, B.nmax,
-                           B.tables, 0);
+    if (part == 2) {
+        hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(256), 0, st, P, B.S, B.bpart, sh.n_we, sh.n_sn, B.nmax,
+                           B.tables, 0, B.wpart, sh.nw);
+    } else if (sh.variant == 1) {
+        dim3 blk(64, 4), grd(sh.nbx, sh.nby);
+        if (part == 0)
+            hipLaunchKernelGGL((k_stage_ref<T, 1>), grd, blk, 0, st, P, U, U, Us, b, mu, B.S, B.bpart, B.wpart,
+                               B.nmax);
+        else
+            hipLaunchKernelGGL((k_stage_ref<T, 2>), grd, blk, 0, st, P, Us, U, U, b, mu, B.S, B.bpart, B.wpart,
+                               B.nmax);
+    } else {
+        dim3 blk(256), grd(sh.blocks);
+        if (part == 0)
+            hipLaunchKernelGGL((k_stage_tiled<T, 1>), grd, blk, 0, st, P, U, U, Us, b, mu, B.S, B.bpart, B.wpart,
+                               B.nmax, sh.R, sh.nstrips, sh.nrb);
+        else
+            hipLaunchKernelGGL((k_stage_tiled<T, 2>), grd, blk, 0, st, P, Us, U, U, b, mu, B.S, B.bpart, B.wpart,
+                               B.nmax, sh.R, sh.nstrips, sh.nrb);
+    }
     return hipGetLastError();
 }
 
@@ -42,8 +43,9 @@ hipError_t Launch<M2P_REAL>::init(const KParams& P, const Bufs& B, hipStream_t s
 {
     using T = M2P_REAL;
     dim3 blk(64, 4), grd((P.nx + 63) / 64, (P.ny + 3) / 4);
-    hipLaunchKernelGGL((k_speeds<T>), grd, blk, 0, st, P, (const T*)B.U, (const T*)B.b, B.S);
-    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(64), 0, st, P, B.S, B.bpart, B.nbx, B.nby, B.nmax, B.tables, 1);
+    hipLaunchKernelGGL((k_speeds<T>), grd, blk, 0, st, P, (const T*)B.U, (const T*)B.b, B.wpart);
+    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(256), 0, st, P, B.S, B.bpart, 0, 0, B.nmax, B.tables, 1,
+                       B.wpart, B.nw_ref);
     return hipGetLastError();
 }
 

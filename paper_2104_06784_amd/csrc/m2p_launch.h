@@ -8,30 +8,43 @@
 
 namespace m2p {
 
+// Launch shape of the stage kernels for one variant.
+struct Shape {
+    int variant;       // 1 reference, 2 tiled
+    int nbx, nby;      // reference: 64 x 4 blocks
+    int R, nstrips, nrb;  // tiled: rows per wavefront, strips, row blocks
+    int n_we, n_sn;    // boundary partials per W/E and per S/N side
+    int nw;            // per-stage partial slots
+    int blocks;        // workgroups per stage launch
+};
+
 struct Bufs {
-    void* U;             // state U^n (6 fields, [ny][pitch] each)
-    void* Us;            // stage state U*
-    const void* b;       // padded DEM / L
-    const void* mu;      // per-cell tan(delta_b) or nullptr
-    DevScalars* S;       // device scalars
-    double* bpart;       // boundary outflow partials [2][4][nmax][2]
+    void* U;               // state U^n (6 fields, [ny][pitch] each)
+    void* Us;              // stage state U*
+    const void* b;         // padded DEM / L
+    const void* mu;        // per-cell tan(delta_b) or nullptr
+    DevScalars* S;         // device scalars
+    double* bpart;         // boundary outflow partials [2][4][nmax][2]
+    double* wpart;         // per-wave / per-block partials [2][nw][4]
     const double* tables;  // inflow hydrographs
-    double* mass_part;   // [2 * kMassBlocks]
-    int nbx, nby, nmax;  // stage-kernel grid and partial stride
+    double* mass_part;     // [2 * kMassBlocks]
+    int nmax;              // stride of bpart
+    int nw_ref;            // partial slots of the reference grid (speeds kernel)
 };
 
 constexpr int kMassBlocks = 1024;
 
+Shape make_shape(const KParams& P, int variant, int rows);
+
 template <typename T>
 struct Launch {
     // part 0: stage 1, part 1: stage 2, part 2: finalize
-    static hipError_t step_part(const KParams& P, const Bufs& B, hipStream_t st, int variant, int rows, int part);
+    static hipError_t step_part(const KParams& P, const Bufs& B, const Shape& sh, hipStream_t st, int part);
     static hipError_t init(const KParams& P, const Bufs& B, hipStream_t st);
     static hipError_t set_state(const KParams& P, const Bufs& B, const double* f, int vertical, int has_v,
                                 hipStream_t st);
     static hipError_t get_fields(const KParams& P, const Bufs& B, double* f, hipStream_t st);
     static hipError_t mass(const KParams& P, const Bufs& B, hipStream_t st);
-    static void grid_dims(const KParams& P, int variant, int rows, int& nbx, int& nby);
 };
 
 }  // namespace m2p

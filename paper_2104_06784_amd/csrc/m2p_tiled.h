@@ -1,0 +1,349 @@
+// m2p_tiled.h -- fused column-marching stage kernel for gfx950.
+//
+// One wavefront owns a strip of 64 columns (60 output columns plus a halo of
+// two on each side) and marches up R rows.  The y-direction stencil of the
+// scheme (minmod slopes need rows j-1..j+2, sources and viscosity rows
+// j-1..j+1) lives in a rolling register window; x-neighbours are exchanged by
+// cross-lane shuffles.  Every face flux, every cell geometry and every
+// derived cell quantity is computed once per stage (the y-face flux of row
+// j+1/2 is carried to the next row), so the kernel reads each state field
+// once per row from HBM and needs no LDS and no barrier.  The arithmetic of
+// every quantity is the one of m2p_device.h in the same order as the
+// reference kernel, so FP64 results are bitwise identical to it.
+#pragma once
+
+#include "m2p_device.h"
+
+namespace m2p {
+
+constexpr int kStripOut = 60;  // output columns per wavefront
+
+template <typename T>
+__device__ __forceinline__ T from_right(T v)  // value of lane + 1
+{
+    return __shfl_down(v, 1, 64);
+}
+
+template <typename T>
+__device__ __forceinline__ T from_left(T v)  // value of lane - 1
+{
+    return __shfl_up(v, 1, 64);
+}
+
+// Per-row quantities kept in the rolling window.
+template <typename T>
+struct RowD {
+    Geo<T> g;      // basal geometry of the cell
+    T u, w;        // fluid velocities (desingularised)
+    T cdxu, cdxw;  // central x-differences of u, w
+    T Jh;          // J_b h = m^s + m^f
+    T Gf;          // J_b h pbar^f
+};
+
+template <typename T>
+__device__ __forceinline__ void make_row(const Consts<T>& K, const T u[NF], T bC, T bS, T bN, RowD<T>& r)
+{
+    const T bE = from_right(bC), bW = from_left(bC);
+    r.g = geometry(bE, bW, bN, bS, K.two_dxi, K.two_deta);
+    r.u = dsg(u[4], u[3], K.md);
+    r.w = dsg(u[5], u[3], K.md);
+    const T uE = from_right(r.u), uW = from_left(r.u);
+    const T wE = from_right(r.w), wW = from_left(r.w);
+    r.cdxu = cdiff(uE, uW, K.dxi);
+    r.cdxw = cdiff(wE, wW, K.dxi);
+    r.Jh = u[0] + u[3];
+    r.Gf = fluid_G(u[0], u[3], r.g);
+}
+
+template <typename T>
+__device__ __forceinline__ void visc_yface_rows(const RowD<T>& a, const RowD<T>& b, const Consts<T>& K, T& GX, T& GY)
+{
+    visc_yface_c(a.u, a.w, b.u, b.w, a.cdxu, a.cdxw, b.cdxu, b.cdxw, a.Jh, b.Jh, a.g, b.g, K.deta, GX, GY);
+}
+
+template <typename T, int STAGE>
+__global__ void __launch_bounds__(256) k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout,
+                                                     const T* __restrict__ b, const T* __restrict__ mu,
+                                                     DevScalars* __restrict__ S, double* __restrict__ bpart,
+                                                     double* __restrict__ wpart, int nmax, int R, int nstrips,
+                                                     int nrb)
+{
+    // XCD-aware block order: consecutive block ids land on different XCDs, so
+    // give each XCD a contiguous range of waves (neighbouring strips share halo
+    // columns in that XCD's L2).
+    const int nblk = gridDim.x;
+    int bid = blockIdx.x;
+    const int nfull = (nblk / 8) * 8;
+    if (bid < nfull) bid = (bid % 8) * (nfull / 8) + bid / 8;
+    const int lane = threadIdx.x & 63;
+    const int wid = bid * 4 + (threadIdx.x >> 6);
+    const int strip = wid % nstrips, rb = wid / nstrips;
+    if (rb >= nrb) return;  // whole wavefront
+    const Consts<T> K(P);
+    const size_t fs = (size_t)P.ny * P.pitch;
+    const int col = strip * kStripOut - 2 + lane;
+    const int cc = col < P.nx + 1 ? col : P.nx + 1;  // lanes past the ghost ring feed no output
+    int fx = 0;
+    const int mi = map_index(cc, P.nx, P.bc[0], P.bc[1], fx);
+    const int bcol = BOFF + cc;
+    const bool out_lane = lane >= 2 && lane < 62 && col < P.nx;
+    const int r0 = rb * R;
+    const int r1 = r0 + R < P.ny ? r0 + R : P.ny;
+    const T dt = T(S->dt);
+    const double(*inf)[4] = S->inflow[STAGE - 1];
+    const bool ownW = out_lane && col == 0;  // this lane owns the W / E boundary face
+    const bool ownE = out_lane && col == P.nx - 1;
+
+    auto loadU = [&](int r, T u[NF]) {
+        int fy = 0;
+        const int mj = map_index(r, P.ny, P.bc[2], P.bc[3], fy);
+        const size_t o = (size_t)mj * P.pitch + mi;
+#pragma unroll
+        for (int k = 0; k < NF; k++) u[k] = Uin[k * fs + o];
+        if (fx) {
+            u[1] = -u[1];
+            u[4] = -u[4];
+        }
+        if (fy) {
+            u[2] = -u[2];
+            u[5] = -u[5];
+        }
+    };
+    auto loadB = [&](int r) { return b[(size_t)(r + BHALO) * P.bpitch + bcol]; };
+
+    double ob[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // outflow W, E, S, N per phase
+    double amx = 0.0, amy = 0.0;
+    int clamps = 0, bad = 0;
+
+    // ---- prologue: rows r0-2 .. r0+1
+    T Um2[NF], Um1[NF], U0[NF], U1[NF];
+    loadU(r0 - 2, Um2);
+    loadU(r0 - 1, Um1);
+    loadU(r0, U0);
+    loadU(r0 + 1, U1);
+    T bm2 = loadB(r0 - 2), bm1 = loadB(r0 - 1), b0 = loadB(r0), b1 = loadB(r0 + 1);
+    RowD<T> Dm, D0;  // rows j-1, j
+    make_row(K, Um1, bm1, bm2, b0, Dm);
+    make_row(K, U0, b0, bm1, b1, D0);
+    T sy0[NF], sy1[NF];  // y-slopes of rows j and j+1
+    T Hy[NF];            // y-face flux j - 1/2
+    {
+        T sym[NF], uL[NF], uR[NF];
+#pragma unroll
+        for (int k = 0; k < NF; k++) {
+            sym[k] = minmod(Um1[k] - Um2[k], U0[k] - Um1[k]);
+            sy0[k] = minmod(U0[k] - Um1[k], U1[k] - U0[k]);
+            uL[k] = Um1[k] + T(0.5) * sym[k];
+            uR[k] = U0[k] - T(0.5) * sy0[k];
+        }
+        central_flux(K, uL, Dm.g, uR, D0.g, 1, Hy);
+        if (r0 == 0 && out_lane) {
+            const int s = inflow_seg_at(P, 2, col);
+            if (s >= 0)
+                inflow_flux(K, D0.g, 1, +1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), Hy);
+            else {
+                ob[4] -= (double)Hy[0] * P.dxi;
+                ob[5] -= (double)Hy[3] * P.dxi;
+            }
+        }
+    }
+    // viscous y-face j - 1/2
+    T vGX = T(0), vGY = T(0);
+    if (P.visc)
+        visc_yface_rows(Dm, D0, K, vGX, vGY);
+    T Uc[NF], Un1[NF];  // rows j, j+1
+#pragma unroll
+    for (int k = 0; k < NF; k++) {
+        Uc[k] = U0[k];
+        Un1[k] = U1[k];
+    }
+    T bj = b0, bj1 = b1;
+
+    for (int j = r0; j < r1; j++) {
+        // ---- new row j+2 (state) and geometry / derived quantities of row j+1
+        T U2[NF];
+        loadU(j + 2, U2);
+        const T bj2 = loadB(j + 2);
+        RowD<T> D1;
+        make_row(K, Un1, bj1, bj, bj2, D1);
+        T uL[NF], uR[NF];
+#pragma unroll
+        for (int k = 0; k < NF; k++) {
+            sy1[k] = minmod(Un1[k] - Uc[k], U2[k] - Un1[k]);
+            uL[k] = Uc[k] + T(0.5) * sy0[k];
+            uR[k] = Un1[k] - T(0.5) * sy1[k];
+        }
+        // ---- y-face j + 1/2
+        T HyN[NF];
+        central_flux(K, uL, D0.g, uR, D1.g, 1, HyN);
+        if (j == P.ny - 1 && out_lane) {
+            const int s = inflow_seg_at(P, 3, col);
+            if (s >= 0)
+                inflow_flux(K, D0.g, 1, -1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HyN);
+            else {
+                ob[6] += (double)HyN[0] * P.dxi;
+                ob[7] += (double)HyN[3] * P.dxi;
+            }
+        }
+        T vGXN = T(0), vGYN = T(0);
+        if (P.visc) visc_yface_rows(D0, D1, K, vGXN, vGYN);
+
+        // ---- x-faces of row j: this lane computes face i + 1/2
+        T Hx[NF], HxL[NF];
+        {
+            T sx[NF], up[NF], um[NF], upR[NF];
+#pragma unroll
+            for (int k = 0; k < NF; k++) {
+                const T wE = from_right(Uc[k]), wW = from_left(Uc[k]);
+                sx[k] = minmod(Uc[k] - wW, wE - Uc[k]);
+                um[k] = Uc[k] + T(0.5) * sx[k];  // left value of face i + 1/2
+                up[k] = Uc[k] - T(0.5) * sx[k];  // right value of face i - 1/2
+            }
+#pragma unroll
+            for (int k = 0; k < NF; k++) upR[k] = from_right(up[k]);
+            Geo<T> gR;
+            gR.bX = from_right(D0.g.bX);
+            gR.bY = from_right(D0.g.bY);
+            gR.J = from_right(D0.g.J);
+            gR.c = from_right(D0.g.c);
+            gR.nX = gR.nY = gR.nZ = T(0);
+            gR.A11 = from_right(D0.g.A11);
+            gR.A12 = from_right(D0.g.A12);
+            gR.A21 = gR.A12;
+            gR.A22 = from_right(D0.g.A22);
+            central_flux(K, um, D0.g, upR, gR, 0, Hx);
+#pragma unroll
+            for (int k = 0; k < NF; k++) HxL[k] = from_left(Hx[k]);
+        }
+        if (ownW) {
+            const int s = inflow_seg_at(P, 0, j);
+            if (s >= 0)
+                inflow_flux(K, D0.g, 0, +1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HxL);
+            else {
+                ob[0] -= (double)HxL[0] * P.deta;
+                ob[1] -= (double)HxL[3] * P.deta;
+            }
+        }
+        if (ownE) {
+            const int s = inflow_seg_at(P, 1, j);
+            if (s >= 0)
+                inflow_flux(K, D0.g, 0, -1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), Hx);
+            else {
+                ob[2] += (double)Hx[0] * P.deta;
+                ob[3] += (double)Hx[3] * P.deta;
+            }
+        }
+
+        // ---- sources of row j
+        T dn[6];
+        {
+            const T nXE = from_right(D0.g.nX), nXW = from_left(D0.g.nX);
+            const T nYE = from_right(D0.g.nY), nYW = from_left(D0.g.nY);
+            const T nZE = from_right(D0.g.nZ), nZW = from_left(D0.g.nZ);
+            dn[0] = (nXE - nXW) / K.two_dxi;
+            dn[1] = (nYE - nYW) / K.two_dxi;
+            dn[2] = (nZE - nZW) / K.two_dxi;
+            dn[3] = (D1.g.nX - Dm.g.nX) / K.two_deta;
+            dn[4] = (D1.g.nY - Dm.g.nY) / K.two_deta;
+            dn[5] = (D1.g.nZ - Dm.g.nZ) / K.two_deta;
+        }
+        const T GE = from_right(D0.Gf), GW = from_left(D0.Gf);
+        const T dGx = (GE - GW) / K.two_dxi;
+        const T dGy = (D1.Gf - Dm.Gf) / K.two_deta;
+        Src<T> Sr;
+        sources(K, P.flags, Uc, D0.g, dn, dGx, dGy, Sr);
+        T svx = T(0), svy = T(0);
+        if (P.visc) {
+            // x-face i + 1/2 viscous fluxes, then face i - 1/2 from the left lane
+            const T cdyu = cdiff(D1.u, Dm.u, K.deta);
+            const T cdyw = cdiff(D1.w, Dm.w, K.deta);
+            const T uE = from_right(D0.u), wE = from_right(D0.w);
+            const T cdyuE = from_right(cdyu), cdywE = from_right(cdyw);
+            const T JhE = from_right(D0.Jh);
+            Geo<T> gE;
+            gE.A11 = from_right(D0.g.A11);
+            gE.A12 = from_right(D0.g.A12);
+            gE.A21 = gE.A12;
+            gE.A22 = from_right(D0.g.A22);
+            T FX1, FY1;
+            visc_xface_c(D0.u, D0.w, uE, wE, cdyu, cdyw, cdyuE, cdywE, D0.Jh, JhE, D0.g, gE, K.dxi, FX1, FY1);
+            const T FX0 = from_left(FX1), FY0 = from_left(FY1);
+            const T SvX = (FX1 - FX0) / K.dxi + (vGXN - vGX) / K.deta;
+            const T SvY = (FY1 - FY0) / K.dxi + (vGYN - vGY) / K.deta;
+            svx = K.eps * Sr.phif * K.inv_n_r * SvX;
+            svy = K.eps * Sr.phif * K.inv_n_r * SvY;
+        }
+        // ---- update and write
+        if (out_lane) {
+            const size_t c = (size_t)j * P.pitch + col;
+            const T tmu = P.has_mu ? mu[c] : K.tan_d;
+            T out[NF];
+            clamps += update_cell(K, Uc, D0.g, HxL, Hx, Hy, HyN, Sr, svx, svy, dt, tmu, out);
+            if (STAGE == 2) {
+#pragma unroll
+                for (int k = 0; k < NF; k++) out[k] = T(0.5) * (Un[k * fs + c] + out[k]);
+                T a[2];
+                side_speed(K, out, D0.g, 0, a);
+                amx = fmax(amx, (double)(a[0] > a[1] ? a[0] : a[1]));
+                side_speed(K, out, D0.g, 1, a);
+                amy = fmax(amy, (double)(a[0] > a[1] ? a[0] : a[1]));
+            }
+#pragma unroll
+            for (int k = 0; k < NF; k++) {
+                if (!isfinite(out[k])) bad = 1;
+                Uout[k * fs + c] = out[k];
+            }
+        }
+        // ---- roll the window
+#pragma unroll
+        for (int k = 0; k < NF; k++) {
+            Hy[k] = HyN[k];
+            sy0[k] = sy1[k];
+            Uc[k] = Un1[k];
+            Un1[k] = U2[k];
+        }
+        vGX = vGXN;
+        vGY = vGYN;
+        Dm = D0;
+        D0 = D1;
+        bj = bj1;
+        bj1 = bj2;
+    }
+
+    // ---- wavefront reductions (fixed butterfly => deterministic in lane 0)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        amx = fmax(amx, __shfl_xor(amx, off, 64));
+        amy = fmax(amy, __shfl_xor(amy, off, 64));
+        clamps += __shfl_xor(clamps, off, 64);
+        bad |= __shfl_xor(bad, off, 64);
+#pragma unroll
+        for (int q = 0; q < 8; q++) ob[q] += __shfl_xor(ob[q], off, 64);
+    }
+    if (lane == 0) {
+        const int st = STAGE - 1;
+        double* wp = wpart + ((size_t)st * nstrips * nrb + wid) * 4;
+        wp[0] = amx;
+        wp[1] = amy;
+        wp[2] = (double)clamps;
+        wp[3] = (double)bad;
+        if (strip == 0) {
+            bpart[((st * 4 + 0) * nmax + rb) * 2 + 0] = ob[0];
+            bpart[((st * 4 + 0) * nmax + rb) * 2 + 1] = ob[1];
+        }
+        if (strip == nstrips - 1) {
+            bpart[((st * 4 + 1) * nmax + rb) * 2 + 0] = ob[2];
+            bpart[((st * 4 + 1) * nmax + rb) * 2 + 1] = ob[3];
+        }
+        if (rb == 0) {
+            bpart[((st * 4 + 2) * nmax + strip) * 2 + 0] = ob[4];
+            bpart[((st * 4 + 2) * nmax + strip) * 2 + 1] = ob[5];
+        }
+        if (rb == nrb - 1) {
+            bpart[((st * 4 + 3) * nmax + strip) * 2 + 0] = ob[6];
+            bpart[((st * 4 + 3) * nmax + strip) * 2 + 1] = ob[7];
+        }
+    }
+}
+
+}  // namespace m2p

@@ -52,9 +52,10 @@ def _compare_steps(prob, nsteps, tol, variant=0, precision="f64"):
 
 # ------------------------------------------------------------------ FP64
 
-def test_config1_fp64_matches_oracle():
-    """Config 1 (128^2, FP64, walls, CFL 0.5), 200 steps."""
-    g, o = _compare_steps(I.config1(), 200, 1e-12, variant=1)
+@pytest.mark.parametrize("variant", [1, 2])
+def test_config1_fp64_matches_oracle(variant):
+    """Config 1 (128^2, FP64, walls, CFL 0.5), 200 steps, both kernel variants."""
+    g, o = _compare_steps(I.config1(), 200, 1e-12, variant=variant)
     dg, do = g.diag(), o.diag()
     assert dg["steps"] == 200 and abs(dg["t"] - do["t"]) <= 1e-12 * do["t"]
     assert abs(dg["mass_s"] - do["mass_s"]) <= 1e-12 * do["mass_s"]
@@ -65,7 +66,8 @@ def test_config1_fp64_matches_oracle():
         assert np.max(np.abs(fg[k] - fo[k])) <= 1e-12 * sc, k
 
 
-def test_ragged_grid_mixed_boundaries_fp64():
+@pytest.mark.parametrize("variant", [1, 2])
+def test_ragged_grid_mixed_boundaries_fp64(variant):
     """A grid that is not a multiple of any tile (67 x 45), different boundary
     modes per side and a Mode-II segment on the south side."""
     n_x, n_y, dx = 67, 45, 10.0
@@ -75,10 +77,11 @@ def test_ragged_grid_mixed_boundaries_fp64():
     seg = I.Inflow(I.SIDE_S, 20, 7, t, Q, ph)
     p = I.Params(delta_b_deg=18.0, cfl=0.2, bc=(1, 0, 0, 1))
     prob = I.Problem("ragged", n_x, n_y, dx, dx, p, dem, h, np.where(h > 0, 0.5, 0.0), [seg])
-    _compare_steps(prob, 150, 1e-12, variant=1)
+    _compare_steps(prob, 150, 1e-12, variant=variant)
 
 
-def test_inflow_on_every_side_budget_fp64():
+@pytest.mark.parametrize("variant", [1, 2])
+def test_inflow_on_every_side_budget_fp64(variant):
     """One inflow segment per side, walls elsewhere: GPU matches the oracle and
     the volume budget closes to round-off."""
     n, dx = 40, 5.0
@@ -89,7 +92,7 @@ def test_inflow_on_every_side_budget_fp64():
         segs.append(I.Inflow(side, 10 + side, 6, t, Q, ph))
     z = np.zeros((n, n))
     prob = I.Problem("inflow4", n, n, dx, dx, I.Params(bc=(1, 1, 1, 1)), dem, z, z.copy(), segs)
-    g, o = _compare_steps(prob, 120, 1e-12, variant=1)
+    g, o = _compare_steps(prob, 120, 1e-12, variant=variant)
     d = g.diag()
     assert d["clamp_count"] == 0
     assert abs(d["mass_s"] - d["in_s"]) <= 1e-12 * d["in_s"]
