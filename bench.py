@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after timing, run 3 device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -126,6 +128,17 @@ def main():
     }
     log(f"[bench] {value:.1f} Mcell-steps/s, stage2 {t2 * 1e3:.3f} ms ({ach:.0f} GB/s)")
     del sim
+    if args.copy_probe_mib > 0:
+        # plain device-to-device copies of known size, so that hardware byte
+        # counters of the step kernels can be calibrated against them
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 4 * n
+        del a, b
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: {args.cpu_steps} oracle steps")
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)

@@ -24,8 +24,11 @@ COMMON = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall",
 PER_FILE = {
     # FP64 arithmetic exactly as written: no FMA contraction.
     "m2p_f64.hip": ["-ffp-contract=off"],
-    # FP32 state: contraction and fast reciprocal / square root.
-    "m2p_f32.hip": ["-ffp-contract=fast", "-fno-hip-fp32-correctly-rounded-divide-sqrt"],
+    # FP32 state: contraction, reciprocal math, fast square root, denormals
+    # flushed (every FP32 quantity of the step is far above 1e-38).
+    "m2p_f32.hip": ["-ffp-contract=fast", "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+                    "-fgpu-flush-denormals-to-zero", "-freciprocal-math", "-fno-signed-zeros",
+                    "-fno-trapping-math"],
     "m2p_abi.hip": ["-ffp-contract=off"],
 }
 

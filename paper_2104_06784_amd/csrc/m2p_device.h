@@ -48,12 +48,15 @@ struct Geo {
     T bX, bY, J, c, nX, nY, nZ, A11, A12, A21, A22;
 };
 
+// minmod(a, b): the argument of smaller magnitude when both have the same
+// strict sign, else 0 (written with selects so the compiler emits no branch)
 template <typename T>
 __device__ __forceinline__ T minmod(T a, T b)
 {
-    if (a > T(0) && b > T(0)) return a < b ? a : b;
-    if (a < T(0) && b < T(0)) return a > b ? a : b;
-    return T(0);
+    const T lo = a < b ? a : b, hi = a > b ? a : b;
+    const bool pos = (a > T(0)) & (b > T(0));
+    const bool neg = (a < T(0)) & (b < T(0));
+    return pos ? lo : (neg ? hi : T(0));
 }
 
 // Continuous desingularisation of num / den (Kurganov-Petrova 2007):
