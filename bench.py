@@ -33,6 +33,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources and build flags: the byte counters recorded in
+    profiles/ apply only while this hash is unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2104_06784_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".h", ".hip")):
+            h.update(f.encode())
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_2104_06784_amd", "build_lib.py"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(n: int, precision: str):
+    """HBM bytes per stage-2 launch from the rocprofv3 counter summary in
+    profiles/, if it was taken on the current kernel sources and workload."""
+    path = os.path.join(ROOT, "profiles", f"stage2_cfg3_{n}_{precision}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic_json:"):
+            rec = json.loads(line.split(":", 1)[1])
+            if rec.get("kernel_source_hash") == kernel_source_hash():
+                return rec["stage2_hbm_bytes_per_launch"]
+    return None
+
+
 def cpu_baseline(prob, nsteps: int) -> dict:
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
@@ -118,7 +146,8 @@ def main():
                                f"half-ellipsoid release, phi_s 0.55, {args.precision} state + FP64 dt/volume",
                    "cells": cells, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic(args.n, args.precision),
                      "kernel": "stage 2 (U* stencil + own U^n + DEM -> U^{n+1})",
                      "kernel_ms": round(t2 * 1e3, 4), "stage1_ms": round(t1 * 1e3, 4),
                      "finalize_ms": round(kt[2] / nk, 4),
