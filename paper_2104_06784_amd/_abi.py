@@ -9,7 +9,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libm2p.so")
+# M2P_LIBRARY overrides the library path (for example a build with other
+# compile-time tile options); the default is the library built in-tree.
+LIB_PATH = os.environ.get("M2P_LIBRARY") or os.path.join(HERE, "libm2p.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "m2p.h")
 
 M2P_OK = 0

@@ -371,10 +371,10 @@ int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t pr
         c->B.nw_ref = nbx * nby;
         if (hipMalloc(&c->bpart, sizeof(double) * 2 * 4 * 2 * (size_t)nmax) != hipSuccess)
             return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
-        hipMemset(c->bpart, 0, sizeof(double) * 2 * 4 * 2 * (size_t)nmax);
+        (void)hipMemset(c->bpart, 0, sizeof(double) * 2 * 4 * 2 * (size_t)nmax);
         if (hipMalloc(&c->wpart, sizeof(double) * 2 * 4 * nw) != hipSuccess)
             return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
-        hipMemset(c->wpart, 0, sizeof(double) * 2 * 4 * nw);
+        (void)hipMemset(c->wpart, 0, sizeof(double) * 2 * 4 * nw);
     }
     if (hipMalloc(&c->mass_part, sizeof(double) * 2 * kMassBlocks) != hipSuccess)
         return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
@@ -397,21 +397,23 @@ int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t pr
 void m2p_destroy(m2p_ctx* c)
 {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
-    else hipDeviceSynchronize();
+    if (c->stream)
+        (void)hipStreamSynchronize(c->stream);
+    else
+        (void)hipDeviceSynchronize();
     if (c->own_state) {
-        if (c->B.U) hipFree(c->B.U);
-        if (c->B.Us) hipFree(c->B.Us);
+        if (c->B.U) (void)hipFree(c->B.U);
+        if (c->B.Us) (void)hipFree(c->B.Us);
     }
-    if (c->b) hipFree(c->b);
-    if (c->mu) hipFree(c->mu);
-    if (c->S) hipFree(c->S);
-    if (c->bpart) hipFree(c->bpart);
-    if (c->wpart) hipFree(c->wpart);
-    if (c->tables) hipFree(c->tables);
-    if (c->mass_part) hipFree(c->mass_part);
-    if (c->staging) hipFree(c->staging);
-    for (hipEvent_t e : c->ev) hipEventDestroy(e);
+    if (c->b) (void)hipFree(c->b);
+    if (c->mu) (void)hipFree(c->mu);
+    if (c->S) (void)hipFree(c->S);
+    if (c->bpart) (void)hipFree(c->bpart);
+    if (c->wpart) (void)hipFree(c->wpart);
+    if (c->tables) (void)hipFree(c->tables);
+    if (c->mass_part) (void)hipFree(c->mass_part);
+    if (c->staging) (void)hipFree(c->staging);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -568,7 +570,7 @@ int m2p_set_inflow(m2p_ctx* c, const m2p_inflow* seg, int32_t nseg)
     }
     K.nseg = nseg;
     HIPCHK(hipStreamSynchronize(c->stream));
-    if (c->tables) hipFree(c->tables);
+    if (c->tables) (void)hipFree(c->tables);
     c->tables = nullptr;
     size_t nb = std::max<size_t>(tab.size(), 8) * sizeof(double);
     if (hipMalloc(&c->tables, nb) != hipSuccess) return fail(M2P_ENOMEM, "table allocation failed");

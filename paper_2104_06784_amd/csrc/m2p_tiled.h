@@ -18,16 +18,27 @@ namespace m2p {
 
 constexpr int kStripOut = 60;  // output columns per wavefront
 
-template <typename T>
-__device__ __forceinline__ T from_right(T v)  // value of lane + 1
+// Wavefront-wide shifts by one lane with DPP (wave_shl:1 / wave_shr:1, a
+// VALU move with no LDS round trip).  The edge lane without a source gets 0;
+// edge lanes are halo lanes whose results never reach an output column.
+__device__ __forceinline__ int dpp_right_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_left_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+
+__device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_right_i(__float_as_int(v))); }
+__device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_left_i(__float_as_int(v))); }
+
+__device__ __forceinline__ double from_right(double v)
 {
-    return __shfl_down(v, 1, 64);
+    const long long x = __double_as_longlong(v);
+    const int lo = dpp_right_i((int)(x & 0xffffffffll)), hi = dpp_right_i((int)(x >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-template <typename T>
-__device__ __forceinline__ T from_left(T v)  // value of lane - 1
+__device__ __forceinline__ double from_left(double v)
 {
-    return __shfl_up(v, 1, 64);
+    const long long x = __double_as_longlong(v);
+    const int lo = dpp_left_i((int)(x & 0xffffffffll)), hi = dpp_left_i((int)(x >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // Per-row quantities kept in the rolling window.
@@ -61,8 +72,20 @@ __device__ __forceinline__ void visc_yface_rows(const RowD<T>& a, const RowD<T>&
     visc_yface_c(a.u, a.w, b.u, b.w, a.cdxu, a.cdxw, b.cdxu, b.cdxw, a.Jh, b.Jh, a.g, b.g, K.deta, GX, GY);
 }
 
+#ifndef M2P_TILED_WAVES_PER_EU
+#define M2P_TILED_WAVES_PER_EU 0
+#endif
+#ifndef M2P_TILED_UNROLL
+#define M2P_TILED_UNROLL 1
+#endif
+#if M2P_TILED_WAVES_PER_EU > 0
+#define M2P_TILED_ATTR __attribute__((amdgpu_waves_per_eu(M2P_TILED_WAVES_PER_EU, M2P_TILED_WAVES_PER_EU)))
+#else
+#define M2P_TILED_ATTR
+#endif
+
 template <typename T, int STAGE>
-__global__ void __launch_bounds__(256) k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout,
+__global__ void __launch_bounds__(256) M2P_TILED_ATTR k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout,
                                                      const T* __restrict__ b, const T* __restrict__ mu,
                                                      DevScalars* __restrict__ S, double* __restrict__ bpart,
                                                      double* __restrict__ wpart, int nmax, int R, int nstrips,
@@ -151,19 +174,30 @@ __global__ void __launch_bounds__(256) k_stage_tiled(KParams P, const T* __restr
     T vGX = T(0), vGY = T(0);
     if (P.visc)
         visc_yface_rows(Dm, D0, K, vGX, vGY);
-    T Uc[NF], Un1[NF];  // rows j, j+1
+    T Uc[NF], Un1[NF], U2[NF];  // rows j, j+1, j+2
 #pragma unroll
     for (int k = 0; k < NF; k++) {
         Uc[k] = U0[k];
         Un1[k] = U1[k];
     }
-    T bj = b0, bj1 = b1;
+    loadU(r0 + 2, U2);
+    T bj = b0, bj1 = b1, bj2 = loadB(r0 + 2);
 
+#pragma unroll M2P_TILED_UNROLL
     for (int j = r0; j < r1; j++) {
-        // ---- new row j+2 (state) and geometry / derived quantities of row j+1
-        T U2[NF];
-        loadU(j + 2, U2);
-        const T bj2 = loadB(j + 2);
+        // ---- prefetch row j+3 (consumed next iteration) and this row's own
+        // values needed at the end (U^n for the Heun average, tan delta)
+        T U3[NF];
+        const int rn = j + 3 <= P.ny + 1 ? j + 3 : P.ny + 1;
+        loadU(rn, U3);
+        const T bj3 = loadB(rn);
+        const size_t cself = (size_t)j * P.pitch + (out_lane ? col : 0);
+        T unr[NF];
+        if (STAGE == 2) {
+#pragma unroll
+            for (int k = 0; k < NF; k++) unr[k] = Un[k * fs + cself];
+        }
+        const T tmu = P.has_mu ? mu[cself] : K.tan_d;
         RowD<T> D1;
         make_row(K, Un1, bj1, bj, bj2, D1);
         T uL[NF], uR[NF];
@@ -275,13 +309,11 @@ __global__ void __launch_bounds__(256) k_stage_tiled(KParams P, const T* __restr
         }
         // ---- update and write
         if (out_lane) {
-            const size_t c = (size_t)j * P.pitch + col;
-            const T tmu = P.has_mu ? mu[c] : K.tan_d;
             T out[NF];
             clamps += update_cell(K, Uc, D0.g, HxL, Hx, Hy, HyN, Sr, svx, svy, dt, tmu, out);
             if (STAGE == 2) {
 #pragma unroll
-                for (int k = 0; k < NF; k++) out[k] = T(0.5) * (Un[k * fs + c] + out[k]);
+                for (int k = 0; k < NF; k++) out[k] = T(0.5) * (unr[k] + out[k]);
                 T a[2];
                 side_speed(K, out, D0.g, 0, a);
                 amx = fmax(amx, (double)(a[0] > a[1] ? a[0] : a[1]));
@@ -291,7 +323,7 @@ __global__ void __launch_bounds__(256) k_stage_tiled(KParams P, const T* __restr
 #pragma unroll
             for (int k = 0; k < NF; k++) {
                 if (!isfinite(out[k])) bad = 1;
-                Uout[k * fs + c] = out[k];
+                Uout[k * fs + cself] = out[k];
             }
         }
         // ---- roll the window
@@ -301,6 +333,7 @@ __global__ void __launch_bounds__(256) k_stage_tiled(KParams P, const T* __restr
             sy0[k] = sy1[k];
             Uc[k] = Un1[k];
             Un1[k] = U2[k];
+            U2[k] = U3[k];
         }
         vGX = vGXN;
         vGY = vGYN;
@@ -308,6 +341,7 @@ __global__ void __launch_bounds__(256) k_stage_tiled(KParams P, const T* __restr
         D0 = D1;
         bj = bj1;
         bj1 = bj2;
+        bj2 = bj3;
     }
 
     // ---- wavefront reductions (fixed butterfly => deterministic in lane 0)
