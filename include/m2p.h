@@ -207,6 +207,54 @@ int m2p_kernel_times(m2p_ctx *c, double *ms3, int64_t *nsteps);
  * field k starts at ptr + k * ny * pitch. */
 int m2p_state_device_ptr(m2p_ctx *c, void **ptr, int64_t *pitch);
 
+/* ---------------------------------------------------------------------------
+ * Batched ensembles: nscen independent scenarios of uneven size advanced
+ * together (the paper's motivation of many runs for parameter back-calculation,
+ * Sect. 1 and Sect. 5).  All states share one ragged SoA arena; one persistent
+ * launch per RK stage walks a work list of (scenario, strip, row block) items;
+ * every scenario keeps its own CFL step, time, integrals and status, so member
+ * i advances exactly like a single-scenario context of the same tile height.
+ * Step sequences are captured into a HIP graph and replayed.  Mode-I only (no
+ * inflow segments).  Arrays are per scenario with that scenario's grid.
+ * ------------------------------------------------------------------------- */
+typedef struct m2p_batch m2p_batch;
+
+/* grids, params, dems: nscen entries (1..2047); tan_mu NULL or nscen entries,
+ * each NULL (uniform delta_b) or a per-cell tan(delta_b) field.  hip_stream
+ * NULL = a private non-blocking stream.  Errors: EINVAL (any scenario), ENOMEM, EHIP. */
+int m2p_batch_create(m2p_batch **out, int32_t nscen, const m2p_grid *grids, const m2p_params *params,
+                     const double *const *dems, const double *const *tan_mu, int32_t prec, void *hip_stream);
+void m2p_batch_destroy(m2p_batch *b);
+
+/* State of scenario i from SI host fields, as m2p_set_state. */
+int m2p_batch_set_state(m2p_batch *b, int32_t i, int32_t depth_kind, const double *h, const double *phi_s,
+                        const double *vxs, const double *vys, const double *vxf, const double *vyf);
+
+/* Enqueue nsteps steps of every scenario (graph-captured chunks, no host sync). */
+int m2p_batch_run(m2p_batch *b, int64_t nsteps);
+
+/* Wait; returns M2P_ENONFINITE / M2P_EDTFLOOR if any scenario's status is set. */
+int m2p_batch_synchronize(m2p_batch *b);
+
+/* Raw state, output fields and diagnostics of scenario i (as the single-context calls). */
+int m2p_batch_get_state_raw(m2p_batch *b, int32_t i, double *U);
+int m2p_batch_get_fields(m2p_batch *b, int32_t i, double *h, double *phi_s, double *vxs, double *vys,
+                         double *vxf, double *vyf);
+int m2p_batch_get_diag(m2p_batch *b, int32_t i, m2p_diag *d);
+
+/* Tile rows per wavefront (>= 4) and persistent workgroups (0 = default). */
+int m2p_batch_set_tile(m2p_batch *b, int32_t rows, int32_t blocks);
+
+/* Steps per captured graph (0 = launch kernels directly). */
+int m2p_batch_set_graph(m2p_batch *b, int32_t chunk);
+
+/* Time trial_steps steps per candidate tile shape on the batch itself (state
+ * and scalars restored after each trial) and keep the fastest. */
+int m2p_batch_autotune(m2p_batch *b, int32_t trial_steps, int32_t *rows, int32_t *blocks, double *ms_per_step);
+
+/* Scenario count, total cells, tile rows, persistent workgroups, work items. */
+int m2p_batch_info(m2p_batch *b, int32_t *nscen, int64_t *cells, int32_t *rows, int32_t *blocks, int32_t *nwork);
+
 #ifdef __cplusplus
 }
 #endif

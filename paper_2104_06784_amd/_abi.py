@@ -90,6 +90,21 @@ SIGNATURES = {
     "m2p_state_device_ptr": (C.c_int, [_P, C.POINTER(_P), C.POINTER(C.c_int64)]),
     "m2p_set_profiling": (C.c_int, [_P, C.c_int32]),
     "m2p_kernel_times": (C.c_int, [_P, _dp, C.POINTER(C.c_int64)]),
+    "m2p_batch_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.POINTER(Grid), C.POINTER(Params),
+                                   C.POINTER(_dp), C.POINTER(_dp), C.c_int32, _P]),
+    "m2p_batch_destroy": (None, [_P]),
+    "m2p_batch_set_state": (C.c_int, [_P, C.c_int32, C.c_int32, _dp, _dp, _dp, _dp, _dp, _dp]),
+    "m2p_batch_run": (C.c_int, [_P, C.c_int64]),
+    "m2p_batch_synchronize": (C.c_int, [_P]),
+    "m2p_batch_get_state_raw": (C.c_int, [_P, C.c_int32, _dp]),
+    "m2p_batch_get_fields": (C.c_int, [_P, C.c_int32, _dp, _dp, _dp, _dp, _dp, _dp]),
+    "m2p_batch_get_diag": (C.c_int, [_P, C.c_int32, C.POINTER(Diag)]),
+    "m2p_batch_set_tile": (C.c_int, [_P, C.c_int32, C.c_int32]),
+    "m2p_batch_set_graph": (C.c_int, [_P, C.c_int32]),
+    "m2p_batch_autotune": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_double)]),
+    "m2p_batch_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
 }
 
 

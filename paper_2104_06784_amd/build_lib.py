@@ -30,6 +30,7 @@ PER_FILE = {
                     "-fgpu-flush-denormals-to-zero", "-freciprocal-math", "-fno-signed-zeros",
                     "-fno-trapping-math"],
     "m2p_abi.hip": ["-ffp-contract=off"],
+    "m2p_batch.hip": ["-ffp-contract=off"],
 }
 
 

@@ -11,13 +11,14 @@
 #include <vector>
 
 #include "../../include/m2p.h"
+#include "m2p_host.h"
 #include "m2p_launch.h"
 
 using namespace m2p;
 
-namespace {
+namespace m2p {
 
-thread_local std::string g_err;
+static thread_local std::string g_err;
 
 int fail(int code, const std::string& msg)
 {
@@ -31,15 +32,9 @@ int hip_fail(hipError_t e, const char* what)
     return M2P_EHIP;
 }
 
-#define HIPCHK(x)                                   \
-    do {                                            \
-        hipError_t e_ = (x);                        \
-        if (e_ != hipSuccess) return hip_fail(e_, #x); \
-    } while (0)
-
 size_t round_up(size_t a, size_t m) { return (a + m - 1) / m * m; }
 
-}  // namespace
+}  // namespace m2p
 
 struct m2p_ctx {
     int dev = 0;
@@ -187,92 +182,12 @@ static int read_scalars(m2p_ctx* c, DevScalars* hs)
     return M2P_OK;
 }
 
-extern "C" {
+namespace m2p {
 
-const char* m2p_version(void) { return "m2p 0.1 (gfx950)"; }
-
-const char* m2p_strerror(int code)
+// Dimensionless constants of a scenario (Sect. 2.2 scheme, Appendix A model).
+KParams make_kparams(const m2p_grid* g, const m2p_params* p, bool has_mu)
 {
-    switch (code) {
-        case M2P_OK: return "ok";
-        case M2P_EINVAL: return "invalid argument";
-        case M2P_ENOMEM: return "out of device memory";
-        case M2P_EHIP: return "HIP runtime error";
-        case M2P_ENONFINITE: return "non-finite value on the device";
-        case M2P_ENEGDEPTH: return "negative thickness";
-        case M2P_EDTFLOOR: return "time step below floor";
-        case M2P_EMAXSTEPS: return "maximum number of steps reached";
-        case M2P_ESTATE: return "invalid call order or poisoned context";
-        default: return "unknown status";
-    }
-}
-
-const char* m2p_last_error(void) { return g_err.c_str(); }
-
-int m2p_device_count(int* count)
-{
-    if (!count) return fail(M2P_EINVAL, "count is NULL");
-    int n = 0;
-    hipError_t e = hipGetDeviceCount(&n);
-    *count = e == hipSuccess ? n : 0;
-    return M2P_OK;
-}
-
-int m2p_buffer_bytes(const m2p_grid* g, int32_t prec, size_t* state_bytes)
-{
-    if (!g || !state_bytes) return fail(M2P_EINVAL, "NULL argument");
-    if (g->nx < 4 || g->ny < 4) return fail(M2P_EINVAL, "grid must be at least 4 x 4");
-    if (prec != M2P_FP64 && prec != M2P_FP32) return fail(M2P_EINVAL, "precision must be M2P_FP64 or M2P_FP32");
-    size_t esz = prec == M2P_FP64 ? 8 : 4;
-    *state_bytes = (size_t)NF * (size_t)g->ny * round_up((size_t)g->nx, 64) * esz;
-    return M2P_OK;
-}
-
-static int validate(const m2p_grid* g, const m2p_params* p, int32_t prec, const double* dem)
-{
-    if (!g || !p || !dem) return fail(M2P_EINVAL, "NULL argument");
-    if (g->nx < 4 || g->ny < 4) return fail(M2P_EINVAL, "grid must be at least 4 x 4");
-    if ((int64_t)g->nx * (int64_t)g->ny > (int64_t)1 << 31) return fail(M2P_EINVAL, "grid too large");
-    if (!(g->dx > 0) || !(g->dy > 0) || !std::isfinite(g->dx) || !std::isfinite(g->dy))
-        return fail(M2P_EINVAL, "dx, dy must be positive");
-    if (prec != M2P_FP64 && prec != M2P_FP32) return fail(M2P_EINVAL, "precision must be M2P_FP64 or M2P_FP32");
-    if (!(p->delta_b_deg >= 0.0 && p->delta_b_deg < 90.0)) return fail(M2P_EINVAL, "delta_b outside [0, 90)");
-    if (!(p->cfl > 0.0 && p->cfl <= 1.0)) return fail(M2P_EINVAL, "cfl outside (0, 1]");
-    if (!(p->rho_s > 0.0) || !(p->rho_f >= 0.0) || !(p->rho_f < p->rho_s))
-        return fail(M2P_EINVAL, "densities must satisfy 0 <= rho_f < rho_s");
-    if (!(p->L > 0.0) || !(p->H > 0.0) || !(p->g > 0.0)) return fail(M2P_EINVAL, "L, H, g must be positive");
-    if (!(p->c_d >= 0.0) || !(p->inv_n_r >= 0.0) || !(p->theta_b >= 0.0) || !(p->m_dry > 0.0) ||
-        !(p->a_min > 0.0) || !std::isfinite(p->chi))
-        return fail(M2P_EINVAL, "c_d, 1/N_R, theta_b >= 0 and m_dry, a_min > 0 required");
-    for (int s = 0; s < 4; s++)
-        if (p->bc[s] != M2P_BC_TRANSMISSIVE && p->bc[s] != M2P_BC_WALL) return fail(M2P_EINVAL, "bad boundary mode");
-    size_t n = (size_t)g->nx * g->ny;
-    for (size_t k = 0; k < n; k++)
-        if (!std::isfinite(dem[k])) return fail(M2P_EINVAL, "non-finite DEM value");
-    return M2P_OK;
-}
-
-int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t prec, const double* dem,
-               const double* tan_mu, void* hip_stream)
-{
-    if (!out) return fail(M2P_EINVAL, "out is NULL");
-    *out = nullptr;
-    int rc = validate(g, p, prec, dem);
-    if (rc) return rc;
-    const size_t n = (size_t)g->nx * g->ny;
-    if (tan_mu)
-        for (size_t k = 0; k < n; k++)
-            if (!(tan_mu[k] >= 0.0) || !std::isfinite(tan_mu[k])) return fail(M2P_EINVAL, "bad tan_mu value");
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(M2P_EHIP, "no HIP device");
-    m2p_ctx* c = new m2p_ctx();
-    HIPCHK(hipGetDevice(&c->dev));
-    c->stream = (hipStream_t)hip_stream;
-    c->prec = prec;
-    c->esz = prec == M2P_FP64 ? 8 : 4;
-    c->g = *g;
-    c->p = *p;
-    KParams& K = c->kp;
+    KParams K;
     std::memset(&K, 0, sizeof(K));
     K.nx = g->nx;
     K.ny = g->ny;
@@ -280,7 +195,7 @@ int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t pr
     K.bpitch = (int)(BOFF + round_up((size_t)g->nx + BHALO, 64));
     for (int s = 0; s < 4; s++) K.bc[s] = p->bc[s];
     K.flags = p->flags;
-    K.has_mu = tan_mu ? 1 : 0;
+    K.has_mu = has_mu ? 1 : 0;
     K.visc = p->inv_n_r != 0.0 ? 1 : 0;
     K.eps = p->H / p->L;
     K.alpha = p->rho_f / p->rho_s;
@@ -304,13 +219,18 @@ int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t pr
     K.cfl = p->cfl;
     K.a_floor = p->a_min / K.V;
     K.dt_floor = 1e-12 * std::min(K.dxi, K.deta) / std::sqrt(K.eps);
+    return K;
+}
 
-    // padded DEM (b / L), linear extrapolation: along Y per column, then along X per row
-    const int nx = g->nx, ny = g->ny, bp = K.bpitch;
+// Padded DEM (b / L) with the two-cell ring continued by linear
+// extrapolation: along Y for every column, then along X for every row.
+std::vector<double> padded_dem(const KParams& K, const double* dem, double L)
+{
+    const int nx = K.nx, ny = K.ny, bp = K.bpitch;
     std::vector<double> bd((size_t)(ny + 2 * BHALO) * bp, 0.0);
     auto B = [&](int i, int j) -> double& { return bd[(size_t)(j + BHALO) * bp + BOFF + i]; };
     for (int j = 0; j < ny; j++)
-        for (int i = 0; i < nx; i++) B(i, j) = dem[(size_t)j * nx + i] / p->L;
+        for (int i = 0; i < nx; i++) B(i, j) = dem[(size_t)j * nx + i] / L;
     for (int i = 0; i < nx; i++) {
         double b0 = B(i, 0), b1 = B(i, 1), bn = B(i, ny - 1), bm = B(i, ny - 2);
         for (int k = 1; k <= BHALO; k++) {
@@ -325,6 +245,100 @@ int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t pr
             B(nx - 1 + k, j) = bn + (double)k * (bn - bm);
         }
     }
+    return bd;
+}
+
+int validate_scenario(const m2p_grid* g, const m2p_params* p, int32_t prec, const double* dem)
+{
+    if (!g || !p || !dem) return fail(M2P_EINVAL, "NULL argument");
+    if (g->nx < 4 || g->ny < 4) return fail(M2P_EINVAL, "grid must be at least 4 x 4");
+    if ((int64_t)g->nx * (int64_t)g->ny > (int64_t)1 << 31) return fail(M2P_EINVAL, "grid too large");
+    if (!(g->dx > 0) || !(g->dy > 0) || !std::isfinite(g->dx) || !std::isfinite(g->dy))
+        return fail(M2P_EINVAL, "dx, dy must be positive");
+    if (prec != M2P_FP64 && prec != M2P_FP32) return fail(M2P_EINVAL, "precision must be M2P_FP64 or M2P_FP32");
+    if (!(p->delta_b_deg >= 0.0 && p->delta_b_deg < 90.0)) return fail(M2P_EINVAL, "delta_b outside [0, 90)");
+    if (!(p->cfl > 0.0 && p->cfl <= 1.0)) return fail(M2P_EINVAL, "cfl outside (0, 1]");
+    if (!(p->rho_s > 0.0) || !(p->rho_f >= 0.0) || !(p->rho_f < p->rho_s))
+        return fail(M2P_EINVAL, "densities must satisfy 0 <= rho_f < rho_s");
+    if (!(p->L > 0.0) || !(p->H > 0.0) || !(p->g > 0.0)) return fail(M2P_EINVAL, "L, H, g must be positive");
+    if (!(p->c_d >= 0.0) || !(p->inv_n_r >= 0.0) || !(p->theta_b >= 0.0) || !(p->m_dry > 0.0) ||
+        !(p->a_min > 0.0) || !std::isfinite(p->chi))
+        return fail(M2P_EINVAL, "c_d, 1/N_R, theta_b >= 0 and m_dry, a_min > 0 required");
+    for (int s = 0; s < 4; s++)
+        if (p->bc[s] != M2P_BC_TRANSMISSIVE && p->bc[s] != M2P_BC_WALL) return fail(M2P_EINVAL, "bad boundary mode");
+    size_t n = (size_t)g->nx * g->ny;
+    for (size_t k = 0; k < n; k++)
+        if (!std::isfinite(dem[k])) return fail(M2P_EINVAL, "non-finite DEM value");
+    return M2P_OK;
+}
+
+}  // namespace m2p
+
+extern "C" {
+
+const char* m2p_version(void) { return "m2p 0.1 (gfx950)"; }
+
+const char* m2p_strerror(int code)
+{
+    switch (code) {
+        case M2P_OK: return "ok";
+        case M2P_EINVAL: return "invalid argument";
+        case M2P_ENOMEM: return "out of device memory";
+        case M2P_EHIP: return "HIP runtime error";
+        case M2P_ENONFINITE: return "non-finite value on the device";
+        case M2P_ENEGDEPTH: return "negative thickness";
+        case M2P_EDTFLOOR: return "time step below floor";
+        case M2P_EMAXSTEPS: return "maximum number of steps reached";
+        case M2P_ESTATE: return "invalid call order or poisoned context";
+        default: return "unknown status";
+    }
+}
+
+const char* m2p_last_error(void) { return m2p::g_err.c_str(); }
+
+int m2p_device_count(int* count)
+{
+    if (!count) return fail(M2P_EINVAL, "count is NULL");
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    *count = e == hipSuccess ? n : 0;
+    return M2P_OK;
+}
+
+int m2p_buffer_bytes(const m2p_grid* g, int32_t prec, size_t* state_bytes)
+{
+    if (!g || !state_bytes) return fail(M2P_EINVAL, "NULL argument");
+    if (g->nx < 4 || g->ny < 4) return fail(M2P_EINVAL, "grid must be at least 4 x 4");
+    if (prec != M2P_FP64 && prec != M2P_FP32) return fail(M2P_EINVAL, "precision must be M2P_FP64 or M2P_FP32");
+    size_t esz = prec == M2P_FP64 ? 8 : 4;
+    *state_bytes = (size_t)NF * (size_t)g->ny * round_up((size_t)g->nx, 64) * esz;
+    return M2P_OK;
+}
+
+int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t prec, const double* dem,
+               const double* tan_mu, void* hip_stream)
+{
+    if (!out) return fail(M2P_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_scenario(g, p, prec, dem);
+    if (rc) return rc;
+    const size_t n = (size_t)g->nx * g->ny;
+    if (tan_mu)
+        for (size_t k = 0; k < n; k++)
+            if (!(tan_mu[k] >= 0.0) || !std::isfinite(tan_mu[k])) return fail(M2P_EINVAL, "bad tan_mu value");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(M2P_EHIP, "no HIP device");
+    m2p_ctx* c = new m2p_ctx();
+    HIPCHK(hipGetDevice(&c->dev));
+    c->stream = (hipStream_t)hip_stream;
+    c->prec = prec;
+    c->esz = prec == M2P_FP64 ? 8 : 4;
+    c->g = *g;
+    c->p = *p;
+    c->kp = make_kparams(g, p, tan_mu != nullptr);
+    const KParams& K = c->kp;
+    const int nx = g->nx, ny = g->ny;
+    std::vector<double> bd = padded_dem(K, dem, p->L);
     auto cleanup = [&](int code) {
         m2p_destroy(c);
         return code;

@@ -377,10 +377,10 @@ __device__ __forceinline__ double inflow_rate(const KParams& P, const double* ta
 // Single wavefront.  mode 0: close the step just taken (time, integrals);
 // both modes: next CFL dt from the speed maxima, inflow states of the next
 // step's two stages, reset of the maxima.
-template <typename T>
-__global__ void __launch_bounds__(256) k_finalize(KParams P, DevScalars* S, const double* __restrict__ bpart,
-                                                  int n_we, int n_sn, int nmax, const double* __restrict__ tables,
-                                                  int mode, const double* __restrict__ wpart, int nw)
+// Body of the per-step finalize, run by one 256-thread workgroup.
+__device__ __forceinline__ void finalize_body(const KParams& P, DevScalars* S, const double* __restrict__ bpart,
+                                              int n_we, int n_sn, int nmax, const double* __restrict__ tables,
+                                              int mode, const double* __restrict__ wpart, int nw)
 {
     // Fixed-order reductions (deterministic): boundary outflow partials, 16
     // threads per (stage, side, phase); per-wave / per-block partials of the
@@ -486,6 +486,14 @@ __global__ void __launch_bounds__(256) k_finalize(KParams P, DevScalars* S, cons
         inflow_state(P, tables, s, t, S->inflow[0][s]);
         inflow_state(P, tables, s, t + dt, S->inflow[1][s]);
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_finalize(KParams P, DevScalars* S, const double* __restrict__ bpart,
+                                                  int n_we, int n_sn, int nmax, const double* __restrict__ tables,
+                                                  int mode, const double* __restrict__ wpart, int nw)
+{
+    finalize_body(P, S, bpart, n_we, n_sn, nmax, tables, mode, wpart, nw);
 }
 
 // ------------------------------------------------- conversions, reductions

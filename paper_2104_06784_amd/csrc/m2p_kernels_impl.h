@@ -76,4 +76,18 @@ hipError_t Launch<M2P_REAL>::mass(const KParams& P, const Bufs& B, hipStream_t s
     return hipGetLastError();
 }
 
+template <>
+hipError_t Launch<M2P_REAL>::batch_part(const ScenDesc<M2P_REAL>* scen, int nscen, const int* work, int nwork, int R,
+                                        int blocks, hipStream_t st, int part, int mode)
+{
+    using T = M2P_REAL;
+    if (part == 2)
+        hipLaunchKernelGGL((k_finalize_batch<T>), dim3(nscen), dim3(256), 0, st, scen, mode);
+    else if (part == 0)
+        hipLaunchKernelGGL((k_stage_batch<T, 1>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);
+    else
+        hipLaunchKernelGGL((k_stage_batch<T, 2>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);
+    return hipGetLastError();
+}
+
 }  // namespace m2p

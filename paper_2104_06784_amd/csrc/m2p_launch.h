@@ -34,6 +34,21 @@ struct Bufs {
 
 constexpr int kMassBlocks = 1024;
 
+// Scenario record of a batched ensemble: constants and device pointers.
+template <typename T>
+struct ScenDesc {
+    KParams P;
+    T* U;
+    T* Us;
+    const T* b;
+    const T* mu;
+    DevScalars* S;
+    double* bpart;
+    double* wpart;
+    const double* tables;
+    int nmax, nstrips, nrb, nw_ref;
+};
+
 Shape make_shape(const KParams& P, int variant, int rows);
 
 template <typename T>
@@ -45,6 +60,10 @@ struct Launch {
                                 hipStream_t st);
     static hipError_t get_fields(const KParams& P, const Bufs& B, double* f, hipStream_t st);
     static hipError_t mass(const KParams& P, const Bufs& B, hipStream_t st);
+    // batched ensemble: part 0 / 1 = persistent stage kernels over the work
+    // list, part 2 = one finalize workgroup per scenario (mode 0 or 1)
+    static hipError_t batch_part(const ScenDesc<T>* scen, int nscen, const int* work, int nwork, int R, int blocks,
+                                 hipStream_t st, int part, int mode);
 };
 
 }  // namespace m2p

@@ -13,6 +13,7 @@
 #pragma once
 
 #include "m2p_device.h"
+#include "m2p_launch.h"
 
 namespace m2p {
 
@@ -84,24 +85,15 @@ __device__ __forceinline__ void visc_yface_rows(const RowD<T>& a, const RowD<T>&
 #define M2P_TILED_ATTR
 #endif
 
+// One wavefront's share of a stage: strip `strip`, row block `rb` of one
+// scenario.  Partials go to wave slot `wslot` of that scenario.
 template <typename T, int STAGE>
-__global__ void __launch_bounds__(256) M2P_TILED_ATTR k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout,
-                                                     const T* __restrict__ b, const T* __restrict__ mu,
-                                                     DevScalars* __restrict__ S, double* __restrict__ bpart,
-                                                     double* __restrict__ wpart, int nmax, int R, int nstrips,
-                                                     int nrb)
+__device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __restrict__ Uin, const T* Un, T* Uout,
+                                                 const T* __restrict__ b, const T* __restrict__ mu,
+                                                 DevScalars* __restrict__ S, double* __restrict__ bpart,
+                                                 double* __restrict__ wpart, int nmax, int R, int nstrips, int nrb,
+                                                 int strip, int rb, int wslot, int lane)
 {
-    // XCD-aware block order: consecutive block ids land on different XCDs, so
-    // give each XCD a contiguous range of waves (neighbouring strips share halo
-    // columns in that XCD's L2).
-    const int nblk = gridDim.x;
-    int bid = blockIdx.x;
-    const int nfull = (nblk / 8) * 8;
-    if (bid < nfull) bid = (bid % 8) * (nfull / 8) + bid / 8;
-    const int lane = threadIdx.x & 63;
-    const int wid = bid * 4 + (threadIdx.x >> 6);
-    const int strip = wid % nstrips, rb = wid / nstrips;
-    if (rb >= nrb) return;  // whole wavefront
     const Consts<T> K(P);
     const size_t fs = (size_t)P.ny * P.pitch;
     const int col = strip * kStripOut - 2 + lane;
@@ -356,7 +348,7 @@ __global__ void __launch_bounds__(256) M2P_TILED_ATTR k_stage_tiled(KParams P, c
     }
     if (lane == 0) {
         const int st = STAGE - 1;
-        double* wp = wpart + ((size_t)st * nstrips * nrb + wid) * 4;
+        double* wp = wpart + ((size_t)st * nstrips * nrb + wslot) * 4;
         wp[0] = amx;
         wp[1] = amy;
         wp[2] = (double)clamps;
@@ -378,6 +370,67 @@ __global__ void __launch_bounds__(256) M2P_TILED_ATTR k_stage_tiled(KParams P, c
             bpart[((st * 4 + 3) * nmax + strip) * 2 + 1] = ob[7];
         }
     }
+}
+
+template <typename T, int STAGE>
+__global__ void __launch_bounds__(256) M2P_TILED_ATTR k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un,
+                                                                    T* Uout, const T* __restrict__ b,
+                                                                    const T* __restrict__ mu,
+                                                                    DevScalars* __restrict__ S,
+                                                                    double* __restrict__ bpart,
+                                                                    double* __restrict__ wpart, int nmax, int R,
+                                                                    int nstrips, int nrb)
+{
+    // XCD-aware block order: consecutive block ids land on different XCDs, so
+    // give each XCD a contiguous range of waves (neighbouring strips share halo
+    // columns in that XCD's L2).
+    const int nblk = gridDim.x;
+    int bid = blockIdx.x;
+    const int nfull = (nblk / 8) * 8;
+    if (bid < nfull) bid = (bid % 8) * (nfull / 8) + bid / 8;
+    const int lane = threadIdx.x & 63;
+    // wavefront-uniform by construction; readfirstlane lets the compiler keep
+    // the strip, row bounds and loop control in scalar registers
+    const int wid = __builtin_amdgcn_readfirstlane(bid * 4 + (int)(threadIdx.x >> 6));
+    const int strip = wid % nstrips, rb = wid / nstrips;
+    if (rb >= nrb) return;  // whole wavefront
+    stage_tiled_wave<T, STAGE>(P, Uin, Un, Uout, b, mu, S, bpart, wpart, nmax, R, nstrips, nrb, strip, rb, wid, lane);
+}
+
+// Persistent batched stage: a fixed grid of wavefronts walks the work list
+// (scenario, strip, row block) with a grid stride; every scenario keeps its
+// own time step and partial slots, so results equal single-scenario runs.
+template <typename T, int STAGE>
+__global__ void __launch_bounds__(256) M2P_TILED_ATTR k_stage_batch(const ScenDesc<T>* __restrict__ scen,
+                                                                    const int* __restrict__ work, int nwork, int R)
+{
+    const int nblk = gridDim.x;
+    int bid = blockIdx.x;
+    const int nfull = (nblk / 8) * 8;
+    if (bid < nfull) bid = (bid % 8) * (nfull / 8) + bid / 8;
+    const int lane = threadIdx.x & 63;
+    const int nwaves = nblk * 4;
+    const int w0 = __builtin_amdgcn_readfirstlane(bid * 4 + (int)(threadIdx.x >> 6));
+    for (int w = w0; w < nwork; w += nwaves) {
+        const int item = __builtin_amdgcn_readfirstlane(work[w]);
+        const int sc = item >> 20, local = item & 0xfffff;
+        const ScenDesc<T>& D = scen[sc];
+        const int strip = local % D.nstrips, rb = local / D.nstrips;
+        if (STAGE == 1)
+            stage_tiled_wave<T, 1>(D.P, D.U, D.U, D.Us, D.b, D.mu, D.S, D.bpart, D.wpart, D.nmax, R, D.nstrips, D.nrb,
+                                   strip, rb, local, lane);
+        else
+            stage_tiled_wave<T, 2>(D.P, D.Us, D.U, D.U, D.b, D.mu, D.S, D.bpart, D.wpart, D.nmax, R, D.nstrips, D.nrb,
+                                   strip, rb, local, lane);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_finalize_batch(const ScenDesc<T>* __restrict__ scen, int mode)
+{
+    const ScenDesc<T>& D = scen[blockIdx.x];
+    finalize_body(D.P, D.S, D.bpart, D.nrb, D.nstrips, D.nmax, D.tables, mode, D.wpart,
+                  mode == 1 ? D.nw_ref : D.nstrips * D.nrb);
 }
 
 }  // namespace m2p

@@ -135,3 +135,90 @@ class Sim:
         p, pitch = C.c_void_p(), C.c_int64()
         A.check(A.lib().m2p_state_device_ptr(self._h, C.byref(p), C.byref(pitch)), "m2p_state_device_ptr")
         return p.value, pitch.value
+
+
+class Batch:
+    """Ensemble of independent scenarios advanced together (``m2p_batch_*``).
+
+    ``probs`` is a list of ``inputs.Problem`` (Mode-I); all share one precision.
+    """
+
+    def __init__(self, probs, precision="f32", stream=None, set_state=True):
+        L = A.lib()
+        self.probs = list(probs)
+        n = len(self.probs)
+        self.prec = A.M2P_FP64 if precision == "f64" else A.M2P_FP32
+        grids = (A.Grid * n)(*[A.Grid(p.nx, p.ny, p.dx, p.dy) for p in self.probs])
+        params = (A.Params * n)(*[make_params(p.params) for p in self.probs])
+        self._dems = [np.ascontiguousarray(p.dem, dtype=np.float64) for p in self.probs]
+        self._mus = [None if p.tan_mu is None else np.ascontiguousarray(p.tan_mu, dtype=np.float64)
+                     for p in self.probs]
+        dem_ptrs = (A._dp * n)(*[A.dptr(d) for d in self._dems])
+        mu_ptrs = None
+        if any(m is not None for m in self._mus):
+            mu_ptrs = (A._dp * n)(*[A.dptr(m) if m is not None else A._dp() for m in self._mus])
+        sp = None if stream is None else C.c_void_p(stream.cuda_stream)
+        h = C.c_void_p()
+        A.check(L.m2p_batch_create(C.byref(h), n, grids, params, dem_ptrs, mu_ptrs, self.prec, sp),
+                "m2p_batch_create")
+        self._h = h
+        if set_state:
+            for i, p in enumerate(self.probs):
+                self.set_state(i, p.h_vert, p.phi_s, vertical=True, vel=p.vel)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            A.lib().m2p_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_state(self, i, h, phi_s, vertical=True, vel=None):
+        a = [np.ascontiguousarray(x, dtype=np.float64) for x in (h, phi_s)]
+        v = [None] * 4 if vel is None else [np.ascontiguousarray(x, dtype=np.float64) for x in vel]
+        kind = A.M2P_DEPTH_VERTICAL if vertical else A.M2P_DEPTH_NORMAL
+        A.check(A.lib().m2p_batch_set_state(self._h, i, kind, A.dptr(a[0]), A.dptr(a[1]),
+                                            *[A.dptr(x) for x in v]), "m2p_batch_set_state")
+
+    def run(self, nsteps):
+        A.check(A.lib().m2p_batch_run(self._h, int(nsteps)), "m2p_batch_run")
+
+    def synchronize(self):
+        A.check(A.lib().m2p_batch_synchronize(self._h), "m2p_batch_synchronize")
+
+    def state(self, i):
+        p = self.probs[i]
+        U = np.empty((6, p.ny, p.nx), dtype=np.float64)
+        A.check(A.lib().m2p_batch_get_state_raw(self._h, i, A.dptr(U)), "m2p_batch_get_state_raw")
+        return U
+
+    def fields(self, i):
+        p = self.probs[i]
+        out = {k: np.empty((p.ny, p.nx), dtype=np.float64) for k in Sim.FIELDS}
+        A.check(A.lib().m2p_batch_get_fields(self._h, i, *[A.dptr(out[k]) for k in Sim.FIELDS]),
+                "m2p_batch_get_fields")
+        return out
+
+    def diag(self, i):
+        d = A.Diag()
+        A.check(A.lib().m2p_batch_get_diag(self._h, i, C.byref(d)), "m2p_batch_get_diag")
+        return {k: getattr(d, k) for k, _ in A.Diag._fields_ if k != "pad"}
+
+    def set_tile(self, rows, blocks=0):
+        A.check(A.lib().m2p_batch_set_tile(self._h, int(rows), int(blocks)), "m2p_batch_set_tile")
+
+    def set_graph(self, chunk):
+        A.check(A.lib().m2p_batch_set_graph(self._h, int(chunk)), "m2p_batch_set_graph")
+
+    def autotune(self, trial_steps=5):
+        r, b, ms = C.c_int32(), C.c_int32(), C.c_double()
+        A.check(A.lib().m2p_batch_autotune(self._h, int(trial_steps), C.byref(r), C.byref(b), C.byref(ms)),
+                "m2p_batch_autotune")
+        return r.value, b.value, ms.value
+
+    def info(self):
+        n, c, r, b, w = C.c_int32(), C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
+        A.check(A.lib().m2p_batch_info(self._h, C.byref(n), C.byref(c), C.byref(r), C.byref(b), C.byref(w)),
+                "m2p_batch_info")
+        return {"nscen": n.value, "cells": c.value, "rows": r.value, "blocks": b.value, "work": w.value}
