@@ -75,6 +75,54 @@ def cpu_baseline(prob, nsteps: int) -> dict:
                       f"(FP64, OpenMP over rows), {el:.1f} s"}
 
 
+def bench_batched(stream, steps: int, warmup: int, nscen: int = 256) -> dict:
+    """Config 4: nscen scenarios of sides U{128..512} advanced together by the
+    persistent work-list kernels (autotuned tile shape, graph replay), against
+    the same scenarios run one after another with single-scenario contexts."""
+    import torch
+
+    from paper_2104_06784_amd import inputs
+    from paper_2104_06784_amd.sim import Batch, Sim
+
+    log(f"[bench] batched: generating {nscen} scenarios")
+    probs = [inputs.config4_scenario(i) for i in range(nscen)]
+    cells = sum(p.cells for p in probs)
+    b = Batch(probs, precision="f32", stream=stream)
+    rows, blocks, tune_ms = b.autotune(3)
+    b.run(warmup)
+    b.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    b.run(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    b.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    del b
+    log("[bench] batched: one-by-one reference")
+    sims = [Sim(p, precision="f32", stream=stream) for p in probs]
+    for s_ in sims:
+        s_.run(warmup)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for s_ in sims:
+        s_.run(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_1 = e0.elapsed_time(e1)
+    for s_ in sims:
+        if s_.diag()["status"] != 0:
+            raise SystemExit("device status set in the one-by-one reference")
+    del sims
+    vb = cells * steps / (ms_b / 1e3) / 1e6
+    v1 = cells * steps / (ms_1 / 1e3) / 1e6
+    return {"value": round(vb, 2), "unit": "Mcell-steps/s", "scenarios": nscen, "cells": cells, "steps": steps,
+            "ms_per_step": round(ms_b / steps, 4), "tile_rows": rows, "blocks": blocks,
+            "one_by_one_value": round(v1, 2), "one_by_one_ms_per_step": round(ms_1 / steps, 4),
+            "speedup_vs_one_by_one": round(vb / v1, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +133,7 @@ def main():
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=50, help="0 skips the batched-ensemble measurement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run 3 device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -157,6 +206,10 @@ def main():
     }
     log(f"[bench] {value:.1f} Mcell-steps/s, stage2 {t2 * 1e3:.3f} ms ({ach:.0f} GB/s)")
     del sim
+    if args.batched_steps > 0:
+        out["batched"] = bench_batched(stream, args.batched_steps, 5)
+        log(f"[bench] batched {out['batched']['value']:.1f} Mcell-steps/s "
+            f"({out['batched']['speedup_vs_one_by_one']:.2f}x one-by-one)")
     if args.copy_probe_mib > 0:
         # plain device-to-device copies of known size, so that hardware byte
         # counters of the step kernels can be calibrated against them

@@ -83,24 +83,35 @@ def test_graph_replay_equals_direct_launches():
             assert np.array_equal(a.state(i), b.state(i))
 
 
-def test_autotune_restores_state_and_keeps_results():
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_autotune_restores_state_and_keeps_results(precision):
+    """The tuner's trial steps leave no trace: the state and scalars are restored
+    bitwise, and later steps equal a fresh batch run with the chosen shape
+    (bitwise in FP64, where results do not depend on the tile height; to FP32
+    rounding in FP32, where FMA contraction may differ between the prologue and
+    the body of a row block)."""
     from paper_2104_06784_amd.sim import Batch
     probs = [_small(i, nx, ny) for i, (nx, ny) in enumerate(SHAPES)]
-    a = Batch(probs, precision="f32")
+    a = Batch(probs, precision=precision)
     a.run(5)
     before = [a.state(i) for i in range(len(probs))]
     rows, blocks, ms = a.autotune(2)
-    _say(f"[batch] autotune rows={rows} blocks={blocks} {ms:.3f} ms/step")
+    _say(f"[batch] autotune {precision} rows={rows} blocks={blocks} {ms:.3f} ms/step")
     assert rows in (8, 16, 32, 64) and blocks > 0 and ms > 0
     for i in range(len(probs)):
         assert np.array_equal(before[i], a.state(i))
         assert a.diag(i)["steps"] == 5
     a.run(10)
-    c = Batch(probs, precision="f32")
+    c = Batch(probs, precision=precision)
     c.set_tile(rows, blocks)
     c.run(15)
     for i in range(len(probs)):
-        assert np.array_equal(a.state(i), c.state(i))
+        Ua, Uc = a.state(i), c.state(i)
+        if precision == "f64":
+            assert np.array_equal(Ua, Uc)
+        else:
+            for k in range(6):
+                assert np.max(np.abs(Ua[k] - Uc[k])) <= 1e-5 * max(np.max(np.abs(Uc[k])), 1e-30)
 
 
 def test_batch_rejects_bad_input():
