@@ -208,6 +208,44 @@ int m2p_kernel_times(m2p_ctx *c, double *ms3, int64_t *nsteps);
 int m2p_state_device_ptr(m2p_ctx *c, void **ptr, int64_t *pitch);
 
 /* ---------------------------------------------------------------------------
+ * Gradients (back-calculation of friction and release volume, the paper's
+ * motivation in Sect. 1 and Sect. 5).  The step is differentiated with the
+ * time steps held fixed ("frozen dt"); non-smooth points (minmod, wave-speed
+ * maximum, Coulomb stop, positivity) take the derivative of the branch the
+ * values select.  Mode-I only.
+ * ------------------------------------------------------------------------- */
+
+/* Set (or replace) the per-cell friction field tan(delta_b), host ny*nx. */
+int m2p_set_friction_field(m2p_ctx *c, const double *tan_mu);
+
+/* Prescribe the time steps (s) of the next n steps counted from step 0 of the
+ * context (n = 0 clears): step k uses dts[k] instead of the CFL step. */
+int m2p_set_dt_schedule(m2p_ctx *c, const double *dts, int64_t n);
+
+/* Loss 1/2 sum (h - h_target)^2 dx dy of the current state (h bed-normal, m;
+ * target host ny*nx). */
+int m2p_loss(m2p_ctx *c, const double *target_h, double *loss);
+
+/* One forward-Euler stage E at the current state with the next step's dt and
+ * the inflow state of stage 0 or 1: E(U) and its directional derivative along
+ * dU (and along dmu, the friction field, if not NULL); host [6][ny][nx] raw
+ * state layout (m2p_get_state_raw), dmu ny*nx. */
+int m2p_stage_jvp(m2p_ctx *c, int32_t stage, const double *dU, const double *dmu, double *E, double *dE);
+
+/* Transpose of the same stage Jacobian applied to lam ([6][ny][nx]):
+ * lam_in = (dE/dU)^T lam and gmu = (dE/dmu)^T lam (ny*nx, may be NULL). */
+int m2p_stage_vjp(m2p_ctx *c, int32_t stage, const double *lam, double *lam_in, double *gmu);
+
+/* From the current state (the release scaled by vol_scale), run nsteps steps
+ * storing a checkpoint every ckpt_every steps and the time steps, evaluate the
+ * loss against target_h, then sweep backwards segment by segment (recomputing
+ * each segment's states) through the transposed stages.  Returns the loss,
+ * dL/d(tan delta_b) per cell (grad_mu, ny*nx, may be NULL) and dL/d(vol_scale)
+ * (may be NULL).  The context ends at the forward run's final state. */
+int m2p_adjoint_run(m2p_ctx *c, int64_t nsteps, int32_t ckpt_every, const double *target_h, double vol_scale,
+                    double *loss, double *grad_mu, double *grad_vol);
+
+/* ---------------------------------------------------------------------------
  * Batched ensembles: nscen independent scenarios of uneven size advanced
  * together (the paper's motivation of many runs for parameter back-calculation,
  * Sect. 1 and Sect. 5).  All states share one ragged SoA arena; one persistent

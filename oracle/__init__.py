@@ -76,6 +76,7 @@ def _load():
         lib.ora_get_fields.argtypes = [P, dp, dp, dp, dp, dp, dp]
         lib.ora_probe.argtypes = [P, C.c_int, C.c_int, dp]
         lib.ora_scales.argtypes = [P, dp]
+        lib.ora_set_dt_schedule.argtypes = [P, dp, C.c_int64]
         lib.ora_set_threads.restype = C.c_int
         lib.ora_set_threads.argtypes = [C.c_int]
         _lib = lib
@@ -157,6 +158,11 @@ class OracleSim:
         dts = np.zeros(int(nsteps), dtype=np.float64)
         n = _load().ora_run(self._h, int(nsteps), t_end, _ptr(dts))
         return dts[:n]
+
+    def set_dt_schedule(self, dts):
+        d = np.ascontiguousarray(dts, dtype=np.float64)
+        self._keep.append(d)
+        _load().ora_set_dt_schedule(self._h, _ptr(d), len(d))
 
     def peek_dt(self, t_end=float("inf")) -> float:
         return _load().ora_peek_dt(self._h, t_end)

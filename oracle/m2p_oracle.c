@@ -80,6 +80,8 @@ typedef struct {
     double in_s, in_f, out_s, out_f;
     double bflux[2][2]; /* per stage, per phase: net outward boundary mass flux rate */
     double last_dt;
+    double *dt_sched;   /* optional prescribed time steps (dimensionless) */
+    int64_t n_sched;
 } ora_sim;
 
 /* ---------------------------------------------------------------- helpers */
@@ -227,7 +229,7 @@ void ora_destroy(ora_sim *o)
 {
     if (!o) return;
     free(o->b); free(o->U); free(o->Us); free(o->Uss); free(o->Ue); free(o->G);
-    free(o->dnx); free(o->dny); free(o->HX); free(o->HY); free(o->tan_mu);
+    free(o->dnx); free(o->dny); free(o->HX); free(o->HY); free(o->tan_mu); free(o->dt_sched);
     for (int k = 0; k < o->nseg; k++) { free(o->seg[k].t); free(o->seg[k].Q); free(o->seg[k].phi); }
     free(o->seg);
     free(o);
@@ -792,6 +794,7 @@ static double next_dt(const ora_sim *o, double t_end_nd)
     max_speeds(o, a);
     double dtx = o->dxi / a[0], dty = o->deta / a[1];
     double dt = o->p.cfl * (dtx < dty ? dtx : dty);
+    if (o->n_sched > 0 && o->steps < o->n_sched) dt = o->dt_sched[o->steps]; /* frozen steps */
     if (t_end_nd - o->t < dt) dt = t_end_nd - o->t;
     if (dt < 0.0) dt = 0.0;
     return dt;
@@ -821,6 +824,18 @@ double ora_step(ora_sim *o, double t_end_si)
     o->steps++;
     o->last_dt = dt * o->T;
     return dt * o->T;
+}
+
+/* Prescribe the time steps (s) of steps 0 .. n-1 (n = 0 clears). */
+void ora_set_dt_schedule(ora_sim *o, const double *dts, int64_t n)
+{
+    free(o->dt_sched);
+    o->dt_sched = NULL;
+    o->n_sched = 0;
+    if (n <= 0) return;
+    o->dt_sched = (double *)xcalloc((size_t)n, sizeof(double));
+    for (int64_t k = 0; k < n; k++) o->dt_sched[k] = dts[k] / o->T;
+    o->n_sched = n;
 }
 
 /* Run ``nsteps`` steps (or until t_end); dt history (s) into dt_hist if given. */

@@ -90,6 +90,12 @@ SIGNATURES = {
     "m2p_state_device_ptr": (C.c_int, [_P, C.POINTER(_P), C.POINTER(C.c_int64)]),
     "m2p_set_profiling": (C.c_int, [_P, C.c_int32]),
     "m2p_kernel_times": (C.c_int, [_P, _dp, C.POINTER(C.c_int64)]),
+    "m2p_set_friction_field": (C.c_int, [_P, _dp]),
+    "m2p_set_dt_schedule": (C.c_int, [_P, _dp, C.c_int64]),
+    "m2p_loss": (C.c_int, [_P, _dp, _dp]),
+    "m2p_stage_jvp": (C.c_int, [_P, C.c_int32, _dp, _dp, _dp, _dp]),
+    "m2p_stage_vjp": (C.c_int, [_P, C.c_int32, _dp, _dp, _dp]),
+    "m2p_adjoint_run": (C.c_int, [_P, C.c_int64, C.c_int32, _dp, C.c_double, _dp, _dp, _dp]),
     "m2p_batch_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.POINTER(Grid), C.POINTER(Params),
                                    C.POINTER(_dp), C.POINTER(_dp), C.c_int32, _P]),
     "m2p_batch_destroy": (None, [_P]),

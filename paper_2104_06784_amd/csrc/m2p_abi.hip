@@ -5,7 +5,9 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
+#include <algorithm>
 #include <limits>
 #include <string>
 #include <vector>
@@ -775,6 +777,308 @@ int m2p_state_device_ptr(m2p_ctx* c, void** ptr, int64_t* pitch)
     if (!c || !ptr || !pitch) return fail(M2P_EINVAL, "NULL argument");
     *ptr = c->B.U;
     *pitch = c->kp.pitch;
+    return M2P_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ adjoint support
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+    int alloc(size_t bytes)
+    {
+        if (hipMalloc(&p, bytes) != hipSuccess) return m2p::fail(M2P_ENOMEM, "device allocation failed");
+        if (hipMemset(p, 0, bytes) != hipSuccess) return m2p::fail(M2P_EHIP, "device memset failed");
+        return M2P_OK;
+    }
+};
+
+// host [k][ny][nx] FP64 <-> device [k][ny][pitch] in the context precision
+int upload(m2p_ctx* c, const double* h, void* d, int nfields)
+{
+    const int nx = c->g.nx, ny = c->g.ny, pitch = c->kp.pitch;
+    const size_t n = (size_t)nx * ny;
+    if (c->prec == M2P_FP64) {
+        std::vector<double> v((size_t)nfields * ny * pitch, 0.0);
+        for (int k = 0; k < nfields; k++)
+            for (int j = 0; j < ny; j++)
+                std::memcpy(&v[((size_t)k * ny + j) * pitch], &h[k * n + (size_t)j * nx], nx * sizeof(double));
+        HIPCHK(hipMemcpy(d, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> v((size_t)nfields * ny * pitch, 0.0f);
+        for (int k = 0; k < nfields; k++)
+            for (int j = 0; j < ny; j++)
+                for (int i = 0; i < nx; i++) v[((size_t)k * ny + j) * pitch + i] = (float)h[k * n + (size_t)j * nx + i];
+        HIPCHK(hipMemcpy(d, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+    }
+    return M2P_OK;
+}
+
+int download(m2p_ctx* c, const void* d, double* h, int nfields)
+{
+    const int nx = c->g.nx, ny = c->g.ny, pitch = c->kp.pitch;
+    const size_t n = (size_t)nx * ny, tot = (size_t)nfields * ny * pitch;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::vector<double> v(tot);
+    if (c->prec == M2P_FP64) {
+        HIPCHK(hipMemcpy(v.data(), d, tot * 8, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> f(tot);
+        HIPCHK(hipMemcpy(f.data(), d, tot * 4, hipMemcpyDeviceToHost));
+        std::copy(f.begin(), f.end(), v.begin());
+    }
+    for (int k = 0; k < nfields; k++)
+        for (int j = 0; j < ny; j++) std::memcpy(&h[k * n + (size_t)j * nx], &v[((size_t)k * ny + j) * pitch], nx * 8);
+    return M2P_OK;
+}
+
+hipError_t L_jvp(m2p_ctx* c, const void* U, const void* dU, const void* dmu, int stage, void* E, void* dE)
+{
+    if (c->prec == M2P_FP64) return Launch<double>::jvp(c->kp, c->B, U, dU, dmu, stage, E, dE, c->stream);
+    return Launch<float>::jvp(c->kp, c->B, U, dU, dmu, stage, E, dE, c->stream);
+}
+
+struct VjpWork {
+    DevBuf GT, DU, FCX, FCY, SC, tmp;
+    int alloc(m2p_ctx* c)
+    {
+        const KParams& K = c->kp;
+        const size_t st = (size_t)NF * K.ny * K.pitch * c->esz;
+        int rc;
+        if ((rc = GT.alloc(st)) || (rc = DU.alloc(st)) || (rc = tmp.alloc(st))) return rc;
+        if ((rc = FCX.alloc((size_t)K.ny * (K.nx + 1) * 24 * c->esz))) return rc;
+        if ((rc = FCY.alloc((size_t)(K.ny + 1) * K.nx * 24 * c->esz))) return rc;
+        return SC.alloc((size_t)K.ny * K.nx * 34 * c->esz);
+    }
+};
+
+hipError_t L_vjp(m2p_ctx* c, VjpWork& w, const void* U, const void* lam, int stage, double dt, void* lam_in,
+                 void* gmu)
+{
+    if (c->prec == M2P_FP64)
+        return Launch<double>::vjp(c->kp, c->B, U, lam, stage, dt, w.GT.p, w.DU.p, w.FCX.p, w.FCY.p, w.SC.p, lam_in,
+                                   gmu, c->stream);
+    return Launch<float>::vjp(c->kp, c->B, U, lam, stage, dt, w.GT.p, w.DU.p, w.FCX.p, w.FCY.p, w.SC.p, lam_in, gmu,
+                              c->stream);
+}
+
+hipError_t L_axpbz(m2p_ctx* c, double a, const void* x, double b, const void* z, void* y)
+{
+    if (c->prec == M2P_FP64) return Launch<double>::axpbz(c->kp, a, x, b, z, y, c->stream);
+    return Launch<float>::axpbz(c->kp, a, x, b, z, y, c->stream);
+}
+
+int L_dot(m2p_ctx* c, const void* x, const void* y, double* out)
+{
+    hipError_t e = c->prec == M2P_FP64 ? Launch<double>::dot(c->kp, x, y, c->mass_part, c->stream)
+                                       : Launch<float>::dot(c->kp, x, y, c->mass_part, c->stream);
+    HIPCHK(e);
+    std::vector<double> part(kMassBlocks);
+    HIPCHK(hipMemcpyAsync(part.data(), c->mass_part, kMassBlocks * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    double acc = 0.0;
+    for (double v : part) acc += v;
+    *out = acc;
+    return M2P_OK;
+}
+
+int L_loss(m2p_ctx* c, const double* target_dev, void* lam, double* loss)
+{
+    hipError_t e = c->prec == M2P_FP64
+                       ? Launch<double>::loss(c->kp, c->B, c->B.U, target_dev, lam, c->mass_part, c->stream)
+                       : Launch<float>::loss(c->kp, c->B, c->B.U, target_dev, lam, c->mass_part, c->stream);
+    HIPCHK(e);
+    std::vector<double> part(kMassBlocks);
+    HIPCHK(hipMemcpyAsync(part.data(), c->mass_part, kMassBlocks * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    double acc = 0.0;
+    for (double v : part) acc += v;
+    *loss = acc;
+    return M2P_OK;
+}
+
+int inflow_unsupported(m2p_ctx* c)
+{
+    if (c->kp.nseg > 0) return m2p::fail(M2P_EINVAL, "the adjoint supports Mode-I (no inflow segments)");
+    return M2P_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int m2p_set_friction_field(m2p_ctx* c, const double* tan_mu)
+{
+    if (!c || !tan_mu) return fail(M2P_EINVAL, "NULL argument");
+    const size_t n = (size_t)c->g.nx * c->g.ny;
+    for (size_t k = 0; k < n; k++)
+        if (!(tan_mu[k] >= 0.0) || !std::isfinite(tan_mu[k])) return fail(M2P_EINVAL, "bad tan_mu value");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (!c->mu) {
+        if (hipMalloc(&c->mu, (size_t)c->g.ny * c->kp.pitch * c->esz) != hipSuccess)
+            return fail(M2P_ENOMEM, "friction field allocation failed");
+        c->B.mu = c->mu;
+    }
+    int rc = upload(c, tan_mu, c->mu, 1);
+    if (rc) return rc;
+    c->kp.has_mu = 1;
+    c->dirty = true;
+    return M2P_OK;
+}
+
+int m2p_set_dt_schedule(m2p_ctx* c, const double* dts, int64_t n)
+{
+    if (!c || n < 0 || (n > 0 && !dts)) return fail(M2P_EINVAL, "bad argument");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    static_assert(sizeof(void*) == 8, "64-bit pointers");
+    double* dev = nullptr;
+    if (n > 0) {
+        std::vector<double> v(n);
+        for (int64_t k = 0; k < n; k++) {
+            if (!(dts[k] > 0.0) || !std::isfinite(dts[k])) return fail(M2P_EINVAL, "time steps must be positive");
+            v[k] = dts[k] / c->kp.T;
+        }
+        if (hipMalloc((void**)&dev, n * 8) != hipSuccess) return fail(M2P_ENOMEM, "schedule allocation failed");
+        HIPCHK(hipMemcpy(dev, v.data(), n * 8, hipMemcpyHostToDevice));
+    }
+    const double* old = nullptr;
+    HIPCHK(hipMemcpy(&old, (char*)c->S + offsetof(DevScalars, dt_sched), sizeof(old), hipMemcpyDeviceToHost));
+    const long long nn = n;
+    HIPCHK(hipMemcpy((char*)c->S + offsetof(DevScalars, dt_sched), &dev, sizeof(dev), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy((char*)c->S + offsetof(DevScalars, n_sched), &nn, sizeof(nn), hipMemcpyHostToDevice));
+    if (old) (void)hipFree((void*)old);
+    c->dirty = true;
+    return M2P_OK;
+}
+
+int m2p_loss(m2p_ctx* c, const double* target_h, double* loss)
+{
+    if (!c || !target_h || !loss) return fail(M2P_EINVAL, "NULL argument");
+    if (!c->has_state) return fail(M2P_ESTATE, "no state");
+    const size_t n = (size_t)c->g.nx * c->g.ny;
+    DevBuf tgt, lam;
+    int rc;
+    if ((rc = tgt.alloc(n * 8)) || (rc = lam.alloc(c->state_bytes))) return rc;
+    HIPCHK(hipMemcpy(tgt.p, target_h, n * 8, hipMemcpyHostToDevice));
+    return L_loss(c, (const double*)tgt.p, lam.p, loss);
+}
+
+int m2p_stage_jvp(m2p_ctx* c, int32_t stage, const double* dU, const double* dmu, double* E, double* dE)
+{
+    if (!c || !dU || !E || !dE || stage < 0 || stage > 1) return fail(M2P_EINVAL, "bad argument");
+    int rc = ensure_ready(c);
+    if (rc) return rc;
+    DevBuf ddU, dE_, E_, dmu_;
+    if ((rc = ddU.alloc(c->state_bytes)) || (rc = E_.alloc(c->state_bytes)) || (rc = dE_.alloc(c->state_bytes)))
+        return rc;
+    if ((rc = upload(c, dU, ddU.p, NF))) return rc;
+    if (dmu) {
+        if ((rc = dmu_.alloc((size_t)c->g.ny * c->kp.pitch * c->esz))) return rc;
+        if ((rc = upload(c, dmu, dmu_.p, 1))) return rc;
+    }
+    HIPCHK(L_jvp(c, c->B.U, ddU.p, dmu_.p, stage, E_.p, dE_.p));
+    if ((rc = download(c, E_.p, E, NF))) return rc;
+    return download(c, dE_.p, dE, NF);
+}
+
+int m2p_stage_vjp(m2p_ctx* c, int32_t stage, const double* lam, double* lam_in, double* gmu)
+{
+    if (!c || !lam || !lam_in || stage < 0 || stage > 1) return fail(M2P_EINVAL, "bad argument");
+    int rc = ensure_ready(c);
+    if (rc) return rc;
+    DevScalars hs;
+    if ((rc = read_scalars(c, &hs))) return rc;
+    VjpWork w;
+    DevBuf l, li, g;
+    if ((rc = w.alloc(c)) || (rc = l.alloc(c->state_bytes)) || (rc = li.alloc(c->state_bytes)) ||
+        (rc = g.alloc((size_t)c->g.ny * c->kp.pitch * c->esz)))
+        return rc;
+    if ((rc = upload(c, lam, l.p, NF))) return rc;
+    HIPCHK(L_vjp(c, w, c->B.U, l.p, stage, hs.dt, li.p, g.p));
+    if ((rc = download(c, li.p, lam_in, NF))) return rc;
+    if (gmu) return download(c, g.p, gmu, 1);
+    return M2P_OK;
+}
+
+int m2p_adjoint_run(m2p_ctx* c, int64_t nsteps, int32_t ckpt_every, const double* target_h, double vol_scale,
+                    double* loss, double* grad_mu, double* grad_vol)
+{
+    if (!c || nsteps < 1 || ckpt_every < 1 || !target_h || !loss || !(vol_scale > 0.0))
+        return fail(M2P_EINVAL, "bad argument");
+    int rc = inflow_unsupported(c);
+    if (rc) return rc;
+    if ((rc = ensure_ready(c))) return rc;
+    const KParams& K = c->kp;
+    const size_t n = (size_t)c->g.nx * c->g.ny, sb = c->state_bytes;
+    const int nseg = (int)((nsteps + ckpt_every - 1) / ckpt_every);
+    const int seglen = (int)std::min<int64_t>(ckpt_every, nsteps);
+    DevBuf ckpt, sck, dts, tapeU, tapeUs, lam, lamh, lamv, gmu, tgt, fin, sfin;
+    VjpWork w;
+    if ((rc = ckpt.alloc(sb * nseg)) || (rc = sck.alloc(sizeof(DevScalars) * nseg)) ||
+        (rc = dts.alloc(8 * nsteps)) || (rc = tapeU.alloc(sb * seglen)) || (rc = tapeUs.alloc(sb * seglen)) ||
+        (rc = lam.alloc(sb)) || (rc = lamh.alloc(sb)) || (rc = lamv.alloc(sb)) ||
+        (rc = gmu.alloc((size_t)K.ny * K.pitch * c->esz)) || (rc = tgt.alloc(n * 8)) || (rc = fin.alloc(sb)) ||
+        (rc = sfin.alloc(sizeof(DevScalars))) || (rc = w.alloc(c)))
+        return rc;
+    HIPCHK(hipMemcpy(tgt.p, target_h, n * 8, hipMemcpyHostToDevice));
+    const hipStream_t st = c->stream;
+    // forward with checkpoints and the time-step record
+    for (int64_t s = 0; s < nsteps; s++) {
+        if (s % ckpt_every == 0) {
+            const int k = (int)(s / ckpt_every);
+            HIPCHK(hipMemcpyAsync((char*)ckpt.p + sb * k, c->B.U, sb, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync((char*)sck.p + sizeof(DevScalars) * k, c->S, sizeof(DevScalars),
+                                  hipMemcpyDeviceToDevice, st));
+        }
+        HIPCHK(hipMemcpyAsync((double*)dts.p + s, &c->S->dt, 8, hipMemcpyDeviceToDevice, st));
+        HIPCHK(do_step(c));
+    }
+    DevScalars hs;
+    if ((rc = read_scalars(c, &hs)) || (rc = check_status(c, hs))) return rc;
+    HIPCHK(hipMemcpyAsync(fin.p, c->B.U, sb, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(sfin.p, c->S, sizeof(DevScalars), hipMemcpyDeviceToDevice, st));
+    std::vector<double> hdt(nsteps);
+    HIPCHK(hipMemcpyAsync(hdt.data(), dts.p, 8 * nsteps, hipMemcpyDeviceToHost, st));
+    if ((rc = L_loss(c, (const double*)tgt.p, lam.p, loss))) return rc;
+    // reverse sweep, segment by segment, recomputing each segment's states
+    for (int sg = nseg - 1; sg >= 0; sg--) {
+        const int64_t n0 = (int64_t)sg * ckpt_every, n1 = std::min<int64_t>(nsteps, n0 + ckpt_every);
+        HIPCHK(hipMemcpyAsync(c->B.U, (char*)ckpt.p + sb * sg, sb, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(c->S, (char*)sck.p + sizeof(DevScalars) * sg, sizeof(DevScalars),
+                              hipMemcpyDeviceToDevice, st));
+        for (int64_t s = n0; s < n1; s++) {
+            HIPCHK(hipMemcpyAsync((char*)tapeU.p + sb * (s - n0), c->B.U, sb, hipMemcpyDeviceToDevice, st));
+            HIPCHK(step_part(c, 0));
+            HIPCHK(hipMemcpyAsync((char*)tapeUs.p + sb * (s - n0), c->B.Us, sb, hipMemcpyDeviceToDevice, st));
+            HIPCHK(step_part(c, 1));
+            HIPCHK(step_part(c, 2));
+        }
+        for (int64_t s = n1 - 1; s >= n0; s--) {
+            const double dt = hdt[s] / 1.0;
+            const void* Un = (char*)tapeU.p + sb * (s - n0);
+            const void* Us = (char*)tapeUs.p + sb * (s - n0);
+            HIPCHK(L_axpbz(c, 0.5, lam.p, 0.0, nullptr, lamh.p));        // cotangent of U**
+            HIPCHK(L_vjp(c, w, Us, lamh.p, 1, dt, lamv.p, gmu.p));      // -> cotangent of U*
+            HIPCHK(L_vjp(c, w, Un, lamv.p, 0, dt, lamh.p, gmu.p));      // -> through stage 1
+            HIPCHK(L_axpbz(c, 0.5, lam.p, 1.0, lamh.p, lam.p));         // lambda^n
+        }
+    }
+    // dL / d(volume scale): the initial state is proportional to the scale
+    double dot0 = 0.0;
+    if ((rc = L_dot(c, lam.p, ckpt.p, &dot0))) return rc;
+    if (grad_vol) *grad_vol = dot0 / vol_scale;
+    if (grad_mu && (rc = download(c, gmu.p, grad_mu, 1))) return rc;
+    // leave the context at the end of the forward run
+    HIPCHK(hipMemcpyAsync(c->B.U, fin.p, sb, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->S, sfin.p, sizeof(DevScalars), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
     return M2P_OK;
 }
 

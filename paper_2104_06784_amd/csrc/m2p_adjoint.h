@@ -1,0 +1,587 @@
+// m2p_adjoint.h -- tangent (JVP) and adjoint (VJP) kernels of one forward-
+// Euler stage E of the scheme, for gradients of a loss through the two-step
+// modified Euler method with frozen time steps.
+//
+// The adjoint is written as the transpose of the stage's structure:
+//   out_c = Clamp(tent_c, U_c, mu_c),  tent_c = U_c + dt R_c,
+//   R_c   = -(H_{c+1/2} - H_{c-1/2}) / dxi - (G_{c+1/2} - G_{c-1/2}) / deta + S_c,
+// where a face flux H depends on the four cells of its reconstruction stencil
+// and S_c on the cell, its four neighbours and (viscosity) its four corners.
+//   pass A (cells):  cotangent of tent_c and of (U_c, mu_c) through Clamp;
+//   pass B (faces):  face cotangent dt (g_R - g_L) / dxi pulled back to the
+//                    four stencil cells; (cells) dt g_tent pulled back through
+//                    S_c to its 34 inputs;
+//   pass C (cells):  fixed-order gather of all contributions that land on a
+//                    cell through the ghost-cell map (sign flips included).
+// Each local Jacobian-transpose product is formed from forward-mode dual
+// evaluations (one per local input) of the same device functions the forward
+// kernels run, so the adjoint differentiates exactly the executed scheme.
+// Non-smooth points (minmod, max of speeds, Coulomb stop, positivity) take the
+// derivative of the branch selected by the values.
+#pragma once
+
+#include "m2p_device.h"
+#include "m2p_dual.h"
+#include "m2p_kernels.h"
+
+namespace m2p {
+
+template <typename T>
+__device__ __forceinline__ Geo<Dual<T>> lift(const Geo<T>& g)
+{
+    Geo<Dual<T>> r;
+    r.bX = Dual<T>(g.bX, T(0));
+    r.bY = Dual<T>(g.bY, T(0));
+    r.J = Dual<T>(g.J, T(0));
+    r.c = Dual<T>(g.c, T(0));
+    r.nX = Dual<T>(g.nX, T(0));
+    r.nY = Dual<T>(g.nY, T(0));
+    r.nZ = Dual<T>(g.nZ, T(0));
+    r.A11 = Dual<T>(g.A11, T(0));
+    r.A12 = Dual<T>(g.A12, T(0));
+    r.A21 = Dual<T>(g.A21, T(0));
+    r.A22 = Dual<T>(g.A22, T(0));
+    return r;
+}
+
+template <typename T> __device__ __forceinline__ Geo<T> liftg(const Geo<T>& g, T*) { return g; }
+template <typename T> __device__ __forceinline__ Geo<Dual<T>> liftg(const Geo<T>& g, Dual<T>*) { return lift(g); }
+template <typename T> __device__ __forceinline__ T liftv(T x, T*) { return x; }
+template <typename T> __device__ __forceinline__ Dual<T> liftv(T x, Dual<T>*) { return Dual<T>(x, T(0)); }
+
+// Geometry of the five cells a stage at (i, j) needs, in the base type.
+template <typename T>
+struct Geo5 {
+    Geo<T> C, W, E, S, N;
+};
+
+template <typename T>
+__device__ __forceinline__ Geo5<T> geo5(const KParams& P, const T* __restrict__ b, int i, int j)
+{
+    const Consts<T> K(P);
+    auto bv = [&](int ii, int jj) { return b[(size_t)(jj + BHALO) * P.bpitch + BOFF + ii]; };
+    auto g = [&](int ii, int jj) {
+        return geometry(bv(ii + 1, jj), bv(ii - 1, jj), bv(ii, jj + 1), bv(ii, jj - 1), K.two_dxi, K.two_deta);
+    };
+    Geo5<T> r;
+    r.C = g(i, j);
+    r.W = g(i - 1, j);
+    r.E = g(i + 1, j);
+    r.S = g(i, j - 1);
+    r.N = g(i, j + 1);
+    return r;
+}
+
+// Stencil values of a cell: row i-2..i+2, column j-2..j+2, 3x3 box.
+template <typename TT>
+struct Stencil {
+    TT row[5][NF], col[5][NF], box[3][3][NF];
+};
+
+// Ghost-mapped load of one cell's 6 fields (base type).
+template <typename T>
+__device__ __forceinline__ void load_mapped(const KParams& P, const T* __restrict__ U, int ii, int jj, T u[NF])
+{
+    const size_t fs = (size_t)P.ny * P.pitch;
+    int fx = 0, fy = 0;
+    const int mi = map_index(ii, P.nx, P.bc[0], P.bc[1], fx);
+    const int mj = map_index(jj, P.ny, P.bc[2], P.bc[3], fy);
+    const size_t c = (size_t)mj * P.pitch + mi;
+#pragma unroll
+    for (int k = 0; k < NF; k++) u[k] = U[k * fs + c];
+    if (fx) {
+        u[1] = -u[1];
+        u[4] = -u[4];
+    }
+    if (fy) {
+        u[2] = -u[2];
+        u[5] = -u[5];
+    }
+}
+
+// Sources (all but the Coulomb clamp) of a cell, including viscosity, from its
+// stencil: returns the per-component source vector added to R (mass: 0) and
+// the Src record (kappa_s for the clamp).
+template <typename TT, typename T>
+__device__ __forceinline__ void cell_sources(const KParams& P, const Consts<TT>& K, const Stencil<TT>& s,
+                                             const Geo5<T>& g5, Src<TT>& Sr, TT& svx, TT& svy)
+{
+    TT* tag = nullptr;
+    const Geo<TT> gC = liftg(g5.C, tag), gW = liftg(g5.W, tag), gE = liftg(g5.E, tag), gS = liftg(g5.S, tag),
+                  gN = liftg(g5.N, tag);
+    const T two_dxi = T(P.two_dxi), two_deta = T(P.two_deta);
+    TT dn[6];
+    dn[0] = liftv((g5.E.nX - g5.W.nX) / two_dxi, tag);
+    dn[1] = liftv((g5.E.nY - g5.W.nY) / two_dxi, tag);
+    dn[2] = liftv((g5.E.nZ - g5.W.nZ) / two_dxi, tag);
+    dn[3] = liftv((g5.N.nX - g5.S.nX) / two_deta, tag);
+    dn[4] = liftv((g5.N.nY - g5.S.nY) / two_deta, tag);
+    dn[5] = liftv((g5.N.nZ - g5.S.nZ) / two_deta, tag);
+    const TT dGx = (fluid_G(s.row[3][0], s.row[3][3], gE) - fluid_G(s.row[1][0], s.row[1][3], gW)) / K.two_dxi;
+    const TT dGy = (fluid_G(s.col[3][0], s.col[3][3], gN) - fluid_G(s.col[1][0], s.col[1][3], gS)) / K.two_deta;
+    sources(K, P.flags, s.row[2], gC, dn, dGx, dGy, Sr);
+    svx = TT(0.0);
+    svy = TT(0.0);
+    if (P.visc) {
+        TT u9[3][3], w9[3][3];
+        for (int a = 0; a < 3; a++)
+            for (int c = 0; c < 3; c++) {
+                u9[a][c] = dsg(s.box[a][c][4], s.box[a][c][3], K.md);
+                w9[a][c] = dsg(s.box[a][c][5], s.box[a][c][3], K.md);
+            }
+        const TT JhC = s.row[2][0] + s.row[2][3];
+        const TT JhW = s.row[1][0] + s.row[1][3], JhE = s.row[3][0] + s.row[3][3];
+        const TT JhS = s.col[1][0] + s.col[1][3], JhN = s.col[3][0] + s.col[3][3];
+        TT cyu[3], cyw[3], cxu[3], cxw[3];
+        for (int q = 0; q < 3; q++) {
+            cyu[q] = cdiff(u9[2][q], u9[0][q], K.deta);
+            cyw[q] = cdiff(w9[2][q], w9[0][q], K.deta);
+            cxu[q] = cdiff(u9[q][2], u9[q][0], K.dxi);
+            cxw[q] = cdiff(w9[q][2], w9[q][0], K.dxi);
+        }
+        TT FX0, FY0, FX1, FY1, GX0, GY0, GX1, GY1;
+        visc_xface_c(u9[1][0], w9[1][0], u9[1][1], w9[1][1], cyu[0], cyw[0], cyu[1], cyw[1], JhW, JhC, gW, gC, K.dxi,
+                     FX0, FY0);
+        visc_xface_c(u9[1][1], w9[1][1], u9[1][2], w9[1][2], cyu[1], cyw[1], cyu[2], cyw[2], JhC, JhE, gC, gE, K.dxi,
+                     FX1, FY1);
+        visc_yface_c(u9[0][1], w9[0][1], u9[1][1], w9[1][1], cxu[0], cxw[0], cxu[1], cxw[1], JhS, JhC, gS, gC,
+                     K.deta, GX0, GY0);
+        visc_yface_c(u9[1][1], w9[1][1], u9[2][1], w9[2][1], cxu[1], cxw[1], cxu[2], cxw[2], JhC, JhN, gC, gN,
+                     K.deta, GX1, GY1);
+        const TT SvX = (FX1 - FX0) / K.dxi + (GX1 - GX0) / K.deta;
+        const TT SvY = (FY1 - FY0) / K.dxi + (GY1 - GY0) / K.deta;
+        svx = K.eps * Sr.phif * K.inv_n_r * SvX;
+        svy = K.eps * Sr.phif * K.inv_n_r * SvY;
+    }
+}
+
+// Face flux H_{a+1/2} in direction d from the 4-cell window (a-1 .. a+2) and
+// the geometries of cells a and a+1.
+template <typename TT, typename T>
+__device__ __forceinline__ void face_flux(const Consts<TT>& K, const TT w[4][NF], const Geo<T>& ga, const Geo<T>& gb,
+                                          int d, TT H[NF])
+{
+    TT* tag = nullptr;
+    TT uL[NF], uR[NF];
+#pragma unroll
+    for (int k = 0; k < NF; k++) {
+        const TT s0 = minmod(w[1][k] - w[0][k], w[2][k] - w[1][k]);
+        const TT s1 = minmod(w[2][k] - w[1][k], w[3][k] - w[2][k]);
+        uL[k] = w[1][k] + TT(0.5) * s0;
+        uR[k] = w[2][k] - TT(0.5) * s1;
+    }
+    central_flux(K, uL, liftg(ga, tag), uR, liftg(gb, tag), d, H);
+}
+
+// Whole stage at interior cell (i, j) from its stencil (the arithmetic of the
+// forward kernels): tentative update and clamped output.
+template <typename TT, typename T>
+__device__ __forceinline__ void cell_stage(const KParams& P, const Stencil<TT>& s, const Geo5<T>& g5, TT dt, TT tmu,
+                                           const double (*inf)[4], int i, int j, TT tent[NF], TT out[NF])
+{
+    const Consts<TT> K(P);
+    TT* tag = nullptr;
+    TT HXl[NF], HXr[NF], HYb[NF], HYt[NF], w[4][NF];
+    for (int q = 0; q < 4; q++)
+        for (int k = 0; k < NF; k++) w[q][k] = s.row[q][k];
+    face_flux(K, w, g5.W, g5.C, 0, HXl);
+    for (int q = 0; q < 4; q++)
+        for (int k = 0; k < NF; k++) w[q][k] = s.row[q + 1][k];
+    face_flux(K, w, g5.C, g5.E, 0, HXr);
+    for (int q = 0; q < 4; q++)
+        for (int k = 0; k < NF; k++) w[q][k] = s.col[q][k];
+    face_flux(K, w, g5.S, g5.C, 1, HYb);
+    for (int q = 0; q < 4; q++)
+        for (int k = 0; k < NF; k++) w[q][k] = s.col[q + 1][k];
+    face_flux(K, w, g5.C, g5.N, 1, HYt);
+    const Geo<TT> gC = liftg(g5.C, tag);
+    int sgi;
+    if (i == 0 && (sgi = inflow_seg_at(P, 0, j)) >= 0)
+        inflow_flux(K, gC, 0, +1, TT(inf[sgi][0]), TT(inf[sgi][1]), TT(inf[sgi][2]), TT(inf[sgi][3]), HXl);
+    if (i == P.nx - 1 && (sgi = inflow_seg_at(P, 1, j)) >= 0)
+        inflow_flux(K, gC, 0, -1, TT(inf[sgi][0]), TT(inf[sgi][1]), TT(inf[sgi][2]), TT(inf[sgi][3]), HXr);
+    if (j == 0 && (sgi = inflow_seg_at(P, 2, i)) >= 0)
+        inflow_flux(K, gC, 1, +1, TT(inf[sgi][0]), TT(inf[sgi][1]), TT(inf[sgi][2]), TT(inf[sgi][3]), HYb);
+    if (j == P.ny - 1 && (sgi = inflow_seg_at(P, 3, i)) >= 0)
+        inflow_flux(K, gC, 1, -1, TT(inf[sgi][0]), TT(inf[sgi][1]), TT(inf[sgi][2]), TT(inf[sgi][3]), HYt);
+    Src<TT> Sr;
+    TT svx, svy;
+    cell_sources(P, K, s, g5, Sr, svx, svy);
+    tentative(K, s.row[2], HXl, HXr, HYb, HYt, Sr, svx, svy, dt, tent);
+    for (int k = 0; k < NF; k++) out[k] = tent[k];
+    clamp_cell(K, gC, Sr.kappa_s, dt, tmu, out);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_stencil(const KParams& P, const T* __restrict__ U, int i, int j, Stencil<T>& s)
+{
+    for (int q = 0; q < 5; q++) load_mapped(P, U, i - 2 + q, j, s.row[q]);
+    for (int q = 0; q < 5; q++) load_mapped(P, U, i, j - 2 + q, s.col[q]);
+    for (int a = 0; a < 3; a++)
+        for (int c = 0; c < 3; c++) load_mapped(P, U, i - 1 + c, j - 1 + a, s.box[a][c]);
+}
+
+// ---------------------------------------------------------------- JVP / E
+
+// E(U) and its directional derivative along dU (both [6][ny][pitch]).
+template <typename T>
+__global__ void __launch_bounds__(128) k_stage_jvp(KParams P, const T* __restrict__ U, const T* __restrict__ dU,
+                                                   const T* __restrict__ b, const T* __restrict__ mu,
+                                                   const T* __restrict__ dmu, const DevScalars* __restrict__ S,
+                                                   int stage, T* __restrict__ E, T* __restrict__ dE)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= P.nx) return;
+    using TT = Dual<T>;
+    Stencil<T> s0, s1;
+    load_stencil(P, U, i, j, s0);
+    load_stencil(P, dU, i, j, s1);
+    Stencil<TT> s;
+    for (int q = 0; q < 5; q++)
+        for (int k = 0; k < NF; k++) {
+            s.row[q][k] = TT(s0.row[q][k], s1.row[q][k]);
+            s.col[q][k] = TT(s0.col[q][k], s1.col[q][k]);
+        }
+    for (int a = 0; a < 3; a++)
+        for (int c = 0; c < 3; c++)
+            for (int k = 0; k < NF; k++) s.box[a][c][k] = TT(s0.box[a][c][k], s1.box[a][c][k]);
+    const Geo5<T> g5 = geo5(P, b, i, j);
+    const size_t c = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
+    const TT tmu(P.has_mu ? mu[c] : T(P.tan_d), dmu ? dmu[c] : T(0));
+    TT tent[NF], out[NF];
+    cell_stage(P, s, g5, TT(T(S->dt), T(0)), tmu, S->inflow[stage], i, j, tent, out);
+    for (int k = 0; k < NF; k++) {
+        E[k * fs + c] = out[k].v;
+        dE[k * fs + c] = out[k].d;
+    }
+}
+
+// ---------------------------------------------------------------- adjoint
+
+// Pass A: per cell, the cotangent of the tentative state (GT), the direct
+// cotangent of U_c (identity of the update + clamp through kappa_s) into DU,
+// and the friction-field cotangent (accumulated into gmu).
+template <typename T>
+__global__ void __launch_bounds__(128) k_adj_post(KParams P, const T* __restrict__ U, const T* __restrict__ lam,
+                                                  const T* __restrict__ b, const T* __restrict__ mu,
+                                                  const DevScalars* __restrict__ S, int stage, T dt,
+                                                  T* __restrict__ GT, T* __restrict__ DU, T* __restrict__ gmu)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= P.nx) return;
+    const size_t c = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
+    Stencil<T> s;
+    load_stencil(P, U, i, j, s);
+    const Geo5<T> g5 = geo5(P, b, i, j);
+    const T tmu = P.has_mu ? mu[c] : T(P.tan_d);
+    T tent[NF], out[NF];
+    cell_stage(P, s, g5, dt, tmu, S->inflow[stage], i, j, tent, out);
+    T lo[NF];
+    for (int k = 0; k < NF; k++) lo[k] = lam[k * fs + c];
+    using TT = Dual<T>;
+    const Consts<TT> K(P);
+    const Geo<TT> gC = lift(g5.C);
+    const T two_dxi = T(P.two_dxi), two_deta = T(P.two_deta);
+    TT dn[6];
+    dn[0] = TT((g5.E.nX - g5.W.nX) / two_dxi, T(0));
+    dn[1] = TT((g5.E.nY - g5.W.nY) / two_dxi, T(0));
+    dn[2] = TT((g5.E.nZ - g5.W.nZ) / two_dxi, T(0));
+    dn[3] = TT((g5.N.nX - g5.S.nX) / two_deta, T(0));
+    dn[4] = TT((g5.N.nY - g5.S.nY) / two_deta, T(0));
+    dn[5] = TT((g5.N.nZ - g5.S.nZ) / two_deta, T(0));
+    T g[13];
+    for (int d = 0; d < 13; d++) {
+        TT te[NF], uc[NF];
+        for (int k = 0; k < NF; k++) {
+            te[k] = TT(tent[k], d == k ? T(1) : T(0));
+            uc[k] = TT(s.row[2][k], d == 6 + k ? T(1) : T(0));
+        }
+        // kappa_s depends on the cell's own velocities only (the interphase
+        // pressure gradient does not enter it)
+        Src<TT> Sr;
+        sources(K, P.flags, uc, gC, dn, TT(0.0), TT(0.0), Sr);
+        TT o[NF];
+        for (int k = 0; k < NF; k++) o[k] = te[k];
+        clamp_cell(K, gC, Sr.kappa_s, TT(dt, T(0)), TT(tmu, d == 12 ? T(1) : T(0)), o);
+        T acc = T(0);
+        for (int k = 0; k < NF; k++) acc += lo[k] * o[k].d;
+        g[d] = acc;
+    }
+    for (int k = 0; k < NF; k++) {
+        GT[k * fs + c] = g[k];
+        DU[k * fs + c] = g[k] + g[6 + k];
+    }
+    gmu[c] += g[12];
+}
+
+// Pass B, faces: x-faces (d = 0) for i in [-1, nx-1] (face between i and i+1)
+// or y-faces (d = 1) for j in [-1, ny-1]; 24 stencil cotangents per face into
+// FC[face][24] (slot = 6 * cell + field, cells a-1 .. a+2).
+template <typename T>
+__global__ void __launch_bounds__(128) k_adj_face(KParams P, const T* __restrict__ U, const T* __restrict__ GT,
+                                                  const T* __restrict__ b, int d, T dt, T* __restrict__ FC)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nf_along = d == 0 ? P.nx + 1 : P.nx;
+    if (t >= nf_along) return;
+    const int line = blockIdx.y;  // row j for x-faces; row-of-faces j for y-faces
+    int i, j;
+    if (d == 0) {
+        i = t - 1;
+        j = line;
+    } else {
+        i = t;
+        j = line - 1;
+    }
+    const size_t fidx = (size_t)line * nf_along + t;
+    T* out = FC + fidx * 24;
+    const size_t fs = (size_t)P.ny * P.pitch;
+    // inflow faces carry a prescribed flux: no dependence on the state
+    bool fixed = false;
+    if (d == 0 && i == -1) fixed = inflow_seg_at(P, 0, j) >= 0;
+    if (d == 0 && i == P.nx - 1) fixed = fixed || inflow_seg_at(P, 1, j) >= 0;
+    if (d == 1 && j == -1) fixed = inflow_seg_at(P, 2, i) >= 0;
+    if (d == 1 && j == P.ny - 1) fixed = fixed || inflow_seg_at(P, 3, i) >= 0;
+    if (fixed) {
+        for (int q = 0; q < 24; q++) out[q] = T(0);
+        return;
+    }
+    // face cotangent: R_left has -H/h, R_right has +H/h
+    const int li = i, lj = j, ri = d == 0 ? i + 1 : i, rj = d == 0 ? j : j + 1;
+    const T h = T(d == 0 ? P.dxi : P.deta);
+    T gH[NF];
+    for (int k = 0; k < NF; k++) {
+        const T gl = (li >= 0 && lj >= 0) ? GT[k * fs + (size_t)lj * P.pitch + li] : T(0);
+        const T gr = (ri < P.nx && rj < P.ny) ? GT[k * fs + (size_t)rj * P.pitch + ri] : T(0);
+        gH[k] = dt * (gr - gl) / h;
+    }
+    T w0[4][NF];
+    for (int q = 0; q < 4; q++) {
+        const int ci = d == 0 ? i - 1 + q : i, cj = d == 0 ? j : j - 1 + q;
+        load_mapped(P, U, ci, cj, w0[q]);
+    }
+    const Consts<T> Kb(P);
+    auto bv = [&](int ii, int jj) { return b[(size_t)(jj + BHALO) * P.bpitch + BOFF + ii]; };
+    auto geo = [&](int ii, int jj) {
+        return geometry(bv(ii + 1, jj), bv(ii - 1, jj), bv(ii, jj + 1), bv(ii, jj - 1), Kb.two_dxi, Kb.two_deta);
+    };
+    const Geo<T> ga = geo(li, lj), gb = geo(ri, rj);
+    using TT = Dual<T>;
+    const Consts<TT> K(P);
+    for (int dir = 0; dir < 24; dir++) {
+        TT w[4][NF];
+        for (int q = 0; q < 4; q++)
+            for (int k = 0; k < NF; k++) w[q][k] = TT(w0[q][k], dir == 6 * q + k ? T(1) : T(0));
+        TT H[NF];
+        face_flux(K, w, ga, gb, d, H);
+        T acc = T(0);
+        for (int k = 0; k < NF; k++) acc += gH[k] * H[k].d;
+        out[dir] = acc;
+    }
+}
+
+// Source input slots: 0..5 centre fields; 6..21 neighbour (E, W, N, S) x
+// fields (0, 3, 4, 5); 22..33 corner (NE, NW, SE, SW) x fields (3, 4, 5).
+__device__ __forceinline__ void src_slot(int s, int& di, int& dj, int& k)
+{
+    if (s < 6) {
+        di = 0;
+        dj = 0;
+        k = s;
+        return;
+    }
+    if (s < 22) {
+        const int n = (s - 6) / 4, f = (s - 6) % 4;
+        const int odi[4] = {1, -1, 0, 0}, odj[4] = {0, 0, 1, -1};
+        const int fk[4] = {0, 3, 4, 5};
+        di = odi[n];
+        dj = odj[n];
+        k = fk[f];
+        return;
+    }
+    const int n = (s - 22) / 3, f = (s - 22) % 3;
+    const int odi[4] = {1, -1, 1, -1}, odj[4] = {1, 1, -1, -1};
+    di = odi[n];
+    dj = odj[n];
+    k = 3 + f;
+}
+
+// Pass B, sources: cotangent dt * GT_c (momentum components) pulled back
+// through S_c to its 34 input slots, into SC[cell][34].
+template <typename T>
+__global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict__ U, const T* __restrict__ GT,
+                                                 const T* __restrict__ b, T dt, T* __restrict__ SC)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= P.nx) return;
+    const size_t c = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
+    T* out = SC + ((size_t)j * P.nx + i) * 34;
+    Stencil<T> s;
+    load_stencil(P, U, i, j, s);
+    const Geo5<T> g5 = geo5(P, b, i, j);
+    T gS[NF];
+    for (int k = 0; k < NF; k++) gS[k] = dt * GT[k * fs + c];
+    using TT = Dual<T>;
+    const Consts<TT> K(P);
+    for (int sl = 0; sl < 34; sl++) {
+        int di, dj, kk;
+        src_slot(sl, di, dj, kk);
+        Stencil<TT> sd;
+        // every stencil position holding cell (i + di, j + dj) gets the tangent
+        for (int q = 0; q < 5; q++)
+            for (int k = 0; k < NF; k++) {
+                sd.row[q][k] = TT(s.row[q][k], (dj == 0 && q - 2 == di && k == kk) ? T(1) : T(0));
+                sd.col[q][k] = TT(s.col[q][k], (di == 0 && q - 2 == dj && k == kk) ? T(1) : T(0));
+            }
+        for (int a = 0; a < 3; a++)
+            for (int cc = 0; cc < 3; cc++)
+                for (int k = 0; k < NF; k++)
+                    sd.box[a][cc][k] = TT(s.box[a][cc][k], (a - 1 == dj && cc - 1 == di && k == kk) ? T(1) : T(0));
+        Src<TT> Sr;
+        TT svx, svy;
+        cell_sources(P, K, sd, g5, Sr, svx, svy);
+        T acc = T(0);
+        for (int ph = 0; ph < 2; ph++)
+            for (int a = 0; a < 2; a++) {
+                TT v = Sr.sn[ph][a];
+                v += Sr.sf[ph][a];
+                v += Sr.sv[ph][a];
+                if (ph == 1) {
+                    v += Sr.sd[a];
+                    v += a == 0 ? svx : svy;
+                }
+                acc += gS[3 * ph + 1 + a] * v.d;
+            }
+        out[sl] = acc;
+    }
+}
+
+// Pass C: lam_in(k) = DU(k) + all face and source contributions that land on
+// cell k through the ghost map, summed in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restrict__ DU, const T* __restrict__ FCX,
+                                                    const T* __restrict__ FCY, const T* __restrict__ SC,
+                                                    T* __restrict__ lam_in)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= P.nx) return;
+    const size_t c = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
+    T acc[NF];
+    for (int k = 0; k < NF; k++) acc[k] = DU[k * fs + c];
+    // x-faces of row j: face index t = fi + 1, fi in [-1, nx-1], stencil cells fi-1 .. fi+2
+    for (int fi = i - 3; fi <= i + 2; fi++) {
+        if (fi < -1 || fi > P.nx - 1) continue;
+        const T* f = FCX + ((size_t)j * (P.nx + 1) + (fi + 1)) * 24;
+        for (int q = 0; q < 4; q++) {
+            int fx = 0;
+            const int mi = map_index(fi - 1 + q, P.nx, P.bc[0], P.bc[1], fx);
+            if (mi != i) continue;
+            for (int k = 0; k < NF; k++) acc[k] += ((fx && (k == 1 || k == 4)) ? -f[6 * q + k] : f[6 * q + k]);
+        }
+    }
+    // y-faces of column i: face line fj + 1, fj in [-1, ny-1]
+    for (int fj = j - 3; fj <= j + 2; fj++) {
+        if (fj < -1 || fj > P.ny - 1) continue;
+        const T* f = FCY + ((size_t)(fj + 1) * P.nx + i) * 24;
+        for (int q = 0; q < 4; q++) {
+            int fy = 0;
+            const int mj = map_index(fj - 1 + q, P.ny, P.bc[2], P.bc[3], fy);
+            if (mj != j) continue;
+            for (int k = 0; k < NF; k++) acc[k] += ((fy && (k == 2 || k == 5)) ? -f[6 * q + k] : f[6 * q + k]);
+        }
+    }
+    // sources of the 3 x 3 neighbourhood
+    for (int cj = j - 1; cj <= j + 1; cj++) {
+        if (cj < 0 || cj >= P.ny) continue;
+        for (int ci = i - 1; ci <= i + 1; ci++) {
+            if (ci < 0 || ci >= P.nx) continue;
+            const T* f = SC + ((size_t)cj * P.nx + ci) * 34;
+            for (int sl = 0; sl < 34; sl++) {
+                int di, dj, k;
+                src_slot(sl, di, dj, k);
+                int fx = 0, fy = 0;
+                const int mi = map_index(ci + di, P.nx, P.bc[0], P.bc[1], fx);
+                const int mj = map_index(cj + dj, P.ny, P.bc[2], P.bc[3], fy);
+                if (mi != i || mj != j) continue;
+                T v = f[sl];
+                if (fx && (k == 1 || k == 4)) v = -v;
+                if (fy && (k == 2 || k == 5)) v = -v;
+                acc[k] += v;
+            }
+        }
+    }
+    for (int k = 0; k < NF; k++) lam_in[k * fs + c] = acc[k];
+}
+
+// Loss 1/2 sum (h - h_target)^2 dx dy (h bed-normal, m) and its cotangent
+// with respect to the state (m^s and m^f entries); FP64 partial sums per block.
+template <typename T>
+__global__ void __launch_bounds__(256) k_loss(KParams P, const T* __restrict__ U, const T* __restrict__ b,
+                                              const double* __restrict__ target, T* __restrict__ lam,
+                                              double* __restrict__ part)
+{
+    __shared__ double sh[256];
+    const int tid = threadIdx.x;
+    const size_t n = (size_t)P.nx * P.ny, fs = (size_t)P.ny * P.pitch;
+    double acc = 0.0;
+    for (size_t q = (size_t)blockIdx.x * 256 + tid; q < n; q += (size_t)gridDim.x * 256) {
+        const int j = (int)(q / P.nx), i = (int)(q - (size_t)j * P.nx);
+        const size_t c = (size_t)j * P.pitch + i;
+        auto bv = [&](int ii, int jj) { return (double)b[(size_t)(jj + BHALO) * P.bpitch + BOFF + ii]; };
+        const Geo<double> g = geometry(bv(i + 1, j), bv(i - 1, j), bv(i, j + 1), bv(i, j - 1), P.two_dxi, P.two_deta);
+        const double h = ((double)U[c] + (double)U[3 * fs + c]) / g.J * P.H;
+        const double r = h - target[q];
+        acc += 0.5 * r * r * P.dx * P.dy;
+        const double gm = r * P.dx * P.dy * P.H / g.J;
+        for (int k = 0; k < NF; k++) lam[k * fs + c] = T(0);
+        lam[c] = T(gm);
+        lam[3 * fs + c] = T(gm);
+    }
+    sh[tid] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) part[blockIdx.x] = sh[0];
+}
+
+// y = a x + c z on [6][ny][pitch] arrays (interior cells only).
+template <typename T>
+__global__ void k_axpbz(KParams P, T a, const T* __restrict__ x, T c, const T* __restrict__ z, T* __restrict__ y)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= P.nx) return;
+    const size_t o = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
+    for (int k = 0; k < NF; k++) y[k * fs + o] = a * x[k * fs + o] + (z ? c * z[k * fs + o] : T(0));
+}
+
+// FP64 partial dot products of two [6][ny][pitch] arrays.
+template <typename T>
+__global__ void __launch_bounds__(256) k_dot(KParams P, const T* __restrict__ x, const T* __restrict__ y,
+                                             double* __restrict__ part)
+{
+    __shared__ double sh[256];
+    const int tid = threadIdx.x;
+    const size_t n = (size_t)P.nx * P.ny, fs = (size_t)P.ny * P.pitch;
+    double acc = 0.0;
+    for (size_t q = (size_t)blockIdx.x * 256 + tid; q < n; q += (size_t)gridDim.x * 256) {
+        const int j = (int)(q / P.nx), i = (int)(q - (size_t)j * P.nx);
+        const size_t c = (size_t)j * P.pitch + i;
+        for (int k = 0; k < NF; k++) acc += (double)x[k * fs + c] * (double)y[k * fs + c];
+    }
+    sh[tid] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) part[blockIdx.x] = sh[0];
+}
+
+}  // namespace m2p

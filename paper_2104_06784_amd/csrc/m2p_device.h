@@ -41,6 +41,8 @@ struct DevScalars {
     unsigned int status;
     unsigned int pad;
     double inflow[2][MAX_SEG][4];      // per stage: q, m_in, v_in, phi
+    const double* dt_sched;            // optional prescribed (frozen) time steps, dimensionless
+    long long n_sched;
 };
 
 template <typename T>
@@ -299,13 +301,13 @@ __device__ __forceinline__ void sources(const Consts<T>& K, int flags, const T u
     S.phif = phif;
 }
 
-// Forward-Euler update of one cell with the face fluxes and sources, then the
-// Coulomb stop-clamp of the solid and positivity.  Returns the number of
-// positivity clamps (tentative negative thickness).
+// Tentative forward-Euler update of one cell from its four face fluxes and
+// its sources (summation order: x-difference, y-difference, then s_n, s_f,
+// s_v, s_d^f, s_vis^f).
 template <typename T>
-__device__ __forceinline__ int update_cell(const Consts<T>& K, const T u[NF], const Geo<T>& g, const T HXl[NF],
-                                           const T HXr[NF], const T HYb[NF], const T HYt[NF], const Src<T>& S,
-                                           T svx, T svy, T dt, T tmu, T out[NF])
+__device__ __forceinline__ void tentative(const Consts<T>& K, const T u[NF], const T HXl[NF], const T HXr[NF],
+                                          const T HYb[NF], const T HYt[NF], const Src<T>& S, T svx, T svy, T dt,
+                                          T out[NF])
 {
 #pragma unroll
     for (int k = 0; k < NF; k++) {
@@ -325,8 +327,17 @@ __device__ __forceinline__ int update_cell(const Consts<T>& K, const T u[NF], co
         }
         out[k] = u[k] + dt * r;
     }
+}
+
+// Coulomb stop-clamp of the solid momentum (basal pressure from the tentative
+// solid thickness, centripetal term kappa_s from the stage input), then
+// positivity: a phase with tentative thickness <= 0 loses its momentum.
+// Returns the number of positivity clamps (tentative thickness < 0).
+template <typename T>
+__device__ __forceinline__ int clamp_cell(const Consts<T>& K, const Geo<T>& g, T kappa_s, T dt, T tmu, T out[NF])
+{
     T hst = out[0] / g.J;
-    T pbt = hst * (g.c * (T(1) - K.al) - K.eps_chi * S.kappa_s);
+    T pbt = hst * (g.c * (T(1) - K.al) - K.eps_chi * kappa_s);
     if (pbt < T(0)) pbt = T(0);
     T F = dt * (g.J * pbt) * tmu;
     T pX = out[1], pY = out[2];
@@ -349,6 +360,15 @@ __device__ __forceinline__ int update_cell(const Consts<T>& K, const T u[NF], co
             out[3 * ph + 2] = T(0);
         }
     return clamps;
+}
+
+template <typename T>
+__device__ __forceinline__ int update_cell(const Consts<T>& K, const T u[NF], const Geo<T>& g, const T HXl[NF],
+                                           const T HXr[NF], const T HYb[NF], const T HYt[NF], const Src<T>& S,
+                                           T svx, T svy, T dt, T tmu, T out[NF])
+{
+    tentative(K, u, HXl, HXr, HYb, HYt, S, svx, svy, dt, out);
+    return clamp_cell(K, g, S.kappa_s, dt, tmu, out);
 }
 
 // Ghost-cell index map (transmissive: copy the edge cell; wall: mirror with

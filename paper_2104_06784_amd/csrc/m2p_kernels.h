@@ -477,6 +477,7 @@ __device__ __forceinline__ void finalize_body(const KParams& P, DevScalars* S, c
     ay = ay > P.a_floor ? ay : P.a_floor;
     double dtx = P.dxi / ax, dty = P.deta / ay;
     double dt = P.cfl * (dtx < dty ? dtx : dty);
+    if (S->n_sched > 0 && S->steps < S->n_sched) dt = S->dt_sched[S->steps];  // frozen schedule
     if (!isfinite(dt)) S->status |= 1u;
     if (dt < P.dt_floor) S->status |= 2u;
     if (S->t_end - t < dt) dt = S->t_end - t;

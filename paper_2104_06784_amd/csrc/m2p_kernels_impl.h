@@ -4,6 +4,7 @@
 
 #include "m2p_kernels.h"
 #include "m2p_tiled.h"
+#include "m2p_adjoint.h"
 
 namespace m2p {
 
@@ -87,6 +88,65 @@ hipError_t Launch<M2P_REAL>::batch_part(const ScenDesc<M2P_REAL>* scen, int nsce
         hipLaunchKernelGGL((k_stage_batch<T, 1>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);
     else
         hipLaunchKernelGGL((k_stage_batch<T, 2>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t Launch<M2P_REAL>::jvp(const KParams& P, const Bufs& B, const void* U, const void* dU, const void* dmu,
+                                 int stage, void* E, void* dE, hipStream_t st)
+{
+    using T = M2P_REAL;
+    dim3 blk(128), grd((P.nx + 127) / 128, P.ny);
+    hipLaunchKernelGGL((k_stage_jvp<T>), grd, blk, 0, st, P, (const T*)U, (const T*)dU, (const T*)B.b,
+                       (const T*)B.mu, (const T*)dmu, B.S, stage, (T*)E, (T*)dE);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t Launch<M2P_REAL>::vjp(const KParams& P, const Bufs& B, const void* U, const void* lam, int stage, double dt,
+                                 void* GT, void* DU, void* FCX, void* FCY, void* SC, void* lam_in, void* gmu,
+                                 hipStream_t st)
+{
+    using T = M2P_REAL;
+    dim3 blk(128), grd((P.nx + 127) / 128, P.ny);
+    const T* b = (const T*)B.b;
+    hipLaunchKernelGGL((k_adj_post<T>), grd, blk, 0, st, P, (const T*)U, (const T*)lam, b, (const T*)B.mu, B.S, stage,
+                       T(dt), (T*)GT, (T*)DU, (T*)gmu);
+    hipLaunchKernelGGL((k_adj_face<T>), dim3((P.nx + 1 + 127) / 128, P.ny), blk, 0, st, P, (const T*)U,
+                       (const T*)GT, b, 0, T(dt), (T*)FCX);
+    hipLaunchKernelGGL((k_adj_face<T>), dim3((P.nx + 127) / 128, P.ny + 1), blk, 0, st, P, (const T*)U,
+                       (const T*)GT, b, 1, T(dt), (T*)FCY);
+    hipLaunchKernelGGL((k_adj_src<T>), grd, blk, 0, st, P, (const T*)U, (const T*)GT, b, T(dt), (T*)SC);
+    hipLaunchKernelGGL((k_adj_gather<T>), grd, blk, 0, st, P, (const T*)DU, (const T*)FCX, (const T*)FCY,
+                       (const T*)SC, (T*)lam_in);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t Launch<M2P_REAL>::loss(const KParams& P, const Bufs& B, const void* U, const double* target, void* lam,
+                                  double* part, hipStream_t st)
+{
+    using T = M2P_REAL;
+    hipLaunchKernelGGL((k_loss<T>), dim3(kMassBlocks), dim3(256), 0, st, P, (const T*)U, (const T*)B.b, target,
+                       (T*)lam, part);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t Launch<M2P_REAL>::axpbz(const KParams& P, double a, const void* x, double c, const void* z, void* y,
+                                   hipStream_t st)
+{
+    using T = M2P_REAL;
+    dim3 blk(128), grd((P.nx + 127) / 128, P.ny);
+    hipLaunchKernelGGL((k_axpbz<T>), grd, blk, 0, st, P, T(a), (const T*)x, T(c), (const T*)z, (T*)y);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t Launch<M2P_REAL>::dot(const KParams& P, const void* x, const void* y, double* part, hipStream_t st)
+{
+    using T = M2P_REAL;
+    hipLaunchKernelGGL((k_dot<T>), dim3(kMassBlocks), dim3(256), 0, st, P, (const T*)x, (const T*)y, part);
     return hipGetLastError();
 }
 

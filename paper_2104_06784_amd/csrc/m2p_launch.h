@@ -64,6 +64,17 @@ struct Launch {
     // list, part 2 = one finalize workgroup per scenario (mode 0 or 1)
     static hipError_t batch_part(const ScenDesc<T>* scen, int nscen, const int* work, int nwork, int R, int blocks,
                                  hipStream_t st, int part, int mode);
+    // adjoint support (buffers are [6][ny][pitch] state-shaped unless noted)
+    static hipError_t jvp(const KParams& P, const Bufs& B, const void* U, const void* dU, const void* dmu, int stage,
+                          void* E, void* dE, hipStream_t st);
+    static hipError_t vjp(const KParams& P, const Bufs& B, const void* U, const void* lam, int stage, double dt,
+                          void* GT, void* DU, void* FCX, void* FCY, void* SC, void* lam_in, void* gmu,
+                          hipStream_t st);
+    static hipError_t loss(const KParams& P, const Bufs& B, const void* U, const double* target, void* lam,
+                           double* part, hipStream_t st);
+    static hipError_t axpbz(const KParams& P, double a, const void* x, double c, const void* z, void* y,
+                            hipStream_t st);
+    static hipError_t dot(const KParams& P, const void* x, const void* y, double* part, hipStream_t st);
 };
 
 }  // namespace m2p

@@ -131,6 +131,47 @@ class Sim:
         A.check(A.lib().m2p_kernel_times(self._h, ms, C.byref(n)), "m2p_kernel_times")
         return list(ms), n.value
 
+    # -- gradients
+    def set_friction_field(self, tan_mu):
+        m = np.ascontiguousarray(tan_mu, dtype=np.float64)
+        A.check(A.lib().m2p_set_friction_field(self._h, A.dptr(m)), "m2p_set_friction_field")
+
+    def set_dt_schedule(self, dts):
+        d = np.ascontiguousarray(dts, dtype=np.float64)
+        A.check(A.lib().m2p_set_dt_schedule(self._h, A.dptr(d) if len(d) else None, len(d)),
+                "m2p_set_dt_schedule")
+
+    def loss(self, target_h) -> float:
+        t = np.ascontiguousarray(target_h, dtype=np.float64)
+        out = C.c_double()
+        A.check(A.lib().m2p_loss(self._h, A.dptr(t), C.byref(out)), "m2p_loss")
+        return out.value
+
+    def stage_jvp(self, dU, dmu=None, stage=0):
+        dU = np.ascontiguousarray(dU, dtype=np.float64)
+        dm = None if dmu is None else np.ascontiguousarray(dmu, dtype=np.float64)
+        E = np.empty_like(dU)
+        dE = np.empty_like(dU)
+        A.check(A.lib().m2p_stage_jvp(self._h, stage, A.dptr(dU), A.dptr(dm), A.dptr(E), A.dptr(dE)),
+                "m2p_stage_jvp")
+        return E, dE
+
+    def stage_vjp(self, lam, stage=0):
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        li = np.empty_like(lam)
+        gmu = np.empty((self.ny, self.nx), dtype=np.float64)
+        A.check(A.lib().m2p_stage_vjp(self._h, stage, A.dptr(lam), A.dptr(li), A.dptr(gmu)), "m2p_stage_vjp")
+        return li, gmu
+
+    def adjoint_run(self, nsteps, ckpt_every, target_h, vol_scale=1.0):
+        """Loss, dL/dmu (per cell) and dL/d(volume scale) of an nsteps run."""
+        t = np.ascontiguousarray(target_h, dtype=np.float64)
+        loss, gv = C.c_double(), C.c_double()
+        gmu = np.empty((self.ny, self.nx), dtype=np.float64)
+        A.check(A.lib().m2p_adjoint_run(self._h, int(nsteps), int(ckpt_every), A.dptr(t), float(vol_scale),
+                                        C.byref(loss), A.dptr(gmu), C.byref(gv)), "m2p_adjoint_run")
+        return loss.value, gmu, gv.value
+
     def device_ptr(self):
         p, pitch = C.c_void_p(), C.c_int64()
         A.check(A.lib().m2p_state_device_ptr(self._h, C.byref(p), C.byref(pitch)), "m2p_state_device_ptr")

@@ -1,0 +1,183 @@
+"""Tangent and adjoint of the step on the GPU.
+
+- the stage JVP (dual arithmetic of the executed scheme) against central
+  finite differences of the stage itself (FP64);
+- the stage VJP is the exact transpose of the JVP: <J du, lam> = <du, J^T lam>
+  to 1e-12 (FP64), for several boundary modes, viscosity and a friction field;
+- the checkpointed adjoint gradient of the deposit loss with respect to the
+  per-cell friction field and the release volume against central finite
+  differences of the FP64 CPU oracle with the same frozen time steps;
+- FP32 adjoint against the FP64 adjoint; bitwise reproducibility.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2104_06784_amd import inputs as I
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _prob(nx=40, ny=36, bc=(0, 0, 0, 0), visc=True, mu=True, seed=7):
+    dx = 10.0
+    dem = I.fractal_dem(nx, dx, seed, 40.0, tilt_deg=22.0, ny=ny)
+    h = I.cylinder(nx, ny, dx, dx, 0.35 * nx * dx, 0.5 * ny * dx, 0.25 * min(nx, ny) * dx, 8.0)
+    p = I.Params(delta_b_deg=20.0, cfl=0.2, bc=bc, inv_n_r=(1.0 / 268.0 if visc else 0.0))
+    tan_mu = None
+    if mu:
+        tan_mu = np.tan(np.radians(20.0 + 2.0 * I.smooth_field(max(nx, ny), seed + 1, 3.0)[:ny, :nx]))
+    return I.Problem("adj", nx, ny, dx, dx, p, dem, h, np.where(h > 0, 0.6, 0.0), tan_mu=tan_mu)
+
+
+def _moving_state(prob, steps=12):
+    from paper_2104_06784_amd.sim import Sim
+    s = Sim(prob, precision="f64")
+    s.run(steps)
+    return s.state()
+
+
+def _dot(a, b):
+    return float(np.sum(a * b))
+
+
+def test_stage_jvp_matches_finite_difference():
+    from paper_2104_06784_amd.sim import Sim
+    prob = _prob()
+    U = _moving_state(prob)
+    rng = np.random.default_rng(1)
+    dU = rng.standard_normal(U.shape) * (np.abs(U) + 1e-3) * 1e-2
+    dU[0] = np.abs(dU[0]) * (U[0] > 0)
+    dU[3] = np.abs(dU[3]) * (U[3] > 0)
+    lam = rng.standard_normal(U.shape)
+    # freeze the step: the CFL step of the unperturbed state
+    s2 = Sim(prob, precision="f64", set_state=False)
+    s2.set_state_raw(U)
+    dt = s2.step()
+    s = Sim(prob, precision="f64", set_state=False)
+    s.set_state_raw(U)
+    s.set_dt_schedule([dt])
+    _, dE = s.stage_jvp(dU)
+    eps = 1e-6
+    vals = []
+    for sgn in (1, -1):
+        q = Sim(prob, precision="f64", set_state=False)
+        q.set_state_raw(U + sgn * eps * dU)
+        q.set_dt_schedule([dt])
+        E, _ = q.stage_jvp(np.zeros_like(U))
+        vals.append(E)
+    fd = (vals[0] - vals[1]) / (2 * eps)
+    a, b = _dot(dE, lam), _dot(fd, lam)
+    _say(f"[jvp] <dE,lam> {a:.12e} fd {b:.12e}")
+    assert abs(a - b) <= 1e-6 * max(abs(a), abs(b))
+
+
+CASES = [
+    dict(bc=(0, 0, 0, 0), visc=True, mu=True),
+    dict(bc=(1, 1, 1, 1), visc=True, mu=False),
+    dict(bc=(1, 0, 0, 1), visc=False, mu=True, nx=61, ny=23),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("stage", [0, 1])
+def test_stage_vjp_is_transpose_of_jvp(case, stage):
+    from paper_2104_06784_amd.sim import Sim
+    kw = dict(CASES[case])
+    prob = _prob(**kw)
+    U = _moving_state(prob)
+    rng = np.random.default_rng(10 + case)
+    s = Sim(prob, precision="f64", set_state=False)
+    s.set_state_raw(U)
+    dU = rng.standard_normal(U.shape)
+    dmu = rng.standard_normal((prob.ny, prob.nx))
+    lam = rng.standard_normal(U.shape)
+    _, dE = s.stage_jvp(dU, dmu, stage=stage)
+    li, gmu = s.stage_vjp(lam, stage=stage)
+    lhs = _dot(dE, lam)
+    rhs = _dot(dU, li) + _dot(dmu, gmu)
+    _say(f"[vjp] case {case} stage {stage}: {lhs:.15e} {rhs:.15e}")
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), abs(rhs), 1e-300)
+
+
+def _loss_oracle(prob, tan_mu, scale, dts, target):
+    import dataclasses
+
+    import oracle
+    q = dataclasses.replace(prob, tan_mu=tan_mu, h_vert=prob.h_vert * scale)
+    o = oracle.OracleSim(q)
+    o.set_dt_schedule(dts)
+    o.run(len(dts))
+    h = o.fields()["h"]
+    return 0.5 * float(np.sum((h - target) ** 2)) * prob.dx * prob.dy
+
+
+def _calibration_case():
+    prob = _prob(48, 44, bc=(0, 0, 0, 0), visc=True, mu=True, seed=21)
+    mu_true = np.tan(np.radians(20.0 + 3.0 * I.smooth_field(48, 31, 4.0)[:44, :48]))
+    return prob, mu_true
+
+
+def test_adjoint_gradient_against_oracle_finite_differences():
+    import dataclasses
+
+    import oracle
+    from paper_2104_06784_amd.sim import Sim
+    prob, mu_true = _calibration_case()
+    nsteps = 60
+    # hidden truth on the oracle: friction field mu_true, volume x 1.2
+    ot = oracle.OracleSim(dataclasses.replace(prob, tan_mu=mu_true, h_vert=prob.h_vert * 1.2))
+    ot.run(nsteps)
+    target = ot.fields()["h"]
+    # base run's time steps, frozen for every finite difference
+    ob = oracle.OracleSim(prob)
+    dts = ob.run(nsteps)
+    g = Sim(prob, precision="f64")
+    loss, gmu, gvol = g.adjoint_run(nsteps, 16, target, 1.0)
+    lo = _loss_oracle(prob, prob.tan_mu, 1.0, dts, target)
+    _say(f"[adj] loss gpu {loss:.12e} oracle {lo:.12e}")
+    assert abs(loss - lo) <= 1e-10 * lo
+    rng = np.random.default_rng(5)
+    eps = 1e-6
+    for k in range(3):
+        d = I.smooth_field(48, 40 + k, 3.0)[:44, :48] * (0.5 + rng.random())
+        lp = _loss_oracle(prob, prob.tan_mu + eps * d, 1.0, dts, target)
+        lm = _loss_oracle(prob, prob.tan_mu - eps * d, 1.0, dts, target)
+        fd = (lp - lm) / (2 * eps)
+        ad = float(np.sum(gmu * d))
+        _say(f"[adj] mu direction {k}: adjoint {ad:.10e} oracle FD {fd:.10e}")
+        assert abs(ad - fd) <= 1e-5 * max(abs(fd), 1e-30)
+    lp = _loss_oracle(prob, prob.tan_mu, 1.0 + eps, dts, target)
+    lm = _loss_oracle(prob, prob.tan_mu, 1.0 - eps, dts, target)
+    fd = (lp - lm) / (2 * eps)
+    _say(f"[adj] volume: adjoint {gvol:.10e} oracle FD {fd:.10e}")
+    assert abs(gvol - fd) <= 1e-5 * abs(fd)
+    assert np.all(np.isfinite(gmu)) and np.max(np.abs(gmu)) > 0
+
+
+def test_adjoint_fp32_close_to_fp64_and_reproducible():
+    import oracle
+    from paper_2104_06784_amd.sim import Sim
+    prob, _ = _calibration_case()
+    nsteps = 60
+    ot = oracle.OracleSim(prob)
+    ot.run(nsteps)
+    target = ot.fields()["h"] * 1.1
+    res = {}
+    for prec in ("f64", "f32", "f32"):
+        g = Sim(prob, precision=prec)
+        res.setdefault(prec, []).append(g.adjoint_run(nsteps, 25, target, 1.0))
+    g64 = res["f64"][0][1]
+    a, b = res["f32"]
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and a[2] == b[2]
+    g32 = a[1]
+    cos = float(np.sum(g32 * g64) / (np.linalg.norm(g32) * np.linalg.norm(g64)))
+    rel = float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))
+    _say(f"[adj] fp32 vs fp64: cosine {cos:.6f}, rel L2 {rel:.3e}, vol {a[2]:.6e} vs {res['f64'][0][2]:.6e}")
+    assert cos >= 0.999 and rel <= 1e-2
+    assert abs(a[2] - res["f64"][0][2]) <= 1e-2 * abs(res["f64"][0][2])

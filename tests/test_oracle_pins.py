@@ -474,3 +474,18 @@ def test_invalid_state_rejected():
     bad[3, 3] = 1.5
     with pytest.raises(ValueError):
         s.set_state_si(prob.h_vert, bad)
+
+
+def test_frozen_time_steps_reproduce_the_run():
+    """A prescribed step sequence equal to the run's own CFL steps gives the
+    same result bitwise (the frozen-step mode used for gradient checks)."""
+    prob = I.config1(n=32)
+    a = _sim(prob)
+    dts = a.run(40)
+    b = _sim(prob)
+    b.set_dt_schedule(dts)
+    assert np.array_equal(b.run(40), dts)
+    assert np.array_equal(a.state(), b.state())
+    c = _sim(prob)
+    c.set_dt_schedule(dts * 0.5)
+    assert np.allclose(c.run(40), dts * 0.5, rtol=0, atol=0)
