@@ -123,6 +123,46 @@ def bench_batched(stream, steps: int, warmup: int, nscen: int = 256) -> dict:
             "speedup_vs_one_by_one": round(vb / v1, 3)}
 
 
+def bench_adjoint(stream, nsteps: int, ckpt: int) -> dict:
+    """Config 5: gradient of the deposit misfit with respect to the per-cell
+    friction field and the release volume through nsteps FP32 steps
+    (checkpoint every ckpt steps, segments recomputed), against the plain
+    forward run of the same workload."""
+    import torch
+
+    from paper_2104_06784_amd import inputs
+    from paper_2104_06784_amd.sim import Sim
+
+    log("[bench] adjoint: target from the hidden-parameter run")
+    truth = inputs.config5(truth=True)
+    t = Sim(truth, precision="f32", stream=stream)
+    t.run(nsteps)
+    target = t.fields()["h"]
+    del t
+    prob = inputs.config5()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f = Sim(prob, precision="f32", stream=stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    f.run(nsteps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_fwd = e0.elapsed_time(e1)
+    del f
+    g = Sim(prob, precision="f32", stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss, gmu, gvol = g.adjoint_run(nsteps, ckpt, target, 1.0)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    cells = prob.cells
+    return {"value": round(cells * nsteps / sec / 1e6, 2), "unit": "Mcell-steps/s", "cells": cells,
+            "steps": nsteps, "checkpoint_every": ckpt, "seconds": round(sec, 3),
+            "forward_only_value": round(cells * nsteps / (ms_fwd / 1e3) / 1e6, 2),
+            "cost_vs_forward": round(sec / (ms_fwd / 1e3), 2), "loss": loss,
+            "grad_mu_l2": float(np.linalg.norm(gmu)), "grad_vol": gvol}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +174,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=50, help="0 skips the batched-ensemble measurement")
+    ap.add_argument("--adjoint-steps", type=int, default=2000, help="0 skips the forward+adjoint measurement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run 3 device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -210,6 +251,10 @@ def main():
         out["batched"] = bench_batched(stream, args.batched_steps, 5)
         log(f"[bench] batched {out['batched']['value']:.1f} Mcell-steps/s "
             f"({out['batched']['speedup_vs_one_by_one']:.2f}x one-by-one)")
+    if args.adjoint_steps > 0:
+        out["fwd_adjoint"] = bench_adjoint(stream, args.adjoint_steps, 100)
+        log(f"[bench] forward+adjoint {out['fwd_adjoint']['value']:.1f} Mcell-steps/s "
+            f"({out['fwd_adjoint']['cost_vs_forward']:.1f}x the forward)")
     if args.copy_probe_mib > 0:
         # plain device-to-device copies of known size, so that hardware byte
         # counters of the step kernels can be calibrated against them
