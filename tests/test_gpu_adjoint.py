@@ -51,10 +51,13 @@ def test_stage_jvp_matches_finite_difference():
     prob = _prob()
     U = _moving_state(prob)
     rng = np.random.default_rng(1)
-    # perturb wet cells only: in dry regions every difference is exactly 0,
-    # minmod(0, 0) sits on its kink and the derivative convention (the branch
-    # the values select, here 0) differs from a one-sided finite difference
+    # a generic point: resting or dry neighbours hold exactly equal values, so
+    # minmod(0, 0) and max(a, a) sit on their kinks, where the derivative takes
+    # the branch the values select and a finite difference sees one-sided
+    # slopes.  Small noise on the wet cells removes the ties; perturbations
+    # stay on wet cells.
     wet = (U[0] + U[3]) > 1e-3
+    U = U + wet * 1e-3 * np.abs(U).max(axis=(1, 2))[:, None, None] * rng.random(U.shape)
     dU = rng.standard_normal(U.shape) * (np.abs(U) + 1e-3) * 1e-2 * wet
     lam = rng.standard_normal(U.shape)
     # freeze the step: the CFL step of the unperturbed state
