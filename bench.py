@@ -3,9 +3,12 @@
 ``python bench.py [--steps K] [--warmup W]`` times K steps of the 4096^2
 large-event workload (fractal valley DEM, 2.5e7 m^3 release, FP32 state with
 FP64 dt / time / volume sums) with the inputs resident in HBM, and prints one
-JSON line: Mcell-steps/s, the roofline of the dominant kernel (stage 2, timed
-live with HIP events on the stream it runs on) and the FP64 CPU oracle timed
-on a bounded sample of the same workload.
+JSON line: Mcell-steps/s; the roofline of the dominant kernel (stage 2, timed
+live with HIP events on the stream it runs on), which is bound by vector-ALU
+issue: algorithmic FLOPs per launch over the launch time against the non-packed
+vector peak, with its HBM rate and fraction beside it; the batched-ensemble and
+forward+adjoint throughputs; and the FP64 CPU oracle timed on a bounded sample
+of the same workload.
 """
 from __future__ import annotations
 
@@ -22,6 +25,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mcell-steps/s (fwd, batched, fwd+adjoint) + % HBM roofline at fixed accuracy"
 HBM_PEAK_GBS = 8000.0
+# vector ALU peak without packed FP32 (the kernels are built without packed
+# instructions): 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz; the
+# FP64 vector peak is the same 78.6 TFLOP/s
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # algorithmic bytes per cell and launch (S = bytes per scalar): stage 1 reads
 # U^n (6 fields) and the DEM and writes U* (6); stage 2 reads U* (6), the
 # cell's own U^n (6) and the DEM and writes U^{n+1} (6)
@@ -58,6 +65,30 @@ def recorded_traffic(n: int, precision: str):
             rec = json.loads(line.split(":", 1)[1])
             if rec.get("kernel_source_hash") == kernel_source_hash():
                 return rec["stage2_hbm_bytes_per_launch"]
+    return None
+
+
+def stage_flops(stage: int, visc: bool) -> float:
+    """Algorithmic FLOPs of one cell in one stage (add, mul, div, sqrt)."""
+    import ctypes as C
+
+    from paper_2104_06784_amd import _abi
+    out = (C.c_double * 5)()
+    _abi.check(_abi.lib().m2p_stage_flops(stage, 1 if visc else 0, out), "m2p_stage_flops")
+    return float(out[0] + out[1] + out[2] + out[3])
+
+
+def recorded_valu(n: int, precision: str):
+    """VALU busy fraction of the stage-2 kernel from the rocprofv3 counter
+    summary in profiles/, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"stage_kernels_cfg3_{n}_{precision}_valu_counters.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("valu_json:"):
+            rec = json.loads(line.split(":", 1)[1])
+            if rec.get("kernel_source_hash") == kernel_source_hash():
+                return rec
     return None
 
 
@@ -218,7 +249,11 @@ def main():
     t2 = kt[1] / nk / 1e3
     t1 = kt[0] / nk / 1e3
     bytes2 = FIELDS_STAGE2 * S * cells
-    ach = bytes2 / t2 / 1e9
+    gbs = bytes2 / t2 / 1e9
+    visc = prob.params.inv_n_r > 0
+    fl2 = stage_flops(2, visc)
+    ach = fl2 * cells / t2 / 1e12
+    valu = recorded_valu(args.n, args.precision)
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -235,17 +270,22 @@ def main():
         "config": {"workload": f"large event {prob.nx}x{prob.ny}, dx 5 m, fractal valley DEM, 2.5e7 m^3 "
                                f"half-ellipsoid release, phi_s 0.55, {args.precision} state + FP64 dt/volume",
                    "cells": cells, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4),
+        # the stage kernels are bound by vector-ALU instruction issue, not by
+        # HBM: achieved = algorithmic FLOPs of a stage-2 launch / its time
+        "roofline": {"bound": "alu", "achieved": round(ach, 2), "peak": round(ALU_PEAK_TFLOPS, 1),
+                     "unit": "TFLOP/s", "frac": round(ach / ALU_PEAK_TFLOPS, 4),
                      "traffic": recorded_traffic(args.n, args.precision),
                      "kernel": "stage 2 (U* stencil + own U^n + DEM -> U^{n+1})",
+                     "flops_per_cell": fl2, "flops_per_launch": fl2 * cells,
                      "kernel_ms": round(t2 * 1e3, 4), "stage1_ms": round(t1 * 1e3, 4),
                      "finalize_ms": round(kt[2] / nk, 4),
-                     "algorithmic_bytes_per_launch": bytes2,
-                     "step_algorithmic_frac": round((FIELDS_STAGE1 + FIELDS_STAGE2) * S * cells
-                                                    / (ms / args.steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+                     "valu_busy": None if valu is None else valu.get("stage2_valu_busy"),
+                     "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": bytes2,
+                             "step_algorithmic_frac": round((FIELDS_STAGE1 + FIELDS_STAGE2) * S * cells
+                                                            / (ms / args.steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}},
     }
-    log(f"[bench] {value:.1f} Mcell-steps/s, stage2 {t2 * 1e3:.3f} ms ({ach:.0f} GB/s)")
+    log(f"[bench] {value:.1f} Mcell-steps/s, stage2 {t2 * 1e3:.3f} ms ({ach:.1f} TFLOP/s, {gbs:.0f} GB/s)")
     del sim
     if args.batched_steps > 0:
         out["batched"] = bench_batched(stream, args.batched_steps, 5)

@@ -43,6 +43,7 @@ extern "C" {
 #define M2P_EDTFLOOR -6    /* the CFL time step fell below 1e-12 of the grid's gravity-wave time */
 #define M2P_EMAXSTEPS -7   /* m2p_run_to stopped at max_steps before t_end */
 #define M2P_ESTATE -8      /* call order (step before set_state, poisoned context, ...) */
+#define M2P_EIO -9         /* a file could not be opened, read or written */
 
 /* arithmetic of the state: FP64, or FP32 state with FP64 time, dt and volume sums */
 #define M2P_FP64 0
@@ -206,6 +207,43 @@ int m2p_kernel_times(m2p_ctx *c, double *ms3, int64_t *nsteps);
 /* Device pointer of the current state buffer and its row pitch (elements);
  * field k starts at ptr + k * ny * pitch. */
 int m2p_state_device_ptr(m2p_ctx *c, void **ptr, int64_t *pitch);
+
+/* Floating-point work of one cell in one stage of the forward step (the
+ * scheme of Sect. 2.2 on the model of Appendix A), for rooflines.  Counted on
+ * the host by running one cell's share of the stage kernel's arithmetic --
+ * its geometry, one x-face and one y-face central flux, one new neighbour
+ * difference per direction and field, sources, viscous face terms, update
+ * and clamps, and in stage 2 the Heun average and CFL speeds -- through the
+ * kernels' own device functions with an operation-counting number type, on
+ * a wet sliding cell (the longer branch of the Coulomb clamp).
+ * stage: 1 or 2.  visc: nonzero when the viscous term is on (inv_n_r > 0).
+ * out[5] (host): additions and subtractions, multiplications, divisions,
+ * square roots, comparisons (min / max / sign tests).  FLOPs are the sum of
+ * the first four.  M2P_EINVAL for another stage or NULL out.  Needs no GPU. */
+int m2p_stage_flops(int32_t stage, int32_t visc, double *out);
+
+/* ---------------------------------------------------------------------------
+ * GIS raster input and output: the DEM and initial fields come from GIS
+ * systems as ASCII grids and results go back in that form (Sect. 1;
+ * Sect. 3.1.2, Stages 1 and 3).  ESRI ASCII grid: header keys ncols, nrows,
+ * xllcorner|xllcenter, yllcorner|yllcenter, cellsize, optional NODATA_value
+ * (case-insensitive), then nrows lines of ncols values, northernmost first.
+ * Arrays here are row-major ny*nx with row 0 at the southern edge.
+ * ------------------------------------------------------------------------- */
+
+/* Read an ESRI ASCII grid.  Fills g (nx = ncols, ny = nrows, dx = dy =
+ * cellsize), the lower-left cell corner (x0, y0; may be NULL) and the NODATA
+ * value (NaN when the file has none; may be NULL).  values (host, capacity
+ * doubles) may be NULL to read the header only; NODATA cells are returned as
+ * stored.  Errors: M2P_EIO (open), M2P_EINVAL (malformed header, too few or
+ * too many values, capacity < nx*ny). */
+int m2p_esri_read(const char *path, m2p_grid *g, double *x0, double *y0, double *nodata, double *values,
+                  size_t capacity);
+
+/* Write values (host, ny*nx, row 0 south) as an ESRI ASCII grid with the
+ * lower-left corner (x0, y0); non-finite values are written as nodata.
+ * Needs square cells (dx == dy).  Errors: M2P_EINVAL, M2P_EIO. */
+int m2p_esri_write(const char *path, const m2p_grid *g, double x0, double y0, double nodata, const double *values);
 
 /* ---------------------------------------------------------------------------
  * Gradients (back-calculation of friction and release volume, the paper's

@@ -23,6 +23,7 @@ M2P_ENEGDEPTH = -5
 M2P_EDTFLOOR = -6
 M2P_EMAXSTEPS = -7
 M2P_ESTATE = -8
+M2P_EIO = -9
 M2P_FP64 = 0
 M2P_FP32 = 1
 M2P_DEPTH_NORMAL = 0
@@ -90,6 +91,9 @@ SIGNATURES = {
     "m2p_state_device_ptr": (C.c_int, [_P, C.POINTER(_P), C.POINTER(C.c_int64)]),
     "m2p_set_profiling": (C.c_int, [_P, C.c_int32]),
     "m2p_kernel_times": (C.c_int, [_P, _dp, C.POINTER(C.c_int64)]),
+    "m2p_stage_flops": (C.c_int, [C.c_int32, C.c_int32, _dp]),
+    "m2p_esri_read": (C.c_int, [C.c_char_p, C.POINTER(Grid), _dp, _dp, _dp, _dp, C.c_size_t]),
+    "m2p_esri_write": (C.c_int, [C.c_char_p, C.POINTER(Grid), C.c_double, C.c_double, C.c_double, _dp]),
     "m2p_set_friction_field": (C.c_int, [_P, _dp]),
     "m2p_set_dt_schedule": (C.c_int, [_P, _dp, C.c_int64]),
     "m2p_loss": (C.c_int, [_P, _dp, _dp]),

@@ -31,6 +31,10 @@ PER_FILE = {
                     "-fno-trapping-math"],
     "m2p_abi.hip": ["-ffp-contract=off"],
     "m2p_batch.hip": ["-ffp-contract=off"],
+    # host-only operation count of the stage arithmetic
+    "m2p_flops.hip": ["-ffp-contract=off"],
+    # host-only ESRI ASCII grid reader and writer
+    "m2p_gis.hip": ["-ffp-contract=off"],
 }
 
 

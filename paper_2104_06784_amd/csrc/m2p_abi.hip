@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/m2p.h"
+#include "m2p.h"
 #include "m2p_host.h"
 #include "m2p_launch.h"
 
@@ -292,6 +292,7 @@ const char* m2p_strerror(int code)
         case M2P_EDTFLOOR: return "time step below floor";
         case M2P_EMAXSTEPS: return "maximum number of steps reached";
         case M2P_ESTATE: return "invalid call order or poisoned context";
+        case M2P_EIO: return "file input/output error";
         default: return "unknown status";
     }
 }

@@ -291,29 +291,160 @@ __global__ void __launch_bounds__(128) k_adj_post(KParams P, const T* __restrict
     dn[3] = TT((g5.N.nX - g5.S.nX) / two_deta, T(0));
     dn[4] = TT((g5.N.nY - g5.S.nY) / two_deta, T(0));
     dn[5] = TT((g5.N.nZ - g5.S.nZ) / two_deta, T(0));
-    T g[13];
-    for (int d = 0; d < 13; d++) {
-        TT te[NF], uc[NF];
-        for (int k = 0; k < NF; k++) {
-            te[k] = TT(tent[k], d == k ? T(1) : T(0));
-            uc[k] = TT(s.row[2][k], d == 6 + k ? T(1) : T(0));
-        }
-        // kappa_s depends on the cell's own velocities only (the interphase
-        // pressure gradient does not enter it)
-        Src<TT> Sr;
-        sources(K, P.flags, uc, gC, dn, TT(0.0), TT(0.0), Sr);
+    // clamp inputs: tentative state (6), kappa_s, friction; kappa_s depends on
+    // the cell's own velocities only (the interphase pressure gradient does
+    // not enter it)
+    Src<TT> S0;
+    {
+        TT uc[NF];
+        for (int k = 0; k < NF; k++) uc[k] = TT(s.row[2][k], T(0));
+        sources(K, P.flags, uc, gC, dn, TT(0.0), TT(0.0), S0);
+    }
+    T gcl[8];
+    for (int d = 0; d < 8; d++) {
         TT o[NF];
-        for (int k = 0; k < NF; k++) o[k] = te[k];
-        clamp_cell(K, gC, Sr.kappa_s, TT(dt, T(0)), TT(tmu, d == 12 ? T(1) : T(0)), o);
+        for (int k = 0; k < NF; k++) o[k] = TT(tent[k], d == k ? T(1) : T(0));
+        clamp_cell(K, gC, TT(S0.kappa_s.v, d == 6 ? T(1) : T(0)), TT(dt, T(0)), TT(tmu, d == 7 ? T(1) : T(0)), o);
         T acc = T(0);
         for (int k = 0; k < NF; k++) acc += lo[k] * o[k].d;
-        g[d] = acc;
+        gcl[d] = acc;
+    }
+    T g[13];
+    for (int k = 0; k < NF; k++) g[k] = gcl[k];
+    g[12] = gcl[7];
+    for (int d = 0; d < NF; d++) {
+        TT uc[NF];
+        for (int k = 0; k < NF; k++) uc[k] = TT(s.row[2][k], d == k ? T(1) : T(0));
+        Src<TT> Sr;
+        sources(K, P.flags, uc, gC, dn, TT(0.0), TT(0.0), Sr);
+        g[6 + d] = gcl[6] * Sr.kappa_s.d;
     }
     for (int k = 0; k < NF; k++) {
         GT[k * fs + c] = g[k];
         DU[k * fs + c] = g[k] + g[6 + k];
     }
     gmu[c] += g[12];
+}
+
+// Which argument the (dual) minmod selects: 0 the first, 1 the second, 2
+// neither (result 0).  Mirrors the selects of minmod on dual numbers.
+template <typename T>
+__device__ __forceinline__ int minmod_pick(T a, T b)
+{
+    const bool pos = (a > T(0)) & (b > T(0));
+    const bool neg = (a < T(0)) & (b < T(0));
+    if (pos) return a < b ? 0 : 1;
+    if (neg) return a > b ? 0 : 1;
+    return 2;
+}
+
+// Transpose of one reconstructed side: cotangents of its flux F, conserved
+// values q and phase speeds a pulled back to the side's six conserved values
+// by six dual evaluations of side_flux.
+template <typename T>
+__device__ __forceinline__ void side_flux_vjp(const Consts<Dual<T>>& K, const T u[NF], const Geo<Dual<T>>& g, int d,
+                                              const T lF[NF], const T lq[NF], const T la[2], T lu[NF])
+{
+    using TT = Dual<T>;
+    for (int dir = 0; dir < NF; dir++) {
+        TT ud[NF];
+#pragma unroll
+        for (int k = 0; k < NF; k++) ud[k] = TT(u[k], k == dir ? T(1) : T(0));
+        TT F[NF], q[NF], a[2];
+        side_flux(K, ud, g, d, F, q, a);
+        T acc = la[0] * a[0].d + la[1] * a[1].d;
+#pragma unroll
+        for (int k = 0; k < NF; k++) acc += lF[k] * F[k].d + lq[k] * q[k].d;
+        lu[dir] = acc;
+    }
+}
+
+// Transpose of the face flux H(w) of face_flux: cotangent gH of H pulled back
+// to the 24 stencil values w[4][NF] (out[6 q + k]).  Central flux by hand
+// (H = (F_L + F_R)/2 - a/2 (q_R - q_L), a = max of the side speeds per
+// phase), each side through side_flux_vjp, then the reconstruction through
+// the branch minmod selects -- the same linear map as dual evaluations of
+// face_flux along the 24 unit directions.
+template <typename T>
+__device__ __forceinline__ void face_flux_vjp(const KParams& P, const T w[4][NF], const Geo<T>& ga, const Geo<T>& gb,
+                                              int d, const T gH[NF], T out[24])
+{
+    using TT = Dual<T>;
+    const Consts<TT> K(P);
+    const Geo<TT> gaD = lift(ga), gbD = lift(gb);
+    T uL[NF], uR[NF];
+    int p0[NF], p1[NF];
+#pragma unroll
+    for (int k = 0; k < NF; k++) {
+        const T a0 = w[1][k] - w[0][k], b0 = w[2][k] - w[1][k], b1 = w[3][k] - w[2][k];
+        const TT s0 = minmod(TT(a0, T(0)), TT(b0, T(0)));
+        const TT s1 = minmod(TT(b0, T(0)), TT(b1, T(0)));
+        p0[k] = minmod_pick(a0, b0);
+        p1[k] = minmod_pick(b0, b1);
+        uL[k] = (TT(w[1][k], T(0)) + TT(0.5) * s0).v;
+        uR[k] = (TT(w[2][k], T(0)) - TT(0.5) * s1).v;
+    }
+    // side values as the dual evaluation computes them
+    TT uLd[NF], uRd[NF], FL[NF], FR[NF], qL[NF], qR[NF], aL[2], aR[2];
+#pragma unroll
+    for (int k = 0; k < NF; k++) {
+        uLd[k] = TT(uL[k], T(0));
+        uRd[k] = TT(uR[k], T(0));
+    }
+    side_flux(K, uLd, gaD, d, FL, qL, aL);
+    side_flux(K, uRd, gbD, d, FR, qR, aR);
+    T lF[NF], lqL[NF], lqR[NF], laL[2], laR[2];
+#pragma unroll
+    for (int ph = 0; ph < 2; ph++) {
+        const bool left = aL[ph].v > aR[ph].v;
+        const T am = left ? aL[ph].v : aR[ph].v;
+        T la = T(0);
+#pragma unroll
+        for (int k = 3 * ph; k < 3 * ph + 3; k++) {
+            lF[k] = T(0.5) * gH[k];
+            lqL[k] = T(0.5) * am * gH[k];
+            lqR[k] = -(T(0.5) * am * gH[k]);
+            la += gH[k] * (qR[k].v - qL[k].v);
+        }
+        la = -(T(0.5) * la);
+        laL[ph] = left ? la : T(0);
+        laR[ph] = left ? T(0) : la;
+    }
+    T luL[NF], luR[NF];
+    side_flux_vjp(K, uL, gaD, d, lF, lqL, laL, luL);
+    side_flux_vjp(K, uR, gbD, d, lF, lqR, laR, luR);
+    T lw[4][NF];
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+        for (int k = 0; k < NF; k++) lw[q][k] = T(0);
+#pragma unroll
+    for (int k = 0; k < NF; k++) {
+        // uL = w1 + s0 / 2, s0 = minmod(w1 - w0, w2 - w1)
+        lw[1][k] += luL[k];
+        const T ls0 = T(0.5) * luL[k];
+        if (p0[k] == 0) {
+            lw[1][k] += ls0;
+            lw[0][k] -= ls0;
+        } else if (p0[k] == 1) {
+            lw[2][k] += ls0;
+            lw[1][k] -= ls0;
+        }
+        // uR = w2 - s1 / 2, s1 = minmod(w2 - w1, w3 - w2)
+        lw[2][k] += luR[k];
+        const T ls1 = -(T(0.5) * luR[k]);
+        if (p1[k] == 0) {
+            lw[2][k] += ls1;
+            lw[1][k] -= ls1;
+        } else if (p1[k] == 1) {
+            lw[3][k] += ls1;
+            lw[2][k] -= ls1;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+        for (int k = 0; k < NF; k++) out[6 * q + k] = lw[q][k];
 }
 
 // Pass B, faces: x-faces (d = 0) for i in [-1, nx-1] (face between i and i+1)
@@ -368,18 +499,7 @@ __global__ void __launch_bounds__(128) k_adj_face(KParams P, const T* __restrict
         return geometry(bv(ii + 1, jj), bv(ii - 1, jj), bv(ii, jj + 1), bv(ii, jj - 1), Kb.two_dxi, Kb.two_deta);
     };
     const Geo<T> ga = geo(li, lj), gb = geo(ri, rj);
-    using TT = Dual<T>;
-    const Consts<TT> K(P);
-    for (int dir = 0; dir < 24; dir++) {
-        TT w[4][NF];
-        for (int q = 0; q < 4; q++)
-            for (int k = 0; k < NF; k++) w[q][k] = TT(w0[q][k], dir == 6 * q + k ? T(1) : T(0));
-        TT H[NF];
-        face_flux(K, w, ga, gb, d, H);
-        T acc = T(0);
-        for (int k = 0; k < NF; k++) acc += gH[k] * H[k].d;
-        out[dir] = acc;
-    }
+    face_flux_vjp(P, w0, ga, gb, d, gH, out);
 }
 
 // Source input slots: 0..5 centre fields; 6..21 neighbour (E, W, N, S) x
@@ -408,8 +528,50 @@ __device__ __forceinline__ void src_slot(int s, int& di, int& dj, int& k)
     k = 3 + f;
 }
 
+// Slot of field k of the box cell (a, c) = (i - 1 + c, j - 1 + a), or -1 if
+// the source does not read that field there (the inverse of src_slot).
+__device__ __forceinline__ int box_slot(int a, int c, int k)
+{
+    if (a == 1 && c == 1) return k;
+    const bool edge = a == 1 || c == 1;
+    if (edge) {
+        const int n = (a == 1) ? (c == 2 ? 0 : 1) : (a == 2 ? 2 : 3);
+        const int f = k == 0 ? 0 : (k >= 3 ? k - 2 : -1);
+        return f < 0 ? -1 : 6 + 4 * n + f;
+    }
+    if (k < 3) return -1;
+    const int n = (a == 2 ? 0 : 2) + (c == 2 ? 0 : 1);
+    return 22 + 3 * n + (k - 3);
+}
+
+// Transpose of one viscous face term (visc_xface_c for d = 0, visc_yface_c
+// for d = 1): cotangents (l0, l1) of its two outputs pulled back to its ten
+// scalar inputs (u0, w0, u1, w1, cd u0, cd w0, cd u1, cd w1, Jh0, Jh1).
+template <typename T>
+__device__ __forceinline__ void visc_face_vjp(int d, const T in[10], const Geo<Dual<T>>& ga, const Geo<Dual<T>>& gb,
+                                              Dual<T> h, T l0, T l1, T lin[10])
+{
+    using TT = Dual<T>;
+    for (int dir = 0; dir < 10; dir++) {
+        TT x[10];
+#pragma unroll
+        for (int q = 0; q < 10; q++) x[q] = TT(in[q], q == dir ? T(1) : T(0));
+        TT o0, o1;
+        if (d == 0)
+            visc_xface_c(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], x[8], x[9], ga, gb, h, o0, o1);
+        else
+            visc_yface_c(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], x[8], x[9], ga, gb, h, o0, o1);
+        lin[dir] = l0 * o0.d + l1 * o1.d;
+    }
+}
+
 // Pass B, sources: cotangent dt * GT_c (momentum components) pulled back
-// through S_c to its 34 input slots, into SC[cell][34].
+// through S_c to its 34 input slots, into SC[cell][34].  Chain rule over the
+// structure of cell_sources: the local sources of the cell's six fields and of
+// the two fluid-pressure gradients (8 dual evaluations of sources), the
+// gradients to the neighbours' thicknesses (fluid_G), and the viscous
+// operator through its four face terms, the central differences and the
+// desingularised velocities of the 3 x 3 box.
 template <typename T>
 __global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict__ U, const T* __restrict__ GT,
                                                  const T* __restrict__ b, T dt, T* __restrict__ SC)
@@ -426,37 +588,191 @@ __global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict_
     for (int k = 0; k < NF; k++) gS[k] = dt * GT[k * fs + c];
     using TT = Dual<T>;
     const Consts<TT> K(P);
-    for (int sl = 0; sl < 34; sl++) {
-        int di, dj, kk;
-        src_slot(sl, di, dj, kk);
-        Stencil<TT> sd;
-        // every stencil position holding cell (i + di, j + dj) gets the tangent
-        for (int q = 0; q < 5; q++)
-            for (int k = 0; k < NF; k++) {
-                sd.row[q][k] = TT(s.row[q][k], (dj == 0 && q - 2 == di && k == kk) ? T(1) : T(0));
-                sd.col[q][k] = TT(s.col[q][k], (di == 0 && q - 2 == dj && k == kk) ? T(1) : T(0));
-            }
+    const Geo<TT> gC = lift(g5.C), gW = lift(g5.W), gE = lift(g5.E), gSo = lift(g5.S), gN = lift(g5.N);
+    T lam[34];
+    for (int q = 0; q < 34; q++) lam[q] = T(0);
+    const T two_dxi = T(P.two_dxi), two_deta = T(P.two_deta);
+    TT dn[6];
+    dn[0] = TT((g5.E.nX - g5.W.nX) / two_dxi, T(0));
+    dn[1] = TT((g5.E.nY - g5.W.nY) / two_dxi, T(0));
+    dn[2] = TT((g5.E.nZ - g5.W.nZ) / two_dxi, T(0));
+    dn[3] = TT((g5.N.nX - g5.S.nX) / two_deta, T(0));
+    dn[4] = TT((g5.N.nY - g5.S.nY) / two_deta, T(0));
+    dn[5] = TT((g5.N.nZ - g5.S.nZ) / two_deta, T(0));
+    auto fg = [&](const T* u, const Geo<TT>& g, int dir) {
+        return fluid_G(TT(u[0], dir == 0 ? T(1) : T(0)), TT(u[3], dir == 1 ? T(1) : T(0)), g);
+    };
+    const T dGx = ((fg(s.row[3], gE, -1) - fg(s.row[1], gW, -1)) / K.two_dxi).v;
+    const T dGy = ((fg(s.col[3], gN, -1) - fg(s.col[1], gSo, -1)) / K.two_deta).v;
+
+    // viscous operator: values of the box velocities, thickness products,
+    // central differences and face terms
+    T u9[3][3], w9[3][3], Jh[5], cyu[3], cyw[3], cxu[3], cxw[3], SvX = T(0), SvY = T(0);
+    const Consts<T> Kb(P);
+    if (P.visc) {
         for (int a = 0; a < 3; a++)
-            for (int cc = 0; cc < 3; cc++)
-                for (int k = 0; k < NF; k++)
-                    sd.box[a][cc][k] = TT(s.box[a][cc][k], (a - 1 == dj && cc - 1 == di && k == kk) ? T(1) : T(0));
+            for (int cc = 0; cc < 3; cc++) {
+                u9[a][cc] = dsg(s.box[a][cc][4], s.box[a][cc][3], Kb.md);
+                w9[a][cc] = dsg(s.box[a][cc][5], s.box[a][cc][3], Kb.md);
+            }
+        Jh[0] = s.row[2][0] + s.row[2][3];  // C
+        Jh[1] = s.row[1][0] + s.row[1][3];  // W
+        Jh[2] = s.row[3][0] + s.row[3][3];  // E
+        Jh[3] = s.col[1][0] + s.col[1][3];  // S
+        Jh[4] = s.col[3][0] + s.col[3][3];  // N
+        for (int q = 0; q < 3; q++) {
+            cyu[q] = cdiff(u9[2][q], u9[0][q], Kb.deta);
+            cyw[q] = cdiff(w9[2][q], w9[0][q], Kb.deta);
+            cxu[q] = cdiff(u9[q][2], u9[q][0], Kb.dxi);
+            cxw[q] = cdiff(w9[q][2], w9[q][0], Kb.dxi);
+        }
+        T FX0, FY0, FX1, FY1, GX0, GY0, GX1, GY1;
+        visc_xface_c(u9[1][0], w9[1][0], u9[1][1], w9[1][1], cyu[0], cyw[0], cyu[1], cyw[1], Jh[1], Jh[0], g5.W, g5.C,
+                     Kb.dxi, FX0, FY0);
+        visc_xface_c(u9[1][1], w9[1][1], u9[1][2], w9[1][2], cyu[1], cyw[1], cyu[2], cyw[2], Jh[0], Jh[2], g5.C, g5.E,
+                     Kb.dxi, FX1, FY1);
+        visc_yface_c(u9[0][1], w9[0][1], u9[1][1], w9[1][1], cxu[0], cxw[0], cxu[1], cxw[1], Jh[3], Jh[0], g5.S, g5.C,
+                     Kb.deta, GX0, GY0);
+        visc_yface_c(u9[1][1], w9[1][1], u9[2][1], w9[2][1], cxu[1], cxw[1], cxu[2], cxw[2], Jh[0], Jh[4], g5.C, g5.N,
+                     Kb.deta, GX1, GY1);
+        SvX = (FX1 - FX0) / Kb.dxi + (GX1 - GX0) / Kb.deta;
+        SvY = (FY1 - FY0) / Kb.dxi + (GY1 - GY0) / Kb.deta;
+    }
+
+    // (1) local sources: the cell's six fields and the two gradients
+    T lGx = T(0), lGy = T(0);
+    for (int dir = 0; dir < 8; dir++) {
+        TT uc[NF];
+        for (int k = 0; k < NF; k++) uc[k] = TT(s.row[2][k], dir == k ? T(1) : T(0));
         Src<TT> Sr;
-        TT svx, svy;
-        cell_sources(P, K, sd, g5, Sr, svx, svy);
+        sources(K, P.flags, uc, gC, dn, TT(dGx, dir == 6 ? T(1) : T(0)), TT(dGy, dir == 7 ? T(1) : T(0)), Sr);
         T acc = T(0);
         for (int ph = 0; ph < 2; ph++)
             for (int a = 0; a < 2; a++) {
                 TT v = Sr.sn[ph][a];
                 v += Sr.sf[ph][a];
                 v += Sr.sv[ph][a];
-                if (ph == 1) {
-                    v += Sr.sd[a];
-                    v += a == 0 ? svx : svy;
-                }
+                if (ph == 1) v += Sr.sd[a];
                 acc += gS[3 * ph + 1 + a] * v.d;
             }
-        out[sl] = acc;
+        if (P.visc) {
+            acc += gS[4] * (K.eps * Sr.phif * K.inv_n_r * TT(SvX, T(0))).d;
+            acc += gS[5] * (K.eps * Sr.phif * K.inv_n_r * TT(SvY, T(0))).d;
+        }
+        if (dir < 6)
+            lam[dir] += acc;
+        else if (dir == 6)
+            lGx = acc;
+        else
+            lGy = acc;
     }
+    // (2) gradients of J_b h pbar^f to the neighbours' m^s, m^f
+    {
+        const T* cell[4] = {s.row[3], s.row[1], s.col[3], s.col[1]};  // E, W, N, S
+        const Geo<TT>* geo[4] = {&gE, &gW, &gN, &gSo};
+        const T coef[4] = {lGx, -lGx, lGy, -lGy};
+        for (int n = 0; n < 4; n++) {
+            const TT den = n < 2 ? K.two_dxi : K.two_deta;
+            for (int dir = 0; dir < 2; dir++) lam[6 + 4 * n + dir] += coef[n] * (fg(cell[n], *geo[n], dir) / den).d;
+        }
+    }
+    // (3) viscous operator
+    if (P.visc) {
+        const T phif = dsg(s.row[2][3], s.row[2][0] + s.row[2][3], Kb.md);
+        const T coef = Kb.eps * phif * Kb.inv_n_r;
+        const T lX = gS[4] * coef, lY = gS[5] * coef;
+        T lu9[3][3], lw9[3][3], lJh[5], lcyu[3], lcyw[3], lcxu[3], lcxw[3];
+        for (int a = 0; a < 3; a++)
+            for (int cc = 0; cc < 3; cc++) lu9[a][cc] = lw9[a][cc] = T(0);
+        for (int q = 0; q < 5; q++) lJh[q] = T(0);
+        for (int q = 0; q < 3; q++) lcyu[q] = lcyw[q] = lcxu[q] = lcxw[q] = T(0);
+        T in[10], lin[10];
+        // x-face i - 1/2 (FX0, FY0) enters with -1/dxi, x-face i + 1/2 with +1/dxi
+        for (int f = 0; f < 2; f++) {
+            const int c0 = f, c1 = f + 1;
+            in[0] = u9[1][c0];
+            in[1] = w9[1][c0];
+            in[2] = u9[1][c1];
+            in[3] = w9[1][c1];
+            in[4] = cyu[c0];
+            in[5] = cyw[c0];
+            in[6] = cyu[c1];
+            in[7] = cyw[c1];
+            in[8] = f == 0 ? Jh[1] : Jh[0];
+            in[9] = f == 0 ? Jh[0] : Jh[2];
+            const T sg = f == 0 ? T(-1) : T(1);
+            visc_face_vjp(0, in, f == 0 ? gW : gC, f == 0 ? gC : gE, K.dxi, sg * lX / Kb.dxi, sg * lY / Kb.dxi, lin);
+            lu9[1][c0] += lin[0];
+            lw9[1][c0] += lin[1];
+            lu9[1][c1] += lin[2];
+            lw9[1][c1] += lin[3];
+            lcyu[c0] += lin[4];
+            lcyw[c0] += lin[5];
+            lcyu[c1] += lin[6];
+            lcyw[c1] += lin[7];
+            lJh[f == 0 ? 1 : 0] += lin[8];
+            lJh[f == 0 ? 0 : 2] += lin[9];
+        }
+        // y-face j - 1/2 (GX0, GY0) with -1/deta, y-face j + 1/2 with +1/deta
+        for (int f = 0; f < 2; f++) {
+            const int a0 = f, a1 = f + 1;
+            in[0] = u9[a0][1];
+            in[1] = w9[a0][1];
+            in[2] = u9[a1][1];
+            in[3] = w9[a1][1];
+            in[4] = cxu[a0];
+            in[5] = cxw[a0];
+            in[6] = cxu[a1];
+            in[7] = cxw[a1];
+            in[8] = f == 0 ? Jh[3] : Jh[0];
+            in[9] = f == 0 ? Jh[0] : Jh[4];
+            const T sg = f == 0 ? T(-1) : T(1);
+            visc_face_vjp(1, in, f == 0 ? gSo : gC, f == 0 ? gC : gN, K.deta, sg * lX / Kb.deta, sg * lY / Kb.deta,
+                          lin);
+            lu9[a0][1] += lin[0];
+            lw9[a0][1] += lin[1];
+            lu9[a1][1] += lin[2];
+            lw9[a1][1] += lin[3];
+            lcxu[a0] += lin[4];
+            lcxw[a0] += lin[5];
+            lcxu[a1] += lin[6];
+            lcxw[a1] += lin[7];
+            lJh[f == 0 ? 3 : 0] += lin[8];
+            lJh[f == 0 ? 0 : 4] += lin[9];
+        }
+        // central differences (up - dn) / (2 h)
+        for (int q = 0; q < 3; q++) {
+            const T ry = lcyu[q] / (T(2) * Kb.deta), rw = lcyw[q] / (T(2) * Kb.deta);
+            lu9[2][q] += ry;
+            lu9[0][q] -= ry;
+            lw9[2][q] += rw;
+            lw9[0][q] -= rw;
+            const T rx = lcxu[q] / (T(2) * Kb.dxi), rxw = lcxw[q] / (T(2) * Kb.dxi);
+            lu9[q][2] += rx;
+            lu9[q][0] -= rx;
+            lw9[q][2] += rxw;
+            lw9[q][0] -= rxw;
+        }
+        // desingularised velocities u = dsg(p^f_X, m^f), w = dsg(p^f_Y, m^f)
+        for (int a = 0; a < 3; a++)
+            for (int cc = 0; cc < 3; cc++) {
+                const T* bx = s.box[a][cc];
+                const TT dup = dsg(TT(bx[4], T(1)), TT(bx[3], T(0)), K.md);
+                const TT dum = dsg(TT(bx[4], T(0)), TT(bx[3], T(1)), K.md);
+                const TT dwp = dsg(TT(bx[5], T(1)), TT(bx[3], T(0)), K.md);
+                const TT dwm = dsg(TT(bx[5], T(0)), TT(bx[3], T(1)), K.md);
+                lam[box_slot(a, cc, 4)] += lu9[a][cc] * dup.d;
+                lam[box_slot(a, cc, 5)] += lw9[a][cc] * dwp.d;
+                lam[box_slot(a, cc, 3)] += lu9[a][cc] * dum.d + lw9[a][cc] * dwm.d;
+            }
+        // J_b h = m^s + m^f of C, W, E, S, N
+        const int ba[5] = {1, 1, 1, 0, 2}, bc[5] = {1, 0, 2, 1, 1};
+        for (int q = 0; q < 5; q++) {
+            lam[box_slot(ba[q], bc[q], 0)] += lJh[q];
+            lam[box_slot(ba[q], bc[q], 3)] += lJh[q];
+        }
+    }
+    for (int q = 0; q < 34; q++) out[q] = lam[q];
 }
 
 // Pass C: lam_in(k) = DU(k) + all face and source contributions that land on

@@ -12,7 +12,7 @@
 #include <limits>
 #include <vector>
 
-#include "../../include/m2p.h"
+#include "m2p.h"
 #include "m2p_host.h"
 #include "m2p_launch.h"
 

@@ -9,6 +9,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
+// Host-and-device so that the arithmetic can also be evaluated on the host
+// with other number types (operation counting).
+#define M2P_FN __host__ __device__ __forceinline__
+
 namespace m2p {
 
 constexpr int NF = 6;        // m^s, p^s_X, p^s_Y, m^f, p^f_X, p^f_Y
@@ -51,10 +57,14 @@ struct Geo {
 };
 
 // minmod(a, b): the argument of smaller magnitude when both have the same
-// strict sign, else 0 (written with selects so the compiler emits no branch)
+// strict sign, else 0 (written with selects so the compiler emits no branch).
+// That is exactly the median of (a, b, 0), one v_med3_f32 in FP32.
 template <typename T>
-__device__ __forceinline__ T minmod(T a, T b)
+M2P_FN T minmod(T a, T b)
 {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (std::is_same<T, float>::value) return __builtin_amdgcn_fmed3f(a, b, 0.0f);
+#endif
     const T lo = a < b ? a : b, hi = a > b ? a : b;
     const bool pos = (a > T(0)) & (b > T(0));
     const bool neg = (a < T(0)) & (b < T(0));
@@ -64,7 +74,7 @@ __device__ __forceinline__ T minmod(T a, T b)
 // Continuous desingularisation of num / den (Kurganov-Petrova 2007):
 // 2 den num / (den^2 + max(den^2, md^2)).
 template <typename T>
-__device__ __forceinline__ T dsg(T num, T den, T md)
+M2P_FN T dsg(T num, T den, T md)
 {
     T d2 = den * den;
     T m2 = md * md;
@@ -75,7 +85,7 @@ __device__ __forceinline__ T dsg(T num, T den, T md)
 // (1, 0, b_X), (0, 1, b_Y), unit normal (-b_X, -b_Y, 1)/s, J_b = s, c = n_Z,
 // A = inverse surface metric.
 template <typename T>
-__device__ __forceinline__ Geo<T> geometry(T bE, T bW, T bN, T bS, T two_dxi, T two_deta)
+M2P_FN Geo<T> geometry(T bE, T bW, T bN, T bS, T two_dxi, T two_deta)
 {
     Geo<T> g;
     T bX = (bE - bW) / two_dxi;
@@ -99,19 +109,65 @@ template <typename T>
 struct Consts {
     T eps, al, oma, md, eps_chi, tan_d, c_d, inv_n_r, theta_b;
     T dxi, deta, two_dxi, two_deta;
-    __device__ explicit Consts(const KParams& P)
+    // folded constants of the FP32 forms: eps (1 - alpha) / 2, eps / 2,
+    // (1 - alpha) / 2, -eps alpha, theta_b / (N_R eps)
+    T k_ps, k_pf, half_oma, m_eps_al, k_fr;
+    M2P_FN explicit Consts(const KParams& P)
         : eps(T(P.eps)), al(T(P.alpha)), oma(T(P.one_m_alpha)), md(T(P.md)), eps_chi(T(P.eps_chi)),
           tan_d(T(P.tan_d)), c_d(T(P.c_d)), inv_n_r(T(P.inv_n_r)), theta_b(T(P.theta_b)),
-          dxi(T(P.dxi)), deta(T(P.deta)), two_dxi(T(P.two_dxi)), two_deta(T(P.two_deta)) {}
+          dxi(T(P.dxi)), deta(T(P.deta)), two_dxi(T(P.two_dxi)), two_deta(T(P.two_deta)),
+          k_ps(T(P.eps * (1.0 - P.alpha) / 2.0)), k_pf(T(P.eps / 2.0)), half_oma(T((1.0 - P.alpha) / 2.0)),
+          m_eps_al(T(-P.eps * P.alpha)), k_fr(T(P.theta_b * P.inv_n_r / P.eps)) {}
 };
+
+// The FP32 build evaluates some formulas in algebraically folded forms with
+// fewer operations: J_b c = 1 (c = 1/J_b, R1), so h^s = m^s c and
+// eps J_b h A N^s = eps (1 - alpha)/2 h h^s A; products of constants are
+// folded.  The FP64 build (bitwise parity with the FP64 oracle) and the
+// dual-number adjoint evaluate the formulas as written.
+template <typename T>
+struct Folded : std::false_type {};
+template <>
+struct Folded<float> : std::true_type {};
 
 // Physical flux of one reconstructed side of a face (flux vectors F, G of
 // Appendix A with the owner cell's geometry), the conserved values entering
 // the numerical diffusion and the phase speeds |v_n| + sqrt(dP/dm).
 template <typename T>
-__device__ __forceinline__ void side_flux(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d,
+M2P_FN void side_flux(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d,
                                           T F[NF], T qv[NF], T a[2])
 {
+    if constexpr (Folded<T>::value) {
+        const T ms = u[0], mf = u[3];
+        const T hs = ms * g.c, hf = mf * g.c, h = hs + hf;
+        const T vXs = dsg(u[1], ms, K.md), vYs = dsg(u[2], ms, K.md);
+        const T vXf = dsg(u[4], mf, K.md), vYf = dsg(u[5], mf, K.md);
+        const T Ax = d == 0 ? g.A11 : g.A21;
+        const T Ay = d == 0 ? g.A12 : g.A22;
+        const T Ann = d == 0 ? g.A11 : g.A22;
+        const T vns = d == 0 ? vXs : vYs;
+        const T vnf = d == 0 ? vXf : vYf;
+        const T Ps = K.k_ps * h * hs;  // eps J_b h N^s / c
+        const T Pf = K.k_pf * h * h;   // eps J_b h pbar^f / c
+        qv[0] = ms;
+        qv[1] = ms * vXs;
+        qv[2] = ms * vYs;
+        qv[3] = mf;
+        qv[4] = mf * vXf;
+        qv[5] = mf * vYf;
+        F[0] = ms * vns;
+        F[1] = qv[1] * vns + Ps * Ax;
+        F[2] = qv[2] * vns + Ps * Ay;
+        F[3] = mf * vnf;
+        F[4] = qv[4] * vnf + Pf * Ax;
+        F[5] = qv[5] * vnf + Pf * Ay;
+        const T ac = K.eps * Ann * g.c;
+        const T cs = ac * K.half_oma * (h + hs);
+        const T cf = ac * h;
+        a[0] = fabs(vns) + sqrt(cs > T(0) ? cs : T(0));
+        a[1] = fabs(vnf) + sqrt(cf > T(0) ? cf : T(0));
+        return;
+    }
     T ms = u[0], mf = u[3];
     T hs = ms / g.J, hf = mf / g.J, h = hs + hf;
     T vXs = dsg(u[1], ms, K.md), vYs = dsg(u[2], ms, K.md);
@@ -143,8 +199,20 @@ __device__ __forceinline__ void side_flux(const Consts<T>& K, const T u[NF], con
 
 // Phase speeds only (identical arithmetic to side_flux).
 template <typename T>
-__device__ __forceinline__ void side_speed(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d, T a[2])
+M2P_FN void side_speed(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d, T a[2])
 {
+    if constexpr (Folded<T>::value) {
+        const T ms = u[0], mf = u[3];
+        const T hs = ms * g.c, hf = mf * g.c, h = hs + hf;
+        const T vns = d == 0 ? dsg(u[1], ms, K.md) : dsg(u[2], ms, K.md);
+        const T vnf = d == 0 ? dsg(u[4], mf, K.md) : dsg(u[5], mf, K.md);
+        const T ac = K.eps * (d == 0 ? g.A11 : g.A22) * g.c;
+        const T cs = ac * K.half_oma * (h + hs);
+        const T cf = ac * h;
+        a[0] = fabs(vns) + sqrt(cs > T(0) ? cs : T(0));
+        a[1] = fabs(vnf) + sqrt(cf > T(0) ? cf : T(0));
+        return;
+    }
     T ms = u[0], mf = u[3];
     T hs = ms / g.J, hf = mf / g.J, h = hs + hf;
     T vns = d == 0 ? dsg(u[1], ms, K.md) : dsg(u[2], ms, K.md);
@@ -158,7 +226,7 @@ __device__ __forceinline__ void side_speed(const Consts<T>& K, const T u[NF], co
 
 // Central (Kurganov-Tadmor) flux per phase: (F- + F+)/2 - a/2 (U+ - U-).
 template <typename T>
-__device__ __forceinline__ void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
+M2P_FN void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
                                              const T uR[NF], const Geo<T>& gR, int d, T H[NF])
 {
     T FL[NF], FR[NF], qL[NF], qR[NF], aL[2], aR[2];
@@ -175,7 +243,7 @@ __device__ __forceinline__ void central_flux(const Consts<T>& K, const T uL[NF],
 // Prescribed Mode-II face flux from the critical-depth inflow state
 // (q, m_in, v_in, phi); sgn = +1 on W/S (inward +X/+Y), -1 on E/N.
 template <typename T>
-__device__ __forceinline__ void inflow_flux(const Consts<T>& K, const Geo<T>& g, int d, int sgn, T q, T m_in,
+M2P_FN void inflow_flux(const Consts<T>& K, const Geo<T>& g, int d, int sgn, T q, T m_in,
                                             T v_in, T phi, T H[NF])
 {
     T h = m_in / g.J, hs = phi * m_in / g.J;
@@ -195,7 +263,7 @@ __device__ __forceinline__ void inflow_flux(const Consts<T>& K, const Geo<T>& g,
 // derivative as the mean of the two cells' central differences (cd*).
 // x-face: FX = 2 Jh (A11 u_x + A21 u_y), FY = Jh (A12 u_x + A22 u_y + A11 w_x + A21 w_y).
 template <typename T>
-__device__ __forceinline__ void visc_xface_c(T u0, T w0, T u1, T w1, T cdyu0, T cdyw0, T cdyu1, T cdyw1, T Jh0,
+M2P_FN void visc_xface_c(T u0, T w0, T u1, T w1, T cdyu0, T cdyw0, T cdyu1, T cdyw1, T Jh0,
                                              T Jh1, const Geo<T>& ga, const Geo<T>& gb, T dxi, T& FX, T& FY)
 {
     T dxu = (u1 - u0) / dxi, dxw = (w1 - w0) / dxi;
@@ -210,7 +278,7 @@ __device__ __forceinline__ void visc_xface_c(T u0, T w0, T u1, T w1, T cdyu0, T 
 
 // y-face: GX = Jh (A12 u_x + A22 u_y + A11 w_x + A21 w_y), GY = 2 Jh (A12 w_x + A22 w_y).
 template <typename T>
-__device__ __forceinline__ void visc_yface_c(T u0, T w0, T u1, T w1, T cdxu0, T cdxw0, T cdxu1, T cdxw1, T Jh0,
+M2P_FN void visc_yface_c(T u0, T w0, T u1, T w1, T cdxu0, T cdxw0, T cdxu1, T cdxw1, T Jh0,
                                              T Jh1, const Geo<T>& ga, const Geo<T>& gb, T deta, T& GX, T& GY)
 {
     T dyu = (u1 - u0) / deta, dyw = (w1 - w0) / deta;
@@ -225,14 +293,14 @@ __device__ __forceinline__ void visc_yface_c(T u0, T w0, T u1, T w1, T cdxu0, T 
 
 // central difference of a neighbour pair over 2 h
 template <typename T>
-__device__ __forceinline__ T cdiff(T up, T dn, T h)
+M2P_FN T cdiff(T up, T dn, T h)
 {
     return (up - dn) / (T(2) * h);
 }
 
 // J_b h pbar^f with pbar^f = c h / 2.
 template <typename T>
-__device__ __forceinline__ T fluid_G(T ms, T mf, const Geo<T>& g)
+M2P_FN T fluid_G(T ms, T mf, const Geo<T>& g)
 {
     T h = (ms + mf) / g.J;
     return g.J * h * (g.c * h / T(2));
@@ -250,9 +318,58 @@ struct Src {
 };
 
 template <typename T>
-__device__ __forceinline__ void sources(const Consts<T>& K, int flags, const T u[NF], const Geo<T>& g,
+M2P_FN void sources(const Consts<T>& K, int flags, const T u[NF], const Geo<T>& g,
                                         const T dn[6], T dGx, T dGy, Src<T>& S)
 {
+    if constexpr (Folded<T>::value) {
+        const T ms = u[0], mf = u[3];
+        const T hs = ms * g.c, hf = mf * g.c, h = hs + hf;
+        const T mt = ms + mf;
+        const T phis = dsg(ms, mt, K.md), phif = dsg(mf, mt, K.md);
+        T v[2][3];
+        v[0][0] = dsg(u[1], ms, K.md);
+        v[0][1] = dsg(u[2], ms, K.md);
+        v[1][0] = dsg(u[4], mf, K.md);
+        v[1][1] = dsg(u[5], mf, K.md);
+#pragma unroll
+        for (int ph = 0; ph < 2; ph++) v[ph][2] = g.bX * v[ph][0] + g.bY * v[ph][1];
+        T kap[2];
+#pragma unroll
+        for (int ph = 0; ph < 2; ph++) {
+            const T ka = v[ph][0] * dn[0] + v[ph][1] * dn[3];
+            const T kb = v[ph][0] * dn[1] + v[ph][1] * dn[4];
+            const T kc = v[ph][0] * dn[2] + v[ph][1] * dn[5];
+            kap[ph] = v[ph][0] * ka + v[ph][1] * kb + v[ph][2] * kc;
+        }
+        T pbs = hs * (g.c * K.oma - K.eps_chi * kap[0]);
+        T pbf = hf * (g.c - K.eps_chi * kap[1]);
+        if (pbs < T(0)) pbs = T(0);
+        if (pbf < T(0)) pbf = T(0);
+        // J_b p_b n (horizontal part) = -p_b (b_X, b_Y)
+        S.sn[0][0] = -pbs * g.bX;
+        S.sn[0][1] = -pbs * g.bY;
+        S.sn[1][0] = -pbf * g.bX;
+        S.sn[1][1] = -pbf * g.bY;
+        const T gx = g.A11 * dGx + g.A21 * dGy;
+        const T gy = g.A12 * dGx + g.A22 * dGy;
+        S.sf[0][0] = K.m_eps_al * phis * gx;
+        S.sf[0][1] = K.m_eps_al * phis * gy;
+        const T wf = (flags & 1) ? phif : phis;
+        S.sf[1][0] = K.eps * wf * gx;
+        S.sf[1][1] = K.eps * wf * gy;
+        const T Kd = K.c_d * g.J * phis * phif * h;
+        const T dvx = v[1][0] - v[0][0], dvy = v[1][1] - v[0][1];
+        S.sv[0][0] = K.al * Kd * dvx;
+        S.sv[0][1] = K.al * Kd * dvy;
+        S.sv[1][0] = -Kd * dvx;
+        S.sv[1][1] = -Kd * dvy;
+        const T fr = K.k_fr * g.J * phif * h;
+        S.sd[0] = -fr * v[1][0];
+        S.sd[1] = -fr * v[1][1];
+        S.kappa_s = kap[0];
+        S.phif = phif;
+        return;
+    }
     T ms = u[0], mf = u[3];
     T hs = ms / g.J, hf = mf / g.J, h = hs + hf;
     T mt = ms + mf;
@@ -305,7 +422,7 @@ __device__ __forceinline__ void sources(const Consts<T>& K, int flags, const T u
 // its sources (summation order: x-difference, y-difference, then s_n, s_f,
 // s_v, s_d^f, s_vis^f).
 template <typename T>
-__device__ __forceinline__ void tentative(const Consts<T>& K, const T u[NF], const T HXl[NF], const T HXr[NF],
+M2P_FN void tentative(const Consts<T>& K, const T u[NF], const T HXl[NF], const T HXr[NF],
                                           const T HYb[NF], const T HYt[NF], const Src<T>& S, T svx, T svy, T dt,
                                           T out[NF])
 {
@@ -334,12 +451,20 @@ __device__ __forceinline__ void tentative(const Consts<T>& K, const T u[NF], con
 // positivity: a phase with tentative thickness <= 0 loses its momentum.
 // Returns the number of positivity clamps (tentative thickness < 0).
 template <typename T>
-__device__ __forceinline__ int clamp_cell(const Consts<T>& K, const Geo<T>& g, T kappa_s, T dt, T tmu, T out[NF])
+M2P_FN int clamp_cell(const Consts<T>& K, const Geo<T>& g, T kappa_s, T dt, T tmu, T out[NF])
 {
-    T hst = out[0] / g.J;
-    T pbt = hst * (g.c * (T(1) - K.al) - K.eps_chi * kappa_s);
-    if (pbt < T(0)) pbt = T(0);
-    T F = dt * (g.J * pbt) * tmu;
+    T F;
+    if constexpr (Folded<T>::value) {
+        // J_b p_b = m^s (c (1 - alpha) - eps^chi kappa_s)
+        T jpb = out[0] * (g.c * K.oma - K.eps_chi * kappa_s);
+        if (jpb < T(0)) jpb = T(0);
+        F = dt * jpb * tmu;
+    } else {
+        T hst = out[0] / g.J;
+        T pbt = hst * (g.c * (T(1) - K.al) - K.eps_chi * kappa_s);
+        if (pbt < T(0)) pbt = T(0);
+        F = dt * (g.J * pbt) * tmu;
+    }
     T pX = out[1], pY = out[2];
     T pZ = g.bX * pX + g.bY * pY;
     T p3 = sqrt(pX * pX + pY * pY + pZ * pZ);
@@ -363,7 +488,7 @@ __device__ __forceinline__ int clamp_cell(const Consts<T>& K, const Geo<T>& g, T
 }
 
 template <typename T>
-__device__ __forceinline__ int update_cell(const Consts<T>& K, const T u[NF], const Geo<T>& g, const T HXl[NF],
+M2P_FN int update_cell(const Consts<T>& K, const T u[NF], const Geo<T>& g, const T HXl[NF],
                                            const T HXr[NF], const T HYb[NF], const T HYt[NF], const Src<T>& S,
                                            T svx, T svy, T dt, T tmu, T out[NF])
 {
@@ -373,7 +498,7 @@ __device__ __forceinline__ int update_cell(const Consts<T>& K, const T u[NF], co
 
 // Ghost-cell index map (transmissive: copy the edge cell; wall: mirror with
 // the normal momentum negated).
-__device__ __forceinline__ int map_index(int i, int n, int bc_lo, int bc_hi, int& flip)
+M2P_FN int map_index(int i, int n, int bc_lo, int bc_hi, int& flip)
 {
     if (i < 0) {
         if (bc_lo == 1) {

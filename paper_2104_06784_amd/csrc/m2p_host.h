@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/m2p.h"
+#include "m2p.h"
 #include "m2p_device.h"
 
 namespace m2p {

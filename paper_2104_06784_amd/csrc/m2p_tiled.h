@@ -73,17 +73,22 @@ __device__ __forceinline__ void visc_yface_rows(const RowD<T>& a, const RowD<T>&
     visc_yface_c(a.u, a.w, b.u, b.w, a.cdxu, a.cdxw, b.cdxu, b.cdxw, a.Jh, b.Jh, a.g, b.g, K.deta, GX, GY);
 }
 
-#ifndef M2P_TILED_WAVES_PER_EU
-#define M2P_TILED_WAVES_PER_EU 0
+// Occupancy hint of the FP32 single-scenario stage kernels (waves per SIMD
+// the register allocation must allow; 1 = no constraint).  FP32 stage 1 fits
+// three waves without spilling in its loop; stage 2 (which also carries U^n
+// and the CFL speeds), the FP64 kernels and the batched kernels keep the
+// compiler's choice.
+#ifndef M2P_TILED_WPE_S1
+#define M2P_TILED_WPE_S1 3
 #endif
-#ifndef M2P_TILED_UNROLL
-#define M2P_TILED_UNROLL 1
+#ifndef M2P_TILED_WPE_S2
+#define M2P_TILED_WPE_S2 1
 #endif
-#if M2P_TILED_WAVES_PER_EU > 0
-#define M2P_TILED_ATTR __attribute__((amdgpu_waves_per_eu(M2P_TILED_WAVES_PER_EU, M2P_TILED_WAVES_PER_EU)))
-#else
-#define M2P_TILED_ATTR
-#endif
+template <typename T, int STAGE>
+constexpr int tiled_wpe()
+{
+    return sizeof(T) == 4 ? (STAGE == 1 ? M2P_TILED_WPE_S1 : M2P_TILED_WPE_S2) : 1;
+}
 
 // One wavefront's share of a stage: strip `strip`, row block `rb` of one
 // scenario.  Partials go to wave slot `wslot` of that scenario.
@@ -166,23 +171,35 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
     T vGX = T(0), vGY = T(0);
     if (P.visc)
         visc_yface_rows(Dm, D0, K, vGX, vGY);
-    T Uc[NF], Un1[NF], U2[NF];  // rows j, j+1, j+2
+    T Ua[NF], Ub[NF], Uc_[NF], Ud[NF];  // U rows, slot (row - r0) mod 4
+    RowD<T> Da, Db, Dc, Dd;            // row quantities, same slot rule
+    T sya[NF], syb[NF], Hya[NF], Hyb[NF];
+    T vGXa = vGX, vGYa = vGY, vGXb = T(0), vGYb = T(0);
 #pragma unroll
     for (int k = 0; k < NF; k++) {
-        Uc[k] = U0[k];
-        Un1[k] = U1[k];
+        Ua[k] = U0[k];
+        Ub[k] = U1[k];
+        sya[k] = sy0[k];
+        Hya[k] = Hy[k];
     }
-    loadU(r0 + 2, U2);
-    T bj = b0, bj1 = b1, bj2 = loadB(r0 + 2);
+    Da = D0;
+    Dd = Dm;
+    loadU(r0 + 2, Uc_);
+    T ba = b0, bb = b1, bc = loadB(r0 + 2), bd = T(0);
 
-#pragma unroll M2P_TILED_UNROLL
-    for (int j = r0; j < r1; j++) {
+    // One row j.  Uc, Un1, U2: rows j..j+2; U3, bj3 receive row j+3.  Dm, D0:
+    // rows j-1, j; D1 receives row j+1.  sy0, Hy, vGX/vGY: y-slopes of row j,
+    // flux and viscous flux of face j-1/2; sy1, HyN, vGXN/vGYN receive those
+    // of row j+1 / face j+1/2.  The march calls it with the slots rotated, so
+    // the window never moves through registers.
+    auto row = [&](int j, T* Uc, T* Un1, T* U2, T* U3, T bj, T bj1, T bj2, T& bj3, RowD<T>& Dm, RowD<T>& D0,
+                   RowD<T>& D1, T* sy0, T* sy1, T* Hy, T* HyN, T vGX, T vGY, T& vGXN, T& vGYN)
+                   __attribute__((always_inline)) {
         // ---- prefetch row j+3 (consumed next iteration) and this row's own
         // values needed at the end (U^n for the Heun average, tan delta)
-        T U3[NF];
         const int rn = j + 3 <= P.ny + 1 ? j + 3 : P.ny + 1;
         loadU(rn, U3);
-        const T bj3 = loadB(rn);
+        bj3 = loadB(rn);
         const size_t cself = (size_t)j * P.pitch + (out_lane ? col : 0);
         T unr[NF];
         if (STAGE == 2) {
@@ -190,7 +207,6 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
             for (int k = 0; k < NF; k++) unr[k] = Un[k * fs + cself];
         }
         const T tmu = P.has_mu ? mu[cself] : K.tan_d;
-        RowD<T> D1;
         make_row(K, Un1, bj1, bj, bj2, D1);
         T uL[NF], uR[NF];
 #pragma unroll
@@ -200,7 +216,6 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
             uR[k] = Un1[k] - T(0.5) * sy1[k];
         }
         // ---- y-face j + 1/2
-        T HyN[NF];
         central_flux(K, uL, D0.g, uR, D1.g, 1, HyN);
         if (j == P.ny - 1 && out_lane) {
             const int s = inflow_seg_at(P, 3, col);
@@ -211,7 +226,8 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
                 ob[7] += (double)HyN[3] * P.dxi;
             }
         }
-        T vGXN = T(0), vGYN = T(0);
+        vGXN = T(0);
+        vGYN = T(0);
         if (P.visc) visc_yface_rows(D0, D1, K, vGXN, vGYN);
 
         // ---- x-faces of row j: this lane computes face i + 1/2
@@ -318,22 +334,17 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
                 Uout[k * fs + cself] = out[k];
             }
         }
-        // ---- roll the window
-#pragma unroll
-        for (int k = 0; k < NF; k++) {
-            Hy[k] = HyN[k];
-            sy0[k] = sy1[k];
-            Uc[k] = Un1[k];
-            Un1[k] = U2[k];
-            U2[k] = U3[k];
-        }
-        vGX = vGXN;
-        vGY = vGYN;
-        Dm = D0;
-        D0 = D1;
-        bj = bj1;
-        bj1 = bj2;
-        bj2 = bj3;
+    };
+
+    // rows r0 .. r1-1, four per trip with the slots rotated
+    for (int j = r0; j < r1; j += 4) {
+        row(j, Ua, Ub, Uc_, Ud, ba, bb, bc, bd, Dd, Da, Db, sya, syb, Hya, Hyb, vGXa, vGYa, vGXb, vGYb);
+        if (j + 1 >= r1) break;
+        row(j + 1, Ub, Uc_, Ud, Ua, bb, bc, bd, ba, Da, Db, Dc, syb, sya, Hyb, Hya, vGXb, vGYb, vGXa, vGYa);
+        if (j + 2 >= r1) break;
+        row(j + 2, Uc_, Ud, Ua, Ub, bc, bd, ba, bb, Db, Dc, Dd, sya, syb, Hya, Hyb, vGXa, vGYa, vGXb, vGYb);
+        if (j + 3 >= r1) break;
+        row(j + 3, Ud, Ua, Ub, Uc_, bd, ba, bb, bc, Dc, Dd, Da, syb, sya, Hyb, Hya, vGXb, vGYb, vGXa, vGYa);
     }
 
     // ---- wavefront reductions (fixed butterfly => deterministic in lane 0)
@@ -373,13 +384,10 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
 }
 
 template <typename T, int STAGE>
-__global__ void __launch_bounds__(256) M2P_TILED_ATTR k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un,
-                                                                    T* Uout, const T* __restrict__ b,
-                                                                    const T* __restrict__ mu,
-                                                                    DevScalars* __restrict__ S,
-                                                                    double* __restrict__ bpart,
-                                                                    double* __restrict__ wpart, int nmax, int R,
-                                                                    int nstrips, int nrb)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_wpe<T, STAGE>())))
+k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout, const T* __restrict__ b,
+              const T* __restrict__ mu, DevScalars* __restrict__ S, double* __restrict__ bpart,
+              double* __restrict__ wpart, int nmax, int R, int nstrips, int nrb)
 {
     // XCD-aware block order: consecutive block ids land on different XCDs, so
     // give each XCD a contiguous range of waves (neighbouring strips share halo
@@ -401,8 +409,8 @@ __global__ void __launch_bounds__(256) M2P_TILED_ATTR k_stage_tiled(KParams P, c
 // (scenario, strip, row block) with a grid stride; every scenario keeps its
 // own time step and partial slots, so results equal single-scenario runs.
 template <typename T, int STAGE>
-__global__ void __launch_bounds__(256) M2P_TILED_ATTR k_stage_batch(const ScenDesc<T>* __restrict__ scen,
-                                                                    const int* __restrict__ work, int nwork, int R)
+__global__ void __launch_bounds__(256)
+k_stage_batch(const ScenDesc<T>* __restrict__ scen, const int* __restrict__ work, int nwork, int R)
 {
     const int nblk = gridDim.x;
     int bid = blockIdx.x;

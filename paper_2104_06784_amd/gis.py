@@ -1,0 +1,39 @@
+"""ESRI ASCII grid input and output through the library (``m2p_esri_*``).
+
+DEMs and initial fields come from GIS systems as ASCII grids and results go
+back in that form (the paper's Sect. 1 and Sect. 3.1.2, Stages 1 and 3).
+Arrays are [ny, nx] float64 with row 0 at the southern edge, as everywhere
+in this package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+from . import _abi as A
+
+
+def read_esri_ascii(path: str):
+    """Return (values [ny, nx], info) with info = {dx, x0, y0, nodata}; x0, y0
+    is the lower-left cell corner, nodata is NaN when the file has none."""
+    L = A.lib()
+    g = A.Grid()
+    x0, y0, nd = C.c_double(), C.c_double(), C.c_double()
+    p = os.fsencode(path)
+    A.check(L.m2p_esri_read(p, C.byref(g), C.byref(x0), C.byref(y0), C.byref(nd), None, 0), "m2p_esri_read")
+    out = np.empty((g.ny, g.nx), dtype=np.float64)
+    A.check(L.m2p_esri_read(p, C.byref(g), None, None, None, A.dptr(out), out.size), "m2p_esri_read")
+    return out, {"dx": g.dx, "x0": x0.value, "y0": y0.value, "nodata": nd.value}
+
+
+def write_esri_ascii(path: str, values, dx: float, x0: float = 0.0, y0: float = 0.0, nodata: float = -9999.0):
+    """Write [ny, nx] values (row 0 south); non-finite values become nodata."""
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    if v.ndim != 2 or not math.isfinite(nodata):
+        raise ValueError("values must be [ny, nx] and nodata finite")
+    g = A.Grid(v.shape[1], v.shape[0], float(dx), float(dx))
+    A.check(A.lib().m2p_esri_write(os.fsencode(path), C.byref(g), float(x0), float(y0), float(nodata), A.dptr(v)),
+            "m2p_esri_write")

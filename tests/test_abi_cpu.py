@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_strerror():
     L = A.lib()
     assert b"gfx950" in L.m2p_version()
-    for code in range(0, -9, -1):
+    for code in range(0, -10, -1):
         assert L.m2p_strerror(code)
     assert L.m2p_strerror(-99) == b"unknown status"
 
@@ -98,3 +98,36 @@ def test_no_device_means_no_context():
         pytest.skip("a GPU is visible")
     rc, h = _create(A.Grid(8, 8, 10.0, 10.0), make_params(I.Params()))
     assert rc == A.M2P_EHIP and not h.value
+
+
+def _flops(stage, visc):
+    out = (C.c_double * 5)()
+    assert A.lib().m2p_stage_flops(stage, visc, out) == 0
+    return np.array(list(out))
+
+
+def test_stage_flop_count():
+    """The per-cell operation tally of the stage arithmetic (used for the ALU
+    roofline; the formulas in the folded forms of the FP32 kernels) against
+    counts derived by hand from the formulas.
+
+    Viscous term on minus off: two face fluxes (13 add, 16 mul, 2 div each),
+    two y central differences (1 add, 1 mul, 1 div each), the two divergences
+    (3 add, 2 div each) and two prefactors (3 mul each): 34 add, 40 mul,
+    10 div.  Stage 2 minus stage 1: the Heun average (6 add, 6 mul) and two
+    speed evaluations (thicknesses 2 mul 1 add; two desingularised velocities
+    1 add 4 mul 1 div 1 cmp each; eps A_nn c 2 mul; the two squared speeds
+    3 mul 1 add; |v| + sqrt(max(., 0)) twice: 2 add 2 sqrt 2 cmp), each with
+    its maximum over the phases and the running maximum (2 cmp):
+    18 add, 36 mul, 4 div, 4 sqrt, 12 cmp."""
+    f10, f11, f20, f21 = _flops(1, 0), _flops(1, 1), _flops(2, 0), _flops(2, 1)
+    assert np.array_equal(f11 - f10, [34, 40, 10, 0, 0])
+    assert np.array_equal(f21 - f20, [34, 40, 10, 0, 0])
+    assert np.array_equal(f20 - f10, [18, 36, 4, 4, 12])
+    # square roots: 4 face sides x 2 phase speeds, the new row's geometry, the
+    # norm of the solid momentum in the Coulomb clamp
+    assert f10[3] == 10
+    assert 600 <= f10[:4].sum() <= 1200
+    out = (C.c_double * 5)()
+    assert A.lib().m2p_stage_flops(3, 0, out) == A.M2P_EINVAL
+    assert A.lib().m2p_stage_flops(1, 0, None) == A.M2P_EINVAL

@@ -186,3 +186,43 @@ def test_adjoint_fp32_close_to_fp64_and_reproducible():
     _say(f"[adj] fp32 vs fp64: cosine {cos:.6f}, rel L2 {rel:.3e}, vol {a[2]:.6e} vs {res['f64'][0][2]:.6e}")
     assert cos >= 0.999 and rel <= 1e-2
     assert abs(a[2] - res["f64"][0][2]) <= 1e-2 * abs(res["f64"][0][2])
+
+
+def test_autograd_function_matches_adjoint_and_descends():
+    """DepositLoss (torch.autograd.Function over the adjoint) returns the
+    library's gradient, and a few projected gradient steps on (mu, s) lower
+    the deposit misfit towards the hidden parameters."""
+    import dataclasses
+
+    import torch
+
+    import oracle
+    from paper_2104_06784_amd.calibrate import DepositLoss
+    from paper_2104_06784_amd.sim import Sim
+    prob, mu_true = _calibration_case()
+    nsteps = 60
+    ot = oracle.OracleSim(dataclasses.replace(prob, tan_mu=mu_true, h_vert=prob.h_vert * 1.2))
+    ot.run(nsteps)
+    target = ot.fields()["h"]
+    f = DepositLoss(prob, target, nsteps, ckpt_every=16, precision="f64")
+    mu = torch.tensor(prob.tan_mu, dtype=torch.float64, requires_grad=True)
+    s = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    loss = f(mu, s)
+    loss.backward()
+    g = Sim(prob, precision="f64")
+    l2, gmu2, gv2 = g.adjoint_run(nsteps, 16, target, 1.0)
+    assert loss.item() == l2 and np.array_equal(mu.grad.numpy(), gmu2) and s.grad.item() == gv2
+    with torch.no_grad():
+        assert float(f(mu, s)) == l2  # forward-only path, same loss
+    hist = [loss.item()]
+    for it in range(4):
+        with torch.no_grad():
+            mu -= 0.02 * mu.grad / mu.grad.abs().max()
+            s -= 0.05 * torch.sign(s.grad)
+        mu.grad = None
+        s.grad = None
+        loss = f(mu, s)
+        loss.backward()
+        hist.append(loss.item())
+    _say(f"[adj] calibration losses {['%.4e' % x for x in hist]}, s {float(s):.3f}")
+    assert all(b < a for a, b in zip(hist, hist[1:]))
