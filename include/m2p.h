@@ -105,6 +105,21 @@ typedef struct {
     const double *t, *Q, *phi_s;
 } m2p_inflow;
 
+/* Mode-II inflow segment given as the state of the inflowing flow (the
+ * paper's inflow condition: hydrographs of flow thickness, solid fraction and
+ * velocity at boundary locations, Sect. 3.1.2 Stage 0): ncells boundary cells
+ * from i0 on side; piecewise-linear hydrographs over time t (s, increasing,
+ * nt >= 1 samples) of the vertical flow thickness h (m, >= 0), the solid
+ * fraction phi_s and the speed v (m/s) of both phases along the inward
+ * boundary normal.  The two ghost cells outside each segment cell hold this
+ * state at the stage time and the boundary face flux is the scheme's central
+ * flux; the flow through these faces enters the out_s / out_f integrals of
+ * m2p_diag (negative for inflow). */
+typedef struct {
+    int32_t side, i0, ncells, nt;
+    const double *t, *h, *phi_s, *v;
+} m2p_inflow_state;
+
 typedef struct {
     double t;            /* model time (s) */
     double dt_last;      /* last step (s) */
@@ -166,6 +181,11 @@ int m2p_set_time(m2p_ctx *c, double t);
 
 /* Mode-II inflow segments (replaces earlier ones); at most 8; arrays copied. */
 int m2p_set_inflow(m2p_ctx *c, const m2p_inflow *seg, int32_t nseg);
+
+/* Replace the Mode-II state segments (m2p_inflow_state; 0..8; nseg = 0
+ * clears).  Segments may not share a boundary cell with each other or with a
+ * discharge segment.  Errors: M2P_EINVAL. */
+int m2p_set_inflow_states(m2p_ctx *c, const m2p_inflow_state *seg, int32_t nseg);
 
 /* Select the stage-kernel variant (M2P_VARIANT_*); results are identical in
  * FP64.  Tile rows per workgroup for the tiled variant (0 = default). */

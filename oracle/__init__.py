@@ -39,6 +39,12 @@ class _Params(C.Structure):
                 ("bc", C.c_int32 * 4), ("flags", C.c_int32)]
 
 
+class _InflowState(C.Structure):
+    _fields_ = [("side", C.c_int32), ("i0", C.c_int32), ("ncells", C.c_int32), ("nt", C.c_int32),
+                ("t", C.POINTER(C.c_double)), ("h", C.POINTER(C.c_double)),
+                ("phi", C.POINTER(C.c_double)), ("v", C.POINTER(C.c_double))]
+
+
 class _Inflow(C.Structure):
     _fields_ = [("side", C.c_int32), ("i0", C.c_int32), ("ncells", C.c_int32), ("nt", C.c_int32),
                 ("t", C.POINTER(C.c_double)), ("Q", C.POINTER(C.c_double)),
@@ -66,6 +72,8 @@ def _load():
         lib.ora_set_time.argtypes = [P, C.c_double]
         lib.ora_set_inflow.restype = C.c_int
         lib.ora_set_inflow.argtypes = [P, C.POINTER(_Inflow), C.c_int]
+        lib.ora_set_inflow_states.restype = C.c_int
+        lib.ora_set_inflow_states.argtypes = [P, C.POINTER(_InflowState), C.c_int]
         lib.ora_step.restype = C.c_double
         lib.ora_step.argtypes = [P, C.c_double]
         lib.ora_run.restype = C.c_int64
@@ -112,6 +120,8 @@ class OracleSim:
         self.set_state_si(prob.h_vert, prob.phi_s, vertical=True, vel=prob.vel)
         if prob.inflows:
             self.set_inflow(prob.inflows)
+        if prob.inflow_states:
+            self.set_inflow_states(prob.inflow_states)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -137,6 +147,15 @@ class OracleSim:
             arr[k] = _Inflow(s.side, s.i0, s.ncells, len(t), _ptr(t), _ptr(Q), _ptr(ph))
         if _load().ora_set_inflow(self._h, arr, len(inflows)) != 0:
             raise ValueError("invalid inflow")
+
+    def set_inflow_states(self, segs):
+        arr = (_InflowState * max(len(segs), 1))()
+        for k, s in enumerate(segs):
+            a = [np.ascontiguousarray(x, dtype=np.float64) for x in (s.t, s.h, s.phi_s, s.v)]
+            self._keep += a
+            arr[k] = _InflowState(s.side, s.i0, s.ncells, len(a[0]), *[_ptr(x) for x in a])
+        if _load().ora_set_inflow_states(self._h, arr, len(segs)) != 0:
+            raise ValueError("invalid inflow state segment")
 
     def state(self) -> np.ndarray:
         U = np.empty((6, self.ny, self.nx), dtype=np.float64)

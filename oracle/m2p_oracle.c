@@ -51,6 +51,18 @@ typedef struct {
     double *t, *Q, *phi;
 } inflow_seg;
 
+/* Mode-II segment given as the state of the inflowing flow (hydrographs of
+ * vertical thickness h in m, solid fraction, inward speed v in m/s). */
+typedef struct {
+    int32_t side, i0, ncells, nt;
+    const double *t, *h, *phi, *v;
+} ora_state_in;
+
+typedef struct {
+    int side, i0, ncells, nt;
+    double *t, *h, *phi, *v;
+} state_seg;
+
 /* Geometry of the basal surface at one cell (Appendix A, O_xi-eta-zeta frame). */
 typedef struct {
     double bX, bY;          /* DEM slopes */
@@ -75,6 +87,8 @@ typedef struct {
     double *Us, *Uss;
     inflow_seg *seg;
     int nseg;
+    state_seg *sseg;
+    int nsseg;
     double t;
     int64_t steps, clamps;
     double in_s, in_f, out_s, out_f;
@@ -232,6 +246,8 @@ void ora_destroy(ora_sim *o)
     free(o->dnx); free(o->dny); free(o->HX); free(o->HY); free(o->tan_mu); free(o->dt_sched);
     for (int k = 0; k < o->nseg; k++) { free(o->seg[k].t); free(o->seg[k].Q); free(o->seg[k].phi); }
     free(o->seg);
+    for (int k = 0; k < o->nsseg; k++) { free(o->sseg[k].t); free(o->sseg[k].h); free(o->sseg[k].phi); free(o->sseg[k].v); }
+    free(o->sseg);
     free(o);
 }
 
@@ -282,6 +298,37 @@ int ora_set_inflow(ora_sim *o, const ora_inflow_in *in, int n)
     return 0;
 }
 
+/* Replace the state-inflow segments.  Segments must lie on their side and
+ * must not share a boundary cell with a flux-inflow segment or each other. */
+int ora_set_inflow_states(ora_sim *o, const ora_state_in *in, int n)
+{
+    for (int k = 0; k < o->nsseg; k++) { free(o->sseg[k].t); free(o->sseg[k].h); free(o->sseg[k].phi); free(o->sseg[k].v); }
+    free(o->sseg);
+    o->sseg = (state_seg *)xcalloc((size_t)n, sizeof(state_seg));
+    o->nsseg = n;
+    for (int k = 0; k < n; k++) {
+        state_seg *s = &o->sseg[k];
+        s->side = in[k].side; s->i0 = in[k].i0; s->ncells = in[k].ncells; s->nt = in[k].nt;
+        int len = (s->side < 2) ? o->ny : o->nx;
+        if (s->side < 0 || s->side > 3 || s->nt < 1 || s->ncells < 1 || s->i0 < 0 || s->i0 + s->ncells > len) return -1;
+        for (int q = 0; q < o->nseg; q++)
+            if (o->seg[q].side == s->side && s->i0 < o->seg[q].i0 + o->seg[q].ncells && o->seg[q].i0 < s->i0 + s->ncells)
+                return -1;
+        for (int q = 0; q < k; q++)
+            if (o->sseg[q].side == s->side && s->i0 < o->sseg[q].i0 + o->sseg[q].ncells && o->sseg[q].i0 < s->i0 + s->ncells)
+                return -1;
+        s->t = (double *)xcalloc((size_t)s->nt, sizeof(double));
+        s->h = (double *)xcalloc((size_t)s->nt, sizeof(double));
+        s->phi = (double *)xcalloc((size_t)s->nt, sizeof(double));
+        s->v = (double *)xcalloc((size_t)s->nt, sizeof(double));
+        memcpy(s->t, in[k].t, (size_t)s->nt * sizeof(double));
+        memcpy(s->h, in[k].h, (size_t)s->nt * sizeof(double));
+        memcpy(s->phi, in[k].phi, (size_t)s->nt * sizeof(double));
+        memcpy(s->v, in[k].v, (size_t)s->nt * sizeof(double));
+    }
+    return 0;
+}
+
 /* ---------------------------------------------------------- boundaries */
 
 /* Index map for a ghost cell.  Transmissive (the paper's non-reflecting
@@ -300,7 +347,34 @@ static int map_index(int i, int n, int bc_lo, int bc_hi, int *flip)
     return i;
 }
 
-static void extend_state(ora_sim *o, const double *U)
+static double interp(const double *t, const double *y, int n, double tau);
+
+/* reading (literal Mode-II, Sect. 3.1.2 Stage 0): the ghost cells outside a
+ * state-inflow segment hold the inflowing flow given by the hydrographs at the
+ * stage time: vertical thickness h (m = h / H), solid fraction phi, both
+ * phases moving along the inward boundary normal with speed v; the boundary
+ * face flux is then the scheme's own central flux. */
+static void ghost_state(const ora_sim *o, const state_seg *s, double tau_nd, double u[NF], double *m_out,
+                        double *v_out)
+{
+    double tau = tau_nd * o->T;
+    double m = interp(s->t, s->h, s->nt, tau) / o->p.H;
+    double ph = interp(s->t, s->phi, s->nt, tau);
+    double v = interp(s->t, s->v, s->nt, tau) / o->V;
+    if (m_out) *m_out = m;
+    if (v_out) *v_out = v;
+    double ex = s->side == 0 ? 1.0 : (s->side == 1 ? -1.0 : 0.0);
+    double ey = s->side == 2 ? 1.0 : (s->side == 3 ? -1.0 : 0.0);
+    double ms = ph * m, mf = (1.0 - ph) * m;
+    u[0] = ms;
+    u[1] = ms * v * ex;
+    u[2] = ms * v * ey;
+    u[3] = mf;
+    u[4] = mf * v * ex;
+    u[5] = mf * v * ey;
+}
+
+static void extend_state(ora_sim *o, const double *U, double tau)
 {
     size_t nc = (size_t)o->nx * o->ny;
     for (int j = -HALO; j < o->ny + HALO; j++)
@@ -317,6 +391,18 @@ static void extend_state(ora_sim *o, const double *U)
                 o->Ue[k * np + q] = v;
             }
         }
+    size_t np = (size_t)o->px * o->py;
+    for (int sg = 0; sg < o->nsseg; sg++) {
+        const state_seg *s = &o->sseg[sg];
+        double u[NF];
+        ghost_state(o, s, tau, u, NULL, NULL);
+        for (int k = s->i0; k < s->i0 + s->ncells; k++)
+            for (int l = 1; l <= HALO; l++) {
+                int i = s->side == 0 ? -l : (s->side == 1 ? o->nx - 1 + l : k);
+                int j = s->side == 2 ? -l : (s->side == 3 ? o->ny - 1 + l : k);
+                for (int f = 0; f < NF; f++) o->Ue[f * np + PIDX(o, i, j)] = u[f];
+            }
+    }
 }
 
 /* ------------------------------------------------------- inflow (Mode II) */
@@ -691,7 +777,7 @@ static void stage(ora_sim *o, const double *Uin, double *Uout, double dt, double
     int nx = o->nx, ny = o->ny;
     size_t nc = (size_t)nx * ny, nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1);
     size_t np = (size_t)o->px * o->py;
-    extend_state(o, Uin);
+    extend_state(o, Uin, tau);
     compute_fluxes(o, tau);
     boundary_outflow(o, o->bflux[st]);
     int64_t clamps = 0;
@@ -781,6 +867,14 @@ static void max_speeds(const ora_sim *o, double amax[2])
         inflow_state(o, &o->seg[s], o->t, &q, &m_in, &v_in, &phi);
         double a = v_in + sqrt(o->eps * m_in);
         if (o->seg[s].side < 2) { if (a > ax) ax = a; }
+        else if (a > ay) ay = a;
+    }
+    /* reading: a state-inflow ghost moves at most |v| + sqrt(eps m) */
+    for (int s = 0; s < o->nsseg; s++) {
+        double u[NF], m, v;
+        ghost_state(o, &o->sseg[s], o->t, u, &m, &v);
+        double a = fabs(v) + sqrt(o->eps * m);
+        if (o->sseg[s].side < 2) { if (a > ax) ax = a; }
         else if (a > ay) ay = a;
     }
     double fl = o->p.a_min / o->V;
@@ -896,7 +990,7 @@ void ora_get_fields(const ora_sim *o, double *h, double *phi_s, double *vxs, dou
  * out[18..33]: s_n, s_f, s_v (solid X,Y then fluid X,Y each), s_d^f, s_vis^f. */
 void ora_probe(ora_sim *o, int i, int j, double out[34])
 {
-    extend_state(o, o->U);
+    extend_state(o, o->U, o->t);
     const geo_t *g = &o->G[PIDX(o, i, j)];
     size_t c = CIDX(o, i, j);
     out[0] = g->bX; out[1] = g->bY; out[2] = g->J; out[3] = g->c;

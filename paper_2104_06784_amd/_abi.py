@@ -50,6 +50,12 @@ class Inflow(C.Structure):
                 ("t", C.POINTER(C.c_double)), ("Q", C.POINTER(C.c_double)), ("phi_s", C.POINTER(C.c_double))]
 
 
+class InflowState(C.Structure):
+    _fields_ = [("side", C.c_int32), ("i0", C.c_int32), ("ncells", C.c_int32), ("nt", C.c_int32),
+                ("t", C.POINTER(C.c_double)), ("h", C.POINTER(C.c_double)), ("phi_s", C.POINTER(C.c_double)),
+                ("v", C.POINTER(C.c_double))]
+
+
 class Diag(C.Structure):
     _fields_ = [("t", C.c_double), ("dt_last", C.c_double), ("dt_next", C.c_double),
                 ("mass_s", C.c_double), ("mass_f", C.c_double), ("in_s", C.c_double), ("in_f", C.c_double),
@@ -81,6 +87,7 @@ SIGNATURES = {
     "m2p_get_state_raw": (C.c_int, [_P, _dp]),
     "m2p_set_time": (C.c_int, [_P, C.c_double]),
     "m2p_set_inflow": (C.c_int, [_P, C.POINTER(Inflow), C.c_int32]),
+    "m2p_set_inflow_states": (C.c_int, [_P, C.POINTER(InflowState), C.c_int32]),
     "m2p_set_variant": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "m2p_step": (C.c_int, [_P, _dp]),
     "m2p_run": (C.c_int, [_P, C.c_int64]),

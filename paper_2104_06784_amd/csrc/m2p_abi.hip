@@ -61,6 +61,7 @@ struct m2p_ctx {
     DevScalars* S = nullptr;
     double* bpart = nullptr;
     double* tables = nullptr;
+    std::vector<double> tab_flux, tab_state;  // host copies of the two kinds of Mode-II hydrograph tables
     double* mass_part = nullptr;
     double* staging = nullptr;  // FP64 field staging [7][ny][nx]
     double t_end = std::numeric_limits<double>::infinity();
@@ -559,42 +560,104 @@ int m2p_set_time(m2p_ctx* c, double t)
     return M2P_OK;
 }
 
-int m2p_set_inflow(m2p_ctx* c, const m2p_inflow* seg, int32_t nseg)
+// Device table of both kinds of hydrographs: discharge segments first, then
+// state segments (their offsets are shifted past the discharge tables).
+static int upload_tables(m2p_ctx* c)
 {
-    if (!c || (nseg > 0 && !seg)) return fail(M2P_EINVAL, "NULL argument");
-    if (nseg < 0 || nseg > MAX_SEG) return fail(M2P_EINVAL, "0..8 inflow segments supported");
-    std::vector<double> tab;
+    std::vector<double> tab(c->tab_flux);
+    const int shift = (int)tab.size();
+    tab.insert(tab.end(), c->tab_state.begin(), c->tab_state.end());
     KParams& K = c->kp;
-    for (int s = 0; s < nseg; s++) {
-        const m2p_inflow& q = seg[s];
-        int len = q.side < 2 ? c->g.ny : c->g.nx;
-        if (q.side < 0 || q.side > 3 || q.ncells < 1 || q.i0 < 0 || q.i0 + q.ncells > len || q.nt < 1 || !q.t ||
-            !q.Q || !q.phi_s)
-            return fail(M2P_EINVAL, "bad inflow segment");
-        for (int k = 0; k < q.nt; k++) {
-            if (!std::isfinite(q.t[k]) || !(q.Q[k] >= 0.0) || !(q.phi_s[k] >= 0.0 && q.phi_s[k] <= 1.0))
-                return fail(M2P_EINVAL, "bad hydrograph sample");
-            if (k > 0 && !(q.t[k] > q.t[k - 1])) return fail(M2P_EINVAL, "hydrograph times must increase");
-        }
-        K.seg[s].side = q.side;
-        K.seg[s].i0 = q.i0;
-        K.seg[s].ncells = q.ncells;
-        K.seg[s].nt = q.nt;
-        K.seg[s].toff = (int)tab.size();
-        tab.insert(tab.end(), q.t, q.t + q.nt);
-        tab.insert(tab.end(), q.Q, q.Q + q.nt);
-        tab.insert(tab.end(), q.phi_s, q.phi_s + q.nt);
-    }
-    K.nseg = nseg;
+    for (int s = 0; s < K.nsseg; s++) K.sseg[s].toff += shift;
     HIPCHK(hipStreamSynchronize(c->stream));
     if (c->tables) (void)hipFree(c->tables);
     c->tables = nullptr;
     size_t nb = std::max<size_t>(tab.size(), 8) * sizeof(double);
     if (hipMalloc(&c->tables, nb) != hipSuccess) return fail(M2P_ENOMEM, "table allocation failed");
     if (!tab.empty()) HIPCHK(hipMemcpy(c->tables, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+    for (int s = 0; s < K.nsseg; s++) K.sseg[s].toff -= shift;
     c->B.tables = c->tables;
     c->dirty = true;
     return M2P_OK;
+}
+
+static bool overlaps(const SegDesc* a, int na, int side, int i0, int n)
+{
+    for (int q = 0; q < na; q++)
+        if (a[q].side == side && i0 < a[q].i0 + a[q].ncells && a[q].i0 < i0 + n) return true;
+    return false;
+}
+
+int m2p_set_inflow(m2p_ctx* c, const m2p_inflow* seg, int32_t nseg)
+{
+    if (!c || (nseg > 0 && !seg)) return fail(M2P_EINVAL, "NULL argument");
+    if (nseg < 0 || nseg > MAX_SEG) return fail(M2P_EINVAL, "0..8 inflow segments supported");
+    std::vector<double> tab;
+    SegDesc sd[MAX_SEG];
+    for (int s = 0; s < nseg; s++) {
+        const m2p_inflow& q = seg[s];
+        int len = q.side < 2 ? c->g.ny : c->g.nx;
+        if (q.side < 0 || q.side > 3 || q.ncells < 1 || q.i0 < 0 || q.i0 + q.ncells > len || q.nt < 1 || !q.t ||
+            !q.Q || !q.phi_s)
+            return fail(M2P_EINVAL, "bad inflow segment");
+        if (overlaps(sd, s, q.side, q.i0, q.ncells) || overlaps(c->kp.sseg, c->kp.nsseg, q.side, q.i0, q.ncells))
+            return fail(M2P_EINVAL, "inflow segments overlap");
+        for (int k = 0; k < q.nt; k++) {
+            if (!std::isfinite(q.t[k]) || !(q.Q[k] >= 0.0) || !(q.phi_s[k] >= 0.0 && q.phi_s[k] <= 1.0))
+                return fail(M2P_EINVAL, "bad hydrograph sample");
+            if (k > 0 && !(q.t[k] > q.t[k - 1])) return fail(M2P_EINVAL, "hydrograph times must increase");
+        }
+        sd[s].side = q.side;
+        sd[s].i0 = q.i0;
+        sd[s].ncells = q.ncells;
+        sd[s].nt = q.nt;
+        sd[s].toff = (int)tab.size();
+        tab.insert(tab.end(), q.t, q.t + q.nt);
+        tab.insert(tab.end(), q.Q, q.Q + q.nt);
+        tab.insert(tab.end(), q.phi_s, q.phi_s + q.nt);
+    }
+    KParams& K = c->kp;
+    for (int s = 0; s < nseg; s++) K.seg[s] = sd[s];
+    K.nseg = nseg;
+    c->tab_flux = tab;
+    return upload_tables(c);
+}
+
+int m2p_set_inflow_states(m2p_ctx* c, const m2p_inflow_state* seg, int32_t nseg)
+{
+    if (!c || (nseg > 0 && !seg)) return fail(M2P_EINVAL, "NULL argument");
+    if (nseg < 0 || nseg > MAX_SEG) return fail(M2P_EINVAL, "0..8 inflow state segments supported");
+    std::vector<double> tab;
+    SegDesc sd[MAX_SEG];
+    for (int s = 0; s < nseg; s++) {
+        const m2p_inflow_state& q = seg[s];
+        int len = q.side < 2 ? c->g.ny : c->g.nx;
+        if (q.side < 0 || q.side > 3 || q.ncells < 1 || q.i0 < 0 || q.i0 + q.ncells > len || q.nt < 1 || !q.t ||
+            !q.h || !q.phi_s || !q.v)
+            return fail(M2P_EINVAL, "bad inflow state segment");
+        if (overlaps(sd, s, q.side, q.i0, q.ncells) || overlaps(c->kp.seg, c->kp.nseg, q.side, q.i0, q.ncells))
+            return fail(M2P_EINVAL, "inflow segments overlap");
+        for (int k = 0; k < q.nt; k++) {
+            if (!std::isfinite(q.t[k]) || !(q.h[k] >= 0.0) || !std::isfinite(q.h[k]) ||
+                !(q.phi_s[k] >= 0.0 && q.phi_s[k] <= 1.0) || !std::isfinite(q.v[k]))
+                return fail(M2P_EINVAL, "bad hydrograph sample");
+            if (k > 0 && !(q.t[k] > q.t[k - 1])) return fail(M2P_EINVAL, "hydrograph times must increase");
+        }
+        sd[s].side = q.side;
+        sd[s].i0 = q.i0;
+        sd[s].ncells = q.ncells;
+        sd[s].nt = q.nt;
+        sd[s].toff = (int)tab.size();
+        tab.insert(tab.end(), q.t, q.t + q.nt);
+        tab.insert(tab.end(), q.h, q.h + q.nt);
+        tab.insert(tab.end(), q.phi_s, q.phi_s + q.nt);
+        tab.insert(tab.end(), q.v, q.v + q.nt);
+    }
+    KParams& K = c->kp;
+    for (int s = 0; s < nseg; s++) K.sseg[s] = sd[s];
+    K.nsseg = nseg;
+    c->tab_state = tab;
+    return upload_tables(c);
 }
 
 int m2p_set_variant(m2p_ctx* c, int32_t variant, int32_t rows)
@@ -907,7 +970,8 @@ int L_loss(m2p_ctx* c, const double* target_dev, void* lam, double* loss)
 
 int inflow_unsupported(m2p_ctx* c)
 {
-    if (c->kp.nseg > 0) return m2p::fail(M2P_EINVAL, "the adjoint supports Mode-I (no inflow segments)");
+    if (c->kp.nseg > 0 || c->kp.nsseg > 0)
+        return m2p::fail(M2P_EINVAL, "the adjoint supports Mode-I (no inflow segments)");
     return M2P_OK;
 }
 

@@ -35,7 +35,9 @@ struct KParams {
     double eps, alpha, one_m_alpha, md, eps_chi, tan_d;
     double c_d, inv_n_r, theta_b;
     double T, V, H, L, dx, dy, cfl, a_floor, dt_floor;
-    SegDesc seg[MAX_SEG];
+    SegDesc seg[MAX_SEG];   // Mode-II segments with a discharge hydrograph (face flux)
+    int nsseg, pad_;
+    SegDesc sseg[MAX_SEG];  // Mode-II segments with a state hydrograph (ghost cells)
 };
 
 // Scalars that live on the device across steps (time, dt, reductions).
@@ -47,6 +49,7 @@ struct DevScalars {
     unsigned int status;
     unsigned int pad;
     double inflow[2][MAX_SEG][4];      // per stage: q, m_in, v_in, phi
+    double sghost[2][MAX_SEG][NF];     // per stage: ghost state of each state segment
     const double* dt_sched;            // optional prescribed (frozen) time steps, dimensionless
     long long n_sched;
 };

@@ -12,13 +12,50 @@ namespace m2p {
 
 // ---------------------------------------------------------------- helpers
 
+// Mode-II state segment covering boundary index k of a side, or -1
+__device__ __forceinline__ int state_seg_at(const KParams& P, int side, int k)
+{
+    for (int s = 0; s < P.nsseg; s++)
+        if (P.sseg[s].side == side && k >= P.sseg[s].i0 && k < P.sseg[s].i0 + P.sseg[s].ncells) return s;
+    return -1;
+}
+
+// Ghost cell (ii, jj) outside exactly one side and next to a Mode-II state
+// segment takes that segment's prescribed inflowing state (gh: the stage's
+// ghost states); other ghost cells keep the boundary rule's value.
+template <typename T>
+__device__ __forceinline__ void ghost_sub(const KParams& P, const double (*gh)[NF], int ii, int jj, T u[NF])
+{
+    int side = -1, k = 0;
+    if (jj < 0) {
+        side = 2;
+        k = ii;
+    } else if (jj >= P.ny) {
+        side = 3;
+        k = ii;
+    } else if (ii < 0) {
+        side = 0;
+        k = jj;
+    } else if (ii >= P.nx) {
+        side = 1;
+        k = jj;
+    }
+    if (side < 0 || k < 0 || k >= (side < 2 ? P.ny : P.nx)) return;
+    const int s = state_seg_at(P, side, k);
+    if (s < 0) return;
+#pragma unroll
+    for (int f = 0; f < NF; f++) u[f] = T(gh[s][f]);
+}
+
 template <typename T>
 struct View {
     const KParams& P;
     const T* U;
     const T* b;
     size_t fs;
-    __device__ View(const KParams& P_, const T* U_, const T* b_) : P(P_), U(U_), b(b_), fs((size_t)P_.ny * P_.pitch) {}
+    const double (*gh)[NF];  // ghost states of Mode-II state segments (stage kernels), else null
+    __device__ View(const KParams& P_, const T* U_, const T* b_, const double (*gh_)[NF] = nullptr)
+        : P(P_), U(U_), b(b_), fs((size_t)P_.ny * P_.pitch), gh(gh_) {}
     // state at any (ii, jj) in [-2, n+1] with the boundary rules applied
     __device__ __forceinline__ void load(int ii, int jj, T u[NF]) const
     {
@@ -36,6 +73,7 @@ struct View {
             u[2] = -u[2];
             u[5] = -u[5];
         }
+        if (gh && P.nsseg > 0) ghost_sub(P, gh, ii, jj, u);
     }
     __device__ __forceinline__ T bv(int ii, int jj) const { return b[(size_t)(jj + BHALO) * P.bpitch + BOFF + ii]; }
     __device__ __forceinline__ Geo<T> geo(int ii, int jj, const Consts<T>& K) const
@@ -100,7 +138,7 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const Consts<T> K(P);
-    const View<T> V(P, Uin, b);
+    const View<T> V(P, Uin, b, S->sghost[STAGE - 1]);
     const bool active = i < P.nx && j < P.ny;
     double red[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // outflow [side][phase], clamps
     double ax = 0.0, ay = 0.0;
@@ -374,6 +412,34 @@ __device__ __forceinline__ double inflow_rate(const KParams& P, const double* ta
     return acc;
 }
 
+// Ghost state of Mode-II state segment s at dimensionless time tau: vertical
+// thickness m = h / H and solid fraction phi from the hydrographs, both
+// phases moving along the inward normal with speed v; also returns m and v.
+__device__ __forceinline__ void ghost_state(const KParams& P, const double* tables, int s, double tau_nd,
+                                            double u[NF], double& m_out, double& v_out)
+{
+    const SegDesc& d = P.sseg[s];
+    const double* t = tables + d.toff;
+    const double* h = t + d.nt;
+    const double* phi = h + d.nt;
+    const double* vel = phi + d.nt;
+    double tau = tau_nd * P.T;
+    double m = interp_table(t, h, d.nt, tau) / P.H;
+    double ph = interp_table(t, phi, d.nt, tau);
+    double v = interp_table(t, vel, d.nt, tau) / P.V;
+    m_out = m;
+    v_out = v;
+    double ex = d.side == 0 ? 1.0 : (d.side == 1 ? -1.0 : 0.0);
+    double ey = d.side == 2 ? 1.0 : (d.side == 3 ? -1.0 : 0.0);
+    double ms = ph * m, mf = (1.0 - ph) * m;
+    u[0] = ms;
+    u[1] = ms * v * ex;
+    u[2] = ms * v * ey;
+    u[3] = mf;
+    u[4] = mf * v * ex;
+    u[5] = mf * v * ey;
+}
+
 // Single wavefront.  mode 0: close the step just taken (time, integrals);
 // both modes: next CFL dt from the speed maxima, inflow states of the next
 // step's two stages, reset of the maxima.
@@ -473,6 +539,15 @@ __device__ __forceinline__ void finalize_body(const KParams& P, DevScalars* S, c
         } else if (a > ay)
             ay = a;
     }
+    for (int s = 0; s < P.nsseg; s++) {
+        double u[NF], m, v;
+        ghost_state(P, tables, s, t, u, m, v);
+        double a = fabs(v) + sqrt(P.eps * m);
+        if (P.sseg[s].side < 2) {
+            if (a > ax) ax = a;
+        } else if (a > ay)
+            ay = a;
+    }
     ax = ax > P.a_floor ? ax : P.a_floor;
     ay = ay > P.a_floor ? ay : P.a_floor;
     double dtx = P.dxi / ax, dty = P.deta / ay;
@@ -486,6 +561,11 @@ __device__ __forceinline__ void finalize_body(const KParams& P, DevScalars* S, c
     for (int s = 0; s < P.nseg; s++) {
         inflow_state(P, tables, s, t, S->inflow[0][s]);
         inflow_state(P, tables, s, t + dt, S->inflow[1][s]);
+    }
+    for (int s = 0; s < P.nsseg; s++) {
+        double m, v;
+        ghost_state(P, tables, s, t, S->sghost[0][s], m, v);
+        ghost_state(P, tables, s, t + dt, S->sghost[1][s], m, v);
     }
 }
 

@@ -128,6 +128,7 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
             u[2] = -u[2];
             u[5] = -u[5];
         }
+        if (P.nsseg > 0) ghost_sub(P, S->sghost[STAGE - 1], cc, r, u);
     };
     auto loadB = [&](int r) { return b[(size_t)(r + BHALO) * P.bpitch + bcol]; };
 

@@ -69,6 +69,22 @@ class Inflow:
 
 
 @dataclasses.dataclass
+class InflowState:
+    """One Mode-II inflow segment given as the state of the inflowing flow:
+    ``ncells`` boundary cells from ``i0`` on ``side``, with piecewise-linear
+    hydrographs over time (s) of the vertical flow thickness h (m), the solid
+    fraction and the speed v (m/s) of both phases along the inward normal."""
+
+    side: int
+    i0: int
+    ncells: int
+    t: np.ndarray
+    h: np.ndarray
+    phi_s: np.ndarray
+    v: np.ndarray
+
+
+@dataclasses.dataclass
 class Problem:
     name: str
     nx: int
@@ -80,6 +96,7 @@ class Problem:
     h_vert: np.ndarray                    # [ny, nx] initial vertical thickness (m)
     phi_s: np.ndarray                     # [ny, nx] initial solid fraction
     inflows: List[Inflow] = dataclasses.field(default_factory=list)
+    inflow_states: List[InflowState] = dataclasses.field(default_factory=list)
     steps: int = 0
     precision: str = "f64"
     tan_mu: Optional[np.ndarray] = None   # optional per-cell tan(delta_b)

@@ -49,6 +49,8 @@ class Sim:
             self.set_state(prob.h_vert, prob.phi_s, vertical=True, vel=prob.vel)
             if prob.inflows:
                 self.set_inflow(prob.inflows)
+            if prob.inflow_states:
+                self.set_inflow_states(prob.inflow_states)
 
     # -- lifetime
     def close(self):
@@ -87,6 +89,16 @@ class Sim:
             self._keep += [t, Q, ph]
             arr[k] = A.Inflow(s.side, s.i0, s.ncells, len(t), A.dptr(t), A.dptr(Q), A.dptr(ph))
         A.check(A.lib().m2p_set_inflow(self._h, arr, len(inflows)), "m2p_set_inflow")
+
+    def set_inflow_states(self, segs):
+        """Mode-II segments given as hydrographs of the inflowing state
+        (``inputs.InflowState``: h in m, phi_s, inward speed v in m/s)."""
+        arr = (A.InflowState * max(1, len(segs)))()
+        for k, s in enumerate(segs):
+            a = [np.ascontiguousarray(x, dtype=np.float64) for x in (s.t, s.h, s.phi_s, s.v)]
+            self._keep += a
+            arr[k] = A.InflowState(s.side, s.i0, s.ncells, len(a[0]), *[A.dptr(x) for x in a])
+        A.check(A.lib().m2p_set_inflow_states(self._h, arr, len(segs)), "m2p_set_inflow_states")
 
     # -- stepping
     def step(self) -> float:

@@ -489,3 +489,86 @@ def test_frozen_time_steps_reproduce_the_run():
     c = _sim(prob)
     c.set_dt_schedule(dts * 0.5)
     assert np.allclose(c.run(40), dts * 0.5, rtol=0, atol=0)
+
+
+# ------------------------------------------- Mode-II inflow given as a state
+
+def _state_seg(side, i0, n, h, phi, v, t=(0.0, 1e6)):
+    k = len(t)
+    return I.InflowState(side, i0, n, np.array(t, dtype=float), np.full(k, h) if np.isscalar(h) else np.array(h),
+                         np.full(k, phi), np.full(k, v) if np.isscalar(v) else np.array(v))
+
+
+def test_state_inflow_feeding_uniform_flow_keeps_it_exactly():
+    """A uniform supercritical two-phase flow on a flat bed without friction,
+    drag or viscosity, fed through every W boundary cell by the same state
+    (h, phi, v along +X), stays exactly uniform: every face flux is equal.
+    The same on the N side with the flow along -Y (pins the ghost state's
+    thickness scaling, phase split, sign and direction)."""
+    n, dx, h, phi, v = 24, 10.0, 2.0, 0.4, 20.0
+    p = I.Params(delta_b_deg=0.0, inv_n_r=0.0, theta_b=0.0, c_d=0.0, cfl=0.4, bc=(0, 0, 0, 0))
+    for side, vel in ((0, (v, 0.0, v, 0.0)), (3, (0.0, -v, 0.0, -v))):
+        full = lambda x: np.full((n, n), x)
+        prob = I.Problem("uniform", n, n, dx, dx, p, np.zeros((n, n)), full(h), full(phi),
+                         vel=tuple(full(c) for c in vel), inflow_states=[_state_seg(side, 0, n, h, phi, v)])
+        s = _sim(prob)
+        U0 = s.state()
+        s.run(40)
+        assert np.max(np.abs(s.state() - U0)) <= 1e-14 * np.max(np.abs(U0)), side
+
+
+def test_state_inflow_volume_budget_closes():
+    """Volume in the domain equals minus the net outflow integral (the state
+    segment's inflow enters it with a negative sign) to round-off, per phase,
+    with time-varying hydrographs on two sides of a tilted bed."""
+    n, dx = 40, 10.0
+    dem = I.plane_dem(n, n, dx, dx, 8.0)
+    p = I.Params(cfl=0.3, bc=(0, 0, 0, 0))
+    segs = [_state_seg(0, 12, 9, [0.0, 3.0, 1.0], 0.5, [4.0, 8.0, 2.0], t=(0.0, 20.0, 60.0)),
+            _state_seg(2, 5, 6, [1.5, 0.5], 0.7, [3.0, 3.0], t=(0.0, 40.0))]
+    prob = I.Problem("budget", n, n, dx, dx, p, dem, np.zeros((n, n)), np.zeros((n, n)), inflow_states=segs)
+    s = _sim(prob)
+    s.run(300)
+    d = s.diag()
+    assert d["mass_s"] > 0 and d["mass_f"] > 0
+    assert abs(d["mass_s"] + d["out_s"]) <= 1e-12 * d["mass_s"]
+    assert abs(d["mass_f"] + d["out_f"]) <= 1e-12 * d["mass_f"]
+    assert d["in_s"] == 0.0 and d["in_f"] == 0.0
+
+
+def test_state_inflow_first_step_closed_form():
+    """Over a dry domain the first CFL step is set by the inflowing state:
+    dt = CFL dx / (|v| + sqrt(g h))."""
+    n, dx, h, v = 16, 5.0, 3.0, 7.0
+    p = I.Params(cfl=0.25)
+    prob = I.Problem("dt", n, n, dx, dx, p, np.zeros((n, n)), np.zeros((n, n)), np.zeros((n, n)),
+                     inflow_states=[_state_seg(1, 3, 4, h, 0.5, v)])
+    s = _sim(prob)
+    assert abs(s.peek_dt() - 0.25 * dx / (v + np.sqrt(9.81 * h))) <= 1e-14 * s.peek_dt()
+
+
+def test_state_inflow_transposes():
+    """A W-side state segment on a DEM equals an S-side segment on the
+    transposed DEM, transposed (p_X <-> p_Y)."""
+    n, dx = 36, 10.0
+    dem = I.fractal_dem(n, dx, 11, 30.0, tilt_deg=10.0)
+    p = I.Params(cfl=0.3, bc=(0, 0, 1, 0))
+    q = dataclasses.replace(p, bc=(1, 0, 0, 0))
+    seg = lambda side: [_state_seg(side, 10, 8, [0.5, 2.5], 0.6, [2.0, 5.0], t=(0.0, 30.0))]
+    z = np.zeros((n, n))
+    a = _sim(I.Problem("W", n, n, dx, dx, p, dem, z, z, inflow_states=seg(0)))
+    b = _sim(I.Problem("S", n, n, dx, dx, q, dem.T.copy(), z, z, inflow_states=seg(2)))
+    np.testing.assert_allclose(a.run(120), b.run(120), rtol=1e-12)
+    Ua, Ub = a.state(), b.state()
+    perm = [0, 2, 1, 3, 5, 4]
+    Ubt = np.stack([Ub[k].T for k in perm])
+    assert np.max(np.abs(Ua - Ubt)) <= 1e-12 * np.max(np.abs(Ua))
+
+
+def test_overlapping_inflow_segments_rejected():
+    n = 16
+    z = np.zeros((n, n))
+    prob = I.Problem("ov", n, n, 10.0, 10.0, I.Params(), z, z, z,
+                     inflow_states=[_state_seg(0, 2, 5, 1.0, 0.5, 1.0), _state_seg(0, 6, 3, 1.0, 0.5, 1.0)])
+    with pytest.raises(ValueError):
+        _sim(prob)
