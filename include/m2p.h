@@ -203,6 +203,18 @@ int m2p_run(m2p_ctx *c, int64_t nsteps);
  * M2P_EMAXSTEPS if t_end was not reached. */
 int m2p_run_to(m2p_ctx *c, double t_end, int64_t max_steps, int64_t *steps_done);
 
+/* Run through the output times t_out[0..n_out) (s, increasing; the step
+ * before each lands on it, as m2p_run_to) and store the output fields of
+ * Sect. 3.1.2 Stage 3 at each: fields (host) is [n_out][6][ny][nx] with
+ * h (bed-normal, m), phi_s, vxs, vys, vxf, vyf (m/s).  Each snapshot is
+ * extracted on the device and copied to pinned host memory on a second
+ * stream while the next interval is computed (two slots, allocated on first
+ * use and kept until m2p_destroy).  max_steps bounds the steps of the whole
+ * call; steps_done (may be NULL) returns them.  Errors: EINVAL, ESTATE,
+ * EMAXSTEPS (outputs before the stop are stored), device errors. */
+int m2p_run_outputs(m2p_ctx *c, const double *t_out, int64_t n_out, int64_t max_steps, double *fields,
+                    int64_t *steps_done);
+
 /* Output fields of the paper (Sect. 3.1.2, Stage 3), SI, host, ny*nx each,
  * NULL skips: bed-normal thickness h, solid fraction, v_X, v_Y of the solid
  * and of the fluid.  Synchronizes. */

@@ -64,6 +64,12 @@ struct m2p_ctx {
     std::vector<double> tab_flux, tab_state;  // host copies of the two kinds of Mode-II hydrograph tables
     double* mass_part = nullptr;
     double* staging = nullptr;  // FP64 field staging [7][ny][nx]
+    // output snapshots (m2p_run_outputs): two device slots of the six output
+    // fields, two pinned host slots and a copy stream (default priority)
+    double* snap_dev[2] = {nullptr, nullptr};
+    double* snap_host[2] = {nullptr, nullptr};
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t snap_ready[2] = {nullptr, nullptr}, snap_copied[2] = {nullptr, nullptr};
     double t_end = std::numeric_limits<double>::infinity();
     // per-kernel HIP-event timing (m2p_set_profiling)
     bool prof = false;
@@ -432,6 +438,14 @@ void m2p_destroy(m2p_ctx* c)
     if (c->mass_part) (void)hipFree(c->mass_part);
     if (c->staging) (void)hipFree(c->staging);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
+    for (int q = 0; q < 2; q++) {
+        if (c->snap_dev[q]) (void)hipFree(c->snap_dev[q]);
+        if (c->snap_host[q]) (void)hipHostFree(c->snap_host[q]);
+        if (c->snap_ready[q]) (void)hipEventDestroy(c->snap_ready[q]);
+        if (c->snap_copied[q]) (void)hipEventDestroy(c->snap_copied[q]);
+    }
+    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
     delete c;
 }
 
@@ -703,10 +717,11 @@ int m2p_run(m2p_ctx* c, int64_t nsteps)
     return M2P_OK;
 }
 
-int m2p_run_to(m2p_ctx* c, double t_end, int64_t max_steps, int64_t* steps_done)
+// Step until the model time reaches t_end (the last step shortened to land on
+// it) or max_steps steps were issued; chunks of steps between host checks.
+static int advance_to(m2p_ctx* c, double t_end, int64_t max_steps, int64_t* steps_done)
 {
-    if (!c || !std::isfinite(t_end) || max_steps < 0) return fail(M2P_EINVAL, "bad argument");
-    if (steps_done) *steps_done = 0;
+    *steps_done = 0;
     c->t_end = t_end;
     c->dirty = true;
     int rc = ensure_ready(c);
@@ -737,9 +752,82 @@ int m2p_run_to(m2p_ctx* c, double t_end, int64_t max_steps, int64_t* steps_done)
             break;
         }
     }
-    if (steps_done) *steps_done = hs.steps - s0;
+    *steps_done = hs.steps - s0;
     c->t_end = std::numeric_limits<double>::infinity();
     c->dirty = true;
+    return rc;
+}
+
+int m2p_run_to(m2p_ctx* c, double t_end, int64_t max_steps, int64_t* steps_done)
+{
+    if (!c || !std::isfinite(t_end) || max_steps < 0) return fail(M2P_EINVAL, "bad argument");
+    int64_t done = 0;
+    const int rc = advance_to(c, t_end, max_steps, &done);
+    if (steps_done) *steps_done = done;
+    return rc;
+}
+
+static int ensure_snapshots(m2p_ctx* c)
+{
+    if (c->copy_stream) return M2P_OK;
+    const size_t bytes = sizeof(double) * 6 * (size_t)c->g.nx * c->g.ny;
+    for (int q = 0; q < 2; q++) {
+        if (hipMalloc(&c->snap_dev[q], bytes) != hipSuccess) return fail(M2P_ENOMEM, "snapshot allocation failed");
+        if (hipHostMalloc(&c->snap_host[q], bytes, hipHostMallocDefault) != hipSuccess)
+            return fail(M2P_ENOMEM, "pinned snapshot allocation failed");
+        HIPCHK(hipEventCreateWithFlags(&c->snap_ready[q], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->snap_copied[q], hipEventDisableTiming));
+    }
+    HIPCHK(hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+    return M2P_OK;
+}
+
+int m2p_run_outputs(m2p_ctx* c, const double* t_out, int64_t n_out, int64_t max_steps, double* fields,
+                    int64_t* steps_done)
+{
+    if (steps_done) *steps_done = 0;
+    if (!c || !t_out || !fields || n_out < 1 || max_steps < 0) return fail(M2P_EINVAL, "bad argument");
+    for (int64_t k = 0; k < n_out; k++)
+        if (!std::isfinite(t_out[k]) || (k > 0 && !(t_out[k] > t_out[k - 1])))
+            return fail(M2P_EINVAL, "output times must be finite and increasing");
+    if (!c->has_state) return fail(M2P_ESTATE, "no state: call m2p_set_state first");
+    int rc = ensure_snapshots(c);
+    if (rc) return rc;
+    const size_t slot = 6 * (size_t)c->g.nx * c->g.ny;
+    int64_t pending[2] = {-1, -1}, total = 0;
+    // host copy of the snapshot in slot q once its device-to-host copy is done
+    auto drain = [&](int q) -> int {
+        if (pending[q] < 0) return M2P_OK;
+        HIPCHK(hipEventSynchronize(c->snap_copied[q]));
+        std::memcpy(fields + (size_t)pending[q] * slot, c->snap_host[q], slot * sizeof(double));
+        pending[q] = -1;
+        return M2P_OK;
+    };
+    for (int64_t k = 0; k < n_out && rc == M2P_OK; k++) {
+        int64_t done = 0;
+        rc = advance_to(c, t_out[k], max_steps - total, &done);
+        total += done;
+        if (rc) break;
+        const int q = (int)(k & 1);
+        if ((rc = drain(q))) break;  // slot q held output k - 2
+        if (c->prec == M2P_FP64) {
+            HIPCHK(Launch<double>::get_fields(c->kp, c->B, c->snap_dev[q], c->stream));
+        } else {
+            HIPCHK(Launch<float>::get_fields(c->kp, c->B, c->snap_dev[q], c->stream));
+        }
+        HIPCHK(hipEventRecord(c->snap_ready[q], c->stream));
+        HIPCHK(hipStreamWaitEvent(c->copy_stream, c->snap_ready[q], 0));
+        HIPCHK(hipMemcpyAsync(c->snap_host[q], c->snap_dev[q], slot * sizeof(double), hipMemcpyDeviceToHost,
+                              c->copy_stream));
+        HIPCHK(hipEventRecord(c->snap_copied[q], c->copy_stream));
+        pending[q] = k;
+    }
+    for (int64_t k = n_out - 2; k < n_out; k++) {
+        if (k < 0) continue;
+        const int r2 = drain((int)(k & 1));
+        if (r2 && rc == M2P_OK) rc = r2;
+    }
+    if (steps_done) *steps_done = total;
     return rc;
 }
 

@@ -114,6 +114,17 @@ class Sim:
         A.check(A.lib().m2p_run_to(self._h, float(t_end), int(max_steps), C.byref(n)), "m2p_run_to")
         return n.value
 
+    def run_outputs(self, times, max_steps: int = 10 ** 9):
+        """Run through the output times (s); returns ([n, 6, ny, nx] fields
+        h, phi_s, vxs, vys, vxf, vyf at each time, steps taken).  Snapshots
+        are copied to the host while the next interval runs."""
+        t = np.ascontiguousarray(times, dtype=np.float64)
+        out = np.empty((len(t), 6, self.ny, self.nx), dtype=np.float64)
+        n = C.c_int64()
+        A.check(A.lib().m2p_run_outputs(self._h, A.dptr(t), len(t), int(max_steps), A.dptr(out), C.byref(n)),
+                "m2p_run_outputs")
+        return out, n.value
+
     def synchronize(self):
         A.check(A.lib().m2p_synchronize(self._h), "m2p_synchronize")
 

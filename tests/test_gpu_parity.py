@@ -176,6 +176,24 @@ def test_run_to_lands_on_end_time():
     assert g.step() > 0
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_run_outputs_equals_run_to_and_get_fields(precision):
+    """Output snapshots copied on the second stream equal run_to + get_fields
+    at the same times, bitwise, with the same step count."""
+    prob = _state_inflow_problem()
+    times = [1.0, 2.5, 4.0, 7.0, 9.5]
+    a = Sim(prob, precision=precision)
+    snaps, na = a.run_outputs(times)
+    b = Sim(prob, precision=precision)
+    nb = 0
+    for k, t in enumerate(times):
+        nb += b.run_to(t)
+        f = b.fields()
+        for q, key in enumerate(("h", "phi_s", "vxs", "vys", "vxf", "vyf")):
+            assert np.array_equal(snaps[k, q], f[key]), (k, key)
+    assert na == nb and a.diag()["t"] == times[-1]
+
+
 def test_vertical_and_normal_thickness_inputs_agree():
     prob = I.config1(n=32)
     a = Sim(prob, precision="f64")
