@@ -62,6 +62,7 @@ struct m2p_ctx {
     double* bpart = nullptr;
     double* tables = nullptr;
     std::vector<double> tab_flux, tab_state;  // host copies of the two kinds of Mode-II hydrograph tables
+    int state_toff[MAX_SEG] = {};             // offsets of the state tables within tab_state
     double* mass_part = nullptr;
     double* staging = nullptr;  // FP64 field staging [7][ny][nx]
     // output snapshots (m2p_run_outputs): two device slots of the six output
@@ -140,14 +141,12 @@ Shape make_shape(const KParams& P, int variant, int rows)
     }
     s.R = R;
     s.nrb = (P.ny + R - 1) / R;
+    s.n_we = P.ny;  // one outflow slot per boundary face
+    s.n_sn = P.nx;
     if (s.variant == 1) {
-        s.n_we = s.nby;
-        s.n_sn = s.nbx;
         s.nw = s.nbx * s.nby;
         s.blocks = s.nbx * s.nby;
     } else {
-        s.n_we = s.nrb;
-        s.n_sn = s.nstrips;
         s.nw = s.nstrips * s.nrb;
         s.blocks = (s.nw + 3) / 4;
     }
@@ -389,7 +388,7 @@ int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t pr
     // wavefronts with at least 4 rows each
     {
         const int nbx = (nx + 63) / 64, nby = (ny + 3) / 4, nstrips = (nx + 59) / 60, nrb = (ny + 3) / 4;
-        const int nmax = std::max(std::max(nbx, nby), std::max(nstrips, nrb)) + 1;
+        const int nmax = std::max(nx, ny) + 1;  // outflow slots: one per boundary face
         const size_t nw = std::max((size_t)nbx * nby, (size_t)nstrips * nrb);
         c->B.nmax = nmax;
         c->B.nw_ref = nbx * nby;
@@ -582,14 +581,13 @@ static int upload_tables(m2p_ctx* c)
     const int shift = (int)tab.size();
     tab.insert(tab.end(), c->tab_state.begin(), c->tab_state.end());
     KParams& K = c->kp;
-    for (int s = 0; s < K.nsseg; s++) K.sseg[s].toff += shift;
+    for (int s = 0; s < K.nsseg; s++) K.sseg[s].toff = shift + c->state_toff[s];
     HIPCHK(hipStreamSynchronize(c->stream));
     if (c->tables) (void)hipFree(c->tables);
     c->tables = nullptr;
     size_t nb = std::max<size_t>(tab.size(), 8) * sizeof(double);
     if (hipMalloc(&c->tables, nb) != hipSuccess) return fail(M2P_ENOMEM, "table allocation failed");
     if (!tab.empty()) HIPCHK(hipMemcpy(c->tables, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
-    for (int s = 0; s < K.nsseg; s++) K.sseg[s].toff -= shift;
     c->B.tables = c->tables;
     c->dirty = true;
     return M2P_OK;
@@ -668,7 +666,10 @@ int m2p_set_inflow_states(m2p_ctx* c, const m2p_inflow_state* seg, int32_t nseg)
         tab.insert(tab.end(), q.v, q.v + q.nt);
     }
     KParams& K = c->kp;
-    for (int s = 0; s < nseg; s++) K.sseg[s] = sd[s];
+    for (int s = 0; s < nseg; s++) {
+        K.sseg[s] = sd[s];
+        c->state_toff[s] = sd[s].toff;
+    }
     K.nsseg = nseg;
     c->tab_state = tab;
     return upload_tables(c);

@@ -256,7 +256,7 @@ int m2p_batch_create(m2p_batch** out, int32_t nscen, const m2p_grid* grids, cons
         B->mu_off.push_back(mb);
         if (hm) mb += (size_t)K.ny * K.pitch * B->esz;
         const int nbx = (K.nx + 63) / 64, nby = (K.ny + 3) / 4, nstrips = (K.nx + 59) / 60, nrb = (K.ny + 3) / 4;
-        const int nm = std::max(std::max(nbx, nby), std::max(nstrips, nrb)) + 1;
+        const int nm = std::max(K.nx, K.ny) + 1;  // outflow slots: one per boundary face
         const int nw = std::max(nbx * nby, nstrips * nrb);
         B->nmax.push_back(nm);
         B->nwcap.push_back(nw);

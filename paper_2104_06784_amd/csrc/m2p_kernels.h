@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
     const Consts<T> K(P);
     const View<T> V(P, Uin, b, S->sghost[STAGE - 1]);
     const bool active = i < P.nx && j < P.ny;
-    double red[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // outflow [side][phase], clamps
+    double red[1] = {0};  // clamps
     double ax = 0.0, ay = 0.0;
     int bad = 0;
     if (active) {
@@ -170,43 +170,41 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
             reconstruct(w, uL, uR);
             central_flux(K, uL, gC, uR, gN, 1, HYt);
         }
-        // Mode-II faces and outflow through the other boundary faces
+        // Mode-II faces, and the flux through every boundary face into the
+        // per-face outflow slots (zero on discharge-inflow faces)
         const double (*inf)[4] = S->inflow[STAGE - 1];
+        const int st = STAGE - 1;
         if (i == 0) {
             int s = inflow_seg_at(P, 0, j);
             if (s >= 0)
                 inflow_flux(K, gC, 0, +1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HXl);
-            else {
-                red[0] = -(double)HXl[0] * P.deta;
-                red[1] = -(double)HXl[3] * P.deta;
-            }
+            double* bp = bpart + ((size_t)(st * 4 + 0) * nmax + j) * 2;
+            bp[0] = s >= 0 ? 0.0 : -(double)HXl[0] * P.deta;
+            bp[1] = s >= 0 ? 0.0 : -(double)HXl[3] * P.deta;
         }
         if (i == P.nx - 1) {
             int s = inflow_seg_at(P, 1, j);
             if (s >= 0)
                 inflow_flux(K, gC, 0, -1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HXr);
-            else {
-                red[2] = (double)HXr[0] * P.deta;
-                red[3] = (double)HXr[3] * P.deta;
-            }
+            double* bp = bpart + ((size_t)(st * 4 + 1) * nmax + j) * 2;
+            bp[0] = s >= 0 ? 0.0 : (double)HXr[0] * P.deta;
+            bp[1] = s >= 0 ? 0.0 : (double)HXr[3] * P.deta;
         }
         if (j == 0) {
             int s = inflow_seg_at(P, 2, i);
             if (s >= 0)
                 inflow_flux(K, gC, 1, +1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HYb);
-            else {
-                red[4] = -(double)HYb[0] * P.dxi;
-                red[5] = -(double)HYb[3] * P.dxi;
-            }
+            double* bp = bpart + ((size_t)(st * 4 + 2) * nmax + i) * 2;
+            bp[0] = s >= 0 ? 0.0 : -(double)HYb[0] * P.dxi;
+            bp[1] = s >= 0 ? 0.0 : -(double)HYb[3] * P.dxi;
         }
         if (j == P.ny - 1) {
             int s = inflow_seg_at(P, 3, i);
             if (s >= 0)
                 inflow_flux(K, gC, 1, -1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HYt);
-            else {
-                red[6] = (double)HYt[0] * P.dxi;
-                red[7] = (double)HYt[3] * P.dxi;
-            }
+            double* bp = bpart + ((size_t)(st * 4 + 3) * nmax + i) * 2;
+            bp[0] = s >= 0 ? 0.0 : (double)HYt[0] * P.dxi;
+            bp[1] = s >= 0 ? 0.0 : (double)HYt[3] * P.dxi;
         }
         // sources
         const T* uC = row[2];
@@ -262,7 +260,7 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
         const size_t fs = (size_t)P.ny * P.pitch;
         T tmu = P.has_mu ? mu[c] : K.tan_d;
         T out[NF];
-        red[8] = (double)update_cell(K, uC, gC, HXl, HXr, HYb, HYt, Sr, svx, svy, dt, tmu, out);
+        red[0] = (double)update_cell(K, uC, gC, HXl, HXr, HYb, HYt, Sr, svx, svy, dt, tmu, out);
         if (STAGE == 2) {
 #pragma unroll
             for (int k = 0; k < NF; k++) out[k] = T(0.5) * (Un[k * fs + c] + out[k]);
@@ -279,7 +277,7 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
         }
     }
     // block reductions (fixed trees: deterministic)
-    block_sum<9, 256>(red, sh);
+    block_sum<1, 256>(red, sh);
     __syncthreads();
     {
         const int tid = threadIdx.x + threadIdx.y * blockDim.x;
@@ -301,24 +299,8 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
             double* wp = wpart + ((size_t)st * gridDim.x * gridDim.y + bid) * 4;
             wp[0] = sh[0];
             wp[1] = sh[256];
-            wp[2] = red[8];
+            wp[2] = red[0];
             wp[3] = sh[512];
-            if (blockIdx.x == 0) {
-                bpart[((st * 4 + 0) * nmax + blockIdx.y) * 2 + 0] = red[0];
-                bpart[((st * 4 + 0) * nmax + blockIdx.y) * 2 + 1] = red[1];
-            }
-            if (blockIdx.x == gridDim.x - 1) {
-                bpart[((st * 4 + 1) * nmax + blockIdx.y) * 2 + 0] = red[2];
-                bpart[((st * 4 + 1) * nmax + blockIdx.y) * 2 + 1] = red[3];
-            }
-            if (blockIdx.y == 0) {
-                bpart[((st * 4 + 2) * nmax + blockIdx.x) * 2 + 0] = red[4];
-                bpart[((st * 4 + 2) * nmax + blockIdx.x) * 2 + 1] = red[5];
-            }
-            if (blockIdx.y == gridDim.y - 1) {
-                bpart[((st * 4 + 3) * nmax + blockIdx.x) * 2 + 0] = red[6];
-                bpart[((st * 4 + 3) * nmax + blockIdx.x) * 2 + 1] = red[7];
-            }
         }
     }
 }

@@ -132,8 +132,16 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
     };
     auto loadB = [&](int r) { return b[(size_t)(r + BHALO) * P.bpitch + bcol]; };
 
-    double ob[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // outflow W, E, S, N per phase
-    double amx = 0.0, amy = 0.0;
+    // flux through each boundary face goes to its own outflow slot (zero on
+    // discharge-inflow faces), reduced in a fixed order by the finalize
+    const int st = STAGE - 1;
+    auto put_b = [&](int side, int k, bool inflow, T m_s, T m_f, double len) {
+        double* bp = bpart + ((size_t)(st * 4 + side) * nmax + k) * 2;
+        const double sg = (side == 0 || side == 2) ? -1.0 : 1.0;
+        bp[0] = inflow ? 0.0 : sg * (double)m_s * len;
+        bp[1] = inflow ? 0.0 : sg * (double)m_f * len;
+    };
+    T amx = T(0), amy = T(0);
     int clamps = 0, bad = 0;
 
     // ---- prologue: rows r0-2 .. r0+1
@@ -162,10 +170,7 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
             const int s = inflow_seg_at(P, 2, col);
             if (s >= 0)
                 inflow_flux(K, D0.g, 1, +1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), Hy);
-            else {
-                ob[4] -= (double)Hy[0] * P.dxi;
-                ob[5] -= (double)Hy[3] * P.dxi;
-            }
+            put_b(2, col, s >= 0, Hy[0], Hy[3], P.dxi);
         }
     }
     // viscous y-face j - 1/2
@@ -222,10 +227,7 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
             const int s = inflow_seg_at(P, 3, col);
             if (s >= 0)
                 inflow_flux(K, D0.g, 1, -1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HyN);
-            else {
-                ob[6] += (double)HyN[0] * P.dxi;
-                ob[7] += (double)HyN[3] * P.dxi;
-            }
+            put_b(3, col, s >= 0, HyN[0], HyN[3], P.dxi);
         }
         vGXN = T(0);
         vGYN = T(0);
@@ -262,19 +264,13 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
             const int s = inflow_seg_at(P, 0, j);
             if (s >= 0)
                 inflow_flux(K, D0.g, 0, +1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HxL);
-            else {
-                ob[0] -= (double)HxL[0] * P.deta;
-                ob[1] -= (double)HxL[3] * P.deta;
-            }
+            put_b(0, j, s >= 0, HxL[0], HxL[3], P.deta);
         }
         if (ownE) {
             const int s = inflow_seg_at(P, 1, j);
             if (s >= 0)
                 inflow_flux(K, D0.g, 0, -1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), Hx);
-            else {
-                ob[2] += (double)Hx[0] * P.deta;
-                ob[3] += (double)Hx[3] * P.deta;
-            }
+            put_b(1, j, s >= 0, Hx[0], Hx[3], P.deta);
         }
 
         // ---- sources of row j
@@ -325,9 +321,9 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
                 for (int k = 0; k < NF; k++) out[k] = T(0.5) * (unr[k] + out[k]);
                 T a[2];
                 side_speed(K, out, D0.g, 0, a);
-                amx = fmax(amx, (double)(a[0] > a[1] ? a[0] : a[1]));
+                amx = fmax(amx, a[0] > a[1] ? a[0] : a[1]);
                 side_speed(K, out, D0.g, 1, a);
-                amy = fmax(amy, (double)(a[0] > a[1] ? a[0] : a[1]));
+                amy = fmax(amy, a[0] > a[1] ? a[0] : a[1]);
             }
 #pragma unroll
             for (int k = 0; k < NF; k++) {
@@ -355,32 +351,13 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
         amy = fmax(amy, __shfl_xor(amy, off, 64));
         clamps += __shfl_xor(clamps, off, 64);
         bad |= __shfl_xor(bad, off, 64);
-#pragma unroll
-        for (int q = 0; q < 8; q++) ob[q] += __shfl_xor(ob[q], off, 64);
     }
     if (lane == 0) {
-        const int st = STAGE - 1;
         double* wp = wpart + ((size_t)st * nstrips * nrb + wslot) * 4;
-        wp[0] = amx;
-        wp[1] = amy;
+        wp[0] = (double)amx;
+        wp[1] = (double)amy;
         wp[2] = (double)clamps;
         wp[3] = (double)bad;
-        if (strip == 0) {
-            bpart[((st * 4 + 0) * nmax + rb) * 2 + 0] = ob[0];
-            bpart[((st * 4 + 0) * nmax + rb) * 2 + 1] = ob[1];
-        }
-        if (strip == nstrips - 1) {
-            bpart[((st * 4 + 1) * nmax + rb) * 2 + 0] = ob[2];
-            bpart[((st * 4 + 1) * nmax + rb) * 2 + 1] = ob[3];
-        }
-        if (rb == 0) {
-            bpart[((st * 4 + 2) * nmax + strip) * 2 + 0] = ob[4];
-            bpart[((st * 4 + 2) * nmax + strip) * 2 + 1] = ob[5];
-        }
-        if (rb == nrb - 1) {
-            bpart[((st * 4 + 3) * nmax + strip) * 2 + 0] = ob[6];
-            bpart[((st * 4 + 3) * nmax + strip) * 2 + 1] = ob[7];
-        }
     }
 }
 
@@ -438,7 +415,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_finalize_batch(const ScenDesc<T>* __restrict__ scen, int mode)
 {
     const ScenDesc<T>& D = scen[blockIdx.x];
-    finalize_body(D.P, D.S, D.bpart, D.nrb, D.nstrips, D.nmax, D.tables, mode, D.wpart,
+    finalize_body(D.P, D.S, D.bpart, D.P.ny, D.P.nx, D.nmax, D.tables, mode, D.wpart,
                   mode == 1 ? D.nw_ref : D.nstrips * D.nrb);
 }
 

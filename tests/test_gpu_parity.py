@@ -133,6 +133,21 @@ def test_state_inflow_segments_fp64(variant):
     assert abs(dg["mass_s"] + dg["out_s"] - dg["in_s"] - (do["mass_s"] + do["out_s"] - do["in_s"])) <= 1e-9
 
 
+def test_state_inflow_set_before_discharge_segments():
+    """The same problem with the state segments given before the discharge
+    segment (the hydrograph tables are laid out again on each call)."""
+    import dataclasses
+    prob = _state_inflow_problem()
+    g = Sim(dataclasses.replace(prob, inflows=[], inflow_states=[]), precision="f64")
+    g.set_inflow_states(prob.inflow_states)
+    g.set_inflow(prob.inflows)
+    o = Ora(prob)
+    dtg = np.array([g.step() for _ in range(100)])
+    dto = o.run(100)
+    np.testing.assert_allclose(dtg, dto, rtol=1e-12, atol=0)
+    assert relerr(g.state(), o.state()) <= 1e-12
+
+
 def test_state_inflow_fp32_close_to_oracle():
     prob = _state_inflow_problem()
     g, o = Sim(prob, precision="f32"), Ora(prob)
