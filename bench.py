@@ -101,9 +101,17 @@ def cpu_baseline(prob, nsteps: int) -> dict:
     t0 = time.perf_counter()
     o.run(nsteps)
     el = time.perf_counter() - t0
+    # one step on one thread: the single-core baseline the paper compares against
+    oracle.set_threads(1)
+    o1 = oracle.OracleSim(prob)
+    t0 = time.perf_counter()
+    o1.run(1)
+    el1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
     return {"value": prob.cells * nsteps / el / 1e6, "unit": "Mcell-steps/s", "cores": used, "kind": "oracle",
             "sample": f"{nsteps} steps of the full {prob.nx}x{prob.ny} grid from the release state "
-                      f"(FP64, OpenMP over rows), {el:.1f} s"}
+                      f"(FP64, OpenMP over rows), {el:.1f} s; single thread: 1 step, {el1:.1f} s",
+            "single_thread_value": round(prob.cells / el1 / 1e6, 3)}
 
 
 def bench_batched(stream, steps: int, warmup: int, nscen: int = 256) -> dict:
@@ -152,6 +160,41 @@ def bench_batched(stream, steps: int, warmup: int, nscen: int = 256) -> dict:
             "ms_per_step": round(ms_b / steps, 4), "tile_rows": rows, "blocks": blocks,
             "one_by_one_value": round(v1, 2), "one_by_one_ms_per_step": round(ms_1 / steps, 4),
             "speedup_vs_one_by_one": round(vb / v1, 3)}
+
+
+def bench_sweep(stream, steps: int) -> dict:
+    """Single-scenario forward over the paper's mesh sizes (Sect. 3.2: 10k to
+    1M cells, plus its two events' grids 377 x 228 and 180 x 154), FP32,
+    steps replayed from HIP graphs and launched kernel by kernel."""
+    import math
+
+    from paper_2104_06784_amd import inputs
+    from paper_2104_06784_amd.sim import Sim
+    import torch
+    rows = []
+    shapes = [(int(round(math.sqrt(c))),) * 2 for c in (10_000, 50_000, 100_000, 250_000, 500_000, 1_000_000)]
+    for nx, ny in shapes + [(377, 228), (180, 154)]:
+        prob = inputs.paper_shaped(nx, ny)
+        rec = {"nx": nx, "ny": ny, "cells": nx * ny}
+        for chunk, key in ((32, "graph"), (0, "direct")):
+            sim = Sim(prob, precision="f32", stream=stream)
+            sim.set_graph(chunk)
+            sim.run(64)
+            sim.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            sim.run(steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            if sim.diag()["status"] != 0:
+                raise SystemExit(f"device status in the mesh sweep at {nx}x{ny}")
+            rec[key] = round(nx * ny * steps / (ms / 1e3) / 1e6, 1)
+            rec[key + "_us_per_step"] = round(ms * 1e3 / steps, 2)
+            del sim
+        rows.append(rec)
+        log(f"[bench] sweep {nx}x{ny}: {rec['graph']} Mcell-steps/s (graph), {rec['direct']} (direct)")
+    return {"unit": "Mcell-steps/s", "steps": steps, "precision": "f32", "rows": rows}
 
 
 def bench_adjoint(stream, nsteps: int, ckpt: int) -> dict:
@@ -206,6 +249,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=50, help="0 skips the batched-ensemble measurement")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="0 skips the forward+adjoint measurement")
+    ap.add_argument("--sweep-steps", type=int, default=1000, help="0 skips the mesh-size sweep")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run 3 device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -295,6 +339,8 @@ def main():
         out["fwd_adjoint"] = bench_adjoint(stream, args.adjoint_steps, 100)
         log(f"[bench] forward+adjoint {out['fwd_adjoint']['value']:.1f} Mcell-steps/s "
             f"({out['fwd_adjoint']['cost_vs_forward']:.1f}x the forward)")
+    if args.sweep_steps > 0:
+        out["mesh_sweep"] = bench_sweep(stream, args.sweep_steps)
     if args.copy_probe_mib > 0:
         # plain device-to-device copies of known size, so that hardware byte
         # counters of the step kernels can be calibrated against them

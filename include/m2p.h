@@ -198,6 +198,14 @@ int m2p_step(m2p_ctx *c, double *dt_out);
 /* Enqueue nsteps steps without any host synchronization. */
 int m2p_run(m2p_ctx *c, int64_t nsteps);
 
+/* Steps are replayed from a HIP graph of `chunk` steps (default 32; 0 =
+ * launch kernel by kernel) when the context has a stream of its own and
+ * per-kernel profiling is off; the graph is captured on first use and again
+ * whenever the constants, buffers or launch shape change.  Replays give the
+ * same results as direct launches.  Errors: M2P_EINVAL for chunk outside
+ * [0, 4096]. */
+int m2p_set_graph(m2p_ctx *c, int32_t chunk);
+
 /* Advance until t >= t_end (the last step is shortened to land on t_end) or
  * max_steps steps, checking the device status between chunks.  Returns
  * M2P_EMAXSTEPS if t_end was not reached. */

@@ -89,6 +89,7 @@ SIGNATURES = {
     "m2p_set_inflow": (C.c_int, [_P, C.POINTER(Inflow), C.c_int32]),
     "m2p_set_inflow_states": (C.c_int, [_P, C.POINTER(InflowState), C.c_int32]),
     "m2p_run_outputs": (C.c_int, [_P, _dp, C.c_int64, C.c_int64, _dp, C.POINTER(C.c_int64)]),
+    "m2p_set_graph": (C.c_int, [_P, C.c_int32]),
     "m2p_set_variant": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "m2p_step": (C.c_int, [_P, _dp]),
     "m2p_run": (C.c_int, [_P, C.c_int64]),

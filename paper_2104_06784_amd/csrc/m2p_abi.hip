@@ -65,6 +65,14 @@ struct m2p_ctx {
     int state_toff[MAX_SEG] = {};             // offsets of the state tables within tab_state
     double* mass_part = nullptr;
     double* staging = nullptr;  // FP64 field staging [7][ny][nx]
+    // step chunks captured in a HIP graph (m2p_set_graph), recaptured when
+    // the kernel arguments they were captured with change
+    int graph_chunk = 32;
+    hipGraphExec_t gexec = nullptr;
+    int gsteps = 0;
+    KParams g_kp{};
+    Bufs g_B{};
+    Shape g_shape{};
     // output snapshots (m2p_run_outputs): two device slots of the six output
     // fields, two pinned host slots and a copy stream (default priority)
     double* snap_dev[2] = {nullptr, nullptr};
@@ -445,6 +453,7 @@ void m2p_destroy(m2p_ctx* c)
         if (c->snap_copied[q]) (void)hipEventDestroy(c->snap_copied[q]);
     }
     if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     delete c;
 }
 
@@ -709,12 +718,65 @@ int m2p_step(m2p_ctx* c, double* dt_out)
     return M2P_OK;
 }
 
+// A graph of graph_chunk steps captured on the context's stream with the
+// current kernel arguments (constants, buffers, launch shape).  Graphs need
+// a stream of their own (not the null stream) and are not used while
+// per-kernel profiling is on.
+static bool graph_usable(const m2p_ctx* c) { return c->stream && !c->prof && c->graph_chunk > 0; }
+
+static int ensure_graph(m2p_ctx* c)
+{
+    if (c->gexec && c->gsteps == c->graph_chunk && !std::memcmp(&c->g_kp, &c->kp, sizeof(KParams)) &&
+        !std::memcmp(&c->g_B, &c->B, sizeof(Bufs)) && !std::memcmp(&c->g_shape, &c->shape, sizeof(Shape)))
+        return M2P_OK;
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    hipGraph_t graph;
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < c->graph_chunk; k++) {
+        const hipError_t e = do_step(c);
+        if (e != hipSuccess) {
+            (void)hipStreamEndCapture(c->stream, &graph);
+            return hip_fail(e, "kernel launch during graph capture");
+        }
+    }
+    HIPCHK(hipStreamEndCapture(c->stream, &graph));
+    const hipError_t e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(e);
+    c->gsteps = c->graph_chunk;
+    std::memcpy(&c->g_kp, &c->kp, sizeof(KParams));
+    std::memcpy(&c->g_B, &c->B, sizeof(Bufs));
+    std::memcpy(&c->g_shape, &c->shape, sizeof(Shape));
+    return M2P_OK;
+}
+
+// n steps: whole graph chunks, then single steps.
+static int issue_steps(m2p_ctx* c, int64_t n)
+{
+    int64_t done = 0;
+    if (graph_usable(c) && n >= c->graph_chunk) {
+        const int rc = ensure_graph(c);
+        if (rc) return rc;
+        for (; done + c->gsteps <= n; done += c->gsteps) HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+    }
+    for (; done < n; done++) HIPCHK(do_step(c));
+    return M2P_OK;
+}
+
 int m2p_run(m2p_ctx* c, int64_t nsteps)
 {
     if (!c || nsteps < 0) return fail(M2P_EINVAL, "bad argument");
     int rc = ensure_ready(c);
     if (rc) return rc;
-    for (int64_t k = 0; k < nsteps; k++) HIPCHK(do_step(c));
+    return issue_steps(c, nsteps);
+}
+
+int m2p_set_graph(m2p_ctx* c, int32_t chunk)
+{
+    if (!c || chunk < 0 || chunk > 4096) return fail(M2P_EINVAL, "graph chunk must be in [0, 4096]");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->graph_chunk = chunk;
     return M2P_OK;
 }
 
@@ -740,7 +802,7 @@ static int advance_to(m2p_ctx* c, double t_end, int64_t max_steps, int64_t* step
             break;
         }
         int64_t k = std::min<int64_t>(chunk, max_steps - issued);
-        for (int64_t q = 0; q < k; q++) HIPCHK(do_step(c));
+        if ((rc = issue_steps(c, k))) break;
         issued += k;
         chunk = std::min<int64_t>(chunk * 2, 1024);
         rc = read_scalars(c, &hs);
@@ -1215,7 +1277,7 @@ int m2p_adjoint_run(m2p_ctx* c, int64_t nsteps, int32_t ckpt_every, const double
             HIPCHK(step_part(c, 2));
         }
         for (int64_t s = n1 - 1; s >= n0; s--) {
-            const double dt = hdt[s] / 1.0;
+            const double dt = hdt[s];
             const void* Un = (char*)tapeU.p + sb * (s - n0);
             const void* Us = (char*)tapeUs.p + sb * (s - n0);
             HIPCHK(L_axpbz(c, 0.5, lam.p, 0.0, nullptr, lamh.p));        // cotangent of U**

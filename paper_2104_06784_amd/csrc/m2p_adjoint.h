@@ -13,10 +13,14 @@
 //                    S_c to its 34 inputs;
 //   pass C (cells):  fixed-order gather of all contributions that land on a
 //                    cell through the ghost-cell map (sign flips included).
-// Each local Jacobian-transpose product is formed from forward-mode dual
-// evaluations (one per local input) of the same device functions the forward
-// kernels run, so the adjoint differentiates exactly the executed scheme.
-// Non-smooth points (minmod, max of speeds, Coulomb stop, positivity) take the
+// The local Jacobian-transpose products follow the structure of the forward
+// arithmetic: the central flux, the face sides (side_flux), the local sources
+// and the viscous face terms are reversed by hand; the Coulomb clamp,
+// kappa, the desingularised quotients and the fluid-pressure products use
+// forward-mode dual evaluations of the same device functions the forward
+// kernels run.  Every product is the transpose of the dual-number JVP of the
+// executed (FP64-order) scheme, which the tests check to 1e-12.  Non-smooth
+// points (minmod, max of speeds, Coulomb stop, positivity, sqrt at 0) take the
 // derivative of the branch selected by the values.
 #pragma once
 
@@ -292,19 +296,19 @@ __global__ void __launch_bounds__(128) k_adj_post(KParams P, const T* __restrict
     dn[4] = TT((g5.N.nY - g5.S.nY) / two_deta, T(0));
     dn[5] = TT((g5.N.nZ - g5.S.nZ) / two_deta, T(0));
     // clamp inputs: tentative state (6), kappa_s, friction; kappa_s depends on
-    // the cell's own velocities only (the interphase pressure gradient does
-    // not enter it)
-    Src<TT> S0;
-    {
-        TT uc[NF];
-        for (int k = 0; k < NF; k++) uc[k] = TT(s.row[2][k], T(0));
-        sources(K, P.flags, uc, gC, dn, TT(0.0), TT(0.0), S0);
-    }
+    // the cell's own solid fields only
+    const T* uc = s.row[2];
+    auto kappa_s = [&](int d) {
+        const TT ms(uc[0], d == 0 ? T(1) : T(0));
+        return kappa_of(dsg(TT(uc[1], d == 1 ? T(1) : T(0)), ms, K.md), dsg(TT(uc[2], d == 2 ? T(1) : T(0)), ms, K.md),
+                        gC, dn);
+    };
+    const T kap_s = kappa_s(-1).v;
     T gcl[8];
     for (int d = 0; d < 8; d++) {
         TT o[NF];
         for (int k = 0; k < NF; k++) o[k] = TT(tent[k], d == k ? T(1) : T(0));
-        clamp_cell(K, gC, TT(S0.kappa_s.v, d == 6 ? T(1) : T(0)), TT(dt, T(0)), TT(tmu, d == 7 ? T(1) : T(0)), o);
+        clamp_cell(K, gC, TT(kap_s, d == 6 ? T(1) : T(0)), TT(dt, T(0)), TT(tmu, d == 7 ? T(1) : T(0)), o);
         T acc = T(0);
         for (int k = 0; k < NF; k++) acc += lo[k] * o[k].d;
         gcl[d] = acc;
@@ -312,13 +316,7 @@ __global__ void __launch_bounds__(128) k_adj_post(KParams P, const T* __restrict
     T g[13];
     for (int k = 0; k < NF; k++) g[k] = gcl[k];
     g[12] = gcl[7];
-    for (int d = 0; d < NF; d++) {
-        TT uc[NF];
-        for (int k = 0; k < NF; k++) uc[k] = TT(s.row[2][k], d == k ? T(1) : T(0));
-        Src<TT> Sr;
-        sources(K, P.flags, uc, gC, dn, TT(0.0), TT(0.0), Sr);
-        g[6 + d] = gcl[6] * Sr.kappa_s.d;
-    }
+    for (int d = 0; d < NF; d++) g[6 + d] = d < 3 ? gcl[6] * kappa_s(d).d : T(0);
     for (int k = 0; k < NF; k++) {
         GT[k * fs + c] = g[k];
         DU[k * fs + c] = g[k] + g[6 + k];
@@ -326,13 +324,23 @@ __global__ void __launch_bounds__(128) k_adj_post(KParams P, const T* __restrict
     gmu[c] += g[12];
 }
 
+// Partial derivatives of dsg(num, den, md) with respect to num and den (dual
+// evaluations of the same function).
+template <typename T>
+__device__ __forceinline__ void dsg_partials(T num, T den, T md, T& d_num, T& d_den)
+{
+    using TT = Dual<T>;
+    d_num = dsg(TT(num, T(1)), TT(den, T(0)), TT(md, T(0))).d;
+    d_den = dsg(TT(num, T(0)), TT(den, T(1)), TT(md, T(0))).d;
+}
+
 // Which argument the (dual) minmod selects: 0 the first, 1 the second, 2
 // neither (result 0).  Mirrors the selects of minmod on dual numbers.
 template <typename T>
 __device__ __forceinline__ int minmod_pick(T a, T b)
 {
-    const bool pos = (a > T(0)) & (b > T(0));
-    const bool neg = (a < T(0)) & (b < T(0));
+    const bool pos = (int)(a > T(0)) & (int)(b > T(0));
+    const bool neg = (int)(a < T(0)) & (int)(b < T(0));
     if (pos) return a < b ? 0 : 1;
     if (neg) return a > b ? 0 : 1;
     return 2;
@@ -340,23 +348,80 @@ __device__ __forceinline__ int minmod_pick(T a, T b)
 
 // Transpose of one reconstructed side: cotangents of its flux F, conserved
 // values q and phase speeds a pulled back to the side's six conserved values
-// by six dual evaluations of side_flux.
+// (the generic side_flux, reverse sweep written out; the desingularised
+// quotients through dual evaluations of dsg).
 template <typename T>
-__device__ __forceinline__ void side_flux_vjp(const Consts<Dual<T>>& K, const T u[NF], const Geo<Dual<T>>& g, int d,
+__device__ __forceinline__ void side_flux_vjp(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d,
                                               const T lF[NF], const T lq[NF], const T la[2], T lu[NF])
 {
-    using TT = Dual<T>;
-    for (int dir = 0; dir < NF; dir++) {
-        TT ud[NF];
-#pragma unroll
-        for (int k = 0; k < NF; k++) ud[k] = TT(u[k], k == dir ? T(1) : T(0));
-        TT F[NF], q[NF], a[2];
-        side_flux(K, ud, g, d, F, q, a);
-        T acc = la[0] * a[0].d + la[1] * a[1].d;
-#pragma unroll
-        for (int k = 0; k < NF; k++) acc += lF[k] * F[k].d + lq[k] * q[k].d;
-        lu[dir] = acc;
+    // forward values
+    const T ms = u[0], mf = u[3];
+    const T hs = ms / g.J, hf = mf / g.J, h = hs + hf;
+    const T vXs = dsg(u[1], ms, K.md), vYs = dsg(u[2], ms, K.md);
+    const T vXf = dsg(u[4], mf, K.md), vYf = dsg(u[5], mf, K.md);
+    const T Ns = g.c * (T(1) - K.al) * hs / T(2);
+    const T pf = g.c * h / T(2);
+    const T Ax = d == 0 ? g.A11 : g.A21;
+    const T Ay = d == 0 ? g.A12 : g.A22;
+    const T Ann = d == 0 ? g.A11 : g.A22;
+    const T vns = d == 0 ? vXs : vYs;
+    const T vnf = d == 0 ? vXf : vYf;
+    const T eJ = K.eps * g.J;
+    const T cs = K.eps * Ann * g.c * (T(1) - K.al) * (h + hs) / T(2);
+    const T cf = K.eps * Ann * g.c * h;
+    // speeds |v_n| + sqrt(max(c, 0)); sqrt has derivative 0 at 0
+    T vns_b = la[0] * (vns < T(0) ? T(-1) : T(1));
+    T vnf_b = la[1] * (vnf < T(0) ? T(-1) : T(1));
+    const T rs = cs > T(0) ? ::sqrt(cs) : T(0), rf = cf > T(0) ? ::sqrt(cf) : T(0);
+    const T cs_b = rs > T(0) ? la[0] / (T(2) * rs) : T(0);
+    const T cf_b = rf > T(0) ? la[1] / (T(2) * rf) : T(0);
+    const T kcs = K.eps * Ann * g.c * (T(1) - K.al) / T(2);
+    T h_b = cs_b * kcs + cf_b * (K.eps * Ann * g.c);
+    T hs_b = cs_b * kcs;
+    // conserved values q
+    T ms_b = lq[0] + lq[1] * vXs + lq[2] * vYs, mf_b = lq[3] + lq[4] * vXf + lq[5] * vYf;
+    T vXs_b = lq[1] * ms, vYs_b = lq[2] * ms, vXf_b = lq[4] * mf, vYf_b = lq[5] * mf;
+    // advective parts m v_a v_n
+    ms_b += lF[0] * vns + (lF[1] * vXs + lF[2] * vYs) * vns;
+    vns_b += lF[0] * ms + (lF[1] * vXs + lF[2] * vYs) * ms;
+    vXs_b += lF[1] * ms * vns;
+    vYs_b += lF[2] * ms * vns;
+    mf_b += lF[3] * vnf + (lF[4] * vXf + lF[5] * vYf) * vnf;
+    vnf_b += lF[3] * mf + (lF[4] * vXf + lF[5] * vYf) * mf;
+    vXf_b += lF[4] * mf * vnf;
+    vYf_b += lF[5] * mf * vnf;
+    // pressure parts eps J_b h A N^s and eps J_b h A pbar^f
+    const T ws = lF[1] * Ax + lF[2] * Ay, wf = lF[4] * Ax + lF[5] * Ay;
+    h_b += eJ * (ws * Ns + wf * pf);
+    const T Ns_b = eJ * h * ws, pf_b = eJ * h * wf;
+    hs_b += Ns_b * g.c * (T(1) - K.al) / T(2);
+    h_b += pf_b * g.c / T(2);
+    if (d == 0) {
+        vXs_b += vns_b;
+        vXf_b += vnf_b;
+    } else {
+        vYs_b += vns_b;
+        vYf_b += vnf_b;
     }
+    hs_b += h_b;
+    const T hf_b = h_b;
+    ms_b += hs_b / g.J;
+    mf_b += hf_b / g.J;
+    T dn_, dd_;
+    dsg_partials(u[1], ms, K.md, dn_, dd_);
+    lu[1] = vXs_b * dn_;
+    ms_b += vXs_b * dd_;
+    dsg_partials(u[2], ms, K.md, dn_, dd_);
+    lu[2] = vYs_b * dn_;
+    ms_b += vYs_b * dd_;
+    dsg_partials(u[4], mf, K.md, dn_, dd_);
+    lu[4] = vXf_b * dn_;
+    mf_b += vXf_b * dd_;
+    dsg_partials(u[5], mf, K.md, dn_, dd_);
+    lu[5] = vYf_b * dn_;
+    mf_b += vYf_b * dd_;
+    lu[0] = ms_b;
+    lu[3] = mf_b;
 }
 
 // Transpose of the face flux H(w) of face_flux: cotangent gH of H pulled back
@@ -411,8 +476,9 @@ __device__ __forceinline__ void face_flux_vjp(const KParams& P, const T w[4][NF]
         laR[ph] = left ? T(0) : la;
     }
     T luL[NF], luR[NF];
-    side_flux_vjp(K, uL, gaD, d, lF, lqL, laL, luL);
-    side_flux_vjp(K, uR, gbD, d, lF, lqR, laR, luR);
+    const Consts<T> Kb(P);
+    side_flux_vjp(Kb, uL, ga, d, lF, lqL, laL, luL);
+    side_flux_vjp(Kb, uR, gb, d, lF, lqR, laR, luR);
     T lw[4][NF];
 #pragma unroll
     for (int q = 0; q < 4; q++)
@@ -528,6 +594,100 @@ __device__ __forceinline__ void src_slot(int s, int& di, int& dj, int& k)
     k = 3 + f;
 }
 
+// Reverse sweep of the generic sources() at one cell: cotangents L[ph][a] of
+// the momentum sources (the sums sn + sf + sv (+ sd) that enter the update)
+// and Lphif of phi^f pulled back to the cell's six fields (ubar) and to the
+// two fluid-pressure gradients.  Same linear map as dual evaluations of
+// sources() along the eight unit directions, in one pass.
+template <typename T>
+__device__ __forceinline__ void sources_vjp(const Consts<T>& K, int flags, const T u[NF], const Geo<T>& g,
+                                            const T dn[6], T dGx, T dGy, const T L[2][2], T Lphif, T ubar[NF],
+                                            T& dGx_bar, T& dGy_bar)
+{
+    using TT = Dual<T>;
+    // forward values (the arithmetic of the generic sources())
+    const T ms = u[0], mf = u[3];
+    const T hs = ms / g.J, hf = mf / g.J, h = hs + hf;
+    const T mt = ms + mf;
+    const T phis = dsg(ms, mt, K.md), phif = dsg(mf, mt, K.md);
+    const T v00 = dsg(u[1], ms, K.md), v01 = dsg(u[2], ms, K.md);
+    const T v10 = dsg(u[4], mf, K.md), v11 = dsg(u[5], mf, K.md);
+    const T kap0 = kappa_of(v00, v01, g, dn), kap1 = kappa_of(v10, v11, g, dn);
+    const T fs_ = g.c * (T(1) - K.al) - K.eps_chi * kap0, ff_ = g.c - K.eps_chi * kap1;
+    const T pbs = hs * fs_, pbf = hf * ff_;
+    const T gx = g.A11 * dGx + g.A21 * dGy, gy = g.A12 * dGx + g.A22 * dGy;
+    const T wf = (flags & 1) ? phif : phis;
+    const T Kd = g.J * K.c_d * phis * phif * h;
+    const T dv0 = v10 - v00, dv1 = v11 - v01;
+    const T fr = g.J * phif * h * K.theta_b * K.inv_n_r / K.eps;
+    // s_n = J p_b n (horizontal), p_b clamped at 0
+    const T pbs_bar = pbs < T(0) ? T(0) : L[0][0] * g.J * g.nX + L[0][1] * g.J * g.nY;
+    const T pbf_bar = pbf < T(0) ? T(0) : L[1][0] * g.J * g.nX + L[1][1] * g.J * g.nY;
+    T hs_bar = pbs_bar * fs_, hf_bar = pbf_bar * ff_, h_bar = T(0);
+    const T kap0_bar = -(pbs_bar * hs * K.eps_chi), kap1_bar = -(pbf_bar * hf * K.eps_chi);
+    // s_f: -eps alpha phi^s grad G (solid), eps w^f grad G (fluid)
+    T phis_bar = -(K.eps * K.al) * (gx * L[0][0] + gy * L[0][1]);
+    const T wf_bar = K.eps * (gx * L[1][0] + gy * L[1][1]);
+    T phif_bar = Lphif;
+    if (flags & 1)
+        phif_bar += wf_bar;
+    else
+        phis_bar += wf_bar;
+    const T gx_bar = -(K.eps * K.al * phis) * L[0][0] + K.eps * wf * L[1][0];
+    const T gy_bar = -(K.eps * K.al * phis) * L[0][1] + K.eps * wf * L[1][1];
+    dGx_bar = g.A11 * gx_bar + g.A12 * gy_bar;
+    dGy_bar = g.A21 * gx_bar + g.A22 * gy_bar;
+    // s_v: alpha Kd (v^f - v^s) (solid), -Kd (v^f - v^s) (fluid)
+    const T Kd_bar = (K.al * L[0][0] - L[1][0]) * dv0 + (K.al * L[0][1] - L[1][1]) * dv1;
+    const T dv0_bar = (K.al * L[0][0] - L[1][0]) * Kd, dv1_bar = (K.al * L[0][1] - L[1][1]) * Kd;
+    T v00_bar = -dv0_bar, v01_bar = -dv1_bar, v10_bar = dv0_bar, v11_bar = dv1_bar;
+    phis_bar += Kd_bar * g.J * K.c_d * phif * h;
+    phif_bar += Kd_bar * g.J * K.c_d * phis * h;
+    h_bar += Kd_bar * g.J * K.c_d * phis * phif;
+    // s_d^f: -fr v^f
+    const T fr_bar = -(v10 * L[1][0] + v11 * L[1][1]);
+    v10_bar -= fr * L[1][0];
+    v11_bar -= fr * L[1][1];
+    phif_bar += fr_bar * g.J * h * K.theta_b * K.inv_n_r / K.eps;
+    h_bar += fr_bar * g.J * phif * K.theta_b * K.inv_n_r / K.eps;
+    // kappa of each phase through its velocities
+    const Geo<TT> gd = lift(g);
+    TT dnd[6];
+#pragma unroll
+    for (int q = 0; q < 6; q++) dnd[q] = TT(dn[q], T(0));
+    v00_bar += kap0_bar * kappa_of(TT(v00, T(1)), TT(v01, T(0)), gd, dnd).d;
+    v01_bar += kap0_bar * kappa_of(TT(v00, T(0)), TT(v01, T(1)), gd, dnd).d;
+    v10_bar += kap1_bar * kappa_of(TT(v10, T(1)), TT(v11, T(0)), gd, dnd).d;
+    v11_bar += kap1_bar * kappa_of(TT(v10, T(0)), TT(v11, T(1)), gd, dnd).d;
+    // thicknesses and desingularised quotients
+    hs_bar += h_bar;
+    hf_bar += h_bar;
+    T ms_bar = hs_bar / g.J, mf_bar = hf_bar / g.J, mt_bar = T(0);
+    T dn_, dd_;
+    dsg_partials(ms, mt, K.md, dn_, dd_);
+    ms_bar += phis_bar * dn_;
+    mt_bar += phis_bar * dd_;
+    dsg_partials(mf, mt, K.md, dn_, dd_);
+    mf_bar += phif_bar * dn_;
+    mt_bar += phif_bar * dd_;
+    ms_bar += mt_bar;
+    mf_bar += mt_bar;
+    dsg_partials(u[1], ms, K.md, dn_, dd_);
+    ubar[1] = v00_bar * dn_;
+    ms_bar += v00_bar * dd_;
+    dsg_partials(u[2], ms, K.md, dn_, dd_);
+    ubar[2] = v01_bar * dn_;
+    ms_bar += v01_bar * dd_;
+    dsg_partials(u[4], mf, K.md, dn_, dd_);
+    ubar[4] = v10_bar * dn_;
+    mf_bar += v10_bar * dd_;
+    dsg_partials(u[5], mf, K.md, dn_, dd_);
+    ubar[5] = v11_bar * dn_;
+    mf_bar += v11_bar * dd_;
+    ubar[0] = ms_bar;
+    ubar[3] = mf_bar;
+}
+
 // Slot of field k of the box cell (a, c) = (i - 1 + c, j - 1 + a), or -1 if
 // the source does not read that field there (the inverse of src_slot).
 __device__ __forceinline__ int box_slot(int a, int c, int k)
@@ -546,23 +706,43 @@ __device__ __forceinline__ int box_slot(int a, int c, int k)
 
 // Transpose of one viscous face term (visc_xface_c for d = 0, visc_yface_c
 // for d = 1): cotangents (l0, l1) of its two outputs pulled back to its ten
-// scalar inputs (u0, w0, u1, w1, cd u0, cd w0, cd u1, cd w1, Jh0, Jh1).
+// scalar inputs (u0, w0, u1, w1, cd u0, cd w0, cd u1, cd w1, Jh0, Jh1).  The
+// terms are bilinear in the velocity differences and J_b h, so the reverse
+// is written out.
 template <typename T>
-__device__ __forceinline__ void visc_face_vjp(int d, const T in[10], const Geo<Dual<T>>& ga, const Geo<Dual<T>>& gb,
-                                              Dual<T> h, T l0, T l1, T lin[10])
+__device__ __forceinline__ void visc_face_vjp(int d, const T in[10], const Geo<T>& ga, const Geo<T>& gb, T h, T l0,
+                                              T l1, T lin[10])
 {
-    using TT = Dual<T>;
-    for (int dir = 0; dir < 10; dir++) {
-        TT x[10];
-#pragma unroll
-        for (int q = 0; q < 10; q++) x[q] = TT(in[q], q == dir ? T(1) : T(0));
-        TT o0, o1;
-        if (d == 0)
-            visc_xface_c(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], x[8], x[9], ga, gb, h, o0, o1);
-        else
-            visc_yface_c(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], x[8], x[9], ga, gb, h, o0, o1);
-        lin[dir] = l0 * o0.d + l1 * o1.d;
+    const T A11 = T(0.5) * (ga.A11 + gb.A11), A12 = T(0.5) * (ga.A12 + gb.A12);
+    const T A21 = T(0.5) * (ga.A21 + gb.A21), A22 = T(0.5) * (ga.A22 + gb.A22);
+    const T Jh = T(0.5) * (in[8] + in[9]);
+    const T nu = (in[2] - in[0]) / h, nw = (in[3] - in[1]) / h;      // normal differences
+    const T tu = T(0.5) * (in[4] + in[6]), tw = T(0.5) * (in[5] + in[7]);  // tangential (mean central)
+    T nu_b, nw_b, tu_b, tw_b, Jh_b;
+    if (d == 0) {
+        // FX = 2 Jh (A11 u_x + A21 u_y), FY = Jh (A12 u_x + A22 u_y + A11 w_x + A21 w_y)
+        const T PX = A11 * nu + A21 * tu, PY = A12 * nu + A22 * tu + A11 * nw + A21 * tw;
+        Jh_b = l0 * T(2) * PX + l1 * PY;
+        nu_b = l0 * T(2) * Jh * A11 + l1 * Jh * A12;
+        tu_b = l0 * T(2) * Jh * A21 + l1 * Jh * A22;
+        nw_b = l1 * Jh * A11;
+        tw_b = l1 * Jh * A21;
+    } else {
+        // GX = Jh (A12 u_x + A22 u_y + A11 w_x + A21 w_y), GY = 2 Jh (A12 w_x + A22 w_y)
+        const T QX = A12 * tu + A22 * nu + A11 * tw + A21 * nw, QY = A12 * tw + A22 * nw;
+        Jh_b = l0 * QX + l1 * T(2) * QY;
+        tu_b = l0 * Jh * A12;
+        nu_b = l0 * Jh * A22;
+        tw_b = l0 * Jh * A11 + l1 * T(2) * Jh * A12;
+        nw_b = l0 * Jh * A21 + l1 * T(2) * Jh * A22;
     }
+    lin[0] = -nu_b / h;
+    lin[2] = nu_b / h;
+    lin[1] = -nw_b / h;
+    lin[3] = nw_b / h;
+    lin[4] = lin[6] = T(0.5) * tu_b;
+    lin[5] = lin[7] = T(0.5) * tw_b;
+    lin[8] = lin[9] = T(0.5) * Jh_b;
 }
 
 // Pass B, sources: cotangent dt * GT_c (momentum components) pulled back
@@ -588,7 +768,7 @@ __global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict_
     for (int k = 0; k < NF; k++) gS[k] = dt * GT[k * fs + c];
     using TT = Dual<T>;
     const Consts<TT> K(P);
-    const Geo<TT> gC = lift(g5.C), gW = lift(g5.W), gE = lift(g5.E), gSo = lift(g5.S), gN = lift(g5.N);
+    const Geo<TT> gW = lift(g5.W), gE = lift(g5.E), gSo = lift(g5.S), gN = lift(g5.N);
     T lam[34];
     for (int q = 0; q < 34; q++) lam[q] = T(0);
     const T two_dxi = T(P.two_dxi), two_deta = T(P.two_deta);
@@ -639,32 +819,20 @@ __global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict_
         SvY = (FY1 - FY0) / Kb.dxi + (GY1 - GY0) / Kb.deta;
     }
 
-    // (1) local sources: the cell's six fields and the two gradients
+    // (1) local sources: the cell's six fields and the two gradients, by the
+    // reverse sweep of sources() (the viscous prefactor eps phi^f / N_R enters
+    // through phi^f)
     T lGx = T(0), lGy = T(0);
-    for (int dir = 0; dir < 8; dir++) {
-        TT uc[NF];
-        for (int k = 0; k < NF; k++) uc[k] = TT(s.row[2][k], dir == k ? T(1) : T(0));
-        Src<TT> Sr;
-        sources(K, P.flags, uc, gC, dn, TT(dGx, dir == 6 ? T(1) : T(0)), TT(dGy, dir == 7 ? T(1) : T(0)), Sr);
-        T acc = T(0);
-        for (int ph = 0; ph < 2; ph++)
-            for (int a = 0; a < 2; a++) {
-                TT v = Sr.sn[ph][a];
-                v += Sr.sf[ph][a];
-                v += Sr.sv[ph][a];
-                if (ph == 1) v += Sr.sd[a];
-                acc += gS[3 * ph + 1 + a] * v.d;
-            }
-        if (P.visc) {
-            acc += gS[4] * (K.eps * Sr.phif * K.inv_n_r * TT(SvX, T(0))).d;
-            acc += gS[5] * (K.eps * Sr.phif * K.inv_n_r * TT(SvY, T(0))).d;
-        }
-        if (dir < 6)
-            lam[dir] += acc;
-        else if (dir == 6)
-            lGx = acc;
-        else
-            lGy = acc;
+    {
+        const Consts<T> Kl(P);
+        T L[2][2] = {{gS[1], gS[2]}, {gS[4], gS[5]}};
+        T Lphif = T(0);
+        if (P.visc) Lphif = Kl.eps * Kl.inv_n_r * (gS[4] * SvX + gS[5] * SvY);
+        T dn_b[6];
+        for (int q = 0; q < 6; q++) dn_b[q] = dn[q].v;
+        T ub[NF];
+        sources_vjp(Kl, P.flags, s.row[2], g5.C, dn_b, dGx, dGy, L, Lphif, ub, lGx, lGy);
+        for (int k = 0; k < NF; k++) lam[k] += ub[k];
     }
     // (2) gradients of J_b h pbar^f to the neighbours' m^s, m^f
     {
@@ -701,7 +869,8 @@ __global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict_
             in[8] = f == 0 ? Jh[1] : Jh[0];
             in[9] = f == 0 ? Jh[0] : Jh[2];
             const T sg = f == 0 ? T(-1) : T(1);
-            visc_face_vjp(0, in, f == 0 ? gW : gC, f == 0 ? gC : gE, K.dxi, sg * lX / Kb.dxi, sg * lY / Kb.dxi, lin);
+            visc_face_vjp(0, in, f == 0 ? g5.W : g5.C, f == 0 ? g5.C : g5.E, Kb.dxi, sg * lX / Kb.dxi,
+                          sg * lY / Kb.dxi, lin);
             lu9[1][c0] += lin[0];
             lw9[1][c0] += lin[1];
             lu9[1][c1] += lin[2];
@@ -727,8 +896,8 @@ __global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict_
             in[8] = f == 0 ? Jh[3] : Jh[0];
             in[9] = f == 0 ? Jh[0] : Jh[4];
             const T sg = f == 0 ? T(-1) : T(1);
-            visc_face_vjp(1, in, f == 0 ? gSo : gC, f == 0 ? gC : gN, K.deta, sg * lX / Kb.deta, sg * lY / Kb.deta,
-                          lin);
+            visc_face_vjp(1, in, f == 0 ? g5.S : g5.C, f == 0 ? g5.C : g5.N, Kb.deta, sg * lX / Kb.deta,
+                          sg * lY / Kb.deta, lin);
             lu9[a0][1] += lin[0];
             lw9[a0][1] += lin[1];
             lu9[a1][1] += lin[2];
@@ -788,6 +957,40 @@ __global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restri
     const size_t c = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
     T acc[NF];
     for (int k = 0; k < NF; k++) acc[k] = DU[k * fs + c];
+    if (i >= 2 && i <= P.nx - 3 && j >= 2 && j <= P.ny - 3) {
+        // No ghost cell maps onto this cell: each contribution comes from a
+        // fixed (face or cell, slot), taken in the order of the general path.
+        for (int fi = i - 2; fi <= i + 1; fi++) {
+            const T* f = FCX + ((size_t)j * (P.nx + 1) + (fi + 1)) * 24 + 6 * (i - fi + 1);
+            for (int k = 0; k < NF; k++) acc[k] += f[k];
+        }
+        for (int fj = j - 2; fj <= j + 1; fj++) {
+            const T* f = FCY + ((size_t)(fj + 1) * P.nx + i) * 24 + 6 * (j - fj + 1);
+            for (int k = 0; k < NF; k++) acc[k] += f[k];
+        }
+        // source cell (i - di, j - dj) reads this cell through its slots of offset (di, dj)
+        for (int cj = j - 1; cj <= j + 1; cj++)
+            for (int ci = i - 1; ci <= i + 1; ci++) {
+                const T* f = SC + ((size_t)cj * P.nx + ci) * 34;
+                const int di = i - ci, dj = j - cj;
+                if (di == 0 && dj == 0) {
+                    for (int k = 0; k < NF; k++) acc[k] += f[k];
+                } else if (di == 0 || dj == 0) {
+                    const int n = dj == 0 ? (di > 0 ? 0 : 1) : (dj > 0 ? 2 : 3);
+                    acc[0] += f[6 + 4 * n];
+                    acc[3] += f[6 + 4 * n + 1];
+                    acc[4] += f[6 + 4 * n + 2];
+                    acc[5] += f[6 + 4 * n + 3];
+                } else {
+                    const int n = (dj > 0 ? 0 : 2) + (di > 0 ? 0 : 1);
+                    acc[3] += f[22 + 3 * n];
+                    acc[4] += f[22 + 3 * n + 1];
+                    acc[5] += f[22 + 3 * n + 2];
+                }
+            }
+        for (int k = 0; k < NF; k++) lam_in[k * fs + c] = acc[k];
+        return;
+    }
     // x-faces of row j: face index t = fi + 1, fi in [-1, nx-1], stencil cells fi-1 .. fi+2
     for (int fi = i - 3; fi <= i + 2; fi++) {
         if (fi < -1 || fi > P.nx - 1) continue;

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
 #include <type_traits>
 
 // Host-and-device so that the arithmetic can also be evaluated on the host
@@ -69,8 +70,8 @@ M2P_FN T minmod(T a, T b)
     if constexpr (std::is_same<T, float>::value) return __builtin_amdgcn_fmed3f(a, b, 0.0f);
 #endif
     const T lo = a < b ? a : b, hi = a > b ? a : b;
-    const bool pos = (a > T(0)) & (b > T(0));
-    const bool neg = (a < T(0)) & (b < T(0));
+    const bool pos = (int)(a > T(0)) & (int)(b > T(0));
+    const bool neg = (int)(a < T(0)) & (int)(b < T(0));
     return pos ? lo : (neg ? hi : T(0));
 }
 
@@ -84,6 +85,31 @@ M2P_FN T dsg(T num, T den, T md)
     return (T(2) * den * num) / (d2 + (d2 > m2 ? d2 : m2));
 }
 
+// The FP32 build evaluates some formulas in algebraically folded forms with
+// fewer operations: J_b c = 1 (c = 1/J_b, R1), so h^s = m^s c and
+// eps J_b h A N^s = eps (1 - alpha)/2 h h^s A; products of constants are
+// folded.  The FP64 build (bitwise parity with the FP64 oracle) and the
+// dual-number adjoint evaluate the formulas as written.
+template <typename T>
+struct Folded : std::false_type {};
+template <>
+struct Folded<float> : std::true_type {};
+
+// 1 / sqrt(x): one hardware reciprocal square root in FP32 device code.
+template <typename T>
+M2P_FN T rsq(T x)
+{
+    return T(1) / sqrt(x);
+}
+M2P_FN float rsq(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rsqf(x);
+#else
+    return 1.0f / std::sqrt(x);
+#endif
+}
+
 // Basal geometry from the four DEM neighbours (b / L): tangents
 // (1, 0, b_X), (0, 1, b_Y), unit normal (-b_X, -b_Y, 1)/s, J_b = s, c = n_Z,
 // A = inverse surface metric.
@@ -93,6 +119,22 @@ M2P_FN Geo<T> geometry(T bE, T bW, T bN, T bS, T two_dxi, T two_deta)
     Geo<T> g;
     T bX = (bE - bW) / two_dxi;
     T bY = (bN - bS) / two_deta;
+    if constexpr (Folded<T>::value) {
+        const T q = T(1) + bX * bX + bY * bY;
+        const T c = rsq(q), c2 = c * c;
+        g.bX = bX;
+        g.bY = bY;
+        g.J = q * c;
+        g.c = c;
+        g.nX = -bX * c;
+        g.nY = -bY * c;
+        g.nZ = c;
+        g.A11 = (T(1) + bY * bY) * c2;
+        g.A12 = -bX * bY * c2;
+        g.A21 = g.A12;
+        g.A22 = (T(1) + bX * bX) * c2;
+        return g;
+    }
     T s = sqrt(T(1) + bX * bX + bY * bY);
     g.bX = bX;
     g.bY = bY;
@@ -123,15 +165,6 @@ struct Consts {
           m_eps_al(T(-P.eps * P.alpha)), k_fr(T(P.theta_b * P.inv_n_r / P.eps)) {}
 };
 
-// The FP32 build evaluates some formulas in algebraically folded forms with
-// fewer operations: J_b c = 1 (c = 1/J_b, R1), so h^s = m^s c and
-// eps J_b h A N^s = eps (1 - alpha)/2 h h^s A; products of constants are
-// folded.  The FP64 build (bitwise parity with the FP64 oracle) and the
-// dual-number adjoint evaluate the formulas as written.
-template <typename T>
-struct Folded : std::false_type {};
-template <>
-struct Folded<float> : std::true_type {};
 
 // Physical flux of one reconstructed side of a face (flux vectors F, G of
 // Appendix A with the owner cell's geometry), the conserved values entering
@@ -314,6 +347,21 @@ M2P_FN T fluid_G(T ms, T mf, const Geo<T>& g)
 // dn: dn/dxi (3) then dn/deta (3).  dGx, dGy: central differences of fluid_G.
 // Out: S[ph][a] accumulated in the order s_n, s_f, s_v, s_d (fluid only);
 // kappa_s for the friction clamp; phif for the viscous prefactor.
+// Centripetal term kappa = v_a (dn_a/dxi v_xi + dn_a/deta v_eta) of one phase
+// from its velocities (v_xi, v_eta; v_Z by tangency) and the normal's
+// derivatives dn (dn/dxi then dn/deta).
+template <typename T>
+M2P_FN T kappa_of(T v0, T v1, const Geo<T>& g, const T dn[6])
+{
+    const T v[3] = {v0, v1, g.bX * v0 + g.bY * v1};
+    T k = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; a++) k += v[a] * dn[a] * v0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) k += v[a] * dn[3 + a] * v1;
+    return k;
+}
+
 template <typename T>
 struct Src {
     T sn[2][2], sf[2][2], sv[2][2], sd[2];
@@ -377,23 +425,14 @@ M2P_FN void sources(const Consts<T>& K, int flags, const T u[NF], const Geo<T>& 
     T hs = ms / g.J, hf = mf / g.J, h = hs + hf;
     T mt = ms + mf;
     T phis = dsg(ms, mt, K.md), phif = dsg(mf, mt, K.md);
-    T v[2][3];
+    T v[2][2];
     v[0][0] = dsg(u[1], ms, K.md);
     v[0][1] = dsg(u[2], ms, K.md);
     v[1][0] = dsg(u[4], mf, K.md);
     v[1][1] = dsg(u[5], mf, K.md);
-#pragma unroll
-    for (int ph = 0; ph < 2; ph++) v[ph][2] = g.bX * v[ph][0] + g.bY * v[ph][1];
     T kap[2];
 #pragma unroll
-    for (int ph = 0; ph < 2; ph++) {
-        T k = T(0);
-#pragma unroll
-        for (int a = 0; a < 3; a++) k += v[ph][a] * dn[a] * v[ph][0];
-#pragma unroll
-        for (int a = 0; a < 3; a++) k += v[ph][a] * dn[3 + a] * v[ph][1];
-        kap[ph] = k;
-    }
+    for (int ph = 0; ph < 2; ph++) kap[ph] = kappa_of(v[ph][0], v[ph][1], g, dn);
     T pbs = hs * (g.c * (T(1) - K.al) - K.eps_chi * kap[0]);
     T pbf = hf * (g.c - K.eps_chi * kap[1]);
     if (pbs < T(0)) pbs = T(0);
@@ -470,13 +509,26 @@ M2P_FN int clamp_cell(const Consts<T>& K, const Geo<T>& g, T kappa_s, T dt, T tm
     }
     T pX = out[1], pY = out[2];
     T pZ = g.bX * pX + g.bY * pY;
-    T p3 = sqrt(pX * pX + pY * pY + pZ * pZ);
-    if (p3 <= F) {
-        out[1] = T(0);
-        out[2] = T(0);
+    if constexpr (Folded<T>::value) {
+        // |p_3| <= F  <=>  |p_3|^2 <= F^2 (F >= 0)
+        const T p2 = pX * pX + pY * pY + pZ * pZ;
+        if (p2 <= F * F) {
+            out[1] = T(0);
+            out[2] = T(0);
+        } else {
+            const T r = T(1) - F * rsq(p2);
+            out[1] = pX * r;
+            out[2] = pY * r;
+        }
     } else {
-        out[1] = pX * (T(1) - F / p3);
-        out[2] = pY * (T(1) - F / p3);
+        T p3 = sqrt(pX * pX + pY * pY + pZ * pZ);
+        if (p3 <= F) {
+            out[1] = T(0);
+            out[2] = T(0);
+        } else {
+            out[1] = pX * (T(1) - F / p3);
+            out[2] = pY * (T(1) - F / p3);
+        }
     }
     int clamps = 0;
 #pragma unroll

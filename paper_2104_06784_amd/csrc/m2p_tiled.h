@@ -154,7 +154,7 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
     RowD<T> Dm, D0;  // rows j-1, j
     make_row(K, Um1, bm1, bm2, b0, Dm);
     make_row(K, U0, b0, bm1, b1, D0);
-    T sy0[NF], sy1[NF];  // y-slopes of rows j and j+1
+    T sy0[NF];  // y-slopes of row r0
     T Hy[NF];            // y-face flux j - 1/2
     {
         T sym[NF], uL[NF], uR[NF];

@@ -114,6 +114,10 @@ class Sim:
         A.check(A.lib().m2p_run_to(self._h, float(t_end), int(max_steps), C.byref(n)), "m2p_run_to")
         return n.value
 
+    def set_graph(self, chunk: int):
+        """Steps per replayed HIP graph (0: kernel-by-kernel launches)."""
+        A.check(A.lib().m2p_set_graph(self._h, int(chunk)), "m2p_set_graph")
+
     def run_outputs(self, times, max_steps: int = 10 ** 9):
         """Run through the output times (s); returns ([n, 6, ny, nx] fields
         h, phi_s, vxs, vys, vxf, vyf at each time, steps taken).  Snapshots

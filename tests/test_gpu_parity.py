@@ -209,6 +209,30 @@ def test_run_outputs_equals_run_to_and_get_fields(precision):
     assert na == nb and a.diag()["t"] == times[-1]
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_graph_replay_equals_direct_launches(precision):
+    """Steps replayed from HIP graphs (chunks of 7 on a stream of the
+    context's own) equal kernel-by-kernel launches bitwise, through run,
+    run_to and a change of the inflow segments (which forces a recapture);
+    replays interleave with eager work and host reads."""
+    import torch
+    prob = _state_inflow_problem()
+    res = []
+    for chunk in (7, 0):
+        st = torch.cuda.Stream()
+        g = Sim(prob, precision=precision, stream=st)
+        g.set_graph(chunk)
+        g.run(23)
+        a = g.state()
+        g.run_to(6.0)
+        b = g.state()
+        g.set_inflow_states(prob.inflow_states[:2])
+        g.run(30)
+        res.append((a, b, g.state(), g.diag()["steps"]))
+    for x, y in zip(res[0], res[1]):
+        assert np.array_equal(x, y)
+
+
 def test_vertical_and_normal_thickness_inputs_agree():
     prob = I.config1(n=32)
     a = Sim(prob, precision="f64")
@@ -254,6 +278,31 @@ def test_fp32_against_fp64_oracle_mode2():
     # the paper's deposit metric: cells above 1 cm that disagree
     mism = np.sum((hg > 0.01) != (ho > 0.01))
     assert mism <= 0.0017 * max(1, np.sum(ho > 0.01))
+
+
+def test_fp32_config2_full_size_5000_steps():
+    """Config 2 at its full size (1024^2, Mode-II hydrograph) for 5000 steps:
+    the FP32 path against the FP64 path (itself within 1e-12 of the oracle in
+    the tests above; the oracle would need minutes here) at the same model
+    time: relative L1 thickness error <= 1e-3, each path's volume budget
+    closes to 1e-6, and the deposit metric of the paper."""
+    prob = I.config2()
+    _say(f"[fp32] cfg2 {prob.nx}^2, 5000 FP64 steps, FP32 to the same time")
+    d64 = Sim(prob, precision="f64")
+    d64.run(5000)
+    t_end = d64.diag()["t"]
+    g = Sim(prob, precision="f32")
+    g.run_to(t_end)
+    hg, h64 = g.fields()["h"], d64.fields()["h"]
+    l1 = np.abs(hg - h64).sum() / h64.sum()
+    res = [l1]
+    for s in (g, d64):
+        d = s.diag()
+        vol = d["mass_s"] + d["mass_f"]
+        res.append(abs(vol - (d["in_s"] + d["in_f"] - d["out_s"] - d["out_f"])) / vol)
+    mism = np.sum((hg > 0.01) != (h64 > 0.01)) / max(1, np.sum(h64 > 0.01))
+    _say(f"   t {t_end:.1f} s  L1 rel {l1:.3e}  budget FP32 {res[1]:.3e} FP64 {res[2]:.3e}  deposit mismatch {mism:.4f}")
+    assert l1 <= 1e-3 and res[1] <= 1e-6 and res[2] <= 1e-6 and mism <= 0.0017
 
 
 def test_fp32_config1_close_to_fp64():
