@@ -61,6 +61,10 @@ extern "C" {
 
 /* m2p_params.flags */
 #define M2P_F_FLUID_PRESSURE_AS_PRINTED 1 /* weight the fluid interphase pressure by phi^f as printed */
+#define M2P_F_RK3 2 /* three-stage third-order SSP Runge-Kutta instead of the paper's two-step modified Euler
+                       (Heun): U1 = E(U^n), U2 = 3/4 U^n + 1/4 E(U1), U^{n+1} = 1/3 U^n + 2/3 E(U2) at stage
+                       times t, t + dt, t + dt/2 (Sect. 2.2 names multi-step Runge-Kutta methods as the family);
+                       single-scenario contexts only, not with the adjoint */
 
 /* thickness convention of m2p_set_state */
 #define M2P_DEPTH_NORMAL 0   /* h measured normal to the bed (the paper's h, Sect. 2.1) */

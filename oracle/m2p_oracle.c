@@ -38,7 +38,8 @@ typedef struct {
     double delta_b_deg, c_d, inv_n_r, theta_b, rho_s, rho_f, cfl;
     double L, H, chi, g, m_dry, a_min;
     int32_t bc[4]; /* W, E, S, N: 0 transmissive, 1 closed wall */
-    int32_t flags; /* bit 0: fluid interphase pressure weighted by phi^f as printed */
+    int32_t flags; /* bit 0: fluid interphase pressure weighted by phi^f as printed;
+                      bit 1: three-stage third-order SSP Runge-Kutta instead of Heun */
 } ora_params;
 
 typedef struct {
@@ -92,7 +93,7 @@ typedef struct {
     double t;
     int64_t steps, clamps;
     double in_s, in_f, out_s, out_f;
-    double bflux[2][2]; /* per stage, per phase: net outward boundary mass flux rate */
+    double bflux[3][2]; /* per stage, per phase: net outward boundary mass flux rate */
     double last_dt;
     double *dt_sched;   /* optional prescribed time steps (dimensionless) */
     int64_t n_sched;
@@ -896,21 +897,41 @@ static double next_dt(const ora_sim *o, double t_end_nd)
 
 /* ----------------------------------------------------------------- step */
 
-/* One step of the two-step modified Euler method (Heun / SSP-RK2):
- * U* = E(U^n), U** = E(U*), U^{n+1} = (U^n + U**) / 2.  Returns dt in s. */
+/* One step of the two-step modified Euler method (Heun / SSP-RK2, the
+ * paper's choice, Sect. 2.2): U* = E(U^n), U** = E(U*),
+ * U^{n+1} = (U^n + U**) / 2.  With flags bit 1, the three-stage SSP
+ * Runge-Kutta method of the same family (the "multi-step RK" the paper
+ * names as an option): U1 = E(U^n), U2 = 3/4 U^n + 1/4 E(U1),
+ * U^{n+1} = 1/3 U^n + 2/3 E(U2), stage times t, t + dt, t + dt/2 and
+ * quadrature weights 1/6, 1/6, 2/3 for the boundary integrals.  Returns dt
+ * in s. */
 double ora_step(ora_sim *o, double t_end_si)
 {
     size_t nc = (size_t)o->nx * o->ny;
     double t_end = t_end_si / o->T;
     double dt = next_dt(o, t_end);
     if (dt <= 0.0) return 0.0;
+    const int rk3 = (o->p.flags & 2) != 0;
     stage(o, o->U, o->Us, dt, o->t, 0);
     stage(o, o->Us, o->Uss, dt, o->t + dt, 1);
-    for (size_t k = 0; k < NF * nc; k++) o->U[k] = 0.5 * (o->U[k] + o->Uss[k]);
+    if (rk3) {
+        for (size_t k = 0; k < NF * nc; k++) o->Us[k] = 0.75 * o->U[k] + 0.25 * o->Uss[k];
+        stage(o, o->Us, o->Uss, dt, o->t + 0.5 * dt, 2);
+        for (size_t k = 0; k < NF * nc; k++) o->U[k] = (1.0 / 3.0) * o->U[k] + (2.0 / 3.0) * o->Uss[k];
+    } else {
+        for (size_t k = 0; k < NF * nc; k++) o->U[k] = 0.5 * (o->U[k] + o->Uss[k]);
+    }
     double scale = o->p.H * o->p.L * o->p.L; /* dimensionless volume -> m^3 */
     for (int ph = 0; ph < 2; ph++) {
-        double out = 0.5 * dt * (o->bflux[0][ph] + o->bflux[1][ph]);
-        double in = 0.5 * dt * (inflow_rate(o, o->t, ph) + inflow_rate(o, o->t + dt, ph));
+        double out, in;
+        if (rk3) {
+            out = dt * (o->bflux[0][ph] / 6.0 + o->bflux[1][ph] / 6.0 + 2.0 * o->bflux[2][ph] / 3.0);
+            in = dt * (inflow_rate(o, o->t, ph) / 6.0 + inflow_rate(o, o->t + dt, ph) / 6.0 +
+                       2.0 * inflow_rate(o, o->t + 0.5 * dt, ph) / 3.0);
+        } else {
+            out = 0.5 * dt * (o->bflux[0][ph] + o->bflux[1][ph]);
+            in = 0.5 * dt * (inflow_rate(o, o->t, ph) + inflow_rate(o, o->t + dt, ph));
+        }
         if (ph == 0) { o->out_s += out * scale; o->in_s += in * scale; }
         else { o->out_f += out * scale; o->in_f += in * scale; }
     }

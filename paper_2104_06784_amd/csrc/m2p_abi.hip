@@ -94,25 +94,28 @@ static hipError_t step_part(m2p_ctx* c, int part)
     return Launch<float>::step_part(c->kp, c->B, c->shape, c->stream, part);
 }
 
+// One step: the rk stage kernels, then the finalize (parts 0 .. rk).  With
+// profiling, an event around every part (rk + 2 events per step).
 static hipError_t do_step(m2p_ctx* c)
 {
+    const int np = c->kp.rk + 1;
     if (!c->prof) {
-        for (int part = 0; part < 3; part++) {
+        for (int part = 0; part < np; part++) {
             hipError_t e = step_part(c, part);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     }
-    while (c->ev.size() < c->ev_used + 4) {
+    while (c->ev.size() < c->ev_used + np + 1) {
         hipEvent_t e;
         hipError_t r = hipEventCreate(&e);
         if (r != hipSuccess) return r;
         c->ev.push_back(e);
     }
     hipEvent_t* e = &c->ev[c->ev_used];
-    c->ev_used += 4;
+    c->ev_used += np + 1;
     hipError_t r = hipEventRecord(e[0], c->stream);
-    for (int part = 0; part < 3 && r == hipSuccess; part++) {
+    for (int part = 0; part < np && r == hipSuccess; part++) {
         r = step_part(c, part);
         if (r == hipSuccess) r = hipEventRecord(e[part + 1], c->stream);
     }
@@ -211,6 +214,7 @@ KParams make_kparams(const m2p_grid* g, const m2p_params* p, bool has_mu)
     K.bpitch = (int)(BOFF + round_up((size_t)g->nx + BHALO, 64));
     for (int s = 0; s < 4; s++) K.bc[s] = p->bc[s];
     K.flags = p->flags;
+    K.rk = (p->flags & M2P_F_RK3) ? 3 : 2;
     K.has_mu = has_mu ? 1 : 0;
     K.visc = p->inv_n_r != 0.0 ? 1 : 0;
     K.eps = p->H / p->L;
@@ -282,6 +286,7 @@ int validate_scenario(const m2p_grid* g, const m2p_params* p, int32_t prec, cons
         return fail(M2P_EINVAL, "c_d, 1/N_R, theta_b >= 0 and m_dry, a_min > 0 required");
     for (int s = 0; s < 4; s++)
         if (p->bc[s] != M2P_BC_TRANSMISSIVE && p->bc[s] != M2P_BC_WALL) return fail(M2P_EINVAL, "bad boundary mode");
+    if (p->flags & ~(M2P_F_FLUID_PRESSURE_AS_PRINTED | M2P_F_RK3)) return fail(M2P_EINVAL, "unknown flag");
     size_t n = (size_t)g->nx * g->ny;
     for (size_t k = 0; k < n; k++)
         if (!std::isfinite(dem[k])) return fail(M2P_EINVAL, "non-finite DEM value");
@@ -400,12 +405,12 @@ int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t pr
         const size_t nw = std::max((size_t)nbx * nby, (size_t)nstrips * nrb);
         c->B.nmax = nmax;
         c->B.nw_ref = nbx * nby;
-        if (hipMalloc(&c->bpart, sizeof(double) * 2 * 4 * 2 * (size_t)nmax) != hipSuccess)
+        if (hipMalloc(&c->bpart, sizeof(double) * 3 * 4 * 2 * (size_t)nmax) != hipSuccess)
             return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
-        (void)hipMemset(c->bpart, 0, sizeof(double) * 2 * 4 * 2 * (size_t)nmax);
-        if (hipMalloc(&c->wpart, sizeof(double) * 2 * 4 * nw) != hipSuccess)
+        (void)hipMemset(c->bpart, 0, sizeof(double) * 3 * 4 * 2 * (size_t)nmax);
+        if (hipMalloc(&c->wpart, sizeof(double) * 3 * 4 * nw) != hipSuccess)
             return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
-        (void)hipMemset(c->wpart, 0, sizeof(double) * 2 * 4 * nw);
+        (void)hipMemset(c->wpart, 0, sizeof(double) * 3 * 4 * nw);
     }
     if (hipMalloc(&c->mass_part, sizeof(double) * 2 * kMassBlocks) != hipSuccess)
         return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
@@ -436,6 +441,7 @@ void m2p_destroy(m2p_ctx* c)
         if (c->B.U) (void)hipFree(c->B.U);
         if (c->B.Us) (void)hipFree(c->B.Us);
     }
+    if (c->B.Us2) (void)hipFree(c->B.Us2);
     if (c->b) (void)hipFree(c->b);
     if (c->mu) (void)hipFree(c->mu);
     if (c->S) (void)hipFree(c->S);
@@ -457,6 +463,15 @@ void m2p_destroy(m2p_ctx* c)
     delete c;
 }
 
+// The three-stage method's second stage state, always owned by the context.
+static int ensure_stage_buffer(m2p_ctx* c)
+{
+    if (c->kp.rk != 3 || c->B.Us2) return M2P_OK;
+    if (hipMalloc(&c->B.Us2, c->state_bytes) != hipSuccess) return fail(M2P_ENOMEM, "state allocation failed");
+    HIPCHK(hipMemsetAsync(c->B.Us2, 0, c->state_bytes, c->stream));
+    return M2P_OK;
+}
+
 int m2p_bind_buffers(m2p_ctx* c, void* a, void* b, size_t bytes)
 {
     if (!c || !a || !b) return fail(M2P_EINVAL, "NULL argument");
@@ -468,7 +483,7 @@ int m2p_bind_buffers(m2p_ctx* c, void* a, void* b, size_t bytes)
     c->own_state = false;
     HIPCHK(hipMemsetAsync(a, 0, c->state_bytes, c->stream));
     HIPCHK(hipMemsetAsync(b, 0, c->state_bytes, c->stream));
-    return M2P_OK;
+    return ensure_stage_buffer(c);
 }
 
 static int ensure_state_buffers(m2p_ctx* c)
@@ -479,7 +494,7 @@ static int ensure_state_buffers(m2p_ctx* c)
     c->own_state = true;
     HIPCHK(hipMemsetAsync(c->B.U, 0, c->state_bytes, c->stream));
     HIPCHK(hipMemsetAsync(c->B.Us, 0, c->state_bytes, c->stream));
-    return M2P_OK;
+    return ensure_stage_buffer(c);
 }
 
 int m2p_set_state(m2p_ctx* c, int32_t kind, const double* h, const double* phi, const double* vxs, const double* vys,
@@ -971,11 +986,13 @@ int m2p_kernel_times(m2p_ctx* c, double* ms, int64_t* nsteps)
 {
     if (!c || !ms || !nsteps) return fail(M2P_EINVAL, "NULL argument");
     HIPCHK(hipStreamSynchronize(c->stream));
-    for (size_t g = 0; g + 4 <= c->ev_used; g += 4) {
-        for (int part = 0; part < 3; part++) {
+    const int np = c->kp.rk + 1;
+    for (size_t g = 0; g + np + 1 <= c->ev_used; g += np + 1) {
+        for (int part = 0; part < np; part++) {
             float t = 0.0f;
             HIPCHK(hipEventElapsedTime(&t, c->ev[g + part], c->ev[g + part + 1]));
-            c->prof_ms[part] += t;
+            // first stage, the other stages, finalize
+            c->prof_ms[part == 0 ? 0 : (part == np - 1 ? 2 : 1)] += t;
         }
         c->prof_n++;
     }
@@ -1123,6 +1140,7 @@ int inflow_unsupported(m2p_ctx* c)
 {
     if (c->kp.nseg > 0 || c->kp.nsseg > 0)
         return m2p::fail(M2P_EINVAL, "the adjoint supports Mode-I (no inflow segments)");
+    if (c->kp.rk != 2) return m2p::fail(M2P_EINVAL, "the adjoint differentiates the two-step (Heun) method");
     return M2P_OK;
 }
 

@@ -515,7 +515,7 @@ __device__ __forceinline__ void face_flux_vjp(const KParams& P, const T w[4][NF]
 
 // Pass B, faces: x-faces (d = 0) for i in [-1, nx-1] (face between i and i+1)
 // or y-faces (d = 1) for j in [-1, ny-1]; 24 stencil cotangents per face into
-// FC[face][24] (slot = 6 * cell + field, cells a-1 .. a+2).
+// FC[24][faces] (slot-major; slot = 6 * cell + field, cells a-1 .. a+2).
 template <typename T>
 __global__ void __launch_bounds__(128) k_adj_face(KParams P, const T* __restrict__ U, const T* __restrict__ GT,
                                                   const T* __restrict__ b, int d, T dt, T* __restrict__ FC)
@@ -533,7 +533,9 @@ __global__ void __launch_bounds__(128) k_adj_face(KParams P, const T* __restrict
         j = line - 1;
     }
     const size_t fidx = (size_t)line * nf_along + t;
-    T* out = FC + fidx * 24;
+    // slot-major: slot q of all faces of this direction is contiguous
+    const size_t nfaces = (size_t)nf_along * gridDim.y;
+    T out[24];
     const size_t fs = (size_t)P.ny * P.pitch;
     // inflow faces carry a prescribed flux: no dependence on the state
     bool fixed = false;
@@ -542,7 +544,7 @@ __global__ void __launch_bounds__(128) k_adj_face(KParams P, const T* __restrict
     if (d == 1 && j == -1) fixed = inflow_seg_at(P, 2, i) >= 0;
     if (d == 1 && j == P.ny - 1) fixed = fixed || inflow_seg_at(P, 3, i) >= 0;
     if (fixed) {
-        for (int q = 0; q < 24; q++) out[q] = T(0);
+        for (int q = 0; q < 24; q++) FC[q * nfaces + fidx] = T(0);
         return;
     }
     // face cotangent: R_left has -H/h, R_right has +H/h
@@ -566,6 +568,7 @@ __global__ void __launch_bounds__(128) k_adj_face(KParams P, const T* __restrict
     };
     const Geo<T> ga = geo(li, lj), gb = geo(ri, rj);
     face_flux_vjp(P, w0, ga, gb, d, gH, out);
+    for (int q = 0; q < 24; q++) FC[q * nfaces + fidx] = out[q];
 }
 
 // Source input slots: 0..5 centre fields; 6..21 neighbour (E, W, N, S) x
@@ -746,7 +749,7 @@ __device__ __forceinline__ void visc_face_vjp(int d, const T in[10], const Geo<T
 }
 
 // Pass B, sources: cotangent dt * GT_c (momentum components) pulled back
-// through S_c to its 34 input slots, into SC[cell][34].  Chain rule over the
+// through S_c to its 34 input slots, into SC[34][cells].  Chain rule over the
 // structure of cell_sources: the local sources of the cell's six fields and of
 // the two fluid-pressure gradients (8 dual evaluations of sources), the
 // gradients to the neighbours' thicknesses (fluid_G), and the viscous
@@ -760,7 +763,8 @@ __global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict_
     const int j = blockIdx.y;
     if (i >= P.nx) return;
     const size_t c = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
-    T* out = SC + ((size_t)j * P.nx + i) * 34;
+    // slot-major: slot q of all cells is contiguous
+    const size_t ncells = (size_t)P.nx * P.ny, cell = (size_t)j * P.nx + i;
     Stencil<T> s;
     load_stencil(P, U, i, j, s);
     const Geo5<T> g5 = geo5(P, b, i, j);
@@ -941,7 +945,7 @@ __global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict_
             lam[box_slot(ba[q], bc[q], 3)] += lJh[q];
         }
     }
-    for (int q = 0; q < 34; q++) out[q] = lam[q];
+    for (int q = 0; q < 34; q++) SC[q * ncells + cell] = lam[q];
 }
 
 // Pass C: lam_in(k) = DU(k) + all face and source contributions that land on
@@ -955,37 +959,39 @@ __global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restri
     const int j = blockIdx.y;
     if (i >= P.nx) return;
     const size_t c = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
+    // slot-major cotangent arrays (slot stride: number of faces or cells)
+    const size_t nfx = (size_t)(P.nx + 1) * P.ny, nfy = (size_t)P.nx * (P.ny + 1), ncl = (size_t)P.nx * P.ny;
     T acc[NF];
     for (int k = 0; k < NF; k++) acc[k] = DU[k * fs + c];
     if (i >= 2 && i <= P.nx - 3 && j >= 2 && j <= P.ny - 3) {
         // No ghost cell maps onto this cell: each contribution comes from a
         // fixed (face or cell, slot), taken in the order of the general path.
         for (int fi = i - 2; fi <= i + 1; fi++) {
-            const T* f = FCX + ((size_t)j * (P.nx + 1) + (fi + 1)) * 24 + 6 * (i - fi + 1);
-            for (int k = 0; k < NF; k++) acc[k] += f[k];
+            const T* f = FCX + ((size_t)j * (P.nx + 1) + (fi + 1)) + 6 * (i - fi + 1) * nfx;
+            for (int k = 0; k < NF; k++) acc[k] += f[k * nfx];
         }
         for (int fj = j - 2; fj <= j + 1; fj++) {
-            const T* f = FCY + ((size_t)(fj + 1) * P.nx + i) * 24 + 6 * (j - fj + 1);
-            for (int k = 0; k < NF; k++) acc[k] += f[k];
+            const T* f = FCY + ((size_t)(fj + 1) * P.nx + i) + 6 * (j - fj + 1) * nfy;
+            for (int k = 0; k < NF; k++) acc[k] += f[k * nfy];
         }
         // source cell (i - di, j - dj) reads this cell through its slots of offset (di, dj)
         for (int cj = j - 1; cj <= j + 1; cj++)
             for (int ci = i - 1; ci <= i + 1; ci++) {
-                const T* f = SC + ((size_t)cj * P.nx + ci) * 34;
+                const T* f = SC + ((size_t)cj * P.nx + ci);
                 const int di = i - ci, dj = j - cj;
                 if (di == 0 && dj == 0) {
-                    for (int k = 0; k < NF; k++) acc[k] += f[k];
+                    for (int k = 0; k < NF; k++) acc[k] += f[k * ncl];
                 } else if (di == 0 || dj == 0) {
                     const int n = dj == 0 ? (di > 0 ? 0 : 1) : (dj > 0 ? 2 : 3);
-                    acc[0] += f[6 + 4 * n];
-                    acc[3] += f[6 + 4 * n + 1];
-                    acc[4] += f[6 + 4 * n + 2];
-                    acc[5] += f[6 + 4 * n + 3];
+                    acc[0] += f[(6 + 4 * n) * ncl];
+                    acc[3] += f[(6 + 4 * n + 1) * ncl];
+                    acc[4] += f[(6 + 4 * n + 2) * ncl];
+                    acc[5] += f[(6 + 4 * n + 3) * ncl];
                 } else {
                     const int n = (dj > 0 ? 0 : 2) + (di > 0 ? 0 : 1);
-                    acc[3] += f[22 + 3 * n];
-                    acc[4] += f[22 + 3 * n + 1];
-                    acc[5] += f[22 + 3 * n + 2];
+                    acc[3] += f[(22 + 3 * n) * ncl];
+                    acc[4] += f[(22 + 3 * n + 1) * ncl];
+                    acc[5] += f[(22 + 3 * n + 2) * ncl];
                 }
             }
         for (int k = 0; k < NF; k++) lam_in[k * fs + c] = acc[k];
@@ -994,23 +1000,25 @@ __global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restri
     // x-faces of row j: face index t = fi + 1, fi in [-1, nx-1], stencil cells fi-1 .. fi+2
     for (int fi = i - 3; fi <= i + 2; fi++) {
         if (fi < -1 || fi > P.nx - 1) continue;
-        const T* f = FCX + ((size_t)j * (P.nx + 1) + (fi + 1)) * 24;
+        const T* f = FCX + ((size_t)j * (P.nx + 1) + (fi + 1));
         for (int q = 0; q < 4; q++) {
             int fx = 0;
             const int mi = map_index(fi - 1 + q, P.nx, P.bc[0], P.bc[1], fx);
             if (mi != i) continue;
-            for (int k = 0; k < NF; k++) acc[k] += ((fx && (k == 1 || k == 4)) ? -f[6 * q + k] : f[6 * q + k]);
+            for (int k = 0; k < NF; k++)
+                acc[k] += ((fx && (k == 1 || k == 4)) ? -f[(6 * q + k) * nfx] : f[(6 * q + k) * nfx]);
         }
     }
     // y-faces of column i: face line fj + 1, fj in [-1, ny-1]
     for (int fj = j - 3; fj <= j + 2; fj++) {
         if (fj < -1 || fj > P.ny - 1) continue;
-        const T* f = FCY + ((size_t)(fj + 1) * P.nx + i) * 24;
+        const T* f = FCY + ((size_t)(fj + 1) * P.nx + i);
         for (int q = 0; q < 4; q++) {
             int fy = 0;
             const int mj = map_index(fj - 1 + q, P.ny, P.bc[2], P.bc[3], fy);
             if (mj != j) continue;
-            for (int k = 0; k < NF; k++) acc[k] += ((fy && (k == 2 || k == 5)) ? -f[6 * q + k] : f[6 * q + k]);
+            for (int k = 0; k < NF; k++)
+                acc[k] += ((fy && (k == 2 || k == 5)) ? -f[(6 * q + k) * nfy] : f[(6 * q + k) * nfy]);
         }
     }
     // sources of the 3 x 3 neighbourhood
@@ -1018,7 +1026,7 @@ __global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restri
         if (cj < 0 || cj >= P.ny) continue;
         for (int ci = i - 1; ci <= i + 1; ci++) {
             if (ci < 0 || ci >= P.nx) continue;
-            const T* f = SC + ((size_t)cj * P.nx + ci) * 34;
+            const T* f = SC + ((size_t)cj * P.nx + ci);
             for (int sl = 0; sl < 34; sl++) {
                 int di, dj, k;
                 src_slot(sl, di, dj, k);
@@ -1026,7 +1034,7 @@ __global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restri
                 const int mi = map_index(ci + di, P.nx, P.bc[0], P.bc[1], fx);
                 const int mj = map_index(cj + dj, P.ny, P.bc[2], P.bc[3], fy);
                 if (mi != i || mj != j) continue;
-                T v = f[sl];
+                T v = f[sl * ncl];
                 if (fx && (k == 1 || k == 4)) v = -v;
                 if (fy && (k == 2 || k == 5)) v = -v;
                 acc[k] += v;

@@ -37,7 +37,8 @@ struct KParams {
     double c_d, inv_n_r, theta_b;
     double T, V, H, L, dx, dy, cfl, a_floor, dt_floor;
     SegDesc seg[MAX_SEG];   // Mode-II segments with a discharge hydrograph (face flux)
-    int nsseg, pad_;
+    int nsseg;
+    int rk;                 // stages per step: 2 (Heun) or 3 (SSP Runge-Kutta)
     SegDesc sseg[MAX_SEG];  // Mode-II segments with a state hydrograph (ghost cells)
 };
 
@@ -49,11 +50,28 @@ struct DevScalars {
     unsigned long long clamps;
     unsigned int status;
     unsigned int pad;
-    double inflow[2][MAX_SEG][4];      // per stage: q, m_in, v_in, phi
-    double sghost[2][MAX_SEG][NF];     // per stage: ghost state of each state segment
+    double inflow[3][MAX_SEG][4];      // per stage: q, m_in, v_in, phi
+    double sghost[3][MAX_SEG][NF];     // per stage: ghost state of each state segment
     const double* dt_sched;            // optional prescribed (frozen) time steps, dimensionless
     long long n_sched;
 };
+
+// Stage kinds of a step.  Heun, the paper's two-step modified Euler method:
+// kinds 1 then 2.  Three-stage SSP Runge-Kutta: kinds 1, 3, 4.
+//   1: U1 = E(U^n)   2: (U^n + E(U1)) / 2   3: 3/4 U^n + 1/4 E(U1)
+//   4: 1/3 U^n + 2/3 E(U2)
+// The slot is the stage's index within the step (its time, inflow states and
+// partial sums); kinds 2 and 4 end the step and give the CFL speeds.
+constexpr int stage_slot(int kind) { return kind == 1 ? 0 : (kind == 4 ? 2 : 1); }
+constexpr bool stage_last(int kind) { return kind == 2 || kind == 4; }
+
+template <int KIND, typename T>
+M2P_FN T stage_combine(T un, T e)
+{
+    if constexpr (KIND == 2) return T(0.5) * (un + e);
+    else if constexpr (KIND == 3) return T(0.75) * un + T(0.25) * e;
+    else return T(1.0 / 3.0) * un + T(2.0 / 3.0) * e;
+}
 
 template <typename T>
 struct Geo {

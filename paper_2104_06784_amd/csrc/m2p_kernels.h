@@ -124,10 +124,11 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh)
 
 // -------------------------------------------------- reference stage kernel
 
-// One thread per cell; every stencil value is read from memory.  STAGE 1:
-// U* = E(U^n) at t^n.  STAGE 2: U^{n+1} = (U^n + E(U*)) / 2 at t^n + dt,
-// written over U^n (only the cell's own U^n is read), plus the maximum phase
-// speeds of U^{n+1} for the next CFL step.
+// One thread per cell; every stencil value is read from memory.  STAGE is
+// the stage kind (stage_combine): kind 1 writes E(U^n) at t^n; kinds 2-4
+// combine E(Uin) with the cell's own U^n (read from Un) and write Uout
+// (kinds 2 and 4 over U^n, with the maximum phase speeds of the new state
+// for the next CFL step).
 template <typename T, int STAGE>
 __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restrict__ Uin, T* Un, T* Uout,
                                                    const T* __restrict__ b, const T* __restrict__ mu,
@@ -138,7 +139,7 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const Consts<T> K(P);
-    const View<T> V(P, Uin, b, S->sghost[STAGE - 1]);
+    const View<T> V(P, Uin, b, S->sghost[stage_slot(STAGE)]);
     const bool active = i < P.nx && j < P.ny;
     double red[1] = {0};  // clamps
     double ax = 0.0, ay = 0.0;
@@ -172,8 +173,8 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
         }
         // Mode-II faces, and the flux through every boundary face into the
         // per-face outflow slots (zero on discharge-inflow faces)
-        const double (*inf)[4] = S->inflow[STAGE - 1];
-        const int st = STAGE - 1;
+        const double (*inf)[4] = S->inflow[stage_slot(STAGE)];
+        const int st = stage_slot(STAGE);
         if (i == 0) {
             int s = inflow_seg_at(P, 0, j);
             if (s >= 0)
@@ -261,9 +262,11 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
         T tmu = P.has_mu ? mu[c] : K.tan_d;
         T out[NF];
         red[0] = (double)update_cell(K, uC, gC, HXl, HXr, HYb, HYt, Sr, svx, svy, dt, tmu, out);
-        if (STAGE == 2) {
+        if (STAGE > 1) {
 #pragma unroll
-            for (int k = 0; k < NF; k++) out[k] = T(0.5) * (Un[k * fs + c] + out[k]);
+            for (int k = 0; k < NF; k++) out[k] = stage_combine<STAGE>(Un[k * fs + c], out[k]);
+        }
+        if (stage_last(STAGE)) {
             T a[2];
             side_speed(K, out, gC, 0, a);
             ax = (double)(a[0] > a[1] ? a[0] : a[1]);
@@ -294,7 +297,7 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
             __syncthreads();
         }
         if (tid == 0) {
-            const int st = STAGE - 1;
+            const int st = stage_slot(STAGE);
             const int bid = blockIdx.y * gridDim.x + blockIdx.x;
             double* wp = wpart + ((size_t)st * gridDim.x * gridDim.y + bid) * 4;
             wp[0] = sh[0];
@@ -338,9 +341,9 @@ __global__ void __launch_bounds__(256) k_speeds(KParams P, const T* __restrict__
         __syncthreads();
     }
     if (tid == 0) {
-        // written into the stage-2 slots, which the init finalize reads
+        // written into the last stage's slots, which the init finalize reads
         const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-        double* wp = wpart + ((size_t)gridDim.x * gridDim.y + bid) * 4;
+        double* wp = wpart + ((size_t)(P.rk - 1) * gridDim.x * gridDim.y + bid) * 4;
         wp[0] = sh[0];
         wp[1] = sh[256];
         wp[2] = 0.0;
@@ -434,36 +437,44 @@ __device__ __forceinline__ void finalize_body(const KParams& P, DevScalars* S, c
     // threads per (stage, side, phase); per-wave / per-block partials of the
     // speed maxima, clamp counts and non-finite flags, 256 strided threads.
     __shared__ double red[4 * 256];
-    __shared__ double part[16];
+    __shared__ double bred[24 * 256];
+    __shared__ double part[24];
     const int tid = threadIdx.x;
+    const int last = P.rk - 1;  // slot of the stage that ends the step
     if (mode == 0) {
-        const int combo = tid >> 4, lane = tid & 15;
-        const int st = combo >> 3, side = (combo >> 1) & 3, ph = combo & 1;
-        const int n = side < 2 ? n_we : n_sn;
-        const double* p = bpart + ((size_t)(st * 4 + side) * nmax) * 2 + ph;
-        double acc = 0.0;
-        for (int q = lane; q < n; q += 16) acc += p[2 * q];
-        red[tid] = acc;
+        // every thread sums a strided share of each (stage, side, phase) list
+        // of per-face outflow slots, then one fixed tree per list
+        const int ncombo = P.rk * 8;
+        for (int combo = 0; combo < ncombo; combo++) {
+            const int st = combo >> 3, side = (combo >> 1) & 3, ph = combo & 1;
+            const int n = side < 2 ? n_we : n_sn;
+            const double* p = bpart + ((size_t)(st * 4 + side) * nmax) * 2 + ph;
+            double acc = 0.0;
+            for (int q = tid; q < n; q += 256) acc += p[2 * q];
+            bred[combo * 256 + tid] = acc;
+        }
         __syncthreads();
-        for (int w = 8; w > 0; w >>= 1) {
-            if (lane < w) red[tid] += red[tid + w];
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w)
+                for (int combo = 0; combo < ncombo; combo++) bred[combo * 256 + tid] += bred[combo * 256 + tid + w];
             __syncthreads();
         }
-        if (lane == 0) part[combo] = red[tid];
+        if (tid < ncombo) part[tid] = bred[tid * 256];
         __syncthreads();
     }
     {
         double ax = 0.0, ay = 0.0, cl = 0.0, bd = 0.0;
-        const double* w2 = wpart + (size_t)nw * 4;  // stage-2 (or speeds) slots
+        const double* wl = wpart + (size_t)nw * 4 * last;  // last stage's (or the speeds') slots
         for (int q = tid; q < nw; q += 256) {
-            ax = fmax(ax, w2[4 * q]);
-            ay = fmax(ay, w2[4 * q + 1]);
-            cl += w2[4 * q + 2];
-            bd = fmax(bd, w2[4 * q + 3]);
-            if (mode == 0) {
-                cl += wpart[4 * q + 2];
-                bd = fmax(bd, wpart[4 * q + 3]);
-            }
+            ax = fmax(ax, wl[4 * q]);
+            ay = fmax(ay, wl[4 * q + 1]);
+            cl += wl[4 * q + 2];
+            bd = fmax(bd, wl[4 * q + 3]);
+            if (mode == 0)
+                for (int st = 0; st < last; st++) {
+                    cl += wpart[((size_t)st * nw + q) * 4 + 2];
+                    bd = fmax(bd, wpart[((size_t)st * nw + q) * 4 + 3]);
+                }
         }
         red[tid] = ax;
         red[256 + tid] = ay;
@@ -488,13 +499,18 @@ __device__ __forceinline__ void finalize_body(const KParams& P, DevScalars* S, c
         const double dt = S->dt;
         const double vs = P.H * P.L * P.L;  // dimensionless volume -> m^3
         for (int ph = 0; ph < 2; ph++) {
-            double B1 = 0.0, B2 = 0.0;
-            for (int side = 0; side < 4; side++) {
-                B1 += part[(0 * 4 + side) * 2 + ph];
-                B2 += part[(1 * 4 + side) * 2 + ph];
+            double B[3] = {0.0, 0.0, 0.0};
+            for (int st = 0; st < P.rk; st++)
+                for (int side = 0; side < 4; side++) B[st] += part[(st * 4 + side) * 2 + ph];
+            double out, in;
+            if (P.rk == 3) {
+                out = dt * (B[0] / 6.0 + B[1] / 6.0 + 2.0 * B[2] / 3.0);
+                in = dt * (inflow_rate(P, tables, t, ph) / 6.0 + inflow_rate(P, tables, t + dt, ph) / 6.0 +
+                           2.0 * inflow_rate(P, tables, t + 0.5 * dt, ph) / 3.0);
+            } else {
+                out = 0.5 * dt * (B[0] + B[1]);
+                in = 0.5 * dt * (inflow_rate(P, tables, t, ph) + inflow_rate(P, tables, t + dt, ph));
             }
-            double out = 0.5 * dt * (B1 + B2);
-            double in = 0.5 * dt * (inflow_rate(P, tables, t, ph) + inflow_rate(P, tables, t + dt, ph));
             if (ph == 0) {
                 S->out_s += out * vs;
                 S->in_s += in * vs;
@@ -540,14 +556,17 @@ __device__ __forceinline__ void finalize_body(const KParams& P, DevScalars* S, c
     if (S->t_end - t < dt) dt = S->t_end - t;
     if (dt < 0.0) dt = 0.0;
     S->dt = dt;
+    // stage times: t, t + dt, and t + dt/2 for the third Runge-Kutta stage
     for (int s = 0; s < P.nseg; s++) {
         inflow_state(P, tables, s, t, S->inflow[0][s]);
         inflow_state(P, tables, s, t + dt, S->inflow[1][s]);
+        if (P.rk == 3) inflow_state(P, tables, s, t + 0.5 * dt, S->inflow[2][s]);
     }
     for (int s = 0; s < P.nsseg; s++) {
         double m, v;
         ghost_state(P, tables, s, t, S->sghost[0][s], m, v);
         ghost_state(P, tables, s, t + dt, S->sghost[1][s], m, v);
+        if (P.rk == 3) ghost_state(P, tables, s, t + 0.5 * dt, S->sghost[2][s], m, v);
     }
 }
 

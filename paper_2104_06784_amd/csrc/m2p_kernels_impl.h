@@ -14,27 +14,46 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
     using T = M2P_REAL;
     T* U = (T*)B.U;
     T* Us = (T*)B.Us;
+    T* Us2 = (T*)B.Us2;
     const T* b = (const T*)B.b;
     const T* mu = (const T*)B.mu;
-    if (part == 2) {
+    if (part == P.rk) {
         hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(256), 0, st, P, B.S, B.bpart, sh.n_we, sh.n_sn, B.nmax,
                            B.tables, 0, B.wpart, sh.nw);
-    } else if (sh.variant == 1) {
+        return hipGetLastError();
+    }
+    // Heun: E(U) -> Us, then (U + E(Us)) / 2 -> U.  Three-stage: E(U) -> Us,
+    // 3/4 U + 1/4 E(Us) -> Us2, then 1/3 U + 2/3 E(Us2) -> U.
+    const int kind = part == 0 ? 1 : (P.rk == 2 ? 2 : (part == 1 ? 3 : 4));
+    const T* in = part == 0 ? U : (kind == 4 ? Us2 : Us);
+    T* out = part == 0 ? Us : (kind == 3 ? Us2 : U);
+    if (sh.variant == 1) {
         dim3 blk(64, 4), grd(sh.nbx, sh.nby);
-        if (part == 0)
-            hipLaunchKernelGGL((k_stage_ref<T, 1>), grd, blk, 0, st, P, U, U, Us, b, mu, B.S, B.bpart, B.wpart,
-                               B.nmax);
+#define M2P_REF(K) \
+    hipLaunchKernelGGL((k_stage_ref<T, K>), grd, blk, 0, st, P, in, U, out, b, mu, B.S, B.bpart, B.wpart, B.nmax)
+        if (kind == 1)
+            M2P_REF(1);
+        else if (kind == 2)
+            M2P_REF(2);
+        else if (kind == 3)
+            M2P_REF(3);
         else
-            hipLaunchKernelGGL((k_stage_ref<T, 2>), grd, blk, 0, st, P, Us, U, U, b, mu, B.S, B.bpart, B.wpart,
-                               B.nmax);
+            M2P_REF(4);
+#undef M2P_REF
     } else {
         dim3 blk(256), grd(sh.blocks);
-        if (part == 0)
-            hipLaunchKernelGGL((k_stage_tiled<T, 1>), grd, blk, 0, st, P, U, U, Us, b, mu, B.S, B.bpart, B.wpart,
-                               B.nmax, sh.R, sh.nstrips, sh.nrb);
+#define M2P_TILED(K)                                                                                             \
+    hipLaunchKernelGGL((k_stage_tiled<T, K>), grd, blk, 0, st, P, in, U, out, b, mu, B.S, B.bpart, B.wpart, B.nmax, \
+                       sh.R, sh.nstrips, sh.nrb)
+        if (kind == 1)
+            M2P_TILED(1);
+        else if (kind == 2)
+            M2P_TILED(2);
+        else if (kind == 3)
+            M2P_TILED(3);
         else
-            hipLaunchKernelGGL((k_stage_tiled<T, 2>), grd, blk, 0, st, P, Us, U, U, b, mu, B.S, B.bpart, B.wpart,
-                               B.nmax, sh.R, sh.nstrips, sh.nrb);
+            M2P_TILED(4);
+#undef M2P_TILED
     }
     return hipGetLastError();
 }

@@ -21,11 +21,12 @@ struct Shape {
 struct Bufs {
     void* U;               // state U^n (6 fields, [ny][pitch] each)
     void* Us;              // stage state U*
+    void* Us2;             // second stage state of the three-stage method (else nullptr)
     const void* b;         // padded DEM / L
     const void* mu;        // per-cell tan(delta_b) or nullptr
     DevScalars* S;         // device scalars
-    double* bpart;         // boundary outflow partials [2][4][nmax][2]
-    double* wpart;         // per-wave / per-block partials [2][nw][4]
+    double* bpart;         // boundary outflow partials [stages][4][nmax][2]
+    double* wpart;         // per-wave / per-block partials [stages][nw][4]
     const double* tables;  // inflow hydrographs
     double* mass_part;     // [2 * kMassBlocks]
     int nmax;              // stride of bpart
@@ -53,7 +54,7 @@ Shape make_shape(const KParams& P, int variant, int rows);
 
 template <typename T>
 struct Launch {
-    // part 0: stage 1, part 1: stage 2, part 2: finalize
+    // parts 0 .. P.rk - 1: the stages of a step, part P.rk: finalize
     static hipError_t step_part(const KParams& P, const Bufs& B, const Shape& sh, hipStream_t st, int part);
     static hipError_t init(const KParams& P, const Bufs& B, hipStream_t st);
     static hipError_t set_state(const KParams& P, const Bufs& B, const double* f, int vertical, int has_v,

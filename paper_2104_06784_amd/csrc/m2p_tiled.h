@@ -110,7 +110,7 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
     const int r0 = rb * R;
     const int r1 = r0 + R < P.ny ? r0 + R : P.ny;
     const T dt = T(S->dt);
-    const double(*inf)[4] = S->inflow[STAGE - 1];
+    const double(*inf)[4] = S->inflow[stage_slot(STAGE)];
     const bool ownW = out_lane && col == 0;  // this lane owns the W / E boundary face
     const bool ownE = out_lane && col == P.nx - 1;
 
@@ -128,13 +128,13 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
             u[2] = -u[2];
             u[5] = -u[5];
         }
-        if (P.nsseg > 0) ghost_sub(P, S->sghost[STAGE - 1], cc, r, u);
+        if (P.nsseg > 0) ghost_sub(P, S->sghost[stage_slot(STAGE)], cc, r, u);
     };
     auto loadB = [&](int r) { return b[(size_t)(r + BHALO) * P.bpitch + bcol]; };
 
     // flux through each boundary face goes to its own outflow slot (zero on
     // discharge-inflow faces), reduced in a fixed order by the finalize
-    const int st = STAGE - 1;
+    const int st = stage_slot(STAGE);
     auto put_b = [&](int side, int k, bool inflow, T m_s, T m_f, double len) {
         double* bp = bpart + ((size_t)(st * 4 + side) * nmax + k) * 2;
         const double sg = (side == 0 || side == 2) ? -1.0 : 1.0;
@@ -208,7 +208,7 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
         bj3 = loadB(rn);
         const size_t cself = (size_t)j * P.pitch + (out_lane ? col : 0);
         T unr[NF];
-        if (STAGE == 2) {
+        if (STAGE > 1) {
 #pragma unroll
             for (int k = 0; k < NF; k++) unr[k] = Un[k * fs + cself];
         }
@@ -316,9 +316,11 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
         if (out_lane) {
             T out[NF];
             clamps += update_cell(K, Uc, D0.g, HxL, Hx, Hy, HyN, Sr, svx, svy, dt, tmu, out);
-            if (STAGE == 2) {
+            if (STAGE > 1) {
 #pragma unroll
-                for (int k = 0; k < NF; k++) out[k] = T(0.5) * (unr[k] + out[k]);
+                for (int k = 0; k < NF; k++) out[k] = stage_combine<STAGE>(unr[k], out[k]);
+            }
+            if (stage_last(STAGE)) {
                 T a[2];
                 side_speed(K, out, D0.g, 0, a);
                 amx = fmax(amx, a[0] > a[1] ? a[0] : a[1]);

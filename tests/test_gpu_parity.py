@@ -179,6 +179,43 @@ def test_state_inflow_argument_errors():
     assert e.value.code == M2P_EINVAL
 
 
+@pytest.mark.parametrize("variant", [1, 2])
+def test_rk3_option_fp64(variant):
+    """The three-stage SSP Runge-Kutta option (M2P_F_RK3) against the oracle's
+    RK3: config 1 and the state/discharge inflow problem, both kernel
+    variants, diagnostics included."""
+    import dataclasses
+    for prob, n in ((I.config1(n=96), 120), (_state_inflow_problem(), 120)):
+        q = dataclasses.replace(prob, params=dataclasses.replace(prob.params, flags=prob.params.flags | I.F_RK3))
+        q.name = prob.name + "-rk3"
+        g, o = _compare_steps(q, n, 1e-12, variant=variant)
+        dg, do = g.diag(), o.diag()
+        for k in ("mass_s", "mass_f", "in_s", "in_f", "out_s", "out_f"):
+            assert abs(dg[k] - do[k]) <= 1e-12 * max(abs(do[k]), 1.0), k
+
+
+def test_rk3_fp32_and_refusals():
+    """FP32 RK3 stays within the FP32 tolerance of the FP64 oracle; the adjoint
+    and the ensemble refuse the option."""
+    import dataclasses
+
+    from paper_2104_06784_amd._abi import M2P_EINVAL, M2PError
+    from paper_2104_06784_amd.sim import Batch
+    prob = I.config1()
+    q = dataclasses.replace(prob, params=dataclasses.replace(prob.params, flags=I.F_RK3))
+    g, o = Sim(q, precision="f32"), Ora(q)
+    g.run_to(3.0)
+    o.run(10 ** 6, 3.0)
+    hg, ho = g.fields()["h"], o.fields()["h"]
+    assert np.abs(hg - ho).sum() / ho.sum() <= 1e-3
+    with pytest.raises(M2PError) as e:
+        g.adjoint_run(4, 2, np.zeros((q.ny, q.nx)))
+    assert e.value.code == M2P_EINVAL
+    with pytest.raises(M2PError) as e:
+        Batch([q, q], precision="f32")
+    assert e.value.code == M2P_EINVAL
+
+
 def test_run_to_lands_on_end_time():
     prob = I.config1(n=64)
     g, o = Sim(prob, precision="f64"), Ora(prob)
@@ -209,14 +246,18 @@ def test_run_outputs_equals_run_to_and_get_fields(precision):
     assert na == nb and a.diag()["t"] == times[-1]
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_graph_replay_equals_direct_launches(precision):
+@pytest.mark.parametrize("precision,rk3", [("f64", False), ("f32", False), ("f32", True)])
+def test_graph_replay_equals_direct_launches(precision, rk3):
     """Steps replayed from HIP graphs (chunks of 7 on a stream of the
     context's own) equal kernel-by-kernel launches bitwise, through run,
     run_to and a change of the inflow segments (which forces a recapture);
-    replays interleave with eager work and host reads."""
+    replays interleave with eager work and host reads.  Heun and RK3."""
+    import dataclasses
+
     import torch
     prob = _state_inflow_problem()
+    if rk3:
+        prob = dataclasses.replace(prob, params=dataclasses.replace(prob.params, flags=I.F_RK3))
     res = []
     for chunk in (7, 0):
         st = torch.cuda.Stream()

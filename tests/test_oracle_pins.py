@@ -231,6 +231,58 @@ def test_two_phase_layer_heun_recurrence():
     assert np.max(np.abs(f["vxf"] - v[1] * V)) <= 1e-13 * abs(v[1] * V)
 
 
+def test_two_phase_layer_rk3_recurrence():
+    """The same uniform layer with the three-stage SSP Runge-Kutta option: the
+    step reduces to U1 = E(U), U2 = 3/4 U + 1/4 E(U1), U' = 1/3 U + 2/3 E(U2)
+    on the 2x2 system (a wrong stage weight breaks the cubic term)."""
+    theta, delta, phis = 30.0, 20.0, 0.5
+    nx, ny, dx = 16, 8, 10.0
+    dem = I.plane_dem(nx, ny, dx, dx, theta)
+    h = np.full((ny, nx), 5.0)
+    p = I.Params(delta_b_deg=delta, bc=(0, 0, 0, 0), flags=I.F_RK3)
+    s = _sim(I.Problem("drag3", nx, ny, dx, dx, p, dem, h, np.full_like(h, phis)))
+    dts = s.run(300)
+    f = s.fields()
+    T, V = math.sqrt(p.L / p.g), math.sqrt(p.g * p.L)
+    eps, al = p.H / p.L, p.rho_f / p.rho_s
+    th, td = math.radians(theta), math.tan(math.radians(delta))
+    fv = np.array([(1 - al) * math.cos(th) * math.sin(th) - (1 - al) * td * math.cos(th) ** 2,
+                   math.cos(th) * math.sin(th)])
+    kf = p.theta_b * p.inv_n_r / eps
+    A = np.array([[-al * p.c_d * (1 - phis), al * p.c_d * (1 - phis)],
+                  [p.c_d * phis, -p.c_d * phis - kf]])
+    v = np.zeros(2)
+    for dt in dts / T:
+        E = lambda w: w + dt * (A @ w + fv)  # noqa: E731
+        v2 = 0.75 * v + 0.25 * E(E(v))
+        v = v / 3.0 + 2.0 * E(v2) / 3.0
+    assert np.max(np.abs(f["vxs"] - v[0] * V)) <= 1e-13 * abs(v[0] * V)
+    assert np.max(np.abs(f["vxf"] - v[1] * V)) <= 1e-13 * abs(v[1] * V)
+
+
+def test_rk3_budgets_close_and_differ_from_heun():
+    """RK3 with Mode-II discharge and state segments on a tilted fractal bed:
+    the volume budget closes to round-off with the 1/6, 1/6, 2/3 quadrature,
+    and the solution differs from Heun's (the option is in effect)."""
+    n, dx = 40, 10.0
+    dem = I.fractal_dem(n, dx, 5, 30.0, tilt_deg=10.0)
+    t, Q, ph = I.triangular_hydrograph(30.0, 10.0, 30.0, 0.4)
+    z = np.zeros((n, n))
+    seg = I.InflowState(2, 10, 8, np.array([0.0, 40.0]), np.array([1.0, 0.2]), np.array([0.5, 0.5]),
+                        np.array([3.0, 1.0]))
+    runs = []
+    for flags in (0, I.F_RK3):
+        p = I.Params(cfl=0.3, bc=(0, 0, 0, 0), flags=flags)
+        prob = I.Problem("rk", n, n, dx, dx, p, dem, z, z, [I.Inflow(0, 12, 6, t, Q, ph)], inflow_states=[seg])
+        s = _sim(prob)
+        s.run(250)
+        d = s.diag()
+        for a in ("s", "f"):
+            assert abs(d["mass_" + a] - (d["in_" + a] - d["out_" + a])) <= 1e-12 * d["mass_" + a]
+        runs.append(s.state())
+    assert np.max(np.abs(runs[0] - runs[1])) > 1e-6 * np.max(np.abs(runs[0]))
+
+
 def test_drag_conserves_mixture_momentum():
     """P7: on a flat bed with only the interphase drag acting (no friction,
     uniform state) rho^s q^s + rho^f q^f is unchanged to round-off, while the
