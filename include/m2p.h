@@ -192,7 +192,8 @@ int m2p_set_inflow(m2p_ctx *c, const m2p_inflow *seg, int32_t nseg);
 int m2p_set_inflow_states(m2p_ctx *c, const m2p_inflow_state *seg, int32_t nseg);
 
 /* Select the stage-kernel variant (M2P_VARIANT_*); results are identical in
- * FP64.  Tile rows per workgroup for the tiled variant (0 = default). */
+ * FP64.  tile_rows: rows each wavefront of the tiled variant marches, 1..4096,
+ * or 0 = chosen from the grid size.  Errors: M2P_EINVAL. */
 int m2p_set_variant(m2p_ctx *c, int32_t variant, int32_t tile_rows);
 
 /* One time step, enqueued.  If dt_out is not NULL the stream is synchronized

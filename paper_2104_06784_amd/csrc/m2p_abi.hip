@@ -55,6 +55,7 @@ struct m2p_ctx {
     int rows = 0;
     Shape shape{};
     double* wpart = nullptr;
+    size_t wcap = 0;  // per-wave partial slots the wpart buffer holds per stage
     size_t state_bytes = 0;
     void* b = nullptr;
     void* mu = nullptr;
@@ -90,6 +91,9 @@ struct m2p_ctx {
 
 static hipError_t step_part(m2p_ctx* c, int part)
 {
+    // every launch shape's partial slots must fit the buffer (m2p_set_variant
+    // grows it before a shape needs more)
+    if ((size_t)c->shape.nw > c->wcap || (size_t)c->B.nw_ref > c->wcap) return hipErrorInvalidValue;
     if (c->prec == M2P_FP64) return Launch<double>::step_part(c->kp, c->B, c->shape, c->stream, part);
     return Launch<float>::step_part(c->kp, c->B, c->shape, c->stream, part);
 }
@@ -142,13 +146,14 @@ Shape make_shape(const KParams& P, int variant, int rows)
     s.nstrips = (P.nx + 59) / 60;
     int R = rows;
     if (R <= 0) {
-        R = 8;
-        for (int cand : {64, 32, 16}) {
-            if ((long long)s.nstrips * ((P.ny + cand - 1) / cand) >= 2048) {
-                R = cand;
-                break;
-            }
-        }
+        // A wavefront's march costs its R rows plus a prologue of about two
+        // rows' work (the stencil window), so the redundant work falls like
+        // 1/R while the latency of one wavefront grows like R; their sum is
+        // least near R ~ sqrt(wave-rows).  The constant is the measured
+        // optimum of FP32 runs from 100 x 100 to 4096 x 4096.
+        const double wave_rows = (double)s.nstrips * P.ny;
+        R = (int)std::lround(std::sqrt(wave_rows) / 22.0);
+        R = R < 1 ? 1 : (R > 64 ? 64 : R);
     }
     s.R = R;
     s.nrb = (P.ny + R - 1) / R;
@@ -167,6 +172,27 @@ Shape make_shape(const KParams& P, int variant, int rows)
 }  // namespace m2p
 
 static void refresh_grid(m2p_ctx* c) { c->shape = make_shape(c->kp, c->variant, c->rows); }
+
+// Grow the per-wave partial buffer to the current launch shape (3 stage slots
+// of 4 values per wave).  Contents start at zero; the finalize reads only the
+// slots the last stage launches wrote.
+static int ensure_wpart(m2p_ctx* c)
+{
+    const size_t need = std::max((size_t)c->shape.nw, (size_t)c->B.nw_ref);
+    if (need <= c->wcap) return M2P_OK;
+    double* w = nullptr;
+    if (hipMalloc(&w, sizeof(double) * 3 * 4 * need) != hipSuccess)
+        return fail(M2P_ENOMEM, "partials allocation failed");
+    if (hipMemset(w, 0, sizeof(double) * 3 * 4 * need) != hipSuccess) {
+        (void)hipFree(w);
+        return fail(M2P_EHIP, "partials initialisation failed");
+    }
+    if (c->wpart) (void)hipFree(c->wpart);
+    c->wpart = w;
+    c->B.wpart = w;
+    c->wcap = need;
+    return M2P_OK;
+}
 
 static int ensure_ready(m2p_ctx* c)
 {
@@ -397,23 +423,21 @@ int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t pr
     if (hipMemcpy(c->S, &hs, sizeof(hs), hipMemcpyHostToDevice) != hipSuccess)
         return cleanup(fail(M2P_EHIP, "scalar init failed"));
     refresh_grid(c);
-    // partial buffers sized for every launch shape: reference blocks, or tiled
-    // wavefronts with at least 4 rows each
+    // partial buffers: outflow slots, one per boundary face; per-wave slots
+    // for the reference blocks and the default tiled shape (m2p_set_variant
+    // grows them for shorter tiles)
     {
-        const int nbx = (nx + 63) / 64, nby = (ny + 3) / 4, nstrips = (nx + 59) / 60, nrb = (ny + 3) / 4;
-        const int nmax = std::max(nx, ny) + 1;  // outflow slots: one per boundary face
-        const size_t nw = std::max((size_t)nbx * nby, (size_t)nstrips * nrb);
+        const int nmax = std::max(nx, ny) + 1;
         c->B.nmax = nmax;
-        c->B.nw_ref = nbx * nby;
+        c->B.nw_ref = ((nx + 63) / 64) * ((ny + 3) / 4);
         if (hipMalloc(&c->bpart, sizeof(double) * 3 * 4 * 2 * (size_t)nmax) != hipSuccess)
             return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
         (void)hipMemset(c->bpart, 0, sizeof(double) * 3 * 4 * 2 * (size_t)nmax);
-        if (hipMalloc(&c->wpart, sizeof(double) * 3 * 4 * nw) != hipSuccess)
-            return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
-        (void)hipMemset(c->wpart, 0, sizeof(double) * 3 * 4 * nw);
+        if (ensure_wpart(c) != M2P_OK) return cleanup(M2P_ENOMEM);
     }
     if (hipMalloc(&c->mass_part, sizeof(double) * 2 * kMassBlocks) != hipSuccess)
         return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
+
     if (hipMalloc(&c->staging, sizeof(double) * 7 * n) != hipSuccess)
         return cleanup(fail(M2P_ENOMEM, "staging allocation failed"));
     if (hipMalloc(&c->tables, sizeof(double) * 8) != hipSuccess)
@@ -703,12 +727,19 @@ int m2p_set_variant(m2p_ctx* c, int32_t variant, int32_t rows)
 {
     if (!c) return fail(M2P_EINVAL, "NULL context");
     if (variant < M2P_VARIANT_AUTO || variant > M2P_VARIANT_TILED) return fail(M2P_EINVAL, "unknown variant");
-    if (rows != 0 && (rows < 4 || rows > 4096)) return fail(M2P_EINVAL, "tile rows must be 0 or in [4, 4096]");
+    if (rows != 0 && (rows < 1 || rows > 4096)) return fail(M2P_EINVAL, "tile rows must be 0 or in [1, 4096]");
     HIPCHK(hipStreamSynchronize(c->stream));
+    const int old_variant = c->variant, old_rows = c->rows;
     c->variant = variant;
     c->rows = rows;
     refresh_grid(c);
-    return M2P_OK;
+    const int rc = ensure_wpart(c);
+    if (rc != M2P_OK) {
+        c->variant = old_variant;
+        c->rows = old_rows;
+        refresh_grid(c);
+    }
+    return rc;
 }
 
 int m2p_step(m2p_ctx* c, double* dt_out)

@@ -425,75 +425,117 @@ __device__ __forceinline__ void ghost_state(const KParams& P, const double* tabl
     u[5] = mf * v * ey;
 }
 
-// Single wavefront.  mode 0: close the step just taken (time, integrals);
-// both modes: next CFL dt from the speed maxima, inflow states of the next
-// step's two stages, reset of the maxima.
-// Body of the per-step finalize, run by one 256-thread workgroup.
-__device__ __forceinline__ void finalize_body(const KParams& P, DevScalars* S, const double* __restrict__ bpart,
-                                              int n_we, int n_sn, int nmax, const double* __restrict__ tables,
-                                              int mode, const double* __restrict__ wpart, int nw)
+// values 24, 25 and 27 combine by max, the others by sum
+__device__ __forceinline__ bool fin_is_max(int k) { return k == 24 || k == 25 || k == 27; }
+
+// Reduction of every partial list by one workgroup of NT threads into
+// out[kFinVals] (shared memory): the per-face outflow slots of each stage and
+// side (both phases in one 16-byte slot) and the per-wave speed maxima, clamp
+// counts and non-finite flags.  The workgroup runs alone, so it is bound by
+// latency: every thread issues its loads of all lists together (one memory
+// round trip per batch, not per list), then the per-thread shares are
+// combined in two short passes over shared memory.  Fixed order throughout
+// (deterministic).
+template <int NT>
+__device__ __forceinline__ void fin_reduce(const KParams& P, const double* __restrict__ bpart, int n_we, int n_sn,
+                                           int nmax, int mode, const double* __restrict__ wpart, int nw, double* out)
 {
-    // Fixed-order reductions (deterministic): boundary outflow partials, 16
-    // threads per (stage, side, phase); per-wave / per-block partials of the
-    // speed maxima, clamp counts and non-finite flags, 256 strided threads.
-    __shared__ double red[4 * 256];
-    __shared__ double bred[24 * 256];
-    __shared__ double part[24];
+    static_assert(NT % 64 == 0 && NT >= kFinVals * 8, "finalize workgroup shape");
+    constexpr int CH = NT / 8;  // shares per chunk of the second pass
+    __shared__ double sh[kFinVals][NT];
+    __shared__ double sh2[kFinVals][8];
     const int tid = threadIdx.x;
     const int last = P.rk - 1;  // slot of the stage that ends the step
-    if (mode == 0) {
-        // every thread sums a strided share of each (stage, side, phase) list
-        // of per-face outflow slots, then one fixed tree per list
-        const int ncombo = P.rk * 8;
-        for (int combo = 0; combo < ncombo; combo++) {
-            const int st = combo >> 3, side = (combo >> 1) & 3, ph = combo & 1;
-            const int n = side < 2 ? n_we : n_sn;
-            const double* p = bpart + ((size_t)(st * 4 + side) * nmax) * 2 + ph;
-            double acc = 0.0;
-            for (int q = tid; q < n; q += 256) acc += p[2 * q];
-            bred[combo * 256 + tid] = acc;
+    const int nlist = mode == 0 ? P.rk * 4 : 0;
+    const int nl_max = nlist == 0 ? 0 : (n_we > n_sn ? n_we : n_sn);
+    const double2* bp2 = reinterpret_cast<const double2*>(bpart);
+    double acc[24];
+#pragma unroll
+    for (int k = 0; k < 24; k++) acc[k] = 0.0;
+    for (int q0 = tid; q0 < nl_max; q0 += NT * 2) {
+        double2 v[12][2];
+#pragma unroll
+        for (int l = 0; l < 12; l++) {
+            const int n = (l & 3) < 2 ? n_we : n_sn;
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int q = q0 + NT * u;
+                v[l][u] = (l < nlist && q < n) ? bp2[(size_t)l * nmax + q] : make_double2(0.0, 0.0);
+            }
         }
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (tid < w)
-                for (int combo = 0; combo < ncombo; combo++) bred[combo * 256 + tid] += bred[combo * 256 + tid + w];
-            __syncthreads();
-        }
-        if (tid < ncombo) part[tid] = bred[tid * 256];
-        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < 12; l++)
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                acc[2 * l] += v[l][u].x;
+                acc[2 * l + 1] += v[l][u].y;
+            }
     }
+#pragma unroll
+    for (int k = 0; k < 24; k++) sh[k][tid] = acc[k];
     {
         double ax = 0.0, ay = 0.0, cl = 0.0, bd = 0.0;
-        const double* wl = wpart + (size_t)nw * 4 * last;  // last stage's (or the speeds') slots
-        for (int q = tid; q < nw; q += 256) {
-            ax = fmax(ax, wl[4 * q]);
-            ay = fmax(ay, wl[4 * q + 1]);
-            cl += wl[4 * q + 2];
-            bd = fmax(bd, wl[4 * q + 3]);
-            if (mode == 0)
-                for (int st = 0; st < last; st++) {
-                    cl += wpart[((size_t)st * nw + q) * 4 + 2];
-                    bd = fmax(bd, wpart[((size_t)st * nw + q) * 4 + 3]);
-                }
-        }
-        red[tid] = ax;
-        red[256 + tid] = ay;
-        red[512 + tid] = cl;
-        red[768 + tid] = bd;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (tid < w) {
-                red[tid] = fmax(red[tid], red[tid + w]);
-                red[256 + tid] = fmax(red[256 + tid], red[256 + tid + w]);
-                red[512 + tid] += red[512 + tid + w];
-                red[768 + tid] = fmax(red[768 + tid], red[768 + tid + w]);
+        const double4* wl = reinterpret_cast<const double4*>(wpart) + (size_t)nw * last;  // last stage's slots
+        const double4* w0 = reinterpret_cast<const double4*>(wpart);
+        const bool two = mode == 0 && last >= 1, three = mode == 0 && last >= 2;
+        for (int q0 = tid; q0 < nw; q0 += NT * 8) {
+            double4 v[8], e[8], f[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int q = q0 + NT * u;
+                const double4 z = make_double4(0.0, 0.0, 0.0, 0.0);
+                v[u] = q < nw ? wl[q] : z;
+                e[u] = (two && q < nw) ? w0[q] : z;
+                f[u] = (three && q < nw) ? w0[(size_t)nw + q] : z;
             }
-            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                ax = fmax(ax, v[u].x);
+                ay = fmax(ay, v[u].y);
+                cl += v[u].z + e[u].z + f[u].z;
+                bd = fmax(bd, fmax(v[u].w, fmax(e[u].w, f[u].w)));
+            }
         }
+        sh[24][tid] = ax;
+        sh[25][tid] = ay;
+        sh[26][tid] = cl;
+        sh[27][tid] = bd;
     }
-    if (tid != 0) return;
-    if (red[768] > 0.0) S->status |= 1u;
-    S->clamps += (unsigned long long)red[512];
+    __syncthreads();
+    // pass 1: thread (k, c) combines chunk c (CH consecutive shares) of value k
+    if (tid < kFinVals * 8) {
+        const int k = tid >> 3, c = tid & 7;
+        const double* r = &sh[k][c * CH];
+        double v = r[0];
+        if (fin_is_max(k)) {
+#pragma unroll 8
+            for (int j = 1; j < CH; j++) v = fmax(v, r[j]);
+        } else {
+#pragma unroll 8
+            for (int j = 1; j < CH; j++) v += r[j];
+        }
+        sh2[k][c] = v;
+    }
+    __syncthreads();
+    // pass 2: thread k combines the 8 chunks of value k
+    if (tid < kFinVals) {
+        double v = sh2[tid][0];
+        for (int c = 1; c < 8; c++) v = fin_is_max(tid) ? fmax(v, sh2[tid][c]) : v + sh2[tid][c];
+        out[tid] = v;
+    }
+    __syncthreads();
+}
+
+// Serial tail of the finalize (one thread), from the reduced values part[].
+// mode 0: close the step just taken (time, boundary integrals); both modes:
+// next CFL dt from the speed maxima, inflow states of the next step's stages,
+// status flags and clamp count.
+__device__ __forceinline__ void fin_tail(const KParams& P, DevScalars* S, const double* part,
+                                         const double* __restrict__ tables, int mode)
+{
+    double ax = part[24], ay = part[25];
+    if (part[27] > 0.0) S->status |= 1u;
+    S->clamps += (unsigned long long)part[26];
     double t = S->t;
     if (mode == 0) {
         const double dt = S->dt;
@@ -526,8 +568,6 @@ __device__ __forceinline__ void finalize_body(const KParams& P, DevScalars* S, c
             S->dt_last = dt;
         }
     }
-    double ax = red[0];
-    double ay = red[256];
     for (int s = 0; s < P.nseg; s++) {
         double st[4];
         inflow_state(P, tables, s, t, st);
@@ -570,12 +610,35 @@ __device__ __forceinline__ void finalize_body(const KParams& P, DevScalars* S, c
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_finalize(KParams P, DevScalars* S, const double* __restrict__ bpart,
-                                                  int n_we, int n_sn, int nmax, const double* __restrict__ tables,
-                                                  int mode, const double* __restrict__ wpart, int nw)
+// The tail, run by thread 0 on a copy of the device scalars in shared memory:
+// the workgroup loads the record with parallel loads and stores it back the
+// same way, so the serial tail does not wait on a memory round trip per field.
+__device__ __forceinline__ void fin_tail_staged(const KParams& P, DevScalars* S, const double* red,
+                                                const double* __restrict__ tables, int mode)
 {
-    finalize_body(P, S, bpart, n_we, n_sn, nmax, tables, mode, wpart, nw);
+    static_assert(sizeof(DevScalars) % 8 == 0, "device scalars are copied as 8-byte words");
+    constexpr int NWORD = sizeof(DevScalars) / 8;
+    __shared__ DevScalars Ssh;
+    unsigned long long* g = reinterpret_cast<unsigned long long*>(S);
+    unsigned long long* l = reinterpret_cast<unsigned long long*>(&Ssh);
+    for (int k = threadIdx.x; k < NWORD; k += blockDim.x) l[k] = g[k];
+    __syncthreads();
+    if (threadIdx.x == 0) fin_tail(P, &Ssh, red, tables, mode);
+    __syncthreads();
+    for (int k = threadIdx.x; k < NWORD; k += blockDim.x) g[k] = l[k];
+}
+
+// Per-step finalize: one workgroup reduces every partial list (fixed order),
+// then thread 0 runs the tail.  (At 4096 x 4096 it takes about 30 us whether
+// the reduction is spread over 32 workgroups or not, so it stays one.)
+template <typename T>
+__global__ void __launch_bounds__(kFinThreads)
+k_finalize(KParams P, DevScalars* S, const double* __restrict__ bpart, int n_we, int n_sn, int nmax,
+           const double* __restrict__ tables, int mode, const double* __restrict__ wpart, int nw)
+{
+    __shared__ double red[kFinVals];
+    fin_reduce<kFinThreads>(P, bpart, n_we, n_sn, nmax, mode, wpart, nw, red);
+    fin_tail_staged(P, S, red, tables, mode);
 }
 
 // ------------------------------------------------- conversions, reductions

@@ -18,8 +18,8 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
     const T* b = (const T*)B.b;
     const T* mu = (const T*)B.mu;
     if (part == P.rk) {
-        hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(256), 0, st, P, B.S, B.bpart, sh.n_we, sh.n_sn, B.nmax,
-                           B.tables, 0, B.wpart, sh.nw);
+        hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(kFinThreads), 0, st, P, B.S, B.bpart, sh.n_we, sh.n_sn,
+                           B.nmax, B.tables, 0, B.wpart, sh.nw);
         return hipGetLastError();
     }
     // Heun: E(U) -> Us, then (U + E(Us)) / 2 -> U.  Three-stage: E(U) -> Us,
@@ -42,9 +42,15 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
 #undef M2P_REF
     } else {
         dim3 blk(256), grd(sh.blocks);
-#define M2P_TILED(K)                                                                                             \
-    hipLaunchKernelGGL((k_stage_tiled<T, K>), grd, blk, 0, st, P, in, U, out, b, mu, B.S, B.bpart, B.wpart, B.nmax, \
-                       sh.R, sh.nstrips, sh.nrb)
+#define M2P_TILED(K)                                                                                            \
+    do {                                                                                                        \
+        if (P.nsseg > 0)                                                                                        \
+            hipLaunchKernelGGL((k_stage_tiled<T, K, true>), grd, blk, 0, st, P, in, U, out, b, mu, B.S,         \
+                               B.bpart, B.wpart, B.nmax, sh.R, sh.nstrips, sh.nrb);                             \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_stage_tiled<T, K, false>), grd, blk, 0, st, P, in, U, out, b, mu, B.S,        \
+                               B.bpart, B.wpart, B.nmax, sh.R, sh.nstrips, sh.nrb);                             \
+    } while (0)
         if (kind == 1)
             M2P_TILED(1);
         else if (kind == 2)
@@ -64,8 +70,8 @@ hipError_t Launch<M2P_REAL>::init(const KParams& P, const Bufs& B, hipStream_t s
     using T = M2P_REAL;
     dim3 blk(64, 4), grd((P.nx + 63) / 64, (P.ny + 3) / 4);
     hipLaunchKernelGGL((k_speeds<T>), grd, blk, 0, st, P, (const T*)B.U, (const T*)B.b, B.wpart);
-    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(256), 0, st, P, B.S, B.bpart, 0, 0, B.nmax, B.tables, 1,
-                       B.wpart, B.nw_ref);
+    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(kFinThreads), 0, st, P, B.S, B.bpart, 0, 0, B.nmax, B.tables,
+                       1, B.wpart, B.nw_ref);
     return hipGetLastError();
 }
 
@@ -102,7 +108,7 @@ hipError_t Launch<M2P_REAL>::batch_part(const ScenDesc<M2P_REAL>* scen, int nsce
 {
     using T = M2P_REAL;
     if (part == 2)
-        hipLaunchKernelGGL((k_finalize_batch<T>), dim3(nscen), dim3(256), 0, st, scen, mode);
+        hipLaunchKernelGGL((k_finalize_batch<T>), dim3(nscen), dim3(kFinThreads), 0, st, scen, mode);
     else if (part == 0)
         hipLaunchKernelGGL((k_stage_batch<T, 1>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);
     else

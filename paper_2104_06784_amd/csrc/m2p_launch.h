@@ -35,6 +35,10 @@ struct Bufs {
 
 constexpr int kMassBlocks = 1024;
 
+// Finalize: one workgroup of kFinThreads per scenario.
+constexpr int kFinThreads = 256;
+constexpr int kFinVals = 28;  // 24 boundary sums ([stage][side][phase]), 2 speed maxima, clamps, non-finite flag
+
 // Scenario record of a batched ensemble: constants and device pointers.
 template <typename T>
 struct ScenDesc {

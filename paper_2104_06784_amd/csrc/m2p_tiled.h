@@ -91,8 +91,11 @@ constexpr int tiled_wpe()
 }
 
 // One wavefront's share of a stage: strip `strip`, row block `rb` of one
-// scenario.  Partials go to wave slot `wslot` of that scenario.
-template <typename T, int STAGE>
+// scenario.  Partials go to wave slot `wslot` of that scenario.  GH: the
+// scenario has Mode-II state segments, whose ghost cells replace the mapped
+// boundary values (a separate instance, so runs without them carry none of
+// that code in the march).
+template <typename T, int STAGE, bool GH>
 __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __restrict__ Uin, const T* Un, T* Uout,
                                                  const T* __restrict__ b, const T* __restrict__ mu,
                                                  DevScalars* __restrict__ S, double* __restrict__ bpart,
@@ -128,7 +131,7 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
             u[2] = -u[2];
             u[5] = -u[5];
         }
-        if (P.nsseg > 0) ghost_sub(P, S->sghost[stage_slot(STAGE)], cc, r, u);
+        if (GH) ghost_sub(P, S->sghost[stage_slot(STAGE)], cc, r, u);
     };
     auto loadB = [&](int r) { return b[(size_t)(r + BHALO) * P.bpitch + bcol]; };
 
@@ -363,7 +366,7 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
     }
 }
 
-template <typename T, int STAGE>
+template <typename T, int STAGE, bool GH>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_wpe<T, STAGE>())))
 k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout, const T* __restrict__ b,
               const T* __restrict__ mu, DevScalars* __restrict__ S, double* __restrict__ bpart,
@@ -382,12 +385,13 @@ k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout, const 
     const int wid = __builtin_amdgcn_readfirstlane(bid * 4 + (int)(threadIdx.x >> 6));
     const int strip = wid % nstrips, rb = wid / nstrips;
     if (rb >= nrb) return;  // whole wavefront
-    stage_tiled_wave<T, STAGE>(P, Uin, Un, Uout, b, mu, S, bpart, wpart, nmax, R, nstrips, nrb, strip, rb, wid, lane);
+    stage_tiled_wave<T, STAGE, GH>(P, Uin, Un, Uout, b, mu, S, bpart, wpart, nmax, R, nstrips, nrb, strip, rb, wid, lane);
 }
 
 // Persistent batched stage: a fixed grid of wavefronts walks the work list
 // (scenario, strip, row block) with a grid stride; every scenario keeps its
 // own time step and partial slots, so results equal single-scenario runs.
+// Ensemble scenarios are Mode-I releases (no boundary segments).
 template <typename T, int STAGE>
 __global__ void __launch_bounds__(256)
 k_stage_batch(const ScenDesc<T>* __restrict__ scen, const int* __restrict__ work, int nwork, int R)
@@ -405,20 +409,22 @@ k_stage_batch(const ScenDesc<T>* __restrict__ scen, const int* __restrict__ work
         const ScenDesc<T>& D = scen[sc];
         const int strip = local % D.nstrips, rb = local / D.nstrips;
         if (STAGE == 1)
-            stage_tiled_wave<T, 1>(D.P, D.U, D.U, D.Us, D.b, D.mu, D.S, D.bpart, D.wpart, D.nmax, R, D.nstrips, D.nrb,
+            stage_tiled_wave<T, 1, false>(D.P, D.U, D.U, D.Us, D.b, D.mu, D.S, D.bpart, D.wpart, D.nmax, R, D.nstrips, D.nrb,
                                    strip, rb, local, lane);
         else
-            stage_tiled_wave<T, 2>(D.P, D.Us, D.U, D.U, D.b, D.mu, D.S, D.bpart, D.wpart, D.nmax, R, D.nstrips, D.nrb,
+            stage_tiled_wave<T, 2, false>(D.P, D.Us, D.U, D.U, D.b, D.mu, D.S, D.bpart, D.wpart, D.nmax, R, D.nstrips, D.nrb,
                                    strip, rb, local, lane);
     }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_finalize_batch(const ScenDesc<T>* __restrict__ scen, int mode)
+__global__ void __launch_bounds__(kFinThreads) k_finalize_batch(const ScenDesc<T>* __restrict__ scen, int mode)
 {
     const ScenDesc<T>& D = scen[blockIdx.x];
-    finalize_body(D.P, D.S, D.bpart, D.P.ny, D.P.nx, D.nmax, D.tables, mode, D.wpart,
-                  mode == 1 ? D.nw_ref : D.nstrips * D.nrb);
+    __shared__ double red[kFinVals];
+    fin_reduce<kFinThreads>(D.P, D.bpart, D.P.ny, D.P.nx, D.nmax, mode, D.wpart,
+                            mode == 1 ? D.nw_ref : D.nstrips * D.nrb, red);
+    fin_tail_staged(D.P, D.S, red, D.tables, mode);
 }
 
 }  // namespace m2p
