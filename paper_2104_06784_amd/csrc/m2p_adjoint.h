@@ -949,15 +949,15 @@ __global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict_
 }
 
 // Pass C: lam_in(k) = DU(k) + all face and source contributions that land on
-// cell k through the ghost map, summed in a fixed order.
+// cell k through the ghost map, summed in a fixed order.  Cells two or more
+// away from every edge take a direct path (no ghost cell maps onto them);
+// the ring of edge cells walks the ghost map.  The two kinds of cell are
+// launched separately, so no wavefront mixes the paths.
 template <typename T>
-__global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restrict__ DU, const T* __restrict__ FCX,
-                                                    const T* __restrict__ FCY, const T* __restrict__ SC,
-                                                    T* __restrict__ lam_in)
+__device__ __forceinline__ void adj_gather_cell(const KParams& P, const T* __restrict__ DU, const T* __restrict__ FCX,
+                                                const T* __restrict__ FCY, const T* __restrict__ SC,
+                                                T* __restrict__ lam_in, int i, int j)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= P.nx) return;
     const size_t c = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
     // slot-major cotangent arrays (slot stride: number of faces or cells)
     const size_t nfx = (size_t)(P.nx + 1) * P.ny, nfy = (size_t)P.nx * (P.ny + 1), ncl = (size_t)P.nx * P.ny;
@@ -1042,6 +1042,111 @@ __global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restri
         }
     }
     for (int k = 0; k < NF; k++) lam_in[k * fs + c] = acc[k];
+}
+
+// Interior cells: i in [2, nx - 3], j in [2, ny - 3] (grid over that box).
+template <typename T>
+__global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restrict__ DU, const T* __restrict__ FCX,
+                                                    const T* __restrict__ FCY, const T* __restrict__ SC,
+                                                    T* __restrict__ lam_in)
+{
+    const int i = 2 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 2 + blockIdx.y;
+    if (i > P.nx - 3 || j > P.ny - 3) return;
+    adj_gather_cell(P, DU, FCX, FCY, SC, lam_in, i, j);
+}
+
+// Edge ring: the cells outside the interior box, enumerated as the bottom
+// two rows, the top two rows, then the two first and two last columns of the
+// rows between (every cell when the grid is narrower than five cells).
+__host__ __device__ inline long long adj_ring_cells(int nx, int ny)
+{
+    const int nbot = ny < 2 ? ny : 2, ntop = (ny - nbot) < 2 ? (ny - nbot) : 2, mid = ny - nbot - ntop;
+    const int ncol = nx <= 4 ? nx : 4;
+    return (long long)(nbot + ntop) * nx + (long long)mid * ncol;
+}
+
+// One wavefront per ring cell: the lanes share the candidate contributions
+// (24 x-face and 24 y-face (face, stencil position) pairs, 9 source cells x
+// 34 slots), keep those the ghost map sends to this cell, and the lanes'
+// partial sums are combined by a fixed butterfly (deterministic).
+template <typename T>
+__global__ void __launch_bounds__(128) k_adj_gather_ring(KParams P, const T* __restrict__ DU,
+                                                         const T* __restrict__ FCX, const T* __restrict__ FCY,
+                                                         const T* __restrict__ SC, T* __restrict__ lam_in)
+{
+    const long long r = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const int nx = P.nx, ny = P.ny;
+    if (r >= adj_ring_cells(nx, ny)) return;  // whole wavefront
+    const int nbot = ny < 2 ? ny : 2, ntop = (ny - nbot) < 2 ? (ny - nbot) : 2;
+    const int ncol = nx <= 4 ? nx : 4;
+    int i, j;
+    if (r < (long long)nbot * nx) {
+        j = (int)(r / nx);
+        i = (int)(r % nx);
+    } else if (r < (long long)(nbot + ntop) * nx) {
+        const long long r2 = r - (long long)nbot * nx;
+        j = ny - ntop + (int)(r2 / nx);
+        i = (int)(r2 % nx);
+    } else {
+        const long long r3 = r - (long long)(nbot + ntop) * nx;
+        j = nbot + (int)(r3 / ncol);
+        const int cc = (int)(r3 % ncol);
+        i = nx <= 4 ? cc : (cc < 2 ? cc : nx - 4 + cc);
+    }
+    const size_t fs = (size_t)ny * P.pitch;
+    const size_t nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1), ncl = (size_t)nx * ny;
+    T acc[NF];
+#pragma unroll
+    for (int k = 0; k < NF; k++) acc[k] = T(0);
+    for (int it = lane; it < 48 + 9 * 34; it += 64) {
+        if (it < 48) {
+            // face fi (x) or fj (y) within 3 cells, stencil position q
+            const int dir = it / 24, fo = (it % 24) / 4, q = it % 4;
+            const int n = dir == 0 ? nx : ny, self = dir == 0 ? i : j;
+            const int fl = self - 3 + fo;  // face index: face between fl and fl + 1
+            if (fl < -1 || fl > n - 1) continue;
+            int flip = 0;
+            const int m = dir == 0 ? map_index(fl - 1 + q, nx, P.bc[0], P.bc[1], flip)
+                                   : map_index(fl - 1 + q, ny, P.bc[2], P.bc[3], flip);
+            if (m != self) continue;
+            const T* f = dir == 0 ? FCX + ((size_t)j * (nx + 1) + (fl + 1)) : FCY + ((size_t)(fl + 1) * nx + i);
+            const size_t st = dir == 0 ? nfx : nfy;
+            const int kn0 = dir == 0 ? 1 : 2, kn1 = dir == 0 ? 4 : 5;  // normal momenta flip at walls
+#pragma unroll
+            for (int k = 0; k < NF; k++) {
+                const T v = f[(6 * q + k) * st];
+                acc[k] += (flip && (k == kn0 || k == kn1)) ? -v : v;
+            }
+        } else {
+            const int s2 = it - 48, nb = s2 / 34, sl = s2 % 34;
+            const int ci = i - 1 + nb % 3, cj = j - 1 + nb / 3;
+            if (ci < 0 || ci >= nx || cj < 0 || cj >= ny) continue;
+            int di, dj, k;
+            src_slot(sl, di, dj, k);
+            int fx = 0, fy = 0;
+            const int mi = map_index(ci + di, nx, P.bc[0], P.bc[1], fx);
+            const int mj = map_index(cj + dj, ny, P.bc[2], P.bc[3], fy);
+            if (mi != i || mj != j) continue;
+            T v = SC[(size_t)sl * ncl + (size_t)cj * nx + ci];
+            if (fx && (k == 1 || k == 4)) v = -v;
+            if (fy && (k == 2 || k == 5)) v = -v;
+#pragma unroll
+            for (int kk = 0; kk < NF; kk++) acc[kk] += kk == k ? v : T(0);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NF; k++)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+    if (lane < NF) {
+        T v = acc[0];
+#pragma unroll
+        for (int k = 1; k < NF; k++) v = lane == k ? acc[k] : v;
+        const size_t c = (size_t)j * P.pitch + i;
+        lam_in[lane * fs + c] = DU[lane * fs + c] + v;
+    }
 }
 
 // Loss 1/2 sum (h - h_target)^2 dx dy (h bed-normal, m) and its cotangent

@@ -142,8 +142,12 @@ hipError_t Launch<M2P_REAL>::vjp(const KParams& P, const Bufs& B, const void* U,
     hipLaunchKernelGGL((k_adj_face<T>), dim3((P.nx + 127) / 128, P.ny + 1), blk, 0, st, P, (const T*)U,
                        (const T*)GT, b, 1, T(dt), (T*)FCY);
     hipLaunchKernelGGL((k_adj_src<T>), grd, blk, 0, st, P, (const T*)U, (const T*)GT, b, T(dt), (T*)SC);
-    hipLaunchKernelGGL((k_adj_gather<T>), grd, blk, 0, st, P, (const T*)DU, (const T*)FCX, (const T*)FCY,
-                       (const T*)SC, (T*)lam_in);
+    if (P.nx >= 5 && P.ny >= 5)
+        hipLaunchKernelGGL((k_adj_gather<T>), dim3((P.nx - 4 + 127) / 128, P.ny - 4), blk, 0, st, P, (const T*)DU,
+                           (const T*)FCX, (const T*)FCY, (const T*)SC, (T*)lam_in);
+    const long long nring = adj_ring_cells(P.nx, P.ny);
+    hipLaunchKernelGGL((k_adj_gather_ring<T>), dim3((unsigned)((nring + 1) / 2)), blk, 0, st, P, (const T*)DU,
+                       (const T*)FCX, (const T*)FCY, (const T*)SC, (T*)lam_in);
     return hipGetLastError();
 }
 
