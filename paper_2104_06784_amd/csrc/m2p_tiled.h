@@ -20,10 +20,11 @@ namespace m2p {
 constexpr int kStripOut = 60;  // output columns per wavefront
 
 // Wavefront-wide shifts by one lane with DPP (wave_shl:1 / wave_shr:1, a
-// VALU move with no LDS round trip).  The edge lane without a source gets 0;
+// VALU move with no LDS round trip).  The edge lane without a source gets 0
+// from the bound control (no zeroed destination register needed first);
 // edge lanes are halo lanes whose results never reach an output column.
-__device__ __forceinline__ int dpp_right_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
-__device__ __forceinline__ int dpp_left_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_right_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_left_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
 
 __device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_right_i(__float_as_int(v))); }
 __device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_left_i(__float_as_int(v))); }
