@@ -104,7 +104,7 @@ M2P_FN T dsg(T num, T den, T md)
 }
 
 // The FP32 build evaluates some formulas in algebraically folded forms with
-// fewer operations: J_b c = 1 (c = 1/J_b, R1), so h^s = m^s c and
+// fewer operations: J_b c = 1 (c = n_Z = 1/J_b), so h^s = m^s c and
 // eps J_b h A N^s = eps (1 - alpha)/2 h h^s A; products of constants are
 // folded.  The FP64 build (bitwise parity with the FP64 oracle) and the
 // dual-number adjoint evaluate the formulas as written.
@@ -112,6 +112,24 @@ template <typename T>
 struct Folded : std::false_type {};
 template <>
 struct Folded<float> : std::true_type {};
+
+// Both ratios n1 / den and n2 / den, desingularised as dsg does.  The FP32
+// build computes the common factor 2 den / (den^2 + max(den^2, md^2)) once
+// (one multiplication per ratio instead of two).
+template <typename T>
+M2P_FN void dsg2(T n1, T n2, T den, T md, T& v1, T& v2)
+{
+    if constexpr (Folded<T>::value) {
+        const T d2 = den * den;
+        const T m2 = md * md;
+        const T sc = (den + den) / (d2 + (d2 > m2 ? d2 : m2));
+        v1 = n1 * sc;
+        v2 = n2 * sc;
+        return;
+    }
+    v1 = dsg(n1, den, md);
+    v2 = dsg(n2, den, md);
+}
 
 // 1 / sqrt(x): one hardware reciprocal square root in FP32 device code.
 template <typename T>
@@ -194,8 +212,9 @@ M2P_FN void side_flux(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d,
     if constexpr (Folded<T>::value) {
         const T ms = u[0], mf = u[3];
         const T hs = ms * g.c, hf = mf * g.c, h = hs + hf;
-        const T vXs = dsg(u[1], ms, K.md), vYs = dsg(u[2], ms, K.md);
-        const T vXf = dsg(u[4], mf, K.md), vYf = dsg(u[5], mf, K.md);
+        T vXs, vYs, vXf, vYf;
+        dsg2(u[1], u[2], ms, K.md, vXs, vYs);
+        dsg2(u[4], u[5], mf, K.md, vXf, vYf);
         const T Ax = d == 0 ? g.A11 : g.A21;
         const T Ay = d == 0 ? g.A12 : g.A22;
         const T Ann = d == 0 ? g.A11 : g.A22;
@@ -394,12 +413,11 @@ M2P_FN void sources(const Consts<T>& K, int flags, const T u[NF], const Geo<T>& 
         const T ms = u[0], mf = u[3];
         const T hs = ms * g.c, hf = mf * g.c, h = hs + hf;
         const T mt = ms + mf;
-        const T phis = dsg(ms, mt, K.md), phif = dsg(mf, mt, K.md);
+        T phis, phif;
+        dsg2(ms, mf, mt, K.md, phis, phif);
         T v[2][3];
-        v[0][0] = dsg(u[1], ms, K.md);
-        v[0][1] = dsg(u[2], ms, K.md);
-        v[1][0] = dsg(u[4], mf, K.md);
-        v[1][1] = dsg(u[5], mf, K.md);
+        dsg2(u[1], u[2], ms, K.md, v[0][0], v[0][1]);
+        dsg2(u[4], u[5], mf, K.md, v[1][0], v[1][1]);
 #pragma unroll
         for (int ph = 0; ph < 2; ph++) v[ph][2] = g.bX * v[ph][0] + g.bY * v[ph][1];
         T kap[2];
@@ -426,13 +444,13 @@ M2P_FN void sources(const Consts<T>& K, int flags, const T u[NF], const Geo<T>& 
         const T wf = (flags & 1) ? phif : phis;
         S.sf[1][0] = K.eps * wf * gx;
         S.sf[1][1] = K.eps * wf * gy;
-        const T Kd = K.c_d * g.J * phis * phif * h;
+        const T Kd = K.c_d * phis * phif * mt;  // J_b h = m^s + m^f
         const T dvx = v[1][0] - v[0][0], dvy = v[1][1] - v[0][1];
         S.sv[0][0] = K.al * Kd * dvx;
         S.sv[0][1] = K.al * Kd * dvy;
         S.sv[1][0] = -Kd * dvx;
         S.sv[1][1] = -Kd * dvy;
-        const T fr = K.k_fr * g.J * phif * h;
+        const T fr = K.k_fr * phif * mt;
         S.sd[0] = -fr * v[1][0];
         S.sd[1] = -fr * v[1][1];
         S.kappa_s = kap[0];

@@ -87,8 +87,7 @@ Row make_row(const Consts<Cnt>& K, const Cnt u[NF], int k)
     Row r;
     const Cnt bE = 0.011 + 0.001 * k, bW = 0.010, bN = 0.012, bS = 0.0105;
     r.g = geometry(bE, bW, bN, bS, K.two_dxi, K.two_deta);
-    r.u = dsg(u[4], u[3], K.md);
-    r.w = dsg(u[5], u[3], K.md);
+    dsg2(u[4], u[5], u[3], K.md, r.u, r.w);
     r.cdxu = cdiff(Cnt(r.u.v * 1.01), Cnt(r.u.v * 0.99), K.dxi);
     r.cdxw = cdiff(Cnt(r.w.v * 1.01), Cnt(r.w.v * 0.99), K.dxi);
     r.Jh = u[0] + u[3];

@@ -228,8 +228,7 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
             T u9[3][3], w9[3][3];
             for (int a = 0; a < 3; a++)
                 for (int c = 0; c < 3; c++) {
-                    u9[a][c] = dsg(c9[a][c][4], c9[a][c][3], K.md);
-                    w9[a][c] = dsg(c9[a][c][5], c9[a][c][3], K.md);
+                    dsg2(c9[a][c][4], c9[a][c][5], c9[a][c][3], K.md, u9[a][c], w9[a][c]);
                 }
             T JhC = uC[0] + uC[3];
             T JhW = row[1][0] + row[1][3], JhE = row[3][0] + row[3][3];

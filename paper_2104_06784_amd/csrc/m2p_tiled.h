@@ -58,8 +58,7 @@ __device__ __forceinline__ void make_row(const Consts<T>& K, const T u[NF], T bC
 {
     const T bE = from_right(bC), bW = from_left(bC);
     r.g = geometry(bE, bW, bN, bS, K.two_dxi, K.two_deta);
-    r.u = dsg(u[4], u[3], K.md);
-    r.w = dsg(u[5], u[3], K.md);
+    dsg2(u[4], u[5], u[3], K.md, r.u, r.w);
     const T uE = from_right(r.u), uW = from_left(r.u);
     const T wE = from_right(r.w), wW = from_left(r.w);
     r.cdxu = cdiff(uE, uW, K.dxi);
@@ -76,10 +75,10 @@ __device__ __forceinline__ void visc_yface_rows(const RowD<T>& a, const RowD<T>&
 
 // Occupancy hint of the FP32 single-scenario stage kernels (waves per SIMD
 // the register allocation must allow; 1 = no constraint).  Three waves (at
-// most 168 VGPRs) for every FP32 stage: stage 1 fits without spilling, the
-// later stages (which also carry U^n and the CFL speeds) spill one register
-// outside the march and run 8 % faster than at two waves.  The FP64 kernels
-// and the batched kernels keep the compiler's choice.
+// most 168 VGPRs) for every FP32 stage: they fit without spilling and the
+// later stages (which also carry U^n and the CFL speeds) run 8 % faster than
+// at two waves.  The FP64 kernels and the batched kernels keep the
+// compiler's choice.
 #ifndef M2P_TILED_WPE_S1
 #define M2P_TILED_WPE_S1 3
 #endif
