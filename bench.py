@@ -13,6 +13,7 @@ of the same workload.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -197,6 +198,53 @@ def bench_sweep(stream, steps: int) -> dict:
     return {"unit": "Mcell-steps/s", "steps": steps, "precision": "f32", "rows": rows}
 
 
+def bench_variants(stream, steps: int, prob3) -> dict:
+    """The scheme variants on their workloads: the three-stage Runge-Kutta
+    option on the large event (prob3, FP32), and Mode-II inflow as a state
+    hydrograph on the paper's second event's grid shape (180 x 154, graph
+    replay) next to the same grid without the segment."""
+    import torch
+
+    from paper_2104_06784_amd import inputs
+    from paper_2104_06784_amd.sim import Sim
+
+    def timed(sim, k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.run(k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if sim.diag()["status"] != 0:
+            raise SystemExit("device status in the variants leg")
+        return e0.elapsed_time(e1)
+
+    out = {}
+    p3 = dataclasses.replace(prob3, params=dataclasses.replace(prob3.params, flags=inputs.F_RK3))
+    sim = Sim(p3, precision="f32", stream=stream)
+    sim.run(5)
+    ms = timed(sim, steps)
+    out["rk3"] = {"value": round(p3.cells * steps / (ms / 1e3) / 1e6, 2), "unit": "Mcell-steps/s",
+                  "ms_per_step": round(ms / steps, 4), "steps": steps, "cells": p3.cells}
+    del sim
+    pd = inputs.df004_shaped()
+    k = 50 * steps
+    rec = {"nx": pd.nx, "ny": pd.ny, "steps": k}
+    for key, prob in (("state_inflow", pd), ("no_inflow", dataclasses.replace(pd, inflow_states=[]))):
+        sim = Sim(prob, precision="f32", stream=stream)
+        sim.run(64)
+        ms = timed(sim, k)
+        rec[key + "_us_per_step"] = round(ms * 1e3 / k, 2)
+        if key == "state_inflow":
+            d = sim.diag()
+            rec["simulated_s"] = round(d["t"], 2)
+            rec["inflow_m3"] = round(-(d["out_s"] + d["out_f"]), 1)  # state segments: negative outflow
+        del sim
+    out["mode2_state"] = rec
+    log(f"[bench] variants: rk3 {out['rk3']['value']} Mcell-steps/s; state inflow "
+        f"{rec['state_inflow_us_per_step']} us/step ({rec['no_inflow_us_per_step']} without)")
+    return out
+
+
 def bench_adjoint(stream, nsteps: int, ckpt: int) -> dict:
     """Config 5: gradient of the deposit misfit with respect to the per-cell
     friction field and the release volume through nsteps FP32 steps
@@ -250,6 +298,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=50, help="0 skips the batched-ensemble measurement")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="0 skips the forward+adjoint measurement")
     ap.add_argument("--sweep-steps", type=int, default=1000, help="0 skips the mesh-size sweep")
+    ap.add_argument("--variant-steps", type=int, default=30,
+                    help="RK3 steps on the large event (x50 on the Mode-II grid); 0 skips the variants")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run 3 device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -341,6 +391,8 @@ def main():
             f"({out['fwd_adjoint']['cost_vs_forward']:.1f}x the forward)")
     if args.sweep_steps > 0:
         out["mesh_sweep"] = bench_sweep(stream, args.sweep_steps)
+    if args.variant_steps > 0:
+        out["variants"] = bench_variants(stream, args.variant_steps, prob)
     if args.copy_probe_mib > 0:
         # plain device-to-device copies of known size, so that hardware byte
         # counters of the step kernels can be calibrated against them

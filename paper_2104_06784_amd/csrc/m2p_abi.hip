@@ -630,6 +630,7 @@ static int upload_tables(m2p_ctx* c)
     tab.insert(tab.end(), c->tab_state.begin(), c->tab_state.end());
     KParams& K = c->kp;
     for (int s = 0; s < K.nsseg; s++) K.sseg[s].toff = shift + c->state_toff[s];
+    K.ntab = (int)tab.size();
     HIPCHK(hipStreamSynchronize(c->stream));
     if (c->tables) (void)hipFree(c->tables);
     c->tables = nullptr;

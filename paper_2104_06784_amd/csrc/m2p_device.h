@@ -40,6 +40,7 @@ struct KParams {
     int nsseg;
     int rk;                 // stages per step: 2 (Heun) or 3 (SSP Runge-Kutta)
     SegDesc sseg[MAX_SEG];  // Mode-II segments with a state hydrograph (ghost cells)
+    int ntab;               // doubles in the hydrograph table of both kinds of segment
 };
 
 // Scalars that live on the device across steps (time, dt, reductions).

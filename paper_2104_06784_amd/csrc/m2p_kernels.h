@@ -352,15 +352,28 @@ __global__ void __launch_bounds__(256) k_speeds(KParams P, const T* __restrict__
 
 // ------------------------------------------------------------- finalize
 
-__device__ __forceinline__ double interp_table(const double* t, const double* y, int n, double tau)
+// Piecewise-linear table lookup: the bracket of tau in the time column
+// (held at the end values outside it), then the value of any column.
+struct Bracket {
+    int k;
+    double w;
+    bool end;  // tau outside the table: the value is y[k]
+};
+
+__device__ __forceinline__ Bracket table_bracket(const double* t, int n, double tau)
 {
-    if (tau <= t[0]) return y[0];
-    if (tau >= t[n - 1]) return y[n - 1];
+    if (tau <= t[0]) return {0, 0.0, true};
+    if (tau >= t[n - 1]) return {n - 1, 0.0, true};
     int k = 0;
     while (k + 1 < n && t[k + 1] < tau) k++;
-    double w = (tau - t[k]) / (t[k + 1] - t[k]);
-    return y[k] + w * (y[k + 1] - y[k]);
+    return {k, (tau - t[k]) / (t[k + 1] - t[k]), false};
 }
+
+__device__ __forceinline__ double table_at(const double* y, const Bracket& b)
+{
+    return b.end ? y[b.k] : y[b.k] + b.w * (y[b.k + 1] - y[b.k]);
+}
+
 
 // Critical-depth inflow state of a segment at dimensionless time tau:
 // q (discharge per unit width), m_in = (q^2/eps)^(1/3), v_in = q / m_in, phi.
@@ -371,9 +384,9 @@ __device__ __forceinline__ void inflow_state(const KParams& P, const double* tab
     const double* t = tables + d.toff;
     const double* Q = t + d.nt;
     const double* ph = Q + d.nt;
-    double tau = tau_nd * P.T;
-    double Qv = interp_table(t, Q, d.nt, tau);
-    double phv = interp_table(t, ph, d.nt, tau);
+    const Bracket br = table_bracket(t, d.nt, tau_nd * P.T);
+    double Qv = table_at(Q, br);
+    double phv = table_at(ph, br);
     double w = (d.side < 2) ? P.dy : P.dx;
     double qs = Qv / ((double)d.ncells * w);
     double qn = qs / (P.H * P.V);
@@ -407,10 +420,10 @@ __device__ __forceinline__ void ghost_state(const KParams& P, const double* tabl
     const double* h = t + d.nt;
     const double* phi = h + d.nt;
     const double* vel = phi + d.nt;
-    double tau = tau_nd * P.T;
-    double m = interp_table(t, h, d.nt, tau) / P.H;
-    double ph = interp_table(t, phi, d.nt, tau);
-    double v = interp_table(t, vel, d.nt, tau) / P.V;
+    const Bracket br = table_bracket(t, d.nt, tau_nd * P.T);  // one search for the three columns
+    double m = table_at(h, br) / P.H;
+    double ph = table_at(phi, br);
+    double v = table_at(vel, br) / P.V;
     m_out = m;
     v_out = v;
     double ex = d.side == 0 ? 1.0 : (d.side == 1 ? -1.0 : 0.0);
@@ -568,7 +581,7 @@ __device__ __forceinline__ void fin_tail(const KParams& P, DevScalars* S, const 
         }
     }
     for (int s = 0; s < P.nseg; s++) {
-        double st[4];
+        double* st = S->inflow[0][s];  // the first stage's inflow state
         inflow_state(P, tables, s, t, st);
         double a = st[2] + sqrt(P.eps * st[1]);
         if (P.seg[s].side < 2) {
@@ -577,8 +590,8 @@ __device__ __forceinline__ void fin_tail(const KParams& P, DevScalars* S, const 
             ay = a;
     }
     for (int s = 0; s < P.nsseg; s++) {
-        double u[NF], m, v;
-        ghost_state(P, tables, s, t, u, m, v);
+        double m, v;
+        ghost_state(P, tables, s, t, S->sghost[0][s], m, v);  // also the first stage's ghost state
         double a = fabs(v) + sqrt(P.eps * m);
         if (P.sseg[s].side < 2) {
             if (a > ax) ax = a;
@@ -597,13 +610,11 @@ __device__ __forceinline__ void fin_tail(const KParams& P, DevScalars* S, const 
     S->dt = dt;
     // stage times: t, t + dt, and t + dt/2 for the third Runge-Kutta stage
     for (int s = 0; s < P.nseg; s++) {
-        inflow_state(P, tables, s, t, S->inflow[0][s]);
         inflow_state(P, tables, s, t + dt, S->inflow[1][s]);
         if (P.rk == 3) inflow_state(P, tables, s, t + 0.5 * dt, S->inflow[2][s]);
     }
     for (int s = 0; s < P.nsseg; s++) {
         double m, v;
-        ghost_state(P, tables, s, t, S->sghost[0][s], m, v);
         ghost_state(P, tables, s, t + dt, S->sghost[1][s], m, v);
         if (P.rk == 3) ghost_state(P, tables, s, t + 0.5 * dt, S->sghost[2][s], m, v);
     }
@@ -630,14 +641,23 @@ __device__ __forceinline__ void fin_tail_staged(const KParams& P, DevScalars* S,
 // Per-step finalize: one workgroup reduces every partial list (fixed order),
 // then thread 0 runs the tail.  (At 4096 x 4096 it takes about 30 us whether
 // the reduction is spread over 32 workgroups or not, so it stays one.)
+// The hydrograph tables of the Mode-II segments are copied into shared memory
+// first when they fit (the tail's table lookups are serial searches, each
+// step of which would otherwise wait on device memory).
+constexpr int kFinTabLds = 2048;
+
 template <typename T>
 __global__ void __launch_bounds__(kFinThreads)
 k_finalize(KParams P, DevScalars* S, const double* __restrict__ bpart, int n_we, int n_sn, int nmax,
            const double* __restrict__ tables, int mode, const double* __restrict__ wpart, int nw)
 {
     __shared__ double red[kFinVals];
+    __shared__ double tab[kFinTabLds];
+    const bool lds_tab = P.ntab > 0 && P.ntab <= kFinTabLds;
+    if (lds_tab)
+        for (int k = threadIdx.x; k < P.ntab; k += blockDim.x) tab[k] = tables[k];
     fin_reduce<kFinThreads>(P, bpart, n_we, n_sn, nmax, mode, wpart, nw, red);
-    fin_tail_staged(P, S, red, tables, mode);
+    fin_tail_staged(P, S, red, lds_tab ? tab : tables, mode);
 }
 
 // ------------------------------------------------- conversions, reductions

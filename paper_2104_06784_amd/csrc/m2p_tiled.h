@@ -117,6 +117,9 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
     const double(*inf)[4] = S->inflow[stage_slot(STAGE)];
     const bool ownW = out_lane && col == 0;  // this lane owns the W / E boundary face
     const bool ownE = out_lane && col == P.nx - 1;
+    // side whose ghost columns this strip holds when it holds one side's only
+    // (wave-uniform): W for the first strip, E for the last, else none
+    const int edge_side = nstrips == 1 ? -1 : (strip == 0 ? 0 : (strip == nstrips - 1 ? 1 : -1));
 
     auto loadU = [&](int r, T u[NF]) {
         int fy = 0;
@@ -132,7 +135,28 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
             u[2] = -u[2];
             u[5] = -u[5];
         }
-        if (GH) ghost_sub(P, S->sghost[stage_slot(STAGE)], cc, r, u);
+        // only cells outside the grid can be ghosts of a state segment (for
+        // interior strips and rows the branch is skipped by the whole wave).
+        // The W / E ghost columns of an edge strip in a grid row all face one
+        // segment, found from wave-uniform values, so its state is read with
+        // scalar loads; ghost rows and single-strip grids take the general
+        // per-lane lookup.
+        if constexpr (GH) {
+            const bool grow = (unsigned)r >= (unsigned)P.ny;
+            const bool gcol = (unsigned)cc >= (unsigned)P.nx;
+            if (!grow && edge_side >= 0) {
+                if (gcol) {
+                    const int sg = state_seg_at(P, edge_side, r);
+                    if (sg >= 0) {
+                        const double* g = S->sghost[stage_slot(STAGE)][sg];
+#pragma unroll
+                        for (int k = 0; k < NF; k++) u[k] = T(g[k]);
+                    }
+                }
+            } else if (grow || gcol) {
+                ghost_sub(P, S->sghost[stage_slot(STAGE)], cc, r, u);
+            }
+        }
     };
     auto loadB = [&](int r) { return b[(size_t)(r + BHALO) * P.bpitch + bcol]; };
 

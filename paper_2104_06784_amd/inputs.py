@@ -282,3 +282,20 @@ def paper_shaped(nx: int, ny: int, seed: int = 4000, precision: str = "f32") -> 
     h = cylinder(nx, ny, dx, dx, 0.3 * nx * dx, 0.5 * ny * dx, 0.15 * min(nx, ny) * dx, 10.0)
     return Problem(f"paper_{nx}x{ny}", nx, ny, dx, dx, Params(), dem, h,
                    np.where(h > 0, 0.5, 0.0), steps=10000, precision=precision)
+
+
+def df004_shaped(precision: str = "f32") -> Problem:
+    """Mode-II stand-in with the shape of the paper's second event (180 x 154
+    cells of 5 m, inflow given as a state hydrograph on 30 boundary cells,
+    12 minutes): a tilted fractal valley side, dry at the start, fed through
+    30 cells of the west edge by a synthetic hydrograph (thickness rising to
+    3 m at 2 min and falling to zero at 12 min, solid fraction 0.5, inward
+    speed 2 -> 5 -> 1 m/s).  The event's DEM and measured hydrograph are not
+    available; only the shapes are taken from the paper."""
+    nx, ny, dx = 180, 154, 5.0
+    dem = fractal_dem(nx, dx, 4004, 30.0, tilt_deg=15.0, ny=ny)
+    z = np.zeros((ny, nx))
+    seg = InflowState(SIDE_W, 62, 30, np.array([0.0, 120.0, 720.0]), np.array([0.0, 3.0, 0.0]),
+                      np.array([0.5, 0.5, 0.5]), np.array([2.0, 5.0, 1.0]))
+    return Problem("df004_shaped", nx, ny, dx, dx, Params(), dem, z, z.copy(), inflow_states=[seg],
+                   steps=0, precision=precision)
