@@ -163,8 +163,8 @@ Shape make_shape(const KParams& P, int variant, int rows)
         s.nw = s.nbx * s.nby;
         s.blocks = s.nbx * s.nby;
     } else {
-        s.nw = s.nstrips * s.nrb;
-        s.blocks = (s.nw + 3) / 4;
+        s.blocks = (s.nstrips * s.nrb + 3) / 4;
+        s.nw = s.blocks;  // one partial record per workgroup of four wavefronts
     }
     return s;
 }

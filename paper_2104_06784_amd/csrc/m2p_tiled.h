@@ -91,17 +91,22 @@ constexpr int tiled_wpe()
     return sizeof(T) == 4 ? (STAGE == 1 ? M2P_TILED_WPE_S1 : M2P_TILED_WPE_S2) : 1;
 }
 
+// Partials of one wavefront's share of a stage: speed maxima (last stage),
+// positivity-clamp count, non-finite flag.
+struct WavePart {
+    double ax, ay, cl, bd;
+};
+
 // One wavefront's share of a stage: strip `strip`, row block `rb` of one
-// scenario.  Partials go to wave slot `wslot` of that scenario.  GH: the
+// scenario; returns its partials (the same in every lane).  GH: the
 // scenario has Mode-II state segments, whose ghost cells replace the mapped
 // boundary values (a separate instance, so runs without them carry none of
 // that code in the march).
 template <typename T, int STAGE, bool GH>
-__device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __restrict__ Uin, const T* Un, T* Uout,
+__device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* __restrict__ Uin, const T* Un, T* Uout,
                                                  const T* __restrict__ b, const T* __restrict__ mu,
                                                  DevScalars* __restrict__ S, double* __restrict__ bpart,
-                                                 double* __restrict__ wpart, int nmax, int R, int nstrips, int nrb,
-                                                 int strip, int rb, int wslot, int lane)
+                                                 int nmax, int R, int nstrips, int nrb, int strip, int rb, int lane)
 {
     const Consts<T> K(P);
     const size_t fs = (size_t)P.ny * P.pitch;
@@ -382,13 +387,7 @@ __device__ __forceinline__ void stage_tiled_wave(const KParams& P, const T* __re
         clamps += __shfl_xor(clamps, off, 64);
         bad |= __shfl_xor(bad, off, 64);
     }
-    if (lane == 0) {
-        double* wp = wpart + ((size_t)st * nstrips * nrb + wslot) * 4;
-        wp[0] = (double)amx;
-        wp[1] = (double)amy;
-        wp[2] = (double)clamps;
-        wp[3] = (double)bad;
-    }
+    return WavePart{(double)amx, (double)amy, (double)clamps, (double)bad};
 }
 
 template <typename T, int STAGE, bool GH>
@@ -407,10 +406,33 @@ k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout, const 
     const int lane = threadIdx.x & 63;
     // wavefront-uniform by construction; readfirstlane lets the compiler keep
     // the strip, row bounds and loop control in scalar registers
-    const int wid = __builtin_amdgcn_readfirstlane(bid * 4 + (int)(threadIdx.x >> 6));
+    const int w = threadIdx.x >> 6;
+    const int wid = __builtin_amdgcn_readfirstlane(bid * 4 + w);
     const int strip = wid % nstrips, rb = wid / nstrips;
-    if (rb >= nrb) return;  // whole wavefront
-    stage_tiled_wave<T, STAGE, GH>(P, Uin, Un, Uout, b, mu, S, bpart, wpart, nmax, R, nstrips, nrb, strip, rb, wid, lane);
+    WavePart r{0.0, 0.0, 0.0, 0.0};  // neutral: speeds are >= 0
+    if (rb < nrb)  // whole wavefront
+        r = stage_tiled_wave<T, STAGE, GH>(P, Uin, Un, Uout, b, mu, S, bpart, nmax, R, nstrips, nrb, strip, rb, lane);
+    // one partial record per workgroup (its four wavefronts in order), so
+    // the finalize reads a quarter as many (at 4096 x 4096 the finalize
+    // takes 30 instead of 42 us; the barrier costs small grids about 0.4 us
+    // per stage)
+    __shared__ WavePart wsh[4];
+    if (lane == 0) wsh[w] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        WavePart a = wsh[0];
+        for (int q = 1; q < 4; q++) {
+            a.ax = fmax(a.ax, wsh[q].ax);
+            a.ay = fmax(a.ay, wsh[q].ay);
+            a.cl += wsh[q].cl;
+            a.bd = fmax(a.bd, wsh[q].bd);
+        }
+        double* wp = wpart + ((size_t)stage_slot(STAGE) * nblk + bid) * 4;
+        wp[0] = a.ax;
+        wp[1] = a.ay;
+        wp[2] = a.cl;
+        wp[3] = a.bd;
+    }
 }
 
 // Persistent batched stage: a fixed grid of wavefronts walks the work list
@@ -433,12 +455,18 @@ k_stage_batch(const ScenDesc<T>* __restrict__ scen, const int* __restrict__ work
         const int sc = item >> 20, local = item & 0xfffff;
         const ScenDesc<T>& D = scen[sc];
         const int strip = local % D.nstrips, rb = local / D.nstrips;
-        if (STAGE == 1)
-            stage_tiled_wave<T, 1, false>(D.P, D.U, D.U, D.Us, D.b, D.mu, D.S, D.bpart, D.wpart, D.nmax, R, D.nstrips, D.nrb,
-                                   strip, rb, local, lane);
-        else
-            stage_tiled_wave<T, 2, false>(D.P, D.Us, D.U, D.U, D.b, D.mu, D.S, D.bpart, D.wpart, D.nmax, R, D.nstrips, D.nrb,
-                                   strip, rb, local, lane);
+        const WavePart r =
+            STAGE == 1 ? stage_tiled_wave<T, 1, false>(D.P, D.U, D.U, D.Us, D.b, D.mu, D.S, D.bpart, D.nmax, R,
+                                                       D.nstrips, D.nrb, strip, rb, lane)
+                       : stage_tiled_wave<T, 2, false>(D.P, D.Us, D.U, D.U, D.b, D.mu, D.S, D.bpart, D.nmax, R,
+                                                       D.nstrips, D.nrb, strip, rb, lane);
+        if (lane == 0) {  // one record per work item (wave slot `local` of the scenario)
+            double* wp = D.wpart + ((size_t)stage_slot(STAGE) * D.nstrips * D.nrb + local) * 4;
+            wp[0] = r.ax;
+            wp[1] = r.ay;
+            wp[2] = r.cl;
+            wp[3] = r.bd;
+        }
     }
 }
 
