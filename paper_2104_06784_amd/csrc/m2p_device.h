@@ -298,6 +298,34 @@ M2P_FN void side_speed(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d
     a[1] = fabs(vnf) + sqrt(cf > T(0) ? cf : T(0));
 }
 
+// CFL speeds of a cell in both directions, each the maximum over the phases
+// of side_speed.  The FP32 forms compute the velocity ratios in pairs (one
+// desingularisation factor per phase); otherwise side_speed twice.
+template <typename T>
+M2P_FN void cell_speeds(const Consts<T>& K, const T u[NF], const Geo<T>& g, T& ax, T& ay)
+{
+    if constexpr (Folded<T>::value) {
+        const T ms = u[0], mf = u[3];
+        const T hs = ms * g.c, hf = mf * g.c, h = hs + hf;
+        T vXs, vYs, vXf, vYf;
+        dsg2(u[1], u[2], ms, K.md, vXs, vYs);
+        dsg2(u[4], u[5], mf, K.md, vXf, vYf);
+        const T hhs = K.half_oma * (h + hs);
+        const T acx = K.eps * g.A11 * g.c, acy = K.eps * g.A22 * g.c;
+        const T csx = acx * hhs, cfx = acx * h, csy = acy * hhs, cfy = acy * h;
+        const T axs = fabs(vXs) + sqrt(csx > T(0) ? csx : T(0)), axf = fabs(vXf) + sqrt(cfx > T(0) ? cfx : T(0));
+        const T ays = fabs(vYs) + sqrt(csy > T(0) ? csy : T(0)), ayf = fabs(vYf) + sqrt(cfy > T(0) ? cfy : T(0));
+        ax = axs > axf ? axs : axf;
+        ay = ays > ayf ? ays : ayf;
+        return;
+    }
+    T a[2];
+    side_speed(K, u, g, 0, a);
+    ax = a[0] > a[1] ? a[0] : a[1];
+    side_speed(K, u, g, 1, a);
+    ay = a[0] > a[1] ? a[0] : a[1];
+}
+
 // Central (Kurganov-Tadmor) flux per phase: (F- + F+)/2 - a/2 (U+ - U-).
 template <typename T>
 M2P_FN void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,

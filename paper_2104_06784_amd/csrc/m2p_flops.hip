@@ -9,7 +9,7 @@
 // quantities, one x-face and one y-face flux (each face belongs to one cell),
 // one new neighbour difference per direction and field (the other one is the
 // neighbour's), the sources, the viscous face terms, the update and, in
-// stage 2, the Heun average and the CFL speeds.  Shuffles, loads, stores,
+// stage 2, the Heun average and the CFL speeds (cell_speeds).  Shuffles, loads, stores,
 // index arithmetic and the FP64 partial sums are not floating-point work of
 // the scheme and are not counted.  The values describe a wet, sliding cell,
 // so the Coulomb clamp takes its longer branch.  The formulas are counted in
@@ -174,11 +174,10 @@ void cell_stage(const Consts<Cnt>& K, int stage, bool visc, int flags)
     update_cell(K, Uc, D0.g, HxL, Hx, Hy, HyN, Sr, svx, svy, dt, tmu, out);
     if (stage == 2) {
         for (int k = 0; k < NF; k++) out[k] = Cnt(0.5) * (unr[k] + out[k]);
-        Cnt a[2], amx = 0.0, amy = 0.0;
-        side_speed(K, out, D0.g, 0, a);
-        amx = fmax(amx, a[0] > a[1] ? a[0] : a[1]);
-        side_speed(K, out, D0.g, 1, a);
-        amy = fmax(amy, a[0] > a[1] ? a[0] : a[1]);
+        Cnt sx, sy, amx = 0.0, amy = 0.0;
+        cell_speeds(K, out, D0.g, sx, sy);
+        amx = fmax(amx, sx);
+        amy = fmax(amy, sy);
     }
 }
 

@@ -354,11 +354,10 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
                 for (int k = 0; k < NF; k++) out[k] = stage_combine<STAGE>(unr[k], out[k]);
             }
             if (stage_last(STAGE)) {
-                T a[2];
-                side_speed(K, out, D0.g, 0, a);
-                amx = fmax(amx, a[0] > a[1] ? a[0] : a[1]);
-                side_speed(K, out, D0.g, 1, a);
-                amy = fmax(amy, a[0] > a[1] ? a[0] : a[1]);
+                T sx, sy;
+                cell_speeds(K, out, D0.g, sx, sy);
+                amx = fmax(amx, sx);
+                amy = fmax(amy, sy);
             }
 #pragma unroll
             for (int k = 0; k < NF; k++) {

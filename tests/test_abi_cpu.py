@@ -114,16 +114,17 @@ def test_stage_flop_count():
     Viscous term on minus off: two face fluxes (13 add, 16 mul, 2 div each),
     two y central differences (1 add, 1 mul, 1 div each), the two divergences
     (3 add, 2 div each) and two prefactors (3 mul each): 34 add, 40 mul,
-    10 div.  Stage 2 minus stage 1: the Heun average (6 add, 6 mul) and two
-    speed evaluations (thicknesses 2 mul 1 add; two desingularised velocities
-    1 add 4 mul 1 div 1 cmp each; eps A_nn c 2 mul; the two squared speeds
-    3 mul 1 add; |v| + sqrt(max(., 0)) twice: 2 add 2 sqrt 2 cmp), each with
-    its maximum over the phases and the running maximum (2 cmp):
-    18 add, 36 mul, 4 div, 4 sqrt, 12 cmp."""
+    10 div.  Stage 2 minus stage 1: the Heun average (6 add, 6 mul) and the
+    cell's speeds in both directions (thicknesses 2 mul 1 add; two pairs of
+    desingularised velocities, 2 add 4 mul 1 div 1 cmp per pair;
+    (1 - alpha)/2 (h + h^s) 1 add 1 mul; eps A_nn c twice, 4 mul; the four
+    squared speeds 4 mul; |v| + sqrt(max(., 0)) four times: 4 add 4 sqrt
+    4 cmp; the maxima over the phases and the running maxima, 4 cmp):
+    16 add, 25 mul, 2 div, 4 sqrt, 10 cmp."""
     f10, f11, f20, f21 = _flops(1, 0), _flops(1, 1), _flops(2, 0), _flops(2, 1)
     assert np.array_equal(f11 - f10, [34, 40, 10, 0, 0])
     assert np.array_equal(f21 - f20, [34, 40, 10, 0, 0])
-    assert np.array_equal(f20 - f10, [18, 36, 4, 4, 12])
+    assert np.array_equal(f20 - f10, [16, 25, 2, 4, 10])
     # square roots: 4 face sides x 2 phase speeds, the new row's geometry, the
     # norm of the solid momentum in the Coulomb clamp
     assert f10[3] == 10
