@@ -192,14 +192,15 @@ struct Consts {
     T eps, al, oma, md, eps_chi, tan_d, c_d, inv_n_r, theta_b;
     T dxi, deta, two_dxi, two_deta;
     // folded constants of the FP32 forms: eps (1 - alpha) / 2, eps / 2,
-    // (1 - alpha) / 2, -eps alpha, theta_b / (N_R eps)
-    T k_ps, k_pf, half_oma, m_eps_al, k_fr;
+    // (1 - alpha) / 2, -eps alpha, theta_b / (N_R eps), 1 / (2 dxi), 1 / (2 deta)
+    T k_ps, k_pf, half_oma, m_eps_al, k_fr, half_rdxi, half_rdeta;
     M2P_FN explicit Consts(const KParams& P)
         : eps(T(P.eps)), al(T(P.alpha)), oma(T(P.one_m_alpha)), md(T(P.md)), eps_chi(T(P.eps_chi)),
           tan_d(T(P.tan_d)), c_d(T(P.c_d)), inv_n_r(T(P.inv_n_r)), theta_b(T(P.theta_b)),
           dxi(T(P.dxi)), deta(T(P.deta)), two_dxi(T(P.two_dxi)), two_deta(T(P.two_deta)),
           k_ps(T(P.eps * (1.0 - P.alpha) / 2.0)), k_pf(T(P.eps / 2.0)), half_oma(T((1.0 - P.alpha) / 2.0)),
-          m_eps_al(T(-P.eps * P.alpha)), k_fr(T(P.theta_b * P.inv_n_r / P.eps)) {}
+          m_eps_al(T(-P.eps * P.alpha)), k_fr(T(P.theta_b * P.inv_n_r / P.eps)), half_rdxi(T(0.5 / P.dxi)),
+          half_rdeta(T(0.5 / P.deta)) {}
 };
 
 
@@ -326,8 +327,18 @@ M2P_FN void cell_speeds(const Consts<T>& K, const T u[NF], const Geo<T>& g, T& a
     ay = a[0] > a[1] ? a[0] : a[1];
 }
 
-// Central (Kurganov-Tadmor) flux per phase: (F- + F+)/2 - a/2 (U+ - U-).
-template <typename T>
+// Face fluxes may be carried as twice the flux (H2, FP32 forms only): the
+// factor 1/2 is then applied once where a face flux is used (the update,
+// the boundary outflow slots) instead of once per component and face.
+template <typename T, bool H2>
+constexpr bool carry_2h()
+{
+    return H2 && Folded<T>::value;
+}
+
+// Central (Kurganov-Tadmor) flux per phase: (F- + F+)/2 - a/2 (U+ - U-)
+// (twice that when carried as 2 H).
+template <typename T, bool H2 = false>
 M2P_FN void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
                                              const T uR[NF], const Geo<T>& gR, int d, T H[NF])
 {
@@ -338,13 +349,18 @@ M2P_FN void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
     for (int ph = 0; ph < 2; ph++) {
         T a = aL[ph] > aR[ph] ? aL[ph] : aR[ph];
 #pragma unroll
-        for (int k = 3 * ph; k < 3 * ph + 3; k++) H[k] = T(0.5) * (FL[k] + FR[k]) - T(0.5) * a * (qR[k] - qL[k]);
+        for (int k = 3 * ph; k < 3 * ph + 3; k++) {
+            if constexpr (carry_2h<T, H2>())
+                H[k] = (FL[k] + FR[k]) - a * (qR[k] - qL[k]);
+            else
+                H[k] = T(0.5) * (FL[k] + FR[k]) - T(0.5) * a * (qR[k] - qL[k]);
+        }
     }
 }
 
 // Prescribed Mode-II face flux from the critical-depth inflow state
 // (q, m_in, v_in, phi); sgn = +1 on W/S (inward +X/+Y), -1 on E/N.
-template <typename T>
+template <typename T, bool H2 = false>
 M2P_FN void inflow_flux(const Consts<T>& K, const Geo<T>& g, int d, int sgn, T q, T m_in,
                                             T v_in, T phi, T H[NF])
 {
@@ -358,6 +374,10 @@ M2P_FN void inflow_flux(const Consts<T>& K, const Geo<T>& g, int d, int sgn, T q
     H[2] = K.eps * g.J * h * Ay * Ns + (d == 1 ? qs * v_in : T(0));
     H[4] = K.eps * g.J * h * Ax * pf + (d == 0 ? qf * v_in : T(0));
     H[5] = K.eps * g.J * h * Ay * pf + (d == 1 ? qf * v_in : T(0));
+    if constexpr (carry_2h<T, H2>()) {
+#pragma unroll
+        for (int k = 0; k < NF; k++) H[k] = H[k] + H[k];
+    }
 }
 
 // Viscous flux pieces at one face: J_b h and A_ij averaged over the two
@@ -528,11 +548,31 @@ M2P_FN void sources(const Consts<T>& K, int flags, const T u[NF], const Geo<T>& 
 // Tentative forward-Euler update of one cell from its four face fluxes and
 // its sources (summation order: x-difference, y-difference, then s_n, s_f,
 // s_v, s_d^f, s_vis^f).
-template <typename T>
+template <typename T, bool H2 = false>
 M2P_FN void tentative(const Consts<T>& K, const T u[NF], const T HXl[NF], const T HXr[NF],
                                           const T HYb[NF], const T HYt[NF], const Src<T>& S, T svx, T svy, T dt,
                                           T out[NF])
 {
+    if constexpr (carry_2h<T, H2>()) {
+        // fluxes carried as 2 H: u + dt s - (dt / 2 dxi) dF - (dt / 2 deta) dG
+        const T cx = dt * K.half_rdxi, cy = dt * K.half_rdeta;
+#pragma unroll
+        for (int k = 0; k < NF; k++) {
+            const T dFx = HXr[k] - HXl[k];
+            const T dGy = HYt[k] - HYb[k];
+            const int ph = k / 3, comp = k % 3;
+            T o = u[k];
+            if (comp > 0) {
+                const int a = comp - 1;
+                T sk = S.sn[ph][a] + S.sf[ph][a] + S.sv[ph][a];
+                if (ph == 1) sk = sk + S.sd[a] + (a == 0 ? svx : svy);
+                o = o + dt * sk;
+            }
+            o = o - cx * dFx;
+            out[k] = o - cy * dGy;
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < NF; k++) {
         T dFx = HXr[k] - HXl[k];
@@ -607,12 +647,12 @@ M2P_FN int clamp_cell(const Consts<T>& K, const Geo<T>& g, T kappa_s, T dt, T tm
     return clamps;
 }
 
-template <typename T>
+template <typename T, bool H2 = false>
 M2P_FN int update_cell(const Consts<T>& K, const T u[NF], const Geo<T>& g, const T HXl[NF],
                                            const T HXr[NF], const T HYb[NF], const T HYt[NF], const Src<T>& S,
                                            T svx, T svy, T dt, T tmu, T out[NF])
 {
-    tentative(K, u, HXl, HXr, HYb, HYt, S, svx, svy, dt, out);
+    tentative<T, H2>(K, u, HXl, HXr, HYb, HYt, S, svx, svy, dt, out);
     return clamp_cell(K, g, S.kappa_s, dt, tmu, out);
 }
 

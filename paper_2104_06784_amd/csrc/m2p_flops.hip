@@ -96,7 +96,8 @@ Row make_row(const Consts<Cnt>& K, const Cnt u[NF], int k)
 }
 
 // One cell's share of one stage (see the file header).
-void cell_stage(const Consts<Cnt>& K, int stage, bool visc, int flags)
+template <bool H2>
+void cell_stage_t(const Consts<Cnt>& K, int stage, bool visc, int flags)
 {
     Tally saved = g_tally;
     // values that earlier rows / neighbouring lanes provide (not counted)
@@ -128,7 +129,7 @@ void cell_stage(const Consts<Cnt>& K, int stage, bool visc, int flags)
         uR[k] = Un1[k] - Cnt(0.5) * sy1[k];
     }
     Cnt HyN[NF];
-    central_flux(K, uL, D0.g, uR, D1.g, 1, HyN);
+    central_flux<Cnt, H2>(K, uL, D0.g, uR, D1.g, 1, HyN);
     Cnt vGXN = 0.0, vGYN = 0.0;
     if (visc)
         visc_yface_c(D0.u, D0.w, D1.u, D1.w, D0.cdxu, D0.cdxw, D1.cdxu, D1.cdxw, D0.Jh, D1.Jh, D0.g, D1.g, K.deta,
@@ -142,7 +143,7 @@ void cell_stage(const Consts<Cnt>& K, int stage, bool visc, int flags)
         const Cnt up = Uc[k] - Cnt(0.5) * sx;  // right value of face i-1/2, sent west
         upR[k] = up.v * 1.01;
     }
-    central_flux(K, um, D0.g, upR, D1.g, 0, Hx);
+    central_flux<Cnt, H2>(K, um, D0.g, upR, D1.g, 0, Hx);
     // ---- sources
     Cnt dn[6];
     dn[0] = (Cnt(D0.g.nX.v * 1.01) - Cnt(D0.g.nX.v * 0.99)) / K.two_dxi;
@@ -171,7 +172,7 @@ void cell_stage(const Consts<Cnt>& K, int stage, bool visc, int flags)
     // ---- update (a sliding cell: the clamp takes its longer branch)
     Cnt out[NF];
     const Cnt dt = 1e-3, tmu = 0.05;
-    update_cell(K, Uc, D0.g, HxL, Hx, Hy, HyN, Sr, svx, svy, dt, tmu, out);
+    update_cell<Cnt, H2>(K, Uc, D0.g, HxL, Hx, Hy, HyN, Sr, svx, svy, dt, tmu, out);
     if (stage == 2) {
         for (int k = 0; k < NF; k++) out[k] = Cnt(0.5) * (unr[k] + out[k]);
         Cnt sx, sy, amx = 0.0, amy = 0.0;
@@ -179,6 +180,15 @@ void cell_stage(const Consts<Cnt>& K, int stage, bool visc, int flags)
         amx = fmax(amx, sx);
         amy = fmax(amy, sy);
     }
+}
+
+// Stage 1 carries face fluxes as 2 H (the FP32 stage-1 kernel's form).
+void cell_stage(const Consts<Cnt>& K, int stage, bool visc, int flags)
+{
+    if (stage == 1)
+        cell_stage_t<true>(K, stage, visc, flags);
+    else
+        cell_stage_t<false>(K, stage, visc, flags);
 }
 
 KParams count_params(int visc)

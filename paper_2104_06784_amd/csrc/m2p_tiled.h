@@ -109,6 +109,10 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
                                                  int nmax, int R, int nstrips, int nrb, int strip, int rb, int lane)
 {
     const Consts<T> K(P);
+    // stage 1 carries face fluxes as 2 H in the FP32 forms (later stages keep
+    // H: the extra registers of the factorised update do not fit their
+    // three-waves-per-SIMD budget)
+    constexpr bool H2 = STAGE == 1;
     const size_t fs = (size_t)P.ny * P.pitch;
     const int col = strip * kStripOut - 2 + lane;
     const int cc = col < P.nx + 1 ? col : P.nx + 1;  // lanes past the ghost ring feed no output
@@ -170,7 +174,8 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
     const int st = stage_slot(STAGE);
     auto put_b = [&](int side, int k, bool inflow, T m_s, T m_f, double len) {
         double* bp = bpart + ((size_t)(st * 4 + side) * nmax + k) * 2;
-        const double sg = (side == 0 || side == 2) ? -1.0 : 1.0;
+        constexpr double unit = carry_2h<T, H2>() ? 0.5 : 1.0;
+        const double sg = (side == 0 || side == 2) ? -unit : unit;
         bp[0] = inflow ? 0.0 : sg * (double)m_s * len;
         bp[1] = inflow ? 0.0 : sg * (double)m_f * len;
     };
@@ -198,11 +203,11 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             uL[k] = Um1[k] + T(0.5) * sym[k];
             uR[k] = U0[k] - T(0.5) * sy0[k];
         }
-        central_flux(K, uL, Dm.g, uR, D0.g, 1, Hy);
+        central_flux<T, H2>(K, uL, Dm.g, uR, D0.g, 1, Hy);
         if (r0 == 0 && out_lane) {
             const int s = inflow_seg_at(P, 2, col);
             if (s >= 0)
-                inflow_flux(K, D0.g, 1, +1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), Hy);
+                inflow_flux<T, H2>(K, D0.g, 1, +1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), Hy);
             put_b(2, col, s >= 0, Hy[0], Hy[3], P.dxi);
         }
     }
@@ -255,11 +260,11 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             uR[k] = Un1[k] - T(0.5) * sy1[k];
         }
         // ---- y-face j + 1/2
-        central_flux(K, uL, D0.g, uR, D1.g, 1, HyN);
+        central_flux<T, H2>(K, uL, D0.g, uR, D1.g, 1, HyN);
         if (j == P.ny - 1 && out_lane) {
             const int s = inflow_seg_at(P, 3, col);
             if (s >= 0)
-                inflow_flux(K, D0.g, 1, -1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HyN);
+                inflow_flux<T, H2>(K, D0.g, 1, -1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HyN);
             put_b(3, col, s >= 0, HyN[0], HyN[3], P.dxi);
         }
         vGXN = T(0);
@@ -289,20 +294,20 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             gR.A12 = from_right(D0.g.A12);
             gR.A21 = gR.A12;
             gR.A22 = from_right(D0.g.A22);
-            central_flux(K, um, D0.g, upR, gR, 0, Hx);
+            central_flux<T, H2>(K, um, D0.g, upR, gR, 0, Hx);
 #pragma unroll
             for (int k = 0; k < NF; k++) HxL[k] = from_left(Hx[k]);
         }
         if (ownW) {
             const int s = inflow_seg_at(P, 0, j);
             if (s >= 0)
-                inflow_flux(K, D0.g, 0, +1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HxL);
+                inflow_flux<T, H2>(K, D0.g, 0, +1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HxL);
             put_b(0, j, s >= 0, HxL[0], HxL[3], P.deta);
         }
         if (ownE) {
             const int s = inflow_seg_at(P, 1, j);
             if (s >= 0)
-                inflow_flux(K, D0.g, 0, -1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), Hx);
+                inflow_flux<T, H2>(K, D0.g, 0, -1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), Hx);
             put_b(1, j, s >= 0, Hx[0], Hx[3], P.deta);
         }
 
@@ -348,7 +353,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
         // ---- update and write
         if (out_lane) {
             T out[NF];
-            clamps += update_cell(K, Uc, D0.g, HxL, Hx, Hy, HyN, Sr, svx, svy, dt, tmu, out);
+            clamps += update_cell<T, H2>(K, Uc, D0.g, HxL, Hx, Hy, HyN, Sr, svx, svy, dt, tmu, out);
             if (STAGE > 1) {
 #pragma unroll
                 for (int k = 0; k < NF; k++) out[k] = stage_combine<STAGE>(unr[k], out[k]);

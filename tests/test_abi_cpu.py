@@ -120,11 +120,16 @@ def test_stage_flop_count():
     (1 - alpha)/2 (h + h^s) 1 add 1 mul; eps A_nn c twice, 4 mul; the four
     squared speeds 4 mul; |v| + sqrt(max(., 0)) four times: 4 add 4 sqrt
     4 cmp; the maxima over the phases and the running maxima, 4 cmp):
-    16 add, 25 mul, 2 div, 4 sqrt, 10 cmp."""
+    16 add, 25 mul, 2 div, 4 sqrt, 10 cmp; plus the flux form of stage 1, which
+    carries face fluxes as 2 H: its two central fluxes save 2 mul per
+    component (24 mul) and its update replaces the 12 divisions by the cell
+    widths with 12 multiplications (dt / 2 dxi, dt / 2 deta, then one factor
+    per flux difference and source sum), so stage 2 has 12 mul and 12 div
+    more: 16 add, 37 mul, 14 div, 4 sqrt, 10 cmp."""
     f10, f11, f20, f21 = _flops(1, 0), _flops(1, 1), _flops(2, 0), _flops(2, 1)
     assert np.array_equal(f11 - f10, [34, 40, 10, 0, 0])
     assert np.array_equal(f21 - f20, [34, 40, 10, 0, 0])
-    assert np.array_equal(f20 - f10, [16, 25, 2, 4, 10])
+    assert np.array_equal(f20 - f10, [16, 37, 14, 4, 10])
     # square roots: 4 face sides x 2 phase speeds, the new row's geometry, the
     # norm of the solid momentum in the Coulomb clamp
     assert f10[3] == 10
