@@ -109,7 +109,12 @@ hipError_t Launch<M2P_REAL>::batch_part(const ScenDesc<M2P_REAL>* scen, int nsce
     using T = M2P_REAL;
     if (part == 2)
         hipLaunchKernelGGL((k_finalize_batch<T>), dim3(nscen), dim3(kFinThreads), 0, st, scen, mode);
-    else if (part == 0)
+    else if ((long long)blocks * 4 >= nwork) {  // one wavefront per work item
+        if (part == 0)
+            hipLaunchKernelGGL((k_stage_batch_flat<T, 1>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);
+        else
+            hipLaunchKernelGGL((k_stage_batch_flat<T, 2>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);
+    } else if (part == 0)
         hipLaunchKernelGGL((k_stage_batch<T, 1>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);
     else
         hipLaunchKernelGGL((k_stage_batch<T, 2>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);

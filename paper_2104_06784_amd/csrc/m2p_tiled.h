@@ -439,10 +439,32 @@ k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout, const 
     }
 }
 
-// Persistent batched stage: a fixed grid of wavefronts walks the work list
-// (scenario, strip, row block) with a grid stride; every scenario keeps its
-// own time step and partial slots, so results equal single-scenario runs.
-// Ensemble scenarios are Mode-I releases (no boundary segments).
+// One work item (scenario, strip, row block) of a batched stage; its partial
+// record goes to wave slot `local` of the scenario.
+template <typename T, int STAGE>
+__device__ __forceinline__ void batch_item(const ScenDesc<T>* __restrict__ scen, int item, int R, int lane)
+{
+    const int sc = item >> 20, local = item & 0xfffff;
+    const ScenDesc<T>& D = scen[sc];
+    const int strip = local % D.nstrips, rb = local / D.nstrips;
+    const WavePart r =
+        STAGE == 1 ? stage_tiled_wave<T, 1, false>(D.P, D.U, D.U, D.Us, D.b, D.mu, D.S, D.bpart, D.nmax, R,
+                                                   D.nstrips, D.nrb, strip, rb, lane)
+                   : stage_tiled_wave<T, 2, false>(D.P, D.Us, D.U, D.U, D.b, D.mu, D.S, D.bpart, D.nmax, R,
+                                                   D.nstrips, D.nrb, strip, rb, lane);
+    if (lane == 0) {
+        double* wp = D.wpart + ((size_t)stage_slot(STAGE) * D.nstrips * D.nrb + local) * 4;
+        wp[0] = r.ax;
+        wp[1] = r.ay;
+        wp[2] = r.cl;
+        wp[3] = r.bd;
+    }
+}
+
+// Batched stage over the work list (every scenario keeps its own time step
+// and partial slots, so results equal single-scenario runs; ensemble
+// scenarios are Mode-I releases).  Persistent form: a fixed grid of
+// wavefronts walks the list with a grid stride.
 template <typename T, int STAGE>
 __global__ void __launch_bounds__(256)
 k_stage_batch(const ScenDesc<T>* __restrict__ scen, const int* __restrict__ work, int nwork, int R)
@@ -454,24 +476,24 @@ k_stage_batch(const ScenDesc<T>* __restrict__ scen, const int* __restrict__ work
     const int lane = threadIdx.x & 63;
     const int nwaves = nblk * 4;
     const int w0 = __builtin_amdgcn_readfirstlane(bid * 4 + (int)(threadIdx.x >> 6));
-    for (int w = w0; w < nwork; w += nwaves) {
-        const int item = __builtin_amdgcn_readfirstlane(work[w]);
-        const int sc = item >> 20, local = item & 0xfffff;
-        const ScenDesc<T>& D = scen[sc];
-        const int strip = local % D.nstrips, rb = local / D.nstrips;
-        const WavePart r =
-            STAGE == 1 ? stage_tiled_wave<T, 1, false>(D.P, D.U, D.U, D.Us, D.b, D.mu, D.S, D.bpart, D.nmax, R,
-                                                       D.nstrips, D.nrb, strip, rb, lane)
-                       : stage_tiled_wave<T, 2, false>(D.P, D.Us, D.U, D.U, D.b, D.mu, D.S, D.bpart, D.nmax, R,
-                                                       D.nstrips, D.nrb, strip, rb, lane);
-        if (lane == 0) {  // one record per work item (wave slot `local` of the scenario)
-            double* wp = D.wpart + ((size_t)stage_slot(STAGE) * D.nstrips * D.nrb + local) * 4;
-            wp[0] = r.ax;
-            wp[1] = r.ay;
-            wp[2] = r.cl;
-            wp[3] = r.bd;
-        }
-    }
+    for (int w = w0; w < nwork; w += nwaves)
+        batch_item<T, STAGE>(scen, __builtin_amdgcn_readfirstlane(work[w]), R, lane);
+}
+
+// Flat form, one wavefront per work item (a grid covering the list): without
+// the walk's loop state the FP32 wave body fits the single-scenario kernels'
+// occupancy.
+template <typename T, int STAGE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_wpe<T, STAGE>())))
+k_stage_batch_flat(const ScenDesc<T>* __restrict__ scen, const int* __restrict__ work, int nwork, int R)
+{
+    const int nblk = gridDim.x;
+    int bid = blockIdx.x;
+    const int nfull = (nblk / 8) * 8;
+    if (bid < nfull) bid = (bid % 8) * (nfull / 8) + bid / 8;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(bid * 4 + (int)(threadIdx.x >> 6));
+    if (w < nwork) batch_item<T, STAGE>(scen, __builtin_amdgcn_readfirstlane(work[w]), R, lane);
 }
 
 template <typename T>
