@@ -452,10 +452,11 @@ template <int NT>
 __device__ __forceinline__ void fin_reduce(const KParams& P, const double* __restrict__ bpart, int n_we, int n_sn,
                                            int nmax, int mode, const double* __restrict__ wpart, int nw, double* out)
 {
-    static_assert(NT % 64 == 0 && NT >= kFinVals * 8, "finalize workgroup shape");
-    constexpr int CH = NT / 8;  // shares per chunk of the second pass
+    constexpr int NCH = NT / 32;  // chunks per value in the first combining pass
+    constexpr int CH = NT / NCH;  // shares per chunk
+    static_assert(NT % 64 == 0 && NT >= kFinVals * NCH, "finalize workgroup shape");
     __shared__ double sh[kFinVals][NT];
-    __shared__ double sh2[kFinVals][8];
+    __shared__ double sh2[kFinVals][NCH];
     const int tid = threadIdx.x;
     const int last = P.rk - 1;  // slot of the stage that ends the step
     const int nlist = mode == 0 ? P.rk * 4 : 0;
@@ -515,8 +516,8 @@ __device__ __forceinline__ void fin_reduce(const KParams& P, const double* __res
     }
     __syncthreads();
     // pass 1: thread (k, c) combines chunk c (CH consecutive shares) of value k
-    if (tid < kFinVals * 8) {
-        const int k = tid >> 3, c = tid & 7;
+    if (tid < kFinVals * NCH) {
+        const int k = tid / NCH, c = tid % NCH;
         const double* r = &sh[k][c * CH];
         double v = r[0];
         if (fin_is_max(k)) {
@@ -529,10 +530,10 @@ __device__ __forceinline__ void fin_reduce(const KParams& P, const double* __res
         sh2[k][c] = v;
     }
     __syncthreads();
-    // pass 2: thread k combines the 8 chunks of value k
+    // pass 2: thread k combines the chunks of value k
     if (tid < kFinVals) {
         double v = sh2[tid][0];
-        for (int c = 1; c < 8; c++) v = fin_is_max(tid) ? fmax(v, sh2[tid][c]) : v + sh2[tid][c];
+        for (int c = 1; c < NCH; c++) v = fin_is_max(tid) ? fmax(v, sh2[tid][c]) : v + sh2[tid][c];
         out[tid] = v;
     }
     __syncthreads();
@@ -646,8 +647,8 @@ __device__ __forceinline__ void fin_tail_staged(const KParams& P, DevScalars* S,
 // step of which would otherwise wait on device memory).
 constexpr int kFinTabLds = 2048;
 
-template <typename T>
-__global__ void __launch_bounds__(kFinThreads)
+template <typename T, int NT = kFinThreads>
+__global__ void __launch_bounds__(NT)
 k_finalize(KParams P, DevScalars* S, const double* __restrict__ bpart, int n_we, int n_sn, int nmax,
            const double* __restrict__ tables, int mode, const double* __restrict__ wpart, int nw)
 {
@@ -656,7 +657,7 @@ k_finalize(KParams P, DevScalars* S, const double* __restrict__ bpart, int n_we,
     const bool lds_tab = P.ntab > 0 && P.ntab <= kFinTabLds;
     if (lds_tab)
         for (int k = threadIdx.x; k < P.ntab; k += blockDim.x) tab[k] = tables[k];
-    fin_reduce<kFinThreads>(P, bpart, n_we, n_sn, nmax, mode, wpart, nw, red);
+    fin_reduce<NT>(P, bpart, n_we, n_sn, nmax, mode, wpart, nw, red);
     fin_tail_staged(P, S, red, lds_tab ? tab : tables, mode);
 }
 

@@ -18,8 +18,14 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
     const T* b = (const T*)B.b;
     const T* mu = (const T*)B.mu;
     if (part == P.rk) {
-        hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(kFinThreads), 0, st, P, B.S, B.bpart, sh.n_we, sh.n_sn,
-                           B.nmax, B.tables, 0, B.wpart, sh.nw);
+        // small grids: one wavefront (shorter combining passes, the lists
+        // give each lane only a few loads)
+        if (sh.n_we <= 256 && sh.n_sn <= 256 && sh.nw <= 512)
+            hipLaunchKernelGGL((k_finalize<T, 64>), dim3(1), dim3(64), 0, st, P, B.S, B.bpart, sh.n_we, sh.n_sn,
+                               B.nmax, B.tables, 0, B.wpart, sh.nw);
+        else
+            hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(kFinThreads), 0, st, P, B.S, B.bpart, sh.n_we,
+                               sh.n_sn, B.nmax, B.tables, 0, B.wpart, sh.nw);
         return hipGetLastError();
     }
     // Heun: E(U) -> Us, then (U + E(Us)) / 2 -> U.  Three-stage: E(U) -> Us,
