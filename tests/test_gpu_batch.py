@@ -32,13 +32,16 @@ def _small(i, nx, ny):
 SHAPES = [(40, 30), (61, 57), (64, 64), (130, 17), (97, 121)]
 
 
+@pytest.mark.parametrize("blocks", [0, 3])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_batch_members_equal_single_runs(precision):
+def test_batch_members_equal_single_runs(precision, blocks):
+    """blocks 0: a wavefront per work item (the flat kernel); 3 workgroups:
+    twelve wavefronts walk the work list (the persistent kernel)."""
     from paper_2104_06784_amd.sim import Batch, Sim
     probs = [_small(i, nx, ny) for i, (nx, ny) in enumerate(SHAPES)]
-    _say(f"[batch] {len(probs)} scenarios {precision}")
+    _say(f"[batch] {len(probs)} scenarios {precision} blocks={blocks}")
     b = Batch(probs, precision=precision)
-    b.set_tile(8, 0)
+    b.set_tile(8, blocks)
     b.set_graph(10)
     b.run(25)
     b.synchronize()
