@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
         }
 #pragma unroll
         for (int k = 0; k < NF; k++) {
-            if (!isfinite(out[k])) bad = 1;
+            if (stage_last(STAGE) && !isfinite(out[k])) bad = 1;  // as the tiled kernel
             Uout[k * fs + c] = out[k];
         }
     }

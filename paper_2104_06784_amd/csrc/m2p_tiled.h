@@ -364,9 +364,11 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
                 amx = fmax(amx, sx);
                 amy = fmax(amy, sy);
             }
+            // non-finite check in the stage that ends the step only: a value
+            // that is not finite after an earlier stage reaches its output
 #pragma unroll
             for (int k = 0; k < NF; k++) {
-                if (!isfinite(out[k])) bad = 1;
+                if (stage_last(STAGE) && !isfinite(out[k])) bad = 1;
                 Uout[k * fs + cself] = out[k];
             }
         }
