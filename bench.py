@@ -42,15 +42,19 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources and build flags: the byte counters recorded in
-    profiles/ apply only while this hash is unchanged."""
+    """Hash of the HIP sources (comments and blank lines removed) and of the
+    build flags: the counters recorded in profiles/ apply only while this hash
+    is unchanged, i.e. while the code they were taken on is unchanged."""
     import hashlib
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2104_06784_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.endswith((".h", ".hip")):
+            text = open(os.path.join(csrc, f), encoding="utf-8").read()
+            code = "\n".join(ln.rstrip() for ln in re.sub(r"//[^\n]*", "", text).splitlines() if ln.strip())
             h.update(f.encode())
-            h.update(open(os.path.join(csrc, f), "rb").read())
+            h.update(code.encode())
     h.update(open(os.path.join(ROOT, "paper_2104_06784_amd", "build_lib.py"), "rb").read())
     return h.hexdigest()[:16]
 

@@ -7,9 +7,11 @@
 // cross-lane shuffles.  Every face flux, every cell geometry and every
 // derived cell quantity is computed once per stage (the y-face flux of row
 // j+1/2 is carried to the next row), so the kernel reads each state field
-// once per row from HBM and needs no LDS and no barrier.  The arithmetic of
+// once per row from HBM and the march needs no LDS and no barrier (one
+// barrier at the end combines a workgroup's partial sums).  The arithmetic of
 // every quantity is the one of m2p_device.h in the same order as the
-// reference kernel, so FP64 results are bitwise identical to it.
+// reference kernel, so FP64 results are bitwise identical to it (the FP32
+// stage 1 carries face fluxes as 2 H, see carry_2h).
 #pragma once
 
 #include "m2p_device.h"
