@@ -89,14 +89,18 @@ struct m2p_ctx {
     int64_t prof_n = 0;
 };
 
-static hipError_t step_part(m2p_ctx* c, int part)
+// One part of a step on the buffers B (the context's, or the same with other
+// state pointers).
+static hipError_t step_part(m2p_ctx* c, const Bufs& B, int part)
 {
     // every launch shape's partial slots must fit the buffer (m2p_set_variant
     // grows it before a shape needs more)
-    if ((size_t)c->shape.nw > c->wcap || (size_t)c->B.nw_ref > c->wcap) return hipErrorInvalidValue;
-    if (c->prec == M2P_FP64) return Launch<double>::step_part(c->kp, c->B, c->shape, c->stream, part);
-    return Launch<float>::step_part(c->kp, c->B, c->shape, c->stream, part);
+    if ((size_t)c->shape.nw > c->wcap || (size_t)B.nw_ref > c->wcap) return hipErrorInvalidValue;
+    if (c->prec == M2P_FP64) return Launch<double>::step_part(c->kp, B, c->shape, c->stream, part);
+    return Launch<float>::step_part(c->kp, B, c->shape, c->stream, part);
 }
+
+static hipError_t step_part(m2p_ctx* c, int part) { return step_part(c, c->B, part); }
 
 // One step: the rk stage kernels, then the finalize (parts 0 .. rk).  With
 // profiling, an event around every part (rk + 2 events per step).
@@ -1123,20 +1127,15 @@ struct VjpWork {
     }
 };
 
+// lam_in = (stage transpose at U) (lscale lam) [+ zc z]
 hipError_t L_vjp(m2p_ctx* c, VjpWork& w, const void* U, const void* lam, int stage, double dt, void* lam_in,
-                 void* gmu)
+                 void* gmu, double lscale = 1.0, const void* z = nullptr, double zc = 0.0)
 {
     if (c->prec == M2P_FP64)
-        return Launch<double>::vjp(c->kp, c->B, U, lam, stage, dt, w.GT.p, w.DU.p, w.FCX.p, w.FCY.p, w.SC.p, lam_in,
-                                   gmu, c->stream);
-    return Launch<float>::vjp(c->kp, c->B, U, lam, stage, dt, w.GT.p, w.DU.p, w.FCX.p, w.FCY.p, w.SC.p, lam_in, gmu,
-                              c->stream);
-}
-
-hipError_t L_axpbz(m2p_ctx* c, double a, const void* x, double b, const void* z, void* y)
-{
-    if (c->prec == M2P_FP64) return Launch<double>::axpbz(c->kp, a, x, b, z, y, c->stream);
-    return Launch<float>::axpbz(c->kp, a, x, b, z, y, c->stream);
+        return Launch<double>::vjp(c->kp, c->B, U, lam, lscale, stage, dt, w.GT.p, w.DU.p, w.FCX.p, w.FCY.p, w.SC.p,
+                                   lam_in, z, zc, gmu, c->stream);
+    return Launch<float>::vjp(c->kp, c->B, U, lam, lscale, stage, dt, w.GT.p, w.DU.p, w.FCX.p, w.FCY.p, w.SC.p,
+                              lam_in, z, zc, gmu, c->stream);
 }
 
 int L_dot(m2p_ctx* c, const void* x, const void* y, double* out)
@@ -1285,11 +1284,11 @@ int m2p_adjoint_run(m2p_ctx* c, int64_t nsteps, int32_t ckpt_every, const double
     const size_t n = (size_t)c->g.nx * c->g.ny, sb = c->state_bytes;
     const int nseg = (int)((nsteps + ckpt_every - 1) / ckpt_every);
     const int seglen = (int)std::min<int64_t>(ckpt_every, nsteps);
-    DevBuf ckpt, sck, dts, tapeU, tapeUs, lam, lamh, lamv, gmu, tgt, fin, sfin;
+    DevBuf ckpt, sck, dts, tapeU, tapeUs, lam, lamv, gmu, tgt, fin, sfin;
     VjpWork w;
     if ((rc = ckpt.alloc(sb * nseg)) || (rc = sck.alloc(sizeof(DevScalars) * nseg)) ||
         (rc = dts.alloc(8 * nsteps)) || (rc = tapeU.alloc(sb * seglen)) || (rc = tapeUs.alloc(sb * seglen)) ||
-        (rc = lam.alloc(sb)) || (rc = lamh.alloc(sb)) || (rc = lamv.alloc(sb)) ||
+        (rc = lam.alloc(sb)) || (rc = lamv.alloc(sb)) ||
         (rc = gmu.alloc((size_t)K.ny * K.pitch * c->esz)) || (rc = tgt.alloc(n * 8)) || (rc = fin.alloc(sb)) ||
         (rc = sfin.alloc(sizeof(DevScalars))) || (rc = w.alloc(c)))
         return rc;
@@ -1316,24 +1315,32 @@ int m2p_adjoint_run(m2p_ctx* c, int64_t nsteps, int32_t ckpt_every, const double
     // reverse sweep, segment by segment, recomputing each segment's states
     for (int sg = nseg - 1; sg >= 0; sg--) {
         const int64_t n0 = (int64_t)sg * ckpt_every, n1 = std::min<int64_t>(nsteps, n0 + ckpt_every);
-        HIPCHK(hipMemcpyAsync(c->B.U, (char*)ckpt.p + sb * sg, sb, hipMemcpyDeviceToDevice, st));
+        // recompute the segment's states straight into the tapes: stage 1
+        // reads U^s from tapeU[s] and writes U*^s to tapeUs[s]; stage 2 writes
+        // U^{s+1} to tapeU[s+1].  The last step needs only its stage 1.
+        HIPCHK(hipMemcpyAsync(tapeU.p, (char*)ckpt.p + sb * sg, sb, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(c->S, (char*)sck.p + sizeof(DevScalars) * sg, sizeof(DevScalars),
                               hipMemcpyDeviceToDevice, st));
         for (int64_t s = n0; s < n1; s++) {
-            HIPCHK(hipMemcpyAsync((char*)tapeU.p + sb * (s - n0), c->B.U, sb, hipMemcpyDeviceToDevice, st));
-            HIPCHK(step_part(c, 0));
-            HIPCHK(hipMemcpyAsync((char*)tapeUs.p + sb * (s - n0), c->B.Us, sb, hipMemcpyDeviceToDevice, st));
-            HIPCHK(step_part(c, 1));
-            HIPCHK(step_part(c, 2));
+            Bufs tb = c->B;
+            tb.U = (char*)tapeU.p + sb * (s - n0);
+            tb.Us = (char*)tapeUs.p + sb * (s - n0);
+            HIPCHK(step_part(c, tb, 0));
+            if (s + 1 < n1) {
+                tb.Uout = (char*)tapeU.p + sb * (s - n0 + 1);
+                HIPCHK(step_part(c, tb, 1));
+                HIPCHK(step_part(c, tb, 2));
+            }
         }
         for (int64_t s = n1 - 1; s >= n0; s--) {
             const double dt = hdt[s];
             const void* Un = (char*)tapeU.p + sb * (s - n0);
             const void* Us = (char*)tapeUs.p + sb * (s - n0);
-            HIPCHK(L_axpbz(c, 0.5, lam.p, 0.0, nullptr, lamh.p));        // cotangent of U**
-            HIPCHK(L_vjp(c, w, Us, lamh.p, 1, dt, lamv.p, gmu.p));      // -> cotangent of U*
-            HIPCHK(L_vjp(c, w, Un, lamv.p, 0, dt, lamh.p, gmu.p));      // -> through stage 1
-            HIPCHK(L_axpbz(c, 0.5, lam.p, 1.0, lamh.p, lam.p));         // lambda^n
+            // U^{n+1} = (U^n + E(U*)) / 2: half of lambda^{n+1} enters the
+            // second stage, and lambda^n = lambda^{n+1} / 2 + (stage-1
+            // transpose of the cotangent of U*), summed by the last gather
+            HIPCHK(L_vjp(c, w, Us, lam.p, 1, dt, lamv.p, gmu.p, 0.5));              // -> cotangent of U*
+            HIPCHK(L_vjp(c, w, Un, lamv.p, 0, dt, lam.p, gmu.p, 1.0, lam.p, 0.5));  // -> lambda^n
         }
     }
     // dL / d(volume scale): the initial state is proportional to the scale

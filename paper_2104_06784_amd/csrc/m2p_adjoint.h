@@ -265,10 +265,12 @@ __global__ void __launch_bounds__(128) k_stage_jvp(KParams P, const T* __restric
 
 // Pass A: per cell, the cotangent of the tentative state (GT), the direct
 // cotangent of U_c (identity of the update + clamp through kappa_s) into DU,
-// and the friction-field cotangent (accumulated into gmu).
+// and the friction-field cotangent (accumulated into gmu).  The incoming
+// cotangent is lscale * lam (the Heun average passes half of it to the second
+// stage).
 template <typename T>
 __global__ void __launch_bounds__(128) k_adj_post(KParams P, const T* __restrict__ U, const T* __restrict__ lam,
-                                                  const T* __restrict__ b, const T* __restrict__ mu,
+                                                  T lscale, const T* __restrict__ b, const T* __restrict__ mu,
                                                   const DevScalars* __restrict__ S, int stage, T dt,
                                                   T* __restrict__ GT, T* __restrict__ DU, T* __restrict__ gmu)
 {
@@ -283,7 +285,7 @@ __global__ void __launch_bounds__(128) k_adj_post(KParams P, const T* __restrict
     T tent[NF], out[NF];
     cell_stage(P, s, g5, dt, tmu, S->inflow[stage], i, j, tent, out);
     T lo[NF];
-    for (int k = 0; k < NF; k++) lo[k] = lam[k * fs + c];
+    for (int k = 0; k < NF; k++) lo[k] = lscale * lam[k * fs + c];
     using TT = Dual<T>;
     const Consts<TT> K(P);
     const Geo<TT> gC = lift(g5.C);
@@ -434,49 +436,39 @@ template <typename T>
 __device__ __forceinline__ void face_flux_vjp(const KParams& P, const T w[4][NF], const Geo<T>& ga, const Geo<T>& gb,
                                               int d, const T gH[NF], T out[24])
 {
-    using TT = Dual<T>;
-    const Consts<TT> K(P);
-    const Geo<TT> gaD = lift(ga), gbD = lift(gb);
+    const Consts<T> Kb(P);
     T uL[NF], uR[NF];
     int p0[NF], p1[NF];
 #pragma unroll
     for (int k = 0; k < NF; k++) {
         const T a0 = w[1][k] - w[0][k], b0 = w[2][k] - w[1][k], b1 = w[3][k] - w[2][k];
-        const TT s0 = minmod(TT(a0, T(0)), TT(b0, T(0)));
-        const TT s1 = minmod(TT(b0, T(0)), TT(b1, T(0)));
         p0[k] = minmod_pick(a0, b0);
         p1[k] = minmod_pick(b0, b1);
-        uL[k] = (TT(w[1][k], T(0)) + TT(0.5) * s0).v;
-        uR[k] = (TT(w[2][k], T(0)) - TT(0.5) * s1).v;
+        uL[k] = w[1][k] + T(0.5) * minmod(a0, b0);
+        uR[k] = w[2][k] - T(0.5) * minmod(b0, b1);
     }
-    // side values as the dual evaluation computes them
-    TT uLd[NF], uRd[NF], FL[NF], FR[NF], qL[NF], qR[NF], aL[2], aR[2];
-#pragma unroll
-    for (int k = 0; k < NF; k++) {
-        uLd[k] = TT(uL[k], T(0));
-        uRd[k] = TT(uR[k], T(0));
-    }
-    side_flux(K, uLd, gaD, d, FL, qL, aL);
-    side_flux(K, uRd, gbD, d, FR, qR, aR);
+    // side values (the flux, conserved values and speeds of each side)
+    T FL[NF], FR[NF], qL[NF], qR[NF], aL[2], aR[2];
+    side_flux(Kb, uL, ga, d, FL, qL, aL);
+    side_flux(Kb, uR, gb, d, FR, qR, aR);
     T lF[NF], lqL[NF], lqR[NF], laL[2], laR[2];
 #pragma unroll
     for (int ph = 0; ph < 2; ph++) {
-        const bool left = aL[ph].v > aR[ph].v;
-        const T am = left ? aL[ph].v : aR[ph].v;
+        const bool left = aL[ph] > aR[ph];
+        const T am = left ? aL[ph] : aR[ph];
         T la = T(0);
 #pragma unroll
         for (int k = 3 * ph; k < 3 * ph + 3; k++) {
             lF[k] = T(0.5) * gH[k];
             lqL[k] = T(0.5) * am * gH[k];
             lqR[k] = -(T(0.5) * am * gH[k]);
-            la += gH[k] * (qR[k].v - qL[k].v);
+            la += gH[k] * (qR[k] - qL[k]);
         }
         la = -(T(0.5) * la);
         laL[ph] = left ? la : T(0);
         laR[ph] = left ? T(0) : la;
     }
     T luL[NF], luR[NF];
-    const Consts<T> Kb(P);
     side_flux_vjp(Kb, uL, ga, d, lF, lqL, laL, luL);
     side_flux_vjp(Kb, uR, gb, d, lF, lqR, laR, luR);
     T lw[4][NF];
@@ -514,16 +506,21 @@ __device__ __forceinline__ void face_flux_vjp(const KParams& P, const T w[4][NF]
 }
 
 // Pass B, faces: x-faces (d = 0) for i in [-1, nx-1] (face between i and i+1)
-// or y-faces (d = 1) for j in [-1, ny-1]; 24 stencil cotangents per face into
-// FC[24][faces] (slot-major; slot = 6 * cell + field, cells a-1 .. a+2).
+// and y-faces (d = 1) for j in [-1, ny-1]; 24 stencil cotangents per face into
+// FCX or FCY [24][faces] (slot-major; slot = 6 * cell + field, cells a-1 ..
+// a+2).  Grid rows 0 .. ny-1 are the x-face rows, rows ny .. 2 ny the y-face
+// rows.
 template <typename T>
 __global__ void __launch_bounds__(128) k_adj_face(KParams P, const T* __restrict__ U, const T* __restrict__ GT,
-                                                  const T* __restrict__ b, int d, T dt, T* __restrict__ FC)
+                                                  const T* __restrict__ b, T dt, T* __restrict__ FCX,
+                                                  T* __restrict__ FCY)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int d = (int)blockIdx.y < P.ny ? 0 : 1;
     const int nf_along = d == 0 ? P.nx + 1 : P.nx;
     if (t >= nf_along) return;
-    const int line = blockIdx.y;  // row j for x-faces; row-of-faces j for y-faces
+    const int line = d == 0 ? (int)blockIdx.y : (int)blockIdx.y - P.ny;  // row j (x-faces), face row j (y-faces)
+    T* __restrict__ FC = d == 0 ? FCX : FCY;
     int i, j;
     if (d == 0) {
         i = t - 1;
@@ -534,7 +531,7 @@ __global__ void __launch_bounds__(128) k_adj_face(KParams P, const T* __restrict
     }
     const size_t fidx = (size_t)line * nf_along + t;
     // slot-major: slot q of all faces of this direction is contiguous
-    const size_t nfaces = (size_t)nf_along * gridDim.y;
+    const size_t nfaces = (size_t)nf_along * (d == 0 ? P.ny : P.ny + 1);
     T out[24];
     const size_t fs = (size_t)P.ny * P.pitch;
     // inflow faces carry a prescribed flux: no dependence on the state
@@ -950,110 +947,52 @@ __global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict_
 
 // Pass C: lam_in(k) = DU(k) + all face and source contributions that land on
 // cell k through the ghost map, summed in a fixed order.  Cells two or more
-// away from every edge take a direct path (no ghost cell maps onto them);
-// the ring of edge cells walks the ghost map.  The two kinds of cell are
-// launched separately, so no wavefront mixes the paths.
+// away from every edge take the direct path below (no ghost cell maps onto
+// them); the ring of edge cells walks the ghost map (k_adj_gather).  With z
+// given, lam_in = (DU + contributions) + zc z (z may be lam_in itself: each
+// cell reads its own z before writing).
 template <typename T>
-__device__ __forceinline__ void adj_gather_cell(const KParams& P, const T* __restrict__ DU, const T* __restrict__ FCX,
-                                                const T* __restrict__ FCY, const T* __restrict__ SC,
-                                                T* __restrict__ lam_in, int i, int j)
+__device__ __forceinline__ void adj_gather_interior(const KParams& P, const T* __restrict__ DU,
+                                                    const T* __restrict__ FCX, const T* __restrict__ FCY,
+                                                    const T* __restrict__ SC, const T* z, T zc, T* lam_in, int i,
+                                                    int j)
 {
     const size_t c = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
     // slot-major cotangent arrays (slot stride: number of faces or cells)
     const size_t nfx = (size_t)(P.nx + 1) * P.ny, nfy = (size_t)P.nx * (P.ny + 1), ncl = (size_t)P.nx * P.ny;
     T acc[NF];
     for (int k = 0; k < NF; k++) acc[k] = DU[k * fs + c];
-    if (i >= 2 && i <= P.nx - 3 && j >= 2 && j <= P.ny - 3) {
-        // No ghost cell maps onto this cell: each contribution comes from a
-        // fixed (face or cell, slot), taken in the order of the general path.
-        for (int fi = i - 2; fi <= i + 1; fi++) {
-            const T* f = FCX + ((size_t)j * (P.nx + 1) + (fi + 1)) + 6 * (i - fi + 1) * nfx;
-            for (int k = 0; k < NF; k++) acc[k] += f[k * nfx];
-        }
-        for (int fj = j - 2; fj <= j + 1; fj++) {
-            const T* f = FCY + ((size_t)(fj + 1) * P.nx + i) + 6 * (j - fj + 1) * nfy;
-            for (int k = 0; k < NF; k++) acc[k] += f[k * nfy];
-        }
-        // source cell (i - di, j - dj) reads this cell through its slots of offset (di, dj)
-        for (int cj = j - 1; cj <= j + 1; cj++)
-            for (int ci = i - 1; ci <= i + 1; ci++) {
-                const T* f = SC + ((size_t)cj * P.nx + ci);
-                const int di = i - ci, dj = j - cj;
-                if (di == 0 && dj == 0) {
-                    for (int k = 0; k < NF; k++) acc[k] += f[k * ncl];
-                } else if (di == 0 || dj == 0) {
-                    const int n = dj == 0 ? (di > 0 ? 0 : 1) : (dj > 0 ? 2 : 3);
-                    acc[0] += f[(6 + 4 * n) * ncl];
-                    acc[3] += f[(6 + 4 * n + 1) * ncl];
-                    acc[4] += f[(6 + 4 * n + 2) * ncl];
-                    acc[5] += f[(6 + 4 * n + 3) * ncl];
-                } else {
-                    const int n = (dj > 0 ? 0 : 2) + (di > 0 ? 0 : 1);
-                    acc[3] += f[(22 + 3 * n) * ncl];
-                    acc[4] += f[(22 + 3 * n + 1) * ncl];
-                    acc[5] += f[(22 + 3 * n + 2) * ncl];
-                }
-            }
-        for (int k = 0; k < NF; k++) lam_in[k * fs + c] = acc[k];
-        return;
+    // No ghost cell maps onto this cell: each contribution comes from a
+    // fixed (face or cell, slot); x-faces, y-faces, then the 3 x 3 sources.
+    for (int fi = i - 2; fi <= i + 1; fi++) {
+        const T* f = FCX + ((size_t)j * (P.nx + 1) + (fi + 1)) + 6 * (i - fi + 1) * nfx;
+        for (int k = 0; k < NF; k++) acc[k] += f[k * nfx];
     }
-    // x-faces of row j: face index t = fi + 1, fi in [-1, nx-1], stencil cells fi-1 .. fi+2
-    for (int fi = i - 3; fi <= i + 2; fi++) {
-        if (fi < -1 || fi > P.nx - 1) continue;
-        const T* f = FCX + ((size_t)j * (P.nx + 1) + (fi + 1));
-        for (int q = 0; q < 4; q++) {
-            int fx = 0;
-            const int mi = map_index(fi - 1 + q, P.nx, P.bc[0], P.bc[1], fx);
-            if (mi != i) continue;
-            for (int k = 0; k < NF; k++)
-                acc[k] += ((fx && (k == 1 || k == 4)) ? -f[(6 * q + k) * nfx] : f[(6 * q + k) * nfx]);
-        }
+    for (int fj = j - 2; fj <= j + 1; fj++) {
+        const T* f = FCY + ((size_t)(fj + 1) * P.nx + i) + 6 * (j - fj + 1) * nfy;
+        for (int k = 0; k < NF; k++) acc[k] += f[k * nfy];
     }
-    // y-faces of column i: face line fj + 1, fj in [-1, ny-1]
-    for (int fj = j - 3; fj <= j + 2; fj++) {
-        if (fj < -1 || fj > P.ny - 1) continue;
-        const T* f = FCY + ((size_t)(fj + 1) * P.nx + i);
-        for (int q = 0; q < 4; q++) {
-            int fy = 0;
-            const int mj = map_index(fj - 1 + q, P.ny, P.bc[2], P.bc[3], fy);
-            if (mj != j) continue;
-            for (int k = 0; k < NF; k++)
-                acc[k] += ((fy && (k == 2 || k == 5)) ? -f[(6 * q + k) * nfy] : f[(6 * q + k) * nfy]);
-        }
-    }
-    // sources of the 3 x 3 neighbourhood
-    for (int cj = j - 1; cj <= j + 1; cj++) {
-        if (cj < 0 || cj >= P.ny) continue;
+    // source cell (i - di, j - dj) reads this cell through its slots of offset (di, dj)
+    for (int cj = j - 1; cj <= j + 1; cj++)
         for (int ci = i - 1; ci <= i + 1; ci++) {
-            if (ci < 0 || ci >= P.nx) continue;
             const T* f = SC + ((size_t)cj * P.nx + ci);
-            for (int sl = 0; sl < 34; sl++) {
-                int di, dj, k;
-                src_slot(sl, di, dj, k);
-                int fx = 0, fy = 0;
-                const int mi = map_index(ci + di, P.nx, P.bc[0], P.bc[1], fx);
-                const int mj = map_index(cj + dj, P.ny, P.bc[2], P.bc[3], fy);
-                if (mi != i || mj != j) continue;
-                T v = f[sl * ncl];
-                if (fx && (k == 1 || k == 4)) v = -v;
-                if (fy && (k == 2 || k == 5)) v = -v;
-                acc[k] += v;
+            const int di = i - ci, dj = j - cj;
+            if (di == 0 && dj == 0) {
+                for (int k = 0; k < NF; k++) acc[k] += f[k * ncl];
+            } else if (di == 0 || dj == 0) {
+                const int n = dj == 0 ? (di > 0 ? 0 : 1) : (dj > 0 ? 2 : 3);
+                acc[0] += f[(6 + 4 * n) * ncl];
+                acc[3] += f[(6 + 4 * n + 1) * ncl];
+                acc[4] += f[(6 + 4 * n + 2) * ncl];
+                acc[5] += f[(6 + 4 * n + 3) * ncl];
+            } else {
+                const int n = (dj > 0 ? 0 : 2) + (di > 0 ? 0 : 1);
+                acc[3] += f[(22 + 3 * n) * ncl];
+                acc[4] += f[(22 + 3 * n + 1) * ncl];
+                acc[5] += f[(22 + 3 * n + 2) * ncl];
             }
         }
-    }
-    for (int k = 0; k < NF; k++) lam_in[k * fs + c] = acc[k];
-}
-
-// Interior cells: i in [2, nx - 3], j in [2, ny - 3] (grid over that box).
-template <typename T>
-__global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restrict__ DU, const T* __restrict__ FCX,
-                                                    const T* __restrict__ FCY, const T* __restrict__ SC,
-                                                    T* __restrict__ lam_in)
-{
-    const int i = 2 + blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = 2 + blockIdx.y;
-    if (i > P.nx - 3 || j > P.ny - 3) return;
-    adj_gather_cell(P, DU, FCX, FCY, SC, lam_in, i, j);
+    for (int k = 0; k < NF; k++) lam_in[k * fs + c] = z ? acc[k] + zc * z[k * fs + c] : acc[k];
 }
 
 // Edge ring: the cells outside the interior box, enumerated as the bottom
@@ -1066,16 +1005,26 @@ __host__ __device__ inline long long adj_ring_cells(int nx, int ny)
     return (long long)(nbot + ntop) * nx + (long long)mid * ncol;
 }
 
-// One wavefront per ring cell: the lanes share the candidate contributions
+// Pass C in one launch of 128-thread workgroups (the two kinds of cell get
+// separate workgroups, so no wavefront mixes the paths).  Workgroups 0 .. nbi-1
+// cover the interior box i in [2, nx - 3], j in [2, ny - 3] (nbx workgroups of
+// 128 cells per row), one thread per cell.  The rest cover the edge ring with
+// one wavefront per ring cell: the lanes share the candidate contributions
 // (24 x-face and 24 y-face (face, stencil position) pairs, 9 source cells x
 // 34 slots), keep those the ghost map sends to this cell, and the lanes'
 // partial sums are combined by a fixed butterfly (deterministic).
 template <typename T>
-__global__ void __launch_bounds__(128) k_adj_gather_ring(KParams P, const T* __restrict__ DU,
-                                                         const T* __restrict__ FCX, const T* __restrict__ FCY,
-                                                         const T* __restrict__ SC, T* __restrict__ lam_in)
+__global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restrict__ DU, const T* __restrict__ FCX,
+                                                    const T* __restrict__ FCY, const T* __restrict__ SC, const T* z,
+                                                    T zc, T* lam_in, int nbi, int nbx)
 {
-    const long long r = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if ((int)blockIdx.x < nbi) {
+        const int i = 2 + ((int)blockIdx.x % nbx) * 128 + (int)threadIdx.x;
+        const int j = 2 + (int)blockIdx.x / nbx;
+        if (i <= P.nx - 3) adj_gather_interior(P, DU, FCX, FCY, SC, z, zc, lam_in, i, j);
+        return;
+    }
+    const long long r = ((long long)(blockIdx.x - nbi) * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     const int nx = P.nx, ny = P.ny;
     if (r >= adj_ring_cells(nx, ny)) return;  // whole wavefront
@@ -1145,7 +1094,8 @@ __global__ void __launch_bounds__(128) k_adj_gather_ring(KParams P, const T* __r
 #pragma unroll
         for (int k = 1; k < NF; k++) v = lane == k ? acc[k] : v;
         const size_t c = (size_t)j * P.pitch + i;
-        lam_in[lane * fs + c] = DU[lane * fs + c] + v;
+        const T o = DU[lane * fs + c] + v;
+        lam_in[lane * fs + c] = z ? o + zc * z[lane * fs + c] : o;
     }
 }
 
@@ -1180,17 +1130,6 @@ __global__ void __launch_bounds__(256) k_loss(KParams P, const T* __restrict__ U
         __syncthreads();
     }
     if (tid == 0) part[blockIdx.x] = sh[0];
-}
-
-// y = a x + c z on [6][ny][pitch] arrays (interior cells only).
-template <typename T>
-__global__ void k_axpbz(KParams P, T a, const T* __restrict__ x, T c, const T* __restrict__ z, T* __restrict__ y)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= P.nx) return;
-    const size_t o = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
-    for (int k = 0; k < NF; k++) y[k * fs + o] = a * x[k * fs + o] + (z ? c * z[k * fs + o] : T(0));
 }
 
 // FP64 partial dot products of two [6][ny][pitch] arrays.

@@ -32,7 +32,7 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
     // 3/4 U + 1/4 E(Us) -> Us2, then 1/3 U + 2/3 E(Us2) -> U.
     const int kind = part == 0 ? 1 : (P.rk == 2 ? 2 : (part == 1 ? 3 : 4));
     const T* in = part == 0 ? U : (kind == 4 ? Us2 : Us);
-    T* out = part == 0 ? Us : (kind == 3 ? Us2 : U);
+    T* out = part == 0 ? Us : (kind == 3 ? Us2 : (B.Uout ? (T*)B.Uout : U));
     if (sh.variant == 1) {
         dim3 blk(64, 4), grd(sh.nbx, sh.nby);
 #define M2P_REF(K) \
@@ -139,26 +139,26 @@ hipError_t Launch<M2P_REAL>::jvp(const KParams& P, const Bufs& B, const void* U,
 }
 
 template <>
-hipError_t Launch<M2P_REAL>::vjp(const KParams& P, const Bufs& B, const void* U, const void* lam, int stage, double dt,
-                                 void* GT, void* DU, void* FCX, void* FCY, void* SC, void* lam_in, void* gmu,
-                                 hipStream_t st)
+hipError_t Launch<M2P_REAL>::vjp(const KParams& P, const Bufs& B, const void* U, const void* lam, double lscale,
+                                 int stage, double dt, void* GT, void* DU, void* FCX, void* FCY, void* SC,
+                                 void* lam_in, const void* z, double zc, void* gmu, hipStream_t st)
 {
     using T = M2P_REAL;
     dim3 blk(128), grd((P.nx + 127) / 128, P.ny);
     const T* b = (const T*)B.b;
-    hipLaunchKernelGGL((k_adj_post<T>), grd, blk, 0, st, P, (const T*)U, (const T*)lam, b, (const T*)B.mu, B.S, stage,
-                       T(dt), (T*)GT, (T*)DU, (T*)gmu);
-    hipLaunchKernelGGL((k_adj_face<T>), dim3((P.nx + 1 + 127) / 128, P.ny), blk, 0, st, P, (const T*)U,
-                       (const T*)GT, b, 0, T(dt), (T*)FCX);
-    hipLaunchKernelGGL((k_adj_face<T>), dim3((P.nx + 127) / 128, P.ny + 1), blk, 0, st, P, (const T*)U,
-                       (const T*)GT, b, 1, T(dt), (T*)FCY);
+    hipLaunchKernelGGL((k_adj_post<T>), grd, blk, 0, st, P, (const T*)U, (const T*)lam, T(lscale), b,
+                       (const T*)B.mu, B.S, stage, T(dt), (T*)GT, (T*)DU, (T*)gmu);
+    // x-face rows 0 .. ny-1, then y-face rows 0 .. ny
+    hipLaunchKernelGGL((k_adj_face<T>), dim3((P.nx + 1 + 127) / 128, 2 * P.ny + 1), blk, 0, st, P, (const T*)U,
+                       (const T*)GT, b, T(dt), (T*)FCX, (T*)FCY);
     hipLaunchKernelGGL((k_adj_src<T>), grd, blk, 0, st, P, (const T*)U, (const T*)GT, b, T(dt), (T*)SC);
-    if (P.nx >= 5 && P.ny >= 5)
-        hipLaunchKernelGGL((k_adj_gather<T>), dim3((P.nx - 4 + 127) / 128, P.ny - 4), blk, 0, st, P, (const T*)DU,
-                           (const T*)FCX, (const T*)FCY, (const T*)SC, (T*)lam_in);
+    // interior box (if any) and the edge ring, one launch
+    const int nbx = P.nx >= 5 && P.ny >= 5 ? (P.nx - 4 + 127) / 128 : 0;
+    const int nbi = nbx * (P.ny >= 5 ? P.ny - 4 : 0);
     const long long nring = adj_ring_cells(P.nx, P.ny);
-    hipLaunchKernelGGL((k_adj_gather_ring<T>), dim3((unsigned)((nring + 1) / 2)), blk, 0, st, P, (const T*)DU,
-                       (const T*)FCX, (const T*)FCY, (const T*)SC, (T*)lam_in);
+    hipLaunchKernelGGL((k_adj_gather<T>), dim3((unsigned)(nbi + (nring + 1) / 2)), blk, 0, st, P, (const T*)DU,
+                       (const T*)FCX, (const T*)FCY, (const T*)SC, (const T*)z, T(zc), (T*)lam_in, nbi,
+                       nbx > 0 ? nbx : 1);
     return hipGetLastError();
 }
 
@@ -169,16 +169,6 @@ hipError_t Launch<M2P_REAL>::loss(const KParams& P, const Bufs& B, const void* U
     using T = M2P_REAL;
     hipLaunchKernelGGL((k_loss<T>), dim3(kMassBlocks), dim3(256), 0, st, P, (const T*)U, (const T*)B.b, target,
                        (T*)lam, part);
-    return hipGetLastError();
-}
-
-template <>
-hipError_t Launch<M2P_REAL>::axpbz(const KParams& P, double a, const void* x, double c, const void* z, void* y,
-                                   hipStream_t st)
-{
-    using T = M2P_REAL;
-    dim3 blk(128), grd((P.nx + 127) / 128, P.ny);
-    hipLaunchKernelGGL((k_axpbz<T>), grd, blk, 0, st, P, T(a), (const T*)x, T(c), (const T*)z, (T*)y);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ struct Bufs {
     void* U;               // state U^n (6 fields, [ny][pitch] each)
     void* Us;              // stage state U*
     void* Us2;             // second stage state of the three-stage method (else nullptr)
+    void* Uout;            // output of the step's last stage (nullptr: in place over U)
     const void* b;         // padded DEM / L
     const void* mu;        // per-cell tan(delta_b) or nullptr
     DevScalars* S;         // device scalars
@@ -72,13 +73,13 @@ struct Launch {
     // adjoint support (buffers are [6][ny][pitch] state-shaped unless noted)
     static hipError_t jvp(const KParams& P, const Bufs& B, const void* U, const void* dU, const void* dmu, int stage,
                           void* E, void* dE, hipStream_t st);
-    static hipError_t vjp(const KParams& P, const Bufs& B, const void* U, const void* lam, int stage, double dt,
-                          void* GT, void* DU, void* FCX, void* FCY, void* SC, void* lam_in, void* gmu,
-                          hipStream_t st);
+    // lam_in = transpose of the stage applied to lscale * lam, plus zc * z if z
+    // is given (z may alias lam_in)
+    static hipError_t vjp(const KParams& P, const Bufs& B, const void* U, const void* lam, double lscale,
+                          int stage, double dt, void* GT, void* DU, void* FCX, void* FCY, void* SC, void* lam_in,
+                          const void* z, double zc, void* gmu, hipStream_t st);
     static hipError_t loss(const KParams& P, const Bufs& B, const void* U, const double* target, void* lam,
                            double* part, hipStream_t st);
-    static hipError_t axpbz(const KParams& P, double a, const void* x, double c, const void* z, void* y,
-                            hipStream_t st);
     static hipError_t dot(const KParams& P, const void* x, const void* y, double* part, hipStream_t st);
 };
 
