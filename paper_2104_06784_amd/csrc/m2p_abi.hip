@@ -1294,16 +1294,37 @@ int m2p_adjoint_run(m2p_ctx* c, int64_t nsteps, int32_t ckpt_every, const double
         return rc;
     HIPCHK(hipMemcpy(tgt.p, target_h, n * 8, hipMemcpyHostToDevice));
     const hipStream_t st = c->stream;
-    // forward with checkpoints and the time-step record
-    for (int64_t s = 0; s < nsteps; s++) {
-        if (s % ckpt_every == 0) {
-            const int k = (int)(s / ckpt_every);
-            HIPCHK(hipMemcpyAsync((char*)ckpt.p + sb * k, c->B.U, sb, hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipMemcpyAsync((char*)sck.p + sizeof(DevScalars) * k, c->S, sizeof(DevScalars),
-                                  hipMemcpyDeviceToDevice, st));
+    // time-step record: dts[0] is the current step's dt; the finalize of
+    // step s stores the dt of step s + 1 (the record is switched off again
+    // on every way out of this call)
+    DevScalars h0;
+    if ((rc = read_scalars(c, &h0))) return rc;
+    HIPCHK(hipMemcpy(dts.p, &h0.dt, 8, hipMemcpyHostToDevice));
+    struct DtLog {
+        double* p;
+        long long base, n;
+    };
+    static_assert(offsetof(DevScalars, n_log) == offsetof(DevScalars, dt_log) + offsetof(DtLog, n) &&
+                      offsetof(DevScalars, log_base) == offsetof(DevScalars, dt_log) + offsetof(DtLog, base),
+                  "time-step record fields");
+    const DtLog on{(double*)dts.p, h0.steps, nsteps};
+    HIPCHK(hipMemcpy((char*)c->S + offsetof(DevScalars, dt_log), &on, sizeof(on), hipMemcpyHostToDevice));
+    struct LogOff {
+        DevScalars* S;
+        hipStream_t st;
+        ~LogOff()
+        {
+            const DtLog off{nullptr, 0, 0};
+            (void)hipStreamSynchronize(st);
+            (void)hipMemcpy((char*)S + offsetof(DevScalars, dt_log), &off, sizeof(off), hipMemcpyHostToDevice);
         }
-        HIPCHK(hipMemcpyAsync((double*)dts.p + s, &c->S->dt, 8, hipMemcpyDeviceToDevice, st));
-        HIPCHK(do_step(c));
+    } log_off{c->S, st};
+    // forward with checkpoints (graph-captured chunks between them)
+    for (int k = 0; k < nseg; k++) {
+        HIPCHK(hipMemcpyAsync((char*)ckpt.p + sb * k, c->B.U, sb, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync((char*)sck.p + sizeof(DevScalars) * k, c->S, sizeof(DevScalars),
+                              hipMemcpyDeviceToDevice, st));
+        if ((rc = issue_steps(c, std::min<int64_t>(ckpt_every, nsteps - (int64_t)k * ckpt_every)))) return rc;
     }
     DevScalars hs;
     if ((rc = read_scalars(c, &hs)) || (rc = check_status(c, hs))) return rc;

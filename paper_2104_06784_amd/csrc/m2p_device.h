@@ -55,6 +55,8 @@ struct DevScalars {
     double sghost[3][MAX_SEG][NF];     // per stage: ghost state of each state segment
     const double* dt_sched;            // optional prescribed (frozen) time steps, dimensionless
     long long n_sched;
+    double* dt_log;                    // optional record: the finalize stores the next step's dt at
+    long long log_base, n_log;         //   dt_log[steps - log_base] when that index is in [0, n_log)
 };
 
 // Stage kinds of a step.  Heun, the paper's two-step modified Euler method:

@@ -609,6 +609,10 @@ __device__ __forceinline__ void fin_tail(const KParams& P, DevScalars* S, const 
     if (S->t_end - t < dt) dt = S->t_end - t;
     if (dt < 0.0) dt = 0.0;
     S->dt = dt;
+    if (S->dt_log) {
+        const long long q = S->steps - S->log_base;
+        if (q >= 0 && q < S->n_log) S->dt_log[q] = dt;
+    }
     // stage times: t, t + dt, and t + dt/2 for the third Runge-Kutta stage
     for (int s = 0; s < P.nseg; s++) {
         inflow_state(P, tables, s, t + dt, S->inflow[1][s]);
