@@ -39,7 +39,8 @@ typedef struct {
     double L, H, chi, g, m_dry, a_min;
     int32_t bc[4]; /* W, E, S, N: 0 transmissive, 1 closed wall */
     int32_t flags; /* bit 0: fluid interphase pressure weighted by phi^f as printed;
-                      bit 1: three-stage third-order SSP Runge-Kutta instead of Heun */
+                      bit 1: three-stage third-order SSP Runge-Kutta instead of Heun;
+                      bit 2: central-upwind face flux (one-sided local speeds) */
 } ora_params;
 
 typedef struct {
@@ -477,14 +478,59 @@ static void side_flux(const ora_sim *o, const double u[NF], const geo_t *g, int 
     a[1] = fabs(vnf) + sqrt(cf > 0.0 ? cf : 0.0);
 }
 
-/* Central (Kurganov-Tadmor) numerical flux at one face, per phase:
- * H = (F(U-) + F(U+))/2 - a/2 (U+ - U-), a = max of the phase's own speed. */
+/* One-sided speeds of one side of a face, per phase: the smallest and the
+ * largest characteristic speed v_n -/+ sqrt(dP/dm) in the face normal
+ * direction, from the same quantities as the speeds of side_flux. */
+static void side_speeds(const ora_sim *o, const double u[NF], const geo_t *g, int d, double lo[2],
+                        double hi[2])
+{
+    double eps = o->eps, al = o->alpha;
+    double ms = u[0], mf = u[3];
+    double hs = ms / g->J, hf = mf / g->J, h = hs + hf;
+    double vns = desing(d == 0 ? u[1] : u[2], ms, o->md);
+    double vnf = desing(d == 0 ? u[4] : u[5], mf, o->md);
+    double Ann = d == 0 ? g->A11 : g->A22;
+    double cs = eps * Ann * g->c * (1.0 - al) * (h + hs) / 2.0;
+    double cf = eps * Ann * g->c * h;
+    double rs = sqrt(cs > 0.0 ? cs : 0.0), rf = sqrt(cf > 0.0 ? cf : 0.0);
+    lo[0] = vns - rs;
+    hi[0] = vns + rs;
+    lo[1] = vnf - rf;
+    hi[1] = vnf + rf;
+}
+
+/* Central numerical flux at one face, per phase.
+ * Default (Kurganov-Tadmor): H = (F(U-) + F(U+))/2 - a/2 (U+ - U-), a = max of
+ * the phase's own speed on the two sides.
+ * flags bit 2, central-upwind (the one-sided-speed form of the same central
+ * scheme family, Kurganov-Noelle-Petrova, which Kurganov-Petrova 2007 builds
+ * on): a+ = max(largest speed of the two sides, 0), a- = min(smallest speed of
+ * the two sides, 0),
+ *   H = (a+ F(U-) - a- F(U+)) / (a+ - a-) + a+ a- / (a+ - a-) (U+ - U-),
+ * and (F(U-) + F(U+))/2 where a+ = a- = 0.  With a- = -a+ it is the
+ * Kurganov-Tadmor flux. */
 static void central_flux(const ora_sim *o, const double uL[NF], const geo_t *gL,
                          const double uR[NF], const geo_t *gR, int d, double H[NF])
 {
     double FL[NF], FR[NF], qL[NF], qR[NF], aL[2], aR[2];
     side_flux(o, uL, gL, d, FL, qL, aL);
     side_flux(o, uR, gR, d, FR, qR, aR);
+    if (o->p.flags & 4) {
+        double loL[2], hiL[2], loR[2], hiR[2];
+        side_speeds(o, uL, gL, d, loL, hiL);
+        side_speeds(o, uR, gR, d, loR, hiR);
+        for (int ph = 0; ph < 2; ph++) {
+            double ap = hiL[ph] > hiR[ph] ? hiL[ph] : hiR[ph];
+            double am = loL[ph] < loR[ph] ? loL[ph] : loR[ph];
+            if (ap < 0.0) ap = 0.0;
+            if (am > 0.0) am = 0.0;
+            double den = ap - am;
+            for (int k = 3 * ph; k < 3 * ph + 3; k++)
+                H[k] = den > 0.0 ? (ap * FL[k] - am * FR[k]) / den + ap * am / den * (qR[k] - qL[k])
+                                 : 0.5 * (FL[k] + FR[k]);
+        }
+        return;
+    }
     for (int ph = 0; ph < 2; ph++) {
         double a = aL[ph] > aR[ph] ? aL[ph] : aR[ph];
         for (int k = 3 * ph; k < 3 * ph + 3; k++)

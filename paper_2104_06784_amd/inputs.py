@@ -31,6 +31,7 @@ SIDE_W, SIDE_E, SIDE_S, SIDE_N = 0, 1, 2, 3
 # Flags.
 F_FLUID_PRESSURE_AS_PRINTED = 1
 F_RK3 = 2                       # three-stage SSP Runge-Kutta instead of Heun
+F_CENTRAL_UPWIND = 4            # central-upwind face flux (one-sided local speeds)
 
 
 @dataclasses.dataclass
