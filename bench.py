@@ -204,9 +204,10 @@ def bench_sweep(stream, steps: int) -> dict:
 
 def bench_variants(stream, steps: int, prob3) -> dict:
     """The scheme variants on their workloads: the three-stage Runge-Kutta
-    option on the large event (prob3, FP32), and Mode-II inflow as a state
-    hydrograph on the paper's second event's grid shape (180 x 154, graph
-    replay) next to the same grid without the segment."""
+    and the central-upwind flux options on the large event (prob3, FP32),
+    and Mode-II inflow as a state hydrograph on the paper's second event's
+    grid shape (180 x 154, graph replay) next to the same grid without the
+    segment."""
     import torch
 
     from paper_2104_06784_amd import inputs
@@ -223,13 +224,14 @@ def bench_variants(stream, steps: int, prob3) -> dict:
         return e0.elapsed_time(e1)
 
     out = {}
-    p3 = dataclasses.replace(prob3, params=dataclasses.replace(prob3.params, flags=inputs.F_RK3))
-    sim = Sim(p3, precision="f32", stream=stream)
-    sim.run(5)
-    ms = timed(sim, steps)
-    out["rk3"] = {"value": round(p3.cells * steps / (ms / 1e3) / 1e6, 2), "unit": "Mcell-steps/s",
-                  "ms_per_step": round(ms / steps, 4), "steps": steps, "cells": p3.cells}
-    del sim
+    for key, flag in (("rk3", inputs.F_RK3), ("central_upwind", inputs.F_CENTRAL_UPWIND)):
+        p3 = dataclasses.replace(prob3, params=dataclasses.replace(prob3.params, flags=flag))
+        sim = Sim(p3, precision="f32", stream=stream)
+        sim.run(5)
+        ms = timed(sim, steps)
+        out[key] = {"value": round(p3.cells * steps / (ms / 1e3) / 1e6, 2), "unit": "Mcell-steps/s",
+                    "ms_per_step": round(ms / steps, 4), "steps": steps, "cells": p3.cells}
+        del sim
     pd = inputs.df004_shaped()
     k = 50 * steps
     rec = {"nx": pd.nx, "ny": pd.ny, "steps": k}
@@ -244,7 +246,8 @@ def bench_variants(stream, steps: int, prob3) -> dict:
             rec["inflow_m3"] = round(-(d["out_s"] + d["out_f"]), 1)  # state segments: negative outflow
         del sim
     out["mode2_state"] = rec
-    log(f"[bench] variants: rk3 {out['rk3']['value']} Mcell-steps/s; state inflow "
+    log(f"[bench] variants: rk3 {out['rk3']['value']}, central-upwind {out['central_upwind']['value']} "
+        f"Mcell-steps/s; state inflow "
         f"{rec['state_inflow_us_per_step']} us/step ({rec['no_inflow_us_per_step']} without)")
     return out
 

@@ -65,6 +65,13 @@ extern "C" {
                        (Heun): U1 = E(U^n), U2 = 3/4 U^n + 1/4 E(U1), U^{n+1} = 1/3 U^n + 2/3 E(U2) at stage
                        times t, t + dt, t + dt/2 (Sect. 2.2 names multi-step Runge-Kutta methods as the family);
                        single-scenario contexts only, not with the adjoint */
+#define M2P_F_CENTRAL_UPWIND 4 /* central-upwind face flux with one-sided local speeds instead of the Kurganov-Tadmor
+                       central flux: per phase a+ = max(largest characteristic speed v_n + sqrt(dP/dm) of the two
+                       sides, 0), a- = min(smallest speed v_n - sqrt(dP/dm), 0), H = (a+ F- - a- F+) / (a+ - a-)
+                       + a+ a- / (a+ - a-) (U+ - U-), (F- + F+) / 2 on a dry face (Sect. 2.2 builds on the central
+                       schemes of Kurganov-Tadmor 2000 and Kurganov-Petrova 2007; this is the latter's flux without
+                       its well-balanced surface reconstruction); single-scenario contexts only, not with the
+                       tangent and adjoint calls */
 
 /* thickness convention of m2p_set_state */
 #define M2P_DEPTH_NORMAL 0   /* h measured normal to the bed (the paper's h, Sect. 2.1) */

@@ -316,7 +316,8 @@ int validate_scenario(const m2p_grid* g, const m2p_params* p, int32_t prec, cons
         return fail(M2P_EINVAL, "c_d, 1/N_R, theta_b >= 0 and m_dry, a_min > 0 required");
     for (int s = 0; s < 4; s++)
         if (p->bc[s] != M2P_BC_TRANSMISSIVE && p->bc[s] != M2P_BC_WALL) return fail(M2P_EINVAL, "bad boundary mode");
-    if (p->flags & ~(M2P_F_FLUID_PRESSURE_AS_PRINTED | M2P_F_RK3)) return fail(M2P_EINVAL, "unknown flag");
+    if (p->flags & ~(M2P_F_FLUID_PRESSURE_AS_PRINTED | M2P_F_RK3 | M2P_F_CENTRAL_UPWIND))
+        return fail(M2P_EINVAL, "unknown flag");
     size_t n = (size_t)g->nx * g->ny;
     for (size_t k = 0; k < n; k++)
         if (!std::isfinite(dem[k])) return fail(M2P_EINVAL, "non-finite DEM value");
@@ -1167,8 +1168,19 @@ int L_loss(m2p_ctx* c, const double* target_dev, void* lam, double* loss)
     return M2P_OK;
 }
 
+static_assert(m2p::kFlagCentralUpwind == M2P_F_CENTRAL_UPWIND, "central-upwind flag bit");
+
+// The tangent and adjoint kernels differentiate the Kurganov-Tadmor flux.
+int flux_unsupported(m2p_ctx* c)
+{
+    if (c->kp.flags & M2P_F_CENTRAL_UPWIND)
+        return m2p::fail(M2P_EINVAL, "the tangent and adjoint kernels differentiate the central (Kurganov-Tadmor) flux");
+    return M2P_OK;
+}
+
 int inflow_unsupported(m2p_ctx* c)
 {
+    if (int rc = flux_unsupported(c)) return rc;
     if (c->kp.nseg > 0 || c->kp.nsseg > 0)
         return m2p::fail(M2P_EINVAL, "the adjoint supports Mode-I (no inflow segments)");
     if (c->kp.rk != 2) return m2p::fail(M2P_EINVAL, "the adjoint differentiates the two-step (Heun) method");
@@ -1238,7 +1250,9 @@ int m2p_loss(m2p_ctx* c, const double* target_h, double* loss)
 int m2p_stage_jvp(m2p_ctx* c, int32_t stage, const double* dU, const double* dmu, double* E, double* dE)
 {
     if (!c || !dU || !E || !dE || stage < 0 || stage > 1) return fail(M2P_EINVAL, "bad argument");
-    int rc = ensure_ready(c);
+    int rc = flux_unsupported(c);
+    if (rc) return rc;
+    rc = ensure_ready(c);
     if (rc) return rc;
     DevBuf ddU, dE_, E_, dmu_;
     if ((rc = ddU.alloc(c->state_bytes)) || (rc = E_.alloc(c->state_bytes)) || (rc = dE_.alloc(c->state_bytes)))
@@ -1256,7 +1270,9 @@ int m2p_stage_jvp(m2p_ctx* c, int32_t stage, const double* dU, const double* dmu
 int m2p_stage_vjp(m2p_ctx* c, int32_t stage, const double* lam, double* lam_in, double* gmu)
 {
     if (!c || !lam || !lam_in || stage < 0 || stage > 1) return fail(M2P_EINVAL, "bad argument");
-    int rc = ensure_ready(c);
+    int rc = flux_unsupported(c);
+    if (rc) return rc;
+    rc = ensure_ready(c);
     if (rc) return rc;
     DevScalars hs;
     if ((rc = read_scalars(c, &hs))) return rc;

@@ -224,6 +224,8 @@ int m2p_batch_create(m2p_batch** out, int32_t nscen, const m2p_grid* grids, cons
         int rc = validate_scenario(&grids[i], &params[i], prec, dems[i]);
         if (rc) return fail(rc, "scenario " + std::to_string(i) + ": " + m2p_last_error());
         if (params[i].flags & M2P_F_RK3) return fail(M2P_EINVAL, "ensembles run the two-step (Heun) method");
+        if (params[i].flags & M2P_F_CENTRAL_UPWIND)
+            return fail(M2P_EINVAL, "ensembles run the central (Kurganov-Tadmor) flux");
         if ((size_t)((grids[i].nx + 59) / 60) * (size_t)((grids[i].ny + 3) / 4) >= (1u << 20))
             return fail(M2P_EINVAL, "scenario too large for a batch");
     }

@@ -208,10 +208,11 @@ struct Consts {
 
 // Physical flux of one reconstructed side of a face (flux vectors F, G of
 // Appendix A with the owner cell's geometry), the conserved values entering
-// the numerical diffusion and the phase speeds |v_n| + sqrt(dP/dm).
-template <typename T>
+// the numerical diffusion and the phase speeds |v_n| + sqrt(dP/dm); with OS
+// (one-sided), a = v_n + sqrt(dP/dm) and am = v_n - sqrt(dP/dm) instead.
+template <typename T, bool OS = false>
 M2P_FN void side_flux(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d,
-                                          T F[NF], T qv[NF], T a[2])
+                                          T F[NF], T qv[NF], T a[2], T* am = nullptr)
 {
     if constexpr (Folded<T>::value) {
         const T ms = u[0], mf = u[3];
@@ -241,8 +242,16 @@ M2P_FN void side_flux(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d,
         const T ac = K.eps * Ann * g.c;
         const T cs = ac * K.half_oma * (h + hs);
         const T cf = ac * h;
-        a[0] = fabs(vns) + sqrt(cs > T(0) ? cs : T(0));
-        a[1] = fabs(vnf) + sqrt(cf > T(0) ? cf : T(0));
+        const T rs = sqrt(cs > T(0) ? cs : T(0)), rf = sqrt(cf > T(0) ? cf : T(0));
+        if constexpr (OS) {
+            a[0] = vns + rs;
+            am[0] = vns - rs;
+            a[1] = vnf + rf;
+            am[1] = vnf - rf;
+        } else {
+            a[0] = fabs(vns) + rs;
+            a[1] = fabs(vnf) + rf;
+        }
         return;
     }
     T ms = u[0], mf = u[3];
@@ -270,8 +279,16 @@ M2P_FN void side_flux(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d,
     qv[5] = mf * vYf;
     T cs = K.eps * Ann * g.c * (T(1) - K.al) * (h + hs) / T(2);
     T cf = K.eps * Ann * g.c * h;
-    a[0] = fabs(vns) + sqrt(cs > T(0) ? cs : T(0));
-    a[1] = fabs(vnf) + sqrt(cf > T(0) ? cf : T(0));
+    T rs = sqrt(cs > T(0) ? cs : T(0)), rf = sqrt(cf > T(0) ? cf : T(0));
+    if constexpr (OS) {
+        a[0] = vns + rs;
+        am[0] = vns - rs;
+        a[1] = vnf + rf;
+        am[1] = vnf - rf;
+    } else {
+        a[0] = fabs(vns) + rs;
+        a[1] = fabs(vnf) + rf;
+    }
 }
 
 // Phase speeds only (identical arithmetic to side_flux).
@@ -338,12 +355,46 @@ constexpr bool carry_2h()
     return H2 && Folded<T>::value;
 }
 
-// Central (Kurganov-Tadmor) flux per phase: (F- + F+)/2 - a/2 (U+ - U-)
-// (twice that when carried as 2 H).
-template <typename T, bool H2 = false>
+// Central flux per phase (twice the flux when carried as 2 H).
+// Default, Kurganov-Tadmor: (F- + F+)/2 - a/2 (U+ - U-), a the larger of the
+// two sides' phase speeds.  CU, central-upwind with one-sided local speeds
+// (the form Kurganov-Petrova 2007 builds on): a+ = max(largest speed of the
+// two sides, 0), a- = min(smallest speed, 0),
+//   H = (a+ F- - a- F+) / (a+ - a-) + a+ a- / (a+ - a-) (U+ - U-),
+// and (F- + F+)/2 where a+ = a- = 0 (a dry face).
+template <typename T, bool H2 = false, bool CU = false>
 M2P_FN void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
                                              const T uR[NF], const Geo<T>& gR, int d, T H[NF])
 {
+    if constexpr (CU) {
+        T FL[NF], FR[NF], qL[NF], qR[NF], hiL[2], loL[2], hiR[2], loR[2];
+        side_flux<T, true>(K, uL, gL, d, FL, qL, hiL, loL);
+        side_flux<T, true>(K, uR, gR, d, FR, qR, hiR, loR);
+#pragma unroll
+        for (int ph = 0; ph < 2; ph++) {
+            T ap = hiL[ph] > hiR[ph] ? hiL[ph] : hiR[ph];
+            T am = loL[ph] < loR[ph] ? loL[ph] : loR[ph];
+            ap = ap < T(0) ? T(0) : ap;
+            am = am > T(0) ? T(0) : am;
+            const T den = ap - am;
+            const bool wet = den > T(0);
+            if constexpr (Folded<T>::value) {
+                // one reciprocal per phase; the 2 H carry folds into it
+                const T r = wet ? (carry_2h<T, H2>() ? T(2) : T(1)) / den : T(0);
+                const T c0 = carry_2h<T, H2>() ? T(1) : T(0.5);
+#pragma unroll
+                for (int k = 3 * ph; k < 3 * ph + 3; k++)
+                    H[k] = wet ? (ap * FL[k] - am * FR[k]) * r + ap * am * r * (qR[k] - qL[k])
+                               : c0 * (FL[k] + FR[k]);
+            } else {
+#pragma unroll
+                for (int k = 3 * ph; k < 3 * ph + 3; k++)
+                    H[k] = wet ? (ap * FL[k] - am * FR[k]) / den + ap * am / den * (qR[k] - qL[k])
+                               : T(0.5) * (FL[k] + FR[k]);
+            }
+        }
+        return;
+    }
     T FL[NF], FR[NF], qL[NF], qR[NF], aL[2], aR[2];
     side_flux(K, uL, gL, d, FL, qL, aL);
     side_flux(K, uR, gR, d, FR, qR, aR);
@@ -358,6 +409,21 @@ M2P_FN void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
                 H[k] = T(0.5) * (FL[k] + FR[k]) - T(0.5) * a * (qR[k] - qL[k]);
         }
     }
+}
+
+// KParams.flags bit of the central-upwind face flux (M2P_F_CENTRAL_UPWIND).
+constexpr int kFlagCentralUpwind = 4;
+
+// The face flux the flags select, chosen at run time (the tiled kernels take
+// the choice as a template argument instead).
+template <typename T>
+M2P_FN void face_flux_sel(const Consts<T>& K, int flags, const T uL[NF], const Geo<T>& gL, const T uR[NF],
+                          const Geo<T>& gR, int d, T H[NF])
+{
+    if (flags & kFlagCentralUpwind)
+        central_flux<T, false, true>(K, uL, gL, uR, gR, d, H);
+    else
+        central_flux(K, uL, gL, uR, gR, d, H);
 }
 
 // Prescribed Mode-II face flux from the critical-depth inflow state

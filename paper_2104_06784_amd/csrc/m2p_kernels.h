@@ -157,19 +157,19 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
             for (int q = 0; q < 4; q++)
                 for (int k = 0; k < NF; k++) w[q][k] = row[q][k];
             reconstruct(w, uL, uR);
-            central_flux(K, uL, gW, uR, gC, 0, HXl);
+            face_flux_sel(K, P.flags, uL, gW, uR, gC, 0, HXl);
             for (int q = 0; q < 4; q++)
                 for (int k = 0; k < NF; k++) w[q][k] = row[q + 1][k];
             reconstruct(w, uL, uR);
-            central_flux(K, uL, gC, uR, gE, 0, HXr);
+            face_flux_sel(K, P.flags, uL, gC, uR, gE, 0, HXr);
             for (int q = 0; q < 4; q++)
                 for (int k = 0; k < NF; k++) w[q][k] = col[q][k];
             reconstruct(w, uL, uR);
-            central_flux(K, uL, gS, uR, gC, 1, HYb);
+            face_flux_sel(K, P.flags, uL, gS, uR, gC, 1, HYb);
             for (int q = 0; q < 4; q++)
                 for (int k = 0; k < NF; k++) w[q][k] = col[q + 1][k];
             reconstruct(w, uL, uR);
-            central_flux(K, uL, gC, uR, gN, 1, HYt);
+            face_flux_sel(K, P.flags, uL, gC, uR, gN, 1, HYt);
         }
         // Mode-II faces, and the flux through every boundary face into the
         // per-face outflow slots (zero on discharge-inflow faces)

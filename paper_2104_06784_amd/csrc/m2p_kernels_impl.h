@@ -48,14 +48,21 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
 #undef M2P_REF
     } else {
         dim3 blk(256), grd(sh.blocks);
+#define M2P_TILED_GC(K, GH, CU)                                                                                 \
+    hipLaunchKernelGGL((k_stage_tiled<T, K, GH, CU>), grd, blk, 0, st, P, in, U, out, b, mu, B.S, B.bpart,      \
+                       B.wpart, B.nmax, sh.R, sh.nstrips, sh.nrb)
 #define M2P_TILED(K)                                                                                            \
     do {                                                                                                        \
-        if (P.nsseg > 0)                                                                                        \
-            hipLaunchKernelGGL((k_stage_tiled<T, K, true>), grd, blk, 0, st, P, in, U, out, b, mu, B.S,         \
-                               B.bpart, B.wpart, B.nmax, sh.R, sh.nstrips, sh.nrb);                             \
+        const bool cu = (P.flags & kFlagCentralUpwind) != 0;                                                    \
+        if (P.nsseg > 0) {                                                                                      \
+            if (cu)                                                                                             \
+                M2P_TILED_GC(K, true, true);                                                                    \
+            else                                                                                                \
+                M2P_TILED_GC(K, true, false);                                                                   \
+        } else if (cu)                                                                                          \
+            M2P_TILED_GC(K, false, true);                                                                       \
         else                                                                                                    \
-            hipLaunchKernelGGL((k_stage_tiled<T, K, false>), grd, blk, 0, st, P, in, U, out, b, mu, B.S,        \
-                               B.bpart, B.wpart, B.nmax, sh.R, sh.nstrips, sh.nrb);                             \
+            M2P_TILED_GC(K, false, false);                                                                      \
     } while (0)
         if (kind == 1)
             M2P_TILED(1);
@@ -66,6 +73,7 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
         else
             M2P_TILED(4);
 #undef M2P_TILED
+#undef M2P_TILED_GC
     }
     return hipGetLastError();
 }

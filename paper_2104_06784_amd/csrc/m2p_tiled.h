@@ -103,8 +103,8 @@ struct WavePart {
 // scenario; returns its partials (the same in every lane).  GH: the
 // scenario has Mode-II state segments, whose ghost cells replace the mapped
 // boundary values (a separate instance, so runs without them carry none of
-// that code in the march).
-template <typename T, int STAGE, bool GH>
+// that code in the march).  CU: central-upwind face fluxes.
+template <typename T, int STAGE, bool GH, bool CU = false>
 __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* __restrict__ Uin, const T* Un, T* Uout,
                                                  const T* __restrict__ b, const T* __restrict__ mu,
                                                  DevScalars* __restrict__ S, double* __restrict__ bpart,
@@ -205,7 +205,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             uL[k] = Um1[k] + T(0.5) * sym[k];
             uR[k] = U0[k] - T(0.5) * sy0[k];
         }
-        central_flux<T, H2>(K, uL, Dm.g, uR, D0.g, 1, Hy);
+        central_flux<T, H2, CU>(K, uL, Dm.g, uR, D0.g, 1, Hy);
         if (r0 == 0 && out_lane) {
             const int s = inflow_seg_at(P, 2, col);
             if (s >= 0)
@@ -262,7 +262,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             uR[k] = Un1[k] - T(0.5) * sy1[k];
         }
         // ---- y-face j + 1/2
-        central_flux<T, H2>(K, uL, D0.g, uR, D1.g, 1, HyN);
+        central_flux<T, H2, CU>(K, uL, D0.g, uR, D1.g, 1, HyN);
         if (j == P.ny - 1 && out_lane) {
             const int s = inflow_seg_at(P, 3, col);
             if (s >= 0)
@@ -296,7 +296,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             gR.A12 = from_right(D0.g.A12);
             gR.A21 = gR.A12;
             gR.A22 = from_right(D0.g.A22);
-            central_flux<T, H2>(K, um, D0.g, upR, gR, 0, Hx);
+            central_flux<T, H2, CU>(K, um, D0.g, upR, gR, 0, Hx);
 #pragma unroll
             for (int k = 0; k < NF; k++) HxL[k] = from_left(Hx[k]);
         }
@@ -398,7 +398,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
     return WavePart{(double)amx, (double)amy, (double)clamps, (double)bad};
 }
 
-template <typename T, int STAGE, bool GH>
+template <typename T, int STAGE, bool GH, bool CU>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_wpe<T, STAGE>())))
 k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout, const T* __restrict__ b,
               const T* __restrict__ mu, DevScalars* __restrict__ S, double* __restrict__ bpart,
@@ -419,7 +419,8 @@ k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout, const 
     const int strip = wid % nstrips, rb = wid / nstrips;
     WavePart r{0.0, 0.0, 0.0, 0.0};  // neutral: speeds are >= 0
     if (rb < nrb)  // whole wavefront
-        r = stage_tiled_wave<T, STAGE, GH>(P, Uin, Un, Uout, b, mu, S, bpart, nmax, R, nstrips, nrb, strip, rb, lane);
+        r = stage_tiled_wave<T, STAGE, GH, CU>(P, Uin, Un, Uout, b, mu, S, bpart, nmax, R, nstrips, nrb, strip, rb,
+                                                   lane);
     // one partial record per workgroup (its four wavefronts in order), so
     // the finalize reads a quarter as many (at 4096 x 4096 the finalize
     // takes 30 instead of 42 us; the barrier costs small grids about 0.4 us

@@ -238,6 +238,64 @@ def test_rk3_fp32_and_refusals():
     assert e.value.code == M2P_EINVAL
 
 
+@pytest.mark.parametrize("variant", [1, 2])
+def test_central_upwind_option_fp64(variant):
+    """The central-upwind flux option (M2P_F_CENTRAL_UPWIND) against the
+    oracle's: config 1 (walls), the state/discharge inflow problem and, on the
+    tiled kernel, config 1 with the three-stage method too; both kernel
+    variants, diagnostics included."""
+    import dataclasses
+    cases = [(I.config1(n=96), 0), (_state_inflow_problem(), 0)]
+    if variant == 2:
+        cases.append((I.config1(n=80), I.F_RK3))
+    for prob, extra in cases:
+        q = dataclasses.replace(prob, params=dataclasses.replace(
+            prob.params, flags=prob.params.flags | I.F_CENTRAL_UPWIND | extra))
+        q.name = prob.name + "-cu"
+        _say(f"[parity] central-upwind {q.name} flags {q.params.flags} variant {variant}")
+        g, o = _compare_steps(q, 120, 1e-12, variant=variant)
+        dg, do = g.diag(), o.diag()
+        for k in ("mass_s", "mass_f", "in_s", "in_f", "out_s", "out_f"):
+            assert abs(dg[k] - do[k]) <= 1e-12 * max(abs(do[k]), 1.0), k
+
+
+def test_central_upwind_fp32_and_refusals():
+    """FP32 central-upwind stays within the FP32 tolerance of the FP64
+    oracle (config 1 to 3 s; the state/discharge inflow problem to 3 s with
+    its volume budget -- later the option's time step collapses there, in
+    the oracle as on the GPU, as thin fluid layers accelerate); the tangent,
+    adjoint and ensemble calls refuse the option."""
+    import dataclasses
+
+    from paper_2104_06784_amd._abi import M2P_EINVAL, M2PError
+    from paper_2104_06784_amd.sim import Batch
+    prob = I.config1()
+    q = dataclasses.replace(prob, params=dataclasses.replace(prob.params, flags=I.F_CENTRAL_UPWIND))
+    g, o = Sim(q, precision="f32"), Ora(q)
+    g.run_to(3.0)
+    o.run(10 ** 6, 3.0)
+    hg, ho = g.fields()["h"], o.fields()["h"]
+    l1 = np.abs(hg - ho).sum() / ho.sum()
+    ps = _state_inflow_problem()
+    ps = dataclasses.replace(ps, params=dataclasses.replace(ps.params, flags=ps.params.flags | I.F_CENTRAL_UPWIND))
+    gs, os_ = Sim(ps, precision="f32"), Ora(ps)
+    gs.run_to(3.0)
+    os_.run(10 ** 6, 3.0)
+    hs_, hso = gs.fields()["h"], os_.fields()["h"]
+    l1s = np.sum(np.abs(hs_ - hso)) / np.sum(np.abs(hso))
+    d = gs.diag()
+    m0 = float(np.sum(ps.h_vert)) * ps.dx * ps.dy
+    bud = abs(d["mass_s"] + d["mass_f"] + d["out_s"] + d["out_f"] - d["in_s"] - d["in_f"] - m0) / m0
+    _say(f"[parity] central-upwind FP32: config 1 rel L1 {l1:.3e}; inflow rel L1 {l1s:.3e}, budget {bud:.3e}")
+    assert l1 <= 1e-3 and l1s <= 1e-3 and bud <= 1e-6
+    z = np.zeros((6, q.ny, q.nx))
+    for call in (lambda: g.adjoint_run(4, 2, np.zeros((q.ny, q.nx))), lambda: g.stage_jvp(z),
+                 lambda: g.stage_vjp(z), lambda: Batch([q, q], precision="f32")):
+        with pytest.raises(M2PError) as e:
+            call()
+        assert e.value.code == M2P_EINVAL
+
+
 def test_run_to_lands_on_end_time():
     prob = I.config1(n=64)
     g, o = Sim(prob, precision="f64"), Ora(prob)
