@@ -86,6 +86,8 @@ CASES = [
     dict(bc=(0, 0, 0, 0), visc=True, mu=True),
     dict(bc=(1, 1, 1, 1), visc=True, mu=False),
     dict(bc=(1, 0, 0, 1), visc=False, mu=True, nx=61, ny=23),
+    # fewer than five rows: every cell is an edge-ring cell of the gather
+    dict(bc=(0, 1, 1, 0), visc=True, mu=True, nx=13, ny=4),
 ]
 
 
