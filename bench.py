@@ -62,7 +62,7 @@ def kernel_source_hash() -> str:
 def recorded_traffic(n: int, precision: str):
     """HBM bytes per stage-2 launch from the rocprofv3 counter summary in
     profiles/, if it was taken on the current kernel sources and workload."""
-    path = os.path.join(ROOT, "profiles", f"stage2_cfg3_{n}_{precision}_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles", f"stage2_valley_event_{n}_{precision}_hbm_counters.md")
     if not os.path.exists(path):
         return None
     for line in open(path):
@@ -86,7 +86,7 @@ def stage_flops(stage: int, visc: bool) -> float:
 def recorded_valu(n: int, precision: str):
     """VALU busy fraction of the stage-2 kernel from the rocprofv3 counter
     summary in profiles/, if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"stage_kernels_cfg3_{n}_{precision}_valu_counters.md")
+    path = os.path.join(ROOT, "profiles", f"stage_kernels_valley_event_{n}_{precision}_valu_counters.md")
     if not os.path.exists(path):
         return None
     for line in open(path):
@@ -120,7 +120,7 @@ def cpu_baseline(prob, nsteps: int) -> dict:
 
 
 def bench_batched(stream, steps: int, warmup: int, nscen: int = 256) -> dict:
-    """Config 4: nscen scenarios of sides U{128..512} advanced together by the
+    """Ensemble: nscen scenarios of sides U{128..512} advanced together by the
     persistent work-list kernels (autotuned tile shape, graph replay), against
     the same scenarios run one after another with single-scenario contexts."""
     import torch
@@ -129,7 +129,7 @@ def bench_batched(stream, steps: int, warmup: int, nscen: int = 256) -> dict:
     from paper_2104_06784_amd.sim import Batch, Sim
 
     log(f"[bench] batched: generating {nscen} scenarios")
-    probs = [inputs.config4_scenario(i) for i in range(nscen)]
+    probs = [inputs.ensemble_member(i) for i in range(nscen)]
     cells = sum(p.cells for p in probs)
     b = Batch(probs, precision="f32", stream=stream)
     rows, blocks, tune_ms = b.autotune(3)
@@ -253,7 +253,7 @@ def bench_variants(stream, steps: int, prob3) -> dict:
 
 
 def bench_adjoint(stream, nsteps: int, ckpt: int) -> dict:
-    """Config 5: gradient of the deposit misfit with respect to the per-cell
+    """Calibration case (512^2): gradient of the deposit misfit with respect to the per-cell
     friction field and the release volume through nsteps FP32 steps
     (checkpoint every ckpt steps, segments recomputed), against the plain
     forward run of the same workload."""
@@ -263,12 +263,12 @@ def bench_adjoint(stream, nsteps: int, ckpt: int) -> dict:
     from paper_2104_06784_amd.sim import Sim
 
     log("[bench] adjoint: target from the hidden-parameter run")
-    truth = inputs.config5(truth=True)
+    truth = inputs.calibration_case(truth=True)
     t = Sim(truth, precision="f32", stream=stream)
     t.run(nsteps)
     target = t.fields()["h"]
     del t
-    prob = inputs.config5()
+    prob = inputs.calibration_case()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     f = Sim(prob, precision="f32", stream=stream)
     torch.cuda.synchronize()
@@ -320,8 +320,8 @@ def main():
     from paper_2104_06784_amd import inputs
     from paper_2104_06784_amd.sim import Sim
 
-    log(f"[bench] generating config 3 at {args.n}^2")
-    prob = inputs.config3(n=args.n)
+    log(f"[bench] generating the valley event at {args.n}^2")
+    prob = inputs.valley_event(n=args.n)
     stream = torch.cuda.Stream()
     sim = Sim(prob, precision=args.precision, stream=stream, variant=args.variant)
     log("[bench] warmup")

@@ -178,7 +178,7 @@ def triangular_hydrograph(q_peak: float, t_peak: float, t_end: float, phi: float
 # the five workloads
 # ---------------------------------------------------------------------------
 
-def config1(n: int = 128) -> Problem:
+def plane_bump_pile(n: int = 128) -> Problem:
     """FP64 parity case: 128^2, dx = 10 m, 30 deg plane plus a 20 m Gaussian bump
     (sigma 150 m), 10 m cylinder of radius 200 m with solid fraction 0.6,
     delta_b = 20 deg, closed walls, CFL 0.5, 200 steps.  The bump and the pile
@@ -189,10 +189,10 @@ def config1(n: int = 128) -> Problem:
         -((X - 800.0) ** 2 + (Y - 640.0) ** 2) / (2.0 * 150.0 ** 2))
     h = cylinder(n, n, dx, dx, 320.0, 640.0, 200.0, 10.0)
     p = Params(delta_b_deg=20.0, delta_int_deg=35.0, cfl=0.5, bc=(BC_WALL,) * 4)
-    return Problem("cfg1", n, n, dx, dx, p, dem, h, np.where(h > 0, 0.6, 0.0), steps=200, precision="f64")
+    return Problem("plane-bump-pile", n, n, dx, dx, p, dem, h, np.where(h > 0, 0.6, 0.0), steps=200, precision="f64")
 
 
-def config2(n: int = 1024, steps: int = 5000) -> Problem:
+def fractal_hydrograph(n: int = 1024, steps: int = 5000) -> Problem:
     """FP32-vs-FP64 case: 1024^2, dx = 5 m, fractal DEM (200 m relief) on a 20 deg
     tilt, Mode-II triangular hydrograph (peak 500 m^3/s at 180 s, end 360 s,
     solid fraction 0.5) on a 10-cell segment centred on the west side."""
@@ -202,10 +202,10 @@ def config2(n: int = 1024, steps: int = 5000) -> Problem:
     seg = Inflow(SIDE_W, n // 2 - 5, 10, t, Q, ph)
     z = np.zeros((n, n))
     p = Params(delta_b_deg=16.0, bc=(BC_TRANSMISSIVE,) * 4)
-    return Problem("cfg2", n, n, dx, dx, p, dem, z, z.copy(), [seg], steps=steps, precision="f32")
+    return Problem("fractal-hydrograph", n, n, dx, dx, p, dem, z, z.copy(), [seg], steps=steps, precision="f32")
 
 
-def config3(n: int = 4096, steps: int = 20000) -> Problem:
+def valley_event(n: int = 4096, steps: int = 20000) -> Problem:
     """Large event: 4096^2, dx = 5 m, exponential longitudinal relief (1.5 km),
     parabolic valley (100 m wall height at 500 m from the axis) plus 50 m of
     fractal roughness; half-ellipsoid release of 2.5e7 m^3 (600 m x 300 m),
@@ -219,10 +219,10 @@ def config3(n: int = 4096, steps: int = 20000) -> Problem:
     h0 = 3.0 * V / (2.0 * math.pi * 600.0 * 300.0)
     h = half_ellipsoid(n, n, dx, dx, 1000.0, yc, 600.0, 300.0, h0)
     p = Params(delta_b_deg=16.0)
-    return Problem("cfg3", n, n, dx, dx, p, dem, h, np.where(h > 0, 0.55, 0.0), steps=steps, precision="f32")
+    return Problem("valley-event", n, n, dx, dx, p, dem, h, np.where(h > 0, 0.55, 0.0), steps=steps, precision="f32")
 
 
-def config4_scenario(i: int) -> Problem:
+def ensemble_member(i: int) -> Problem:
     """Scenario i of the 256-member ensemble: side U{128..512}, dx = 10 m,
     fractal DEM minus a 20 deg tilt, delta_b ~ U(15, 30) deg, release volume
     lognormal (median 1e6 m^3, sigma 0.5), solid fraction U(0.4, 0.7)."""
@@ -241,10 +241,10 @@ def config4_scenario(i: int) -> Problem:
         hgt = V / (math.pi * r * r)
     h = cylinder(n, n, dx, dx, 0.25 * n * dx, 0.5 * n * dx, r, hgt)
     p = Params(delta_b_deg=delta)
-    return Problem(f"cfg4_{i}", n, n, dx, dx, p, dem, h, np.where(h > 0, phi, 0.0), steps=2000, precision="f32")
+    return Problem(f"member-{i}", n, n, dx, dx, p, dem, h, np.where(h > 0, phi, 0.0), steps=2000, precision="f32")
 
 
-def config5(n: int = 512, truth: bool = False) -> Problem:
+def calibration_case(n: int = 512, truth: bool = False) -> Problem:
     """Adjoint case: 512^2, dx = 10 m, fractal DEM on a 20 deg tilt, 10 m cylinder
     (r = 200 m) at (1280, 2560) m, solid fraction 0.6, 2000 FP32 steps.  With
     ``truth`` the hidden per-cell friction tan(20 deg + 3 deg g) and the volume
@@ -259,7 +259,7 @@ def config5(n: int = 512, truth: bool = False) -> Problem:
         h = 1.2 * h
     else:
         tan_mu = np.full((n, n), math.tan(math.radians(20.0)))
-    return Problem("cfg5", n, n, dx, dx, p, dem, h, np.where(h > 0, 0.6, 0.0), steps=2000,
+    return Problem("calibration", n, n, dx, dx, p, dem, h, np.where(h > 0, 0.6, 0.0), steps=2000,
                    precision="f32", tan_mu=tan_mu)
 
 

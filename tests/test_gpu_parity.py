@@ -53,9 +53,9 @@ def _compare_steps(prob, nsteps, tol, variant=0, precision="f64"):
 # ------------------------------------------------------------------ FP64
 
 @pytest.mark.parametrize("variant", [1, 2])
-def test_config1_fp64_matches_oracle(variant):
-    """Config 1 (128^2, FP64, walls, CFL 0.5), 200 steps, both kernel variants."""
-    g, o = _compare_steps(I.config1(), 200, 1e-12, variant=variant)
+def test_plane_bump_pile_fp64_matches_oracle(variant):
+    """The plane-bump-pile problem (128^2, FP64, walls, CFL 0.5), 200 steps, both kernel variants."""
+    g, o = _compare_steps(I.plane_bump_pile(), 200, 1e-12, variant=variant)
     dg, do = g.diag(), o.diag()
     assert dg["steps"] == 200 and abs(dg["t"] - do["t"]) <= 1e-12 * do["t"]
     assert abs(dg["mass_s"] - do["mass_s"]) <= 1e-12 * do["mass_s"]
@@ -204,10 +204,10 @@ def test_state_inflow_argument_errors():
 @pytest.mark.parametrize("variant", [1, 2])
 def test_rk3_option_fp64(variant):
     """The three-stage SSP Runge-Kutta option (M2P_F_RK3) against the oracle's
-    RK3: config 1 and the state/discharge inflow problem, both kernel
+    RK3: the plane-bump-pile problem and the state/discharge inflow problem, both kernel
     variants, diagnostics included."""
     import dataclasses
-    for prob, n in ((I.config1(n=96), 120), (_state_inflow_problem(), 120)):
+    for prob, n in ((I.plane_bump_pile(n=96), 120), (_state_inflow_problem(), 120)):
         q = dataclasses.replace(prob, params=dataclasses.replace(prob.params, flags=prob.params.flags | I.F_RK3))
         q.name = prob.name + "-rk3"
         g, o = _compare_steps(q, n, 1e-12, variant=variant)
@@ -223,7 +223,7 @@ def test_rk3_fp32_and_refusals():
 
     from paper_2104_06784_amd._abi import M2P_EINVAL, M2PError
     from paper_2104_06784_amd.sim import Batch
-    prob = I.config1()
+    prob = I.plane_bump_pile()
     q = dataclasses.replace(prob, params=dataclasses.replace(prob.params, flags=I.F_RK3))
     g, o = Sim(q, precision="f32"), Ora(q)
     g.run_to(3.0)
@@ -241,13 +241,13 @@ def test_rk3_fp32_and_refusals():
 @pytest.mark.parametrize("variant", [1, 2])
 def test_central_upwind_option_fp64(variant):
     """The central-upwind flux option (M2P_F_CENTRAL_UPWIND) against the
-    oracle's: config 1 (walls), the state/discharge inflow problem and, on the
-    tiled kernel, config 1 with the three-stage method too; both kernel
+    oracle's: the plane-bump-pile problem (walls), the state/discharge inflow
+    problem and, on the tiled kernel, the first with the three-stage method too; both kernel
     variants, diagnostics included."""
     import dataclasses
-    cases = [(I.config1(n=96), 0), (_state_inflow_problem(), 0)]
+    cases = [(I.plane_bump_pile(n=96), 0), (_state_inflow_problem(), 0)]
     if variant == 2:
-        cases.append((I.config1(n=80), I.F_RK3))
+        cases.append((I.plane_bump_pile(n=80), I.F_RK3))
     for prob, extra in cases:
         q = dataclasses.replace(prob, params=dataclasses.replace(
             prob.params, flags=prob.params.flags | I.F_CENTRAL_UPWIND | extra))
@@ -261,7 +261,7 @@ def test_central_upwind_option_fp64(variant):
 
 def test_central_upwind_fp32_and_refusals():
     """FP32 central-upwind stays within the FP32 tolerance of the FP64
-    oracle (config 1 to 3 s; the state/discharge inflow problem to 3 s with
+    oracle (the plane-bump-pile problem to 3 s; the state/discharge inflow problem to 3 s with
     its volume budget -- later the option's time step collapses there, in
     the oracle as on the GPU, as thin fluid layers accelerate); the tangent,
     adjoint and ensemble calls refuse the option."""
@@ -269,7 +269,7 @@ def test_central_upwind_fp32_and_refusals():
 
     from paper_2104_06784_amd._abi import M2P_EINVAL, M2PError
     from paper_2104_06784_amd.sim import Batch
-    prob = I.config1()
+    prob = I.plane_bump_pile()
     q = dataclasses.replace(prob, params=dataclasses.replace(prob.params, flags=I.F_CENTRAL_UPWIND))
     g, o = Sim(q, precision="f32"), Ora(q)
     g.run_to(3.0)
@@ -286,7 +286,7 @@ def test_central_upwind_fp32_and_refusals():
     d = gs.diag()
     m0 = float(np.sum(ps.h_vert)) * ps.dx * ps.dy
     bud = abs(d["mass_s"] + d["mass_f"] + d["out_s"] + d["out_f"] - d["in_s"] - d["in_f"] - m0) / m0
-    _say(f"[parity] central-upwind FP32: config 1 rel L1 {l1:.3e}; inflow rel L1 {l1s:.3e}, budget {bud:.3e}")
+    _say(f"[parity] central-upwind FP32: plane-bump-pile rel L1 {l1:.3e}; inflow rel L1 {l1s:.3e}, budget {bud:.3e}")
     assert l1 <= 1e-3 and l1s <= 1e-3 and bud <= 1e-6
     z = np.zeros((6, q.ny, q.nx))
     for call in (lambda: g.adjoint_run(4, 2, np.zeros((q.ny, q.nx))), lambda: g.stage_jvp(z),
@@ -297,7 +297,7 @@ def test_central_upwind_fp32_and_refusals():
 
 
 def test_run_to_lands_on_end_time():
-    prob = I.config1(n=64)
+    prob = I.plane_bump_pile(n=64)
     g, o = Sim(prob, precision="f64"), Ora(prob)
     n = g.run_to(2.5)
     dto = o.run(10 ** 6, 2.5)
@@ -355,7 +355,7 @@ def test_graph_replay_equals_direct_launches(precision, rk3):
 
 
 def test_vertical_and_normal_thickness_inputs_agree():
-    prob = I.config1(n=32)
+    prob = I.plane_bump_pile(n=32)
     a = Sim(prob, precision="f64")
     f = a.fields()
     b = Sim(prob, precision="f64", set_state=False)
@@ -367,7 +367,7 @@ def test_vertical_and_normal_thickness_inputs_agree():
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_bitwise_determinism(precision):
-    prob = I.config1()
+    prob = I.plane_bump_pile()
     runs = []
     for _ in range(2):
         g = Sim(prob, precision=precision)
@@ -381,10 +381,10 @@ def test_bitwise_determinism(precision):
 # --------------------------------------------------------------------- FP32
 
 def test_fp32_against_fp64_oracle_mode2():
-    """Config-2 recipe at 256^2: FP32 state vs the FP64 oracle at the same model
+    """The fractal-hydrograph recipe at 256^2: FP32 state vs the FP64 oracle at the same model
     time: relative L1 thickness error <= 1e-3; volume budget closes to 1e-6."""
-    prob = I.config2(n=256)
-    _say("[fp32] cfg2-256 run_to 60 s")
+    prob = I.fractal_hydrograph(n=256)
+    _say("[fp32] fractal-hydrograph 256^2 run_to 60 s")
     g = Sim(prob, precision="f32")
     o = Ora(prob)
     g.run_to(20.0)
@@ -402,13 +402,13 @@ def test_fp32_against_fp64_oracle_mode2():
 
 
 def test_fp32_config2_full_size_5000_steps():
-    """Config 2 at its full size (1024^2, Mode-II hydrograph) for 5000 steps:
+    """The fractal-hydrograph problem at its full size (1024^2, Mode-II hydrograph) for 5000 steps:
     the FP32 path against the FP64 path (itself within 1e-12 of the oracle in
     the tests above; the oracle would need minutes here) at the same model
     time: relative L1 thickness error <= 1e-3, each path's volume budget
     closes to 1e-6, and the deposit metric of the paper."""
-    prob = I.config2()
-    _say(f"[fp32] cfg2 {prob.nx}^2, 5000 FP64 steps, FP32 to the same time")
+    prob = I.fractal_hydrograph()
+    _say(f"[fp32] fractal-hydrograph {prob.nx}^2, 5000 FP64 steps, FP32 to the same time")
     d64 = Sim(prob, precision="f64")
     d64.run(5000)
     t_end = d64.diag()["t"]
@@ -426,8 +426,8 @@ def test_fp32_config2_full_size_5000_steps():
     assert l1 <= 1e-3 and res[1] <= 1e-6 and res[2] <= 1e-6 and mism <= 0.0017
 
 
-def test_fp32_config1_close_to_fp64():
-    prob = I.config1()
+def test_fp32_plane_bump_pile_close_to_fp64():
+    prob = I.plane_bump_pile()
     g = Sim(prob, precision="f32")
     o = Ora(prob)
     g.run_to(3.0)
@@ -442,7 +442,7 @@ def test_host_forced_overflow_is_reported_and_poisons():
     """A finite but absurd momentum overflows in the flux; the device status
     word turns it into M2P_ENONFINITE and the context refuses further steps."""
     from paper_2104_06784_amd import _abi as A
-    prob = I.config1(n=16)
+    prob = I.plane_bump_pile(n=16)
     g = Sim(prob, precision="f64")
     U = g.state()
     U[1, 8, 8] = 1e300
@@ -460,7 +460,7 @@ def test_host_forced_overflow_is_reported_and_poisons():
 
 def test_set_state_rejects_non_finite():
     from paper_2104_06784_amd import _abi as A
-    prob = I.config1(n=16)
+    prob = I.plane_bump_pile(n=16)
     g = Sim(prob, precision="f64")
     U = g.state()
     U[0, 1, 1] = np.nan
@@ -475,7 +475,7 @@ def test_set_state_rejects_non_finite():
 
 def test_max_steps_reported():
     from paper_2104_06784_amd import _abi as A
-    g = Sim(I.config1(n=32), precision="f64")
+    g = Sim(I.plane_bump_pile(n=32), precision="f64")
     with pytest.raises(A.M2PError) as e:
         g.run_to(1e6, max_steps=5)
     assert e.value.code == A.M2P_EMAXSTEPS
@@ -485,15 +485,15 @@ def test_max_steps_reported():
 # ------------------------------------------------- full size, one step
 
 @pytest.mark.parametrize("precision,tol", [("f32", 2e-5), ("f64", 1e-12)])
-def test_full_size_config3_one_step(precision, tol):
-    """Config 3 at its full 4096^2 size, the launch configuration the benchmark
+def test_full_size_valley_event_one_step(precision, tol):
+    """The valley event at its full 4096^2 size, the launch configuration the benchmark
     times: after 20 GPU steps, one more GPU step and one oracle step from the
     same state must agree (FP64: 1e-12; FP32 state: 2e-5 of each field's max,
     about 20x the FP32 rounding of the flux terms relative to the momenta)."""
     import oracle
     oracle.set_threads(16)
-    prob = I.config3()
-    _say(f"[full] cfg3 4096^2 {precision}")
+    prob = I.valley_event()
+    _say(f"[full] valley-event 4096^2 {precision}")
     g = Sim(prob, precision=precision)
     g.run(20)
     U0 = g.state()

@@ -40,10 +40,10 @@ def _ritter(x_rel, t, h0, g):
 # ---------------------------------------------------------------- invariants
 
 def test_mass_conserved_per_phase_with_walls():
-    """P1: closed walls, config-1 problem, 200 steps: each phase's volume is
+    """P1: closed walls, plane-bump-pile problem, 200 steps: each phase's volume is
     conserved separately (no mass exchange between phases, mass balances of
     Appendix A) and no positivity clamp fires."""
-    s = _sim(I.config1())
+    s = _sim(I.plane_bump_pile())
     d0 = s.diag()
     s.run(200)
     d1 = s.diag()
@@ -53,10 +53,10 @@ def test_mass_conserved_per_phase_with_walls():
     assert d1["steps"] == 200
 
 
-def test_mirror_symmetry_config1():
+def test_mirror_symmetry_plane_bump_pile():
     """P2: bump and pile centred on the face Y = 640 m, walls: the solution is
     mirror-symmetric with p_Y negated."""
-    s = _sim(I.config1())
+    s = _sim(I.plane_bump_pile())
     s.run(200)
     U = s.state()
     M = U[:, ::-1, :].copy()
@@ -69,7 +69,7 @@ def test_mirror_symmetry_config1():
 def test_transpose_symmetry():
     """P3: swapping X and Y in the DEM and the release transposes the solution
     with p_X <-> p_Y (pins A12 vs A21 and the xi/eta code paths)."""
-    p = I.config1(n=64)
+    p = I.plane_bump_pile(n=64)
     p.dem = p.dem + 0.3 * np.sin(np.arange(64) / 5.0)[:, None] * 10.0  # break the Y symmetry
     p.h_vert = np.roll(p.h_vert, 7, axis=0)
     p.phi_s = np.roll(p.phi_s, 7, axis=0)
@@ -206,13 +206,13 @@ def _cu(params):
 
 
 def test_central_upwind_mass_and_mirror_symmetry():
-    """Central-upwind option, config-1 problem with walls, 200 steps: each
+    """Central-upwind option, plane-bump-pile problem with walls, 200 steps: each
     phase's volume conserved to round-off (conservative face form, zero mass
     flux at a wall) and the solution mirror-symmetric about the fall line.
     A swap of the two one-sided speeds (or of the sides they weight) breaks
     the mirror symmetry, since the mirror maps v_n to -v_n and exchanges the
     largest and smallest speeds."""
-    p = I.config1()
+    p = I.plane_bump_pile()
     s = _sim(dataclasses.replace(p, params=_cu(p.params)))
     d0 = s.diag()
     s.run(200)
@@ -234,7 +234,7 @@ def test_central_upwind_mass_and_mirror_symmetry():
 def test_central_upwind_transpose_symmetry():
     """Swapping X and Y transposes the central-upwind solution with
     p_X <-> p_Y (the one-sided speeds of the eta faces use v_Y and A22)."""
-    p = I.config1(n=64)
+    p = I.plane_bump_pile(n=64)
     p.dem = p.dem + 0.3 * np.sin(np.arange(64) / 5.0)[:, None] * 10.0
     p.h_vert = np.roll(p.h_vert, 7, axis=0)
     p.phi_s = np.roll(p.phi_s, 7, axis=0)
@@ -617,7 +617,7 @@ def test_dry_domain_stays_dry_and_time_lands_exactly():
 
 def test_invalid_state_rejected():
     import oracle
-    prob = I.config1(n=16)
+    prob = I.plane_bump_pile(n=16)
     s = oracle.OracleSim(prob)
     bad = prob.phi_s.copy()
     bad[3, 3] = 1.5
@@ -628,7 +628,7 @@ def test_invalid_state_rejected():
 def test_frozen_time_steps_reproduce_the_run():
     """A prescribed step sequence equal to the run's own CFL steps gives the
     same result bitwise (the frozen-step mode used for gradient checks)."""
-    prob = I.config1(n=32)
+    prob = I.plane_bump_pile(n=32)
     a = _sim(prob)
     dts = a.run(40)
     b = _sim(prob)
