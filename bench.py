@@ -306,12 +306,12 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="0 skips the forward+adjoint measurement")
     ap.add_argument("--sweep-steps", type=int, default=1000, help="0 skips the mesh-size sweep")
     ap.add_argument("--variant-steps", type=int, default=30,
-                    help="RK3 steps on the large event (x50 on the Mode-II grid); 0 skips the variants")
+                    help="RK3 and central-upwind steps on the large event (x50 on the Mode-II grid); 0 skips the variants")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run 3 device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
