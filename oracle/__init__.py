@@ -36,7 +36,7 @@ class _Params(C.Structure):
                 ("theta_b", C.c_double), ("rho_s", C.c_double), ("rho_f", C.c_double),
                 ("cfl", C.c_double), ("L", C.c_double), ("H", C.c_double), ("chi", C.c_double),
                 ("g", C.c_double), ("m_dry", C.c_double), ("a_min", C.c_double),
-                ("bc", C.c_int32 * 4), ("flags", C.c_int32)]
+                ("bc", C.c_int32 * 4), ("flags", C.c_int32), ("delta_int_deg", C.c_double)]
 
 
 class _InflowState(C.Structure):
@@ -110,7 +110,7 @@ class OracleSim:
         self.nx, self.ny = prob.nx, prob.ny
         cp = _Params(prob.nx, prob.ny, prob.dx, prob.dy, p.delta_b_deg, p.c_d, p.inv_n_r, p.theta_b,
                      p.rho_s, p.rho_f, p.cfl, p.L, p.H, p.chi, p.g, p.m_dry, p.a_min,
-                     (C.c_int32 * 4)(*p.bc), p.flags)
+                     (C.c_int32 * 4)(*p.bc), p.flags, p.delta_int_deg)
         dem = np.ascontiguousarray(prob.dem, dtype=np.float64)
         mu = None if prob.tan_mu is None else np.ascontiguousarray(prob.tan_mu, dtype=np.float64)
         self._h = lib.ora_create(C.byref(cp), _ptr(dem), _ptr(mu))

@@ -40,7 +40,9 @@ typedef struct {
     int32_t bc[4]; /* W, E, S, N: 0 transmissive, 1 closed wall */
     int32_t flags; /* bit 0: fluid interphase pressure weighted by phi^f as printed;
                       bit 1: three-stage third-order SSP Runge-Kutta instead of Heun;
-                      bit 2: central-upwind face flux (one-sided local speeds) */
+                      bit 2: central-upwind face flux (one-sided local speeds);
+                      bit 3: Savage-Hutter earth-pressure coefficients on the solid pressure */
+    double delta_int_deg; /* internal friction angle (used with bit 3) */
 } ora_params;
 
 typedef struct {
@@ -98,6 +100,8 @@ typedef struct {
     double last_dt;
     double *dt_sched;   /* optional prescribed time steps (dimensionless) */
     int64_t n_sched;
+    double cos2_int;    /* cos^2 of the internal friction angle (earth pressure) */
+    double *Kx, *Ky;    /* padded earth-pressure coefficients of the stage input */
 } ora_sim;
 
 /* ---------------------------------------------------------------- helpers */
@@ -191,6 +195,15 @@ static void geometry_at(const ora_sim *o, int i, int j, geo_t *g)
 ora_sim *ora_create(const ora_params *p, const double *dem, const double *tan_mu)
 {
     if (p->nx < 2 || p->ny < 2) return NULL;
+    if (p->flags & 8) {
+        /* earth pressure needs delta_b <= delta_int < 90 deg everywhere */
+        if (!(p->delta_int_deg >= 0.0 && p->delta_int_deg < 90.0) || p->delta_b_deg > p->delta_int_deg) return NULL;
+        if (tan_mu) {
+            double ti = tan(p->delta_int_deg * M_PI / 180.0);
+            for (size_t k = 0; k < (size_t)p->nx * p->ny; k++)
+                if (!(tan_mu[k] <= ti)) return NULL;
+        }
+    }
     ora_sim *o = (ora_sim *)xcalloc(1, sizeof(ora_sim));
     o->p = *p;
     o->nx = p->nx;
@@ -221,6 +234,12 @@ ora_sim *ora_create(const ora_params *p, const double *dem, const double *tan_mu
         o->tan_mu = (double *)xcalloc(nc, sizeof(double));
         memcpy(o->tan_mu, tan_mu, nc * sizeof(double));
     }
+    if (p->flags & 8) {
+        double ci = cos(p->delta_int_deg * M_PI / 180.0);
+        o->cos2_int = ci * ci;
+        o->Kx = (double *)xcalloc(npad, sizeof(double));
+        o->Ky = (double *)xcalloc(npad, sizeof(double));
+    }
     extend_dem(o, dem);
     /* static geometry on the interior plus one ghost ring */
     for (int j = -1; j <= o->ny; j++)
@@ -246,6 +265,7 @@ void ora_destroy(ora_sim *o)
     if (!o) return;
     free(o->b); free(o->U); free(o->Us); free(o->Uss); free(o->Ue); free(o->G);
     free(o->dnx); free(o->dny); free(o->HX); free(o->HY); free(o->tan_mu); free(o->dt_sched);
+    free(o->Kx); free(o->Ky);
     for (int k = 0; k < o->nseg; k++) { free(o->seg[k].t); free(o->seg[k].Q); free(o->seg[k].phi); }
     free(o->seg);
     for (int k = 0; k < o->nsseg; k++) { free(o->sseg[k].t); free(o->sseg[k].h); free(o->sseg[k].phi); free(o->sseg[k].v); }
@@ -407,6 +427,62 @@ static void extend_state(ora_sim *o, const double *U, double tau)
     }
 }
 
+/* ------------------------------------------------------- earth pressure */
+
+/* Savage-Hutter earth-pressure coefficients (Savage and Hutter 1989; the
+ * two-dimensional form of Hutter et al. 1993), from the internal friction
+ * angle (c2 = cos^2 delta_int) and the basal friction t = tan delta_b:
+ *   K_x = 2 (1 -/+ sqrt(1 - c2 (1 + t^2))) / c2 - 1,
+ *   K_y = (K_x + 1 -/+ sqrt((K_x - 1)^2 + 4 t^2)) / 2,
+ * the upper sign (active) where the flow extends in that direction, the lower
+ * (passive) where it is compressed. */
+static double ep_kx(double c2, double t, int active)
+{
+    double disc = 1.0 - c2 * (1.0 + t * t);
+    double r = sqrt(disc > 0.0 ? disc : 0.0);
+    return 2.0 * (active ? 1.0 - r : 1.0 + r) / c2 - 1.0;
+}
+
+static double ep_ky(double kx, double t, int active)
+{
+    double r = sqrt((kx - 1.0) * (kx - 1.0) + 4.0 * t * t);
+    return 0.5 * (active ? kx + 1.0 - r : kx + 1.0 + r);
+}
+
+/* reading: the largest coefficient a cell can take (passive K_x, then the
+ * passive K_y of it), bounding the solid's pressure speed in the CFL step
+ * so that the time step needs no neighbour values. */
+static double ep_kmax(double c2, double t) { return ep_ky(ep_kx(c2, t, 0), t, 0); }
+
+/* reading: per cell, active in X where the central difference of the
+ * (desingularised) solid velocity v_X^s along xi is >= 0, passive otherwise;
+ * likewise in Y with v_Y^s along eta; from the extended stage input.  A ghost
+ * cell takes the coefficients of the cell its boundary rule maps it to. */
+static void earth_pressure(ora_sim *o)
+{
+    size_t np = (size_t)o->px * o->py;
+    const double *m = o->Ue, *px = o->Ue + np, *py = o->Ue + 2 * np;
+    for (int j = 0; j < o->ny; j++)
+        for (int i = 0; i < o->nx; i++) {
+            size_t e = PIDX(o, i + 1, j), w = PIDX(o, i - 1, j), n = PIDX(o, i, j + 1), s = PIDX(o, i, j - 1);
+            double dvx = desing(px[e], m[e], o->md) - desing(px[w], m[w], o->md);
+            double dvy = desing(py[n], m[n], o->md) - desing(py[s], m[s], o->md);
+            double t = o->tan_mu ? o->tan_mu[CIDX(o, i, j)] : o->tan_d;
+            double kx = ep_kx(o->cos2_int, t, dvx >= 0.0);
+            o->Kx[PIDX(o, i, j)] = kx;
+            o->Ky[PIDX(o, i, j)] = ep_ky(kx, t, dvy >= 0.0);
+        }
+    for (int j = -HALO; j < o->ny + HALO; j++)
+        for (int i = -HALO; i < o->nx + HALO; i++) {
+            if (i >= 0 && i < o->nx && j >= 0 && j < o->ny) continue;
+            int f = 0;
+            int ii = map_index(i, o->nx, o->p.bc[0], o->p.bc[1], &f);
+            int jj = map_index(j, o->ny, o->p.bc[2], o->p.bc[3], &f);
+            o->Kx[PIDX(o, i, j)] = o->Kx[PIDX(o, ii, jj)];
+            o->Ky[PIDX(o, i, j)] = o->Ky[PIDX(o, ii, jj)];
+        }
+}
+
 /* ------------------------------------------------------- inflow (Mode II) */
 
 static double interp(const double *t, const double *y, int n, double tau)
@@ -447,14 +523,16 @@ static void inflow_state(const ora_sim *o, const inflow_seg *s, double tau_nd,
  * conserved values used by the numerical diffusion (momenta recomputed from
  * the desingularised velocities) and the local speeds of the two phases. */
 static void side_flux(const ora_sim *o, const double u[NF], const geo_t *g, int d,
-                      double F[NF], double qv[NF], double a[2])
+                      double F[NF], double qv[NF], double a[2], double kep)
 {
     double eps = o->eps, al = o->alpha;
     double ms = u[0], mf = u[3];
     double hs = ms / g->J, hf = mf / g->J, h = hs + hf;
     double vXs = desing(u[1], ms, o->md), vYs = desing(u[2], ms, o->md);
     double vXf = desing(u[4], mf, o->md), vYf = desing(u[5], mf, o->md);
-    double Ns = g->c * (1.0 - al) * hs / 2.0; /* depth-averaged solid pressure */
+    /* depth-averaged solid pressure, times the earth-pressure coefficient kep
+     * of the flux direction (1 in the paper's model) */
+    double Ns = kep * (g->c * (1.0 - al) * hs / 2.0);
     double pf = g->c * h / 2.0;               /* mean fluid pressure */
     double Ax = d == 0 ? g->A11 : g->A21;     /* weight of the X-momentum pressure term */
     double Ay = d == 0 ? g->A12 : g->A22;     /* weight of the Y-momentum pressure term */
@@ -472,7 +550,7 @@ static void side_flux(const ora_sim *o, const double u[NF], const geo_t *g, int 
     qv[0] = ms; qv[1] = ms * vXs; qv[2] = ms * vYs;
     qv[3] = mf; qv[4] = mf * vXf; qv[5] = mf * vYf;
     /* reading: phase speeds from the pressure terms, |v_n| + sqrt(dP/dm) */
-    double cs = eps * Ann * g->c * (1.0 - al) * (h + hs) / 2.0;
+    double cs = kep * (eps * Ann * g->c * (1.0 - al) * (h + hs) / 2.0);
     double cf = eps * Ann * g->c * h;
     a[0] = fabs(vns) + sqrt(cs > 0.0 ? cs : 0.0);
     a[1] = fabs(vnf) + sqrt(cf > 0.0 ? cf : 0.0);
@@ -482,7 +560,7 @@ static void side_flux(const ora_sim *o, const double u[NF], const geo_t *g, int 
  * largest characteristic speed v_n -/+ sqrt(dP/dm) in the face normal
  * direction, from the same quantities as the speeds of side_flux. */
 static void side_speeds(const ora_sim *o, const double u[NF], const geo_t *g, int d, double lo[2],
-                        double hi[2])
+                        double hi[2], double kep)
 {
     double eps = o->eps, al = o->alpha;
     double ms = u[0], mf = u[3];
@@ -490,7 +568,7 @@ static void side_speeds(const ora_sim *o, const double u[NF], const geo_t *g, in
     double vns = desing(d == 0 ? u[1] : u[2], ms, o->md);
     double vnf = desing(d == 0 ? u[4] : u[5], mf, o->md);
     double Ann = d == 0 ? g->A11 : g->A22;
-    double cs = eps * Ann * g->c * (1.0 - al) * (h + hs) / 2.0;
+    double cs = kep * (eps * Ann * g->c * (1.0 - al) * (h + hs) / 2.0);
     double cf = eps * Ann * g->c * h;
     double rs = sqrt(cs > 0.0 ? cs : 0.0), rf = sqrt(cf > 0.0 ? cf : 0.0);
     lo[0] = vns - rs;
@@ -510,15 +588,15 @@ static void side_speeds(const ora_sim *o, const double u[NF], const geo_t *g, in
  * and (F(U-) + F(U+))/2 where a+ = a- = 0.  With a- = -a+ it is the
  * Kurganov-Tadmor flux. */
 static void central_flux(const ora_sim *o, const double uL[NF], const geo_t *gL,
-                         const double uR[NF], const geo_t *gR, int d, double H[NF])
+                         const double uR[NF], const geo_t *gR, int d, double H[NF], double kL, double kR)
 {
     double FL[NF], FR[NF], qL[NF], qR[NF], aL[2], aR[2];
-    side_flux(o, uL, gL, d, FL, qL, aL);
-    side_flux(o, uR, gR, d, FR, qR, aR);
+    side_flux(o, uL, gL, d, FL, qL, aL, kL);
+    side_flux(o, uR, gR, d, FR, qR, aR, kR);
     if (o->p.flags & 4) {
         double loL[2], hiL[2], loR[2], hiR[2];
-        side_speeds(o, uL, gL, d, loL, hiL);
-        side_speeds(o, uR, gR, d, loR, hiR);
+        side_speeds(o, uL, gL, d, loL, hiL, kL);
+        side_speeds(o, uR, gR, d, loR, hiR, kR);
         for (int ph = 0; ph < 2; ph++) {
             double ap = hiL[ph] > hiR[ph] ? hiL[ph] : hiR[ph];
             double am = loL[ph] < loR[ph] ? loL[ph] : loR[ph];
@@ -590,7 +668,9 @@ static void compute_fluxes(ora_sim *o, double tau)
         for (int i = -1; i < nx; i++) {
             double uL[NF], uR[NF], H[NF];
             face_values(o, i, j, 0, uL, uR);
-            central_flux(o, uL, &o->G[PIDX(o, i, j)], uR, &o->G[PIDX(o, i + 1, j)], 0, H);
+            const int ep = (o->p.flags & 8) != 0;
+            central_flux(o, uL, &o->G[PIDX(o, i, j)], uR, &o->G[PIDX(o, i + 1, j)], 0, H,
+                         ep ? o->Kx[PIDX(o, i, j)] : 1.0, ep ? o->Kx[PIDX(o, i + 1, j)] : 1.0);
             size_t f = (size_t)j * (nx + 1) + (size_t)(i + 1);
             for (int k = 0; k < NF; k++) o->HX[k * nfx + f] = H[k];
         }
@@ -599,7 +679,9 @@ static void compute_fluxes(ora_sim *o, double tau)
         for (int i = 0; i < nx; i++) {
             double uL[NF], uR[NF], H[NF];
             face_values(o, i, j, 1, uL, uR);
-            central_flux(o, uL, &o->G[PIDX(o, i, j)], uR, &o->G[PIDX(o, i, j + 1)], 1, H);
+            const int ep = (o->p.flags & 8) != 0;
+            central_flux(o, uL, &o->G[PIDX(o, i, j)], uR, &o->G[PIDX(o, i, j + 1)], 1, H,
+                         ep ? o->Ky[PIDX(o, i, j)] : 1.0, ep ? o->Ky[PIDX(o, i, j + 1)] : 1.0);
             size_t f = (size_t)(j + 1) * nx + (size_t)i;
             for (int k = 0; k < NF; k++) o->HY[k * nfy + f] = H[k];
         }
@@ -825,6 +907,7 @@ static void stage(ora_sim *o, const double *Uin, double *Uout, double dt, double
     size_t nc = (size_t)nx * ny, nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1);
     size_t np = (size_t)o->px * o->py;
     extend_state(o, Uin, tau);
+    if (o->p.flags & 8) earth_pressure(o);
     compute_fluxes(o, tau);
     boundary_outflow(o, o->bflux[st]);
     int64_t clamps = 0;
@@ -902,10 +985,12 @@ static void max_speeds(const ora_sim *o, double amax[2])
             double u[NF], F[NF], qv[NF], a[2];
             for (int k = 0; k < NF; k++) u[k] = o->U[k * nc + c];
             const geo_t *g = &o->G[PIDX(o, i, j)];
-            side_flux(o, u, g, 0, F, qv, a);
+            double km = 1.0;
+            if (o->p.flags & 8) km = ep_kmax(o->cos2_int, o->tan_mu ? o->tan_mu[c] : o->tan_d);
+            side_flux(o, u, g, 0, F, qv, a, km);
             if (a[0] > ax) ax = a[0];
             if (a[1] > ax) ax = a[1];
-            side_flux(o, u, g, 1, F, qv, a);
+            side_flux(o, u, g, 1, F, qv, a, km);
             if (a[0] > ay) ay = a[0];
             if (a[1] > ay) ay = a[1];
         }

@@ -32,6 +32,7 @@ SIDE_W, SIDE_E, SIDE_S, SIDE_N = 0, 1, 2, 3
 F_FLUID_PRESSURE_AS_PRINTED = 1
 F_RK3 = 2                       # three-stage SSP Runge-Kutta instead of Heun
 F_CENTRAL_UPWIND = 4            # central-upwind face flux (one-sided local speeds)
+F_EARTH_PRESSURE = 8            # Savage-Hutter earth-pressure coefficients from delta_int
 
 
 @dataclasses.dataclass
@@ -44,7 +45,7 @@ class Params:
     theta_b: float = 5.0          # fluid basal friction coefficient
     rho_s: float = 2700.0
     rho_f: float = 1000.0
-    delta_int_deg: float = 35.0   # recorded only; the model has no earth-pressure coefficient
+    delta_int_deg: float = 35.0   # used only with F_EARTH_PRESSURE (the paper's model has no such coefficient)
     cfl: float = 0.1              # Sect. 2.2
     L: float = 1000.0             # length scale (m)
     H: float = 10.0               # thickness scale (m)

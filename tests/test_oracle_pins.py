@@ -296,6 +296,137 @@ def test_central_upwind_ritter_and_convergence():
     assert orders[-1] >= 0.8 and orders[-2] >= 0.8
 
 
+# ------------------------------------------------ earth-pressure option
+
+def _ep(params, delta_int):
+    return dataclasses.replace(params, flags=params.flags | I.F_EARTH_PRESSURE, delta_int_deg=delta_int)
+
+
+def test_earth_pressure_reduces_to_the_model_without_friction_angles():
+    """With delta_int = delta_b = 0 both Savage-Hutter coefficients are
+    exactly 1 (and so is their CFL bound): the option reproduces the paper's
+    model bitwise on a two-phase flow over the bump."""
+    p = I.plane_bump_pile(n=48)
+    base = dataclasses.replace(p.params, delta_b_deg=0.0)
+    a = _sim(dataclasses.replace(p, params=base))
+    b = _sim(dataclasses.replace(p, params=_ep(base, 0.0)))
+    assert np.array_equal(a.run(80), b.run(80))
+    assert np.array_equal(a.state(), b.state())
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_earth_pressure_ritter_active(axis):
+    """Pure-solid dam break on a flat frictionless bed (delta_b = 0, no pore
+    fluid), delta_int = 35 deg: the flow extends everywhere, so the solid
+    pressure carries the active coefficient K = (1 - sin d)/(1 + sin d) in
+    both directions (K_y at delta_b = 0 equals K_x) and the thickness follows
+    Ritter's solution with gravity K g, along X and, transposed, along Y."""
+    K = (1 - math.sin(math.radians(35.0))) / (1 + math.sin(math.radians(35.0)))
+    p = I.Params(delta_b_deg=0.0, rho_f=0.0, inv_n_r=0.0, theta_b=0.0, cfl=0.1, bc=(0, 0, 1, 1))
+    prob = _flat_strip(400, 10.0, 1.0, _ep(p, 35.0))
+    if axis == 1:
+        q = dataclasses.replace(p, bc=(1, 1, 0, 0))
+        prob = dataclasses.replace(prob, nx=prob.ny, ny=prob.nx, dx=prob.dy, dy=prob.dx, params=_ep(q, 35.0),
+                                   dem=prob.dem.T.copy(), h_vert=prob.h_vert.T.copy(), phi_s=prob.phi_s.T.copy())
+    s = _sim(prob)
+    s.run(10 ** 6, 20.0)
+    h = s.fields()["h"]
+    h = h[1] if axis == 0 else h[:, 1]
+    x = (np.arange(400) + 0.5) * 5.0 - 1000.0
+    he, _ = _ritter(x, 20.0, 10.0, 9.81 * K)
+    err = np.abs(h - he).sum() / he.sum()
+    assert err < 1e-2
+    # the same run without the coefficient follows Ritter with the full g
+    he1, _ = _ritter(x, 20.0, 10.0, 9.81)
+    assert np.abs(h - he1).sum() / he1.sum() > 5 * err
+
+
+_S30 = math.sin(math.radians(30.0))
+_S35 = math.sin(math.radians(35.0))
+EP_STEP_CASES = [
+    # axis, delta_b, delta_int, compression?, coefficient the pressure must carry
+    (0, 0.0, 35.0, True, (1 + _S35) / (1 - _S35)),        # passive K_x at delta_b = 0
+    (1, 0.0, 35.0, True, 1.0),                            # passive K_y = max(K_x, 1) at delta_b = 0
+    (0, 30.0, 30.0, True, (1 + _S30 ** 2) / (1 - _S30 ** 2)),  # delta_b = delta_int: K_x = 2 / cos^2 - 1
+    (1, 30.0, 30.0, True, 1 / (1 - _S30)),                # ... passive K_y = 1 / (1 - sin)
+    (1, 30.0, 30.0, False, 1 / (1 + _S30)),               # ... active K_y = 1 / (1 + sin)
+]
+
+
+@pytest.mark.parametrize("axis,delta_b,delta_int,compress,K", EP_STEP_CASES)
+def test_earth_pressure_first_step_closed_form(axis, delta_b, delta_int, compress, K):
+    """A pure-solid ramp h = h0 + s x with momentum h v = -/+ c (x - x_c) along
+    one axis on a flat bed: v decreases (compression) or increases
+    (extension) along that axis everywhere, and both conserved fields are
+    linear, so the face values are exact and the numerical diffusion
+    vanishes.  Over one tiny step the momentum change then differs from the
+    model without coefficients by -dt (K - 1) eps m dm/dxi, away from the
+    ends (the Coulomb stop subtracts the same impulse in both runs).  The
+    coefficients are the closed forms of the Savage-Hutter definitions at
+    delta_b = 0 (K_x = (1 + sin)/(1 - sin) passive, K_y = max(K_x, 1)) and at
+    delta_b = delta_int (K_x = 2/cos^2 - 1 on both branches, K_y = 1/(1 -/+
+    sin))."""
+    n, w, dx = 80, 6, 10.0
+    nx, ny = (n, w) if axis == 0 else (w, n)
+    X, Y = I.cell_centres(nx, ny, dx, dx)
+    x = X if axis == 0 else Y
+    h = 5.0 + 0.02 * x
+    v = (-0.05 if compress else 0.05) * (x - 400.0) / h
+    z = np.zeros((ny, nx))
+    vel = (v, z, z, z) if axis == 0 else (z, v, z, z)
+    bc = (0, 0, 1, 1) if axis == 0 else (1, 1, 0, 0)
+    p = I.Params(delta_b_deg=delta_b, rho_f=0.0, inv_n_r=0.0, theta_b=0.0, cfl=0.1, bc=bc)
+    runs = []
+    for q in (p, _ep(p, delta_int)):
+        s = _sim(I.Problem("ramp", nx, ny, dx, dx, q, z, h, np.ones((ny, nx)), vel=vel))
+        U0 = s.state()
+        s.set_dt_schedule([1e-4])
+        s.run(1)
+        runs.append(s.state() - U0)
+    eps, L = p.H / p.L, p.L
+    dt = 1e-4 / math.sqrt(L / p.g)
+    m = U0[0]
+    want = -dt * (K - 1.0) * eps * m * np.gradient(m, dx / L, axis=1 - axis)
+    got = runs[1][1 + axis] - runs[0][1 + axis]
+    core = (slice(None), slice(4, n - 4)) if axis == 0 else (slice(4, n - 4), slice(None))
+    scale = np.max(np.abs(want[core])) if K != 1.0 else dt * eps * np.max(m * np.abs(np.gradient(m, dx / L, axis=0)))
+    assert np.max(np.abs(got[core] - want[core])) <= 1e-3 * scale
+    assert np.max(np.abs(runs[1][2 - axis])) == np.max(np.abs(runs[0][2 - axis]))  # cross momentum untouched
+
+
+def test_earth_pressure_mass_and_mirror_symmetry():
+    """Earth-pressure option (delta_int 35 deg, delta_b 20 deg) on the
+    plane-bump-pile problem with walls at CFL 0.25: no positivity clamp,
+    per-phase volumes conserved to
+    round-off and the solution mirror-symmetric about the fall line (the
+    active/passive choice in Y uses dv_Y/dY, which the mirror leaves
+    unchanged); and it differs from the model without the coefficients."""
+    p = I.plane_bump_pile()
+    p = dataclasses.replace(p, params=dataclasses.replace(p.params, cfl=0.25))
+    s = _sim(dataclasses.replace(p, params=_ep(p.params, 35.0)))
+    d0 = s.diag()
+    s.run(150)
+    d1 = s.diag()
+    assert d1["clamps"] == 0
+    assert abs(d1["mass_s"] - d0["mass_s"]) / d0["mass_s"] <= 1e-13
+    assert abs(d1["mass_f"] - d0["mass_f"]) / d0["mass_f"] <= 1e-13
+    U = s.state()
+    M = U[:, ::-1, :].copy()
+    M[2] *= -1
+    M[5] *= -1
+    assert np.max(np.abs(U - M)) <= 1e-13 * np.max(np.abs(U))
+    k = _sim(p)
+    k.run(150)
+    assert np.max(np.abs(k.state() - U)) > 1e-6 * np.max(np.abs(U))
+
+
+def test_earth_pressure_rejects_basal_above_internal_friction():
+    import oracle
+    p = I.plane_bump_pile(n=16)
+    with pytest.raises(ValueError):
+        oracle.OracleSim(dataclasses.replace(p, params=_ep(p.params, 15.0)))  # delta_b 20 > 15
+
+
 # ---------------------------------------------------------- drag and fluid
 
 def test_two_phase_layer_heun_recurrence():
