@@ -203,8 +203,9 @@ def bench_sweep(stream, steps: int) -> dict:
 
 
 def bench_variants(stream, steps: int, prob3) -> dict:
-    """The scheme variants on their workloads: the three-stage Runge-Kutta
-    and the central-upwind flux options on the large event (prob3, FP32),
+    """The scheme variants on their workloads: the three-stage Runge-Kutta,
+    central-upwind flux and earth-pressure (reference kernel) options on the
+    large event (prob3, FP32),
     and Mode-II inflow as a state hydrograph on the paper's second event's
     grid shape (180 x 154, graph replay) next to the same grid without the
     segment."""
@@ -224,7 +225,8 @@ def bench_variants(stream, steps: int, prob3) -> dict:
         return e0.elapsed_time(e1)
 
     out = {}
-    for key, flag in (("rk3", inputs.F_RK3), ("central_upwind", inputs.F_CENTRAL_UPWIND)):
+    for key, flag in (("rk3", inputs.F_RK3), ("central_upwind", inputs.F_CENTRAL_UPWIND),
+                      ("earth_pressure", inputs.F_EARTH_PRESSURE)):
         p3 = dataclasses.replace(prob3, params=dataclasses.replace(prob3.params, flags=flag))
         sim = Sim(p3, precision="f32", stream=stream)
         sim.run(5)
@@ -246,8 +248,8 @@ def bench_variants(stream, steps: int, prob3) -> dict:
             rec["inflow_m3"] = round(-(d["out_s"] + d["out_f"]), 1)  # state segments: negative outflow
         del sim
     out["mode2_state"] = rec
-    log(f"[bench] variants: rk3 {out['rk3']['value']}, central-upwind {out['central_upwind']['value']} "
-        f"Mcell-steps/s; state inflow "
+    log(f"[bench] variants: rk3 {out['rk3']['value']}, central-upwind {out['central_upwind']['value']}, "
+        f"earth pressure {out['earth_pressure']['value']} Mcell-steps/s; state inflow "
         f"{rec['state_inflow_us_per_step']} us/step ({rec['no_inflow_us_per_step']} without)")
     return out
 
@@ -306,7 +308,7 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="0 skips the forward+adjoint measurement")
     ap.add_argument("--sweep-steps", type=int, default=1000, help="0 skips the mesh-size sweep")
     ap.add_argument("--variant-steps", type=int, default=30,
-                    help="RK3 and central-upwind steps on the large event (x50 on the Mode-II grid); 0 skips the variants")
+                    help="steps of each scheme option on the large event (x50 on the Mode-II grid); 0 skips the variants")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run 3 device copies of this many MiB (counter calibration)")
     args = ap.parse_args()

@@ -72,6 +72,13 @@ extern "C" {
                        schemes of Kurganov-Tadmor 2000 and Kurganov-Petrova 2007; this is the latter's flux without
                        its well-balanced surface reconstruction); single-scenario contexts only, not with the
                        tangent and adjoint calls */
+#define M2P_F_EARTH_PRESSURE 8 /* Savage-Hutter earth-pressure coefficients on the solid pressure (the paper's model has
+                       none, Appendix A): per cell and direction, active where the solid velocity's central
+                       difference along the direction is >= 0, else passive, K_x = 2 (1 -/+ sqrt(1 - cos^2 d_int
+                       (1 + tan^2 d_b))) / cos^2 d_int - 1, K_y = (K_x + 1 -/+ sqrt((K_x - 1)^2 + 4 tan^2 d_b)) / 2,
+                       d_int = delta_int_deg; needs delta_b (and every tan_mu) <= delta_int < 90 deg; Mode-I
+                       releases on single-scenario contexts, run by the reference kernel; not with the tangent and
+                       adjoint calls */
 
 /* thickness convention of m2p_set_state */
 #define M2P_DEPTH_NORMAL 0   /* h measured normal to the bed (the paper's h, Sect. 2.1) */
@@ -96,7 +103,7 @@ typedef struct {
     double inv_n_r;       /* 1 / N_R; 0 switches fluid friction and viscosity off */
     double theta_b;       /* fluid basal friction coefficient */
     double rho_s, rho_f;  /* densities; alpha_rho = rho_f / rho_s */
-    double delta_int_deg; /* internal friction angle: recorded, unused by the model */
+    double delta_int_deg; /* internal friction angle: used by M2P_F_EARTH_PRESSURE only */
     double cfl;           /* CFL number, (0, 1]; the paper uses 0.1 */
     double L, H;          /* length and thickness scales (m); aspect ratio eps = H / L */
     double chi;           /* exponent of eps on the centripetal term of the basal pressure */

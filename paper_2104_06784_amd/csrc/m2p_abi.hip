@@ -144,7 +144,8 @@ namespace m2p {
 Shape make_shape(const KParams& P, int variant, int rows)
 {
     Shape s{};
-    s.variant = variant == M2P_VARIANT_REFERENCE ? 1 : 2;
+    // the earth-pressure option runs on the reference kernel
+    s.variant = (variant == M2P_VARIANT_REFERENCE || (P.flags & kFlagEarthPressure)) ? 1 : 2;
     s.nbx = (P.nx + 63) / 64;
     s.nby = (P.ny + 3) / 4;
     s.nstrips = (P.nx + 59) / 60;
@@ -257,6 +258,10 @@ KParams make_kparams(const m2p_grid* g, const m2p_params* p, bool has_mu)
     K.md = p->m_dry / p->H;
     K.eps_chi = std::pow(K.eps, p->chi);
     K.tan_d = std::tan(p->delta_b_deg * M_PI / 180.0);
+    if (p->flags & M2P_F_EARTH_PRESSURE) {
+        const double ci = std::cos(p->delta_int_deg * M_PI / 180.0);
+        K.cos2_int = ci * ci;
+    }
     K.c_d = p->c_d;
     K.inv_n_r = p->inv_n_r;
     K.theta_b = p->theta_b;
@@ -298,6 +303,16 @@ std::vector<double> padded_dem(const KParams& K, const double* dem, double L)
     return bd;
 }
 
+// With the earth-pressure option every basal friction must stay at or below
+// the internal friction (the coefficients are real only there).
+int ep_friction_ok(const m2p_params* p, const double* tan_mu, size_t n)
+{
+    const double ti = std::tan(p->delta_int_deg * M_PI / 180.0);
+    for (size_t k = 0; k < n; k++)
+        if (!(tan_mu[k] <= ti)) return fail(M2P_EINVAL, "earth pressure needs tan(delta_b) <= tan(delta_int) everywhere");
+    return M2P_OK;
+}
+
 int validate_scenario(const m2p_grid* g, const m2p_params* p, int32_t prec, const double* dem)
 {
     if (!g || !p || !dem) return fail(M2P_EINVAL, "NULL argument");
@@ -316,8 +331,11 @@ int validate_scenario(const m2p_grid* g, const m2p_params* p, int32_t prec, cons
         return fail(M2P_EINVAL, "c_d, 1/N_R, theta_b >= 0 and m_dry, a_min > 0 required");
     for (int s = 0; s < 4; s++)
         if (p->bc[s] != M2P_BC_TRANSMISSIVE && p->bc[s] != M2P_BC_WALL) return fail(M2P_EINVAL, "bad boundary mode");
-    if (p->flags & ~(M2P_F_FLUID_PRESSURE_AS_PRINTED | M2P_F_RK3 | M2P_F_CENTRAL_UPWIND))
+    if (p->flags & ~(M2P_F_FLUID_PRESSURE_AS_PRINTED | M2P_F_RK3 | M2P_F_CENTRAL_UPWIND | M2P_F_EARTH_PRESSURE))
         return fail(M2P_EINVAL, "unknown flag");
+    if ((p->flags & M2P_F_EARTH_PRESSURE) &&
+        !(p->delta_int_deg >= 0.0 && p->delta_int_deg < 90.0 && p->delta_b_deg <= p->delta_int_deg))
+        return fail(M2P_EINVAL, "earth pressure needs delta_b <= delta_int < 90 deg");
     size_t n = (size_t)g->nx * g->ny;
     for (size_t k = 0; k < n; k++)
         if (!std::isfinite(dem[k])) return fail(M2P_EINVAL, "non-finite DEM value");
@@ -379,6 +397,7 @@ int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t pr
     if (tan_mu)
         for (size_t k = 0; k < n; k++)
             if (!(tan_mu[k] >= 0.0) || !std::isfinite(tan_mu[k])) return fail(M2P_EINVAL, "bad tan_mu value");
+    if (tan_mu && (p->flags & M2P_F_EARTH_PRESSURE) && (rc = ep_friction_ok(p, tan_mu, n))) return rc;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(M2P_EHIP, "no HIP device");
     m2p_ctx* c = new m2p_ctx();
@@ -447,6 +466,8 @@ int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t pr
         return cleanup(fail(M2P_ENOMEM, "staging allocation failed"));
     if (hipMalloc(&c->tables, sizeof(double) * 8) != hipSuccess)
         return cleanup(fail(M2P_ENOMEM, "table allocation failed"));
+    if ((p->flags & M2P_F_EARTH_PRESSURE) && hipMalloc(&c->B.kep, 2 * (size_t)ny * K.pitch * c->esz) != hipSuccess)
+        return cleanup(fail(M2P_ENOMEM, "earth-pressure allocation failed"));
     m2p_buffer_bytes(g, prec, &c->state_bytes);
     c->B.b = c->b;
     c->B.mu = c->mu;
@@ -479,6 +500,7 @@ void m2p_destroy(m2p_ctx* c)
     if (c->tables) (void)hipFree(c->tables);
     if (c->mass_part) (void)hipFree(c->mass_part);
     if (c->staging) (void)hipFree(c->staging);
+    if (c->B.kep) (void)hipFree(c->B.kep);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
     for (int q = 0; q < 2; q++) {
@@ -657,6 +679,8 @@ static bool overlaps(const SegDesc* a, int na, int side, int i0, int n)
 int m2p_set_inflow(m2p_ctx* c, const m2p_inflow* seg, int32_t nseg)
 {
     if (!c || (nseg > 0 && !seg)) return fail(M2P_EINVAL, "NULL argument");
+    if (nseg > 0 && (c->kp.flags & M2P_F_EARTH_PRESSURE))
+        return fail(M2P_EINVAL, "the earth-pressure option runs Mode-I releases only");
     if (nseg < 0 || nseg > MAX_SEG) return fail(M2P_EINVAL, "0..8 inflow segments supported");
     std::vector<double> tab;
     SegDesc sd[MAX_SEG];
@@ -692,6 +716,8 @@ int m2p_set_inflow(m2p_ctx* c, const m2p_inflow* seg, int32_t nseg)
 int m2p_set_inflow_states(m2p_ctx* c, const m2p_inflow_state* seg, int32_t nseg)
 {
     if (!c || (nseg > 0 && !seg)) return fail(M2P_EINVAL, "NULL argument");
+    if (nseg > 0 && (c->kp.flags & M2P_F_EARTH_PRESSURE))
+        return fail(M2P_EINVAL, "the earth-pressure option runs Mode-I releases only");
     if (nseg < 0 || nseg > MAX_SEG) return fail(M2P_EINVAL, "0..8 inflow state segments supported");
     std::vector<double> tab;
     SegDesc sd[MAX_SEG];
@@ -1169,12 +1195,16 @@ int L_loss(m2p_ctx* c, const double* target_dev, void* lam, double* loss)
 }
 
 static_assert(m2p::kFlagCentralUpwind == M2P_F_CENTRAL_UPWIND, "central-upwind flag bit");
+static_assert(m2p::kFlagEarthPressure == M2P_F_EARTH_PRESSURE, "earth-pressure flag bit");
 
-// The tangent and adjoint kernels differentiate the Kurganov-Tadmor flux.
+// The tangent and adjoint kernels differentiate the Kurganov-Tadmor flux of
+// the paper's model.
 int flux_unsupported(m2p_ctx* c)
 {
     if (c->kp.flags & M2P_F_CENTRAL_UPWIND)
         return m2p::fail(M2P_EINVAL, "the tangent and adjoint kernels differentiate the central (Kurganov-Tadmor) flux");
+    if (c->kp.flags & M2P_F_EARTH_PRESSURE)
+        return m2p::fail(M2P_EINVAL, "the tangent and adjoint kernels differentiate the model without earth pressure");
     return M2P_OK;
 }
 
@@ -1197,6 +1227,10 @@ int m2p_set_friction_field(m2p_ctx* c, const double* tan_mu)
     const size_t n = (size_t)c->g.nx * c->g.ny;
     for (size_t k = 0; k < n; k++)
         if (!(tan_mu[k] >= 0.0) || !std::isfinite(tan_mu[k])) return fail(M2P_EINVAL, "bad tan_mu value");
+    if (c->p.flags & M2P_F_EARTH_PRESSURE) {
+        const int rc = ep_friction_ok(&c->p, tan_mu, n);
+        if (rc) return rc;
+    }
     HIPCHK(hipStreamSynchronize(c->stream));
     if (!c->mu) {
         if (hipMalloc(&c->mu, (size_t)c->g.ny * c->kp.pitch * c->esz) != hipSuccess)

@@ -41,6 +41,7 @@ struct KParams {
     int rk;                 // stages per step: 2 (Heun) or 3 (SSP Runge-Kutta)
     SegDesc sseg[MAX_SEG];  // Mode-II segments with a state hydrograph (ghost cells)
     int ntab;               // doubles in the hydrograph table of both kinds of segment
+    double cos2_int;        // cos^2 of the internal friction angle (earth-pressure option)
 };
 
 // Scalars that live on the device across steps (time, dt, reductions).
@@ -212,7 +213,7 @@ struct Consts {
 // (one-sided), a = v_n + sqrt(dP/dm) and am = v_n - sqrt(dP/dm) instead.
 template <typename T, bool OS = false>
 M2P_FN void side_flux(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d,
-                                          T F[NF], T qv[NF], T a[2], T* am = nullptr)
+                                          T F[NF], T qv[NF], T a[2], T* am = nullptr, T kep = T(1))
 {
     if constexpr (Folded<T>::value) {
         const T ms = u[0], mf = u[3];
@@ -225,7 +226,7 @@ M2P_FN void side_flux(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d,
         const T Ann = d == 0 ? g.A11 : g.A22;
         const T vns = d == 0 ? vXs : vYs;
         const T vnf = d == 0 ? vXf : vYf;
-        const T Ps = K.k_ps * h * hs;  // eps J_b h N^s / c
+        const T Ps = kep * (K.k_ps * h * hs);  // eps J_b h N^s / c, times the earth-pressure coefficient
         const T Pf = K.k_pf * h * h;   // eps J_b h pbar^f / c
         qv[0] = ms;
         qv[1] = ms * vXs;
@@ -240,7 +241,7 @@ M2P_FN void side_flux(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d,
         F[4] = qv[4] * vnf + Pf * Ax;
         F[5] = qv[5] * vnf + Pf * Ay;
         const T ac = K.eps * Ann * g.c;
-        const T cs = ac * K.half_oma * (h + hs);
+        const T cs = kep * (ac * K.half_oma * (h + hs));
         const T cf = ac * h;
         const T rs = sqrt(cs > T(0) ? cs : T(0)), rf = sqrt(cf > T(0) ? cf : T(0));
         if constexpr (OS) {
@@ -258,7 +259,7 @@ M2P_FN void side_flux(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d,
     T hs = ms / g.J, hf = mf / g.J, h = hs + hf;
     T vXs = dsg(u[1], ms, K.md), vYs = dsg(u[2], ms, K.md);
     T vXf = dsg(u[4], mf, K.md), vYf = dsg(u[5], mf, K.md);
-    T Ns = g.c * (T(1) - K.al) * hs / T(2);
+    T Ns = kep * (g.c * (T(1) - K.al) * hs / T(2));  // times the earth-pressure coefficient
     T pf = g.c * h / T(2);
     T Ax = d == 0 ? g.A11 : g.A21;
     T Ay = d == 0 ? g.A12 : g.A22;
@@ -277,7 +278,7 @@ M2P_FN void side_flux(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d,
     qv[3] = mf;
     qv[4] = mf * vXf;
     qv[5] = mf * vYf;
-    T cs = K.eps * Ann * g.c * (T(1) - K.al) * (h + hs) / T(2);
+    T cs = kep * (K.eps * Ann * g.c * (T(1) - K.al) * (h + hs) / T(2));
     T cf = K.eps * Ann * g.c * h;
     T rs = sqrt(cs > T(0) ? cs : T(0)), rf = sqrt(cf > T(0) ? cf : T(0));
     if constexpr (OS) {
@@ -293,7 +294,7 @@ M2P_FN void side_flux(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d,
 
 // Phase speeds only (identical arithmetic to side_flux).
 template <typename T>
-M2P_FN void side_speed(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d, T a[2])
+M2P_FN void side_speed(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d, T a[2], T kep = T(1))
 {
     if constexpr (Folded<T>::value) {
         const T ms = u[0], mf = u[3];
@@ -301,7 +302,7 @@ M2P_FN void side_speed(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d
         const T vns = d == 0 ? dsg(u[1], ms, K.md) : dsg(u[2], ms, K.md);
         const T vnf = d == 0 ? dsg(u[4], mf, K.md) : dsg(u[5], mf, K.md);
         const T ac = K.eps * (d == 0 ? g.A11 : g.A22) * g.c;
-        const T cs = ac * K.half_oma * (h + hs);
+        const T cs = kep * (ac * K.half_oma * (h + hs));
         const T cf = ac * h;
         a[0] = fabs(vns) + sqrt(cs > T(0) ? cs : T(0));
         a[1] = fabs(vnf) + sqrt(cf > T(0) ? cf : T(0));
@@ -312,7 +313,7 @@ M2P_FN void side_speed(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d
     T vns = d == 0 ? dsg(u[1], ms, K.md) : dsg(u[2], ms, K.md);
     T vnf = d == 0 ? dsg(u[4], mf, K.md) : dsg(u[5], mf, K.md);
     T Ann = d == 0 ? g.A11 : g.A22;
-    T cs = K.eps * Ann * g.c * (T(1) - K.al) * (h + hs) / T(2);
+    T cs = kep * (K.eps * Ann * g.c * (T(1) - K.al) * (h + hs) / T(2));
     T cf = K.eps * Ann * g.c * h;
     a[0] = fabs(vns) + sqrt(cs > T(0) ? cs : T(0));
     a[1] = fabs(vnf) + sqrt(cf > T(0) ? cf : T(0));
@@ -322,7 +323,7 @@ M2P_FN void side_speed(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d
 // of side_speed.  The FP32 forms compute the velocity ratios in pairs (one
 // desingularisation factor per phase); otherwise side_speed twice.
 template <typename T>
-M2P_FN void cell_speeds(const Consts<T>& K, const T u[NF], const Geo<T>& g, T& ax, T& ay)
+M2P_FN void cell_speeds(const Consts<T>& K, const T u[NF], const Geo<T>& g, T& ax, T& ay, T kep = T(1))
 {
     if constexpr (Folded<T>::value) {
         const T ms = u[0], mf = u[3];
@@ -330,7 +331,7 @@ M2P_FN void cell_speeds(const Consts<T>& K, const T u[NF], const Geo<T>& g, T& a
         T vXs, vYs, vXf, vYf;
         dsg2(u[1], u[2], ms, K.md, vXs, vYs);
         dsg2(u[4], u[5], mf, K.md, vXf, vYf);
-        const T hhs = K.half_oma * (h + hs);
+        const T hhs = kep * (K.half_oma * (h + hs));
         const T acx = K.eps * g.A11 * g.c, acy = K.eps * g.A22 * g.c;
         const T csx = acx * hhs, cfx = acx * h, csy = acy * hhs, cfy = acy * h;
         const T axs = fabs(vXs) + sqrt(csx > T(0) ? csx : T(0)), axf = fabs(vXf) + sqrt(cfx > T(0) ? cfx : T(0));
@@ -340,9 +341,9 @@ M2P_FN void cell_speeds(const Consts<T>& K, const T u[NF], const Geo<T>& g, T& a
         return;
     }
     T a[2];
-    side_speed(K, u, g, 0, a);
+    side_speed(K, u, g, 0, a, kep);
     ax = a[0] > a[1] ? a[0] : a[1];
-    side_speed(K, u, g, 1, a);
+    side_speed(K, u, g, 1, a, kep);
     ay = a[0] > a[1] ? a[0] : a[1];
 }
 
@@ -364,12 +365,13 @@ constexpr bool carry_2h()
 // and (F- + F+)/2 where a+ = a- = 0 (a dry face).
 template <typename T, bool H2 = false, bool CU = false>
 M2P_FN void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
-                                             const T uR[NF], const Geo<T>& gR, int d, T H[NF])
+                                             const T uR[NF], const Geo<T>& gR, int d, T H[NF], T kL = T(1),
+                                             T kR = T(1))
 {
     if constexpr (CU) {
         T FL[NF], FR[NF], qL[NF], qR[NF], hiL[2], loL[2], hiR[2], loR[2];
-        side_flux<T, true>(K, uL, gL, d, FL, qL, hiL, loL);
-        side_flux<T, true>(K, uR, gR, d, FR, qR, hiR, loR);
+        side_flux<T, true>(K, uL, gL, d, FL, qL, hiL, loL, kL);
+        side_flux<T, true>(K, uR, gR, d, FR, qR, hiR, loR, kR);
 #pragma unroll
         for (int ph = 0; ph < 2; ph++) {
             T ap = hiL[ph] > hiR[ph] ? hiL[ph] : hiR[ph];
@@ -396,8 +398,8 @@ M2P_FN void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
         return;
     }
     T FL[NF], FR[NF], qL[NF], qR[NF], aL[2], aR[2];
-    side_flux(K, uL, gL, d, FL, qL, aL);
-    side_flux(K, uR, gR, d, FR, qR, aR);
+    side_flux<T>(K, uL, gL, d, FL, qL, aL, nullptr, kL);
+    side_flux<T>(K, uR, gR, d, FR, qR, aR, nullptr, kR);
 #pragma unroll
     for (int ph = 0; ph < 2; ph++) {
         T a = aL[ph] > aR[ph] ? aL[ph] : aR[ph];
@@ -411,19 +413,48 @@ M2P_FN void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
     }
 }
 
-// KParams.flags bit of the central-upwind face flux (M2P_F_CENTRAL_UPWIND).
+// KParams.flags bits of the central-upwind face flux and of the earth-pressure
+// coefficients (M2P_F_CENTRAL_UPWIND, M2P_F_EARTH_PRESSURE).
 constexpr int kFlagCentralUpwind = 4;
+constexpr int kFlagEarthPressure = 8;
 
 // The face flux the flags select, chosen at run time (the tiled kernels take
-// the choice as a template argument instead).
+// the choice as a template argument instead); kL, kR: the earth-pressure
+// coefficients of the two sides' owner cells in the face's direction.
 template <typename T>
 M2P_FN void face_flux_sel(const Consts<T>& K, int flags, const T uL[NF], const Geo<T>& gL, const T uR[NF],
-                          const Geo<T>& gR, int d, T H[NF])
+                          const Geo<T>& gR, int d, T H[NF], T kL = T(1), T kR = T(1))
 {
     if (flags & kFlagCentralUpwind)
-        central_flux<T, false, true>(K, uL, gL, uR, gR, d, H);
+        central_flux<T, false, true>(K, uL, gL, uR, gR, d, H, kL, kR);
     else
-        central_flux(K, uL, gL, uR, gR, d, H);
+        central_flux(K, uL, gL, uR, gR, d, H, kL, kR);
+}
+
+// Savage-Hutter earth-pressure coefficients (Savage and Hutter 1989, in the
+// two-dimensional form of Hutter et al. 1993) from c2 = cos^2 delta_int and
+// t = tan delta_b: K_x = 2 (1 -/+ sqrt(1 - c2 (1 + t^2))) / c2 - 1 and
+// K_y = (K_x + 1 -/+ sqrt((K_x - 1)^2 + 4 t^2)) / 2, the upper sign (active)
+// where the flow extends along the direction, the lower (passive) where it is
+// compressed.  ep_kmax is the largest value a cell can take (passive, then
+// passive), the bound of the solid's pressure speed in the CFL step.
+template <typename T>
+M2P_FN T ep_kx(T c2, T t, bool active)
+{
+    const T disc = T(1) - c2 * (T(1) + t * t);
+    const T r = sqrt(disc > T(0) ? disc : T(0));
+    return T(2) * (active ? T(1) - r : T(1) + r) / c2 - T(1);
+}
+template <typename T>
+M2P_FN T ep_ky(T kx, T t, bool active)
+{
+    const T r = sqrt((kx - T(1)) * (kx - T(1)) + T(4) * t * t);
+    return T(0.5) * (active ? kx + T(1) - r : kx + T(1) + r);
+}
+template <typename T>
+M2P_FN T ep_kmax(T c2, T t)
+{
+    return ep_ky(ep_kx(c2, t, false), t, false);
 }
 
 // Prescribed Mode-II face flux from the critical-depth inflow state

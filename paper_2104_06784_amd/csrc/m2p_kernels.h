@@ -133,7 +133,8 @@ template <typename T, int STAGE>
 __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restrict__ Uin, T* Un, T* Uout,
                                                    const T* __restrict__ b, const T* __restrict__ mu,
                                                    DevScalars* __restrict__ S, double* __restrict__ bpart,
-                                                   double* __restrict__ wpart, int nmax)
+                                                   double* __restrict__ wpart, int nmax,
+                                                   const T* __restrict__ KE)
 {
     __shared__ double sh[9 * 256];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -144,6 +145,17 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
     double red[1] = {0};  // clamps
     double ax = 0.0, ay = 0.0;
     int bad = 0;
+    // earth-pressure coefficient of cell (ii, jj) in direction d (a ghost
+    // cell: that of the cell it maps to); 1 without the option
+    const bool ep = (P.flags & kFlagEarthPressure) != 0;
+    const size_t kfs = (size_t)P.ny * P.pitch;
+    auto kep = [&](int ii, int jj, int d) {
+        if (!ep) return T(1);
+        int f = 0;
+        const int mi = map_index(ii, P.nx, P.bc[0], P.bc[1], f);
+        const int mj = map_index(jj, P.ny, P.bc[2], P.bc[3], f);
+        return KE[d * kfs + (size_t)mj * P.pitch + mi];
+    };
     if (active) {
         const T dt = T(S->dt);
         T row[5][NF], col[5][NF];
@@ -157,19 +169,19 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
             for (int q = 0; q < 4; q++)
                 for (int k = 0; k < NF; k++) w[q][k] = row[q][k];
             reconstruct(w, uL, uR);
-            face_flux_sel(K, P.flags, uL, gW, uR, gC, 0, HXl);
+            face_flux_sel(K, P.flags, uL, gW, uR, gC, 0, HXl, kep(i - 1, j, 0), kep(i, j, 0));
             for (int q = 0; q < 4; q++)
                 for (int k = 0; k < NF; k++) w[q][k] = row[q + 1][k];
             reconstruct(w, uL, uR);
-            face_flux_sel(K, P.flags, uL, gC, uR, gE, 0, HXr);
+            face_flux_sel(K, P.flags, uL, gC, uR, gE, 0, HXr, kep(i, j, 0), kep(i + 1, j, 0));
             for (int q = 0; q < 4; q++)
                 for (int k = 0; k < NF; k++) w[q][k] = col[q][k];
             reconstruct(w, uL, uR);
-            face_flux_sel(K, P.flags, uL, gS, uR, gC, 1, HYb);
+            face_flux_sel(K, P.flags, uL, gS, uR, gC, 1, HYb, kep(i, j - 1, 1), kep(i, j, 1));
             for (int q = 0; q < 4; q++)
                 for (int k = 0; k < NF; k++) w[q][k] = col[q + 1][k];
             reconstruct(w, uL, uR);
-            face_flux_sel(K, P.flags, uL, gC, uR, gN, 1, HYt);
+            face_flux_sel(K, P.flags, uL, gC, uR, gN, 1, HYt, kep(i, j, 1), kep(i, j + 1, 1));
         }
         // Mode-II faces, and the flux through every boundary face into the
         // per-face outflow slots (zero on discharge-inflow faces)
@@ -267,9 +279,10 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
         }
         if (stage_last(STAGE)) {
             T a[2];
-            side_speed(K, out, gC, 0, a);
+            const T km = ep ? ep_kmax(T(P.cos2_int), tmu) : T(1);
+            side_speed(K, out, gC, 0, a, km);
             ax = (double)(a[0] > a[1] ? a[0] : a[1]);
-            side_speed(K, out, gC, 1, a);
+            side_speed(K, out, gC, 1, a, km);
             ay = (double)(a[0] > a[1] ? a[0] : a[1]);
         }
 #pragma unroll
@@ -307,11 +320,41 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
     }
 }
 
+// ---------------------------------------------- earth pressure (option)
+
+// Per cell, the earth-pressure coefficients of the stage input Uin into KE
+// ([2][ny][pitch]: K_x, K_y): active in X where the central difference of the
+// desingularised solid velocity v_X^s along xi is >= 0, passive otherwise;
+// likewise in Y with v_Y^s along eta (neighbours through the ghost map).
+template <typename T>
+__global__ void __launch_bounds__(256) k_earth_pressure(KParams P, const T* __restrict__ Uin,
+                                                        const T* __restrict__ b, const T* __restrict__ mu,
+                                                        T* __restrict__ KE)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= P.nx || j >= P.ny) return;
+    const Consts<T> K(P);
+    const View<T> V(P, Uin, b);
+    T uE[NF], uW[NF], uN[NF], uS[NF];
+    V.load(i + 1, j, uE);
+    V.load(i - 1, j, uW);
+    V.load(i, j + 1, uN);
+    V.load(i, j - 1, uS);
+    const T dvx = dsg(uE[1], uE[0], K.md) - dsg(uW[1], uW[0], K.md);
+    const T dvy = dsg(uN[2], uN[0], K.md) - dsg(uS[2], uS[0], K.md);
+    const size_t c = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
+    const T t = P.has_mu ? mu[c] : K.tan_d;
+    const T kx = ep_kx(T(P.cos2_int), t, dvx >= T(0));
+    KE[c] = kx;
+    KE[fs + c] = ep_ky(kx, t, dvy >= T(0));
+}
+
 // ------------------------------------------------------- speeds (init)
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_speeds(KParams P, const T* __restrict__ U, const T* __restrict__ b,
-                                                double* __restrict__ wpart)
+                                                const T* __restrict__ mu, double* __restrict__ wpart)
 {
     __shared__ double sh[512];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -323,9 +366,12 @@ __global__ void __launch_bounds__(256) k_speeds(KParams P, const T* __restrict__
         T u[NF], a[2];
         V.load(i, j, u);
         Geo<T> g = V.geo(i, j, K);
-        side_speed(K, u, g, 0, a);
+        T km = T(1);
+        if (P.flags & kFlagEarthPressure)
+            km = ep_kmax(T(P.cos2_int), P.has_mu ? mu[(size_t)j * P.pitch + i] : K.tan_d);
+        side_speed(K, u, g, 0, a, km);
         ax = (double)(a[0] > a[1] ? a[0] : a[1]);
-        side_speed(K, u, g, 1, a);
+        side_speed(K, u, g, 1, a, km);
         ay = (double)(a[0] > a[1] ? a[0] : a[1]);
     }
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;

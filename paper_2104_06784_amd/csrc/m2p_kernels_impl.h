@@ -33,10 +33,18 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
     const int kind = part == 0 ? 1 : (P.rk == 2 ? 2 : (part == 1 ? 3 : 4));
     const T* in = part == 0 ? U : (kind == 4 ? Us2 : Us);
     T* out = part == 0 ? Us : (kind == 3 ? Us2 : (B.Uout ? (T*)B.Uout : U));
+    if (P.flags & kFlagEarthPressure) {
+        // the option's coefficients of the stage input; the reference kernel
+        // runs the stage (make_shape selects it for such contexts)
+        if (sh.variant != 1 || !B.kep) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_earth_pressure<T>), dim3(sh.nbx, sh.nby), dim3(64, 4), 0, st, P, in, b, mu,
+                           (T*)B.kep);
+    }
     if (sh.variant == 1) {
         dim3 blk(64, 4), grd(sh.nbx, sh.nby);
 #define M2P_REF(K) \
-    hipLaunchKernelGGL((k_stage_ref<T, K>), grd, blk, 0, st, P, in, U, out, b, mu, B.S, B.bpart, B.wpart, B.nmax)
+    hipLaunchKernelGGL((k_stage_ref<T, K>), grd, blk, 0, st, P, in, U, out, b, mu, B.S, B.bpart, B.wpart, B.nmax, \
+                       (const T*)B.kep)
         if (kind == 1)
             M2P_REF(1);
         else if (kind == 2)
@@ -83,7 +91,7 @@ hipError_t Launch<M2P_REAL>::init(const KParams& P, const Bufs& B, hipStream_t s
 {
     using T = M2P_REAL;
     dim3 blk(64, 4), grd((P.nx + 63) / 64, (P.ny + 3) / 4);
-    hipLaunchKernelGGL((k_speeds<T>), grd, blk, 0, st, P, (const T*)B.U, (const T*)B.b, B.wpart);
+    hipLaunchKernelGGL((k_speeds<T>), grd, blk, 0, st, P, (const T*)B.U, (const T*)B.b, (const T*)B.mu, B.wpart);
     hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(kFinThreads), 0, st, P, B.S, B.bpart, 0, 0, B.nmax, B.tables,
                        1, B.wpart, B.nw_ref);
     return hipGetLastError();

@@ -23,6 +23,7 @@ struct Bufs {
     void* Us;              // stage state U*
     void* Us2;             // second stage state of the three-stage method (else nullptr)
     void* Uout;            // output of the step's last stage (nullptr: in place over U)
+    void* kep;             // earth-pressure coefficients [2][ny][pitch] (the option only, else nullptr)
     const void* b;         // padded DEM / L
     const void* mu;        // per-cell tan(delta_b) or nullptr
     DevScalars* S;         // device scalars

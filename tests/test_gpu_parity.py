@@ -296,6 +296,61 @@ def test_central_upwind_fp32_and_refusals():
         assert e.value.code == M2P_EINVAL
 
 
+def _ep_problem(n=96, mu=False):
+    import dataclasses
+    prob = I.plane_bump_pile(n=n)
+    prm = dataclasses.replace(prob.params, cfl=0.25, flags=I.F_EARTH_PRESSURE, delta_int_deg=35.0)
+    q = dataclasses.replace(prob, params=prm)
+    if mu:
+        q.tan_mu = np.tan(np.radians(20.0 + 8.0 * I.smooth_field(n, 77, 4.0)))
+    q.name = prob.name + ("-ep-mu" if mu else "-ep")
+    return q
+
+
+@pytest.mark.parametrize("mu", [False, True])
+def test_earth_pressure_option_fp64(mu):
+    """The Savage-Hutter earth-pressure option (M2P_F_EARTH_PRESSURE) against
+    the oracle's: the plane-bump-pile problem with walls (delta_int 35 deg),
+    with the uniform basal friction and with a per-cell friction field; the
+    reference kernel runs the option whichever variant is asked for."""
+    q = _ep_problem(mu=mu)
+    for variant in (1, 2):
+        g, o = _compare_steps(q, 120, 1e-12, variant=variant)
+        dg, do = g.diag(), o.diag()
+        for k in ("mass_s", "mass_f", "out_s", "out_f"):
+            assert abs(dg[k] - do[k]) <= 1e-12 * max(abs(do[k]), 1.0), k
+
+
+def test_earth_pressure_fp32_and_refusals():
+    """FP32 earth pressure stays within the FP32 tolerance of the FP64 oracle
+    (to 5 s); contexts with delta_b > delta_int, inflow segments, the tangent,
+    adjoint and ensemble calls refuse the option."""
+    import dataclasses
+
+    from paper_2104_06784_amd._abi import M2P_EINVAL, M2PError
+    from paper_2104_06784_amd.sim import Batch
+    q = _ep_problem(n=128)
+    g, o = Sim(q, precision="f32"), Ora(q)
+    g.run_to(5.0)
+    o.run(10 ** 6, 5.0)
+    hg, ho = g.fields()["h"], o.fields()["h"]
+    l1 = np.abs(hg - ho).sum() / ho.sum()
+    _say(f"[parity] earth pressure FP32: rel L1 {l1:.3e}")
+    assert l1 <= 1e-3
+    z = np.zeros((6, q.ny, q.nx))
+    t, Q, ph = I.triangular_hydrograph(30.0, 5.0, 20.0, 0.5)
+    one = np.array([0.0])
+    calls = (lambda: g.adjoint_run(4, 2, np.zeros((q.ny, q.nx))), lambda: g.stage_jvp(z), lambda: g.stage_vjp(z),
+             lambda: Batch([q, q], precision="f32"), lambda: g.set_inflow([I.Inflow(I.SIDE_W, 10, 5, t, Q, ph)]),
+             lambda: g.set_inflow_states([I.InflowState(I.SIDE_W, 10, 5, one, one + 1.0, one + 0.5, one + 1.0)]),
+             lambda: Sim(dataclasses.replace(q, params=dataclasses.replace(q.params, delta_int_deg=15.0)),
+                         precision="f32"))
+    for call in calls:
+        with pytest.raises(M2PError) as e:
+            call()
+        assert e.value.code == M2P_EINVAL
+
+
 def test_run_to_lands_on_end_time():
     prob = I.plane_bump_pile(n=64)
     g, o = Sim(prob, precision="f64"), Ora(prob)
