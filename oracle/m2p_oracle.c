@@ -12,7 +12,10 @@
  * Tadmor 2000) with minmod-limited linear reconstruction, advanced by the
  * two-step modified Euler method (Heun, second-order Runge-Kutta) with a
  * CFL-limited time step.  Readings chosen where the paper is silent are marked
- * "reading:"; the same readings are followed by the HIP path.
+ * "reading:"; the same readings are followed by the HIP path.  Options beside
+ * the paper's choices (params.flags): the three-stage SSP Runge-Kutta method,
+ * the central-upwind face flux with one-sided speeds, and Savage-Hutter
+ * earth-pressure coefficients from the internal friction angle.
  *
  * Units: SI at the interface; inside, the shallow scaling X, Y, b ~ L,
  * h ~ H, v ~ sqrt(g L), t ~ sqrt(L / g), aspect ratio eps = H / L.
