@@ -311,14 +311,21 @@ def _ep_problem(n=96, mu=False):
 def test_earth_pressure_option_fp64(mu):
     """The Savage-Hutter earth-pressure option (M2P_F_EARTH_PRESSURE) against
     the oracle's: the plane-bump-pile problem with walls (delta_int 35 deg),
-    with the uniform basal friction and with a per-cell friction field; the
+    with the uniform basal friction and with a per-cell friction field, and
+    combined with the three-stage method and the central-upwind flux; the
     reference kernel runs the option whichever variant is asked for."""
+    import dataclasses
     q = _ep_problem(mu=mu)
     for variant in (1, 2):
         g, o = _compare_steps(q, 120, 1e-12, variant=variant)
         dg, do = g.diag(), o.diag()
         for k in ("mass_s", "mass_f", "out_s", "out_f"):
             assert abs(dg[k] - do[k]) <= 1e-12 * max(abs(do[k]), 1.0), k
+    # with the three-stage method and the central-upwind flux as well
+    r = dataclasses.replace(q, params=dataclasses.replace(
+        q.params, flags=q.params.flags | I.F_RK3 | I.F_CENTRAL_UPWIND))
+    r.name = q.name + "-rk3-cu"
+    _compare_steps(r, 60, 1e-12, variant=1)
 
 
 def test_earth_pressure_fp32_and_refusals():
