@@ -78,6 +78,19 @@ def test_create_rejects_bad_grid_and_dem():
     assert _create(A.Grid(8, 8, 10.0, 10.0), make_params(bc))[0] == A.M2P_EINVAL
 
 
+@pytest.mark.parametrize("kw", [
+    dict(flags=16),                                                      # unknown flag
+    dict(flags=I.F_EARTH_PRESSURE, delta_b_deg=20.0, delta_int_deg=15.0),  # basal above internal friction
+    dict(flags=I.F_EARTH_PRESSURE, delta_int_deg=90.0),
+    dict(flags=I.F_EARTH_PRESSURE, delta_int_deg=-1.0)])
+def test_create_rejects_bad_options(kw):
+    """Option flags are validated before any device call: unknown bits, and
+    earth-pressure angles outside delta_b <= delta_int < 90 deg."""
+    rc, h = _create(A.Grid(8, 8, 10.0, 10.0), make_params(I.Params(**kw)))
+    assert rc == A.M2P_EINVAL and not h.value
+    assert A.lib().m2p_last_error()
+
+
 def test_null_arguments_rejected():
     L = A.lib()
     assert L.m2p_create(None, None, None, 0, None, None, None) == A.M2P_EINVAL
