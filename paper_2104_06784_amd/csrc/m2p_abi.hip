@@ -1148,7 +1148,8 @@ struct VjpWork {
         const size_t st = (size_t)NF * K.ny * K.pitch * c->esz;
         int rc;
         if ((rc = GT.alloc(st)) || (rc = DU.alloc(st)) || (rc = tmp.alloc(st))) return rc;
-        if ((rc = FCX.alloc((size_t)K.ny * (K.nx + 1) * 24 * c->esz))) return rc;
+        // per-cell x-face sums over the row extended by two ghost columns a side
+        if ((rc = FCX.alloc((size_t)K.ny * (K.nx + 4) * NF * c->esz))) return rc;
         if ((rc = FCY.alloc((size_t)(K.ny + 1) * K.nx * 24 * c->esz))) return rc;
         return SC.alloc((size_t)K.ny * K.nx * 34 * c->esz);
     }

@@ -505,43 +505,22 @@ __device__ __forceinline__ void face_flux_vjp(const KParams& P, const T w[4][NF]
         for (int k = 0; k < NF; k++) out[6 * q + k] = lw[q][k];
 }
 
-// Pass B, faces: x-faces (d = 0) for i in [-1, nx-1] (face between i and i+1)
-// and y-faces (d = 1) for j in [-1, ny-1]; 24 stencil cotangents per face into
-// FCX or FCY [24][faces] (slot-major; slot = 6 * cell + field, cells a-1 ..
-// a+2).  Grid rows 0 .. ny-1 are the x-face rows, rows ny .. 2 ny the y-face
-// rows.
+// The 24 stencil cotangents of one face (out[6 q + k] for cell a-1+q, a the
+// face's left cell): x-face (d = 0) between (i, j) and (i + 1, j), y-face
+// (d = 1) between (i, j) and (i, j + 1).  Faces with a prescribed inflow flux
+// do not depend on the state: zeros.
 template <typename T>
-__global__ void __launch_bounds__(128) k_adj_face(KParams P, const T* __restrict__ U, const T* __restrict__ GT,
-                                                  const T* __restrict__ b, T dt, T* __restrict__ FCX,
-                                                  T* __restrict__ FCY)
+__device__ __forceinline__ void adj_face_out(const KParams& P, const T* __restrict__ U, const T* __restrict__ GT,
+                                             const T* __restrict__ b, int d, T dt, int i, int j, T out[24])
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int d = (int)blockIdx.y < P.ny ? 0 : 1;
-    const int nf_along = d == 0 ? P.nx + 1 : P.nx;
-    if (t >= nf_along) return;
-    const int line = d == 0 ? (int)blockIdx.y : (int)blockIdx.y - P.ny;  // row j (x-faces), face row j (y-faces)
-    T* __restrict__ FC = d == 0 ? FCX : FCY;
-    int i, j;
-    if (d == 0) {
-        i = t - 1;
-        j = line;
-    } else {
-        i = t;
-        j = line - 1;
-    }
-    const size_t fidx = (size_t)line * nf_along + t;
-    // slot-major: slot q of all faces of this direction is contiguous
-    const size_t nfaces = (size_t)nf_along * (d == 0 ? P.ny : P.ny + 1);
-    T out[24];
     const size_t fs = (size_t)P.ny * P.pitch;
-    // inflow faces carry a prescribed flux: no dependence on the state
     bool fixed = false;
     if (d == 0 && i == -1) fixed = inflow_seg_at(P, 0, j) >= 0;
     if (d == 0 && i == P.nx - 1) fixed = fixed || inflow_seg_at(P, 1, j) >= 0;
     if (d == 1 && j == -1) fixed = inflow_seg_at(P, 2, i) >= 0;
     if (d == 1 && j == P.ny - 1) fixed = fixed || inflow_seg_at(P, 3, i) >= 0;
     if (fixed) {
-        for (int q = 0; q < 24; q++) FC[q * nfaces + fidx] = T(0);
+        for (int q = 0; q < 24; q++) out[q] = T(0);
         return;
     }
     // face cotangent: R_left has -H/h, R_right has +H/h
@@ -565,7 +544,60 @@ __global__ void __launch_bounds__(128) k_adj_face(KParams P, const T* __restrict
     };
     const Geo<T> ga = geo(li, lj), gb = geo(ri, rj);
     face_flux_vjp(P, w0, ga, gb, d, gH, out);
-    for (int q = 0; q < 24; q++) FC[q * nfaces + fidx] = out[q];
+}
+
+// Wavefronts of x-faces per grid row: each covers 60 cells of the row
+// extended by two ghost columns per side (extended column e = i + 2).
+__host__ __device__ inline int adj_xwaves(int nx) { return (nx + 4 + 59) / 60; }
+
+// Pass B, faces, in one launch of 128-thread workgroups.  Grid rows
+// 0 .. ny-1: x-faces of grid row j, gathered per cell in registers -- lane l
+// of wavefront w computes face f = 60 w - 4 + l (between cells f and f + 1;
+// faces outside [-1, nx-1] contribute zeros) and lanes 1..60 sum the four
+// faces of cell f + 1 (slots 3, 2, 1, 0 of faces f - 1 .. f + 2, fixed
+// order) into XS[6][ny][nx + 4] at extended column f + 3, ghost columns
+// included.  Grid rows ny .. 2 ny: y-faces j in [-1, ny-1], one thread per
+// face, 24 stencil cotangents into FCY[24][faces] (slot-major; slot = 6 *
+// cell + field, cells j-1 .. j+2).
+template <typename T>
+__global__ void __launch_bounds__(128) k_adj_face(KParams P, const T* __restrict__ U, const T* __restrict__ GT,
+                                                  const T* __restrict__ b, T dt, T* __restrict__ XS,
+                                                  T* __restrict__ FCY)
+{
+    T out[24];
+    if ((int)blockIdx.y < P.ny) {
+        const int j = (int)blockIdx.y;
+        const int lane = threadIdx.x & 63;
+        const int w = (int)blockIdx.x * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+        if (w >= adj_xwaves(P.nx)) return;  // whole wavefront
+        const int f = 60 * w - 4 + lane;
+        if (f >= -1 && f <= P.nx - 1)
+            adj_face_out(P, U, GT, b, 0, dt, f, j, out);
+        else
+            for (int q = 0; q < 24; q++) out[q] = T(0);
+        // every lane of the wavefront takes part in the shuffles
+        T acc[NF];
+#pragma unroll
+        for (int k = 0; k < NF; k++) {
+            const T a3 = __shfl(out[18 + k], lane - 1, 64);
+            const T a1 = __shfl(out[6 + k], lane + 1, 64);
+            const T a0 = __shfl(out[k], lane + 2, 64);
+            acc[k] = ((a3 + out[12 + k]) + a1) + a0;
+        }
+        const int e = f + 3;
+        if (lane >= 1 && lane <= 60 && e < P.nx + 4) {
+            const size_t nxs = (size_t)P.ny * (P.nx + 4), o = (size_t)j * (P.nx + 4) + e;
+#pragma unroll
+            for (int k = 0; k < NF; k++) XS[k * nxs + o] = acc[k];
+        }
+        return;
+    }
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P.nx) return;
+    const int line = (int)blockIdx.y - P.ny;  // face row: the face between rows line - 1 and line
+    adj_face_out(P, U, GT, b, 1, dt, t, line - 1, out);
+    const size_t fidx = (size_t)line * P.nx + t, nfaces = (size_t)P.nx * (P.ny + 1);
+    for (int q = 0; q < 24; q++) FCY[q * nfaces + fidx] = out[q];
 }
 
 // Source input slots: 0..5 centre fields; 6..21 neighbour (E, W, N, S) x
@@ -953,20 +985,21 @@ __global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict_
 // cell reads its own z before writing).
 template <typename T>
 __device__ __forceinline__ void adj_gather_interior(const KParams& P, const T* __restrict__ DU,
-                                                    const T* __restrict__ FCX, const T* __restrict__ FCY,
+                                                    const T* __restrict__ XS, const T* __restrict__ FCY,
                                                     const T* __restrict__ SC, const T* z, T zc, T* lam_in, int i,
                                                     int j)
 {
     const size_t c = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
     // slot-major cotangent arrays (slot stride: number of faces or cells)
-    const size_t nfx = (size_t)(P.nx + 1) * P.ny, nfy = (size_t)P.nx * (P.ny + 1), ncl = (size_t)P.nx * P.ny;
+    const size_t nxs = (size_t)P.ny * (P.nx + 4), nfy = (size_t)P.nx * (P.ny + 1), ncl = (size_t)P.nx * P.ny;
     T acc[NF];
     for (int k = 0; k < NF; k++) acc[k] = DU[k * fs + c];
     // No ghost cell maps onto this cell: each contribution comes from a
-    // fixed (face or cell, slot); x-faces, y-faces, then the 3 x 3 sources.
-    for (int fi = i - 2; fi <= i + 1; fi++) {
-        const T* f = FCX + ((size_t)j * (P.nx + 1) + (fi + 1)) + 6 * (i - fi + 1) * nfx;
-        for (int k = 0; k < NF; k++) acc[k] += f[k * nfx];
+    // fixed (face or cell, slot); x-faces (summed per cell), y-faces, then
+    // the 3 x 3 sources.
+    {
+        const T* f = XS + (size_t)j * (P.nx + 4) + (i + 2);
+        for (int k = 0; k < NF; k++) acc[k] += f[k * nxs];
     }
     for (int fj = j - 2; fj <= j + 1; fj++) {
         const T* f = FCY + ((size_t)(fj + 1) * P.nx + i) + 6 * (j - fj + 1) * nfy;
@@ -1010,18 +1043,19 @@ __host__ __device__ inline long long adj_ring_cells(int nx, int ny)
 // cover the interior box i in [2, nx - 3], j in [2, ny - 3] (nbx workgroups of
 // 128 cells per row), one thread per cell.  The rest cover the edge ring with
 // one wavefront per ring cell: the lanes share the candidate contributions
-// (24 x-face and 24 y-face (face, stencil position) pairs, 9 source cells x
-// 34 slots), keep those the ghost map sends to this cell, and the lanes'
-// partial sums are combined by a fixed butterfly (deterministic).
+// (the cell's own and the four ghost columns' x-face sums, 24 y-face (face,
+// stencil position) pairs, 9 source cells x 34 slots), keep those the ghost
+// map sends to this cell, and the lanes' partial sums are combined by a fixed
+// butterfly (deterministic).
 template <typename T>
-__global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restrict__ DU, const T* __restrict__ FCX,
+__global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restrict__ DU, const T* __restrict__ XS,
                                                     const T* __restrict__ FCY, const T* __restrict__ SC, const T* z,
                                                     T zc, T* lam_in, int nbi, int nbx)
 {
     if ((int)blockIdx.x < nbi) {
         const int i = 2 + ((int)blockIdx.x % nbx) * 128 + (int)threadIdx.x;
         const int j = 2 + (int)blockIdx.x / nbx;
-        if (i <= P.nx - 3) adj_gather_interior(P, DU, FCX, FCY, SC, z, zc, lam_in, i, j);
+        if (i <= P.nx - 3) adj_gather_interior(P, DU, XS, FCY, SC, z, zc, lam_in, i, j);
         return;
     }
     const long long r = ((long long)(blockIdx.x - nbi) * blockDim.x + threadIdx.x) >> 6;
@@ -1045,31 +1079,38 @@ __global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restri
         i = nx <= 4 ? cc : (cc < 2 ? cc : nx - 4 + cc);
     }
     const size_t fs = (size_t)ny * P.pitch;
-    const size_t nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1), ncl = (size_t)nx * ny;
+    const size_t nxs = (size_t)ny * (nx + 4), nfy = (size_t)nx * (ny + 1), ncl = (size_t)nx * ny;
     T acc[NF];
 #pragma unroll
     for (int k = 0; k < NF; k++) acc[k] = T(0);
-    for (int it = lane; it < 48 + 9 * 34; it += 64) {
-        if (it < 48) {
-            // face fi (x) or fj (y) within 3 cells, stencil position q
-            const int dir = it / 24, fo = (it % 24) / 4, q = it % 4;
-            const int n = dir == 0 ? nx : ny, self = dir == 0 ? i : j;
-            const int fl = self - 3 + fo;  // face index: face between fl and fl + 1
-            if (fl < -1 || fl > n - 1) continue;
+    for (int it = lane; it < 5 + 24 + 9 * 34; it += 64) {
+        if (it < 5) {
+            // x-face sums: this cell's, then the ghost columns -2, -1, nx, nx+1
+            // when the ghost map sends them here (normal momenta flip at walls)
+            const int g = it == 0 ? i : (it == 1 ? -2 : (it == 2 ? -1 : nx + it - 3));
             int flip = 0;
-            const int m = dir == 0 ? map_index(fl - 1 + q, nx, P.bc[0], P.bc[1], flip)
-                                   : map_index(fl - 1 + q, ny, P.bc[2], P.bc[3], flip);
-            if (m != self) continue;
-            const T* f = dir == 0 ? FCX + ((size_t)j * (nx + 1) + (fl + 1)) : FCY + ((size_t)(fl + 1) * nx + i);
-            const size_t st = dir == 0 ? nfx : nfy;
-            const int kn0 = dir == 0 ? 1 : 2, kn1 = dir == 0 ? 4 : 5;  // normal momenta flip at walls
+            if (it > 0 && map_index(g, nx, P.bc[0], P.bc[1], flip) != i) continue;
+            const T* f = XS + (size_t)j * (nx + 4) + (g + 2);
 #pragma unroll
             for (int k = 0; k < NF; k++) {
-                const T v = f[(6 * q + k) * st];
-                acc[k] += (flip && (k == kn0 || k == kn1)) ? -v : v;
+                const T v = f[k * nxs];
+                acc[k] += (flip && (k == 1 || k == 4)) ? -v : v;
+            }
+        } else if (it < 29) {
+            // y-face fj within 3 rows, stencil position q
+            const int fo = (it - 5) / 4, q = (it - 5) % 4;
+            const int fl = j - 3 + fo;  // face between rows fl and fl + 1
+            if (fl < -1 || fl > ny - 1) continue;
+            int flip = 0;
+            if (map_index(fl - 1 + q, ny, P.bc[2], P.bc[3], flip) != j) continue;
+            const T* f = FCY + ((size_t)(fl + 1) * nx + i);
+#pragma unroll
+            for (int k = 0; k < NF; k++) {
+                const T v = f[(6 * q + k) * nfy];
+                acc[k] += (flip && (k == 2 || k == 5)) ? -v : v;
             }
         } else {
-            const int s2 = it - 48, nb = s2 / 34, sl = s2 % 34;
+            const int s2 = it - 29, nb = s2 / 34, sl = s2 % 34;
             const int ci = i - 1 + nb % 3, cj = j - 1 + nb / 3;
             if (ci < 0 || ci >= nx || cj < 0 || cj >= ny) continue;
             int di, dj, k;

@@ -164,9 +164,10 @@ hipError_t Launch<M2P_REAL>::vjp(const KParams& P, const Bufs& B, const void* U,
     const T* b = (const T*)B.b;
     hipLaunchKernelGGL((k_adj_post<T>), grd, blk, 0, st, P, (const T*)U, (const T*)lam, T(lscale), b,
                        (const T*)B.mu, B.S, stage, T(dt), (T*)GT, (T*)DU, (T*)gmu);
-    // x-face rows 0 .. ny-1, then y-face rows 0 .. ny
-    hipLaunchKernelGGL((k_adj_face<T>), dim3((P.nx + 1 + 127) / 128, 2 * P.ny + 1), blk, 0, st, P, (const T*)U,
-                       (const T*)GT, b, T(dt), (T*)FCX, (T*)FCY);
+    // x-face rows 0 .. ny-1 (two wavefronts per workgroup), then y-face rows 0 .. ny
+    const int nfb = std::max((adj_xwaves(P.nx) + 1) / 2, (P.nx + 127) / 128);
+    hipLaunchKernelGGL((k_adj_face<T>), dim3(nfb, 2 * P.ny + 1), blk, 0, st, P, (const T*)U, (const T*)GT, b, T(dt),
+                       (T*)FCX, (T*)FCY);
     hipLaunchKernelGGL((k_adj_src<T>), grd, blk, 0, st, P, (const T*)U, (const T*)GT, b, T(dt), (T*)SC);
     // interior box (if any) and the edge ring, one launch
     const int nbx = P.nx >= 5 && P.ny >= 5 ? (P.nx - 4 + 127) / 128 : 0;
