@@ -1151,7 +1151,9 @@ struct VjpWork {
         // per-cell x-face sums over the row extended by two ghost columns a side
         if ((rc = FCX.alloc((size_t)K.ny * (K.nx + 4) * NF * c->esz))) return rc;
         if ((rc = FCY.alloc((size_t)(K.ny + 1) * K.nx * 24 * c->esz))) return rc;
-        return SC.alloc((size_t)K.ny * K.nx * 34 * c->esz);
+        // per target column (row extended by a ghost column a side) the source
+        // sums landing level (6 fields), one row up and one row down (4 each)
+        return SC.alloc((size_t)K.ny * (K.nx + 2) * 14 * c->esz);
     }
 };
 

@@ -778,22 +778,17 @@ __device__ __forceinline__ void visc_face_vjp(int d, const T in[10], const Geo<T
 }
 
 // Pass B, sources: cotangent dt * GT_c (momentum components) pulled back
-// through S_c to its 34 input slots, into SC[34][cells].  Chain rule over the
+// through S_c to its 34 input slots (lam[34]).  Chain rule over the
 // structure of cell_sources: the local sources of the cell's six fields and of
 // the two fluid-pressure gradients (8 dual evaluations of sources), the
 // gradients to the neighbours' thicknesses (fluid_G), and the viscous
 // operator through its four face terms, the central differences and the
 // desingularised velocities of the 3 x 3 box.
 template <typename T>
-__global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict__ U, const T* __restrict__ GT,
-                                                 const T* __restrict__ b, T dt, T* __restrict__ SC)
+__device__ __forceinline__ void adj_src_lam(const KParams& P, const T* __restrict__ U, const T* __restrict__ GT,
+                                            const T* __restrict__ b, T dt, int i, int j, T lam[34])
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= P.nx) return;
     const size_t c = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
-    // slot-major: slot q of all cells is contiguous
-    const size_t ncells = (size_t)P.nx * P.ny, cell = (size_t)j * P.nx + i;
     Stencil<T> s;
     load_stencil(P, U, i, j, s);
     const Geo5<T> g5 = geo5(P, b, i, j);
@@ -802,7 +797,6 @@ __global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict_
     using TT = Dual<T>;
     const Consts<TT> K(P);
     const Geo<TT> gW = lift(g5.W), gE = lift(g5.E), gSo = lift(g5.S), gN = lift(g5.N);
-    T lam[34];
     for (int q = 0; q < 34; q++) lam[q] = T(0);
     const T two_dxi = T(P.two_dxi), two_deta = T(P.two_deta);
     TT dn[6];
@@ -974,7 +968,56 @@ __global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict_
             lam[box_slot(ba[q], bc[q], 3)] += lJh[q];
         }
     }
-    for (int q = 0; q < 34; q++) SC[q * ncells + cell] = lam[q];
+}
+
+// Wavefronts of sources per grid row: each covers 60 target columns of the
+// row extended by one ghost column per side (extended column t + 1).
+__host__ __device__ inline int adj_swaves(int nx) { return (nx + 2 + 59) / 60; }
+
+// Pass B, sources, per grid row of source cells: lane l of wavefront w takes
+// source cell c = 60 w - 2 + l (cells outside the grid contribute zeros) and
+// lanes 1..60 sum, for target column t = c (fixed order: own, west neighbour's,
+// east neighbour's slots), what lands on (t, j) [6 fields], on (t, j + 1)
+// and on (t, j - 1) [fields 0, 3, 4, 5 each] into SS[14][ny][nx + 2] at
+// extended column t + 1 (source row j), ghost columns included.
+template <typename T>
+__global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict__ U, const T* __restrict__ GT,
+                                                 const T* __restrict__ b, T dt, T* __restrict__ SS)
+{
+    const int j = (int)blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int w = (int)blockIdx.x * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+    if (w >= adj_swaves(P.nx)) return;  // whole wavefront
+    const int c = 60 * w - 2 + lane;
+    T lam[34];
+    if (c >= 0 && c < P.nx)
+        adj_src_lam(P, U, GT, b, dt, c, j, lam);
+    else
+        for (int q = 0; q < 34; q++) lam[q] = T(0);
+    // every lane of the wavefront takes part in the shuffles.  Slots: 0..5
+    // centre; 6 + 4 n + f neighbour n (E, W, N, S) field (0, 3, 4, 5)[f];
+    // 22 + 3 n + f corner n (NE, NW, SE, SW) field 3 + f.
+    T o[14];
+#pragma unroll
+    for (int k = 0; k < NF; k++) o[k] = lam[k];
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+        const int k = f == 0 ? 0 : 2 + f;  // field 0, 3, 4, 5
+        o[k] = (o[k] + __shfl(lam[6 + f], lane - 1, 64)) + __shfl(lam[10 + f], lane + 1, 64);
+        T up = lam[14 + f], dn = lam[18 + f];
+        if (f > 0) {
+            up = (up + __shfl(lam[22 + f - 1], lane - 1, 64)) + __shfl(lam[25 + f - 1], lane + 1, 64);
+            dn = (dn + __shfl(lam[28 + f - 1], lane - 1, 64)) + __shfl(lam[31 + f - 1], lane + 1, 64);
+        }
+        o[6 + f] = up;
+        o[10 + f] = dn;
+    }
+    const int e = c + 1;
+    if (lane >= 1 && lane <= 60 && e < P.nx + 2) {
+        const size_t nss = (size_t)P.ny * (P.nx + 2), off = (size_t)j * (P.nx + 2) + e;
+#pragma unroll
+        for (int q = 0; q < 14; q++) SS[q * nss + off] = o[q];
+    }
 }
 
 // Pass C: lam_in(k) = DU(k) + all face and source contributions that land on
@@ -986,12 +1029,12 @@ __global__ void __launch_bounds__(128) k_adj_src(KParams P, const T* __restrict_
 template <typename T>
 __device__ __forceinline__ void adj_gather_interior(const KParams& P, const T* __restrict__ DU,
                                                     const T* __restrict__ XS, const T* __restrict__ FCY,
-                                                    const T* __restrict__ SC, const T* z, T zc, T* lam_in, int i,
+                                                    const T* __restrict__ SS, const T* z, T zc, T* lam_in, int i,
                                                     int j)
 {
     const size_t c = (size_t)j * P.pitch + i, fs = (size_t)P.ny * P.pitch;
     // slot-major cotangent arrays (slot stride: number of faces or cells)
-    const size_t nxs = (size_t)P.ny * (P.nx + 4), nfy = (size_t)P.nx * (P.ny + 1), ncl = (size_t)P.nx * P.ny;
+    const size_t nxs = (size_t)P.ny * (P.nx + 4), nfy = (size_t)P.nx * (P.ny + 1), nss = (size_t)P.ny * (P.nx + 2);
     T acc[NF];
     for (int k = 0; k < NF; k++) acc[k] = DU[k * fs + c];
     // No ghost cell maps onto this cell: each contribution comes from a
@@ -1005,26 +1048,18 @@ __device__ __forceinline__ void adj_gather_interior(const KParams& P, const T* _
         const T* f = FCY + ((size_t)(fj + 1) * P.nx + i) + 6 * (j - fj + 1) * nfy;
         for (int k = 0; k < NF; k++) acc[k] += f[k * nfy];
     }
-    // source cell (i - di, j - dj) reads this cell through its slots of offset (di, dj)
-    for (int cj = j - 1; cj <= j + 1; cj++)
-        for (int ci = i - 1; ci <= i + 1; ci++) {
-            const T* f = SC + ((size_t)cj * P.nx + ci);
-            const int di = i - ci, dj = j - cj;
-            if (di == 0 && dj == 0) {
-                for (int k = 0; k < NF; k++) acc[k] += f[k * ncl];
-            } else if (di == 0 || dj == 0) {
-                const int n = dj == 0 ? (di > 0 ? 0 : 1) : (dj > 0 ? 2 : 3);
-                acc[0] += f[(6 + 4 * n) * ncl];
-                acc[3] += f[(6 + 4 * n + 1) * ncl];
-                acc[4] += f[(6 + 4 * n + 2) * ncl];
-                acc[5] += f[(6 + 4 * n + 3) * ncl];
-            } else {
-                const int n = (dj > 0 ? 0 : 2) + (di > 0 ? 0 : 1);
-                acc[3] += f[(22 + 3 * n) * ncl];
-                acc[4] += f[(22 + 3 * n + 1) * ncl];
-                acc[5] += f[(22 + 3 * n + 2) * ncl];
-            }
-        }
+    // sources: what lands on this cell from source rows j, j - 1 (upward) and
+    // j + 1 (downward), each already summed over the three source columns
+    {
+        const size_t o = (size_t)(i + 1);
+        const T* f0 = SS + (size_t)j * (P.nx + 2) + o;
+        const T* fu = SS + (size_t)(j - 1) * (P.nx + 2) + o;
+        const T* fd = SS + (size_t)(j + 1) * (P.nx + 2) + o;
+        for (int k = 0; k < NF; k++) acc[k] += f0[k * nss];
+        const int kk[4] = {0, 3, 4, 5};
+        for (int f = 0; f < 4; f++) acc[kk[f]] += fu[(6 + f) * nss];
+        for (int f = 0; f < 4; f++) acc[kk[f]] += fd[(10 + f) * nss];
+    }
     for (int k = 0; k < NF; k++) lam_in[k * fs + c] = z ? acc[k] + zc * z[k * fs + c] : acc[k];
 }
 
@@ -1044,18 +1079,19 @@ __host__ __device__ inline long long adj_ring_cells(int nx, int ny)
 // 128 cells per row), one thread per cell.  The rest cover the edge ring with
 // one wavefront per ring cell: the lanes share the candidate contributions
 // (the cell's own and the four ghost columns' x-face sums, 24 y-face (face,
-// stencil position) pairs, 9 source cells x 34 slots), keep those the ghost
-// map sends to this cell, and the lanes' partial sums are combined by a fixed
+// stencil position) pairs, and the source sums landing on the 3 x 3 targets
+// (cell or ghost, from the source row below, level or above)), keep those the
+// ghost map sends to this cell, and the lanes' partial sums are combined by a fixed
 // butterfly (deterministic).
 template <typename T>
 __global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restrict__ DU, const T* __restrict__ XS,
-                                                    const T* __restrict__ FCY, const T* __restrict__ SC, const T* z,
+                                                    const T* __restrict__ FCY, const T* __restrict__ SS, const T* z,
                                                     T zc, T* lam_in, int nbi, int nbx)
 {
     if ((int)blockIdx.x < nbi) {
         const int i = 2 + ((int)blockIdx.x % nbx) * 128 + (int)threadIdx.x;
         const int j = 2 + (int)blockIdx.x / nbx;
-        if (i <= P.nx - 3) adj_gather_interior(P, DU, XS, FCY, SC, z, zc, lam_in, i, j);
+        if (i <= P.nx - 3) adj_gather_interior(P, DU, XS, FCY, SS, z, zc, lam_in, i, j);
         return;
     }
     const long long r = ((long long)(blockIdx.x - nbi) * blockDim.x + threadIdx.x) >> 6;
@@ -1079,11 +1115,11 @@ __global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restri
         i = nx <= 4 ? cc : (cc < 2 ? cc : nx - 4 + cc);
     }
     const size_t fs = (size_t)ny * P.pitch;
-    const size_t nxs = (size_t)ny * (nx + 4), nfy = (size_t)nx * (ny + 1), ncl = (size_t)nx * ny;
+    const size_t nxs = (size_t)ny * (nx + 4), nfy = (size_t)nx * (ny + 1), nss = (size_t)ny * (nx + 2);
     T acc[NF];
 #pragma unroll
     for (int k = 0; k < NF; k++) acc[k] = T(0);
-    for (int it = lane; it < 5 + 24 + 9 * 34; it += 64) {
+    for (int it = lane; it < 5 + 24 + 27; it += 64) {
         if (it < 5) {
             // x-face sums: this cell's, then the ghost columns -2, -1, nx, nx+1
             // when the ghost map sends them here (normal momenta flip at walls)
@@ -1110,20 +1146,35 @@ __global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restri
                 acc[k] += (flip && (k == 2 || k == 5)) ? -v : v;
             }
         } else {
-            const int s2 = it - 29, nb = s2 / 34, sl = s2 % 34;
-            const int ci = i - 1 + nb % 3, cj = j - 1 + nb / 3;
-            if (ci < 0 || ci >= nx || cj < 0 || cj >= ny) continue;
-            int di, dj, k;
-            src_slot(sl, di, dj, k);
+            // target (ti, tj) in {i, ghost columns} x {j, ghost rows} of the
+            // source sums: level (source row tj), upward (tj - 1), downward (tj + 1)
+            const int s2 = it - 29, kind = s2 / 9, ti_c = (s2 % 9) % 3, tj_c = (s2 % 9) / 3;
+            const int ti = ti_c == 0 ? i : (ti_c == 1 ? -1 : nx), tj = tj_c == 0 ? j : (tj_c == 1 ? -1 : ny);
             int fx = 0, fy = 0;
-            const int mi = map_index(ci + di, nx, P.bc[0], P.bc[1], fx);
-            const int mj = map_index(cj + dj, ny, P.bc[2], P.bc[3], fy);
-            if (mi != i || mj != j) continue;
-            T v = SC[(size_t)sl * ncl + (size_t)cj * nx + ci];
-            if (fx && (k == 1 || k == 4)) v = -v;
-            if (fy && (k == 2 || k == 5)) v = -v;
+            if (map_index(ti, nx, P.bc[0], P.bc[1], fx) != i || map_index(tj, ny, P.bc[2], P.bc[3], fy) != j) continue;
+            if (ti_c != 0 && ti == i) continue;  // a ghost column never equals the cell
+            const int sr = kind == 0 ? tj : (kind == 1 ? tj - 1 : tj + 1);  // source row
+            if (sr < 0 || sr >= ny) continue;
+            const T* f = SS + (size_t)sr * (nx + 2) + (ti + 1);
+            if (kind == 0) {
 #pragma unroll
-            for (int kk = 0; kk < NF; kk++) acc[kk] += kk == k ? v : T(0);
+                for (int k = 0; k < NF; k++) {
+                    T v = f[k * nss];
+                    if (fx && (k == 1 || k == 4)) v = -v;
+                    if (fy && (k == 2 || k == 5)) v = -v;
+                    acc[k] += v;
+                }
+            } else {
+                const int base = kind == 1 ? 6 : 10;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int k = q == 0 ? 0 : 2 + q;
+                    T v = f[(base + q) * nss];
+                    if (fx && k == 4) v = -v;
+                    if (fy && k == 5) v = -v;
+                    acc[k] += v;
+                }
+            }
         }
     }
 #pragma unroll

@@ -168,7 +168,8 @@ hipError_t Launch<M2P_REAL>::vjp(const KParams& P, const Bufs& B, const void* U,
     const int nfb = std::max((adj_xwaves(P.nx) + 1) / 2, (P.nx + 127) / 128);
     hipLaunchKernelGGL((k_adj_face<T>), dim3(nfb, 2 * P.ny + 1), blk, 0, st, P, (const T*)U, (const T*)GT, b, T(dt),
                        (T*)FCX, (T*)FCY);
-    hipLaunchKernelGGL((k_adj_src<T>), grd, blk, 0, st, P, (const T*)U, (const T*)GT, b, T(dt), (T*)SC);
+    hipLaunchKernelGGL((k_adj_src<T>), dim3((adj_swaves(P.nx) + 1) / 2, P.ny), blk, 0, st, P, (const T*)U,
+                       (const T*)GT, b, T(dt), (T*)SC);
     // interior box (if any) and the edge ring, one launch
     const int nbx = P.nx >= 5 && P.ny >= 5 ? (P.nx - 4 + 127) / 128 : 0;
     const int nbi = nbx * (P.ny >= 5 ? P.ny - 4 : 0);
