@@ -83,6 +83,7 @@ def _load():
         lib.ora_diag.argtypes = [P, dp]
         lib.ora_get_fields.argtypes = [P, dp, dp, dp, dp, dp, dp]
         lib.ora_probe.argtypes = [P, C.c_int, C.c_int, dp]
+        lib.ora_stage_probe.argtypes = [P, C.c_double, dp]
         lib.ora_scales.argtypes = [P, dp]
         lib.ora_set_dt_schedule.argtypes = [P, dp, C.c_int64]
         lib.ora_set_threads.restype = C.c_int
@@ -201,6 +202,13 @@ class OracleSim:
         out = np.zeros(34)
         _load().ora_probe(self._h, int(i), int(j), _ptr(out))
         return out
+
+    def stage_probe(self, dt) -> np.ndarray:
+        """One forward-Euler stage E(U) of the current state with step dt (s),
+        raw layout [6, ny, nx]; the simulation itself does not advance."""
+        E = np.empty((6, self.ny, self.nx), dtype=np.float64)
+        _load().ora_stage_probe(self._h, float(dt), _ptr(E))
+        return E
 
     def scales(self) -> dict:
         out = np.zeros(7)

@@ -1163,6 +1163,20 @@ void ora_probe(ora_sim *o, int i, int j, double out[34])
     out[k++] = S.svis[0]; out[k++] = S.svis[1];
 }
 
+/* Probe for tests: one forward-Euler stage E(U) of the scheme (Sect. 2.2) from
+ * the current state at the current time with the step dt (s), written to
+ * Uout (raw layout, 6 * nx * ny).  The state, time, counters and boundary
+ * integrals are left as they were. */
+void ora_stage_probe(ora_sim *o, double dt_si, double *Uout)
+{
+    int64_t clamps = o->clamps;
+    double bf[3][2];
+    memcpy(bf, o->bflux, sizeof bf);
+    stage(o, o->U, Uout, dt_si / o->T, o->t, 0);
+    o->clamps = clamps;
+    memcpy(o->bflux, bf, sizeof bf);
+}
+
 /* Scales for tests: eps, alpha, T (s), V (m/s), dxi, deta, md. */
 void ora_scales(const ora_sim *o, double out[7])
 {

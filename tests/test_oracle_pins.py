@@ -852,3 +852,173 @@ def test_overlapping_inflow_segments_rejected():
                      inflow_states=[_state_seg(0, 2, 5, 1.0, 0.5, 1.0), _state_seg(0, 6, 3, 1.0, 0.5, 1.0)])
     with pytest.raises(ValueError):
         _sim(prob)
+
+
+# ------------------------------------------- discharge inflow face (Mode-II)
+
+def _dry_inflow(side, Q, phi, ncells=4, i0=3, n=(12, 10), dx=5.0, dy=5.0, params=None):
+    nx, ny = n
+    p = params or I.Params(delta_b_deg=0.0, inv_n_r=0.0, theta_b=0.0, bc=(1, 1, 1, 1))
+    seg = I.Inflow(side, i0, ncells, np.array([0.0, 1e6]), np.array([Q, Q]), np.array([phi, phi]))
+    z = np.zeros((ny, nx))
+    return _sim(I.Problem("inflow-face", nx, ny, dx, dy, p, z, z, z.copy(), [seg]))
+
+
+@pytest.mark.parametrize("side", [I.SIDE_W, I.SIDE_E, I.SIDE_S, I.SIDE_N])
+def test_discharge_inflow_first_stage_closed_form(side):
+    """One forward-Euler stage over a dry flat bed (no friction) with a constant
+    discharge Q on a boundary segment: only the segment's boundary cells change,
+    by dt/dx times the face flux of the critical-depth state of the unit
+    discharge q = Q / (n dx), h_in = (q^2 / g)^(1/3), v_in = q / h_in (Froude
+    number 1; the Mode-II reading of Sect. 3.1.2 Stage 0), split by the solid
+    fraction: mass phi q and (1 - phi) q; normal momentum phi q v_in +
+    g (1 - alpha) phi h_in^2 / 2 (solid) and (1 - phi) q v_in + g h_in^2 / 2
+    (fluid: its pressure carries the mixture thickness), directed inward, and
+    no tangential momentum.  Pins the discharge split, the critical state,
+    the momentum flux and the orientation on all four sides."""
+    Q, phi, nc, i0 = 40.0, 0.4, 4, 3
+    dx = dy = 5.0
+    s = _dry_inflow(side, Q, phi, nc, i0, dx=dx, dy=dy)
+    sc = s.scales()
+    H, V, al, g = 10.0, sc["V"], sc["alpha"], 9.81
+    dt = 0.05
+    E = s.stage_probe(dt)
+    q = Q / (nc * (dy if side < 2 else dx))
+    h_in = (q * q / g) ** (1.0 / 3.0)
+    v_in = q / h_in
+    w = dx if side < 2 else dy              # cell width across the face
+    inward = 1.0 if side in (I.SIDE_W, I.SIDE_S) else -1.0
+    mom_s = phi * q * v_in + g * (1 - al) * phi * h_in ** 2 / 2
+    mom_f = (1 - phi) * q * v_in + g * h_in ** 2 / 2
+    nx, ny = s.nx, s.ny
+    cells = [(0 if side == I.SIDE_W else nx - 1, k) if side < 2 else (k, 0 if side == I.SIDE_S else ny - 1)
+             for k in range(i0, i0 + nc)]
+    normal, tang = (1, 2) if side < 2 else (2, 1)
+    expect = np.zeros_like(E)
+    for (i, j) in cells:
+        expect[0, j, i] = dt * phi * q / w / H
+        expect[3, j, i] = dt * (1 - phi) * q / w / H
+        expect[normal, j, i] = inward * dt * mom_s / w / (H * V)
+        expect[normal + 3, j, i] = inward * dt * mom_f / w / (H * V)
+    assert np.all(E[tang] == 0.0) and np.all(E[tang + 3] == 0.0)
+    np.testing.assert_allclose(E, expect, rtol=1e-13, atol=0.0)
+
+
+def test_discharge_inflow_first_cfl_step():
+    """Over a dry domain with a discharge segment the first CFL step is set by
+    the critical inflow state, dt = CFL dx / (v_in + sqrt(g h_in)) = CFL dx /
+    (2 sqrt(g h_in)), unless the speed floor a_min in the other direction
+    binds; with Q = 0 only the floor is left."""
+    for side, dx, dy in ((I.SIDE_W, 5.0, 5.0), (I.SIDE_N, 4.0, 6.0)):
+        Q, nc = 10.0, 4
+        s = _dry_inflow(side, Q, 0.5, nc, dx=dx, dy=dy)
+        q = Q / (nc * (dy if side < 2 else dx))
+        h_in = (q * q / 9.81) ** (1.0 / 3.0)
+        a = q / h_in + math.sqrt(9.81 * h_in)
+        d_along = dx if side < 2 else dy        # the flux crosses faces normal to this spacing
+        d_other = dy if side < 2 else dx
+        expect = 0.1 * min(d_along / a, d_other / 1.0)
+        assert abs(s.peek_dt() - expect) <= 1e-14 * expect
+        s0 = _dry_inflow(side, 0.0, 0.5, nc, dx=dx, dy=dy)
+        assert abs(s0.peek_dt() - 0.1 * min(dx, dy)) <= 1e-14
+
+
+# ------------------------------------------------ lift-off on a convex crest
+
+def _crest(v, delta_b=16.0, R=200.0, nx=41, ny=5, dx=5.0):
+    X, _ = I.cell_centres(nx, ny, dx, dx)
+    xc = X[0, nx // 2]
+    dem = -(X - xc) ** 2 / (2 * R)
+    vel = (np.full((ny, nx), v), np.zeros((ny, nx)), np.full((ny, nx), v), np.zeros((ny, nx)))
+    p = I.Params(delta_b_deg=delta_b)
+    prob = I.Problem("crest", nx, ny, dx, dx, p, dem, np.full((ny, nx), 3.0), np.full((ny, nx), 0.5), vel=vel)
+    return _sim(prob), X, xc
+
+
+def test_basal_pressure_lift_off_on_crest():
+    """On the crest b = -X^2 / (2R) the centripetal term is +v^2 / (R s) (the
+    mirror of the valley's -v^2 / (R s)).  Slow flow: s_n,X = m (x/R)
+    ((1 - alpha) - v^2 / R) / s^2 for the solid (without (1 - alpha) for the
+    fluid; n_X = x / (R s) points downhill away from the crest).  Fast flow with v^2 / R above (1 - alpha) (solid) and 1 (fluid),
+    in units of g: the basal pressure would be negative, the bed cannot pull,
+    so p_b = 0 and s_n = 0 exactly (the lift-off reading of the basal
+    pressure, Appendix A)."""
+    R = 200.0
+    slow, X, xc = _crest(20.0, R=R)
+    sc = slow.scales()
+    i = 26
+    x, Rn = (X[0, i] - xc) / 1000.0, R / 1000.0
+    sl = math.sqrt(1 + (x / Rn) ** 2)
+    v = 20.0 / sc["V"]
+    ms = 0.5 * 3.0 / 10.0
+    pr = slow.probe(i, 2)
+    assert abs(pr[16] - v * v / (Rn * sl)) <= 5 * (5.0 / R) ** 2 * abs(pr[16])
+    exp_s = ms * (x / Rn) * ((1 - sc["alpha"]) - v * v / Rn) / sl ** 2
+    exp_f = ms * (x / Rn) * (1.0 - v * v / Rn) / sl ** 2
+    assert exp_s > 0 and exp_f > 0          # still pressed onto the bed
+    assert abs(pr[18] - exp_s) <= 5 * (5.0 / R) ** 2 * abs(exp_s)
+    assert abs(pr[20] - exp_f) <= 5 * (5.0 / R) ** 2 * abs(exp_f)
+    fast, _, _ = _crest(60.0, R=R)          # v^2 / (g R) = 1.83
+    for i in (17, 19, 22, 26):
+        pr = fast.probe(i, 2)
+        assert pr[16] > (1.0 - sc["alpha"]) and pr[17] > 1.0
+        assert pr[18] == 0.0 and pr[19] == 0.0 and pr[20] == 0.0 and pr[21] == 0.0
+
+
+def test_coulomb_friction_vanishes_at_lift_off():
+    """The Coulomb stop-clamp's basal pressure is clamped like s_n: on the crest
+    with fast flow a stage with delta_b = 30 deg equals the stage with
+    delta_b = 0 bitwise in every lifted-off cell, while in slow flow the
+    friction removes momentum."""
+    dt = 0.02
+    fast30, _, _ = _crest(60.0, delta_b=30.0)
+    fast0, _, _ = _crest(60.0, delta_b=0.0)
+    E30, E0 = fast30.stage_probe(dt), fast0.stage_probe(dt)
+    lifted = [i for i in range(4, 37) if fast30.probe(i, 2)[16] > 1.0]
+    assert len(lifted) >= 20
+    for i in lifted:
+        assert np.array_equal(E30[:, 2, i], E0[:, 2, i])
+    slow30, _, _ = _crest(20.0, delta_b=30.0)
+    slow0, _, _ = _crest(20.0, delta_b=0.0)
+    E30, E0 = slow30.stage_probe(dt), slow0.stage_probe(dt)
+    assert np.all(np.abs(E30[1, 2, 4:37]) < np.abs(E0[1, 2, 4:37]))
+
+
+# ------------------------------------------------------- a massless phase
+
+def test_massless_fluid_carries_no_momentum():
+    """A pure-solid release (phi^s = 1) with rho_f > 0 flowing down a bumpy
+    plane: the fluid's flux and interphase-pressure source see the mixture
+    thickness, but a phase without mass carries no momentum (the reading of
+    the positivity step), so the fluid momentum stays exactly 0 in every cell
+    while the solid moves."""
+    prob = I.plane_bump_pile(n=48)
+    prob.phi_s = np.where(prob.h_vert > 0, 1.0, 0.0)
+    s = _sim(prob)
+    s.run(60)
+    U = s.state()
+    assert np.max(np.abs(U[1])) > 1e-2
+    assert np.all(U[3] == 0.0) and np.all(U[4] == 0.0) and np.all(U[5] == 0.0)
+    assert s.diag()["clamps"] == 0
+
+
+# -------------------------------------- earth-pressure bound of the CFL step
+
+@pytest.mark.parametrize("delta_b,delta_int,K", [
+    (0.0, 35.0, (1 + math.sin(math.radians(35.0))) / (1 - math.sin(math.radians(35.0)))),
+    (30.0, 30.0, 1.0 / (1 - math.sin(math.radians(30.0)))),
+])
+def test_earth_pressure_cfl_uses_the_passive_bound(delta_b, delta_int, K):
+    """With the earth-pressure option the CFL step bounds the solid's pressure
+    speed with the largest coefficient a cell can take (passive along both
+    directions).  A resting pure-solid layer (rho_f = 0) on a flat bed:
+    dt = CFL dx / sqrt(K g h) with the Rankine passive coefficient
+    (1 + sin d)/(1 - sin d) at delta_b = 0 and 1/(1 - sin d) at
+    delta_b = delta_int (closed forms of the Savage-Hutter coefficients)."""
+    n, dx, h = 8, 10.0, 4.0
+    p = I.Params(delta_b_deg=delta_b, delta_int_deg=delta_int, rho_f=0.0, inv_n_r=0.0,
+                 flags=I.F_EARTH_PRESSURE)
+    z = np.zeros((n, n))
+    s = _sim(I.Problem("ep-dt", n, n, dx, dx, p, z, np.full((n, n), h), np.ones((n, n))))
+    expect = 0.1 * dx / math.sqrt(K * 9.81 * h)
+    assert abs(s.peek_dt() - expect) <= 1e-13 * expect
