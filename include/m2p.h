@@ -294,7 +294,8 @@ int m2p_stage_flops(int32_t stage, int32_t visc, double *out);
  * cellsize), the lower-left cell corner (x0, y0; may be NULL) and the NODATA
  * value (NaN when the file has none; may be NULL).  values (host, capacity
  * doubles) may be NULL to read the header only; NODATA cells are returned as
- * stored.  Errors: M2P_EIO (open), M2P_EINVAL (malformed header, too few or
+ * NaN, so a grid with missing cells cannot reach m2p_create or m2p_set_state
+ * unnoticed (both reject non-finite values): fill them explicitly first.  Errors: M2P_EIO (open), M2P_EINVAL (malformed header, too few or
  * too many values, capacity < nx*ny). */
 int m2p_esri_read(const char *path, m2p_grid *g, double *x0, double *y0, double *nodata, double *values,
                   size_t capacity);

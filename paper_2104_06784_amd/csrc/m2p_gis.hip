@@ -102,11 +102,16 @@ extern "C" int m2p_esri_read(const char* path, m2p_grid* g, double* x0, double* 
             } else {
                 for (long r = 0; r < h.nrows && rc == M2P_OK; r++) {
                     double* row = values + (size_t)(h.nrows - 1 - r) * h.ncols;  // file row 0 is the north edge
-                    for (long c = 0; c < h.ncols; c++)
+                    for (long c = 0; c < h.ncols; c++) {
                         if (std::fscanf(f, " %lf", &row[c]) != 1) {
                             rc = m2p::fail(M2P_EINVAL, "ESRI grid: fewer values than ncols * nrows");
                             break;
                         }
+                        // a cell without data is NaN, never a number: a DEM or
+                        // a thickness holding one is rejected by m2p_create /
+                        // m2p_set_state instead of becoming a pit of -9999 m
+                        if (h.has_nodata && row[c] == h.nodata) row[c] = NAN;
+                    }
                 }
                 double extra;
                 if (rc == M2P_OK && std::fscanf(f, " %lf", &extra) == 1)

@@ -18,7 +18,8 @@ from . import _abi as A
 
 def read_esri_ascii(path: str):
     """Return (values [ny, nx], info) with info = {dx, x0, y0, nodata}; x0, y0
-    is the lower-left cell corner, nodata is NaN when the file has none."""
+    is the lower-left cell corner, nodata is NaN when the file has none.  Cells
+    holding the NODATA value come back as NaN."""
     L = A.lib()
     g = A.Grid()
     x0, y0, nd = C.c_double(), C.c_double(), C.c_double()
@@ -37,3 +38,28 @@ def write_esri_ascii(path: str, values, dx: float, x0: float = 0.0, y0: float = 
     g = A.Grid(v.shape[1], v.shape[0], float(dx), float(dx))
     A.check(A.lib().m2p_esri_write(os.fsencode(path), C.byref(g), float(x0), float(y0), float(nodata), A.dptr(v)),
             "m2p_esri_write")
+
+
+def read_dem(path: str, fill=None):
+    """Read a DEM grid for ``m2p_create``.  Cells without data are an error
+    unless ``fill`` says how to fill them: a number (metres), or "nearest"
+    (the value of the nearest cell with data, by grid distance).  Returns
+    (dem [ny, nx], info) as :func:`read_esri_ascii`."""
+    dem, info = read_esri_ascii(path)
+    miss = ~np.isfinite(dem)
+    if not miss.any():
+        return dem, info
+    if fill is None:
+        raise ValueError(f"{path}: {int(miss.sum())} cells without data; pass fill= a value or 'nearest'")
+    if miss.all():
+        raise ValueError(f"{path}: no cell has data")
+    if fill == "nearest":
+        from scipy import ndimage
+        _, (jj, ii) = ndimage.distance_transform_edt(miss, return_indices=True)
+        return dem[jj, ii], info
+    v = float(fill)
+    if not math.isfinite(v):
+        raise ValueError("fill value must be finite")
+    out = dem.copy()
+    out[miss] = v
+    return out, info

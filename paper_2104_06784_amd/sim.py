@@ -1,7 +1,8 @@
 """Python wrapper of one scenario context (argument marshalling over the C ABI).
 
 ``Sim`` owns an ``m2p_ctx``.  PyTorch, when given, supplies only device memory
-(``bind_torch``) and the HIP stream; the step itself runs in ``libm2p.so``.
+(``buffers=``: two tensors that become the state buffers through
+``m2p_bind_buffers``) and the HIP stream; the step itself runs in ``libm2p.so``.
 """
 from __future__ import annotations
 
@@ -22,12 +23,17 @@ class Sim:
 
     ``prob`` is an ``inputs.Problem``; ``precision`` "f64" or "f32" (default:
     the problem's).  ``stream`` is an optional ``torch.cuda.Stream``.
+    ``buffers`` is an optional pair of contiguous CUDA tensors, each at least
+    ``Sim.buffer_bytes`` long and 256-byte aligned, that hold the two state
+    buffers instead of context-owned memory (they must outlive the Sim; the
+    current state U^n is in the first after every step, [6][ny][pitch] in the
+    context precision).
     """
 
     FIELDS = ("h", "phi_s", "vxs", "vys", "vxf", "vyf")
 
     def __init__(self, prob, precision=None, stream=None, params=None, variant=A.M2P_VARIANT_AUTO,
-                 tile_rows=0, set_state=True):
+                 tile_rows=0, set_state=True, buffers=None):
         L = A.lib()
         self.prob = prob
         self.nx, self.ny = prob.nx, prob.ny
@@ -45,6 +51,8 @@ class Sim:
         self._keep = []
         if variant != A.M2P_VARIANT_AUTO or tile_rows:
             self.set_variant(variant, tile_rows)
+        if buffers is not None:
+            self.bind_buffers(*buffers)
         if set_state:
             self.set_state(prob.h_vert, prob.phi_s, vertical=True, vel=prob.vel)
             if prob.inflows:
@@ -62,6 +70,27 @@ class Sim:
         self.close()
 
     # -- set-up
+    @staticmethod
+    def buffer_bytes(nx, ny, precision="f64") -> int:
+        """Bytes of one state buffer (6 fields of ny rows of nx rounded up to 64)."""
+        out = C.c_size_t()
+        g = A.Grid(int(nx), int(ny), 1.0, 1.0)
+        prec = A.M2P_FP64 if precision == "f64" else A.M2P_FP32
+        A.check(A.lib().m2p_buffer_bytes(C.byref(g), prec, C.byref(out)), "m2p_buffer_bytes")
+        return out.value
+
+    def bind_buffers(self, a, b):
+        """Make two caller-owned device tensors the state buffers (m2p_bind_buffers)."""
+        need = self.buffer_bytes(self.nx, self.ny, "f64" if self.prec == A.M2P_FP64 else "f32")
+        for t in (a, b):
+            if not (t.is_cuda and t.is_contiguous()):
+                raise ValueError("state buffers must be contiguous device tensors")
+            if t.numel() * t.element_size() < need:
+                raise ValueError(f"state buffer of {t.numel() * t.element_size()} bytes, {need} needed")
+        A.check(A.lib().m2p_bind_buffers(self._h, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), need),
+                "m2p_bind_buffers")
+        self._keep += [a, b]
+
     def set_variant(self, variant, tile_rows=0):
         A.check(A.lib().m2p_set_variant(self._h, variant, tile_rows), "m2p_set_variant")
 
