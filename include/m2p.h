@@ -324,6 +324,20 @@ int m2p_set_dt_schedule(m2p_ctx *c, const double *dts, int64_t n);
  * target host ny*nx). */
 int m2p_loss(m2p_ctx *c, const double *target_h, double *loss);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight calibration or serving loops, harnesses that forbid
+ * hipMalloc: the loss of m2p_loss with nothing allocated and no host
+ * synchronization.  target_dev: device FP64 [ny][nx] target bed-normal
+ * thickness (m), caller-owned; loss_dev: device FP64 scalar that receives
+ * 1/2 sum (h - h_target)^2 dx dy (the same bits as m2p_loss).  Enqueued on
+ * the context's stream.  The kernels' 1024 per-block partial sums live in a
+ * library-owned device array of 2048 doubles (16 KiB) on each GPU, held until
+ * the process ends and shared by every call on that GPU: calls that overlap
+ * on one GPU (other streams or threads) race.  Any grid size fits (the
+ * partial count does not depend on it).  Errors: EINVAL (NULL argument),
+ * ESTATE (no state), EHIP. */
+int m2p_loss_noalloc(m2p_ctx *c, const double *target_dev, double *loss_dev);
+
 /* One forward-Euler stage E at the current state with the next step's dt and
  * the inflow state of stage 0 or 1: E(U) and its directional derivative along
  * dU (and along dmu, the friction field, if not NULL); host [6][ny][nx] raw

@@ -106,6 +106,7 @@ SIGNATURES = {
     "m2p_set_friction_field": (C.c_int, [_P, _dp]),
     "m2p_set_dt_schedule": (C.c_int, [_P, _dp, C.c_int64]),
     "m2p_loss": (C.c_int, [_P, _dp, _dp]),
+    "m2p_loss_noalloc": (C.c_int, [_P, _P, _P]),
     "m2p_stage_jvp": (C.c_int, [_P, C.c_int32, _dp, _dp, _dp, _dp]),
     "m2p_stage_vjp": (C.c_int, [_P, C.c_int32, _dp, _dp, _dp]),
     "m2p_adjoint_run": (C.c_int, [_P, C.c_int64, C.c_int32, _dp, C.c_double, _dp, _dp, _dp]),

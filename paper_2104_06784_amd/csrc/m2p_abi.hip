@@ -9,6 +9,7 @@
 #include <cstring>
 #include <algorithm>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -87,7 +88,51 @@ struct m2p_ctx {
     size_t ev_used = 0;
     double prof_ms[3] = {0, 0, 0};
     int64_t prof_n = 0;
+    double* scratch = nullptr;  // device address of this device's scratch array (m2p_loss_noalloc)
 };
+
+// ------------------------------------------- scratch of the allocation-free loss
+//
+// m2p_loss_noalloc keeps the loss kernel's per-block partial sums in a fixed
+// device array (16 KiB on every GPU the library runs on, held until the
+// process ends) instead of context memory or a hipMalloc.  In host code the
+// array's name is a host-side stand-in, never a device address: its address
+// on a device comes from hipGetSymbolAddress, looked up once per device with
+// that device current, and only that address reaches kernels.
+constexpr int kScratchDoubles = 2048;
+static_assert(kMassBlocks <= kScratchDoubles, "the loss kernel's partial sums must fit the scratch array");
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the scratch array on device dev (the current device).
+static int scratch_address(int dev, double** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(M2P_EINVAL, "device index outside the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return M2P_OK;
+}
+
+// Sum of part[0 .. n) by one thread in index order: the same additions in the
+// same order as the host sum of m2p_loss, so both give the same bits.
+__global__ void __launch_bounds__(64) k_sum_in_order(const double* __restrict__ part, int n, double* __restrict__ out)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double acc = 0.0;
+    for (int q = 0; q < n; q++) acc += part[q];
+    *out = acc;
+}
 
 // One part of a step on the buffers B (the context's, or the same with other
 // state pointers).
@@ -476,6 +521,8 @@ int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t pr
     c->B.wpart = c->wpart;
     c->B.tables = c->tables;
     c->B.mass_part = c->mass_part;
+    // this device's scratch array (the context's device is current here)
+    if ((rc = scratch_address(c->dev, &c->scratch)) != M2P_OK) return cleanup(rc);
     *out = c;
     return M2P_OK;
 }
@@ -1282,6 +1329,23 @@ int m2p_loss(m2p_ctx* c, const double* target_h, double* loss)
     if ((rc = tgt.alloc(n * 8)) || (rc = lam.alloc(c->state_bytes))) return rc;
     HIPCHK(hipMemcpy(tgt.p, target_h, n * 8, hipMemcpyHostToDevice));
     return L_loss(c, (const double*)tgt.p, lam.p, loss);
+}
+
+int m2p_loss_noalloc(m2p_ctx* c, const double* target_dev, double* loss_dev)
+{
+    if (!c || !target_dev || !loss_dev) return fail(M2P_EINVAL, "NULL argument");
+    if (!c->has_state) return fail(M2P_ESTATE, "no state");
+    if (!c->scratch) return fail(M2P_ESTATE, "scratch array not set up");
+    // partials: one per block of the loss kernel (kMassBlocks, checked to fit
+    // the scratch array at compile time); no lam output
+    hipError_t e = c->prec == M2P_FP64
+                       ? Launch<double>::loss(c->kp, c->B, c->B.U, target_dev, nullptr, c->scratch, c->stream)
+                       : Launch<float>::loss(c->kp, c->B, c->B.U, target_dev, nullptr, c->scratch, c->stream);
+    HIPCHK(e);
+    hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(64), 0, c->stream, (const double*)c->scratch, kMassBlocks,
+                       loss_dev);
+    HIPCHK(hipGetLastError());
+    return M2P_OK;
 }
 
 int m2p_stage_jvp(m2p_ctx* c, int32_t stage, const double* dU, const double* dmu, double* E, double* dE)

@@ -1191,8 +1191,9 @@ __global__ void __launch_bounds__(128) k_adj_gather(KParams P, const T* __restri
     }
 }
 
-// Loss 1/2 sum (h - h_target)^2 dx dy (h bed-normal, m) and its cotangent
-// with respect to the state (m^s and m^f entries); FP64 partial sums per block.
+// Loss 1/2 sum (h - h_target)^2 dx dy (h bed-normal, m) and, if lam is not
+// null, its cotangent with respect to the state (m^s and m^f entries); FP64
+// partial sums per block.
 template <typename T>
 __global__ void __launch_bounds__(256) k_loss(KParams P, const T* __restrict__ U, const T* __restrict__ b,
                                               const double* __restrict__ target, T* __restrict__ lam,
@@ -1210,10 +1211,12 @@ __global__ void __launch_bounds__(256) k_loss(KParams P, const T* __restrict__ U
         const double h = ((double)U[c] + (double)U[3 * fs + c]) / g.J * P.H;
         const double r = h - target[q];
         acc += 0.5 * r * r * P.dx * P.dy;
-        const double gm = r * P.dx * P.dy * P.H / g.J;
-        for (int k = 0; k < NF; k++) lam[k * fs + c] = T(0);
-        lam[c] = T(gm);
-        lam[3 * fs + c] = T(gm);
+        if (lam) {  // the loss alone is asked for without it
+            const double gm = r * P.dx * P.dy * P.H / g.J;
+            for (int k = 0; k < NF; k++) lam[k * fs + c] = T(0);
+            lam[c] = T(gm);
+            lam[3 * fs + c] = T(gm);
+        }
     }
     sh[tid] = acc;
     __syncthreads();
