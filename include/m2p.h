@@ -80,6 +80,14 @@ extern "C" {
                        releases on single-scenario contexts, run by the reference kernel; not with the tangent and
                        adjoint calls */
 
+#define M2P_F_SMOOTH_FRICTION 16 /* smooth Coulomb friction, for finite-difference checks of gradients (the
+                       stop-clamp of the paper's friction term has a kink at rest): after the tentative
+                       update the solid momentum is scaled by r / (r + F), F = dt J_b p_b tan(delta_b) the
+                       Coulomb impulse and r = sqrt(|p_3D|^2 + (m^s v_eps)^2), a regularised form of
+                       -F v / sqrt(|v|^2 + v_eps^2) that never reverses the flow; a layer below the
+                       friction angle creeps instead of resting.  Needs v_eps > 0; single-scenario
+                       contexts, run by the reference kernel; differentiated by the tangent and adjoint */
+
 /* thickness convention of m2p_set_state */
 #define M2P_DEPTH_NORMAL 0   /* h measured normal to the bed (the paper's h, Sect. 2.1) */
 #define M2P_DEPTH_VERTICAL 1 /* vertical thickness */
@@ -112,6 +120,7 @@ typedef struct {
     double a_min;         /* floor of the CFL wave speed (m/s) */
     int32_t bc[4];        /* M2P_BC_* for W, E, S, N */
     int32_t flags;        /* M2P_F_* */
+    double v_eps;         /* regularisation speed (m/s) of M2P_F_SMOOTH_FRICTION (> 0 with it; else unused) */
 } m2p_params;
 
 /* One Mode-II inflow segment (Sect. 3.1.2, Stage 0; Sect. 4.2): ncells

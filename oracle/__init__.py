@@ -36,7 +36,8 @@ class _Params(C.Structure):
                 ("theta_b", C.c_double), ("rho_s", C.c_double), ("rho_f", C.c_double),
                 ("cfl", C.c_double), ("L", C.c_double), ("H", C.c_double), ("chi", C.c_double),
                 ("g", C.c_double), ("m_dry", C.c_double), ("a_min", C.c_double),
-                ("bc", C.c_int32 * 4), ("flags", C.c_int32), ("delta_int_deg", C.c_double)]
+                ("bc", C.c_int32 * 4), ("flags", C.c_int32), ("delta_int_deg", C.c_double),
+                ("v_eps", C.c_double)]
 
 
 class _InflowState(C.Structure):
@@ -84,6 +85,8 @@ def _load():
         lib.ora_get_fields.argtypes = [P, dp, dp, dp, dp, dp, dp]
         lib.ora_probe.argtypes = [P, C.c_int, C.c_int, dp]
         lib.ora_stage_probe.argtypes = [P, C.c_double, dp]
+        lib.ora_cbrt_nearest.restype = C.c_double
+        lib.ora_cbrt_nearest.argtypes = [C.c_double]
         lib.ora_scales.argtypes = [P, dp]
         lib.ora_set_dt_schedule.argtypes = [P, dp, C.c_int64]
         lib.ora_set_threads.restype = C.c_int
@@ -94,6 +97,11 @@ def _load():
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def cbrt_nearest(x: float) -> float:
+    """The oracle's cube root of the critical depth (test probe)."""
+    return _load().ora_cbrt_nearest(float(x))
 
 
 def set_threads(n: int) -> int:
@@ -111,7 +119,7 @@ class OracleSim:
         self.nx, self.ny = prob.nx, prob.ny
         cp = _Params(prob.nx, prob.ny, prob.dx, prob.dy, p.delta_b_deg, p.c_d, p.inv_n_r, p.theta_b,
                      p.rho_s, p.rho_f, p.cfl, p.L, p.H, p.chi, p.g, p.m_dry, p.a_min,
-                     (C.c_int32 * 4)(*p.bc), p.flags, p.delta_int_deg)
+                     (C.c_int32 * 4)(*p.bc), p.flags, p.delta_int_deg, p.v_eps)
         dem = np.ascontiguousarray(prob.dem, dtype=np.float64)
         mu = None if prob.tan_mu is None else np.ascontiguousarray(prob.tan_mu, dtype=np.float64)
         self._h = lib.ora_create(C.byref(cp), _ptr(dem), _ptr(mu))

@@ -14,8 +14,10 @@
  * CFL-limited time step.  Readings chosen where the paper is silent are marked
  * "reading:"; the same readings are followed by the HIP path.  Options beside
  * the paper's choices (params.flags): the three-stage SSP Runge-Kutta method,
- * the central-upwind face flux with one-sided speeds, and Savage-Hutter
- * earth-pressure coefficients from the internal friction angle.
+ * the central-upwind face flux with one-sided speeds, Savage-Hutter
+ * earth-pressure coefficients from the internal friction angle, and a
+ * smooth (regularised) Coulomb friction for finite-difference checks of
+ * gradients.
  *
  * Units: SI at the interface; inside, the shallow scaling X, Y, b ~ L,
  * h ~ H, v ~ sqrt(g L), t ~ sqrt(L / g), aspect ratio eps = H / L.
@@ -44,8 +46,10 @@ typedef struct {
     int32_t flags; /* bit 0: fluid interphase pressure weighted by phi^f as printed;
                       bit 1: three-stage third-order SSP Runge-Kutta instead of Heun;
                       bit 2: central-upwind face flux (one-sided local speeds);
-                      bit 3: Savage-Hutter earth-pressure coefficients on the solid pressure */
+                      bit 3: Savage-Hutter earth-pressure coefficients on the solid pressure;
+                      bit 4: smooth Coulomb friction with regularisation speed v_eps */
     double delta_int_deg; /* internal friction angle (used with bit 3) */
+    double v_eps;         /* m/s (used with bit 4) */
 } ora_params;
 
 typedef struct {
@@ -198,6 +202,7 @@ static void geometry_at(const ora_sim *o, int i, int j, geo_t *g)
 ora_sim *ora_create(const ora_params *p, const double *dem, const double *tan_mu)
 {
     if (p->nx < 2 || p->ny < 2) return NULL;
+    if ((p->flags & 16) && !(p->v_eps > 0.0)) return NULL;
     if (p->flags & 8) {
         /* earth pressure needs delta_b <= delta_int < 90 deg everywhere */
         if (!(p->delta_int_deg >= 0.0 && p->delta_int_deg < 90.0) || p->delta_b_deg > p->delta_int_deg) return NULL;
@@ -498,6 +503,45 @@ static double interp(const double *t, const double *y, int n, double tau)
     return y[k] + w * (y[k + 1] - y[k]);
 }
 
+/* Cube root of x > 0 rounded to the double whose cube lies nearest to x:
+ * from the library's cbrt(x) (a few units in the last place off, and
+ * differently so on other platforms) step to the neighbour with the smaller
+ * exact residual |y^3 - x| until neither neighbour is smaller (the residual
+ * is unimodal in y, so every start ends on the same double).  It is formed with
+ * error-free products (y^2 = p + e, y p = q + f exactly by fused
+ * multiply-add; q - x is exact because q and x are within a factor of two),
+ * which leaves only the tiny y e term rounded. */
+static double cube_residual(double y, double x)
+{
+    double p = y * y;
+    double e = fma(y, y, -p);
+    double q = y * p;
+    double f = fma(y, p, -q);
+    double g = y * e;
+    return ((q - x) + f) + g;
+}
+
+static double cbrt_nearest(double x)
+{
+    double y = cbrt(x);
+    if (!(x > 0.0) || !isfinite(x)) return y;
+    double r = fabs(cube_residual(y, x));
+    for (int it = 0; it < 16; it++) {
+        double lo = nextafter(y, 0.0), hi = nextafter(y, INFINITY);
+        double rl = fabs(cube_residual(lo, x)), rh = fabs(cube_residual(hi, x));
+        if (rl < r) {
+            y = lo;
+            r = rl;
+        } else if (rh < r) {
+            y = hi;
+            r = rh;
+        } else {
+            break;
+        }
+    }
+    return y;
+}
+
 /* reading: the inflow segment imposes the boundary face flux.  The discharge
  * per unit width q = Q / (ncells * face length) enters as a critical-depth
  * state (Froude number 1 over a flat bed): m_in = (q^2 / eps)^(1/3),
@@ -511,7 +555,7 @@ static void inflow_state(const ora_sim *o, const inflow_seg *s, double tau_nd,
     double w = (s->side < 2) ? o->p.dy : o->p.dx;
     double qs = Q / ((double)s->ncells * w);    /* m^2/s */
     double qn = qs / (o->p.H * o->V);            /* dimensionless */
-    double m = cbrt(qn * qn / o->eps);
+    double m = cbrt_nearest(qn * qn / o->eps);
     *q = qn;
     *m_in = m;
     *v_in = m > 0.0 ? qn / m : 0.0;
@@ -953,13 +997,27 @@ static void stage(ora_sim *o, const double *Uin, double *Uout, double dt, double
             double F = dt * (g->J * pbt) * tmu;
             double pX = out[1], pY = out[2];
             double pZ = g->bX * pX + g->bY * pY;
-            double p3 = sqrt(pX * pX + pY * pY + pZ * pZ);
-            if (p3 <= F) {
-                out[1] = 0.0;
-                out[2] = 0.0;
+            if (o->p.flags & 16) {
+                /* smooth friction, for finite-difference checks of gradients
+                 * (the stop-clamp has a kink at rest): the Coulomb term
+                 * -F v / sqrt(|v|^2 + v_eps^2) in a form that never reverses
+                 * the flow, p = p~ r / (r + F) with
+                 * r = sqrt(|p~_3D|^2 + (m~^s v_eps)^2), smooth in p~ and F */
+                if (F > 0.0) {
+                    double me = out[0] * (o->p.v_eps / o->V);
+                    double r = sqrt(pX * pX + pY * pY + pZ * pZ + me * me);
+                    out[1] = pX * (r / (r + F));
+                    out[2] = pY * (r / (r + F));
+                }
             } else {
-                out[1] = pX * (1.0 - F / p3);
-                out[2] = pY * (1.0 - F / p3);
+                double p3 = sqrt(pX * pX + pY * pY + pZ * pZ);
+                if (p3 <= F) {
+                    out[1] = 0.0;
+                    out[2] = 0.0;
+                } else {
+                    out[1] = pX * (1.0 - F / p3);
+                    out[2] = pY * (1.0 - F / p3);
+                }
             }
             /* positivity; reading: a phase without mass carries no momentum */
             for (int ph = 0; ph < 2; ph++)
@@ -1176,6 +1234,9 @@ void ora_stage_probe(ora_sim *o, double dt_si, double *Uout)
     o->clamps = clamps;
     memcpy(o->bflux, bf, sizeof bf);
 }
+
+/* Probe for tests: the cube root the critical depth uses. */
+double ora_cbrt_nearest(double x) { return cbrt_nearest(x); }
 
 /* Scales for tests: eps, alpha, T (s), V (m/s), dxi, deta, md. */
 void ora_scales(const ora_sim *o, double out[7])

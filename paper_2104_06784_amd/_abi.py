@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("theta_b", C.c_double), ("rho_s", C.c_double), ("rho_f", C.c_double),
                 ("delta_int_deg", C.c_double), ("cfl", C.c_double), ("L", C.c_double), ("H", C.c_double),
                 ("chi", C.c_double), ("g", C.c_double), ("m_dry", C.c_double), ("a_min", C.c_double),
-                ("bc", C.c_int32 * 4), ("flags", C.c_int32)]
+                ("bc", C.c_int32 * 4), ("flags", C.c_int32), ("v_eps", C.c_double)]
 
 
 class Inflow(C.Structure):

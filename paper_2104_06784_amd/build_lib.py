@@ -24,9 +24,15 @@ COMMON = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall",
 PER_FILE = {
     # FP64 arithmetic exactly as written: no FMA contraction.
     "m2p_f64.hip": ["-ffp-contract=off"],
-    # FP32 state: contraction, reciprocal math, fast square root, denormals
-    # flushed (every FP32 quantity of the step is far above 1e-38).
-    "m2p_f32.hip": ["-ffp-contract=fast", "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+    # FP32 state: reciprocal math, fast square root, denormals flushed (every
+    # FP32 quantity of the step is far above 1e-38).  Multiply-adds are fused
+    # within each expression everywhere and across statements only in the
+    # functions a stage evaluates once per cell (update, sources, clamp, CFL
+    # speeds: "fp contract(fast)" blocks in m2p_device.h), so the face fluxes,
+    # slopes and row quantities that a row block's first rows recompute come
+    # out with the bits of the block below, and FP32 results do not depend on
+    # the tile height.
+    "m2p_f32.hip": ["-ffp-contract=on", "-fno-hip-fp32-correctly-rounded-divide-sqrt",
                     "-fgpu-flush-denormals-to-zero", "-freciprocal-math", "-fno-signed-zeros",
                     "-fno-trapping-math"],
     "m2p_abi.hip": ["-ffp-contract=off"],

@@ -189,8 +189,9 @@ namespace m2p {
 Shape make_shape(const KParams& P, int variant, int rows)
 {
     Shape s{};
-    // the earth-pressure option runs on the reference kernel
-    s.variant = (variant == M2P_VARIANT_REFERENCE || (P.flags & kFlagEarthPressure)) ? 1 : 2;
+    // the earth-pressure and smooth-friction options run on the reference kernel
+    s.variant =
+        (variant == M2P_VARIANT_REFERENCE || (P.flags & (kFlagEarthPressure | kFlagSmoothFriction))) ? 1 : 2;
     s.nbx = (P.nx + 63) / 64;
     s.nby = (P.ny + 3) / 4;
     s.nstrips = (P.nx + 59) / 60;
@@ -318,6 +319,7 @@ KParams make_kparams(const m2p_grid* g, const m2p_params* p, bool has_mu)
     K.dy = g->dy;
     K.cfl = p->cfl;
     K.a_floor = p->a_min / K.V;
+    K.v_eps = (p->flags & M2P_F_SMOOTH_FRICTION) ? p->v_eps / K.V : 0.0;
     K.dt_floor = 1e-12 * std::min(K.dxi, K.deta) / std::sqrt(K.eps);
     return K;
 }
@@ -376,8 +378,11 @@ int validate_scenario(const m2p_grid* g, const m2p_params* p, int32_t prec, cons
         return fail(M2P_EINVAL, "c_d, 1/N_R, theta_b >= 0 and m_dry, a_min > 0 required");
     for (int s = 0; s < 4; s++)
         if (p->bc[s] != M2P_BC_TRANSMISSIVE && p->bc[s] != M2P_BC_WALL) return fail(M2P_EINVAL, "bad boundary mode");
-    if (p->flags & ~(M2P_F_FLUID_PRESSURE_AS_PRINTED | M2P_F_RK3 | M2P_F_CENTRAL_UPWIND | M2P_F_EARTH_PRESSURE))
+    if (p->flags & ~(M2P_F_FLUID_PRESSURE_AS_PRINTED | M2P_F_RK3 | M2P_F_CENTRAL_UPWIND | M2P_F_EARTH_PRESSURE |
+                     M2P_F_SMOOTH_FRICTION))
         return fail(M2P_EINVAL, "unknown flag");
+    if ((p->flags & M2P_F_SMOOTH_FRICTION) && !(p->v_eps > 0.0 && std::isfinite(p->v_eps)))
+        return fail(M2P_EINVAL, "smooth friction needs v_eps > 0");
     if ((p->flags & M2P_F_EARTH_PRESSURE) &&
         !(p->delta_int_deg >= 0.0 && p->delta_int_deg < 90.0 && p->delta_b_deg <= p->delta_int_deg))
         return fail(M2P_EINVAL, "earth pressure needs delta_b <= delta_int < 90 deg");
@@ -1246,6 +1251,7 @@ int L_loss(m2p_ctx* c, const double* target_dev, void* lam, double* loss)
 
 static_assert(m2p::kFlagCentralUpwind == M2P_F_CENTRAL_UPWIND, "central-upwind flag bit");
 static_assert(m2p::kFlagEarthPressure == M2P_F_EARTH_PRESSURE, "earth-pressure flag bit");
+static_assert(m2p::kFlagSmoothFriction == M2P_F_SMOOTH_FRICTION, "smooth-friction flag bit");
 
 // The tangent and adjoint kernels differentiate the Kurganov-Tadmor flux of
 // the paper's model.

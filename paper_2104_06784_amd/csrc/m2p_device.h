@@ -2,8 +2,11 @@
 // two-phase depth-integrated shallow-flow model (Appendix A of the paper)
 // with the central scheme of Sect. 2.2.  Templated on the state type T
 // (float or double).  The FP64 build is compiled without FMA contraction and
-// follows the evaluation order written here exactly; the FP32 build lets the
-// compiler contract and use fast reciprocals.
+// follows the evaluation order written here exactly; the FP32 build uses fast
+// reciprocals and fuses multiply-adds within each expression, and across
+// statements only in the functions a stage evaluates once per cell (the
+// "fp contract(fast)" blocks), so that a quantity a tile recomputes at its
+// edge has the same bits as in the neighbouring tile.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -42,6 +45,7 @@ struct KParams {
     SegDesc sseg[MAX_SEG];  // Mode-II segments with a state hydrograph (ghost cells)
     int ntab;               // doubles in the hydrograph table of both kinds of segment
     double cos2_int;        // cos^2 of the internal friction angle (earth-pressure option)
+    double v_eps;           // regularisation speed of the smooth-friction option, / sqrt(g L)
 };
 
 // Scalars that live on the device across steps (time, dt, reductions).
@@ -82,6 +86,16 @@ struct Geo {
     T bX, bY, J, c, nX, nY, nZ, A11, A12, A21, A22;
 };
 
+// The FP32 build evaluates some formulas in algebraically folded forms with
+// fewer operations: J_b c = 1 (c = n_Z = 1/J_b), so h^s = m^s c and
+// eps J_b h A N^s = eps (1 - alpha)/2 h h^s A; products of constants are
+// folded.  The FP64 build (bitwise parity with the FP64 oracle) and the
+// dual-number adjoint evaluate the formulas as written.
+template <typename T>
+struct Folded : std::false_type {};
+template <>
+struct Folded<float> : std::true_type {};
+
 // minmod(a, b): the argument of smaller magnitude when both have the same
 // strict sign, else 0 (written with selects so the compiler emits no branch).
 // That is exactly the median of (a, b, 0), one v_med3_f32 in FP32.
@@ -97,25 +111,35 @@ M2P_FN T minmod(T a, T b)
     return pos ? lo : (neg ? hi : T(0));
 }
 
+// max of two values for the FP32 forms: one v_max_f32 (the same value as
+// the select a > b ? a : b for the finite, non-negative operands it gets)
+M2P_FN float fmax_f(float a, float b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_fmaxf(a, b);
+#else
+    return a > b ? a : b;
+#endif
+}
+template <typename T>
+M2P_FN T fmax_f(T a, T b)
+{
+    return a > b ? a : b;
+}
+
 // Continuous desingularisation of num / den (Kurganov-Petrova 2007):
 // 2 den num / (den^2 + max(den^2, md^2)).
 template <typename T>
 M2P_FN T dsg(T num, T den, T md)
 {
+    if constexpr (Folded<T>::value) {
+        const T d2 = den * den;
+        return ((den + den) * num) / (d2 + fmax_f(d2, md * md));
+    }
     T d2 = den * den;
     T m2 = md * md;
     return (T(2) * den * num) / (d2 + (d2 > m2 ? d2 : m2));
 }
-
-// The FP32 build evaluates some formulas in algebraically folded forms with
-// fewer operations: J_b c = 1 (c = n_Z = 1/J_b), so h^s = m^s c and
-// eps J_b h A N^s = eps (1 - alpha)/2 h h^s A; products of constants are
-// folded.  The FP64 build (bitwise parity with the FP64 oracle) and the
-// dual-number adjoint evaluate the formulas as written.
-template <typename T>
-struct Folded : std::false_type {};
-template <>
-struct Folded<float> : std::true_type {};
 
 // Both ratios n1 / den and n2 / den, desingularised as dsg does.  The FP32
 // build computes the common factor 2 den / (den^2 + max(den^2, md^2)) once
@@ -126,7 +150,7 @@ M2P_FN void dsg2(T n1, T n2, T den, T md, T& v1, T& v2)
     if constexpr (Folded<T>::value) {
         const T d2 = den * den;
         const T m2 = md * md;
-        const T sc = (den + den) / (d2 + (d2 > m2 ? d2 : m2));
+        const T sc = (den + den) / (d2 + fmax_f(d2, m2));
         v1 = n1 * sc;
         v2 = n2 * sc;
         return;
@@ -195,15 +219,20 @@ struct Consts {
     T eps, al, oma, md, eps_chi, tan_d, c_d, inv_n_r, theta_b;
     T dxi, deta, two_dxi, two_deta;
     // folded constants of the FP32 forms: eps (1 - alpha) / 2, eps / 2,
-    // (1 - alpha) / 2, -eps alpha, theta_b / (N_R eps), 1 / (2 dxi), 1 / (2 deta)
-    T k_ps, k_pf, half_oma, m_eps_al, k_fr, half_rdxi, half_rdeta;
+    // (1 - alpha) / 2, -eps alpha, theta_b / (N_R eps), 1 / (2 dxi), 1 / (2 deta),
+    // 1 / dxi, 1 / deta
+    T k_ps, k_pf, half_oma, m_eps_al, k_fr, half_rdxi, half_rdeta, rdxi, rdeta;
+    // smooth-friction option (flags bit 4) and its regularisation speed
+    bool smooth;
+    T veps;
     M2P_FN explicit Consts(const KParams& P)
         : eps(T(P.eps)), al(T(P.alpha)), oma(T(P.one_m_alpha)), md(T(P.md)), eps_chi(T(P.eps_chi)),
           tan_d(T(P.tan_d)), c_d(T(P.c_d)), inv_n_r(T(P.inv_n_r)), theta_b(T(P.theta_b)),
           dxi(T(P.dxi)), deta(T(P.deta)), two_dxi(T(P.two_dxi)), two_deta(T(P.two_deta)),
           k_ps(T(P.eps * (1.0 - P.alpha) / 2.0)), k_pf(T(P.eps / 2.0)), half_oma(T((1.0 - P.alpha) / 2.0)),
           m_eps_al(T(-P.eps * P.alpha)), k_fr(T(P.theta_b * P.inv_n_r / P.eps)), half_rdxi(T(0.5 / P.dxi)),
-          half_rdeta(T(0.5 / P.deta)) {}
+          half_rdeta(T(0.5 / P.deta)), rdxi(T(1.0 / P.dxi)), rdeta(T(1.0 / P.deta)),
+          smooth((P.flags & 16) != 0), veps(T(P.v_eps)) {}  // 16: M2P_F_SMOOTH_FRICTION
 };
 
 
@@ -326,6 +355,7 @@ template <typename T>
 M2P_FN void cell_speeds(const Consts<T>& K, const T u[NF], const Geo<T>& g, T& ax, T& ay, T kep = T(1))
 {
     if constexpr (Folded<T>::value) {
+        _Pragma("clang fp contract(fast)")
         const T ms = u[0], mf = u[3];
         const T hs = ms * g.c, hf = mf * g.c, h = hs + hf;
         T vXs, vYs, vXf, vYf;
@@ -417,6 +447,7 @@ M2P_FN void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
 // coefficients (M2P_F_CENTRAL_UPWIND, M2P_F_EARTH_PRESSURE).
 constexpr int kFlagCentralUpwind = 4;
 constexpr int kFlagEarthPressure = 8;
+constexpr int kFlagSmoothFriction = 16;
 
 // The face flux the flags select, chosen at run time (the tiled kernels take
 // the choice as a template argument instead); kL, kR: the earth-pressure
@@ -523,6 +554,11 @@ M2P_FN T cdiff(T up, T dn, T h)
 template <typename T>
 M2P_FN T fluid_G(T ms, T mf, const Geo<T>& g)
 {
+    if constexpr (Folded<T>::value) {
+        // J_b c = 1: J_b h (c h / 2) = (c (m^s + m^f))^2 / 2
+        const T hc = (ms + mf) * g.c;
+        return T(0.5) * hc * hc;
+    }
     T h = (ms + mf) / g.J;
     return g.J * h * (g.c * h / T(2));
 }
@@ -558,6 +594,7 @@ M2P_FN void sources(const Consts<T>& K, int flags, const T u[NF], const Geo<T>& 
                                         const T dn[6], T dGx, T dGy, Src<T>& S)
 {
     if constexpr (Folded<T>::value) {
+        _Pragma("clang fp contract(fast)")
         const T ms = u[0], mf = u[3];
         const T hs = ms * g.c, hf = mf * g.c, h = hs + hf;
         const T mt = ms + mf;
@@ -653,8 +690,30 @@ M2P_FN void tentative(const Consts<T>& K, const T u[NF], const T HXl[NF], const 
                                           T out[NF])
 {
     if constexpr (carry_2h<T, H2>()) {
+        _Pragma("clang fp contract(fast)")
         // fluxes carried as 2 H: u + dt s - (dt / 2 dxi) dF - (dt / 2 deta) dG
         const T cx = dt * K.half_rdxi, cy = dt * K.half_rdeta;
+#pragma unroll
+        for (int k = 0; k < NF; k++) {
+            const T dFx = HXr[k] - HXl[k];
+            const T dGy = HYt[k] - HYb[k];
+            const int ph = k / 3, comp = k % 3;
+            T o = u[k];
+            if (comp > 0) {
+                const int a = comp - 1;
+                T sk = S.sn[ph][a] + S.sf[ph][a] + S.sv[ph][a];
+                if (ph == 1) sk = sk + S.sd[a] + (a == 0 ? svx : svy);
+                o = o + dt * sk;
+            }
+            o = o - cx * dFx;
+            out[k] = o - cy * dGy;
+        }
+        return;
+    }
+    if constexpr (Folded<T>::value) {
+        _Pragma("clang fp contract(fast)")
+        // u + dt s - (dt / dxi) dF - (dt / deta) dG
+        const T cx = dt * K.rdxi, cy = dt * K.rdeta;
 #pragma unroll
         for (int k = 0; k < NF; k++) {
             const T dFx = HXr[k] - HXl[k];
@@ -696,11 +755,14 @@ M2P_FN void tentative(const Consts<T>& K, const T u[NF], const T HXl[NF], const 
 // solid thickness, centripetal term kappa_s from the stage input), then
 // positivity: a phase with tentative thickness <= 0 loses its momentum.
 // Returns the number of positivity clamps (tentative thickness < 0).
-template <typename T>
+// SMOOTH = false leaves out the smooth-friction option (the fused stage
+// kernels; contexts with the option run the reference kernel).
+template <typename T, bool SMOOTH = true>
 M2P_FN int clamp_cell(const Consts<T>& K, const Geo<T>& g, T kappa_s, T dt, T tmu, T out[NF])
 {
     T F;
     if constexpr (Folded<T>::value) {
+        _Pragma("clang fp contract(fast)")
         // J_b p_b = m^s (c (1 - alpha) - eps^chi kappa_s)
         T jpb = out[0] * (g.c * K.oma - K.eps_chi * kappa_s);
         if (jpb < T(0)) jpb = T(0);
@@ -713,7 +775,17 @@ M2P_FN int clamp_cell(const Consts<T>& K, const Geo<T>& g, T kappa_s, T dt, T tm
     }
     T pX = out[1], pY = out[2];
     T pZ = g.bX * pX + g.bY * pY;
-    if constexpr (Folded<T>::value) {
+    if (SMOOTH && K.smooth) {
+        // smooth friction (gradient checks): p = p~ r / (r + F),
+        // r = sqrt(|p~_3D|^2 + (m~^s v_eps)^2), a regularised Coulomb term
+        // that never reverses the flow
+        if (F > T(0)) {
+            const T me = out[0] * K.veps;
+            const T r = sqrt(pX * pX + pY * pY + pZ * pZ + me * me);
+            out[1] = pX * (r / (r + F));
+            out[2] = pY * (r / (r + F));
+        }
+    } else if constexpr (Folded<T>::value) {
         // |p_3| <= F  <=>  |p_3|^2 <= F^2 (F >= 0)
         const T p2 = pX * pX + pY * pY + pZ * pZ;
         if (p2 <= F * F) {
@@ -746,13 +818,13 @@ M2P_FN int clamp_cell(const Consts<T>& K, const Geo<T>& g, T kappa_s, T dt, T tm
     return clamps;
 }
 
-template <typename T, bool H2 = false>
+template <typename T, bool H2 = false, bool SMOOTH = true>
 M2P_FN int update_cell(const Consts<T>& K, const T u[NF], const Geo<T>& g, const T HXl[NF],
                                            const T HXr[NF], const T HYb[NF], const T HYt[NF], const Src<T>& S,
                                            T svx, T svy, T dt, T tmu, T out[NF])
 {
     tentative<T, H2>(K, u, HXl, HXr, HYb, HYt, S, svx, svy, dt, out);
-    return clamp_cell(K, g, S.kappa_s, dt, tmu, out);
+    return clamp_cell<T, SMOOTH>(K, g, S.kappa_s, dt, tmu, out);
 }
 
 // Ghost-cell index map (transmissive: copy the edge cell; wall: mirror with

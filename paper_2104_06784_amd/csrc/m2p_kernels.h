@@ -421,6 +421,43 @@ __device__ __forceinline__ double table_at(const double* y, const Bracket& b)
 }
 
 
+// Cube root of x > 0 to the double whose cube is nearest to x: from the
+// device cbrt, step to the neighbour with the smaller exact residual
+// |y^3 - x| until neither is smaller (the residual is unimodal, so every
+// start ends on the same double; error-free products by fused multiply-add:
+// y^2 = p + e, y p = q + f; q - x is exact).  Library cube roots differ by
+// units in the last place between platforms; this result does not.
+__device__ __forceinline__ double cube_residual(double y, double x)
+{
+    const double p = y * y;
+    const double e = fma(y, y, -p);
+    const double q = y * p;
+    const double f = fma(y, p, -q);
+    const double g = y * e;
+    return ((q - x) + f) + g;
+}
+
+__device__ __forceinline__ double cbrt_nearest(double x)
+{
+    double y = cbrt(x);
+    if (!(x > 0.0) || !isfinite(x)) return y;
+    double r = fabs(cube_residual(y, x));
+    for (int it = 0; it < 16; it++) {
+        const double lo = nextafter(y, 0.0), hi = nextafter(y, INFINITY);
+        const double rl = fabs(cube_residual(lo, x)), rh = fabs(cube_residual(hi, x));
+        if (rl < r) {
+            y = lo;
+            r = rl;
+        } else if (rh < r) {
+            y = hi;
+            r = rh;
+        } else {
+            break;
+        }
+    }
+    return y;
+}
+
 // Critical-depth inflow state of a segment at dimensionless time tau:
 // q (discharge per unit width), m_in = (q^2/eps)^(1/3), v_in = q / m_in, phi.
 __device__ __forceinline__ void inflow_state(const KParams& P, const double* tables, int s, double tau_nd,
@@ -436,7 +473,7 @@ __device__ __forceinline__ void inflow_state(const KParams& P, const double* tab
     double w = (d.side < 2) ? P.dy : P.dx;
     double qs = Qv / ((double)d.ncells * w);
     double qn = qs / (P.H * P.V);
-    double m = cbrt(qn * qn / P.eps);
+    double m = cbrt_nearest(qn * qn / P.eps);
     out[0] = qn;
     out[1] = m;
     out[2] = m > 0.0 ? qn / m : 0.0;

@@ -11,7 +11,10 @@
 // barrier at the end combines a workgroup's partial sums).  The arithmetic of
 // every quantity is the one of m2p_device.h in the same order as the
 // reference kernel, so FP64 results are bitwise identical to it (the FP32
-// stage 1 carries face fluxes as 2 H, see carry_2h).
+// stage 1 carries face fluxes as 2 H, see carry_2h).  In FP32 the quantities
+// a row block's prologue recomputes (row geometry, slopes, the face flux
+// below the block) are fused the same way as in the march, so FP32 results
+// do not depend on the tile height either.
 #pragma once
 
 #include "m2p_device.h"
@@ -355,7 +358,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
         // ---- update and write
         if (out_lane) {
             T out[NF];
-            clamps += update_cell<T, H2>(K, Uc, D0.g, HxL, Hx, Hy, HyN, Sr, svx, svy, dt, tmu, out);
+            clamps += update_cell<T, H2, false>(K, Uc, D0.g, HxL, Hx, Hy, HyN, Sr, svx, svy, dt, tmu, out);
             if (STAGE > 1) {
 #pragma unroll
                 for (int k = 0; k < NF; k++) out[k] = stage_combine<STAGE>(unr[k], out[k]);

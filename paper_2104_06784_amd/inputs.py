@@ -33,6 +33,7 @@ F_FLUID_PRESSURE_AS_PRINTED = 1
 F_RK3 = 2                       # three-stage SSP Runge-Kutta instead of Heun
 F_CENTRAL_UPWIND = 4            # central-upwind face flux (one-sided local speeds)
 F_EARTH_PRESSURE = 8            # Savage-Hutter earth-pressure coefficients from delta_int
+F_SMOOTH_FRICTION = 16          # smooth Coulomb friction (finite-difference checks of gradients)
 
 
 @dataclasses.dataclass
@@ -55,6 +56,7 @@ class Params:
     a_min: float = 1.0            # floor on the CFL wave speed (m/s)
     bc: tuple = (BC_TRANSMISSIVE,) * 4
     flags: int = 0
+    v_eps: float = 0.01           # regularisation speed (m/s) of F_SMOOTH_FRICTION
 
 
 @dataclasses.dataclass

@@ -15,7 +15,7 @@ from . import _abi as A
 
 def make_params(p) -> A.Params:
     return A.Params(p.delta_b_deg, p.c_d, p.inv_n_r, p.theta_b, p.rho_s, p.rho_f, p.delta_int_deg, p.cfl,
-                    p.L, p.H, p.chi, p.g, p.m_dry, p.a_min, (C.c_int32 * 4)(*p.bc), p.flags)
+                    p.L, p.H, p.chi, p.g, p.m_dry, p.a_min, (C.c_int32 * 4)(*p.bc), p.flags, p.v_eps)
 
 
 class Sim:

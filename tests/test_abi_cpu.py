@@ -79,12 +79,15 @@ def test_create_rejects_bad_grid_and_dem():
 
 
 @pytest.mark.parametrize("kw", [
-    dict(flags=16),                                                      # unknown flag
+    dict(flags=32),                                                      # unknown flag
+    dict(flags=I.F_SMOOTH_FRICTION, v_eps=0.0),                          # smooth friction without a speed
+    dict(flags=I.F_SMOOTH_FRICTION, v_eps=math.nan),
     dict(flags=I.F_EARTH_PRESSURE, delta_b_deg=20.0, delta_int_deg=15.0),  # basal above internal friction
     dict(flags=I.F_EARTH_PRESSURE, delta_int_deg=90.0),
     dict(flags=I.F_EARTH_PRESSURE, delta_int_deg=-1.0)])
 def test_create_rejects_bad_options(kw):
-    """Option flags are validated before any device call: unknown bits, and
+    """Option flags are validated before any device call: unknown bits, a
+    smooth friction without a positive regularisation speed, and
     earth-pressure angles outside delta_b <= delta_int < 90 deg."""
     rc, h = _create(A.Grid(8, 8, 10.0, 10.0), make_params(I.Params(**kw)))
     assert rc == A.M2P_EINVAL and not h.value
@@ -135,14 +138,13 @@ def test_stage_flop_count():
     4 cmp; the maxima over the phases and the running maxima, 4 cmp):
     16 add, 25 mul, 2 div, 4 sqrt, 10 cmp; plus the flux form of stage 1, which
     carries face fluxes as 2 H: its two central fluxes save 2 mul per
-    component (24 mul) and its update replaces the 12 divisions by the cell
-    widths with 12 multiplications (dt / 2 dxi, dt / 2 deta, then one factor
-    per flux difference and source sum), so stage 2 has 12 mul and 12 div
-    more: 16 add, 37 mul, 14 div, 4 sqrt, 10 cmp."""
+    component (24 mul), while both updates multiply each flux difference by
+    dt over the cell width (dt / 2 dxi in stage 1, dt / dxi in stage 2): 16
+    add, 49 mul, 2 div, 4 sqrt, 10 cmp."""
     f10, f11, f20, f21 = _flops(1, 0), _flops(1, 1), _flops(2, 0), _flops(2, 1)
     assert np.array_equal(f11 - f10, [34, 40, 10, 0, 0])
     assert np.array_equal(f21 - f20, [34, 40, 10, 0, 0])
-    assert np.array_equal(f20 - f10, [16, 37, 14, 4, 10])
+    assert np.array_equal(f20 - f10, [16, 49, 2, 4, 10])
     # square roots: 4 face sides x 2 phase speeds, the new row's geometry, the
     # norm of the solid momentum in the Coulomb clamp
     assert f10[3] == 10

@@ -9,6 +9,7 @@
   differences of the FP64 CPU oracle with the same frozen time steps;
 - FP32 adjoint against the FP64 adjoint; bitwise reproducibility.
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -24,11 +25,12 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _prob(nx=40, ny=36, bc=(0, 0, 0, 0), visc=True, mu=True, seed=7):
+def _prob(nx=40, ny=36, bc=(0, 0, 0, 0), visc=True, mu=True, seed=7, smooth=False):
     dx = 10.0
     dem = I.fractal_dem(nx, dx, seed, 40.0, tilt_deg=22.0, ny=ny)
     h = I.cylinder(nx, ny, dx, dx, 0.35 * nx * dx, 0.5 * ny * dx, 0.25 * min(nx, ny) * dx, 8.0)
-    p = I.Params(delta_b_deg=20.0, cfl=0.2, bc=bc, inv_n_r=(1.0 / 268.0 if visc else 0.0))
+    p = I.Params(delta_b_deg=20.0, cfl=0.2, bc=bc, inv_n_r=(1.0 / 268.0 if visc else 0.0),
+                 flags=I.F_SMOOTH_FRICTION if smooth else 0, v_eps=0.05)
     tan_mu = None
     if mu:
         tan_mu = np.tan(np.radians(20.0 + 2.0 * I.smooth_field(max(nx, ny), seed + 1, 3.0)[:ny, :nx]))
@@ -88,6 +90,8 @@ CASES = [
     dict(bc=(1, 0, 0, 1), visc=False, mu=True, nx=61, ny=23),
     # fewer than five rows: every cell is an edge-ring cell of the gather
     dict(bc=(0, 1, 1, 0), visc=True, mu=True, nx=13, ny=4),
+    # smooth friction option
+    dict(bc=(0, 0, 1, 1), visc=True, mu=True, smooth=True),
 ]
 
 
@@ -228,3 +232,127 @@ def test_autograd_function_matches_adjoint_and_descends():
         hist.append(loss.item())
     _say(f"[adj] calibration losses {['%.4e' % x for x in hist]}, s {float(s):.3f}")
     assert all(b < a for a, b in zip(hist, hist[1:]))
+
+
+# ------------------------------------------------- gradients at full strength
+#
+# With the smooth-friction option the Coulomb term has no kink at rest, so
+# central finite differences of the loss converge to the derivative the
+# adjoint computes (minmod, the speed maxima and positivity keep kinks of
+# their own; a difference that straddles one shows up as a larger error).
+
+
+def _smooth(prob):
+    p = dataclasses.replace(prob.params, flags=prob.params.flags | I.F_SMOOTH_FRICTION, v_eps=0.05)
+    return dataclasses.replace(prob, params=p)
+
+
+def test_adjoint_against_oracle_fd_64x64_200_steps_smooth_friction():
+    """64 x 64 cells, 200 FP64 steps with smooth friction: the adjoint's loss
+    equals the oracle's to 1e-10, and its gradient along the release-volume
+    scale and along 8 random smooth friction directions matches central
+    finite differences of the oracle's loss with the same frozen time steps
+    to 1e-6 relative (step 1e-7; the step 1e-6 is reported beside it: the
+    longer secant is more likely to straddle a kink of minmod, the speed
+    maxima or positivity somewhere in the 200 steps)."""
+    import oracle
+    from paper_2104_06784_amd.sim import Sim
+    n, nsteps = 64, 200
+    prob = _smooth(_prob(n, n, bc=(0, 0, 0, 0), visc=True, mu=True, seed=23))
+    mu_true = np.tan(np.radians(20.0 + 3.0 * I.smooth_field(n, 33, 4.0)))
+    ot = oracle.OracleSim(dataclasses.replace(prob, tan_mu=mu_true, h_vert=prob.h_vert * 1.2))
+    ot.run(nsteps)
+    target = ot.fields()["h"]
+    dts = oracle.OracleSim(prob).run(nsteps)
+    g = Sim(prob, precision="f64")
+    loss, gmu, gvol = g.adjoint_run(nsteps, 25, target, 1.0)
+    lo = _loss_oracle(prob, prob.tan_mu, 1.0, dts, target)
+    _say(f"[p12] 64^2 x {nsteps}: loss gpu {loss:.12e} oracle {lo:.12e}")
+    assert abs(loss - lo) <= 1e-10 * lo
+    rng = np.random.default_rng(12)
+    worst = {1e-6: 0.0, 1e-7: 0.0}
+    for k in range(8):
+        d = I.smooth_field(n, 60 + k, 3.0) * (0.5 + rng.random())
+        ad = float(np.sum(gmu * d))
+        for eps in worst:
+            fd = (_loss_oracle(prob, prob.tan_mu + eps * d, 1.0, dts, target)
+                  - _loss_oracle(prob, prob.tan_mu - eps * d, 1.0, dts, target)) / (2 * eps)
+            e = abs(ad - fd) / abs(fd)
+            worst[eps] = max(worst[eps], e)
+            _say(f"   friction direction {k} step {eps:g}: adjoint {ad:.12e} FD {fd:.12e} rel {e:.2e}")
+    for eps in worst:
+        fd = (_loss_oracle(prob, prob.tan_mu, 1.0 + eps, dts, target)
+              - _loss_oracle(prob, prob.tan_mu, 1.0 - eps, dts, target)) / (2 * eps)
+        ev = abs(gvol - fd) / abs(fd)
+        _say(f"   volume step {eps:g}: adjoint {gvol:.12e} FD {fd:.12e} rel {ev:.2e}")
+        worst[eps] = max(worst[eps], ev)
+    assert worst[1e-7] <= 1e-6
+
+
+def _config5_target(prec, smooth, nsteps):
+    from paper_2104_06784_amd.sim import Sim
+    truth = I.calibration_case(truth=True)
+    truth = _smooth(truth) if smooth else truth
+    t = Sim(truth, precision=prec)
+    t.run(nsteps)
+    return t.fields()["h"]
+
+
+def test_adjoint_config5_length_directional_fd_fp64():
+    """The calibration workload at full size and length (512^2, 2000 steps,
+    checkpoint every 100, smooth friction), FP64: the adjoint's directional
+    derivative along a smooth friction field and along the volume scale
+    against central differences of the same loss computed by the forward
+    path with the same frozen time steps, to 1e-6 relative."""
+    from paper_2104_06784_amd.sim import Sim
+    nsteps = 2000
+    prob = _smooth(I.calibration_case())
+    target = _config5_target("f64", True, nsteps)
+    _say("[p12] 512^2 x 2000 FP64: base steps")
+    base = Sim(prob, precision="f64")
+    dts = np.array([base.step() for _ in range(nsteps)])
+    a = Sim(prob, precision="f64")
+    loss, gmu, gvol = a.adjoint_run(nsteps, 100, target, 1.0)
+    assert abs(loss - base.loss(target)) <= 1e-12 * loss
+
+    def L(mu_shift=None, scale=1.0):
+        q = dataclasses.replace(prob, tan_mu=prob.tan_mu + (0.0 if mu_shift is None else mu_shift),
+                                h_vert=prob.h_vert * scale)
+        s = Sim(q, precision="f64")
+        s.set_dt_schedule(dts)
+        s.run(nsteps)
+        return s.loss(target)
+
+    eps = 1e-6
+    d = I.smooth_field(512, 77, 5.0) * 0.5
+    fd = (L(eps * d) - L(-eps * d)) / (2 * eps)
+    ad = float(np.sum(gmu * d))
+    fv = (L(scale=1.0 + eps) - L(scale=1.0 - eps)) / (2 * eps)
+    _say(f"   friction: adjoint {ad:.12e} FD {fd:.12e} rel {abs(ad - fd) / abs(fd):.2e}; "
+         f"volume: adjoint {gvol:.12e} FD {fv:.12e} rel {abs(gvol - fv) / abs(fv):.2e}")
+    assert abs(ad - fd) <= 1e-6 * abs(fd)
+    assert abs(gvol - fv) <= 1e-6 * abs(fv)
+
+
+@pytest.mark.parametrize("smooth", [False, True])
+def test_adjoint_fp32_against_fp64_config5_length(smooth):
+    """The calibration workload at full size and length (512^2, 2000 steps,
+    checkpoint every 100, 20 recomputed segments): the FP32 adjoint's
+    friction gradient against the FP64 adjoint's, cosine >= 0.999 and
+    relative L2 <= 1e-2, and the volume derivative to 1e-2 -- with the
+    paper's stop-clamp and with smooth friction."""
+    from paper_2104_06784_amd.sim import Sim
+    nsteps = 2000
+    prob = _smooth(I.calibration_case()) if smooth else I.calibration_case()
+    target = _config5_target("f64", smooth, nsteps)
+    res = {}
+    for prec in ("f64", "f32"):
+        g = Sim(prob, precision=prec)
+        res[prec] = g.adjoint_run(nsteps, 100, target, 1.0)
+    g64, g32 = res["f64"][1], res["f32"][1]
+    cos = float(np.sum(g32 * g64) / (np.linalg.norm(g32) * np.linalg.norm(g64)))
+    rel = float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))
+    v64, v32 = res["f64"][2], res["f32"][2]
+    _say(f"[p12] config 5 smooth={smooth}: cosine {cos:.6f} rel L2 {rel:.3e} volume {v32:.6e} vs {v64:.6e}")
+    assert cos >= 0.999 and rel <= 1e-2
+    assert abs(v32 - v64) <= 1e-2 * abs(v64)

@@ -90,9 +90,7 @@ def test_graph_replay_equals_direct_launches():
 def test_autotune_restores_state_and_keeps_results(precision):
     """The tuner's trial steps leave no trace: the state and scalars are restored
     bitwise, and later steps equal a fresh batch run with the chosen shape
-    (bitwise in FP64, where results do not depend on the tile height; to FP32
-    rounding in FP32, where FMA contraction may differ between the prologue and
-    the body of a row block)."""
+    bitwise, in FP64 and in FP32 (results do not depend on the tile height)."""
     from paper_2104_06784_amd.sim import Batch
     probs = [_small(i, nx, ny) for i, (nx, ny) in enumerate(SHAPES)]
     a = Batch(probs, precision=precision)
@@ -109,12 +107,7 @@ def test_autotune_restores_state_and_keeps_results(precision):
     c.set_tile(rows, blocks)
     c.run(15)
     for i in range(len(probs)):
-        Ua, Uc = a.state(i), c.state(i)
-        if precision == "f64":
-            assert np.array_equal(Ua, Uc)
-        else:
-            for k in range(6):
-                assert np.max(np.abs(Ua[k] - Uc[k])) <= 1e-5 * max(np.max(np.abs(Uc[k])), 1e-30)
+        assert np.array_equal(a.state(i), c.state(i))
 
 
 def test_batch_rejects_bad_input():

@@ -1022,3 +1022,78 @@ def test_earth_pressure_cfl_uses_the_passive_bound(delta_b, delta_int, K):
     s = _sim(I.Problem("ep-dt", n, n, dx, dx, p, z, np.full((n, n), h), np.ones((n, n))))
     expect = 0.1 * dx / math.sqrt(K * 9.81 * h)
     assert abs(s.peek_dt() - expect) <= 1e-13 * expect
+
+
+# ------------------------------------------------ smooth friction (option)
+
+@pytest.mark.parametrize("theta", [30.0, 15.0])
+def test_smooth_friction_layer_recurrence(theta):
+    """The smooth-friction option (flags bit 4, for finite-difference checks
+    of gradients) on a uniform pure-solid layer: each stage adds the gravity
+    impulse dt h g sin(theta) cos(theta) to the horizontal momentum q = h v and
+    then scales it by r / (r + F), r = sqrt((q / cos(theta))^2 + (h v_eps)^2)
+    the regularised 3-D momentum norm, F = dt h g tan(delta) cos(theta) the
+    Coulomb impulse; Heun averages the two stages.  Above the friction angle
+    the layer slides a little faster than the stop-clamp's block (the form
+    removes F r / (r + F) instead of F), below it creeps at a speed of order
+    dt g (the form never stops the grains, which is what makes it smooth)
+    instead of resting.  Pins the form, its place after the tentative update,
+    the 3-D norm and the thickness in the regularisation, to round-off."""
+    nx, ny, dx, hv, delta, veps = 16, 8, 10.0, 5.0, 20.0, 0.05
+    p = I.Params(delta_b_deg=delta, rho_f=0.0, inv_n_r=0.0, theta_b=0.0, bc=(0, 0, 0, 0),
+                 flags=I.F_SMOOTH_FRICTION, v_eps=veps)
+    prob = I.Problem("smooth", nx, ny, dx, dx, p, I.plane_dem(nx, ny, dx, dx, theta), np.full((ny, nx), hv),
+                     np.ones((ny, nx)))
+    s = _sim(prob)
+    dts = s.run(300)
+    vx = s.fields()["vxs"]
+    g, th, td = 9.81, math.radians(theta), math.tan(math.radians(delta))
+
+    def E(q, dt):
+        qt = q + dt * hv * g * math.sin(th) * math.cos(th)
+        F = dt * hv * g * td * math.cos(th)
+        r = math.sqrt((qt / math.cos(th)) ** 2 + (hv * veps) ** 2)
+        return qt * r / (r + F)
+
+    q = 0.0
+    for dt in dts:
+        q = 0.5 * (q + E(E(q, dt), dt))
+    v = q / hv
+    assert np.max(np.abs(vx - v)) <= 1e-12 * abs(v)
+    assert np.max(np.abs(s.fields()["vys"])) == 0.0
+    if theta > delta:
+        clamp = 9.81 * math.cos(th) * (math.sin(th) - td * math.cos(th)) * dts.sum()
+        assert clamp < v <= 1.1 * clamp
+    else:
+        free = 9.81 * math.sin(th) * math.cos(th) * dts.sum()
+        assert 0.0 < v < 0.1 * free
+
+
+def test_smooth_friction_needs_a_positive_speed():
+    p = I.Params(flags=I.F_SMOOTH_FRICTION, v_eps=0.0)
+    z = np.zeros((6, 6))
+    with pytest.raises(ValueError):
+        _sim(I.Problem("bad", 6, 6, 10.0, 10.0, p, z, z, z))
+
+
+def test_critical_depth_cube_root_is_the_nearest_cube():
+    """The critical depth's cube root returns, for every input, the double
+    whose cube is nearest to the input, checked with exact rational
+    arithmetic against the neighbours of numpy's cube root (a library cube
+    root may be units in the last place off; the GPU path makes the same
+    choice, so discharge inflows stay bitwise equal over long runs)."""
+    from fractions import Fraction
+
+    import oracle
+    rng = np.random.default_rng(77)
+    xs = np.concatenate([10.0 ** rng.uniform(-12, 6, 3000), [1.0, 8.0, 27.0, 0.125, 1e-300, 3.0]])
+    for x in xs:
+        y = oracle.cbrt_nearest(x)
+        c = float(np.cbrt(x))
+        cands = {c}
+        for _ in range(4):
+            cands |= {float(np.nextafter(v, 0.0)) for v in cands} | {float(np.nextafter(v, np.inf)) for v in cands}
+        X = Fraction(float(x))
+        best = min(cands, key=lambda v: abs(Fraction(v) ** 3 - X))
+        assert y == best, x
+    assert oracle.cbrt_nearest(0.0) == 0.0
