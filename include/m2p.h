@@ -77,8 +77,9 @@ extern "C" {
                        difference along the direction is >= 0, else passive, K_x = 2 (1 -/+ sqrt(1 - cos^2 d_int
                        (1 + tan^2 d_b))) / cos^2 d_int - 1, K_y = (K_x + 1 -/+ sqrt((K_x - 1)^2 + 4 tan^2 d_b)) / 2,
                        d_int = delta_int_deg; needs delta_b (and every tan_mu) <= delta_int < 90 deg; Mode-I
-                       releases on single-scenario contexts, run by the reference kernel; not with the tangent and
-                       adjoint calls */
+                       releases on single-scenario contexts (the tiled kernel computes the coefficients in its
+                       march; with M2P_F_CENTRAL_UPWIND the reference kernel runs the option after a coefficient
+                       pass); not with the tangent and adjoint calls */
 
 #define M2P_F_SMOOTH_FRICTION 16 /* smooth Coulomb friction, for finite-difference checks of gradients (the
                        stop-clamp of the paper's friction term has a kink at rest): after the tentative
@@ -218,6 +219,15 @@ int m2p_set_inflow_states(m2p_ctx *c, const m2p_inflow_state *seg, int32_t nseg)
  * FP64.  tile_rows: rows each wavefront of the tiled variant marches, 1..4096,
  * or 0 = chosen from the grid size.  Errors: M2P_EINVAL. */
 int m2p_set_variant(m2p_ctx *c, int32_t variant, int32_t tile_rows);
+
+/* Choose the tile height of the tiled variant by timing: run trial_steps
+ * steps (1..10000) at each of a few heights around the size rule's on the
+ * context itself, putting the state, time, integrals and step count back
+ * after each trial, and keep the fastest (results do not depend on the
+ * height in either precision).  Returns the height and its ms per step (may
+ * be NULL).  Synchronizes.  Errors: EINVAL (reference variant selected),
+ * ESTATE, ENOMEM, EHIP. */
+int m2p_autotune(m2p_ctx *c, int32_t trial_steps, int32_t *rows, double *ms_per_step);
 
 /* One time step, enqueued.  If dt_out is not NULL the stream is synchronized
  * and the step taken (s) is returned (0 once t reached the run_to end time). */

@@ -91,6 +91,7 @@ SIGNATURES = {
     "m2p_run_outputs": (C.c_int, [_P, _dp, C.c_int64, C.c_int64, _dp, C.POINTER(C.c_int64)]),
     "m2p_set_graph": (C.c_int, [_P, C.c_int32]),
     "m2p_set_variant": (C.c_int, [_P, C.c_int32, C.c_int32]),
+    "m2p_autotune": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32), _dp]),
     "m2p_step": (C.c_int, [_P, _dp]),
     "m2p_run": (C.c_int, [_P, C.c_int64]),
     "m2p_run_to": (C.c_int, [_P, C.c_double, C.c_int64, C.POINTER(C.c_int64)]),

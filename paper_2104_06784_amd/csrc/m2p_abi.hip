@@ -189,9 +189,11 @@ namespace m2p {
 Shape make_shape(const KParams& P, int variant, int rows)
 {
     Shape s{};
-    // the earth-pressure and smooth-friction options run on the reference kernel
-    s.variant =
-        (variant == M2P_VARIANT_REFERENCE || (P.flags & (kFlagEarthPressure | kFlagSmoothFriction))) ? 1 : 2;
+    // the smooth-friction option, and earth pressure with the central-upwind
+    // flux or with Mode-II state segments, run on the reference kernel
+    const bool ep_ref =
+        (P.flags & kFlagEarthPressure) && ((P.flags & kFlagCentralUpwind) || P.nsseg > 0);
+    s.variant = (variant == M2P_VARIANT_REFERENCE || (P.flags & kFlagSmoothFriction) || ep_ref) ? 1 : 2;
     s.nbx = (P.nx + 63) / 64;
     s.nby = (P.ny + 3) / 4;
     s.nstrips = (P.nx + 59) / 60;
@@ -504,9 +506,10 @@ int m2p_create(m2p_ctx** out, const m2p_grid* g, const m2p_params* p, int32_t pr
         const int nmax = std::max(nx, ny) + 1;
         c->B.nmax = nmax;
         c->B.nw_ref = ((nx + 63) / 64) * ((ny + 3) / 4);
-        if (hipMalloc(&c->bpart, sizeof(double) * 3 * 4 * 2 * (size_t)nmax) != hipSuccess)
+        if (hipMalloc(&c->bpart, sizeof(double) * (outflow_dt_index(nmax) + 2)) != hipSuccess)
             return cleanup(fail(M2P_ENOMEM, "partials allocation failed"));
-        (void)hipMemset(c->bpart, 0, sizeof(double) * 3 * 4 * 2 * (size_t)nmax);
+        if (hipMemset(c->bpart, 0, sizeof(double) * (outflow_dt_index(nmax) + 2)) != hipSuccess)
+            return cleanup(fail(M2P_EHIP, "partials initialisation failed"));
         if (ensure_wpart(c) != M2P_OK) return cleanup(M2P_ENOMEM);
     }
     if (hipMalloc(&c->mass_part, sizeof(double) * 2 * kMassBlocks) != hipSuccess)
@@ -826,6 +829,93 @@ int m2p_set_variant(m2p_ctx* c, int32_t variant, int32_t rows)
     return rc;
 }
 
+int m2p_autotune(m2p_ctx* c, int32_t trial_steps, int32_t* rows_out, double* ms_out)
+{
+    if (!c || trial_steps < 1 || trial_steps > 10000) return fail(M2P_EINVAL, "bad argument");
+    int rc = ensure_ready(c);
+    if (rc) return rc;
+    const Shape auto_shape = make_shape(c->kp, M2P_VARIANT_TILED, 0);
+    if (make_shape(c->kp, c->variant, c->rows).variant != 2) return fail(M2P_EINVAL, "the reference kernel has no tile");
+    // candidates around the size rule's height
+    const int r0 = auto_shape.R;
+    std::vector<int> cand;
+    for (double f : {0.5, 0.67, 0.8, 1.0, 1.2, 1.33, 1.5, 1.75}) {
+        const int r = std::max(1, std::min(64, (int)std::lround(r0 * f)));
+        if (std::find(cand.begin(), cand.end(), r) == cand.end()) cand.push_back(r);
+    }
+    // the trials run on the context's own state: keep the state, the device
+    // scalars and the outflow integrals, and put them back after each trial
+    const size_t bbytes = sizeof(double) * 4 * 2 * (size_t)c->B.nmax;
+    void *ub = nullptr, *sb = nullptr, *bb = nullptr;
+    if (hipMalloc(&ub, c->state_bytes) != hipSuccess || hipMalloc(&sb, sizeof(DevScalars)) != hipSuccess ||
+        hipMalloc(&bb, bbytes) != hipSuccess) {
+        if (ub) (void)hipFree(ub);
+        if (sb) (void)hipFree(sb);
+        return fail(M2P_ENOMEM, "autotune backup allocation failed");
+    }
+    struct Free {
+        void *a, *b, *c;
+        ~Free()
+        {
+            (void)hipFree(a);
+            (void)hipFree(b);
+            (void)hipFree(c);
+        }
+    } free_bufs{ub, sb, bb};
+    HIPCHK(hipMemcpyAsync(ub, c->B.U, c->state_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(sb, c->S, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(bb, c->bpart, bbytes, hipMemcpyDeviceToDevice, c->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int old_variant = c->variant, old_rows = c->rows;
+    const bool old_prof = c->prof;
+    c->prof = false;
+    double best = 1e300;
+    int bestR = r0;
+    for (int r : cand) {
+        c->variant = M2P_VARIANT_TILED;
+        c->rows = r;
+        refresh_grid(c);
+        if ((rc = ensure_wpart(c))) break;
+        hipError_t e = do_step(c);  // warm
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int k = 0; k < trial_steps && e == hipSuccess; k++) e = do_step(c);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->B.U, ub, c->state_bytes, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->S, sb, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->bpart, bb, bbytes, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune trial");
+            break;
+        }
+        if (ms < best) {
+            best = ms;
+            bestR = r;
+        }
+    }
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->prof = old_prof;
+    if (rc) {
+        c->variant = old_variant;
+        c->rows = old_rows;
+        refresh_grid(c);
+        return rc;
+    }
+    c->variant = old_variant;
+    c->rows = bestR;
+    refresh_grid(c);
+    if ((rc = ensure_wpart(c))) return rc;
+    if (rows_out) *rows_out = bestR;
+    if (ms_out) *ms_out = best / trial_steps;
+    return M2P_OK;
+}
+
 int m2p_step(m2p_ctx* c, double* dt_out)
 {
     if (!c) return fail(M2P_EINVAL, "NULL context");
@@ -1043,6 +1133,35 @@ int m2p_get_fields(m2p_ctx* c, double* h, double* phi, double* vxs, double* vys,
     return M2P_OK;
 }
 
+}  // extern "C"
+
+namespace m2p {
+
+// Outflow volumes (m^3) of both phases from the per-face running integrals
+// ([4 sides][nmax][2]), summed on the host in a fixed order: side by side,
+// face by face.
+int outflow_volumes(const double* bpart_dev, int nmax, int nx, int ny, const KParams& K, hipStream_t st,
+                    double* out_s, double* out_f)
+{
+    std::vector<double> acc((size_t)4 * nmax * 2);
+    HIPCHK(hipMemcpyAsync(acc.data(), bpart_dev, acc.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double o[2] = {0.0, 0.0};
+    for (int side = 0; side < 4; side++) {
+        const int n = side < 2 ? ny : nx;
+        for (int k = 0; k < n; k++)
+            for (int ph = 0; ph < 2; ph++) o[ph] += acc[((size_t)side * nmax + k) * 2 + ph];
+    }
+    const double vs = K.H * K.L * K.L;  // dimensionless volume -> m^3
+    *out_s = o[0] * vs;
+    *out_f = o[1] * vs;
+    return M2P_OK;
+}
+
+}  // namespace m2p
+
+extern "C" {
+
 int m2p_get_diag(m2p_ctx* c, m2p_diag* d)
 {
     if (!c || !d) return fail(M2P_EINVAL, "NULL argument");
@@ -1075,8 +1194,8 @@ int m2p_get_diag(m2p_ctx* c, m2p_diag* d)
     d->dt_next = hs.dt * c->kp.T;
     d->in_s = hs.in_s;
     d->in_f = hs.in_f;
-    d->out_s = hs.out_s;
-    d->out_f = hs.out_f;
+    rc = outflow_volumes(c->bpart, c->B.nmax, c->g.nx, c->g.ny, c->kp, c->stream, &d->out_s, &d->out_f);
+    if (rc) return rc;
     d->steps = hs.steps;
     d->clamp_count = (int64_t)hs.clamps;
     d->status = (int32_t)hs.status;
@@ -1407,13 +1526,14 @@ int m2p_adjoint_run(m2p_ctx* c, int64_t nsteps, int32_t ckpt_every, const double
     const size_t n = (size_t)c->g.nx * c->g.ny, sb = c->state_bytes;
     const int nseg = (int)((nsteps + ckpt_every - 1) / ckpt_every);
     const int seglen = (int)std::min<int64_t>(ckpt_every, nsteps);
-    DevBuf ckpt, sck, dts, tapeU, tapeUs, lam, lamv, gmu, tgt, fin, sfin;
+    DevBuf ckpt, sck, dts, tapeU, tapeUs, lam, lamv, gmu, tgt, fin, sfin, bscr;
     VjpWork w;
     if ((rc = ckpt.alloc(sb * nseg)) || (rc = sck.alloc(sizeof(DevScalars) * nseg)) ||
         (rc = dts.alloc(8 * nsteps)) || (rc = tapeU.alloc(sb * seglen)) || (rc = tapeUs.alloc(sb * seglen)) ||
         (rc = lam.alloc(sb)) || (rc = lamv.alloc(sb)) ||
         (rc = gmu.alloc((size_t)K.ny * K.pitch * c->esz)) || (rc = tgt.alloc(n * 8)) || (rc = fin.alloc(sb)) ||
-        (rc = sfin.alloc(sizeof(DevScalars))) || (rc = w.alloc(c)))
+        (rc = sfin.alloc(sizeof(DevScalars))) || (rc = w.alloc(c)) ||
+        (rc = bscr.alloc(sizeof(double) * (outflow_dt_index(c->B.nmax) + 2))))
         return rc;
     HIPCHK(hipMemcpy(tgt.p, target_h, n * 8, hipMemcpyHostToDevice));
     const hipStream_t st = c->stream;
@@ -1467,6 +1587,7 @@ int m2p_adjoint_run(m2p_ctx* c, int64_t nsteps, int32_t ckpt_every, const double
                               hipMemcpyDeviceToDevice, st));
         for (int64_t s = n0; s < n1; s++) {
             Bufs tb = c->B;
+            tb.bpart = (double*)bscr.p;  // the recomputation adds nothing to the outflow integrals
             tb.U = (char*)tapeU.p + sb * (s - n0);
             tb.Us = (char*)tapeUs.p + sb * (s - n0);
             HIPCHK(step_part(c, tb, 0));

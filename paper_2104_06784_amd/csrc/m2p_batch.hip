@@ -41,6 +41,7 @@ struct m2p_batch {
     double* staging = nullptr;
     size_t staging_cells = 0;
     size_t u_bytes = 0;
+    size_t bp_total = 0;  // doubles of the boundary-slot arena
     void* scen = nullptr;  // ScenDesc<T>[nscen] on the device
     int* work = nullptr;
     int nwork = 0;
@@ -269,13 +270,14 @@ int m2p_batch_create(m2p_batch** out, int32_t nscen, const m2p_grid* grids, cons
         B->nwcap.push_back(nw);
         B->nw_ref.push_back(nbx * nby);
         B->bp_off.push_back(bp);
-        bp += (size_t)2 * 4 * 2 * nm;
+        bp += outflow_dt_index(nm) + 2;  // keeps each scenario's block 16-byte aligned
         B->wp_off.push_back(wp);
         wp += (size_t)2 * 4 * nw;
         maxcells = std::max(maxcells, (size_t)K.nx * K.ny);
     }
     B->has_state.assign(nscen, 0);
     B->u_bytes = ub;
+    B->bp_total = bp;
     if (hipMalloc(&B->U, ub) != hipSuccess || hipMalloc(&B->Us, ub) != hipSuccess ||
         hipMalloc(&B->b, bb) != hipSuccess || hipMalloc(&B->S, nscen * sizeof(DevScalars)) != hipSuccess ||
         hipMalloc(&B->bpart, bp * sizeof(double)) != hipSuccess ||
@@ -443,8 +445,9 @@ int m2p_batch_get_diag(m2p_batch* B, int32_t i, m2p_diag* d)
     d->dt_next = hs.dt * K.T;
     d->in_s = hs.in_s;
     d->in_f = hs.in_f;
-    d->out_s = hs.out_s;
-    d->out_f = hs.out_f;
+    const int rc = outflow_volumes(B->bpart + B->bp_off[i], B->nmax[i], K.nx, K.ny, K, B->stream, &d->out_s,
+                                   &d->out_f);
+    if (rc) return rc;
     d->steps = hs.steps;
     d->clamp_count = (int64_t)hs.clamps;
     d->status = (int32_t)hs.status;
@@ -492,12 +495,17 @@ int m2p_batch_autotune(m2p_batch* B, int32_t trial_steps, int32_t* rows_out, int
     if (rc) return rc;
     void* backup = nullptr;
     DevScalars* sback = nullptr;
-    if (hipMalloc(&backup, B->u_bytes) != hipSuccess || hipMalloc(&sback, B->nscen * sizeof(DevScalars)) != hipSuccess) {
+    double* bback = nullptr;
+    const size_t bbytes = B->bp_total * sizeof(double);
+    if (hipMalloc(&backup, B->u_bytes) != hipSuccess || hipMalloc(&sback, B->nscen * sizeof(DevScalars)) != hipSuccess ||
+        hipMalloc(&bback, bbytes) != hipSuccess) {
         if (backup) (void)hipFree(backup);
+        if (sback) (void)hipFree(sback);
         return fail(M2P_ENOMEM, "autotune backup allocation failed");
     }
     HIPCHK(hipMemcpyAsync(backup, B->U, B->u_bytes, hipMemcpyDeviceToDevice, B->stream));
     HIPCHK(hipMemcpyAsync(sback, B->S, B->nscen * sizeof(DevScalars), hipMemcpyDeviceToDevice, B->stream));
+    HIPCHK(hipMemcpyAsync(bback, B->bpart, bbytes, hipMemcpyDeviceToDevice, B->stream));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -523,6 +531,7 @@ int m2p_batch_autotune(m2p_batch* B, int32_t trial_steps, int32_t* rows_out, int
             }
             HIPCHK(hipMemcpyAsync(B->U, backup, B->u_bytes, hipMemcpyDeviceToDevice, B->stream));
             HIPCHK(hipMemcpyAsync(B->S, sback, B->nscen * sizeof(DevScalars), hipMemcpyDeviceToDevice, B->stream));
+            HIPCHK(hipMemcpyAsync(B->bpart, bback, bbytes, hipMemcpyDeviceToDevice, B->stream));
         }
         if (rc) break;
     }
@@ -531,6 +540,7 @@ int m2p_batch_autotune(m2p_batch* B, int32_t trial_steps, int32_t* rows_out, int
     (void)hipEventDestroy(e1);
     (void)hipFree(backup);
     (void)hipFree(sback);
+    (void)hipFree(bback);
     B->graph_chunk = saved_chunk;
     int rc2 = set_shape(B, bestR, bestB);
     if (rc) return rc;

@@ -64,6 +64,18 @@ struct DevScalars {
     long long log_base, n_log;         //   dt_log[steps - log_base] when that index is in [0, n_log)
 };
 
+// Boundary outflow integrals, [4 sides][nmax][2 phases] doubles: each step
+// adds, per boundary face and stage in stage order, the stage's quadrature
+// weight times dt times its volume flux through the face to that face's
+// running integral (Heun: dt/2, dt/2; the three-stage method: dt/6, dt/6,
+// 2 dt/3).  The stages store their fluxes in slots and the finalize adds them
+// (one thread per face), so each integral is a fixed-order sum; they are
+// summed over the faces on demand.
+constexpr double stage_weight(int kind, int rk)
+{
+    return kind == 1 ? (rk == 3 ? 1.0 / 6.0 : 0.5) : (kind == 2 ? 0.5 : (kind == 3 ? 1.0 / 6.0 : 2.0 / 3.0));
+}
+
 // Stage kinds of a step.  Heun, the paper's two-step modified Euler method:
 // kinds 1 then 2.  Three-stage SSP Runge-Kutta: kinds 1, 3, 4.
 //   1: U1 = E(U^n)   2: (U^n + E(U1)) / 2   3: 3/4 U^n + 1/4 E(U1)

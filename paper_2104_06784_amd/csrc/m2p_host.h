@@ -18,6 +18,8 @@ size_t round_up(size_t a, size_t m);
 int validate_scenario(const m2p_grid* g, const m2p_params* p, int32_t prec, const double* dem);
 KParams make_kparams(const m2p_grid* g, const m2p_params* p, bool has_mu);
 std::vector<double> padded_dem(const KParams& K, const double* dem, double L);
+int outflow_volumes(const double* bpart_dev, int nmax, int nx, int ny, const KParams& K, hipStream_t st,
+                    double* out_s, double* out_f);
 
 }  // namespace m2p
 

@@ -122,6 +122,47 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh)
     for (int q = 0; q < NV; q++) v[q] = sh[q * NT];
 }
 
+// Outflow through one boundary face in one stage: f0, f1 = the sign-adjusted
+// volume flux of each phase times the face length, stored in the stage's slot
+// of bpart ([kOutSlots][4][nmax][2]: slot 0 holds the running integrals, slot
+// 1 + s stage slot s; then the step's dt at outflow_dt_index).  The finalize
+// adds the weighted slots to the integrals (a read-modify-write of the
+// integral here would keep its address, value and weight live across the
+// march).
+__device__ __forceinline__ void put_outflow(double* __restrict__ bpart, int nmax, int slot, int side, int k,
+                                            double f0, double f1)
+{
+    double* v = bpart + ((size_t)((1 + slot) * 4 + side) * nmax + k) * 2;
+    v[0] = f0;
+    v[1] = f1;
+}
+
+// quadrature weight of stage slot s (the stage kinds of stage_slot, in order)
+__device__ __forceinline__ double slot_weight(int s, int rk)
+{
+    return stage_weight(s == 0 ? 1 : (rk == 2 ? 2 : (s == 1 ? 3 : 4)), rk);
+}
+
+// Boundary face q ([4][nmax], side-major): the step's stage fluxes, each
+// times its weight times dt, added to the face's running integral in stage
+// order.
+__device__ __forceinline__ void outflow_accumulate(const KParams& P, double* __restrict__ bpart, int nmax, int q)
+{
+    const int side = q / nmax, k = q - side * nmax;
+    if (side >= 4 || k >= (side < 2 ? P.ny : P.nx)) return;
+    const double dt = bpart[outflow_dt_index(nmax)];
+    double* acc = bpart + (size_t)q * 2;
+    const size_t slot = (size_t)4 * nmax * 2;
+    double a0 = acc[0], a1 = acc[1];
+    for (int s = 0; s < P.rk; s++) {
+        const double w = slot_weight(s, P.rk) * dt;
+        a0 += w * acc[(s + 1) * slot];
+        a1 += w * acc[(s + 1) * slot + 1];
+    }
+    acc[0] = a0;
+    acc[1] = a1;
+}
+
 // -------------------------------------------------- reference stage kernel
 
 // One thread per cell; every stencil value is read from memory.  STAGE is
@@ -183,41 +224,39 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
             reconstruct(w, uL, uR);
             face_flux_sel(K, P.flags, uL, gC, uR, gN, 1, HYt, kep(i, j, 1), kep(i, j + 1, 1));
         }
-        // Mode-II faces, and the flux through every boundary face into the
-        // per-face outflow slots (zero on discharge-inflow faces)
+        // Mode-II faces, and the flux through every boundary face into its
+        // running outflow integral (zero on discharge-inflow faces)
         const double (*inf)[4] = S->inflow[stage_slot(STAGE)];
-        const int st = stage_slot(STAGE);
+        constexpr int sl = stage_slot(STAGE);
+        // the step's dt (in the state's precision, as the updates use it)
+        if (STAGE == 1 && i == 0 && j == 0) bpart[outflow_dt_index(nmax)] = (double)dt;
         if (i == 0) {
             int s = inflow_seg_at(P, 0, j);
             if (s >= 0)
                 inflow_flux(K, gC, 0, +1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HXl);
-            double* bp = bpart + ((size_t)(st * 4 + 0) * nmax + j) * 2;
-            bp[0] = s >= 0 ? 0.0 : -(double)HXl[0] * P.deta;
-            bp[1] = s >= 0 ? 0.0 : -(double)HXl[3] * P.deta;
+            put_outflow(bpart, nmax, sl, 0, j, s >= 0 ? 0.0 : -(double)HXl[0] * P.deta,
+                        s >= 0 ? 0.0 : -(double)HXl[3] * P.deta);
         }
         if (i == P.nx - 1) {
             int s = inflow_seg_at(P, 1, j);
             if (s >= 0)
                 inflow_flux(K, gC, 0, -1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HXr);
-            double* bp = bpart + ((size_t)(st * 4 + 1) * nmax + j) * 2;
-            bp[0] = s >= 0 ? 0.0 : (double)HXr[0] * P.deta;
-            bp[1] = s >= 0 ? 0.0 : (double)HXr[3] * P.deta;
+            put_outflow(bpart, nmax, sl, 1, j, s >= 0 ? 0.0 : (double)HXr[0] * P.deta,
+                        s >= 0 ? 0.0 : (double)HXr[3] * P.deta);
         }
         if (j == 0) {
             int s = inflow_seg_at(P, 2, i);
             if (s >= 0)
                 inflow_flux(K, gC, 1, +1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HYb);
-            double* bp = bpart + ((size_t)(st * 4 + 2) * nmax + i) * 2;
-            bp[0] = s >= 0 ? 0.0 : -(double)HYb[0] * P.dxi;
-            bp[1] = s >= 0 ? 0.0 : -(double)HYb[3] * P.dxi;
+            put_outflow(bpart, nmax, sl, 2, i, s >= 0 ? 0.0 : -(double)HYb[0] * P.dxi,
+                        s >= 0 ? 0.0 : -(double)HYb[3] * P.dxi);
         }
         if (j == P.ny - 1) {
             int s = inflow_seg_at(P, 3, i);
             if (s >= 0)
                 inflow_flux(K, gC, 1, -1, T(inf[s][0]), T(inf[s][1]), T(inf[s][2]), T(inf[s][3]), HYt);
-            double* bp = bpart + ((size_t)(st * 4 + 3) * nmax + i) * 2;
-            bp[0] = s >= 0 ? 0.0 : (double)HYt[0] * P.dxi;
-            bp[1] = s >= 0 ? 0.0 : (double)HYt[3] * P.dxi;
+            put_outflow(bpart, nmax, sl, 3, i, s >= 0 ? 0.0 : (double)HYt[0] * P.dxi,
+                        s >= 0 ? 0.0 : (double)HYt[3] * P.dxi);
         }
         // sources
         const T* uC = row[2];
@@ -520,20 +559,20 @@ __device__ __forceinline__ void ghost_state(const KParams& P, const double* tabl
     u[5] = mf * v * ey;
 }
 
-// values 24, 25 and 27 combine by max, the others by sum
-__device__ __forceinline__ bool fin_is_max(int k) { return k == 24 || k == 25 || k == 27; }
+// values 0, 1 (speed maxima) and 3 (non-finite flag) combine by max, value 2
+// (clamp count) by sum
+__device__ __forceinline__ bool fin_is_max(int k) { return k != 2; }
 
-// Reduction of every partial list by one workgroup of NT threads into
-// out[kFinVals] (shared memory): the per-face outflow slots of each stage and
-// side (both phases in one 16-byte slot) and the per-wave speed maxima, clamp
-// counts and non-finite flags.  The workgroup runs alone, so it is bound by
-// latency: every thread issues its loads of all lists together (one memory
-// round trip per batch, not per list), then the per-thread shares are
-// combined in two short passes over shared memory.  Fixed order throughout
-// (deterministic).
+// Reduction of the per-wave (or per-block) partial records of a step by one
+// workgroup of NT threads into out[kFinVals] (shared memory): the speed
+// maxima of the stage that ends the step and the positivity-clamp counts and
+// non-finite flags of every stage.  Every thread issues its loads of all
+// records together (one memory round trip per batch), then the per-thread
+// shares are combined in two short passes over shared memory.  Fixed order
+// throughout (deterministic).
 template <int NT>
-__device__ __forceinline__ void fin_reduce(const KParams& P, const double* __restrict__ bpart, int n_we, int n_sn,
-                                           int nmax, int mode, const double* __restrict__ wpart, int nw, double* out)
+__device__ __forceinline__ void fin_reduce(const KParams& P, int mode, const double* __restrict__ wpart, int nw,
+                                           double* out)
 {
     constexpr int NCH = NT / 32;  // chunks per value in the first combining pass
     constexpr int CH = NT / NCH;  // shares per chunk
@@ -542,33 +581,6 @@ __device__ __forceinline__ void fin_reduce(const KParams& P, const double* __res
     __shared__ double sh2[kFinVals][NCH];
     const int tid = threadIdx.x;
     const int last = P.rk - 1;  // slot of the stage that ends the step
-    const int nlist = mode == 0 ? P.rk * 4 : 0;
-    const int nl_max = nlist == 0 ? 0 : (n_we > n_sn ? n_we : n_sn);
-    const double2* bp2 = reinterpret_cast<const double2*>(bpart);
-    double acc[24];
-#pragma unroll
-    for (int k = 0; k < 24; k++) acc[k] = 0.0;
-    for (int q0 = tid; q0 < nl_max; q0 += NT * 2) {
-        double2 v[12][2];
-#pragma unroll
-        for (int l = 0; l < 12; l++) {
-            const int n = (l & 3) < 2 ? n_we : n_sn;
-#pragma unroll
-            for (int u = 0; u < 2; u++) {
-                const int q = q0 + NT * u;
-                v[l][u] = (l < nlist && q < n) ? bp2[(size_t)l * nmax + q] : make_double2(0.0, 0.0);
-            }
-        }
-#pragma unroll
-        for (int l = 0; l < 12; l++)
-#pragma unroll
-            for (int u = 0; u < 2; u++) {
-                acc[2 * l] += v[l][u].x;
-                acc[2 * l + 1] += v[l][u].y;
-            }
-    }
-#pragma unroll
-    for (int k = 0; k < 24; k++) sh[k][tid] = acc[k];
     {
         double ax = 0.0, ay = 0.0, cl = 0.0, bd = 0.0;
         const double4* wl = reinterpret_cast<const double4*>(wpart) + (size_t)nw * last;  // last stage's slots
@@ -592,10 +604,10 @@ __device__ __forceinline__ void fin_reduce(const KParams& P, const double* __res
                 bd = fmax(bd, fmax(v[u].w, fmax(e[u].w, f[u].w)));
             }
         }
-        sh[24][tid] = ax;
-        sh[25][tid] = ay;
-        sh[26][tid] = cl;
-        sh[27][tid] = bd;
+        sh[0][tid] = ax;
+        sh[1][tid] = ay;
+        sh[2][tid] = cl;
+        sh[3][tid] = bd;
     }
     __syncthreads();
     // pass 1: thread (k, c) combines chunk c (CH consecutive shares) of value k
@@ -622,40 +634,33 @@ __device__ __forceinline__ void fin_reduce(const KParams& P, const double* __res
     __syncthreads();
 }
 
-// Serial tail of the finalize (one thread), from the reduced values part[].
-// mode 0: close the step just taken (time, boundary integrals); both modes:
-// next CFL dt from the speed maxima, inflow states of the next step's stages,
-// status flags and clamp count.
+// Serial tail of the finalize (one thread), from the reduced values part[]
+// (speed maxima, clamp count, non-finite flag).  mode 0: close the step just
+// taken (time, inflow integrals; the outflow integrals are kept per boundary
+// face by the stage kernels); both modes: next CFL dt from the speed maxima,
+// inflow states of the next step's stages, status flags and clamp count.
 __device__ __forceinline__ void fin_tail(const KParams& P, DevScalars* S, const double* part,
                                          const double* __restrict__ tables, int mode)
 {
-    double ax = part[24], ay = part[25];
-    if (part[27] > 0.0) S->status |= 1u;
-    S->clamps += (unsigned long long)part[26];
+    double ax = part[0], ay = part[1];
+    if (part[3] > 0.0) S->status |= 1u;
+    S->clamps += (unsigned long long)part[2];
     double t = S->t;
     if (mode == 0) {
         const double dt = S->dt;
         const double vs = P.H * P.L * P.L;  // dimensionless volume -> m^3
         for (int ph = 0; ph < 2; ph++) {
-            double B[3] = {0.0, 0.0, 0.0};
-            for (int st = 0; st < P.rk; st++)
-                for (int side = 0; side < 4; side++) B[st] += part[(st * 4 + side) * 2 + ph];
-            double out, in;
+            double in;
             if (P.rk == 3) {
-                out = dt * (B[0] / 6.0 + B[1] / 6.0 + 2.0 * B[2] / 3.0);
                 in = dt * (inflow_rate(P, tables, t, ph) / 6.0 + inflow_rate(P, tables, t + dt, ph) / 6.0 +
                            2.0 * inflow_rate(P, tables, t + 0.5 * dt, ph) / 3.0);
             } else {
-                out = 0.5 * dt * (B[0] + B[1]);
                 in = 0.5 * dt * (inflow_rate(P, tables, t, ph) + inflow_rate(P, tables, t + dt, ph));
             }
-            if (ph == 0) {
-                S->out_s += out * vs;
+            if (ph == 0)
                 S->in_s += in * vs;
-            } else {
-                S->out_f += out * vs;
+            else
                 S->in_f += in * vs;
-            }
         }
         if (dt > 0.0) {
             t += dt;
@@ -726,27 +731,33 @@ __device__ __forceinline__ void fin_tail_staged(const KParams& P, DevScalars* S,
     for (int k = threadIdx.x; k < NWORD; k += blockDim.x) g[k] = l[k];
 }
 
-// Per-step finalize: one workgroup reduces every partial list (fixed order),
-// then thread 0 runs the tail.  (At 4096 x 4096 it takes about 30 us whether
-// the reduction is spread over 32 workgroups or not, so it stays one.)
-// The hydrograph tables of the Mode-II segments are copied into shared memory
-// first when they fit (the tail's table lookups are serial searches, each
-// step of which would otherwise wait on device memory).
+// Per-step finalize: workgroup 0 reduces the partial records (fixed order),
+// then thread 0 runs the tail; in a step (mode 0) the other workgroups, one
+// thread per boundary face, add the stages' outflow values to the running
+// integrals (launched with 1 + ceil(4 nmax / NT) workgroups).  The hydrograph
+// tables of the Mode-II segments are copied into shared memory first when
+// they fit (the tail's table lookups are serial searches, each step of which
+// would otherwise wait on device memory).
 constexpr int kFinTabLds = 2048;
 
 template <typename T, int NT = kFinThreads>
 __global__ void __launch_bounds__(NT)
-k_finalize(KParams P, DevScalars* S, const double* __restrict__ bpart, int n_we, int n_sn, int nmax,
-           const double* __restrict__ tables, int mode, const double* __restrict__ wpart, int nw)
+k_finalize(KParams P, DevScalars* S, const double* __restrict__ tables, int mode, const double* __restrict__ wpart,
+           int nw, double* __restrict__ bpart, int nmax)
 {
+    if (blockIdx.x > 0) {
+        outflow_accumulate(P, bpart, nmax, (blockIdx.x - 1) * NT + threadIdx.x);
+        return;
+    }
     __shared__ double red[kFinVals];
     __shared__ double tab[kFinTabLds];
     const bool lds_tab = P.ntab > 0 && P.ntab <= kFinTabLds;
     if (lds_tab)
         for (int k = threadIdx.x; k < P.ntab; k += blockDim.x) tab[k] = tables[k];
-    fin_reduce<NT>(P, bpart, n_we, n_sn, nmax, mode, wpart, nw, red);
+    fin_reduce<NT>(P, mode, wpart, nw, red);
     fin_tail_staged(P, S, red, lds_tab ? tab : tables, mode);
 }
+
 
 // ------------------------------------------------- conversions, reductions
 

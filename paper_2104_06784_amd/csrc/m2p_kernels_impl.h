@@ -18,14 +18,13 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
     const T* b = (const T*)B.b;
     const T* mu = (const T*)B.mu;
     if (part == P.rk) {
-        // small grids: one wavefront (shorter combining passes, the lists
-        // give each lane only a few loads)
-        if (sh.n_we <= 256 && sh.n_sn <= 256 && sh.nw <= 512)
-            hipLaunchKernelGGL((k_finalize<T, 64>), dim3(1), dim3(64), 0, st, P, B.S, B.bpart, sh.n_we, sh.n_sn,
-                               B.nmax, B.tables, 0, B.wpart, sh.nw);
+        // small grids: one wavefront (shorter combining passes)
+        if (sh.nw <= 512)
+            hipLaunchKernelGGL((k_finalize<T, 64>), dim3(1 + (4 * B.nmax + 63) / 64), dim3(64), 0, st, P, B.S,
+                               B.tables, 0, B.wpart, sh.nw, B.bpart, B.nmax);
         else
-            hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(kFinThreads), 0, st, P, B.S, B.bpart, sh.n_we,
-                               sh.n_sn, B.nmax, B.tables, 0, B.wpart, sh.nw);
+            hipLaunchKernelGGL((k_finalize<T>), dim3(1 + (4 * B.nmax + kFinThreads - 1) / kFinThreads),
+                               dim3(kFinThreads), 0, st, P, B.S, B.tables, 0, B.wpart, sh.nw, B.bpart, B.nmax);
         return hipGetLastError();
     }
     // Heun: E(U) -> Us, then (U + E(Us)) / 2 -> U.  Three-stage: E(U) -> Us,
@@ -33,10 +32,10 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
     const int kind = part == 0 ? 1 : (P.rk == 2 ? 2 : (part == 1 ? 3 : 4));
     const T* in = part == 0 ? U : (kind == 4 ? Us2 : Us);
     T* out = part == 0 ? Us : (kind == 3 ? Us2 : (B.Uout ? (T*)B.Uout : U));
-    if (P.flags & kFlagEarthPressure) {
-        // the option's coefficients of the stage input; the reference kernel
-        // runs the stage (make_shape selects it for such contexts)
-        if (sh.variant != 1 || !B.kep) return hipErrorInvalidValue;
+    if ((P.flags & kFlagEarthPressure) && sh.variant == 1) {
+        // the option's coefficients of the stage input for the reference
+        // kernel (the tiled kernel computes them in its march)
+        if (!B.kep) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_earth_pressure<T>), dim3(sh.nbx, sh.nby), dim3(64, 4), 0, st, P, in, b, mu,
                            (T*)B.kep);
     }
@@ -56,21 +55,23 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
 #undef M2P_REF
     } else {
         dim3 blk(256), grd(sh.blocks);
-#define M2P_TILED_GC(K, GH, CU)                                                                                 \
-    hipLaunchKernelGGL((k_stage_tiled<T, K, GH, CU>), grd, blk, 0, st, P, in, U, out, b, mu, B.S, B.bpart,      \
+#define M2P_TILED_GC(K, GH, CU, EP)                                                                             \
+    hipLaunchKernelGGL((k_stage_tiled<T, K, GH, CU, EP>), grd, blk, 0, st, P, in, U, out, b, mu, B.S, B.bpart,  \
                        B.wpart, B.nmax, sh.R, sh.nstrips, sh.nrb)
 #define M2P_TILED(K)                                                                                            \
     do {                                                                                                        \
         const bool cu = (P.flags & kFlagCentralUpwind) != 0;                                                    \
-        if (P.nsseg > 0) {                                                                                      \
+        if (P.flags & kFlagEarthPressure)                                                                       \
+            M2P_TILED_GC(K, false, false, true);                                                                \
+        else if (P.nsseg > 0) {                                                                                 \
             if (cu)                                                                                             \
-                M2P_TILED_GC(K, true, true);                                                                    \
+                M2P_TILED_GC(K, true, true, false);                                                             \
             else                                                                                                \
-                M2P_TILED_GC(K, true, false);                                                                   \
+                M2P_TILED_GC(K, true, false, false);                                                            \
         } else if (cu)                                                                                          \
-            M2P_TILED_GC(K, false, true);                                                                       \
+            M2P_TILED_GC(K, false, true, false);                                                                \
         else                                                                                                    \
-            M2P_TILED_GC(K, false, false);                                                                      \
+            M2P_TILED_GC(K, false, false, false);                                                               \
     } while (0)
         if (kind == 1)
             M2P_TILED(1);
@@ -92,8 +93,8 @@ hipError_t Launch<M2P_REAL>::init(const KParams& P, const Bufs& B, hipStream_t s
     using T = M2P_REAL;
     dim3 blk(64, 4), grd((P.nx + 63) / 64, (P.ny + 3) / 4);
     hipLaunchKernelGGL((k_speeds<T>), grd, blk, 0, st, P, (const T*)B.U, (const T*)B.b, (const T*)B.mu, B.wpart);
-    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(kFinThreads), 0, st, P, B.S, B.bpart, 0, 0, B.nmax, B.tables,
-                       1, B.wpart, B.nw_ref);
+    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(kFinThreads), 0, st, P, B.S, B.tables, 1, B.wpart, B.nw_ref,
+                       B.bpart, B.nmax);
     return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ struct Bufs {
     const void* b;         // padded DEM / L
     const void* mu;        // per-cell tan(delta_b) or nullptr
     DevScalars* S;         // device scalars
-    double* bpart;         // boundary outflow partials [stages][4][nmax][2]
+    double* bpart;         // outflow integrals and stage values per boundary face [kOutSlots][4][nmax][2]
     double* wpart;         // per-wave / per-block partials [stages][nw][4]
     const double* tables;  // inflow hydrographs
     double* mass_part;     // [2 * kMassBlocks]
@@ -39,7 +39,10 @@ constexpr int kMassBlocks = 1024;
 
 // Finalize: one workgroup of kFinThreads per scenario.
 constexpr int kFinThreads = 256;
-constexpr int kFinVals = 28;  // 24 boundary sums ([stage][side][phase]), 2 speed maxima, clamps, non-finite flag
+constexpr int kFinVals = 4;  // 2 speed maxima, clamps, non-finite flag
+constexpr int kOutSlots = 4;  // outflow integrals + the values of up to three stages
+// index of the step's dt in bpart, after the slots (the buffer holds 2 more doubles)
+constexpr size_t outflow_dt_index(int nmax) { return (size_t)kOutSlots * 4 * nmax * 2; }
 
 // Scenario record of a batched ensemble: constants and device pointers.
 template <typename T>

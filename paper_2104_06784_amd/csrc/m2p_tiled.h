@@ -56,10 +56,16 @@ struct RowD {
     T cdxu, cdxw;  // central x-differences of u, w
     T Jh;          // J_b h = m^s + m^f
     T Gf;          // J_b h pbar^f
+    T kx, ky;      // earth-pressure coefficients of the stage input (the option; else unused)
 };
 
-template <typename T>
-__device__ __forceinline__ void make_row(const Consts<T>& K, const T u[NF], T bC, T bS, T bN, RowD<T>& r)
+// With EP, also the row's earth-pressure coefficients from the solid
+// velocities of its x-neighbours (lane shifts) and of the rows below (uS) and
+// above (uN), with the cell's basal friction tmu -- the arithmetic of the
+// coefficient pass k_earth_pressure.
+template <typename T, bool EP = false>
+__device__ __forceinline__ void make_row(const Consts<T>& K, const T u[NF], T bC, T bS, T bN, RowD<T>& r,
+                                         const T* uS = nullptr, const T* uN = nullptr, T c2 = T(0), T tmu = T(0))
 {
     const T bE = from_right(bC), bW = from_left(bC);
     r.g = geometry(bE, bW, bN, bS, K.two_dxi, K.two_deta);
@@ -70,6 +76,13 @@ __device__ __forceinline__ void make_row(const Consts<T>& K, const T u[NF], T bC
     r.cdxw = cdiff(wE, wW, K.dxi);
     r.Jh = u[0] + u[3];
     r.Gf = fluid_G(u[0], u[3], r.g);
+    if constexpr (EP) {
+        const T vxs = dsg(u[1], u[0], K.md);
+        const T dvx = from_right(vxs) - from_left(vxs);
+        const T dvy = dsg(uN[2], uN[0], K.md) - dsg(uS[2], uS[0], K.md);
+        r.kx = ep_kx(c2, tmu, dvx >= T(0));
+        r.ky = ep_ky(r.kx, tmu, dvy >= T(0));
+    }
 }
 
 template <typename T>
@@ -90,10 +103,12 @@ __device__ __forceinline__ void visc_yface_rows(const RowD<T>& a, const RowD<T>&
 #ifndef M2P_TILED_WPE_S2
 #define M2P_TILED_WPE_S2 3
 #endif
-template <typename T, int STAGE>
+template <typename T, int STAGE, bool EP = false>
 constexpr int tiled_wpe()
 {
-    return sizeof(T) == 4 ? (STAGE == 1 ? M2P_TILED_WPE_S1 : M2P_TILED_WPE_S2) : 1;
+    // the earth-pressure instance carries the coefficients of three rows
+    // besides: two waves, no spills
+    return sizeof(T) == 4 ? (EP ? 2 : (STAGE == 1 ? M2P_TILED_WPE_S1 : M2P_TILED_WPE_S2)) : 1;
 }
 
 // Partials of one wavefront's share of a stage: speed maxima (last stage),
@@ -106,8 +121,10 @@ struct WavePart {
 // scenario; returns its partials (the same in every lane).  GH: the
 // scenario has Mode-II state segments, whose ghost cells replace the mapped
 // boundary values (a separate instance, so runs without them carry none of
-// that code in the march).  CU: central-upwind face fluxes.
-template <typename T, int STAGE, bool GH, bool CU = false>
+// that code in the march).  CU: central-upwind face fluxes.  EP: Savage-Hutter
+// earth-pressure coefficients, computed in the march for the row ahead (a
+// ghost cell takes those of the cell it maps to).
+template <typename T, int STAGE, bool GH, bool CU = false, bool EP = false>
 __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* __restrict__ Uin, const T* Un, T* Uout,
                                                  const T* __restrict__ b, const T* __restrict__ mu,
                                                  DevScalars* __restrict__ S, double* __restrict__ bpart,
@@ -174,15 +191,15 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
     };
     auto loadB = [&](int r) { return b[(size_t)(r + BHALO) * P.bpitch + bcol]; };
 
-    // flux through each boundary face goes to its own outflow slot (zero on
-    // discharge-inflow faces), reduced in a fixed order by the finalize
-    const int st = stage_slot(STAGE);
+    // flux through each boundary face into the stage's outflow slot (zero on
+    // discharge-inflow faces); the first stage records the step the updates
+    // use (dt in the state's precision: the volume that left the cells)
+    if (STAGE == 1 && strip == 0 && rb == 0 && lane == 0) bpart[outflow_dt_index(nmax)] = (double)dt;
     auto put_b = [&](int side, int k, bool inflow, T m_s, T m_f, double len) {
-        double* bp = bpart + ((size_t)(st * 4 + side) * nmax + k) * 2;
         constexpr double unit = carry_2h<T, H2>() ? 0.5 : 1.0;
         const double sg = (side == 0 || side == 2) ? -unit : unit;
-        bp[0] = inflow ? 0.0 : sg * (double)m_s * len;
-        bp[1] = inflow ? 0.0 : sg * (double)m_f * len;
+        put_outflow(bpart, nmax, stage_slot(STAGE), side, k,
+                    inflow ? 0.0 : sg * (double)m_s * len, inflow ? 0.0 : sg * (double)m_f * len);
     };
     T amx = T(0), amy = T(0);
     int clamps = 0, bad = 0;
@@ -195,8 +212,19 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
     loadU(r0 + 1, U1);
     T bm2 = loadB(r0 - 2), bm1 = loadB(r0 - 1), b0 = loadB(r0), b1 = loadB(r0 + 1);
     RowD<T> Dm, D0;  // rows j-1, j
-    make_row(K, Um1, bm1, bm2, b0, Dm);
-    make_row(K, U0, b0, bm1, b1, D0);
+    const T c2 = T(P.cos2_int);
+    // basal friction of row r (the earth-pressure coefficients need it)
+    auto tmu_row = [&](int r) {
+        if (!P.has_mu) return K.tan_d;
+        int f = 0;
+        return mu[(size_t)map_index(r, P.ny, P.bc[2], P.bc[3], f) * P.pitch + mi];
+    };
+    // lanes of the ghost columns next to the edges take the coefficient of
+    // the edge cell they map to (the lanes further out feed no used face)
+    const bool ghostW = col == -1, ghostE = col == P.nx;
+    make_row<T, EP>(K, Um1, bm1, bm2, b0, Dm, Um2, U0, c2, EP ? tmu_row(r0 - 1) : T(0));
+    make_row<T, EP>(K, U0, b0, bm1, b1, D0, Um1, U1, c2, EP ? tmu_row(r0) : T(0));
+    if (EP && r0 == 0) Dm.ky = D0.ky;  // ghost row -1 maps to row 0
     T sy0[NF];  // y-slopes of row r0
     T Hy[NF];            // y-face flux j - 1/2
     {
@@ -208,7 +236,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             uL[k] = Um1[k] + T(0.5) * sym[k];
             uR[k] = U0[k] - T(0.5) * sy0[k];
         }
-        central_flux<T, H2, CU>(K, uL, Dm.g, uR, D0.g, 1, Hy);
+        central_flux<T, H2, CU>(K, uL, Dm.g, uR, D0.g, 1, Hy, EP ? Dm.ky : T(1), EP ? D0.ky : T(1));
         if (r0 == 0 && out_lane) {
             const int s = inflow_seg_at(P, 2, col);
             if (s >= 0)
@@ -256,7 +284,8 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             for (int k = 0; k < NF; k++) unr[k] = Un[k * fs + cself];
         }
         const T tmu = P.has_mu ? mu[cself] : K.tan_d;
-        make_row(K, Un1, bj1, bj, bj2, D1);
+        make_row<T, EP>(K, Un1, bj1, bj, bj2, D1, Uc, U2, c2, EP ? tmu_row(j + 1) : T(0));
+        if (EP && j + 1 == P.ny) D1.ky = D0.ky;  // ghost row ny maps to row ny - 1
         T uL[NF], uR[NF];
 #pragma unroll
         for (int k = 0; k < NF; k++) {
@@ -265,7 +294,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             uR[k] = Un1[k] - T(0.5) * sy1[k];
         }
         // ---- y-face j + 1/2
-        central_flux<T, H2, CU>(K, uL, D0.g, uR, D1.g, 1, HyN);
+        central_flux<T, H2, CU>(K, uL, D0.g, uR, D1.g, 1, HyN, EP ? D0.ky : T(1), EP ? D1.ky : T(1));
         if (j == P.ny - 1 && out_lane) {
             const int s = inflow_seg_at(P, 3, col);
             if (s >= 0)
@@ -299,7 +328,13 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             gR.A12 = from_right(D0.g.A12);
             gR.A21 = gR.A12;
             gR.A22 = from_right(D0.g.A22);
-            central_flux<T, H2, CU>(K, um, D0.g, upR, gR, 0, Hx);
+            T kL = T(1), kR = T(1);
+            if constexpr (EP) {
+                const T fromE = from_right(D0.kx), fromW = from_left(D0.kx);
+                kL = ghostW ? fromE : (ghostE ? fromW : D0.kx);
+                kR = from_right(kL);
+            }
+            central_flux<T, H2, CU>(K, um, D0.g, upR, gR, 0, Hx, kL, kR);
 #pragma unroll
             for (int k = 0; k < NF; k++) HxL[k] = from_left(Hx[k]);
         }
@@ -365,7 +400,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             }
             if (stage_last(STAGE)) {
                 T sx, sy;
-                cell_speeds(K, out, D0.g, sx, sy);
+                cell_speeds(K, out, D0.g, sx, sy, EP ? ep_kmax(c2, tmu) : T(1));
                 amx = fmax(amx, sx);
                 amy = fmax(amy, sy);
             }
@@ -401,8 +436,8 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
     return WavePart{(double)amx, (double)amy, (double)clamps, (double)bad};
 }
 
-template <typename T, int STAGE, bool GH, bool CU>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_wpe<T, STAGE>())))
+template <typename T, int STAGE, bool GH, bool CU, bool EP = false>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_wpe<T, STAGE, EP>())))
 k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout, const T* __restrict__ b,
               const T* __restrict__ mu, DevScalars* __restrict__ S, double* __restrict__ bpart,
               double* __restrict__ wpart, int nmax, int R, int nstrips, int nrb)
@@ -422,12 +457,12 @@ k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout, const 
     const int strip = wid % nstrips, rb = wid / nstrips;
     WavePart r{0.0, 0.0, 0.0, 0.0};  // neutral: speeds are >= 0
     if (rb < nrb)  // whole wavefront
-        r = stage_tiled_wave<T, STAGE, GH, CU>(P, Uin, Un, Uout, b, mu, S, bpart, nmax, R, nstrips, nrb, strip, rb,
-                                                   lane);
+        r = stage_tiled_wave<T, STAGE, GH, CU, EP>(P, Uin, Un, Uout, b, mu, S, bpart, nmax, R, nstrips, nrb, strip,
+                                                       rb, lane);
     // one partial record per workgroup (its four wavefronts in order), so
-    // the finalize reads a quarter as many (at 4096 x 4096 the finalize
-    // takes 30 instead of 42 us; the barrier costs small grids about 0.4 us
-    // per stage)
+    // the finalize reads a quarter as many (the barrier costs small grids
+    // about 0.4 us per stage).  Plain stores: accumulating them with
+    // device-wide atomics on one address made the stage 10 % slower.
     __shared__ WavePart wsh[4];
     if (lane == 0) wsh[w] = r;
     __syncthreads();
@@ -509,9 +544,11 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize_batch(const ScenDesc<T
 {
     const ScenDesc<T>& D = scen[blockIdx.x];
     __shared__ double red[kFinVals];
-    fin_reduce<kFinThreads>(D.P, D.bpart, D.P.ny, D.P.nx, D.nmax, mode, D.wpart,
+    fin_reduce<kFinThreads>(D.P, mode, D.wpart,
                             mode == 1 ? D.nw_ref : D.nstrips * D.nrb, red);
     fin_tail_staged(D.P, D.S, red, D.tables, mode);
+    if (mode == 0)
+        for (int q = threadIdx.x; q < 4 * D.nmax; q += kFinThreads) outflow_accumulate(D.P, D.bpart, D.nmax, q);
 }
 
 }  // namespace m2p

@@ -129,6 +129,14 @@ class Sim:
             arr[k] = A.InflowState(s.side, s.i0, s.ncells, len(a[0]), *[A.dptr(x) for x in a])
         A.check(A.lib().m2p_set_inflow_states(self._h, arr, len(segs)), "m2p_set_inflow_states")
 
+    def autotune(self, trial_steps: int = 10):
+        """Time a few tile heights on this context (state restored after each
+        trial) and keep the fastest; returns (rows, ms per step)."""
+        r = C.c_int32()
+        ms = C.c_double()
+        A.check(A.lib().m2p_autotune(self._h, int(trial_steps), C.byref(r), C.byref(ms)), "m2p_autotune")
+        return r.value, ms.value
+
     # -- stepping
     def step(self) -> float:
         dt = C.c_double()

@@ -338,8 +338,8 @@ def test_earth_pressure_option_fp64(mu):
     """The Savage-Hutter earth-pressure option (M2P_F_EARTH_PRESSURE) against
     the oracle's: the plane-bump-pile problem with walls (delta_int 35 deg),
     with the uniform basal friction and with a per-cell friction field, and
-    combined with the three-stage method and the central-upwind flux; the
-    reference kernel runs the option whichever variant is asked for."""
+    combined with the three-stage method and the central-upwind flux (which
+    the reference kernel runs whichever variant is asked for)."""
     import dataclasses
     q = _ep_problem(mu=mu)
     for variant in (1, 2):
@@ -352,6 +352,44 @@ def test_earth_pressure_option_fp64(mu):
         q.params, flags=q.params.flags | I.F_RK3 | I.F_CENTRAL_UPWIND))
     r.name = q.name + "-rk3-cu"
     _compare_steps(r, 60, 1e-12, variant=1)
+
+
+def test_earth_pressure_tiled_bitwise_equal_reference():
+    """The tiled kernel's earth-pressure coefficients (computed in its march,
+    ghost cells taking those of the cells they map to) reproduce the reference
+    kernel's coefficient pass bitwise in FP64 -- state, dt and diagnostics --
+    at tile heights that do and do not divide the grid, on a ragged grid of
+    three strips with a wall and a transmissive side in each direction and a
+    per-cell friction field; in FP32 the results do not depend on the tile
+    height."""
+    import dataclasses
+    n_x, n_y, dx = 131, 77, 10.0
+    dem = I.fractal_dem(n_x, dx, 81, 60.0, tilt_deg=15.0, ny=n_y)
+    # two piles on opposite corners: every side is wet within the run
+    h = (I.cylinder(n_x, n_y, dx, dx, 1100.0, 650.0, 260.0, 8.0)
+         + I.cylinder(n_x, n_y, dx, dx, 200.0, 130.0, 250.0, 6.0))
+    p = I.Params(delta_b_deg=18.0, cfl=0.25, bc=(0, 1, 1, 0), flags=I.F_EARTH_PRESSURE, delta_int_deg=35.0)
+    prob = I.Problem("ep-rows", n_x, n_y, dx, dx, p, dem, h, np.where(h > 0, 0.5, 0.0), [])
+    prob.tan_mu = np.tan(np.radians(16.0 + 5.0 * I.smooth_field(n_x, 82, 4.0)[:n_y]))
+    a = Sim(prob, precision="f64", variant=1)
+    da = [a.step() for _ in range(120)]
+    Ua = a.state()
+    assert min(np.abs(Ua[0, :, 0]).max(), np.abs(Ua[0, :, -1]).max(), np.abs(Ua[0, 0, :]).max(),
+               np.abs(Ua[0, -1, :]).max()) > 0.1
+    for rows in (1, 7, n_y):
+        b = Sim(prob, precision="f64", variant=2, tile_rows=rows)
+        db = [b.step() for _ in range(120)]
+        _say(f"[ep rows] R={rows}: bitwise={np.array_equal(Ua, b.state())}")
+        assert da == db
+        assert np.array_equal(Ua, b.state())
+        assert a.diag() == b.diag()
+    ref = Sim(prob, precision="f32", variant=2, tile_rows=1)
+    ref.run(120)
+    for rows in (7, n_y):
+        b = Sim(prob, precision="f32", variant=2, tile_rows=rows)
+        b.run(120)
+        assert np.array_equal(b.state(), ref.state()), rows
+        assert b.diag() == ref.diag()
 
 
 def test_earth_pressure_fp32_and_refusals():
@@ -406,6 +444,29 @@ def test_smooth_friction_option():
     assert l1 <= 1e-3
     with pytest.raises(A.M2PError):
         Batch([prob], precision="f32")
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_autotune_restores_state_and_keeps_results(precision):
+    """The single-scenario tile-height tuner leaves no trace (state, time, step
+    count and outflow integrals put back bitwise), and the run continued at
+    the chosen height equals an untuned run bitwise."""
+    n_x, n_y, dx = 300, 220, 10.0
+    dem = I.fractal_dem(n_x, dx, 91, 80.0, tilt_deg=18.0, ny=n_y)
+    h = I.cylinder(n_x, n_y, dx, dx, 700.0, 1100.0, 300.0, 8.0)
+    p = I.Params(cfl=0.3, bc=(0, 0, 0, 0))
+    prob = I.Problem("tune", n_x, n_y, dx, dx, p, dem, h, np.where(h > 0, 0.6, 0.0))
+    a = Sim(prob, precision=precision)
+    a.run(40)
+    before, d0 = a.state(), a.diag()
+    rows, ms = a.autotune(3)
+    _say(f"[tune] {precision}: rows {rows}, {ms:.4f} ms/step")
+    assert 1 <= rows <= 64 and ms > 0
+    assert np.array_equal(before, a.state()) and a.diag() == d0
+    a.run(40)
+    b = Sim(prob, precision=precision)
+    b.run(80)
+    assert np.array_equal(a.state(), b.state()) and a.diag() == b.diag()
 
 
 def test_run_to_lands_on_end_time():
@@ -511,6 +572,48 @@ def test_fp32_against_fp64_oracle_mode2():
     # the paper's deposit metric: cells above 1 cm that disagree
     mism = np.sum((hg > 0.01) != (ho > 0.01))
     assert mism <= 0.0017 * max(1, np.sum(ho > 0.01))
+
+
+GOLDEN_CFG2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fractal_hydrograph_1024_5000.npz")
+
+
+def test_config2_full_size_against_oracle_fixture():
+    """The fractal-hydrograph workload at full size (1024^2 cells of 5 m, Mode-II
+    triangular hydrograph, 5000 steps) against the FP64 oracle's result stored
+    by tests/golden/make_fractal_hydrograph_1024.py (written by the oracle
+    alone).  FP64 path: the 5000 time steps to 1e-12 and the state to 1e-12
+    (max-norm, relative, per field).  FP32 path, run to the same model time:
+    relative L1 thickness error <= 1e-3, volume budget closed to 1e-6 with the
+    FP64 sums, and the paper's deposit metric (cells above 1 cm that disagree
+    <= 0.17 %)."""
+    z = np.load(GOLDEN_CFG2, allow_pickle=False)
+    diag = dict(zip(z["diag_keys"].tolist(), z["diag_vals"].tolist()))
+    prob = I.fractal_hydrograph()
+    _say(f"[cfg2] {prob.nx}^2, 5000 FP64 steps against the oracle fixture (t = {diag['t']:.3f} s)")
+    g = Sim(prob, precision="f64")
+    dtg = np.array([g.step() for _ in range(5000)])
+    np.testing.assert_allclose(dtg, z["dts"], rtol=1e-12, atol=0)
+    e = relerr(g.state(), z["U"])
+    d = g.diag()
+    _say(f"   FP64 max rel err {e:.3e}, t {d['t']:.6f} vs {diag['t']:.6f}")
+    assert e <= 1e-12
+    assert abs(d["t"] - diag["t"]) <= 1e-12 * diag["t"]
+    for k in ("in_s", "in_f", "out_s", "out_f"):
+        assert abs(d[k] - diag[k]) <= 1e-12 * max(abs(diag[k]), diag["in_s"]), k
+    _say("[cfg2] FP32 to the same model time")
+    g32 = Sim(prob, precision="f32")
+    g32.run_to(diag["t"])
+    h32, ho = g32.fields()["h"], z["h"]
+    l1 = np.abs(h32 - ho).sum() / ho.sum()
+    d = g32.diag()
+    vol = d["mass_s"] + d["mass_f"]
+    budget = abs(vol - (d["in_s"] + d["in_f"] - d["out_s"] - d["out_f"])) / vol
+    mism = np.sum((h32 > 0.01) != (ho > 0.01)) / max(1, np.sum(ho > 0.01))
+    vol_o = diag["mass_s"] + diag["mass_f"]
+    _say(f"   FP32 L1 rel {l1:.3e}  budget {budget:.3e}  volume vs oracle {abs(vol - vol_o) / vol_o:.3e}  "
+         f"deposit mismatch {mism:.4f}")
+    assert l1 <= 1e-3 and budget <= 1e-6 and mism <= 0.0017
+    assert abs(vol - vol_o) <= 1e-3 * vol_o
 
 
 def test_fp32_plane_bump_pile_close_to_fp64():
