@@ -88,6 +88,24 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
 }
 
 template <>
+int Launch<M2P_REAL>::resident_waves(const KParams& P)
+{
+    using T = M2P_REAL;
+    int dev = 0, cus = 0, nb = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    hipError_t e;
+    if (P.flags & kFlagEarthPressure)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stage_tiled<T, 2, false, false, true>, 256, 0);
+    else if (P.flags & kFlagCentralUpwind)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stage_tiled<T, 2, false, true, false>, 256, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stage_tiled<T, 2, false, false, false>, 256, 0);
+    return e == hipSuccess ? nb * 4 * cus : 0;
+}
+
+template <>
 hipError_t Launch<M2P_REAL>::init(const KParams& P, const Bufs& B, hipStream_t st)
 {
     using T = M2P_REAL;

@@ -59,13 +59,16 @@ struct ScenDesc {
     int nmax, nstrips, nrb, nw_ref;
 };
 
-Shape make_shape(const KParams& P, int variant, int rows);
+Shape make_shape(const KParams& P, int variant, int rows, int slots);
 
 template <typename T>
 struct Launch {
     // parts 0 .. P.rk - 1: the stages of a step, part P.rk: finalize
     static hipError_t step_part(const KParams& P, const Bufs& B, const Shape& sh, hipStream_t st, int part);
     static hipError_t init(const KParams& P, const Bufs& B, hipStream_t st);
+    // wavefronts of the tiled stage-2 kernel the current device holds at
+    // once (its occupancy times the compute units), 0 if unknown
+    static int resident_waves(const KParams& P);
     static hipError_t set_state(const KParams& P, const Bufs& B, const double* f, int vertical, int has_v,
                                 hipStream_t st);
     static hipError_t get_fields(const KParams& P, const Bufs& B, double* f, hipStream_t st);

@@ -59,13 +59,33 @@ struct RowD {
     T kx, ky;      // earth-pressure coefficients of the stage input (the option; else unused)
 };
 
+// Earth-pressure coefficients for a uniform basal friction t: K_x active and
+// passive, K_y for each K_x and each sign of the y-difference (kyap: K_x
+// active, K_y passive), computed once by the per-cell functions; kypp is also
+// the CFL bound ep_kmax.
+template <typename T>
+struct EPTab {
+    T kxa, kxp, kyaa, kyap, kypa, kypp;
+    __device__ __forceinline__ void init(T c2, T t)
+    {
+        kxa = ep_kx(c2, t, true);
+        kxp = ep_kx(c2, t, false);
+        kyaa = ep_ky(kxa, t, true);
+        kyap = ep_ky(kxa, t, false);
+        kypa = ep_ky(kxp, t, true);
+        kypp = ep_ky(kxp, t, false);
+    }
+};
+
 // With EP, also the row's earth-pressure coefficients from the solid
 // velocities of its x-neighbours (lane shifts) and of the rows below (uS) and
 // above (uN), with the cell's basal friction tmu -- the arithmetic of the
-// coefficient pass k_earth_pressure.
+// coefficient pass k_earth_pressure (with a uniform friction, uni, the
+// coefficients come from tab).
 template <typename T, bool EP = false>
 __device__ __forceinline__ void make_row(const Consts<T>& K, const T u[NF], T bC, T bS, T bN, RowD<T>& r,
-                                         const T* uS = nullptr, const T* uN = nullptr, T c2 = T(0), T tmu = T(0))
+                                         const T* uS = nullptr, const T* uN = nullptr, T c2 = T(0), T tmu = T(0),
+                                         bool uni = false, const EPTab<T>* tab = nullptr)
 {
     const T bE = from_right(bC), bW = from_left(bC);
     r.g = geometry(bE, bW, bN, bS, K.two_dxi, K.two_deta);
@@ -80,8 +100,13 @@ __device__ __forceinline__ void make_row(const Consts<T>& K, const T u[NF], T bC
         const T vxs = dsg(u[1], u[0], K.md);
         const T dvx = from_right(vxs) - from_left(vxs);
         const T dvy = dsg(uN[2], uN[0], K.md) - dsg(uS[2], uS[0], K.md);
-        r.kx = ep_kx(c2, tmu, dvx >= T(0));
-        r.ky = ep_ky(r.kx, tmu, dvy >= T(0));
+        if (uni) {
+            r.kx = dvx >= T(0) ? tab->kxa : tab->kxp;
+            r.ky = dvx >= T(0) ? (dvy >= T(0) ? tab->kyaa : tab->kyap) : (dvy >= T(0) ? tab->kypa : tab->kypp);
+        } else {
+            r.kx = ep_kx(c2, tmu, dvx >= T(0));
+            r.ky = ep_ky(r.kx, tmu, dvy >= T(0));
+        }
     }
 }
 
@@ -103,12 +128,15 @@ __device__ __forceinline__ void visc_yface_rows(const RowD<T>& a, const RowD<T>&
 #ifndef M2P_TILED_WPE_S2
 #define M2P_TILED_WPE_S2 3
 #endif
+// The earth-pressure instance carries the coefficients of three rows
+// besides: two waves, no spills.
+#ifndef M2P_TILED_WPE_EP
+#define M2P_TILED_WPE_EP 2
+#endif
 template <typename T, int STAGE, bool EP = false>
 constexpr int tiled_wpe()
 {
-    // the earth-pressure instance carries the coefficients of three rows
-    // besides: two waves, no spills
-    return sizeof(T) == 4 ? (EP ? 2 : (STAGE == 1 ? M2P_TILED_WPE_S1 : M2P_TILED_WPE_S2)) : 1;
+    return sizeof(T) == 4 ? (EP ? M2P_TILED_WPE_EP : (STAGE == 1 ? M2P_TILED_WPE_S1 : M2P_TILED_WPE_S2)) : 1;
 }
 
 // Partials of one wavefront's share of a stage: speed maxima (last stage),
@@ -222,8 +250,11 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
     // lanes of the ghost columns next to the edges take the coefficient of
     // the edge cell they map to (the lanes further out feed no used face)
     const bool ghostW = col == -1, ghostE = col == P.nx;
-    make_row<T, EP>(K, Um1, bm1, bm2, b0, Dm, Um2, U0, c2, EP ? tmu_row(r0 - 1) : T(0));
-    make_row<T, EP>(K, U0, b0, bm1, b1, D0, Um1, U1, c2, EP ? tmu_row(r0) : T(0));
+    const bool uni = !P.has_mu;
+    EPTab<T> tab;
+    if (EP && uni) tab.init(c2, K.tan_d);
+    make_row<T, EP>(K, Um1, bm1, bm2, b0, Dm, Um2, U0, c2, EP && !uni ? tmu_row(r0 - 1) : T(0), uni, &tab);
+    make_row<T, EP>(K, U0, b0, bm1, b1, D0, Um1, U1, c2, EP && !uni ? tmu_row(r0) : T(0), uni, &tab);
     if (EP && r0 == 0) Dm.ky = D0.ky;  // ghost row -1 maps to row 0
     T sy0[NF];  // y-slopes of row r0
     T Hy[NF];            // y-face flux j - 1/2
@@ -284,7 +315,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             for (int k = 0; k < NF; k++) unr[k] = Un[k * fs + cself];
         }
         const T tmu = P.has_mu ? mu[cself] : K.tan_d;
-        make_row<T, EP>(K, Un1, bj1, bj, bj2, D1, Uc, U2, c2, EP ? tmu_row(j + 1) : T(0));
+        make_row<T, EP>(K, Un1, bj1, bj, bj2, D1, Uc, U2, c2, EP && !uni ? tmu_row(j + 1) : T(0), uni, &tab);
         if (EP && j + 1 == P.ny) D1.ky = D0.ky;  // ghost row ny maps to row ny - 1
         T uL[NF], uR[NF];
 #pragma unroll
@@ -400,7 +431,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             }
             if (stage_last(STAGE)) {
                 T sx, sy;
-                cell_speeds(K, out, D0.g, sx, sy, EP ? ep_kmax(c2, tmu) : T(1));
+                cell_speeds(K, out, D0.g, sx, sy, EP ? (uni ? tab.kypp : ep_kmax(c2, tmu)) : T(1));
                 amx = fmax(amx, sx);
                 amy = fmax(amy, sy);
             }
