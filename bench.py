@@ -275,8 +275,9 @@ def bench_variants(stream, steps: int, prob3) -> dict:
 def bench_adjoint(stream, nsteps: int, ckpt: int) -> dict:
     """Calibration case (512^2): gradient of the deposit misfit with respect to the per-cell
     friction field and the release volume through nsteps FP32 steps
-    (checkpoint every ckpt steps, segments recomputed), against the plain
-    forward run of the same workload."""
+    (checkpoint every ckpt steps, segments recomputed; ckpt >= nsteps tapes
+    the whole forward run), against the plain forward run of the same
+    workload."""
     import torch
 
     from paper_2104_06784_amd import inputs
@@ -413,7 +414,9 @@ def main():
         log(f"[bench] batched {out['batched']['value']:.1f} Mcell-steps/s "
             f"({out['batched']['speedup_vs_one_by_one']:.2f}x one-by-one)")
     if args.adjoint_steps > 0:
-        out["fwd_adjoint"] = bench_adjoint(stream, args.adjoint_steps, 100)
+        # the whole run taped (2 x 2000 states of 6.3 MB fit in HBM easily):
+        # the forward writes the tape and the reverse sweep recomputes nothing
+        out["fwd_adjoint"] = bench_adjoint(stream, args.adjoint_steps, args.adjoint_steps)
         log(f"[bench] forward+adjoint {out['fwd_adjoint']['value']:.1f} Mcell-steps/s "
             f"({out['fwd_adjoint']['cost_vs_forward']:.1f}x the forward)")
     if args.sweep_steps > 0:

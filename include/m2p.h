@@ -370,9 +370,13 @@ int m2p_stage_vjp(m2p_ctx *c, int32_t stage, const double *lam, double *lam_in, 
 /* From the current state (the release scaled by vol_scale), run nsteps steps
  * storing a checkpoint every ckpt_every steps and the time steps, evaluate the
  * loss against target_h, then sweep backwards segment by segment (recomputing
- * each segment's states) through the transposed stages.  Returns the loss,
- * dL/d(tan delta_b) per cell (grad_mu, ny*nx, may be NULL) and dL/d(vol_scale)
- * (may be NULL).  The context ends at the forward run's final state. */
+ * each segment's states) through the transposed stages.  With ckpt_every >=
+ * nsteps the forward run writes the whole tape (U^n and U* of every step:
+ * 2 nsteps state buffers of device memory) and nothing is recomputed; the
+ * results are the same bits either way.  Returns the loss, dL/d(tan delta_b)
+ * per cell (grad_mu, ny*nx, may be NULL) and dL/d(vol_scale) (may be NULL).
+ * M2P_ENOMEM if the tape does not fit.  The context ends at the forward run's
+ * final state. */
 int m2p_adjoint_run(m2p_ctx *c, int64_t nsteps, int32_t ckpt_every, const double *target_h, double vol_scale,
                     double *loss, double *grad_mu, double *grad_vol);
 

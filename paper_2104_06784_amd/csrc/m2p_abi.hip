@@ -1579,12 +1579,32 @@ int m2p_adjoint_run(m2p_ctx* c, int64_t nsteps, int32_t ckpt_every, const double
             (void)hipMemcpy((char*)S + offsetof(DevScalars, dt_log), &off, sizeof(off), hipMemcpyHostToDevice);
         }
     } log_off{c->S, st};
-    // forward with checkpoints (graph-captured chunks between them)
-    for (int k = 0; k < nseg; k++) {
-        HIPCHK(hipMemcpyAsync((char*)ckpt.p + sb * k, c->B.U, sb, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync((char*)sck.p + sizeof(DevScalars) * k, c->S, sizeof(DevScalars),
-                              hipMemcpyDeviceToDevice, st));
-        if ((rc = issue_steps(c, std::min<int64_t>(ckpt_every, nsteps - (int64_t)k * ckpt_every)))) return rc;
+    // With one segment (ckpt_every >= nsteps) the forward itself writes the
+    // tape -- stage 1 reads U^s from tapeU[s] and writes U*^s to tapeUs[s],
+    // stage 2 writes U^{s+1} to tapeU[s+1] (the last step to the context's
+    // state) -- and the reverse sweep recomputes nothing.  Otherwise the
+    // forward keeps a checkpoint per segment (graph-captured chunks between
+    // them) and each segment is recomputed before its sweep.
+    const bool taped = nseg == 1;
+    if (taped) {
+        HIPCHK(hipMemcpyAsync(ckpt.p, c->B.U, sb, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(tapeU.p, c->B.U, sb, hipMemcpyDeviceToDevice, st));
+        for (int64_t s = 0; s < nsteps; s++) {
+            Bufs tb = c->B;
+            tb.U = (char*)tapeU.p + sb * s;
+            tb.Us = (char*)tapeUs.p + sb * s;
+            tb.Uout = s + 1 < nsteps ? (char*)tapeU.p + sb * (s + 1) : c->B.U;
+            HIPCHK(step_part(c, tb, 0));
+            HIPCHK(step_part(c, tb, 1));
+            HIPCHK(step_part(c, tb, 2));
+        }
+    } else {
+        for (int k = 0; k < nseg; k++) {
+            HIPCHK(hipMemcpyAsync((char*)ckpt.p + sb * k, c->B.U, sb, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync((char*)sck.p + sizeof(DevScalars) * k, c->S, sizeof(DevScalars),
+                                  hipMemcpyDeviceToDevice, st));
+            if ((rc = issue_steps(c, std::min<int64_t>(ckpt_every, nsteps - (int64_t)k * ckpt_every)))) return rc;
+        }
     }
     DevScalars hs;
     if ((rc = read_scalars(c, &hs)) || (rc = check_status(c, hs))) return rc;
@@ -1599,10 +1619,12 @@ int m2p_adjoint_run(m2p_ctx* c, int64_t nsteps, int32_t ckpt_every, const double
         // recompute the segment's states straight into the tapes: stage 1
         // reads U^s from tapeU[s] and writes U*^s to tapeUs[s]; stage 2 writes
         // U^{s+1} to tapeU[s+1].  The last step needs only its stage 1.
-        HIPCHK(hipMemcpyAsync(tapeU.p, (char*)ckpt.p + sb * sg, sb, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(c->S, (char*)sck.p + sizeof(DevScalars) * sg, sizeof(DevScalars),
-                              hipMemcpyDeviceToDevice, st));
-        for (int64_t s = n0; s < n1; s++) {
+        if (!taped) {
+            HIPCHK(hipMemcpyAsync(tapeU.p, (char*)ckpt.p + sb * sg, sb, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(c->S, (char*)sck.p + sizeof(DevScalars) * sg, sizeof(DevScalars),
+                                  hipMemcpyDeviceToDevice, st));
+        }
+        for (int64_t s = n0; s < n1 && !taped; s++) {
             Bufs tb = c->B;
             tb.bpart = (double*)bscr.p;  // the recomputation adds nothing to the outflow integrals
             tb.U = (char*)tapeU.p + sb * (s - n0);

@@ -194,6 +194,29 @@ def test_adjoint_fp32_close_to_fp64_and_reproducible():
     assert abs(a[2] - res["f64"][0][2]) <= 1e-2 * abs(res["f64"][0][2])
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_taped_adjoint_equals_checkpointed(prec):
+    """With one segment (ckpt_every >= nsteps) the forward run writes the tape
+    and nothing is recomputed; the loss, both gradients, the final state and
+    the diagnostics are the same bits as with checkpoints every 7 and every 25
+    steps (segments recomputed, the last one shorter)."""
+    import oracle
+    from paper_2104_06784_amd.sim import Sim
+    prob, _ = _calibration_case()
+    nsteps = 60
+    ot = oracle.OracleSim(prob)
+    ot.run(nsteps)
+    target = ot.fields()["h"] * 1.1
+    out = []
+    for ck in (nsteps, 1000, 7, 25):
+        g = Sim(prob, precision=prec)
+        r = g.adjoint_run(nsteps, ck, target, 1.0)
+        out.append((r, g.state(), g.diag()))
+    for r, U, d in out[1:]:
+        assert r[0] == out[0][0][0] and np.array_equal(r[1], out[0][0][1]) and r[2] == out[0][0][2]
+        assert np.array_equal(U, out[0][1]) and d == out[0][2]
+
+
 def test_autograd_function_matches_adjoint_and_descends():
     """DepositLoss (torch.autograd.Function over the adjoint) returns the
     library's gradient, and a few projected gradient steps on (mu, s) lower
