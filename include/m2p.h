@@ -97,6 +97,8 @@ extern "C" {
 #define M2P_VARIANT_AUTO 0
 #define M2P_VARIANT_REFERENCE 1 /* one thread per cell, every stencil value from memory */
 #define M2P_VARIANT_TILED 2     /* fused LDS-free column-marching stage kernel */
+#define M2P_VARIANT_TILED_GLOBAL 3 /* the tiled kernel with 64-bit global addresses instead of raw buffer
+                                      accesses, as used where the state or the DEM exceeds 2 GiB */
 
 typedef struct m2p_ctx m2p_ctx;
 

@@ -31,6 +31,7 @@ M2P_DEPTH_VERTICAL = 1
 M2P_VARIANT_AUTO = 0
 M2P_VARIANT_REFERENCE = 1
 M2P_VARIANT_TILED = 2
+M2P_VARIANT_TILED_GLOBAL = 3
 
 
 class Grid(C.Structure):

@@ -196,6 +196,7 @@ Shape make_shape(const KParams& P, int variant, int rows, int slots)
     const bool ep_ref =
         (P.flags & kFlagEarthPressure) && ((P.flags & kFlagCentralUpwind) || P.nsseg > 0);
     s.variant = (variant == M2P_VARIANT_REFERENCE || (P.flags & kFlagSmoothFriction) || ep_ref) ? 1 : 2;
+    s.global_addr = variant == M2P_VARIANT_TILED_GLOBAL;
     s.nbx = (P.nx + 63) / 64;
     s.nby = (P.ny + 3) / 4;
     s.nstrips = (P.nx + 59) / 60;
@@ -829,7 +830,7 @@ int m2p_set_inflow_states(m2p_ctx* c, const m2p_inflow_state* seg, int32_t nseg)
 int m2p_set_variant(m2p_ctx* c, int32_t variant, int32_t rows)
 {
     if (!c) return fail(M2P_EINVAL, "NULL context");
-    if (variant < M2P_VARIANT_AUTO || variant > M2P_VARIANT_TILED) return fail(M2P_EINVAL, "unknown variant");
+    if (variant < M2P_VARIANT_AUTO || variant > M2P_VARIANT_TILED_GLOBAL) return fail(M2P_EINVAL, "unknown variant");
     if (rows != 0 && (rows < 1 || rows > 4096)) return fail(M2P_EINVAL, "tile rows must be 0 or in [1, 4096]");
     HIPCHK(hipStreamSynchronize(c->stream));
     const int old_variant = c->variant, old_rows = c->rows;

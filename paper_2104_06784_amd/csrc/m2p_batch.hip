@@ -46,6 +46,7 @@ struct m2p_batch {
     int* work = nullptr;
     int nwork = 0;
     int R = 16, blocks = 0;
+    bool buf = true;  // every member's state and DEM below 2 GiB: raw buffer accesses
     bool dirty = true, poisoned = false;
     int graph_chunk = 50;
     hipGraphExec_t gexec = nullptr;
@@ -117,9 +118,9 @@ hipError_t part(m2p_batch* B, int p, int mode)
 {
     if (B->prec == M2P_FP64)
         return Launch<double>::batch_part((const ScenDesc<double>*)B->scen, B->nscen, B->work, B->nwork, B->R,
-                                          B->blocks, B->stream, p, mode);
+                                          B->blocks, B->buf, B->stream, p, mode);
     return Launch<float>::batch_part((const ScenDesc<float>*)B->scen, B->nscen, B->work, B->nwork, B->R, B->blocks,
-                                     B->stream, p, mode);
+                                     B->buf, B->stream, p, mode);
 }
 
 hipError_t one_step(m2p_batch* B)
@@ -261,6 +262,9 @@ int m2p_batch_create(m2p_batch** out, int32_t nscen, const m2p_grid* grids, cons
         ub += (size_t)NF * K.ny * K.pitch * B->esz;
         B->b_off.push_back(bb);
         bb += (size_t)(K.ny + 2 * BHALO) * K.bpitch * B->esz;
+        if ((uint64_t)NF * K.ny * K.pitch * B->esz >= (1ull << 31) ||
+            (uint64_t)(K.ny + 2 * BHALO) * K.bpitch * B->esz >= (1ull << 31))
+            B->buf = false;
         B->mu_off.push_back(mb);
         if (hm) mb += (size_t)K.ny * K.pitch * B->esz;
         const int nbx = (K.nx + 63) / 64, nby = (K.ny + 3) / 4, nstrips = (K.nx + 59) / 60, nrb = (K.ny + 3) / 4;

@@ -608,7 +608,7 @@ M2P_FN void sources(const Consts<T>& K, int flags, const T u[NF], const Geo<T>& 
     if constexpr (Folded<T>::value) {
         _Pragma("clang fp contract(fast)")
         const T ms = u[0], mf = u[3];
-        const T hs = ms * g.c, hf = mf * g.c, h = hs + hf;
+        const T hs = ms * g.c, hf = mf * g.c;
         const T mt = ms + mf;
         T phis, phif;
         dsg2(ms, mf, mt, K.md, phis, phif);

@@ -55,9 +55,19 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
 #undef M2P_REF
     } else {
         dim3 blk(256), grd(sh.blocks);
+        // raw buffer accesses when every byte offset of the state and the DEM
+        // fits in 31 bits (4096 x 4096 FP32: 403 MB)
+        const bool buf = !sh.global_addr && (uint64_t)NF * P.ny * P.pitch * sizeof(T) < (1ull << 31) &&
+                         (uint64_t)(P.ny + 2 * BHALO) * P.bpitch * sizeof(T) < (1ull << 31);
 #define M2P_TILED_GC(K, GH, CU, EP)                                                                             \
-    hipLaunchKernelGGL((k_stage_tiled<T, K, GH, CU, EP>), grd, blk, 0, st, P, in, U, out, b, mu, B.S, B.bpart,  \
-                       B.wpart, B.nmax, sh.R, sh.nstrips, sh.nrb)
+    do {                                                                                                        \
+        if (buf)                                                                                                \
+            hipLaunchKernelGGL((k_stage_tiled<T, K, GH, CU, EP, true>), grd, blk, 0, st, P, in, U, out, b, mu,  \
+                               B.S, B.bpart, B.wpart, B.nmax, sh.R, sh.nstrips, sh.nrb);                         \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_stage_tiled<T, K, GH, CU, EP, false>), grd, blk, 0, st, P, in, U, out, b, mu, \
+                               B.S, B.bpart, B.wpart, B.nmax, sh.R, sh.nstrips, sh.nrb);                         \
+    } while (0)
 #define M2P_TILED(K)                                                                                            \
     do {                                                                                                        \
         const bool cu = (P.flags & kFlagCentralUpwind) != 0;                                                    \
@@ -145,20 +155,30 @@ hipError_t Launch<M2P_REAL>::mass(const KParams& P, const Bufs& B, hipStream_t s
 
 template <>
 hipError_t Launch<M2P_REAL>::batch_part(const ScenDesc<M2P_REAL>* scen, int nscen, const int* work, int nwork, int R,
-                                        int blocks, hipStream_t st, int part, int mode)
+                                        int blocks, bool buf, hipStream_t st, int part, int mode)
 {
     using T = M2P_REAL;
-    if (part == 2)
+    if (part == 2) {
         hipLaunchKernelGGL((k_finalize_batch<T>), dim3(nscen), dim3(kFinThreads), 0, st, scen, mode);
-    else if ((long long)blocks * 4 >= nwork) {  // one wavefront per work item
+        return hipGetLastError();
+    }
+#define M2P_BATCH(KERNEL, K)                                                                                    \
+    do {                                                                                                        \
+        if (buf)                                                                                                \
+            hipLaunchKernelGGL((KERNEL<T, K, true>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);     \
+        else                                                                                                    \
+            hipLaunchKernelGGL((KERNEL<T, K, false>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);    \
+    } while (0)
+    if ((long long)blocks * 4 >= nwork) {  // one wavefront per work item
         if (part == 0)
-            hipLaunchKernelGGL((k_stage_batch_flat<T, 1>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);
+            M2P_BATCH(k_stage_batch_flat, 1);
         else
-            hipLaunchKernelGGL((k_stage_batch_flat<T, 2>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);
+            M2P_BATCH(k_stage_batch_flat, 2);
     } else if (part == 0)
-        hipLaunchKernelGGL((k_stage_batch<T, 1>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);
+        M2P_BATCH(k_stage_batch, 1);
     else
-        hipLaunchKernelGGL((k_stage_batch<T, 2>), dim3(blocks), dim3(256), 0, st, scen, work, nwork, R);
+        M2P_BATCH(k_stage_batch, 2);
+#undef M2P_BATCH
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ struct Shape {
     int n_we, n_sn;    // boundary partials per W/E and per S/N side
     int nw;            // per-stage partial slots
     int blocks;        // workgroups per stage launch
+    int global_addr;   // tiled: 64-bit global addresses even where raw buffer offsets would reach
 };
 
 struct Bufs {
@@ -76,6 +77,7 @@ struct Launch {
     // batched ensemble: part 0 / 1 = persistent stage kernels over the work
     // list, part 2 = one finalize workgroup per scenario (mode 0 or 1)
     static hipError_t batch_part(const ScenDesc<T>* scen, int nscen, const int* work, int nwork, int R, int blocks,
+                                 bool buf,
                                  hipStream_t st, int part, int mode);
     // adjoint support (buffers are [6][ny][pitch] state-shaped unless noted)
     static hipError_t jvp(const KParams& P, const Bufs& B, const void* U, const void* dU, const void* dmu, int stage,
