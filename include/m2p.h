@@ -39,7 +39,7 @@ extern "C" {
 #define M2P_ENOMEM -2      /* device allocation failed */
 #define M2P_EHIP -3        /* a HIP runtime call failed (text in m2p_last_error) */
 #define M2P_ENONFINITE -4  /* the device saw a NaN or Inf in the state or in dt */
-#define M2P_ENEGDEPTH -5   /* reserved: negative thickness handed in */
+#define M2P_ENEGDEPTH -5   /* negative thickness handed to m2p_set_state or m2p_batch_set_state */
 #define M2P_EDTFLOOR -6    /* the CFL time step fell below 1e-12 of the grid's gravity-wave time */
 #define M2P_EMAXSTEPS -7   /* m2p_run_to stopped at max_steps before t_end */
 #define M2P_ESTATE -8      /* call order (step before set_state, poisoned context, ...) */
@@ -196,7 +196,8 @@ int m2p_bind_buffers(m2p_ctx *c, void *state_a, void *state_b, size_t bytes);
 /* Mode-I release or any state from SI host fields (ny*nx each): thickness h
  * (depth_kind M2P_DEPTH_NORMAL or M2P_DEPTH_VERTICAL), solid fraction in
  * [0, 1], horizontal velocities of solid and fluid (NULL = 0).  Resets nothing
- * else (time, integrals and step count persist).  Errors: EINVAL, EHIP. */
+ * else (time, integrals and step count persist).  Errors: ENEGDEPTH (a finite
+ * h < 0), EINVAL (non-finite values, solid fraction outside [0, 1]), EHIP. */
 int m2p_set_state(m2p_ctx *c, int32_t depth_kind, const double *h, const double *phi_s,
                   const double *vxs, const double *vys, const double *vxf, const double *vyf);
 

@@ -628,7 +628,8 @@ int m2p_set_state(m2p_ctx* c, int32_t kind, const double* h, const double* phi, 
     if (kind != M2P_DEPTH_NORMAL && kind != M2P_DEPTH_VERTICAL) return fail(M2P_EINVAL, "bad depth kind");
     const size_t n = (size_t)c->g.nx * c->g.ny;
     for (size_t k = 0; k < n; k++) {
-        if (!(h[k] >= 0.0) || !std::isfinite(h[k])) return fail(M2P_EINVAL, "thickness must be finite and >= 0");
+        if (!std::isfinite(h[k])) return fail(M2P_EINVAL, "thickness must be finite");
+        if (h[k] < 0.0) return fail(M2P_ENEGDEPTH, "negative thickness");
         if (!(phi[k] >= 0.0 && phi[k] <= 1.0)) return fail(M2P_EINVAL, "solid fraction outside [0, 1]");
     }
     const double* v[4] = {vxs, vys, vxf, vyf};

@@ -357,7 +357,8 @@ int m2p_batch_set_state(m2p_batch* B, int32_t i, int32_t kind, const double* h, 
     if (kind != M2P_DEPTH_NORMAL && kind != M2P_DEPTH_VERTICAL) return fail(M2P_EINVAL, "bad depth kind");
     const size_t n = (size_t)B->kp[i].nx * B->kp[i].ny;
     for (size_t k = 0; k < n; k++) {
-        if (!(h[k] >= 0.0) || !std::isfinite(h[k])) return fail(M2P_EINVAL, "thickness must be finite and >= 0");
+        if (!std::isfinite(h[k])) return fail(M2P_EINVAL, "thickness must be finite");
+        if (h[k] < 0.0) return fail(M2P_ENEGDEPTH, "negative thickness");
         if (!(phi[k] >= 0.0 && phi[k] <= 1.0)) return fail(M2P_EINVAL, "solid fraction outside [0, 1]");
     }
     const double* v[4] = {vxs, vys, vxf, vyf};

@@ -690,8 +690,19 @@ def test_set_state_rejects_non_finite():
     assert e.value.code == A.M2P_EINVAL
     bad = prob.phi_s.copy()
     bad[0, 0] = -0.1
-    with pytest.raises(A.M2PError):
+    with pytest.raises(A.M2PError) as e:
         g.set_state(prob.h_vert, bad)
+    assert e.value.code == A.M2P_EINVAL
+    hneg = prob.h_vert.copy()
+    hneg[3, 2] = -1e-3
+    with pytest.raises(A.M2PError) as e:
+        g.set_state(hneg, prob.phi_s)
+    assert e.value.code == A.M2P_ENEGDEPTH
+    hnan = prob.h_vert.copy()
+    hnan[3, 2] = np.inf
+    with pytest.raises(A.M2PError) as e:
+        g.set_state(hnan, prob.phi_s)
+    assert e.value.code == A.M2P_EINVAL
 
 
 def test_max_steps_reported():
