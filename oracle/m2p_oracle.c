@@ -15,9 +15,9 @@
  * "reading:"; the same readings are followed by the HIP path.  Options beside
  * the paper's choices (params.flags): the three-stage SSP Runge-Kutta method,
  * the central-upwind face flux with one-sided speeds, Savage-Hutter
- * earth-pressure coefficients from the internal friction angle, and a
- * smooth (regularised) Coulomb friction for finite-difference checks of
- * gradients.
+ * earth-pressure coefficients from the internal friction angle, a smooth
+ * (regularised) Coulomb friction for finite-difference checks of gradients,
+ * and a well-balanced hydrostatic reconstruction of the face states.
  *
  * Units: SI at the interface; inside, the shallow scaling X, Y, b ~ L,
  * h ~ H, v ~ sqrt(g L), t ~ sqrt(L / g), aspect ratio eps = H / L.
@@ -47,7 +47,8 @@ typedef struct {
                       bit 1: three-stage third-order SSP Runge-Kutta instead of Heun;
                       bit 2: central-upwind face flux (one-sided local speeds);
                       bit 3: Savage-Hutter earth-pressure coefficients on the solid pressure;
-                      bit 4: smooth Coulomb friction with regularisation speed v_eps */
+                      bit 4: smooth Coulomb friction with regularisation speed v_eps;
+                      bit 5: well-balanced hydrostatic reconstruction (Mode-I only) */
     double delta_int_deg; /* internal friction angle (used with bit 3) */
     double v_eps;         /* m/s (used with bit 4) */
 } ora_params;
@@ -95,6 +96,7 @@ typedef struct {
     geo_t *G;            /* padded geometry (ring 1 used) */
     double *dnx, *dny;   /* d n / d xi, d n / d eta (3 each) per interior cell */
     double *HX, *HY;     /* face fluxes */
+    double *HXcL, *HXcR, *HYcL, *HYcR; /* well-balanced option: pressure corrections of the face's left / right cell */
     double *Us, *Uss;
     inflow_seg *seg;
     int nseg;
@@ -203,6 +205,7 @@ ora_sim *ora_create(const ora_params *p, const double *dem, const double *tan_mu
 {
     if (p->nx < 2 || p->ny < 2) return NULL;
     if ((p->flags & 16) && !(p->v_eps > 0.0)) return NULL;
+    if ((p->flags & 32) && (p->flags & 8)) return NULL; /* not with earth pressure */
     if (p->flags & 8) {
         /* earth pressure needs delta_b <= delta_int < 90 deg everywhere */
         if (!(p->delta_int_deg >= 0.0 && p->delta_int_deg < 90.0) || p->delta_b_deg > p->delta_int_deg) return NULL;
@@ -238,6 +241,12 @@ ora_sim *ora_create(const ora_params *p, const double *dem, const double *tan_mu
     o->dny = (double *)xcalloc(3 * nc, sizeof(double));
     o->HX = (double *)xcalloc(NF * (size_t)(o->nx + 1) * o->ny, sizeof(double));
     o->HY = (double *)xcalloc(NF * (size_t)o->nx * (o->ny + 1), sizeof(double));
+    if (p->flags & 32) {
+        o->HXcL = (double *)xcalloc(NF * (size_t)(o->nx + 1) * o->ny, sizeof(double));
+        o->HXcR = (double *)xcalloc(NF * (size_t)(o->nx + 1) * o->ny, sizeof(double));
+        o->HYcL = (double *)xcalloc(NF * (size_t)o->nx * (o->ny + 1), sizeof(double));
+        o->HYcR = (double *)xcalloc(NF * (size_t)o->nx * (o->ny + 1), sizeof(double));
+    }
     if (tan_mu) {
         o->tan_mu = (double *)xcalloc(nc, sizeof(double));
         memcpy(o->tan_mu, tan_mu, nc * sizeof(double));
@@ -273,6 +282,7 @@ void ora_destroy(ora_sim *o)
     if (!o) return;
     free(o->b); free(o->U); free(o->Us); free(o->Uss); free(o->Ue); free(o->G);
     free(o->dnx); free(o->dny); free(o->HX); free(o->HY); free(o->tan_mu); free(o->dt_sched);
+    free(o->HXcL); free(o->HXcR); free(o->HYcL); free(o->HYcR);
     free(o->Kx); free(o->Ky);
     for (int k = 0; k < o->nseg; k++) { free(o->seg[k].t); free(o->seg[k].Q); free(o->seg[k].phi); }
     free(o->seg);
@@ -311,6 +321,7 @@ void ora_set_time(ora_sim *o, double t_si) { o->t = t_si / o->T; }
 
 int ora_set_inflow(ora_sim *o, const ora_inflow_in *in, int n)
 {
+    if ((o->p.flags & 32) && n > 0) return -1; /* the well-balanced option is Mode-I only */
     o->seg = (inflow_seg *)xcalloc((size_t)n, sizeof(inflow_seg));
     o->nseg = n;
     for (int k = 0; k < n; k++) {
@@ -332,6 +343,7 @@ int ora_set_inflow(ora_sim *o, const ora_inflow_in *in, int n)
  * must not share a boundary cell with a flux-inflow segment or each other. */
 int ora_set_inflow_states(ora_sim *o, const ora_state_in *in, int n)
 {
+    if ((o->p.flags & 32) && n > 0) return -1; /* the well-balanced option is Mode-I only */
     for (int k = 0; k < o->nsseg; k++) { free(o->sseg[k].t); free(o->sseg[k].h); free(o->sseg[k].phi); free(o->sseg[k].v); }
     free(o->sseg);
     o->sseg = (state_seg *)xcalloc((size_t)n, sizeof(state_seg));
@@ -635,11 +647,20 @@ static void side_speeds(const ora_sim *o, const double u[NF], const geo_t *g, in
  * and (F(U-) + F(U+))/2 where a+ = a- = 0.  With a- = -a+ it is the
  * Kurganov-Tadmor flux. */
 static void central_flux(const ora_sim *o, const double uL[NF], const geo_t *gL,
-                         const double uR[NF], const geo_t *gR, int d, double H[NF], double kL, double kR)
+                         const double uR[NF], const geo_t *gR, int d, double H[NF], double kL, double kR,
+                         const double *dqm)
 {
     double FL[NF], FR[NF], qL[NF], qR[NF], aL[2], aR[2];
     side_flux(o, uL, gL, d, FL, qL, aL, kL);
     side_flux(o, uR, gR, d, FR, qR, aR, kR);
+    /* jump of each conserved field across the face in the numerical
+     * diffusion (the well-balanced option gives the masses' from eta) */
+    double dq[NF];
+    for (int k = 0; k < NF; k++) dq[k] = qR[k] - qL[k];
+    if (dqm) {
+        dq[0] = dqm[0];
+        dq[3] = dqm[1];
+    }
     if (o->p.flags & 4) {
         double loL[2], hiL[2], loR[2], hiR[2];
         side_speeds(o, uL, gL, d, loL, hiL, kL);
@@ -651,7 +672,7 @@ static void central_flux(const ora_sim *o, const double uL[NF], const geo_t *gL,
             if (am > 0.0) am = 0.0;
             double den = ap - am;
             for (int k = 3 * ph; k < 3 * ph + 3; k++)
-                H[k] = den > 0.0 ? (ap * FL[k] - am * FR[k]) / den + ap * am / den * (qR[k] - qL[k])
+                H[k] = den > 0.0 ? (ap * FL[k] - am * FR[k]) / den + ap * am / den * dq[k]
                                  : 0.5 * (FL[k] + FR[k]);
         }
         return;
@@ -659,7 +680,7 @@ static void central_flux(const ora_sim *o, const double uL[NF], const geo_t *gL,
     for (int ph = 0; ph < 2; ph++) {
         double a = aL[ph] > aR[ph] ? aL[ph] : aR[ph];
         for (int k = 3 * ph; k < 3 * ph + 3; k++)
-            H[k] = 0.5 * (FL[k] + FR[k]) - 0.5 * a * (qR[k] - qL[k]);
+            H[k] = 0.5 * (FL[k] + FR[k]) - 0.5 * a * dq[k];
     }
 }
 
@@ -706,6 +727,133 @@ static void face_values(const ora_sim *o, int i, int j, int d, double uL[NF], do
     }
 }
 
+/* ---------------------------------- well-balanced option (flags bit 5)
+ * reading (the well-balanced central-upwind line of work Sect. 2.2 cites,
+ * with the hydrostatic reconstruction of Audusse et al. 2004 in this model's
+ * variables): at rest (v = 0, kappa = 0) a phase's pressure flux through a
+ * xi-face is (1 + b_Y^2) eta^2 / (2 eps) (times 1 - alpha for the solid) and
+ * its basal-pressure source is -(eta / eps) b_X, with eta = eps c^2 m
+ * (= eps c h); so on beds that vary in one direction, and on planes (where the
+ * eta-faces' cross term closes it), the model's rest states are b + eta =
+ * const per phase; on a general two-dimensional bed the two momentum
+ * balances give two conditions for one thickness and the model has no rest
+ * state besides the dry bed.  Per cell and direction: face
+ * values of eta and of the bed by minmod; at a face, B* = max of the two bed
+ * values, eta* = max(0, eta + b - B*) per side; the face flux from the starred
+ * states (m* = eta* / (eps c^2), momenta m* times the side's velocity, the
+ * masses' numerical diffusion on eta*); each cell adds the difference of the
+ * pressure terms of its own face state and the starred one; the hydrostatic
+ * part of the basal-pressure source uses the mean of the cell's two face
+ * values of eta and the difference of its two bed face values. */
+
+static double hr_c2(const ora_sim *o, int ii, int jj, int d)
+{
+    int p = d == 0 ? ii : jj, n = d == 0 ? o->nx : o->ny;
+    int st = p < -1 ? 1 : (p > n ? -1 : 0);
+    int di = d == 0 ? st : 0, dj = d == 0 ? 0 : st;
+    double c = o->G[PIDX(o, ii + di, jj + dj)].c;
+    return c * c;
+}
+
+/* cell (i, j) along d: face values of eta of phase ph (em at i - 1/2, ep at
+ * i + 1/2) and of the bed (bm, bp) */
+static void hr_cell(const ora_sim *o, int i, int j, int d, int ph, double *em, double *ep, double *bm, double *bp)
+{
+    size_t np = (size_t)o->px * o->py;
+    int di = d == 0 ? 1 : 0, dj = d == 0 ? 0 : 1;
+    const double *f = o->Ue + (size_t)(3 * ph) * np;
+    double eta[3], b[3];
+    for (int q = 0; q < 3; q++) {
+        int ii = i + (q - 1) * di, jj = j + (q - 1) * dj;
+        eta[q] = o->eps * hr_c2(o, ii, jj, d) * f[PIDX(o, ii, jj)];
+        b[q] = o->b[PIDX(o, ii, jj)];
+    }
+    double se = minmod(eta[1] - eta[0], eta[2] - eta[1]);
+    double sb = minmod(b[1] - b[0], b[2] - b[1]);
+    *em = eta[1] - 0.5 * se;
+    *ep = eta[1] + 0.5 * se;
+    *bm = b[1] - 0.5 * sb;
+    *bp = b[1] + 0.5 * sb;
+}
+
+/* pressure parts of the side flux F (momentum components), the terms of side_flux */
+static void hr_pterm(const ora_sim *o, const double u[NF], const geo_t *g, int d, double P[NF])
+{
+    double eps = o->eps, al = o->alpha;
+    double hs = u[0] / g->J, hf = u[3] / g->J, h = hs + hf;
+    double Ns = g->c * (1.0 - al) * hs / 2.0, pf = g->c * h / 2.0;
+    double Ax = d == 0 ? g->A11 : g->A21, Ay = d == 0 ? g->A12 : g->A22;
+    for (int k = 0; k < NF; k++) P[k] = 0.0;
+    P[1] = eps * g->J * h * Ax * Ns;
+    P[2] = eps * g->J * h * Ay * Ns;
+    P[4] = eps * g->J * h * Ax * pf;
+    P[5] = eps * g->J * h * Ay * pf;
+}
+
+/* Well-balanced face (i, j) + 1/2 along d: starred states, flux H and the
+ * corrections cL, cR of the left and right cell. */
+static void hr_face(ora_sim *o, int i, int j, int d, const double uL[NF], const double uR[NF], double H[NF],
+                    double cL[NF], double cR[NF])
+{
+    int di = d == 0 ? 1 : 0, dj = d == 0 ? 0 : 1;
+    const geo_t *gL = &o->G[PIDX(o, i, j)], *gR = &o->G[PIDX(o, i + di, j + dj)];
+    double c2L = hr_c2(o, i, j, d), c2R = hr_c2(o, i + di, j + dj, d);
+    /* a wall face: the ghost side mirrors the edge cell (its face values of
+     * eta and the bed, its c and geometry), so no mass crosses the wall and a
+     * lake at rest stays at rest against it */
+    int p = d == 0 ? i : j, n = d == 0 ? o->nx : o->ny;
+    int wallL = p == -1 && o->p.bc[2 * d] == 1, wallR = p + 1 == n && o->p.bc[2 * d + 1] == 1;
+    if (wallL) {
+        gL = gR;
+        c2L = c2R;
+    }
+    if (wallR) {
+        gR = gL;
+        c2R = c2L;
+    }
+    double sL[NF], sR[NF], dqm[2];
+    for (int ph = 0; ph < 2; ph++) {
+        double em, ep, bm, bp, fm, fp, gm, gp;
+        hr_cell(o, i, j, d, ph, &em, &ep, &bm, &bp);
+        hr_cell(o, i + di, j + dj, d, ph, &fm, &fp, &gm, &gp);
+        double etaL = ep, bL = bp, etaR = fm, bR = gm;
+        if (wallL) {
+            etaL = etaR;
+            bL = bR;
+        }
+        if (wallR) {
+            etaR = etaL;
+            bR = bL;
+        }
+        double Bs = bL > bR ? bL : bR;
+        double esL = etaL + bL - Bs, esR = etaR + bR - Bs;
+        if (esL < 0.0) esL = 0.0;
+        if (esR < 0.0) esR = 0.0;
+        int k0 = 3 * ph;
+        double mL = etaL / (o->eps * c2L), mR = etaR / (o->eps * c2R);
+        double msL = esL / (o->eps * c2L), msR = esR / (o->eps * c2R);
+        /* starred face states: the masses from eta*, the momenta of the plain
+         * reconstruction scaled by the same factor (the velocity is kept) */
+        double fL = mL > 0.0 ? msL / mL : 0.0, fR = mR > 0.0 ? msR / mR : 0.0;
+        sL[k0] = msL; sL[k0 + 1] = uL[k0 + 1] * fL; sL[k0 + 2] = uL[k0 + 2] * fL;
+        sR[k0] = msR; sR[k0 + 1] = uR[k0 + 1] * fR; sR[k0 + 2] = uR[k0 + 2] * fR;
+        dqm[ph] = (esR - esL) * ((1.0 / c2L + 1.0 / c2R) / (2.0 * o->eps));
+        /* unstarred face states for the pressure corrections */
+        cL[k0] = mL; cL[k0 + 1] = uL[k0 + 1]; cL[k0 + 2] = uL[k0 + 2];
+        cR[k0] = mR; cR[k0 + 1] = uR[k0 + 1]; cR[k0 + 2] = uR[k0 + 2];
+    }
+    central_flux(o, sL, gL, sR, gR, d, H, 1.0, 1.0, dqm);
+    double PL[NF], PLs[NF], PR[NF], PRs[NF];
+    hr_pterm(o, cL, gL, d, PL);
+    hr_pterm(o, sL, gL, d, PLs);
+    hr_pterm(o, cR, gR, d, PR);
+    hr_pterm(o, sR, gR, d, PRs);
+    for (int k = 0; k < NF; k++) {
+        cL[k] = PL[k] - PLs[k];
+        cR[k] = PR[k] - PRs[k];
+    }
+}
+
 static void compute_fluxes(ora_sim *o, double tau)
 {
     int nx = o->nx, ny = o->ny;
@@ -715,10 +863,19 @@ static void compute_fluxes(ora_sim *o, double tau)
         for (int i = -1; i < nx; i++) {
             double uL[NF], uR[NF], H[NF];
             face_values(o, i, j, 0, uL, uR);
-            const int ep = (o->p.flags & 8) != 0;
-            central_flux(o, uL, &o->G[PIDX(o, i, j)], uR, &o->G[PIDX(o, i + 1, j)], 0, H,
-                         ep ? o->Kx[PIDX(o, i, j)] : 1.0, ep ? o->Kx[PIDX(o, i + 1, j)] : 1.0);
             size_t f = (size_t)j * (nx + 1) + (size_t)(i + 1);
+            if (o->p.flags & 32) {
+                double cL[NF], cR[NF];
+                hr_face(o, i, j, 0, uL, uR, H, cL, cR);
+                for (int k = 0; k < NF; k++) {
+                    o->HXcL[k * nfx + f] = cL[k];
+                    o->HXcR[k * nfx + f] = cR[k];
+                }
+            } else {
+                const int ep = (o->p.flags & 8) != 0;
+                central_flux(o, uL, &o->G[PIDX(o, i, j)], uR, &o->G[PIDX(o, i + 1, j)], 0, H,
+                             ep ? o->Kx[PIDX(o, i, j)] : 1.0, ep ? o->Kx[PIDX(o, i + 1, j)] : 1.0, NULL);
+            }
             for (int k = 0; k < NF; k++) o->HX[k * nfx + f] = H[k];
         }
 #pragma omp parallel for schedule(static)
@@ -726,10 +883,19 @@ static void compute_fluxes(ora_sim *o, double tau)
         for (int i = 0; i < nx; i++) {
             double uL[NF], uR[NF], H[NF];
             face_values(o, i, j, 1, uL, uR);
-            const int ep = (o->p.flags & 8) != 0;
-            central_flux(o, uL, &o->G[PIDX(o, i, j)], uR, &o->G[PIDX(o, i, j + 1)], 1, H,
-                         ep ? o->Ky[PIDX(o, i, j)] : 1.0, ep ? o->Ky[PIDX(o, i, j + 1)] : 1.0);
             size_t f = (size_t)(j + 1) * nx + (size_t)i;
+            if (o->p.flags & 32) {
+                double cL[NF], cR[NF];
+                hr_face(o, i, j, 1, uL, uR, H, cL, cR);
+                for (int k = 0; k < NF; k++) {
+                    o->HYcL[k * nfy + f] = cL[k];
+                    o->HYcR[k * nfy + f] = cR[k];
+                }
+            } else {
+                const int ep = (o->p.flags & 8) != 0;
+                central_flux(o, uL, &o->G[PIDX(o, i, j)], uR, &o->G[PIDX(o, i, j + 1)], 1, H,
+                             ep ? o->Ky[PIDX(o, i, j)] : 1.0, ep ? o->Ky[PIDX(o, i, j + 1)] : 1.0, NULL);
+            }
             for (int k = 0; k < NF; k++) o->HY[k * nfy + f] = H[k];
         }
     /* Mode-II: prescribed fluxes on the inflow faces */
@@ -910,6 +1076,25 @@ static void sources(const ora_sim *o, int i, int j, src_t *S)
     if (pbf < 0.0) pbf = 0.0;
     S->sn[0][0] = g->J * pbs * g->nX; S->sn[0][1] = g->J * pbs * g->nY;
     S->sn[1][0] = g->J * pbf * g->nX; S->sn[1][1] = g->J * pbf * g->nY;
+    if (o->p.flags & 32) {
+        /* well-balanced option: the hydrostatic part J h c n of s_n (with
+         * (1 - alpha) for the solid) in the form that balances the face
+         * corrections: -(fac / eps) (mean face eta) (bed face difference) / step */
+        for (int ph = 0; ph < 2; ph++) {
+            double fac = ph == 0 ? 1.0 - al : 1.0;
+            double hph = ph == 0 ? hs : hf;
+            double pb = ph == 0 ? pbs : pbf;
+            if (!(pb > 0.0)) continue; /* lifted off: no normal force */
+            for (int d = 0; d < 2; d++) {
+                double em, ep, bm, bp;
+                hr_cell(o, i, j, d, ph, &em, &ep, &bm, &bp);
+                double nd = d == 0 ? g->nX : g->nY;
+                double hydro = g->J * hph * g->c * fac * nd;
+                double wb = -(fac / eps) * (0.5 * (em + ep)) * (bp - bm) / (d == 0 ? o->dxi : o->deta);
+                S->sn[ph][d] += wb - hydro;
+            }
+        }
+    }
     /* interphase pressure: gradient of J_b h pbar^f by central differences */
     double dGx = (fluid_G(o, i + 1, j) - fluid_G(o, i - 1, j)) / (2.0 * o->dxi);
     double dGy = (fluid_G(o, i, j + 1) - fluid_G(o, i, j - 1)) / (2.0 * o->deta);
@@ -969,6 +1154,10 @@ static void stage(ora_sim *o, const double *Uin, double *Uout, double dt, double
             for (int k = 0; k < NF; k++) {
                 double dFx = o->HX[k * nfx + (size_t)j * (nx + 1) + i + 1] - o->HX[k * nfx + (size_t)j * (nx + 1) + i];
                 double dGy = o->HY[k * nfy + (size_t)(j + 1) * nx + i] - o->HY[k * nfy + (size_t)j * nx + i];
+                if (o->p.flags & 32) {
+                    dFx += o->HXcL[k * nfx + (size_t)j * (nx + 1) + i + 1] - o->HXcR[k * nfx + (size_t)j * (nx + 1) + i];
+                    dGy += o->HYcL[k * nfy + (size_t)(j + 1) * nx + i] - o->HYcR[k * nfy + (size_t)j * nx + i];
+                }
                 double r = -dFx / o->dxi - dGy / o->deta;
                 int ph = k / 3, comp = k % 3;
                 if (comp > 0) {

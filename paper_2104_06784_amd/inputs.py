@@ -34,6 +34,7 @@ F_RK3 = 2                       # three-stage SSP Runge-Kutta instead of Heun
 F_CENTRAL_UPWIND = 4            # central-upwind face flux (one-sided local speeds)
 F_EARTH_PRESSURE = 8            # Savage-Hutter earth-pressure coefficients from delta_int
 F_SMOOTH_FRICTION = 16          # smooth Coulomb friction (finite-difference checks of gradients)
+F_WELL_BALANCED = 32            # well-balanced hydrostatic reconstruction of the face states (Mode-I)
 
 
 @dataclasses.dataclass

@@ -1097,3 +1097,122 @@ def test_critical_depth_cube_root_is_the_nearest_cube():
         best = min(cands, key=lambda v: abs(Fraction(v) ** 3 - X))
         assert y == best, x
     assert oracle.cbrt_nearest(0.0) == 0.0
+
+
+# ------------------------------------------- well-balanced option (flag 32)
+
+def _lake(along_y=False, wb=True, n=64, m=24, seed=5, flat_edges=True, level_above=5.0):
+    """A lake at rest on a bed that varies in one direction only (a smoothed
+    random profile of 30 m relief, flat within four cells of its two ends so the
+    ghost cells' copies continue the lake), closed walls, fully wet: eta = eps c^2 m
+    = (level - b) / L per cell, no momentum."""
+    rng = np.random.default_rng(seed)
+    prof = np.cumsum(rng.standard_normal(n))
+    prof = np.convolve(prof, np.ones(5) / 5, mode="same")
+    prof = (prof - prof.min()) / np.ptp(prof) * 30.0
+    if flat_edges:
+        prof[:4] = prof[4]
+        prof[-4:] = prof[-5]
+    nx, ny = (m, n) if along_y else (n, m)
+    dx = 10.0
+    dem = np.tile(prof[:, None], (1, m)) if along_y else np.tile(prof, (m, 1))
+    p = I.Params(delta_b_deg=20.0, cfl=0.25, bc=(1, 1, 1, 1), flags=I.F_WELL_BALANCED if wb else 0)
+    z = np.zeros((ny, nx))
+    prob = I.Problem("lake", nx, ny, dx, dx, p, dem, z, z.copy(), [])
+    eps = p.H / p.L
+    b = dem / p.L
+    bp = np.pad(b, 1, mode="reflect", reflect_type="odd")  # the DEM's linear extension
+    bX = (bp[1:-1, 2:] - bp[1:-1, :-2]) / (2 * dx / p.L)
+    bY = (bp[2:, 1:-1] - bp[:-2, 1:-1]) / (2 * dx / p.L)
+    c2 = 1.0 / (1.0 + bX ** 2 + bY ** 2)
+    U = np.zeros((6, ny, nx))
+    U[3] = np.maximum((dem.max() + level_above) / p.L - b, 0.0) / (eps * c2)
+    return prob, U
+
+
+@pytest.mark.parametrize("along_y", [False, True])
+def test_well_balanced_lake_at_rest(along_y):
+    """On a bed that varies in one direction (along X, and along Y), the model's
+    rest state b + eps c h = const (the pressure flux (1 + b_Y^2) eta^2 / (2 eps)
+    against the basal-pressure source -(eta / eps) b_X, eta = eps c h) stays at
+    rest to rounding for 200 steps with the well-balanced option; the plain
+    scheme moves it (the pin fails if the face corrections, the bed face values
+    or the source's mean face thickness are off)."""
+    for wb in (True, False):
+        prob, U0 = _lake(along_y, wb)
+        s = _sim(prob)
+        s.set_state_raw(U0)
+        s.run(200)
+        U = s.state()
+        pmax = np.abs(U[4:6]).max()
+        dm = np.abs(U[3] - U0[3]).max() / U0[3].max()
+        if wb:
+            assert pmax <= 1e-14 and dm <= 1e-13, (pmax, dm)
+        else:
+            assert pmax > 1e-4 and dm > 1e-3
+
+
+def test_well_balanced_dry_front_positivity_mass_and_symmetry():
+    """The plane-bump-pile release (30 deg plane, dry bed around the pile, walls)
+    at CFL 0.25 with the well-balanced option: no positivity clamp in 1300 steps
+    (to about 20 s, after the flow has reached the side walls), each phase's
+    volume conserved to 1e-13 (no mass through the walls: the ghost side of a
+    wall face mirrors the edge cell; with the linearly extended ghost bed there
+    instead the fluid volume drifts by about 2e-12 by then), and the exact mirror
+    symmetry of the problem kept."""
+    prob = I.plane_bump_pile()
+    prob = dataclasses.replace(prob, params=dataclasses.replace(prob.params, flags=I.F_WELL_BALANCED, cfl=0.25))
+    s = _sim(prob)
+    d0 = s.diag()
+    s.run(1300)
+    d1 = s.diag()
+    U = s.state()
+    assert d1["clamps"] == 0
+    assert abs(d1["mass_s"] - d0["mass_s"]) / d0["mass_s"] <= 1e-13
+    assert abs(d1["mass_f"] - d0["mass_f"]) / d0["mass_f"] <= 1e-13
+    for k, sg in ((0, 1), (1, 1), (2, -1), (3, 1), (4, 1), (5, -1)):
+        assert np.array_equal(U[k], sg * U[k][::-1, :]), k
+
+
+def test_well_balanced_walls_on_a_slope_keep_the_volume():
+    """A lake whose walls stand on sloping bed (the profile not flattened at
+    its ends), raised by half near the west wall: the ghost side of each wall
+    face mirrors the edge cell, so the volume is conserved to 1e-13 over 200
+    steps while the water sloshes against the walls."""
+    prob, U0 = _lake(flat_edges=False)
+    U0[3, :, : U0.shape[2] // 3] *= 1.5
+    s = _sim(prob)
+    s.set_state_raw(U0)
+    d0 = s.diag()
+    s.run(200)
+    d1 = s.diag()
+    assert np.abs(s.state()[4:6]).max() > 1e-6  # it does move at the walls
+    assert abs(d1["mass_f"] - d0["mass_f"]) / d0["mass_f"] <= 1e-13
+
+
+def test_well_balanced_equals_plain_scheme_on_a_flat_bed():
+    """On a flat bed the hydrostatic reconstruction changes nothing (B* is the
+    bed, the starred states are the face states, the source term vanishes): 100
+    steps of the pile on a flat walled domain equal the plain scheme to rounding,
+    so Ritter's dam break and the other flat-bed pins carry over."""
+    prob = I.plane_bump_pile()
+    flat = dataclasses.replace(prob, dem=np.zeros((prob.ny, prob.nx)))
+    res = []
+    for flags in (0, I.F_WELL_BALANCED):
+        s = _sim(dataclasses.replace(flat, params=dataclasses.replace(flat.params, flags=flags)))
+        s.run(100)
+        res.append(s.state())
+    assert np.max(np.abs(res[1] - res[0])) <= 1e-13 * np.max(np.abs(res[0]))
+
+
+def test_well_balanced_is_mode_one_only_and_not_with_earth_pressure():
+    """The option refuses inflow segments and the earth-pressure option."""
+    import oracle
+    prob, _ = _lake()
+    s = _sim(prob)
+    t, Q, ph = I.triangular_hydrograph(30.0, 5.0, 20.0, 0.5)
+    with pytest.raises(ValueError):
+        s.set_inflow([I.Inflow(I.SIDE_W, 5, 4, t, Q, ph)])
+    bad = dataclasses.replace(prob, params=dataclasses.replace(prob.params, flags=I.F_WELL_BALANCED | I.F_EARTH_PRESSURE))
+    with pytest.raises(Exception):
+        oracle.OracleSim(bad)
