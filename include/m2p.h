@@ -88,6 +88,19 @@ extern "C" {
                        -F v / sqrt(|v|^2 + v_eps^2) that never reverses the flow; a layer below the
                        friction angle creeps instead of resting.  Needs v_eps > 0; single-scenario
                        contexts, run by the reference kernel; differentiated by the tangent and adjoint */
+#define M2P_F_WELL_BALANCED 32 /* well-balanced hydrostatic reconstruction of the face states (Sect. 2.2 cites the
+                       well-balanced central-upwind schemes; this is the reconstruction of Audusse et al. 2004 in
+                       the model's variables): per phase eta = eps c^2 m; per cell and direction minmod face values
+                       of eta and of the bed; at a face B* = max of the two bed values, eta* = max(0, eta + b - B*)
+                       per side, the flux from the starred states (m* = eta* / (eps c^2), momenta scaled by m* / m,
+                       the masses' numerical diffusion on eta*), each cell adding the pressure terms of its
+                       unstarred minus its starred face state; the hydrostatic part of the basal-pressure source
+                       becomes -(fac / eps) (mean face eta) (bed face difference) / step (fac = 1 - alpha for the
+                       solid, 1 for the fluid).  A wall face mirrors the edge cell.  Keeps a lake at rest on beds
+                       that vary in one direction and the model's other states to the scheme's order; Mode-I
+                       releases on single-scenario contexts, run by the reference kernel; not with
+                       M2P_F_EARTH_PRESSURE, ensembles, the tangent and adjoint calls (m2p_create returns
+                       M2P_EINVAL for the combination, m2p_set_inflow and m2p_set_inflow_states for segments) */
 
 /* thickness convention of m2p_set_state */
 #define M2P_DEPTH_NORMAL 0   /* h measured normal to the bed (the paper's h, Sect. 2.1) */

@@ -191,11 +191,14 @@ namespace m2p {
 Shape make_shape(const KParams& P, int variant, int rows, int slots)
 {
     Shape s{};
-    // the smooth-friction option, and earth pressure with the central-upwind
-    // flux or with Mode-II state segments, run on the reference kernel
+    // the smooth-friction and well-balanced options, and earth pressure with
+    // the central-upwind flux or with Mode-II state segments, run on the
+    // reference kernel
     const bool ep_ref =
         (P.flags & kFlagEarthPressure) && ((P.flags & kFlagCentralUpwind) || P.nsseg > 0);
-    s.variant = (variant == M2P_VARIANT_REFERENCE || (P.flags & kFlagSmoothFriction) || ep_ref) ? 1 : 2;
+    s.variant = (variant == M2P_VARIANT_REFERENCE || (P.flags & (kFlagSmoothFriction | kFlagWellBalanced)) || ep_ref)
+                    ? 1
+                    : 2;
     s.global_addr = variant == M2P_VARIANT_TILED_GLOBAL;
     s.nbx = (P.nx + 63) / 64;
     s.nby = (P.ny + 3) / 4;
@@ -397,8 +400,10 @@ int validate_scenario(const m2p_grid* g, const m2p_params* p, int32_t prec, cons
     for (int s = 0; s < 4; s++)
         if (p->bc[s] != M2P_BC_TRANSMISSIVE && p->bc[s] != M2P_BC_WALL) return fail(M2P_EINVAL, "bad boundary mode");
     if (p->flags & ~(M2P_F_FLUID_PRESSURE_AS_PRINTED | M2P_F_RK3 | M2P_F_CENTRAL_UPWIND | M2P_F_EARTH_PRESSURE |
-                     M2P_F_SMOOTH_FRICTION))
+                     M2P_F_SMOOTH_FRICTION | M2P_F_WELL_BALANCED))
         return fail(M2P_EINVAL, "unknown flag");
+    if ((p->flags & M2P_F_WELL_BALANCED) && (p->flags & M2P_F_EARTH_PRESSURE))
+        return fail(M2P_EINVAL, "the well-balanced option is not combined with earth pressure");
     if ((p->flags & M2P_F_SMOOTH_FRICTION) && !(p->v_eps > 0.0 && std::isfinite(p->v_eps)))
         return fail(M2P_EINVAL, "smooth friction needs v_eps > 0");
     if ((p->flags & M2P_F_EARTH_PRESSURE) &&
@@ -754,6 +759,8 @@ int m2p_set_inflow(m2p_ctx* c, const m2p_inflow* seg, int32_t nseg)
     if (!c || (nseg > 0 && !seg)) return fail(M2P_EINVAL, "NULL argument");
     if (nseg > 0 && (c->kp.flags & M2P_F_EARTH_PRESSURE))
         return fail(M2P_EINVAL, "the earth-pressure option runs Mode-I releases only");
+    if (nseg > 0 && (c->kp.flags & M2P_F_WELL_BALANCED))
+        return fail(M2P_EINVAL, "the well-balanced option runs Mode-I releases only");
     if (nseg < 0 || nseg > MAX_SEG) return fail(M2P_EINVAL, "0..8 inflow segments supported");
     std::vector<double> tab;
     SegDesc sd[MAX_SEG];
@@ -791,6 +798,8 @@ int m2p_set_inflow_states(m2p_ctx* c, const m2p_inflow_state* seg, int32_t nseg)
     if (!c || (nseg > 0 && !seg)) return fail(M2P_EINVAL, "NULL argument");
     if (nseg > 0 && (c->kp.flags & M2P_F_EARTH_PRESSURE))
         return fail(M2P_EINVAL, "the earth-pressure option runs Mode-I releases only");
+    if (nseg > 0 && (c->kp.flags & M2P_F_WELL_BALANCED))
+        return fail(M2P_EINVAL, "the well-balanced option runs Mode-I releases only");
     if (nseg < 0 || nseg > MAX_SEG) return fail(M2P_EINVAL, "0..8 inflow state segments supported");
     std::vector<double> tab;
     SegDesc sd[MAX_SEG];
@@ -1390,6 +1399,7 @@ int L_loss(m2p_ctx* c, const double* target_dev, void* lam, double* loss)
 static_assert(m2p::kFlagCentralUpwind == M2P_F_CENTRAL_UPWIND, "central-upwind flag bit");
 static_assert(m2p::kFlagEarthPressure == M2P_F_EARTH_PRESSURE, "earth-pressure flag bit");
 static_assert(m2p::kFlagSmoothFriction == M2P_F_SMOOTH_FRICTION, "smooth-friction flag bit");
+static_assert(m2p::kFlagWellBalanced == M2P_F_WELL_BALANCED, "well-balanced flag bit");
 
 // The tangent and adjoint kernels differentiate the Kurganov-Tadmor flux of
 // the paper's model.
@@ -1399,6 +1409,8 @@ int flux_unsupported(m2p_ctx* c)
         return m2p::fail(M2P_EINVAL, "the tangent and adjoint kernels differentiate the central (Kurganov-Tadmor) flux");
     if (c->kp.flags & M2P_F_EARTH_PRESSURE)
         return m2p::fail(M2P_EINVAL, "the tangent and adjoint kernels differentiate the model without earth pressure");
+    if (c->kp.flags & M2P_F_WELL_BALANCED)
+        return m2p::fail(M2P_EINVAL, "the tangent and adjoint kernels differentiate the plain face reconstruction");
     return M2P_OK;
 }
 

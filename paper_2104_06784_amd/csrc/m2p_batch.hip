@@ -230,6 +230,8 @@ int m2p_batch_create(m2p_batch** out, int32_t nscen, const m2p_grid* grids, cons
             return fail(M2P_EINVAL, "ensembles run the central (Kurganov-Tadmor) flux");
         if (params[i].flags & M2P_F_EARTH_PRESSURE)
             return fail(M2P_EINVAL, "ensembles run the model without earth pressure");
+        if (params[i].flags & M2P_F_WELL_BALANCED)
+            return fail(M2P_EINVAL, "ensembles run the plain face reconstruction");
         if (params[i].flags & M2P_F_SMOOTH_FRICTION)
             return fail(M2P_EINVAL, "ensembles run the Coulomb stop-clamp (smooth friction is for gradient checks)");
         if ((size_t)((grids[i].nx + 59) / 60) * (size_t)((grids[i].ny + 3) / 4) >= (1u << 20))

@@ -405,11 +405,17 @@ constexpr bool carry_2h()
 // two sides, 0), a- = min(smallest speed, 0),
 //   H = (a+ F- - a- F+) / (a+ - a-) + a+ a- / (a+ - a-) (U+ - U-),
 // and (F- + F+)/2 where a+ = a- = 0 (a dry face).
+// dqm (the well-balanced option): the jumps of the two masses in the
+// numerical diffusion, in place of m+ - m-.
 template <typename T, bool H2 = false, bool CU = false>
 M2P_FN void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
                                              const T uR[NF], const Geo<T>& gR, int d, T H[NF], T kL = T(1),
-                                             T kR = T(1))
+                                             T kR = T(1), const T* dqm = nullptr)
 {
+    // jump of a conserved field across the face in the numerical diffusion
+    auto jump = [&](const T* qL, const T* qR, int k) {
+        return (dqm && k % 3 == 0) ? dqm[k / 3] : qR[k] - qL[k];
+    };
     if constexpr (CU) {
         T FL[NF], FR[NF], qL[NF], qR[NF], hiL[2], loL[2], hiR[2], loR[2];
         side_flux<T, true>(K, uL, gL, d, FL, qL, hiL, loL, kL);
@@ -428,12 +434,12 @@ M2P_FN void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
                 const T c0 = carry_2h<T, H2>() ? T(1) : T(0.5);
 #pragma unroll
                 for (int k = 3 * ph; k < 3 * ph + 3; k++)
-                    H[k] = wet ? (ap * FL[k] - am * FR[k]) * r + ap * am * r * (qR[k] - qL[k])
+                    H[k] = wet ? (ap * FL[k] - am * FR[k]) * r + ap * am * r * jump(qL, qR, k)
                                : c0 * (FL[k] + FR[k]);
             } else {
 #pragma unroll
                 for (int k = 3 * ph; k < 3 * ph + 3; k++)
-                    H[k] = wet ? (ap * FL[k] - am * FR[k]) / den + ap * am / den * (qR[k] - qL[k])
+                    H[k] = wet ? (ap * FL[k] - am * FR[k]) / den + ap * am / den * jump(qL, qR, k)
                                : T(0.5) * (FL[k] + FR[k]);
             }
         }
@@ -448,9 +454,9 @@ M2P_FN void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
 #pragma unroll
         for (int k = 3 * ph; k < 3 * ph + 3; k++) {
             if constexpr (carry_2h<T, H2>())
-                H[k] = (FL[k] + FR[k]) - a * (qR[k] - qL[k]);
+                H[k] = (FL[k] + FR[k]) - a * jump(qL, qR, k);
             else
-                H[k] = T(0.5) * (FL[k] + FR[k]) - T(0.5) * a * (qR[k] - qL[k]);
+                H[k] = T(0.5) * (FL[k] + FR[k]) - T(0.5) * a * jump(qL, qR, k);
         }
     }
 }
@@ -460,18 +466,138 @@ M2P_FN void central_flux(const Consts<T>& K, const T uL[NF], const Geo<T>& gL,
 constexpr int kFlagCentralUpwind = 4;
 constexpr int kFlagEarthPressure = 8;
 constexpr int kFlagSmoothFriction = 16;
+constexpr int kFlagWellBalanced = 32;
 
 // The face flux the flags select, chosen at run time (the tiled kernels take
 // the choice as a template argument instead); kL, kR: the earth-pressure
 // coefficients of the two sides' owner cells in the face's direction.
 template <typename T>
 M2P_FN void face_flux_sel(const Consts<T>& K, int flags, const T uL[NF], const Geo<T>& gL, const T uR[NF],
-                          const Geo<T>& gR, int d, T H[NF], T kL = T(1), T kR = T(1))
+                          const Geo<T>& gR, int d, T H[NF], T kL = T(1), T kR = T(1), const T* dqm = nullptr)
 {
     if (flags & kFlagCentralUpwind)
-        central_flux<T, false, true>(K, uL, gL, uR, gR, d, H, kL, kR);
+        central_flux<T, false, true>(K, uL, gL, uR, gR, d, H, kL, kR, dqm);
     else
-        central_flux(K, uL, gL, uR, gR, d, H, kL, kR);
+        central_flux(K, uL, gL, uR, gR, d, H, kL, kR, dqm);
+}
+
+// ------------------------------------- well-balanced option (flags bit 5)
+// Hydrostatic reconstruction (Audusse et al. 2004; Sect. 2.2 cites the
+// well-balanced central-upwind schemes) in this model's variables.  At rest
+// a phase's pressure flux through a face is (1 + b_t^2) eta^2 / (2 eps) (times
+// 1 - alpha for the solid) and its basal-pressure source -(eta / eps) b_n, with
+// eta = eps c^2 m; on beds that vary in one direction the rest states are
+// b + eta = const per phase.  Per cell and direction the face values of eta
+// and of the bed come from minmod slopes; at a face B* is the larger bed value,
+// eta* = max(0, eta + b - B*) per side, the flux is taken from the starred
+// states (m* = eta* / (eps c^2), momenta scaled by m* / m, the masses'
+// numerical diffusion on eta*), and each cell adds the difference of the
+// pressure terms of its unstarred and starred face states; the hydrostatic
+// part of the basal-pressure source takes the matching discrete form.
+
+// Face values (minus, plus side) of eta and of the bed of the middle cell of
+// three along a direction.
+template <typename T>
+M2P_FN void wb_cell(T e0, T e1, T e2, T b0, T b1, T b2, T& em, T& ep, T& bm, T& bp)
+{
+    const T se = minmod(e1 - e0, e2 - e1);
+    const T sb = minmod(b1 - b0, b2 - b1);
+    em = e1 - T(0.5) * se;
+    ep = e1 + T(0.5) * se;
+    bm = b1 - T(0.5) * sb;
+    bp = b1 + T(0.5) * sb;
+}
+
+// Pressure parts of a side's physical flux (the momentum components of
+// side_flux, in the same form).
+template <typename T>
+M2P_FN void wb_pterm(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d, T P[NF])
+{
+    const T Ax = d == 0 ? g.A11 : g.A21, Ay = d == 0 ? g.A12 : g.A22;
+    P[0] = T(0);
+    P[3] = T(0);
+    if constexpr (Folded<T>::value) {
+        const T hs = u[0] * g.c, hf = u[3] * g.c, h = hs + hf;
+        const T Ps = K.k_ps * h * hs, Pf = K.k_pf * h * h;
+        P[1] = Ps * Ax;
+        P[2] = Ps * Ay;
+        P[4] = Pf * Ax;
+        P[5] = Pf * Ay;
+    } else {
+        const T hs = u[0] / g.J, hf = u[3] / g.J, h = hs + hf;
+        const T Ns = g.c * (T(1) - K.al) * hs / T(2), pf = g.c * h / T(2);
+        P[1] = K.eps * g.J * h * Ax * Ns;
+        P[2] = K.eps * g.J * h * Ay * Ns;
+        P[4] = K.eps * g.J * h * Ax * pf;
+        P[5] = K.eps * g.J * h * Ay * pf;
+    }
+}
+
+// One face along d between a left and a right cell: uL, uR the plain
+// reconstructed states, c2L, c2R the cells' c^2, etaL/bL the left cell's
+// plus-side face values (per phase), etaR/bR the right cell's minus-side ones.
+// A wall face (wallL: the left cell is the ghost; wallR: the right one) takes
+// the ghost side as the mirror image of the edge cell (its face values, c and
+// geometry), so no mass crosses the wall.  Out: the flux H and the corrections
+// cL, cR of the left and right cell.
+template <typename T>
+M2P_FN void wb_face(const Consts<T>& K, int flags, const T uL[NF], Geo<T> gL, T c2L, const T uR[NF], Geo<T> gR,
+                    T c2R, const T etaL_[2], const T bL_[2], const T etaR_[2], const T bR_[2], bool wallL,
+                    bool wallR, int d, T H[NF], T cL[NF], T cR[NF])
+{
+    if (wallL) {
+        gL = gR;
+        c2L = c2R;
+    }
+    if (wallR) {
+        gR = gL;
+        c2R = c2L;
+    }
+    T sL[NF], sR[NF], dqm[2];
+#pragma unroll
+    for (int ph = 0; ph < 2; ph++) {
+        T etaL = etaL_[ph], bL = bL_[ph], etaR = etaR_[ph], bR = bR_[ph];
+        if (wallL) {
+            etaL = etaR;
+            bL = bR;
+        }
+        if (wallR) {
+            etaR = etaL;
+            bR = bL;
+        }
+        const T Bs = bL > bR ? bL : bR;
+        T esL = etaL + bL - Bs, esR = etaR + bR - Bs;
+        if (esL < T(0)) esL = T(0);
+        if (esR < T(0)) esR = T(0);
+        const int k0 = 3 * ph;
+        const T mL = etaL / (K.eps * c2L), mR = etaR / (K.eps * c2R);
+        const T msL = esL / (K.eps * c2L), msR = esR / (K.eps * c2R);
+        const T fL = mL > T(0) ? msL / mL : T(0), fR = mR > T(0) ? msR / mR : T(0);
+        sL[k0] = msL;
+        sL[k0 + 1] = uL[k0 + 1] * fL;
+        sL[k0 + 2] = uL[k0 + 2] * fL;
+        sR[k0] = msR;
+        sR[k0 + 1] = uR[k0 + 1] * fR;
+        sR[k0 + 2] = uR[k0 + 2] * fR;
+        dqm[ph] = (esR - esL) * ((T(1) / c2L + T(1) / c2R) / (T(2) * K.eps));
+        cL[k0] = mL;
+        cL[k0 + 1] = uL[k0 + 1];
+        cL[k0 + 2] = uL[k0 + 2];
+        cR[k0] = mR;
+        cR[k0 + 1] = uR[k0 + 1];
+        cR[k0 + 2] = uR[k0 + 2];
+    }
+    face_flux_sel(K, flags, sL, gL, sR, gR, d, H, T(1), T(1), dqm);
+    T PL[NF], PLs[NF], PR[NF], PRs[NF];
+    wb_pterm(K, cL, gL, d, PL);
+    wb_pterm(K, sL, gL, d, PLs);
+    wb_pterm(K, cR, gR, d, PR);
+    wb_pterm(K, sR, gR, d, PRs);
+#pragma unroll
+    for (int k = 0; k < NF; k++) {
+        cL[k] = PL[k] - PLs[k];
+        cR[k] = PR[k] - PRs[k];
+    }
 }
 
 // Savage-Hutter earth-pressure coefficients (Savage and Hutter 1989, in the
@@ -601,9 +727,14 @@ struct Src {
     T kappa_s, phif;
 };
 
+// wbs (the well-balanced option): per phase and direction, the balanced
+// form -(fac / eps) (mean of the cell's two face values of eta) (difference
+// of its two bed face values) / step that replaces the hydrostatic part of
+// the basal-pressure source where the phase rests on the bed (fac = 1 - alpha
+// for the solid, 1 for the fluid).
 template <typename T>
 M2P_FN void sources(const Consts<T>& K, int flags, const T u[NF], const Geo<T>& g,
-                                        const T dn[6], T dGx, T dGy, Src<T>& S)
+                                        const T dn[6], T dGx, T dGy, Src<T>& S, const T* wbs = nullptr)
 {
     if constexpr (Folded<T>::value) {
         _Pragma("clang fp contract(fast)")
@@ -634,6 +765,20 @@ M2P_FN void sources(const Consts<T>& K, int flags, const T u[NF], const Geo<T>& 
         S.sn[0][1] = -pbs * g.bY;
         S.sn[1][0] = -pbf * g.bX;
         S.sn[1][1] = -pbf * g.bY;
+        if (wbs) {
+            // hydrostatic part of -p_b b_n: -h c fac b_n
+#pragma unroll
+            for (int ph = 0; ph < 2; ph++) {
+                const T fac = ph == 0 ? K.oma : T(1);
+                const T hph = ph == 0 ? hs : hf;
+                if (!((ph == 0 ? pbs : pbf) > T(0))) continue;
+#pragma unroll
+                for (int d = 0; d < 2; d++) {
+                    const T hydro = -(hph * g.c * fac) * (d == 0 ? g.bX : g.bY);
+                    S.sn[ph][d] = S.sn[ph][d] + (wbs[2 * ph + d] - hydro);
+                }
+            }
+        }
         const T gx = g.A11 * dGx + g.A21 * dGy;
         const T gy = g.A12 * dGx + g.A22 * dGy;
         S.sf[0][0] = K.m_eps_al * phis * gx;
@@ -674,6 +819,20 @@ M2P_FN void sources(const Consts<T>& K, int flags, const T u[NF], const Geo<T>& 
     S.sn[0][1] = g.J * pbs * g.nY;
     S.sn[1][0] = g.J * pbf * g.nX;
     S.sn[1][1] = g.J * pbf * g.nY;
+    if (wbs) {
+        // hydrostatic part J_b h c fac n of J_b p_b n
+#pragma unroll
+        for (int ph = 0; ph < 2; ph++) {
+            const T fac = ph == 0 ? T(1) - K.al : T(1);
+            const T hph = ph == 0 ? hs : hf;
+            if (!((ph == 0 ? pbs : pbf) > T(0))) continue;
+#pragma unroll
+            for (int d = 0; d < 2; d++) {
+                const T hydro = g.J * hph * g.c * fac * (d == 0 ? g.nX : g.nY);
+                S.sn[ph][d] += wbs[2 * ph + d] - hydro;
+            }
+        }
+    }
     T gx = g.A11 * dGx + g.A21 * dGy;
     T gy = g.A12 * dGx + g.A22 * dGy;
     S.sf[0][0] = -K.eps * K.al * phis * gx;
@@ -696,10 +855,12 @@ M2P_FN void sources(const Consts<T>& K, int flags, const T u[NF], const Geo<T>& 
 // Tentative forward-Euler update of one cell from its four face fluxes and
 // its sources (summation order: x-difference, y-difference, then s_n, s_f,
 // s_v, s_d^f, s_vis^f).
+// cx, cy (the well-balanced option): per component, the cell's pressure
+// corrections of its two faces in each direction, added to the flux differences.
 template <typename T, bool H2 = false>
 M2P_FN void tentative(const Consts<T>& K, const T u[NF], const T HXl[NF], const T HXr[NF],
                                           const T HYb[NF], const T HYt[NF], const Src<T>& S, T svx, T svy, T dt,
-                                          T out[NF])
+                                          T out[NF], const T* cx_wb = nullptr, const T* cy_wb = nullptr)
 {
     if constexpr (carry_2h<T, H2>()) {
         _Pragma("clang fp contract(fast)")
@@ -707,8 +868,8 @@ M2P_FN void tentative(const Consts<T>& K, const T u[NF], const T HXl[NF], const 
         const T cx = dt * K.half_rdxi, cy = dt * K.half_rdeta;
 #pragma unroll
         for (int k = 0; k < NF; k++) {
-            const T dFx = HXr[k] - HXl[k];
-            const T dGy = HYt[k] - HYb[k];
+            const T dFx = cx_wb ? (HXr[k] - HXl[k]) + cx_wb[k] : HXr[k] - HXl[k];
+            const T dGy = cy_wb ? (HYt[k] - HYb[k]) + cy_wb[k] : HYt[k] - HYb[k];
             const int ph = k / 3, comp = k % 3;
             T o = u[k];
             if (comp > 0) {
@@ -728,8 +889,8 @@ M2P_FN void tentative(const Consts<T>& K, const T u[NF], const T HXl[NF], const 
         const T cx = dt * K.rdxi, cy = dt * K.rdeta;
 #pragma unroll
         for (int k = 0; k < NF; k++) {
-            const T dFx = HXr[k] - HXl[k];
-            const T dGy = HYt[k] - HYb[k];
+            const T dFx = cx_wb ? (HXr[k] - HXl[k]) + cx_wb[k] : HXr[k] - HXl[k];
+            const T dGy = cy_wb ? (HYt[k] - HYb[k]) + cy_wb[k] : HYt[k] - HYb[k];
             const int ph = k / 3, comp = k % 3;
             T o = u[k];
             if (comp > 0) {
@@ -747,6 +908,8 @@ M2P_FN void tentative(const Consts<T>& K, const T u[NF], const T HXl[NF], const 
     for (int k = 0; k < NF; k++) {
         T dFx = HXr[k] - HXl[k];
         T dGy = HYt[k] - HYb[k];
+        if (cx_wb) dFx += cx_wb[k];
+        if (cy_wb) dGy += cy_wb[k];
         T r = -dFx / K.dxi - dGy / K.deta;
         const int ph = k / 3, comp = k % 3;
         if (comp > 0) {
@@ -833,9 +996,10 @@ M2P_FN int clamp_cell(const Consts<T>& K, const Geo<T>& g, T kappa_s, T dt, T tm
 template <typename T, bool H2 = false, bool SMOOTH = true>
 M2P_FN int update_cell(const Consts<T>& K, const T u[NF], const Geo<T>& g, const T HXl[NF],
                                            const T HXr[NF], const T HYb[NF], const T HYt[NF], const Src<T>& S,
-                                           T svx, T svy, T dt, T tmu, T out[NF])
+                                           T svx, T svy, T dt, T tmu, T out[NF], const T* cx_wb = nullptr,
+                                           const T* cy_wb = nullptr)
 {
-    tentative<T, H2>(K, u, HXl, HXr, HYb, HYt, S, svx, svy, dt, out);
+    tentative<T, H2>(K, u, HXl, HXr, HYb, HYt, S, svx, svy, dt, out, cx_wb, cy_wb);
     return clamp_cell<T, SMOOTH>(K, g, S.kappa_s, dt, tmu, out);
 }
 

@@ -170,7 +170,7 @@ __device__ __forceinline__ void outflow_accumulate(const KParams& P, double* __r
 // combine E(Uin) with the cell's own U^n (read from Un) and write Uout
 // (kinds 2 and 4 over U^n, with the maximum phase speeds of the new state
 // for the next CFL step).
-template <typename T, int STAGE>
+template <typename T, int STAGE, bool WB = false>
 __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restrict__ Uin, T* Un, T* Uout,
                                                    const T* __restrict__ b, const T* __restrict__ mu,
                                                    DevScalars* __restrict__ S, double* __restrict__ bpart,
@@ -205,7 +205,60 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
         const Geo<T> gC = V.geo(i, j, K), gW = V.geo(i - 1, j, K), gE = V.geo(i + 1, j, K);
         const Geo<T> gS = V.geo(i, j - 1, K), gN = V.geo(i, j + 1, K);
         T HXl[NF], HXr[NF], HYb[NF], HYt[NF], uL[NF], uR[NF];
-        {
+        // well-balanced option: per direction the cell's pressure corrections
+        // and, per phase, its balanced basal-pressure source term
+        T cxw[NF], cyw[NF], wbs[4];
+        if constexpr (WB) {
+            T w[4][NF];
+            for (int d = 0; d < 2; d++) {
+                const T(*cs)[NF] = d == 0 ? row : col;
+                const int n = d == 0 ? P.nx : P.ny, p = d == 0 ? i : j;
+                // c^2 of the five cells (a cell two outside the domain takes
+                // the c of the ghost cell next to the edge) and their beds
+                T c2[5], bb[5];
+                for (int q = 0; q < 5; q++) {
+                    int pq = p - 2 + q;
+                    pq = pq < -1 ? -1 : (pq > n ? n : pq);
+                    const T c = d == 0 ? V.geo(pq, j, K).c : V.geo(i, pq, K).c;
+                    c2[q] = c * c;
+                    bb[q] = d == 0 ? V.bv(i - 2 + q, j) : V.bv(i, j - 2 + q);
+                }
+                // face values of the cells p - 1, p, p + 1
+                T em[3][2], ep[3][2], bm[3][2], bp[3][2];
+                for (int ph = 0; ph < 2; ph++) {
+                    T e[5];
+                    for (int q = 0; q < 5; q++) e[q] = K.eps * c2[q] * cs[q][3 * ph];
+                    for (int q = 1; q < 4; q++)
+                        wb_cell(e[q - 1], e[q], e[q + 1], bb[q - 1], bb[q], bb[q + 1], em[q - 1][ph],
+                                ep[q - 1][ph], bm[q - 1][ph], bp[q - 1][ph]);
+                }
+                const Geo<T>& gM = d == 0 ? gW : gS;
+                const Geo<T>& gP = d == 0 ? gE : gN;
+                const int lo = P.bc[2 * d] == 1, hi = P.bc[2 * d + 1] == 1;
+                T Hm[NF], Hp[NF], cl[NF], cr[NF], cm[NF];
+                for (int q = 0; q < 4; q++)
+                    for (int k = 0; k < NF; k++) w[q][k] = cs[q][k];
+                reconstruct(w, uL, uR);
+                wb_face(K, P.flags, uL, gM, c2[1], uR, gC, c2[2], ep[0], bp[0], em[1], bm[1], p == 0 && lo,
+                        false, d, Hm, cl, cm);
+                for (int q = 0; q < 4; q++)
+                    for (int k = 0; k < NF; k++) w[q][k] = cs[q + 1][k];
+                reconstruct(w, uL, uR);
+                wb_face(K, P.flags, uL, gC, c2[2], uR, gP, c2[3], ep[1], bp[1], em[2], bm[2], false,
+                        p + 1 == n && hi, d, Hp, cl, cr);
+                T* cw = d == 0 ? cxw : cyw;
+                for (int k = 0; k < NF; k++) {
+                    cw[k] = cl[k] - cm[k];
+                    (d == 0 ? HXl : HYb)[k] = Hm[k];
+                    (d == 0 ? HXr : HYt)[k] = Hp[k];
+                }
+                for (int ph = 0; ph < 2; ph++) {
+                    const T fac = ph == 0 ? T(1) - K.al : T(1);
+                    wbs[2 * ph + d] = -(fac / K.eps) * (T(0.5) * (em[1][ph] + ep[1][ph])) *
+                                      (bp[1][ph] - bm[1][ph]) / (d == 0 ? K.dxi : K.deta);
+                }
+            }
+        } else {
             T w[4][NF];
             for (int q = 0; q < 4; q++)
                 for (int k = 0; k < NF; k++) w[q][k] = row[q][k];
@@ -270,7 +323,7 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
         T dGx = (fluid_G(row[3][0], row[3][3], gE) - fluid_G(row[1][0], row[1][3], gW)) / K.two_dxi;
         T dGy = (fluid_G(col[3][0], col[3][3], gN) - fluid_G(col[1][0], col[1][3], gS)) / K.two_deta;
         Src<T> Sr;
-        sources(K, P.flags, uC, gC, dn, dGx, dGy, Sr);
+        sources(K, P.flags, uC, gC, dn, dGx, dGy, Sr, WB ? wbs : nullptr);
         T svx = T(0), svy = T(0);
         if (P.visc) {
             T c9[3][3][NF];
@@ -311,7 +364,8 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
         const size_t fs = (size_t)P.ny * P.pitch;
         T tmu = P.has_mu ? mu[c] : K.tan_d;
         T out[NF];
-        red[0] = (double)update_cell(K, uC, gC, HXl, HXr, HYb, HYt, Sr, svx, svy, dt, tmu, out);
+        red[0] = (double)update_cell(K, uC, gC, HXl, HXr, HYb, HYt, Sr, svx, svy, dt, tmu, out,
+                                     WB ? cxw : nullptr, WB ? cyw : nullptr);
         if (STAGE > 1) {
 #pragma unroll
             for (int k = 0; k < NF; k++) out[k] = stage_combine<STAGE>(Un[k * fs + c], out[k]);

@@ -41,9 +41,15 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
     }
     if (sh.variant == 1) {
         dim3 blk(64, 4), grd(sh.nbx, sh.nby);
-#define M2P_REF(K) \
-    hipLaunchKernelGGL((k_stage_ref<T, K>), grd, blk, 0, st, P, in, U, out, b, mu, B.S, B.bpart, B.wpart, B.nmax, \
-                       (const T*)B.kep)
+#define M2P_REF(K)                                                                                              \
+    do {                                                                                                        \
+        if (P.flags & kFlagWellBalanced)                                                                        \
+            hipLaunchKernelGGL((k_stage_ref<T, K, true>), grd, blk, 0, st, P, in, U, out, b, mu, B.S, B.bpart,  \
+                               B.wpart, B.nmax, (const T*)B.kep);                                               \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_stage_ref<T, K>), grd, blk, 0, st, P, in, U, out, b, mu, B.S, B.bpart,        \
+                               B.wpart, B.nmax, (const T*)B.kep);                                               \
+    } while (0)
         if (kind == 1)
             M2P_REF(1);
         else if (kind == 2)

@@ -79,16 +79,18 @@ def test_create_rejects_bad_grid_and_dem():
 
 
 @pytest.mark.parametrize("kw", [
-    dict(flags=32),                                                      # unknown flag
+    dict(flags=64),                                                      # unknown flag
+    dict(flags=I.F_WELL_BALANCED | I.F_EARTH_PRESSURE, delta_int_deg=35.0),  # well-balanced with earth pressure
     dict(flags=I.F_SMOOTH_FRICTION, v_eps=0.0),                          # smooth friction without a speed
     dict(flags=I.F_SMOOTH_FRICTION, v_eps=math.nan),
     dict(flags=I.F_EARTH_PRESSURE, delta_b_deg=20.0, delta_int_deg=15.0),  # basal above internal friction
     dict(flags=I.F_EARTH_PRESSURE, delta_int_deg=90.0),
     dict(flags=I.F_EARTH_PRESSURE, delta_int_deg=-1.0)])
 def test_create_rejects_bad_options(kw):
-    """Option flags are validated before any device call: unknown bits, a
-    smooth friction without a positive regularisation speed, and
-    earth-pressure angles outside delta_b <= delta_int < 90 deg."""
+    """Option flags are validated before any device call: unknown bits, the
+    well-balanced option with earth pressure, a smooth friction without a
+    positive regularisation speed, and earth-pressure angles outside
+    delta_b <= delta_int < 90 deg."""
     rc, h = _create(A.Grid(8, 8, 10.0, 10.0), make_params(I.Params(**kw)))
     assert rc == A.M2P_EINVAL and not h.value
     assert A.lib().m2p_last_error()

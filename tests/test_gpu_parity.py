@@ -2,6 +2,7 @@
 the same seeded inputs.  FP64: max-norm relative error <= 1e-12 per field and
 the same dt sequence; FP32: relative L1 thickness error <= 1e-3 and volume
 budget error <= 1e-6 (FP64 dt, time and volume sums)."""
+import math
 import os
 import sys
 
@@ -476,6 +477,104 @@ def test_smooth_friction_option():
     assert l1 <= 1e-3
     with pytest.raises(A.M2PError):
         Batch([prob], precision="f32")
+
+
+def _wb(prob, extra=0, cfl=None):
+    import dataclasses
+    prm = dataclasses.replace(prob.params, flags=prob.params.flags | I.F_WELL_BALANCED | extra)
+    if cfl is not None:
+        prm = dataclasses.replace(prm, cfl=cfl)
+    q = dataclasses.replace(prob, params=prm)
+    q.name = prob.name + f"-wb{extra}"
+    return q
+
+
+def test_well_balanced_option_fp64():
+    """The well-balanced option (M2P_F_WELL_BALANCED) against the oracle's,
+    FP64 to 1e-12 (state and dt) and its diagnostics: the plane-bump-pile
+    release (walls, dry bed around the pile), with the central-upwind flux,
+    with the three-stage method and a friction field, the ragged grid with
+    transmissive sides (its Mode-II segment removed: the option is Mode-I
+    only), and lakes at rest on beds that vary along X and along Y, which stay
+    at rest on the GPU too.  Any kernel variant request runs the reference
+    kernel."""
+    import dataclasses
+    from wb_lake import lake
+    pile = I.plane_bump_pile(n=96)
+    mu = _wb(I.plane_bump_pile(n=80), I.F_RK3, cfl=0.3)
+    mu.tan_mu = np.tan(np.radians(20.0 + 3.0 * I.smooth_field(80, 8, 4.0)))
+    n_x, n_y, dx = 67, 45, 10.0
+    dem = I.fractal_dem(n_x, dx, 77, 60.0, tilt_deg=15.0, ny=n_y)
+    h = I.cylinder(n_x, n_y, dx, dx, 300.0, 200.0, 90.0, 6.0)
+    ragged = I.Problem("ragged", n_x, n_y, dx, dx, I.Params(delta_b_deg=18.0, cfl=0.2, bc=(1, 0, 0, 1)), dem, h,
+                       np.where(h > 0, 0.5, 0.0), [])
+    for q, variant in ((_wb(pile, cfl=0.25), 0), (_wb(pile, I.F_CENTRAL_UPWIND, cfl=0.25), 2), (mu, 0),
+                       (_wb(ragged), 2)):
+        _say(f"[parity] well-balanced {q.name} flags {q.params.flags} variant request {variant}")
+        g, o = _compare_steps(q, 150, 1e-12, variant=variant)
+        dg, do = g.diag(), o.diag()
+        assert dg["clamp_count"] == do["clamps"]
+        for k in ("mass_s", "mass_f", "out_s", "out_f"):
+            assert abs(dg[k] - do[k]) <= 1e-12 * max(abs(do[k]), 1.0), k
+    for along_y in (False, True):
+        prob, U0 = lake(along_y)
+        _say(f"[parity] well-balanced lake along {'Y' if along_y else 'X'}")
+        g, o = Sim(prob, precision="f64"), Ora(prob)
+        g.set_state_raw(U0)
+        o.set_state_raw(U0)
+        dtg = np.array([g.step() for _ in range(100)])
+        dto = o.run(100)
+        Ug, Uo = g.state(), o.state()
+        _say(f"   max |p| {np.abs(Ug[[1, 2, 4, 5]]).max():.2e}  bitwise={np.array_equal(Ug, Uo)}")
+        np.testing.assert_allclose(dtg, dto, rtol=1e-12, atol=0)
+        assert relerr(Ug, Uo) <= 1e-12
+        assert np.abs(Ug[[1, 2, 4, 5]]).max() <= 1e-14 * Ug[3].max()
+        assert np.abs(Ug[3] - U0[3]).max() <= 1e-13 * U0[3].max()
+
+
+def test_well_balanced_fp32_and_refusals():
+    """FP32 with the well-balanced option: the plane-bump-pile release to 3 s
+    within the FP32 tolerance of the FP64 oracle with its volume kept to 1e-6,
+    and a lake at rest that stays at rest to FP32 rounding (velocities below
+    1e-5 of the lake's wave speed after 200 steps); the option refuses earth
+    pressure, inflow segments, the tangent and adjoint calls and ensembles."""
+    import dataclasses
+
+    from wb_lake import lake
+
+    from paper_2104_06784_amd._abi import M2P_EINVAL, M2PError
+    from paper_2104_06784_amd.sim import Batch
+    q = _wb(I.plane_bump_pile(), cfl=0.25)
+    g, o = Sim(q, precision="f32"), Ora(q)
+    m0 = g.diag()
+    g.run_to(3.0)
+    o.run(10 ** 6, 3.0)
+    hg, ho = g.fields()["h"], o.fields()["h"]
+    l1 = np.abs(hg - ho).sum() / ho.sum()
+    d = g.diag()
+    vol = abs(d["mass_s"] + d["mass_f"] - m0["mass_s"] - m0["mass_f"]) / (m0["mass_s"] + m0["mass_f"])
+    prob, U0 = lake()
+    gl = Sim(prob, precision="f32")
+    gl.set_state_raw(U0)
+    gl.run(200)
+    Ul = gl.state()
+    eps = prob.params.H / prob.params.L
+    # largest fluid speed relative to the deepest point's gravity-wave speed (scaled units)
+    vmax = (np.abs(Ul[[4, 5]]) / Ul[3]).max() / math.sqrt(eps * Ul[3].max())
+    _say(f"[parity] well-balanced FP32: plane-bump-pile rel L1 {l1:.3e}, volume {vol:.2e}; lake |v|/c {vmax:.2e}")
+    assert l1 <= 1e-3 and vol <= 1e-6 and vmax <= 1e-5
+    bad = dataclasses.replace(q, params=dataclasses.replace(q.params, flags=q.params.flags | I.F_EARTH_PRESSURE,
+                                                            delta_int_deg=35.0))
+    t, Q, ph = I.triangular_hydrograph(40.0, 10.0, 30.0, 0.45)
+    z = np.zeros((6, q.ny, q.nx))
+    for call in (lambda: Sim(bad, precision="f32"),
+                 lambda: g.set_inflow([I.Inflow(I.SIDE_S, 20, 7, t, Q, ph)]),
+                 lambda: g.set_inflow_states([I.InflowState(I.SIDE_S, 20, 7, t, 2.0 + 0 * t, ph, 1.0 + 0 * t)]),
+                 lambda: g.adjoint_run(4, 2, np.zeros((q.ny, q.nx))), lambda: g.stage_jvp(z),
+                 lambda: g.stage_vjp(z), lambda: Batch([q, q], precision="f32")):
+        with pytest.raises(M2PError) as e:
+            call()
+        assert e.value.code == M2P_EINVAL
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from paper_2104_06784_amd import inputs as I
+from wb_lake import lake
 
 pytestmark = pytest.mark.usefixtures("oracle_lib")
 
@@ -1101,35 +1102,6 @@ def test_critical_depth_cube_root_is_the_nearest_cube():
 
 # ------------------------------------------- well-balanced option (flag 32)
 
-def _lake(along_y=False, wb=True, n=64, m=24, seed=5, flat_edges=True, level_above=5.0):
-    """A lake at rest on a bed that varies in one direction only (a smoothed
-    random profile of 30 m relief, flat within four cells of its two ends so the
-    ghost cells' copies continue the lake), closed walls, fully wet: eta = eps c^2 m
-    = (level - b) / L per cell, no momentum."""
-    rng = np.random.default_rng(seed)
-    prof = np.cumsum(rng.standard_normal(n))
-    prof = np.convolve(prof, np.ones(5) / 5, mode="same")
-    prof = (prof - prof.min()) / np.ptp(prof) * 30.0
-    if flat_edges:
-        prof[:4] = prof[4]
-        prof[-4:] = prof[-5]
-    nx, ny = (m, n) if along_y else (n, m)
-    dx = 10.0
-    dem = np.tile(prof[:, None], (1, m)) if along_y else np.tile(prof, (m, 1))
-    p = I.Params(delta_b_deg=20.0, cfl=0.25, bc=(1, 1, 1, 1), flags=I.F_WELL_BALANCED if wb else 0)
-    z = np.zeros((ny, nx))
-    prob = I.Problem("lake", nx, ny, dx, dx, p, dem, z, z.copy(), [])
-    eps = p.H / p.L
-    b = dem / p.L
-    bp = np.pad(b, 1, mode="reflect", reflect_type="odd")  # the DEM's linear extension
-    bX = (bp[1:-1, 2:] - bp[1:-1, :-2]) / (2 * dx / p.L)
-    bY = (bp[2:, 1:-1] - bp[:-2, 1:-1]) / (2 * dx / p.L)
-    c2 = 1.0 / (1.0 + bX ** 2 + bY ** 2)
-    U = np.zeros((6, ny, nx))
-    U[3] = np.maximum((dem.max() + level_above) / p.L - b, 0.0) / (eps * c2)
-    return prob, U
-
-
 @pytest.mark.parametrize("along_y", [False, True])
 def test_well_balanced_lake_at_rest(along_y):
     """On a bed that varies in one direction (along X, and along Y), the model's
@@ -1139,7 +1111,7 @@ def test_well_balanced_lake_at_rest(along_y):
     scheme moves it (the pin fails if the face corrections, the bed face values
     or the source's mean face thickness are off)."""
     for wb in (True, False):
-        prob, U0 = _lake(along_y, wb)
+        prob, U0 = lake(along_y, wb)
         s = _sim(prob)
         s.set_state_raw(U0)
         s.run(200)
@@ -1179,7 +1151,7 @@ def test_well_balanced_walls_on_a_slope_keep_the_volume():
     its ends), raised by half near the west wall: the ghost side of each wall
     face mirrors the edge cell, so the volume is conserved to 1e-13 over 200
     steps while the water sloshes against the walls."""
-    prob, U0 = _lake(flat_edges=False)
+    prob, U0 = lake(flat_edges=False)
     U0[3, :, : U0.shape[2] // 3] *= 1.5
     s = _sim(prob)
     s.set_state_raw(U0)
@@ -1208,7 +1180,7 @@ def test_well_balanced_equals_plain_scheme_on_a_flat_bed():
 def test_well_balanced_is_mode_one_only_and_not_with_earth_pressure():
     """The option refuses inflow segments and the earth-pressure option."""
     import oracle
-    prob, _ = _lake()
+    prob, _ = lake()
     s = _sim(prob)
     t, Q, ph = I.triangular_hydrograph(30.0, 5.0, 20.0, 0.5)
     with pytest.raises(ValueError):
