@@ -191,14 +191,11 @@ namespace m2p {
 Shape make_shape(const KParams& P, int variant, int rows, int slots)
 {
     Shape s{};
-    // the smooth-friction and well-balanced options, and earth pressure with
-    // the central-upwind flux or with Mode-II state segments, run on the
-    // reference kernel
+    // the smooth-friction option, and earth pressure with the central-upwind
+    // flux or with Mode-II state segments, run on the reference kernel
     const bool ep_ref =
         (P.flags & kFlagEarthPressure) && ((P.flags & kFlagCentralUpwind) || P.nsseg > 0);
-    s.variant = (variant == M2P_VARIANT_REFERENCE || (P.flags & (kFlagSmoothFriction | kFlagWellBalanced)) || ep_ref)
-                    ? 1
-                    : 2;
+    s.variant = (variant == M2P_VARIANT_REFERENCE || (P.flags & kFlagSmoothFriction) || ep_ref) ? 1 : 2;
     s.global_addr = variant == M2P_VARIANT_TILED_GLOBAL;
     s.nbx = (P.nx + 63) / 64;
     s.nby = (P.ny + 3) / 4;

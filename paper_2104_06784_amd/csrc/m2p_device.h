@@ -545,6 +545,7 @@ M2P_FN void wb_face(const Consts<T>& K, int flags, const T uL[NF], Geo<T> gL, T 
                     T c2R, const T etaL_[2], const T bL_[2], const T etaR_[2], const T bR_[2], bool wallL,
                     bool wallR, int d, T H[NF], T cL[NF], T cR[NF])
 {
+    // (the flux of the starred states is the one the flags select)
     if (wallL) {
         gL = gR;
         c2L = c2R;

@@ -65,29 +65,31 @@ hipError_t Launch<M2P_REAL>::step_part(const KParams& P, const Bufs& B, const Sh
         // fits in 31 bits (4096 x 4096 FP32: 403 MB)
         const bool buf = !sh.global_addr && (uint64_t)NF * P.ny * P.pitch * sizeof(T) < (1ull << 31) &&
                          (uint64_t)(P.ny + 2 * BHALO) * P.bpitch * sizeof(T) < (1ull << 31);
-#define M2P_TILED_GC(K, GH, CU, EP)                                                                             \
+#define M2P_TILED_GC(K, GH, CU, EP, WB)                                                                         \
     do {                                                                                                        \
         if (buf)                                                                                                \
-            hipLaunchKernelGGL((k_stage_tiled<T, K, GH, CU, EP, true>), grd, blk, 0, st, P, in, U, out, b, mu,  \
-                               B.S, B.bpart, B.wpart, B.nmax, sh.R, sh.nstrips, sh.nrb);                         \
+            hipLaunchKernelGGL((k_stage_tiled<T, K, GH, CU, EP, true, WB>), grd, blk, 0, st, P, in, U, out, b,  \
+                               mu, B.S, B.bpart, B.wpart, B.nmax, sh.R, sh.nstrips, sh.nrb);                     \
         else                                                                                                    \
-            hipLaunchKernelGGL((k_stage_tiled<T, K, GH, CU, EP, false>), grd, blk, 0, st, P, in, U, out, b, mu, \
-                               B.S, B.bpart, B.wpart, B.nmax, sh.R, sh.nstrips, sh.nrb);                         \
+            hipLaunchKernelGGL((k_stage_tiled<T, K, GH, CU, EP, false, WB>), grd, blk, 0, st, P, in, U, out, b, \
+                               mu, B.S, B.bpart, B.wpart, B.nmax, sh.R, sh.nstrips, sh.nrb);                     \
     } while (0)
 #define M2P_TILED(K)                                                                                            \
     do {                                                                                                        \
         const bool cu = (P.flags & kFlagCentralUpwind) != 0;                                                    \
-        if (P.flags & kFlagEarthPressure)                                                                       \
-            M2P_TILED_GC(K, false, false, true);                                                                \
+        if (P.flags & kFlagWellBalanced)                                                                        \
+            M2P_TILED_GC(K, false, false, false, true);                                                         \
+        else if (P.flags & kFlagEarthPressure)                                                                  \
+            M2P_TILED_GC(K, false, false, true, false);                                                         \
         else if (P.nsseg > 0) {                                                                                 \
             if (cu)                                                                                             \
-                M2P_TILED_GC(K, true, true, false);                                                             \
+                M2P_TILED_GC(K, true, true, false, false);                                                      \
             else                                                                                                \
-                M2P_TILED_GC(K, true, false, false);                                                            \
+                M2P_TILED_GC(K, true, false, false, false);                                                     \
         } else if (cu)                                                                                          \
-            M2P_TILED_GC(K, false, true, false);                                                                \
+            M2P_TILED_GC(K, false, true, false, false);                                                         \
         else                                                                                                    \
-            M2P_TILED_GC(K, false, false, false);                                                               \
+            M2P_TILED_GC(K, false, false, false, false);                                                        \
     } while (0)
         if (kind == 1)
             M2P_TILED(1);
@@ -112,7 +114,10 @@ int Launch<M2P_REAL>::resident_waves(const KParams& P)
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     hipError_t e;
-    if (P.flags & kFlagEarthPressure)
+    if (P.flags & kFlagWellBalanced)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stage_tiled<T, 2, false, false, false, true, true>,
+                                                         256, 0);
+    else if (P.flags & kFlagEarthPressure)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stage_tiled<T, 2, false, false, true>, 256, 0);
     else if (P.flags & kFlagCentralUpwind)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stage_tiled<T, 2, false, true, false>, 256, 0);

@@ -84,6 +84,7 @@ struct RowD {
     T Jh;          // J_b h = m^s + m^f
     T Gf;          // J_b h pbar^f
     T kx, ky;      // earth-pressure coefficients of the stage input (the option; else unused)
+    T cx;          // well-balanced option: c with the bed of both x-neighbours from memory (else unused)
 };
 
 // Earth-pressure coefficients for a uniform basal friction t: K_x active and
@@ -103,6 +104,31 @@ struct EPTab {
         kypp = ep_ky(kxp, t, false);
     }
 };
+
+// Well-balanced option: a row's face values along y (eta per phase and the
+// bed, minus and plus side) and the right-cell pressure correction of the
+// y-face below it (momentum components 1, 2, 4, 5), carried up the march.
+template <typename T>
+struct WBRow {
+    T em[2], ep[2], bm, bp;
+    T cr[4];
+};
+
+// Face values along one direction of a cell from the masses m0..m2 of phase
+// ph's three cells along it, their c^2 and beds (wb_cell on eta = eps c^2 m).
+template <typename T>
+__device__ __forceinline__ void wb_row_values(const Consts<T>& K, const T* u0, const T* u1, const T* u2, T c0, T c1,
+                                              T c2, T b0, T b1, T b2, WBRow<T>& w)
+{
+#pragma unroll
+    for (int ph = 0; ph < 2; ph++) {
+        T bm, bp;
+        wb_cell(K.eps * (c0 * c0) * u0[3 * ph], K.eps * (c1 * c1) * u1[3 * ph], K.eps * (c2 * c2) * u2[3 * ph], b0, b1,
+                b2, w.em[ph], w.ep[ph], bm, bp);
+        w.bm = bm;
+        w.bp = bp;
+    }
+}
 
 // With EP, also the row's earth-pressure coefficients from the solid
 // velocities of its x-neighbours (lane shifts) and of the rows below (uS) and
@@ -160,10 +186,17 @@ __device__ __forceinline__ void visc_yface_rows(const RowD<T>& a, const RowD<T>&
 #ifndef M2P_TILED_WPE_EP
 #define M2P_TILED_WPE_EP 2
 #endif
-template <typename T, int STAGE, bool EP = false>
+// The well-balanced instance carries the face values and corrections of the
+// hydrostatic reconstruction besides: two waves.
+#ifndef M2P_TILED_WPE_WB
+#define M2P_TILED_WPE_WB 2
+#endif
+template <typename T, int STAGE, bool EP = false, bool WB = false>
 constexpr int tiled_wpe()
 {
-    return sizeof(T) == 4 ? (EP ? M2P_TILED_WPE_EP : (STAGE == 1 ? M2P_TILED_WPE_S1 : M2P_TILED_WPE_S2)) : 1;
+    return sizeof(T) == 4 ? (WB ? M2P_TILED_WPE_WB
+                                : (EP ? M2P_TILED_WPE_EP : (STAGE == 1 ? M2P_TILED_WPE_S1 : M2P_TILED_WPE_S2)))
+                          : 1;
 }
 
 // Partials of one wavefront's share of a stage: speed maxima (last stage),
@@ -180,8 +213,9 @@ struct WavePart {
 // earth-pressure coefficients, computed in the march for the row ahead (a
 // ghost cell takes those of the cell it maps to).  BUF: the state and DEM
 // accesses as raw buffer accesses (every byte offset below 2 GiB; 3 % faster
-// per step at 4096 x 4096).
-template <typename T, int STAGE, bool GH, bool CU = false, bool EP = false, bool BUF = false>
+// per step at 4096 x 4096).  WB: the well-balanced hydrostatic reconstruction
+// (Mode-I, no earth pressure; the face flux the flags select).
+template <typename T, int STAGE, bool GH, bool CU = false, bool EP = false, bool BUF = false, bool WB = false>
 __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* __restrict__ Uin, const T* Un, T* Uout,
                                                  const T* __restrict__ b, const T* __restrict__ mu,
                                                  DevScalars* __restrict__ S, double* __restrict__ bpart,
@@ -191,7 +225,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
     // stage 1 carries face fluxes as 2 H in the FP32 forms (later stages keep
     // H: the extra registers of the factorised update do not fit their
     // three-waves-per-SIMD budget)
-    constexpr bool H2 = STAGE == 1;
+    constexpr bool H2 = STAGE == 1 && !WB;
     const size_t fs = (size_t)P.ny * P.pitch;
     const int col = strip * kStripOut - 2 + lane;
     const int cc = col < P.nx + 1 ? col : P.nx + 1;  // lanes past the ghost ring feed no output
@@ -260,6 +294,26 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
         else
             return b[o];
     };
+    // Well-balanced option: the eta slopes along x of lanes 1 and 62 need c
+    // of lanes 0 and 63, whose geometry took one x-neighbour's bed from
+    // outside the wavefront; those two lanes recompute c with that bed read
+    // from memory (a column of the padded DEM row, clamped into the row).
+    auto wb_cx = [&](int r, T bC, T bS, T bN, RowD<T>& D) {
+        if constexpr (WB) {
+            const T bE = from_right(bC), bW = from_left(bC);
+            D.cx = D.g.c;
+            if (lane == 0 || lane == 63) {
+                const int c = bcol + (lane == 0 ? -1 : 1);
+                const size_t o = (size_t)(r + BHALO) * P.bpitch + (c < P.bpitch ? c : P.bpitch - 1);
+                T bo;
+                if constexpr (BUF)
+                    bo = bload((T*)nullptr, rB, (unsigned)(o * sizeof(T)), 0u);
+                else
+                    bo = b[o];
+                D.cx = geometry(lane == 63 ? bo : bE, lane == 0 ? bo : bW, bN, bS, K.two_dxi, K.two_deta).c;
+            }
+        }
+    };
 
     // flux through each boundary face into the stage's outflow slot (zero on
     // discharge-inflow faces); the first stage records the step the updates
@@ -297,9 +351,12 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
     if (EP && uni) tab.init(c2, K.tan_d);
     make_row<T, EP>(K, Um1, bm1, bm2, b0, Dm, Um2, U0, c2, EP && !uni ? tmu_row(r0 - 1) : T(0), uni, &tab);
     make_row<T, EP>(K, U0, b0, bm1, b1, D0, Um1, U1, c2, EP && !uni ? tmu_row(r0) : T(0), uni, &tab);
+    wb_cx(r0 - 1, bm1, bm2, b0, Dm);
+    wb_cx(r0, b0, bm1, b1, D0);
     if (EP && r0 == 0) Dm.ky = D0.ky;  // ghost row -1 maps to row 0
     T sy0[NF];  // y-slopes of row r0
     T Hy[NF];            // y-face flux j - 1/2
+    WBRow<T> wa, wb;     // well-balanced carries, slot (row - r0) mod 2
     {
         T sym[NF], uL[NF], uR[NF];
 #pragma unroll
@@ -309,7 +366,28 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             uL[k] = Um1[k] + T(0.5) * sym[k];
             uR[k] = U0[k] - T(0.5) * sy0[k];
         }
-        central_flux<T, H2, CU>(K, uL, Dm.g, uR, D0.g, 1, Hy, EP ? Dm.ky : T(1), EP ? D0.ky : T(1));
+        if constexpr (WB) {
+            // face values of rows r0 - 1 and r0: c of row r0 - 2 (the ghost row
+            // -2 takes row -1's) and of row r0 + 1 from their geometry
+            const T bm3 = r0 - 2 < -1 ? T(0) : loadB(r0 - 3);
+            const T cm2 = r0 - 2 < -1 ? Dm.g.c
+                                      : geometry(from_right(bm2), from_left(bm2), bm1, bm3, K.two_dxi, K.two_deta).c;
+            const T b2 = loadB(r0 + 2);
+            const T c1 = geometry(from_right(b1), from_left(b1), b2, b0, K.two_dxi, K.two_deta).c;
+            WBRow<T> wm;
+            wb_row_values(K, Um2, Um1, U0, cm2, Dm.g.c, D0.g.c, bm2, bm1, b0, wm);
+            wb_row_values(K, Um1, U0, U1, Dm.g.c, D0.g.c, c1, bm1, b0, b1, wa);
+            const T wmb[2] = {wm.bp, wm.bp}, wab[2] = {wa.bm, wa.bm};
+            T cl[NF], cr[NF];
+            wb_face(K, P.flags, uL, Dm.g, Dm.g.c * Dm.g.c, uR, D0.g, D0.g.c * D0.g.c, wm.ep, wmb, wa.em, wab,
+                    r0 == 0 && P.bc[2] == 1, false, 1, Hy, cl, cr);
+            wa.cr[0] = cr[1];
+            wa.cr[1] = cr[2];
+            wa.cr[2] = cr[4];
+            wa.cr[3] = cr[5];
+        } else {
+            central_flux<T, H2, CU>(K, uL, Dm.g, uR, D0.g, 1, Hy, EP ? Dm.ky : T(1), EP ? D0.ky : T(1));
+        }
         if (r0 == 0 && out_lane) {
             const int s = inflow_seg_at(P, 2, col);
             if (s >= 0)
@@ -343,8 +421,8 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
     // of row j+1 / face j+1/2.  The march calls it with the slots rotated, so
     // the window never moves through registers.
     auto row = [&](int j, T* Uc, T* Un1, T* U2, T* U3, T bj, T bj1, T bj2, T& bj3, RowD<T>& Dm, RowD<T>& D0,
-                   RowD<T>& D1, T* sy0, T* sy1, T* Hy, T* HyN, T vGX, T vGY, T& vGXN, T& vGYN)
-                   __attribute__((always_inline)) {
+                   RowD<T>& D1, T* sy0, T* sy1, T* Hy, T* HyN, T vGX, T vGY, T& vGXN, T& vGYN, WBRow<T>& w0,
+                   WBRow<T>& w1) __attribute__((always_inline)) {
         // ---- prefetch row j+3 (consumed next iteration) and this row's own
         // values needed at the end (U^n for the Heun average, tan delta)
         const int rn = j + 3 <= P.ny + 1 ? j + 3 : P.ny + 1;
@@ -363,6 +441,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
         }
         const T tmu = P.has_mu ? mu[cself] : K.tan_d;
         make_row<T, EP>(K, Un1, bj1, bj, bj2, D1, Uc, U2, c2, EP && !uni ? tmu_row(j + 1) : T(0), uni, &tab);
+        wb_cx(j + 1, bj1, bj, bj2, D1);
         if (EP && j + 1 == P.ny) D1.ky = D0.ky;  // ghost row ny maps to row ny - 1
         T uL[NF], uR[NF];
 #pragma unroll
@@ -372,7 +451,30 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             uR[k] = Un1[k] - T(0.5) * sy1[k];
         }
         // ---- y-face j + 1/2
-        central_flux<T, H2, CU>(K, uL, D0.g, uR, D1.g, 1, HyN, EP ? D0.ky : T(1), EP ? D1.ky : T(1));
+        T cy[NF];  // well-balanced: the cell's y corrections
+        if constexpr (WB) {
+            // face values of row j + 1 (c of row j + 2 from its geometry; the
+            // ghost row ny + 1 takes row ny's)
+            const T cj2 = j + 2 > P.ny ? D1.g.c
+                                       : geometry(from_right(bj2), from_left(bj2), bj3, bj1, K.two_dxi, K.two_deta).c;
+            wb_row_values(K, Uc, Un1, U2, D0.g.c, D1.g.c, cj2, bj, bj1, bj2, w1);
+            const T w0b[2] = {w0.bp, w0.bp}, w1b[2] = {w1.bm, w1.bm};
+            T cl[NF], cr[NF];
+            wb_face(K, P.flags, uL, D0.g, D0.g.c * D0.g.c, uR, D1.g, D1.g.c * D1.g.c, w0.ep, w0b, w1.em, w1b, false,
+                    j + 1 == P.ny && P.bc[3] == 1, 1, HyN, cl, cr);
+            cy[0] = T(0);
+            cy[1] = cl[1] - w0.cr[0];
+            cy[2] = cl[2] - w0.cr[1];
+            cy[3] = T(0);
+            cy[4] = cl[4] - w0.cr[2];
+            cy[5] = cl[5] - w0.cr[3];
+            w1.cr[0] = cr[1];
+            w1.cr[1] = cr[2];
+            w1.cr[2] = cr[4];
+            w1.cr[3] = cr[5];
+        } else {
+            central_flux<T, H2, CU>(K, uL, D0.g, uR, D1.g, 1, HyN, EP ? D0.ky : T(1), EP ? D1.ky : T(1));
+        }
         if (j == P.ny - 1 && out_lane) {
             const int s = inflow_seg_at(P, 3, col);
             if (s >= 0)
@@ -385,6 +487,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
 
         // ---- x-faces of row j: this lane computes face i + 1/2
         T Hx[NF], HxL[NF];
+        T cxw[NF], wbs[4];  // well-balanced: the cell's x corrections, balanced source terms
         {
             T sx[NF], up[NF], um[NF], upR[NF];
 #pragma unroll
@@ -412,7 +515,37 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
                 kL = ghostW ? fromE : (ghostE ? fromW : D0.kx);
                 kR = from_right(kL);
             }
-            central_flux<T, H2, CU>(K, um, D0.g, upR, gR, 0, Hx, kL, kR);
+            if constexpr (WB) {
+                // c along x: a column two outside takes the ghost column's
+                const T cE = from_right(D0.cx), cW = from_left(D0.cx);
+                const T cx = col <= -2 ? cE : (col >= P.nx + 1 ? cW : D0.cx);
+                const T c2x = cx * cx;
+                const T bE = from_right(bj), bW = from_left(bj);
+                T em[2], ep[2], bm[2], bp[2], emR[2], bmR[2];
+#pragma unroll
+                for (int ph = 0; ph < 2; ph++) {
+                    const T e = K.eps * c2x * Uc[3 * ph];
+                    wb_cell(from_left(e), e, from_right(e), bW, bj, bE, em[ph], ep[ph], bm[ph], bp[ph]);
+                    emR[ph] = from_right(em[ph]);
+                    bmR[ph] = from_right(bm[ph]);
+                }
+                T cl[NF], cr[NF];
+                wb_face(K, P.flags, um, D0.g, c2x, upR, gR, from_right(c2x), ep, bp, emR, bmR,
+                        col == -1 && P.bc[0] == 1, col + 1 == P.nx && P.bc[1] == 1, 0, Hx, cl, cr);
+                cxw[0] = T(0);
+                cxw[3] = T(0);
+#pragma unroll
+                for (int k = 1; k < NF; k++)
+                    if (k != 3) cxw[k] = cl[k] - from_left(cr[k]);
+#pragma unroll
+                for (int ph = 0; ph < 2; ph++) {
+                    const T fac = ph == 0 ? T(1) - K.al : T(1);
+                    wbs[2 * ph] = -(fac / K.eps) * (T(0.5) * (em[ph] + ep[ph])) * (bp[ph] - bm[ph]) / K.dxi;
+                    wbs[2 * ph + 1] = -(fac / K.eps) * (T(0.5) * (w0.em[ph] + w0.ep[ph])) * (w0.bp - w0.bm) / K.deta;
+                }
+            } else {
+                central_flux<T, H2, CU>(K, um, D0.g, upR, gR, 0, Hx, kL, kR);
+            }
 #pragma unroll
             for (int k = 0; k < NF; k++) HxL[k] = from_left(Hx[k]);
         }
@@ -446,7 +579,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
         const T dGx = (GE - GW) / K.two_dxi;
         const T dGy = (D1.Gf - Dm.Gf) / K.two_deta;
         Src<T> Sr;
-        sources(K, P.flags, Uc, D0.g, dn, dGx, dGy, Sr);
+        sources(K, P.flags, Uc, D0.g, dn, dGx, dGy, Sr, WB ? wbs : nullptr);
         T svx = T(0), svy = T(0);
         if (P.visc) {
             // x-face i + 1/2 viscous fluxes, then face i - 1/2 from the left lane
@@ -471,7 +604,8 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
         // ---- update and write
         if (out_lane) {
             T out[NF];
-            clamps += update_cell<T, H2, false>(K, Uc, D0.g, HxL, Hx, Hy, HyN, Sr, svx, svy, dt, tmu, out);
+            clamps += update_cell<T, H2, false>(K, Uc, D0.g, HxL, Hx, Hy, HyN, Sr, svx, svy, dt, tmu, out,
+                                                WB ? cxw : nullptr, WB ? cy : nullptr);
             if (STAGE > 1) {
 #pragma unroll
                 for (int k = 0; k < NF; k++) out[k] = stage_combine<STAGE>(unr[k], out[k]);
@@ -497,13 +631,13 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
 
     // rows r0 .. r1-1, four per trip with the slots rotated
     for (int j = r0; j < r1; j += 4) {
-        row(j, Ua, Ub, Uc_, Ud, ba, bb, bc, bd, Dd, Da, Db, sya, syb, Hya, Hyb, vGXa, vGYa, vGXb, vGYb);
+        row(j, Ua, Ub, Uc_, Ud, ba, bb, bc, bd, Dd, Da, Db, sya, syb, Hya, Hyb, vGXa, vGYa, vGXb, vGYb, wa, wb);
         if (j + 1 >= r1) break;
-        row(j + 1, Ub, Uc_, Ud, Ua, bb, bc, bd, ba, Da, Db, Dc, syb, sya, Hyb, Hya, vGXb, vGYb, vGXa, vGYa);
+        row(j + 1, Ub, Uc_, Ud, Ua, bb, bc, bd, ba, Da, Db, Dc, syb, sya, Hyb, Hya, vGXb, vGYb, vGXa, vGYa, wb, wa);
         if (j + 2 >= r1) break;
-        row(j + 2, Uc_, Ud, Ua, Ub, bc, bd, ba, bb, Db, Dc, Dd, sya, syb, Hya, Hyb, vGXa, vGYa, vGXb, vGYb);
+        row(j + 2, Uc_, Ud, Ua, Ub, bc, bd, ba, bb, Db, Dc, Dd, sya, syb, Hya, Hyb, vGXa, vGYa, vGXb, vGYb, wa, wb);
         if (j + 3 >= r1) break;
-        row(j + 3, Ud, Ua, Ub, Uc_, bd, ba, bb, bc, Dc, Dd, Da, syb, sya, Hyb, Hya, vGXb, vGYb, vGXa, vGYa);
+        row(j + 3, Ud, Ua, Ub, Uc_, bd, ba, bb, bc, Dc, Dd, Da, syb, sya, Hyb, Hya, vGXb, vGYb, vGXa, vGYa, wb, wa);
     }
 
     // ---- wavefront reductions (fixed butterfly => deterministic in lane 0)
@@ -517,8 +651,8 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
     return WavePart{(double)amx, (double)amy, (double)clamps, (double)bad};
 }
 
-template <typename T, int STAGE, bool GH, bool CU, bool EP = false, bool BUF = false>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_wpe<T, STAGE, EP>())))
+template <typename T, int STAGE, bool GH, bool CU, bool EP = false, bool BUF = false, bool WB = false>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_wpe<T, STAGE, EP, WB>())))
 k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout, const T* __restrict__ b,
               const T* __restrict__ mu, DevScalars* __restrict__ S, double* __restrict__ bpart,
               double* __restrict__ wpart, int nmax, int R, int nstrips, int nrb)
@@ -538,8 +672,8 @@ k_stage_tiled(KParams P, const T* __restrict__ Uin, const T* Un, T* Uout, const 
     const int strip = wid % nstrips, rb = wid / nstrips;
     WavePart r{0.0, 0.0, 0.0, 0.0};  // neutral: speeds are >= 0
     if (rb < nrb)  // whole wavefront
-        r = stage_tiled_wave<T, STAGE, GH, CU, EP, BUF>(P, Uin, Un, Uout, b, mu, S, bpart, nmax, R, nstrips, nrb, strip,
-                                                       rb, lane);
+        r = stage_tiled_wave<T, STAGE, GH, CU, EP, BUF, WB>(P, Uin, Un, Uout, b, mu, S, bpart, nmax, R, nstrips, nrb,
+                                                           strip, rb, lane);
     // one partial record per workgroup (its four wavefronts in order), so
     // the finalize reads a quarter as many (the barrier costs small grids
     // about 0.4 us per stage).  Plain stores: accumulating them with

@@ -489,15 +489,15 @@ def _wb(prob, extra=0, cfl=None):
     return q
 
 
-def test_well_balanced_option_fp64():
+@pytest.mark.parametrize("variant", [1, 2])
+def test_well_balanced_option_fp64(variant):
     """The well-balanced option (M2P_F_WELL_BALANCED) against the oracle's,
-    FP64 to 1e-12 (state and dt) and its diagnostics: the plane-bump-pile
-    release (walls, dry bed around the pile), with the central-upwind flux,
-    with the three-stage method and a friction field, the ragged grid with
-    transmissive sides (its Mode-II segment removed: the option is Mode-I
-    only), and lakes at rest on beds that vary along X and along Y, which stay
-    at rest on the GPU too.  Any kernel variant request runs the reference
-    kernel."""
+    FP64 to 1e-12 (state and dt) and its diagnostics, on both kernel variants:
+    the plane-bump-pile release (walls, dry bed around the pile), with the
+    central-upwind flux, with the three-stage method and a friction field, the
+    ragged grid with transmissive sides (its Mode-II segment removed: the
+    option is Mode-I only), and lakes at rest on beds that vary along X and
+    along Y, which stay at rest on the GPU too."""
     import dataclasses
     from wb_lake import lake
     pile = I.plane_bump_pile(n=96)
@@ -508,9 +508,8 @@ def test_well_balanced_option_fp64():
     h = I.cylinder(n_x, n_y, dx, dx, 300.0, 200.0, 90.0, 6.0)
     ragged = I.Problem("ragged", n_x, n_y, dx, dx, I.Params(delta_b_deg=18.0, cfl=0.2, bc=(1, 0, 0, 1)), dem, h,
                        np.where(h > 0, 0.5, 0.0), [])
-    for q, variant in ((_wb(pile, cfl=0.25), 0), (_wb(pile, I.F_CENTRAL_UPWIND, cfl=0.25), 2), (mu, 0),
-                       (_wb(ragged), 2)):
-        _say(f"[parity] well-balanced {q.name} flags {q.params.flags} variant request {variant}")
+    for q in (_wb(pile, cfl=0.25), _wb(pile, I.F_CENTRAL_UPWIND, cfl=0.25), mu, _wb(ragged)):
+        _say(f"[parity] well-balanced {q.name} flags {q.params.flags} variant {variant}")
         g, o = _compare_steps(q, 150, 1e-12, variant=variant)
         dg, do = g.diag(), o.diag()
         assert dg["clamp_count"] == do["clamps"]
@@ -519,7 +518,7 @@ def test_well_balanced_option_fp64():
     for along_y in (False, True):
         prob, U0 = lake(along_y)
         _say(f"[parity] well-balanced lake along {'Y' if along_y else 'X'}")
-        g, o = Sim(prob, precision="f64"), Ora(prob)
+        g, o = Sim(prob, precision="f64", variant=variant), Ora(prob)
         g.set_state_raw(U0)
         o.set_state_raw(U0)
         dtg = np.array([g.step() for _ in range(100)])
@@ -530,6 +529,41 @@ def test_well_balanced_option_fp64():
         assert relerr(Ug, Uo) <= 1e-12
         assert np.abs(Ug[[1, 2, 4, 5]]).max() <= 1e-14 * Ug[3].max()
         assert np.abs(Ug[3] - U0[3]).max() <= 1e-13 * U0[3].max()
+
+
+@pytest.mark.parametrize("rows", [1, 2, 3, 7, 45])
+def test_well_balanced_tiled_bitwise_equal_reference(rows):
+    """The tiled kernel's well-balanced instance at any tile height equals the
+    reference kernel's bitwise in FP64 (state, dt, diagnostics) on a ragged
+    three-strip grid whose release straddles the first strip boundary (the
+    eta slopes there read the c of the strips' outermost lanes): walls on two
+    sides, then walls on all four and the central-upwind flux; in FP32 every
+    tile height gives the bits of the one-row tiles."""
+    import dataclasses
+    n_x, n_y, dx = 131, 45, 10.0
+    dem = I.fractal_dem(n_x, dx, 78, 60.0, tilt_deg=15.0, ny=n_y)
+    h = I.cylinder(n_x, n_y, dx, dx, 600.0, 200.0, 150.0, 6.0)
+    p = I.Params(delta_b_deg=18.0, cfl=0.2, bc=(0, 1, 1, 0), flags=I.F_WELL_BALANCED)
+    prob = I.Problem("rows-wb", n_x, n_y, dx, dx, p, dem, h, np.where(h > 0, 0.5, 0.0), [])
+    cu = dataclasses.replace(prob, params=dataclasses.replace(p, flags=I.F_WELL_BALANCED | I.F_CENTRAL_UPWIND,
+                                                              bc=(1, 1, 1, 1)))
+    for q in (prob, cu):
+        a = Sim(q, precision="f64", variant=1)
+        b = Sim(q, precision="f64", variant=2, tile_rows=rows)
+        da = [a.step() for _ in range(60)]
+        db = [b.step() for _ in range(60)]
+        _say(f"[rows wb] flags {q.params.flags} R={rows}: bitwise={np.array_equal(a.state(), b.state())} "
+             f"max diff {np.max(np.abs(a.state() - b.state())):.3e}")
+        assert da == db
+        assert np.array_equal(a.state(), b.state())
+        assert a.diag() == b.diag()
+    if rows > 1:
+        ref = Sim(prob, precision="f32", variant=2, tile_rows=1)
+        b = Sim(prob, precision="f32", variant=2, tile_rows=rows)
+        ref.run(60)
+        b.run(60)
+        assert np.array_equal(ref.state(), b.state())
+        assert ref.diag() == b.diag()
 
 
 def test_well_balanced_fp32_and_refusals():
