@@ -222,8 +222,8 @@ def bench_sweep(stream, steps: int) -> dict:
 
 def bench_variants(stream, steps: int, prob3) -> dict:
     """The scheme variants on their workloads: the three-stage Runge-Kutta,
-    central-upwind flux and earth-pressure (reference kernel) options on the
-    large event (prob3, FP32),
+    central-upwind flux, earth-pressure and well-balanced options on the
+    large event (prob3, FP32, tiled kernel),
     and Mode-II inflow as a state hydrograph on the paper's second event's
     grid shape (180 x 154, graph replay) next to the same grid without the
     segment."""
@@ -244,7 +244,7 @@ def bench_variants(stream, steps: int, prob3) -> dict:
 
     out = {}
     for key, flag in (("rk3", inputs.F_RK3), ("central_upwind", inputs.F_CENTRAL_UPWIND),
-                      ("earth_pressure", inputs.F_EARTH_PRESSURE)):
+                      ("earth_pressure", inputs.F_EARTH_PRESSURE), ("well_balanced", inputs.F_WELL_BALANCED)):
         p3 = dataclasses.replace(prob3, params=dataclasses.replace(prob3.params, flags=flag))
         sim = Sim(p3, precision="f32", stream=stream)
         sim.run(5)
@@ -267,7 +267,8 @@ def bench_variants(stream, steps: int, prob3) -> dict:
         del sim
     out["mode2_state"] = rec
     log(f"[bench] variants: rk3 {out['rk3']['value']}, central-upwind {out['central_upwind']['value']}, "
-        f"earth pressure {out['earth_pressure']['value']} Mcell-steps/s; state inflow "
+        f"earth pressure {out['earth_pressure']['value']}, well-balanced {out['well_balanced']['value']} "
+        f"Mcell-steps/s; state inflow "
         f"{rec['state_inflow_us_per_step']} us/step ({rec['no_inflow_us_per_step']} without)")
     return out
 
