@@ -741,7 +741,8 @@ static void face_values(const ora_sim *o, int i, int j, int d, double uL[NF], do
  * values of eta and of the bed by minmod; at a face, B* = max of the two bed
  * values, eta* = max(0, eta + b - B*) per side; the face flux from the starred
  * states (m* = eta* / (eps c^2), momenta m* times the side's velocity, the
- * masses' numerical diffusion on eta*); each cell adds the difference of the
+ * masses' numerical diffusion on eta* with the larger 1 / (eps c^2) of the two
+ * sides); each cell adds the difference of the
  * pressure terms of its own face state and the starred one; the hydrostatic
  * part of the basal-pressure source uses the mean of the cell's two face
  * values of eta and the difference of its two bed face values. */
@@ -837,7 +838,10 @@ static void hr_face(ora_sim *o, int i, int j, int d, const double uL[NF], const 
         double fL = mL > 0.0 ? msL / mL : 0.0, fR = mR > 0.0 ? msR / mR : 0.0;
         sL[k0] = msL; sL[k0 + 1] = uL[k0 + 1] * fL; sL[k0 + 2] = uL[k0 + 2] * fL;
         sR[k0] = msR; sR[k0 + 1] = uR[k0 + 1] * fR; sR[k0 + 2] = uR[k0 + 2] * fR;
-        dqm[ph] = (esR - esL) * ((1.0 / c2L + 1.0 / c2R) / (2.0 * o->eps));
+        /* mass diffusion weight: the larger 1 / (eps c^2) of the two sides,
+         * so each side's diffusion covers its own flux m* v (no mass leaves a
+         * dry cell next to a wet one on a different slope) */
+        dqm[ph] = (esR - esL) * ((c2L < c2R ? 1.0 / c2L : 1.0 / c2R) / o->eps);
         /* unstarred face states for the pressure corrections */
         cL[k0] = mL; cL[k0 + 1] = uL[k0 + 1]; cL[k0 + 2] = uL[k0 + 2];
         cR[k0] = mR; cR[k0 + 1] = uR[k0 + 1]; cR[k0 + 2] = uR[k0 + 2];
