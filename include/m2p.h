@@ -93,7 +93,8 @@ extern "C" {
                        the model's variables): per phase eta = eps c^2 m; per cell and direction minmod face values
                        of eta and of the bed; at a face B* = max of the two bed values, eta* = max(0, eta + b - B*)
                        per side, the flux from the starred states (m* = eta* / (eps c^2), momenta scaled by m* / m,
-                       the masses' numerical diffusion on eta*), each cell adding the pressure terms of its
+                       the masses' numerical diffusion on eta* weighted with the larger 1 / (eps c^2) of the two
+                       sides, which keeps dry cells positive), each cell adding the pressure terms of its
                        unstarred minus its starred face state; the hydrostatic part of the basal-pressure source
                        becomes -(fac / eps) (mean face eta) (bed face difference) / step (fac = 1 - alpha for the
                        solid, 1 for the fluid).  A wall face mirrors the edge cell.  Keeps a lake at rest on beds

@@ -491,7 +491,8 @@ M2P_FN void face_flux_sel(const Consts<T>& K, int flags, const T uL[NF], const G
 // and of the bed come from minmod slopes; at a face B* is the larger bed value,
 // eta* = max(0, eta + b - B*) per side, the flux is taken from the starred
 // states (m* = eta* / (eps c^2), momenta scaled by m* / m, the masses'
-// numerical diffusion on eta*), and each cell adds the difference of the
+// numerical diffusion on eta* weighted with the larger 1 / (eps c^2) of the
+// two sides), and each cell adds the difference of the
 // pressure terms of its unstarred and starred face states; the hydrostatic
 // part of the basal-pressure source takes the matching discrete form.
 
@@ -580,7 +581,10 @@ M2P_FN void wb_face(const Consts<T>& K, int flags, const T uL[NF], Geo<T> gL, T 
         sR[k0] = msR;
         sR[k0 + 1] = uR[k0 + 1] * fR;
         sR[k0 + 2] = uR[k0 + 2] * fR;
-        dqm[ph] = (esR - esL) * ((T(1) / c2L + T(1) / c2R) / (T(2) * K.eps));
+        // the larger 1 / (eps c^2) of the two sides: each side's diffusion
+        // covers its own flux m* v (no mass leaves a dry cell next to a wet
+        // one on a different slope)
+        dqm[ph] = (esR - esL) * ((c2L < c2R ? T(1) / c2L : T(1) / c2R) / K.eps);
         cL[k0] = mL;
         cL[k0 + 1] = uL[k0 + 1];
         cL[k0 + 2] = uL[k0 + 2];
