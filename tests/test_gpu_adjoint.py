@@ -312,7 +312,7 @@ def test_adjoint_against_oracle_fd_64x64_200_steps_smooth_friction():
     assert worst[1e-7] <= 1e-6
 
 
-def _config5_target(prec, smooth, nsteps):
+def _calibration_target(prec, smooth, nsteps):
     from paper_2104_06784_amd.sim import Sim
     truth = I.calibration_case(truth=True)
     truth = _smooth(truth) if smooth else truth
@@ -321,7 +321,7 @@ def _config5_target(prec, smooth, nsteps):
     return t.fields()["h"]
 
 
-def test_adjoint_config5_length_directional_fd_fp64():
+def test_adjoint_calibration_full_length_directional_fd_fp64():
     """The calibration workload at full size and length (512^2, 2000 steps,
     checkpoint every 100, smooth friction), FP64: the adjoint's directional
     derivative along a smooth friction field and along the volume scale
@@ -330,7 +330,7 @@ def test_adjoint_config5_length_directional_fd_fp64():
     from paper_2104_06784_amd.sim import Sim
     nsteps = 2000
     prob = _smooth(I.calibration_case())
-    target = _config5_target("f64", True, nsteps)
+    target = _calibration_target("f64", True, nsteps)
     _say("[p12] 512^2 x 2000 FP64: base steps")
     base = Sim(prob, precision="f64")
     dts = np.array([base.step() for _ in range(nsteps)])
@@ -358,7 +358,7 @@ def test_adjoint_config5_length_directional_fd_fp64():
 
 
 @pytest.mark.parametrize("smooth", [False, True])
-def test_adjoint_fp32_against_fp64_config5_length(smooth):
+def test_adjoint_fp32_against_fp64_calibration_full_length(smooth):
     """The calibration workload at full size and length (512^2, 2000 steps,
     checkpoint every 100, 20 recomputed segments): the FP32 adjoint's
     friction gradient against the FP64 adjoint's, cosine >= 0.999 and
@@ -367,7 +367,7 @@ def test_adjoint_fp32_against_fp64_config5_length(smooth):
     from paper_2104_06784_amd.sim import Sim
     nsteps = 2000
     prob = _smooth(I.calibration_case()) if smooth else I.calibration_case()
-    target = _config5_target("f64", smooth, nsteps)
+    target = _calibration_target("f64", smooth, nsteps)
     res = {}
     for prec in ("f64", "f32"):
         g = Sim(prob, precision=prec)
@@ -376,6 +376,6 @@ def test_adjoint_fp32_against_fp64_config5_length(smooth):
     cos = float(np.sum(g32 * g64) / (np.linalg.norm(g32) * np.linalg.norm(g64)))
     rel = float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))
     v64, v32 = res["f64"][2], res["f32"][2]
-    _say(f"[p12] config 5 smooth={smooth}: cosine {cos:.6f} rel L2 {rel:.3e} volume {v32:.6e} vs {v64:.6e}")
+    _say(f"[p12] calibration 512^2 x 2000 smooth={smooth}: cosine {cos:.6f} rel L2 {rel:.3e} volume {v32:.6e} vs {v64:.6e}")
     assert cos >= 0.999 and rel <= 1e-2
     assert abs(v32 - v64) <= 1e-2 * abs(v64)

@@ -739,10 +739,10 @@ def test_fp32_against_fp64_oracle_mode2():
     assert mism <= 0.0017 * max(1, np.sum(ho > 0.01))
 
 
-GOLDEN_CFG2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fractal_hydrograph_1024_5000.npz")
+GOLDEN_FRACTAL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fractal_hydrograph_1024_5000.npz")
 
 
-def test_config2_full_size_against_oracle_fixture():
+def test_fractal_hydrograph_1024_against_oracle_fixture():
     """The fractal-hydrograph workload at full size (1024^2 cells of 5 m, Mode-II
     triangular hydrograph, 5000 steps) against the FP64 oracle's result stored
     by tests/golden/make_fractal_hydrograph_1024.py (written by the oracle
@@ -751,10 +751,10 @@ def test_config2_full_size_against_oracle_fixture():
     relative L1 thickness error <= 1e-3, volume budget closed to 1e-6 with the
     FP64 sums, and the paper's deposit metric (cells above 1 cm that disagree
     <= 0.17 %)."""
-    z = np.load(GOLDEN_CFG2, allow_pickle=False)
+    z = np.load(GOLDEN_FRACTAL, allow_pickle=False)
     diag = dict(zip(z["diag_keys"].tolist(), z["diag_vals"].tolist()))
     prob = I.fractal_hydrograph()
-    _say(f"[cfg2] {prob.nx}^2, 5000 FP64 steps against the oracle fixture (t = {diag['t']:.3f} s)")
+    _say(f"[fractal-hydrograph] {prob.nx}^2, 5000 FP64 steps against the oracle fixture (t = {diag['t']:.3f} s)")
     g = Sim(prob, precision="f64")
     dtg = np.array([g.step() for _ in range(5000)])
     np.testing.assert_allclose(dtg, z["dts"], rtol=1e-12, atol=0)
@@ -765,7 +765,7 @@ def test_config2_full_size_against_oracle_fixture():
     assert abs(d["t"] - diag["t"]) <= 1e-12 * diag["t"]
     for k in ("in_s", "in_f", "out_s", "out_f"):
         assert abs(d[k] - diag[k]) <= 1e-12 * max(abs(diag[k]), diag["in_s"]), k
-    _say("[cfg2] FP32 to the same model time")
+    _say("[fractal-hydrograph] FP32 to the same model time")
     g32 = Sim(prob, precision="f32")
     g32.run_to(diag["t"])
     h32, ho = g32.fields()["h"], z["h"]
