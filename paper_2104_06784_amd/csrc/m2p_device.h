@@ -497,9 +497,9 @@ M2P_FN void face_flux_sel(const Consts<T>& K, int flags, const T uL[NF], const G
 // part of the basal-pressure source takes the matching discrete form.
 
 // Face values (minus, plus side) of eta and of the bed of the middle cell of
-// three along a direction.
+// three along a direction; sbo (if given) receives the bed slope.
 template <typename T>
-M2P_FN void wb_cell(T e0, T e1, T e2, T b0, T b1, T b2, T& em, T& ep, T& bm, T& bp)
+M2P_FN void wb_cell(T e0, T e1, T e2, T b0, T b1, T b2, T& em, T& ep, T& bm, T& bp, T* sbo = nullptr)
 {
     const T se = minmod(e1 - e0, e2 - e1);
     const T sb = minmod(b1 - b0, b2 - b1);
@@ -507,6 +507,18 @@ M2P_FN void wb_cell(T e0, T e1, T e2, T b0, T b1, T b2, T& em, T& ep, T& bm, T& 
     ep = e1 + T(0.5) * se;
     bm = b1 - T(0.5) * sb;
     bp = b1 + T(0.5) * sb;
+    if (sbo) *sbo = sb;
+}
+
+// The difference of a face's two bed values, left minus right, from the two
+// cells' beds bl, br and slopes sl, sr: (bl - br) + (sl + sr) / 2, the bed
+// difference of neighbouring cells formed first (exact in floating point for
+// beds within a factor two of each other), so the FP32 forms keep it to the
+// precision of the slopes rather than of the bed elevation.
+template <typename T>
+M2P_FN T wb_bed_jump(T bl, T br, T sl, T sr)
+{
+    return (bl - br) + T(0.5) * (sl + sr);
 }
 
 // Pressure parts of a side's physical flux (the momentum components of
@@ -540,10 +552,13 @@ M2P_FN void wb_pterm(const Consts<T>& K, const T u[NF], const Geo<T>& g, int d, 
 // A wall face (wallL: the left cell is the ghost; wallR: the right one) takes
 // the ghost side as the mirror image of the edge cell (its face values, c and
 // geometry), so no mass crosses the wall.  Out: the flux H and the corrections
-// cL, cR of the left and right cell.
+// cL, cR of the left and right cell.  The FP32 forms take the bed values'
+// difference dB (wb_bed_jump) instead of the face values, eta* as
+// max(0, eta + min(0, +-dB)) (the same value; the bed elevation never enters
+// a sum with the much smaller eta), and one reciprocal of eps c^2 per side.
 template <typename T>
 M2P_FN void wb_face(const Consts<T>& K, int flags, const T uL[NF], Geo<T> gL, T c2L, const T uR[NF], Geo<T> gR,
-                    T c2R, const T etaL_[2], const T bL_[2], const T etaR_[2], const T bR_[2], bool wallL,
+                    T c2R, const T etaL_[2], const T bL_[2], const T etaR_[2], const T bR_[2], T dB, bool wallL,
                     bool wallR, int d, T H[NF], T cL[NF], T cR[NF])
 {
     // (the flux of the starred states is the one the flags select)
@@ -556,41 +571,72 @@ M2P_FN void wb_face(const Consts<T>& K, int flags, const T uL[NF], Geo<T> gL, T 
         c2R = c2L;
     }
     T sL[NF], sR[NF], dqm[2];
+    if constexpr (Folded<T>::value) {
+        const T rL = T(1) / (K.eps * c2L), rR = T(1) / (K.eps * c2R);
+        const T wd = rL > rR ? rL : rR;
+        const T dBw = (wallL || wallR) ? T(0) : dB;
+        const T dL = dBw < T(0) ? dBw : T(0), dR = dBw > T(0) ? -dBw : T(0);
 #pragma unroll
-    for (int ph = 0; ph < 2; ph++) {
-        T etaL = etaL_[ph], bL = bL_[ph], etaR = etaR_[ph], bR = bR_[ph];
-        if (wallL) {
-            etaL = etaR;
-            bL = bR;
+        for (int ph = 0; ph < 2; ph++) {
+            T etaL = etaL_[ph], etaR = etaR_[ph];
+            if (wallL) etaL = etaR;
+            if (wallR) etaR = etaL;
+            T esL = etaL + dL, esR = etaR + dR;
+            if (esL < T(0)) esL = T(0);
+            if (esR < T(0)) esR = T(0);
+            const int k0 = 3 * ph;
+            const T fL = etaL > T(0) ? esL / etaL : T(0), fR = etaR > T(0) ? esR / etaR : T(0);
+            sL[k0] = esL * rL;
+            sL[k0 + 1] = uL[k0 + 1] * fL;
+            sL[k0 + 2] = uL[k0 + 2] * fL;
+            sR[k0] = esR * rR;
+            sR[k0 + 1] = uR[k0 + 1] * fR;
+            sR[k0 + 2] = uR[k0 + 2] * fR;
+            dqm[ph] = (esR - esL) * wd;
+            cL[k0] = etaL * rL;
+            cL[k0 + 1] = uL[k0 + 1];
+            cL[k0 + 2] = uL[k0 + 2];
+            cR[k0] = etaR * rR;
+            cR[k0 + 1] = uR[k0 + 1];
+            cR[k0 + 2] = uR[k0 + 2];
         }
-        if (wallR) {
-            etaR = etaL;
-            bR = bL;
+    } else {
+#pragma unroll
+        for (int ph = 0; ph < 2; ph++) {
+            T etaL = etaL_[ph], bL = bL_[ph], etaR = etaR_[ph], bR = bR_[ph];
+            if (wallL) {
+                etaL = etaR;
+                bL = bR;
+            }
+            if (wallR) {
+                etaR = etaL;
+                bR = bL;
+            }
+            const T Bs = bL > bR ? bL : bR;
+            T esL = etaL + bL - Bs, esR = etaR + bR - Bs;
+            if (esL < T(0)) esL = T(0);
+            if (esR < T(0)) esR = T(0);
+            const int k0 = 3 * ph;
+            const T mL = etaL / (K.eps * c2L), mR = etaR / (K.eps * c2R);
+            const T msL = esL / (K.eps * c2L), msR = esR / (K.eps * c2R);
+            const T fL = mL > T(0) ? msL / mL : T(0), fR = mR > T(0) ? msR / mR : T(0);
+            sL[k0] = msL;
+            sL[k0 + 1] = uL[k0 + 1] * fL;
+            sL[k0 + 2] = uL[k0 + 2] * fL;
+            sR[k0] = msR;
+            sR[k0 + 1] = uR[k0 + 1] * fR;
+            sR[k0 + 2] = uR[k0 + 2] * fR;
+            // the larger 1 / (eps c^2) of the two sides: each side's diffusion
+            // covers its own flux m* v (no mass leaves a dry cell next to a wet
+            // one on a different slope)
+            dqm[ph] = (esR - esL) * ((c2L < c2R ? T(1) / c2L : T(1) / c2R) / K.eps);
+            cL[k0] = mL;
+            cL[k0 + 1] = uL[k0 + 1];
+            cL[k0 + 2] = uL[k0 + 2];
+            cR[k0] = mR;
+            cR[k0 + 1] = uR[k0 + 1];
+            cR[k0 + 2] = uR[k0 + 2];
         }
-        const T Bs = bL > bR ? bL : bR;
-        T esL = etaL + bL - Bs, esR = etaR + bR - Bs;
-        if (esL < T(0)) esL = T(0);
-        if (esR < T(0)) esR = T(0);
-        const int k0 = 3 * ph;
-        const T mL = etaL / (K.eps * c2L), mR = etaR / (K.eps * c2R);
-        const T msL = esL / (K.eps * c2L), msR = esR / (K.eps * c2R);
-        const T fL = mL > T(0) ? msL / mL : T(0), fR = mR > T(0) ? msR / mR : T(0);
-        sL[k0] = msL;
-        sL[k0 + 1] = uL[k0 + 1] * fL;
-        sL[k0 + 2] = uL[k0 + 2] * fL;
-        sR[k0] = msR;
-        sR[k0 + 1] = uR[k0 + 1] * fR;
-        sR[k0 + 2] = uR[k0 + 2] * fR;
-        // the larger 1 / (eps c^2) of the two sides: each side's diffusion
-        // covers its own flux m* v (no mass leaves a dry cell next to a wet
-        // one on a different slope)
-        dqm[ph] = (esR - esL) * ((c2L < c2R ? T(1) / c2L : T(1) / c2R) / K.eps);
-        cL[k0] = mL;
-        cL[k0 + 1] = uL[k0 + 1];
-        cL[k0 + 2] = uL[k0 + 2];
-        cR[k0] = mR;
-        cR[k0 + 1] = uR[k0 + 1];
-        cR[k0 + 2] = uR[k0 + 2];
     }
     face_flux_sel(K, flags, sL, gL, sR, gR, d, H, T(1), T(1), dqm);
     T PL[NF], PLs[NF], PR[NF], PRs[NF];

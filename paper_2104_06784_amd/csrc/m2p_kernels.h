@@ -223,14 +223,14 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
                     c2[q] = c * c;
                     bb[q] = d == 0 ? V.bv(i - 2 + q, j) : V.bv(i, j - 2 + q);
                 }
-                // face values of the cells p - 1, p, p + 1
-                T em[3][2], ep[3][2], bm[3][2], bp[3][2];
+                // face values (and bed slopes) of the cells p - 1, p, p + 1
+                T em[3][2], ep[3][2], bm[3][2], bp[3][2], sb[3];
                 for (int ph = 0; ph < 2; ph++) {
                     T e[5];
                     for (int q = 0; q < 5; q++) e[q] = K.eps * c2[q] * cs[q][3 * ph];
                     for (int q = 1; q < 4; q++)
                         wb_cell(e[q - 1], e[q], e[q + 1], bb[q - 1], bb[q], bb[q + 1], em[q - 1][ph],
-                                ep[q - 1][ph], bm[q - 1][ph], bp[q - 1][ph]);
+                                ep[q - 1][ph], bm[q - 1][ph], bp[q - 1][ph], &sb[q - 1]);
                 }
                 const Geo<T>& gM = d == 0 ? gW : gS;
                 const Geo<T>& gP = d == 0 ? gE : gN;
@@ -239,13 +239,13 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
                 for (int q = 0; q < 4; q++)
                     for (int k = 0; k < NF; k++) w[q][k] = cs[q][k];
                 reconstruct(w, uL, uR);
-                wb_face(K, P.flags, uL, gM, c2[1], uR, gC, c2[2], ep[0], bp[0], em[1], bm[1], p == 0 && lo,
-                        false, d, Hm, cl, cm);
+                wb_face(K, P.flags, uL, gM, c2[1], uR, gC, c2[2], ep[0], bp[0], em[1], bm[1],
+                        wb_bed_jump(bb[1], bb[2], sb[0], sb[1]), p == 0 && lo, false, d, Hm, cl, cm);
                 for (int q = 0; q < 4; q++)
                     for (int k = 0; k < NF; k++) w[q][k] = cs[q + 1][k];
                 reconstruct(w, uL, uR);
-                wb_face(K, P.flags, uL, gC, c2[2], uR, gP, c2[3], ep[1], bp[1], em[2], bm[2], false,
-                        p + 1 == n && hi, d, Hp, cl, cr);
+                wb_face(K, P.flags, uL, gC, c2[2], uR, gP, c2[3], ep[1], bp[1], em[2], bm[2],
+                        wb_bed_jump(bb[2], bb[3], sb[1], sb[2]), false, p + 1 == n && hi, d, Hp, cl, cr);
                 T* cw = d == 0 ? cxw : cyw;
                 for (int k = 0; k < NF; k++) {
                     cw[k] = cl[k] - cm[k];
@@ -254,8 +254,10 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
                 }
                 for (int ph = 0; ph < 2; ph++) {
                     const T fac = ph == 0 ? T(1) - K.al : T(1);
-                    wbs[2 * ph + d] = -(fac / K.eps) * (T(0.5) * (em[1][ph] + ep[1][ph])) *
-                                      (bp[1][ph] - bm[1][ph]) / (d == 0 ? K.dxi : K.deta);
+                    // (the FP32 forms take the bed slope itself for the face difference)
+                    const T db = Folded<T>::value ? sb[1] : bp[1][ph] - bm[1][ph];
+                    wbs[2 * ph + d] =
+                        -(fac / K.eps) * (T(0.5) * (em[1][ph] + ep[1][ph])) * db / (d == 0 ? K.dxi : K.deta);
                 }
             }
         } else {

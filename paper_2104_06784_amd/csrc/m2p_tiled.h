@@ -110,7 +110,7 @@ struct EPTab {
 // y-face below it (momentum components 1, 2, 4, 5), carried up the march.
 template <typename T>
 struct WBRow {
-    T em[2], ep[2], bm, bp;
+    T em[2], ep[2], bm, bp, sb;  // sb: the bed slope along y
     T cr[4];
 };
 
@@ -122,11 +122,12 @@ __device__ __forceinline__ void wb_row_values(const Consts<T>& K, const T* u0, c
 {
 #pragma unroll
     for (int ph = 0; ph < 2; ph++) {
-        T bm, bp;
+        T bm, bp, sb;
         wb_cell(K.eps * (c0 * c0) * u0[3 * ph], K.eps * (c1 * c1) * u1[3 * ph], K.eps * (c2 * c2) * u2[3 * ph], b0, b1,
-                b2, w.em[ph], w.ep[ph], bm, bp);
+                b2, w.em[ph], w.ep[ph], bm, bp, &sb);
         w.bm = bm;
         w.bp = bp;
+        w.sb = sb;
     }
 }
 
@@ -380,7 +381,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             const T wmb[2] = {wm.bp, wm.bp}, wab[2] = {wa.bm, wa.bm};
             T cl[NF], cr[NF];
             wb_face(K, P.flags, uL, Dm.g, Dm.g.c * Dm.g.c, uR, D0.g, D0.g.c * D0.g.c, wm.ep, wmb, wa.em, wab,
-                    r0 == 0 && P.bc[2] == 1, false, 1, Hy, cl, cr);
+                    wb_bed_jump(bm1, b0, wm.sb, wa.sb), r0 == 0 && P.bc[2] == 1, false, 1, Hy, cl, cr);
             wa.cr[0] = cr[1];
             wa.cr[1] = cr[2];
             wa.cr[2] = cr[4];
@@ -460,8 +461,8 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             wb_row_values(K, Uc, Un1, U2, D0.g.c, D1.g.c, cj2, bj, bj1, bj2, w1);
             const T w0b[2] = {w0.bp, w0.bp}, w1b[2] = {w1.bm, w1.bm};
             T cl[NF], cr[NF];
-            wb_face(K, P.flags, uL, D0.g, D0.g.c * D0.g.c, uR, D1.g, D1.g.c * D1.g.c, w0.ep, w0b, w1.em, w1b, false,
-                    j + 1 == P.ny && P.bc[3] == 1, 1, HyN, cl, cr);
+            wb_face(K, P.flags, uL, D0.g, D0.g.c * D0.g.c, uR, D1.g, D1.g.c * D1.g.c, w0.ep, w0b, w1.em, w1b,
+                    wb_bed_jump(bj, bj1, w0.sb, w1.sb), false, j + 1 == P.ny && P.bc[3] == 1, 1, HyN, cl, cr);
             cy[0] = T(0);
             cy[1] = cl[1] - w0.cr[0];
             cy[2] = cl[2] - w0.cr[1];
@@ -521,17 +522,18 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
                 const T cx = col <= -2 ? cE : (col >= P.nx + 1 ? cW : D0.cx);
                 const T c2x = cx * cx;
                 const T bE = from_right(bj), bW = from_left(bj);
-                T em[2], ep[2], bm[2], bp[2], emR[2], bmR[2];
+                T em[2], ep[2], bm[2], bp[2], emR[2], bmR[2], sb = T(0);
 #pragma unroll
                 for (int ph = 0; ph < 2; ph++) {
                     const T e = K.eps * c2x * Uc[3 * ph];
-                    wb_cell(from_left(e), e, from_right(e), bW, bj, bE, em[ph], ep[ph], bm[ph], bp[ph]);
+                    wb_cell(from_left(e), e, from_right(e), bW, bj, bE, em[ph], ep[ph], bm[ph], bp[ph], &sb);
                     emR[ph] = from_right(em[ph]);
                     bmR[ph] = from_right(bm[ph]);
                 }
                 T cl[NF], cr[NF];
                 wb_face(K, P.flags, um, D0.g, c2x, upR, gR, from_right(c2x), ep, bp, emR, bmR,
-                        col == -1 && P.bc[0] == 1, col + 1 == P.nx && P.bc[1] == 1, 0, Hx, cl, cr);
+                        wb_bed_jump(bj, bE, sb, from_right(sb)), col == -1 && P.bc[0] == 1,
+                        col + 1 == P.nx && P.bc[1] == 1, 0, Hx, cl, cr);
                 cxw[0] = T(0);
                 cxw[3] = T(0);
 #pragma unroll
@@ -540,8 +542,11 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
 #pragma unroll
                 for (int ph = 0; ph < 2; ph++) {
                     const T fac = ph == 0 ? T(1) - K.al : T(1);
-                    wbs[2 * ph] = -(fac / K.eps) * (T(0.5) * (em[ph] + ep[ph])) * (bp[ph] - bm[ph]) / K.dxi;
-                    wbs[2 * ph + 1] = -(fac / K.eps) * (T(0.5) * (w0.em[ph] + w0.ep[ph])) * (w0.bp - w0.bm) / K.deta;
+                    // (the FP32 forms take the bed slopes themselves for the face differences)
+                    const T dbx = Folded<T>::value ? sb : bp[ph] - bm[ph];
+                    const T dby = Folded<T>::value ? w0.sb : w0.bp - w0.bm;
+                    wbs[2 * ph] = -(fac / K.eps) * (T(0.5) * (em[ph] + ep[ph])) * dbx / K.dxi;
+                    wbs[2 * ph + 1] = -(fac / K.eps) * (T(0.5) * (w0.em[ph] + w0.ep[ph])) * dby / K.deta;
                 }
             } else {
                 central_flux<T, H2, CU>(K, um, D0.g, upR, gR, 0, Hx, kL, kR);
