@@ -183,7 +183,12 @@ __device__ __forceinline__ void visc_yface_rows(const RowD<T>& a, const RowD<T>&
 #define M2P_TILED_WPE_S2 3
 #endif
 // The earth-pressure instance carries the coefficients of three rows
-// besides: two waves, no spills.
+// besides: its first stage at three waves (4 VGPRs spilled, 4 % faster per
+// step than at two), the later stages at two (at three they spill 15 and run
+// 8 % slower).
+#ifndef M2P_TILED_WPE_EP1
+#define M2P_TILED_WPE_EP1 3
+#endif
 #ifndef M2P_TILED_WPE_EP
 #define M2P_TILED_WPE_EP 2
 #endif
@@ -195,9 +200,11 @@ __device__ __forceinline__ void visc_yface_rows(const RowD<T>& a, const RowD<T>&
 template <typename T, int STAGE, bool EP = false, bool WB = false>
 constexpr int tiled_wpe()
 {
-    return sizeof(T) == 4 ? (WB ? M2P_TILED_WPE_WB
-                                : (EP ? M2P_TILED_WPE_EP : (STAGE == 1 ? M2P_TILED_WPE_S1 : M2P_TILED_WPE_S2)))
-                          : 1;
+    return sizeof(T) == 4
+               ? (WB ? M2P_TILED_WPE_WB
+                     : (EP ? (STAGE == 1 ? M2P_TILED_WPE_EP1 : M2P_TILED_WPE_EP)
+                           : (STAGE == 1 ? M2P_TILED_WPE_S1 : M2P_TILED_WPE_S2)))
+               : 1;
 }
 
 // Partials of one wavefront's share of a stage: speed maxima (last stage),
