@@ -183,14 +183,12 @@ __device__ __forceinline__ void visc_yface_rows(const RowD<T>& a, const RowD<T>&
 #define M2P_TILED_WPE_S2 3
 #endif
 // The earth-pressure instance carries the coefficients of three rows
-// besides: its first stage at three waves (4 VGPRs spilled, 4 % faster per
-// step than at two), the later stages at two (at three they spill 15 and run
-// 8 % slower).
-#ifndef M2P_TILED_WPE_EP1
-#define M2P_TILED_WPE_EP1 3
-#endif
+// besides; it fits three waves (its last stages with 6 VGPRs spilled, 9 %
+// faster per step than at two waves) because its march reads the cell's own
+// U^n just before the update and prefetches row j + 3 after the row's stores
+// (both held across the whole row otherwise).
 #ifndef M2P_TILED_WPE_EP
-#define M2P_TILED_WPE_EP 2
+#define M2P_TILED_WPE_EP 3
 #endif
 // The well-balanced instance carries the face values and corrections of the
 // hydrostatic reconstruction besides: two waves.
@@ -202,8 +200,7 @@ constexpr int tiled_wpe()
 {
     return sizeof(T) == 4
                ? (WB ? M2P_TILED_WPE_WB
-                     : (EP ? (STAGE == 1 ? M2P_TILED_WPE_EP1 : M2P_TILED_WPE_EP)
-                           : (STAGE == 1 ? M2P_TILED_WPE_S1 : M2P_TILED_WPE_S2)))
+                     : (EP ? M2P_TILED_WPE_EP : (STAGE == 1 ? M2P_TILED_WPE_S1 : M2P_TILED_WPE_S2)))
                : 1;
 }
 
@@ -432,13 +429,17 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
                    RowD<T>& D1, T* sy0, T* sy1, T* Hy, T* HyN, T vGX, T vGY, T& vGXN, T& vGYN, WBRow<T>& w0,
                    WBRow<T>& w1) __attribute__((always_inline)) {
         // ---- prefetch row j+3 (consumed next iteration) and this row's own
-        // values needed at the end (U^n for the Heun average, tan delta)
+        // values needed at the end (U^n for the Heun average, tan delta);
+        // the earth-pressure instance reads them where they are used instead
+        // (fewer registers held across the row: it then fits three waves)
         const int rn = j + 3 <= P.ny + 1 ? j + 3 : P.ny + 1;
-        loadU(rn, U3);
-        bj3 = loadB(rn);
+        if (!EP) {
+            loadU(rn, U3);
+            bj3 = loadB(rn);
+        }
         const size_t cself = (size_t)j * P.pitch + (out_lane ? col : 0);
         T unr[NF];
-        if (STAGE > 1) {
+        auto load_un = [&]() {
 #pragma unroll
             for (int k = 0; k < NF; k++) {
                 if constexpr (BUF)
@@ -446,7 +447,8 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
                 else
                     unr[k] = Un[k * fs + cself];
             }
-        }
+        };
+        if (STAGE > 1 && !EP) load_un();
         const T tmu = P.has_mu ? mu[cself] : K.tan_d;
         make_row<T, EP>(K, Un1, bj1, bj, bj2, D1, Uc, U2, c2, EP && !uni ? tmu_row(j + 1) : T(0), uni, &tab);
         wb_cx(j + 1, bj1, bj, bj2, D1);
@@ -619,6 +621,7 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
             clamps += update_cell<T, H2, false>(K, Uc, D0.g, HxL, Hx, Hy, HyN, Sr, svx, svy, dt, tmu, out,
                                                 WB ? cxw : nullptr, WB ? cy : nullptr);
             if (STAGE > 1) {
+                if (EP) load_un();
 #pragma unroll
                 for (int k = 0; k < NF; k++) out[k] = stage_combine<STAGE>(unr[k], out[k]);
             }
@@ -638,6 +641,10 @@ __device__ __forceinline__ WavePart stage_tiled_wave(const KParams& P, const T* 
                 else
                     Uout[k * fs + cself] = out[k];
             }
+        }
+        if (EP) {
+            loadU(rn, U3);
+            bj3 = loadB(rn);
         }
     };
 
