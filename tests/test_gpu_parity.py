@@ -105,21 +105,22 @@ def test_tile_heights_bitwise_equal_reference_fp64(rows):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("opt", ["plain", "cu", "ep", "state", "rk3"])
+@pytest.mark.parametrize("opt", ["plain", "cu", "ep", "state", "rk3", "wb"])
 def test_global_addressing_equals_buffer_accesses(precision, opt):
     """The tiled kernel's raw buffer accesses (grids whose state and DEM stay
     below 2 GiB) and its 64-bit global-address instances (larger grids,
     forced with M2P_VARIANT_TILED_GLOBAL) give the same bits: state, dt and
     diagnostics, on a ragged grid with walls and transmissive sides, with the
-    central-upwind flux, earth pressure, a Mode-II state segment or the
-    three-stage method (stage kinds 1, 3, 4)."""
+    central-upwind flux, earth pressure, a Mode-II state segment, the
+    three-stage method (stage kinds 1, 3, 4) or the well-balanced option."""
     import dataclasses
 
     from paper_2104_06784_amd._abi import M2P_VARIANT_TILED, M2P_VARIANT_TILED_GLOBAL
     n_x, n_y, dx = 131, 77, 10.0
     dem = I.fractal_dem(n_x, dx, 83, 60.0, tilt_deg=15.0, ny=n_y)
     h = I.cylinder(n_x, n_y, dx, dx, 500.0, 380.0, 200.0, 8.0)
-    flags = {"plain": 0, "cu": I.F_CENTRAL_UPWIND, "ep": I.F_EARTH_PRESSURE, "state": 0, "rk3": I.F_RK3}[opt]
+    flags = {"plain": 0, "cu": I.F_CENTRAL_UPWIND, "ep": I.F_EARTH_PRESSURE, "state": 0, "rk3": I.F_RK3,
+             "wb": I.F_WELL_BALANCED}[opt]
     p = I.Params(delta_b_deg=18.0, cfl=0.2, bc=(0, 1, 1, 0), flags=flags, delta_int_deg=35.0)
     prob = I.Problem("addr", n_x, n_y, dx, dx, p, dem, h, np.where(h > 0, 0.5, 0.0), [])
     runs = []
