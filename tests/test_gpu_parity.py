@@ -693,6 +693,26 @@ def test_graph_replay_equals_direct_launches(precision, rk3):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_graph_replay_well_balanced(precision):
+    """The well-balanced instances replayed from HIP graphs (chunks of 7)
+    equal kernel-by-kernel launches bitwise, through run and run_to, on the
+    plane-bump-pile release."""
+    import torch
+    prob = _wb(I.plane_bump_pile(n=96), cfl=0.25)
+    res = []
+    for chunk in (7, 0):
+        st = torch.cuda.Stream()
+        g = Sim(prob, precision=precision, stream=st)
+        g.set_graph(chunk)
+        g.run(23)
+        a = g.state()
+        g.run_to(2.0)
+        res.append((a, g.state(), g.diag()["steps"]))
+    for x, y in zip(res[0], res[1]):
+        assert np.array_equal(x, y)
+
+
 def test_vertical_and_normal_thickness_inputs_agree():
     prob = I.plane_bump_pile(n=32)
     a = Sim(prob, precision="f64")
