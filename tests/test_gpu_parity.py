@@ -532,6 +532,19 @@ def test_well_balanced_option_fp64(variant):
         assert np.abs(Ug[3] - U0[3]).max() <= 1e-13 * U0[3].max()
 
 
+def test_well_balanced_with_smooth_friction_fp64():
+    """The well-balanced option with the smooth friction of gradient checks
+    (a combination the reference kernel runs) equals the oracle to 1e-12 on
+    the plane-bump-pile release with a friction field."""
+    import dataclasses
+    prob = I.plane_bump_pile(n=64)
+    prob = dataclasses.replace(prob, params=dataclasses.replace(
+        prob.params, flags=I.F_WELL_BALANCED | I.F_SMOOTH_FRICTION, v_eps=0.05, cfl=0.25))
+    prob.tan_mu = np.tan(np.radians(20.0 + 3.0 * I.smooth_field(64, 8, 4.0)))
+    prob.name = "plane-bump-pile-wb-smooth"
+    _compare_steps(prob, 150, 1e-12, variant=2)
+
+
 @pytest.mark.parametrize("rows", [1, 2, 3, 7, 45])
 def test_well_balanced_tiled_bitwise_equal_reference(rows):
     """The tiled kernel's well-balanced instance at any tile height equals the
