@@ -48,7 +48,7 @@ typedef struct {
                       bit 2: central-upwind face flux (one-sided local speeds);
                       bit 3: Savage-Hutter earth-pressure coefficients on the solid pressure;
                       bit 4: smooth Coulomb friction with regularisation speed v_eps;
-                      bit 5: well-balanced hydrostatic reconstruction (Mode-I only) */
+                      bit 5: well-balanced hydrostatic reconstruction (Mode-II inflow only as ghost states) */
     double delta_int_deg; /* internal friction angle (used with bit 3) */
     double v_eps;         /* m/s (used with bit 4) */
 } ora_params;
@@ -321,7 +321,9 @@ void ora_set_time(ora_sim *o, double t_si) { o->t = t_si / o->T; }
 
 int ora_set_inflow(ora_sim *o, const ora_inflow_in *in, int n)
 {
-    if ((o->p.flags & 32) && n > 0) return -1; /* the well-balanced option is Mode-I only */
+    /* the well-balanced option takes Mode-II inflow as ghost states only (a
+     * prescribed face flux has no reconstructed state to balance) */
+    if ((o->p.flags & 32) && n > 0) return -1;
     o->seg = (inflow_seg *)xcalloc((size_t)n, sizeof(inflow_seg));
     o->nseg = n;
     for (int k = 0; k < n; k++) {
@@ -343,7 +345,6 @@ int ora_set_inflow(ora_sim *o, const ora_inflow_in *in, int n)
  * must not share a boundary cell with a flux-inflow segment or each other. */
 int ora_set_inflow_states(ora_sim *o, const ora_state_in *in, int n)
 {
-    if ((o->p.flags & 32) && n > 0) return -1; /* the well-balanced option is Mode-I only */
     for (int k = 0; k < o->nsseg; k++) { free(o->sseg[k].t); free(o->sseg[k].h); free(o->sseg[k].phi); free(o->sseg[k].v); }
     free(o->sseg);
     o->sseg = (state_seg *)xcalloc((size_t)n, sizeof(state_seg));
@@ -791,6 +792,14 @@ static void hr_pterm(const ora_sim *o, const double u[NF], const geo_t *g, int d
     P[5] = eps * g->J * h * Ay * pf;
 }
 
+/* 1 if a state-inflow segment covers boundary index k of a side */
+static int hr_segment_at(const ora_sim *o, int side, int k)
+{
+    for (int s = 0; s < o->nsseg; s++)
+        if (o->sseg[s].side == side && k >= o->sseg[s].i0 && k < o->sseg[s].i0 + o->sseg[s].ncells) return 1;
+    return 0;
+}
+
 /* Well-balanced face (i, j) + 1/2 along d: starred states, flux H and the
  * corrections cL, cR of the left and right cell. */
 static void hr_face(ora_sim *o, int i, int j, int d, const double uL[NF], const double uR[NF], double H[NF],
@@ -801,9 +810,11 @@ static void hr_face(ora_sim *o, int i, int j, int d, const double uL[NF], const 
     double c2L = hr_c2(o, i, j, d), c2R = hr_c2(o, i + di, j + dj, d);
     /* a wall face: the ghost side mirrors the edge cell (its face values of
      * eta and the bed, its c and geometry), so no mass crosses the wall and a
-     * lake at rest stays at rest against it */
-    int p = d == 0 ? i : j, n = d == 0 ? o->nx : o->ny;
-    int wallL = p == -1 && o->p.bc[2 * d] == 1, wallR = p + 1 == n && o->p.bc[2 * d + 1] == 1;
+     * lake at rest stays at rest against it; not where a state-inflow segment
+     * holds the ghost cells */
+    int p = d == 0 ? i : j, n = d == 0 ? o->nx : o->ny, kb = d == 0 ? j : i;
+    int wallL = p == -1 && o->p.bc[2 * d] == 1 && !hr_segment_at(o, 2 * d, kb);
+    int wallR = p + 1 == n && o->p.bc[2 * d + 1] == 1 && !hr_segment_at(o, 2 * d + 1, kb);
     if (wallL) {
         gL = gR;
         c2L = c2R;

@@ -1237,8 +1237,38 @@ def test_well_balanced_ritter_convergence():
     assert orders[-1] >= 0.8 and orders[-2] >= 0.8
 
 
-def test_well_balanced_is_mode_one_only_and_not_with_earth_pressure():
-    """The option refuses inflow segments and the earth-pressure option."""
+def test_well_balanced_state_inflow_uniform_flow_and_wall_segment():
+    """Mode-II inflow as ghost states with the well-balanced option: a uniform
+    supercritical flow on a flat bed fed through the whole W side stays uniform
+    to 1e-14; and on a tilted bed closed by walls, a segment on the W wall
+    feeds the domain (the wall mirror is not applied at the segment's faces)
+    while each phase's volume equals minus the outflow integral to 1e-12."""
+    n, dx, h, phi, v = 24, 10.0, 2.0, 0.4, 20.0
+    p = I.Params(delta_b_deg=0.0, inv_n_r=0.0, theta_b=0.0, c_d=0.0, cfl=0.25, bc=(0, 0, 0, 0),
+                 flags=I.F_WELL_BALANCED)
+    full = lambda x: np.full((n, n), x)
+    prob = I.Problem("uniform-wb", n, n, dx, dx, p, np.zeros((n, n)), full(h), full(phi),
+                     vel=(full(v), full(0.0), full(v), full(0.0)), inflow_states=[_state_seg(0, 0, n, h, phi, v)])
+    s = _sim(prob)
+    U0 = s.state()
+    s.run(40)
+    assert np.max(np.abs(s.state() - U0)) <= 1e-14 * np.max(np.abs(U0))
+    m, dx = 40, 10.0
+    dem = I.plane_dem(m, m, dx, dx, 8.0)
+    pw = I.Params(cfl=0.25, bc=(1, 1, 1, 1), flags=I.F_WELL_BALANCED)
+    segs = [_state_seg(0, 12, 9, [0.0, 3.0, 1.0], 0.5, [4.0, 8.0, 2.0], t=(0.0, 20.0, 60.0))]
+    prob = I.Problem("wall-seg", m, m, dx, dx, pw, dem, np.zeros((m, m)), np.zeros((m, m)), inflow_states=segs)
+    s = _sim(prob)
+    s.run(300)
+    d = s.diag()
+    assert d["mass_s"] > 0 and d["mass_f"] > 0 and d["clamps"] == 0
+    assert abs(d["mass_s"] + d["out_s"]) <= 1e-12 * d["mass_s"]
+    assert abs(d["mass_f"] + d["out_f"]) <= 1e-12 * d["mass_f"]
+
+
+def test_well_balanced_refuses_discharge_segments_and_earth_pressure():
+    """The option refuses discharge-inflow segments (a prescribed face flux
+    has no reconstructed state to balance) and the earth-pressure option."""
     import oracle
     prob, _ = lake()
     s = _sim(prob)
