@@ -98,12 +98,13 @@ extern "C" {
                        unstarred minus its starred face state; the hydrostatic part of the basal-pressure source
                        becomes -(fac / eps) (mean face eta) (bed face difference) / step (fac = 1 - alpha for the
                        solid, 1 for the fluid).  A wall face mirrors the edge cell.  Keeps a lake at rest on beds
-                       that vary in one direction and the model's other states to the scheme's order; Mode-I
-                       releases on single-scenario contexts, both kernel variants (the tiled kernel has its own
-                       instance, FP64 results bitwise equal to the reference kernel's); with either face flux;
-                       not with M2P_F_EARTH_PRESSURE, ensembles, the tangent and adjoint calls (m2p_create
-                       returns M2P_EINVAL for the combination, m2p_set_inflow and m2p_set_inflow_states for
-                       segments) */
+                       that vary in one direction and the model's other states to the scheme's order;
+                       single-scenario contexts, both kernel variants (the tiled kernel has its own instance,
+                       FP64 results bitwise equal to the reference kernel's; with state-inflow segments the
+                       reference kernel runs); with either face flux; Mode-II inflow only as state segments
+                       (m2p_set_inflow_states; a wall face that a segment covers is not mirrored): m2p_set_inflow
+                       returns M2P_EINVAL for discharge segments; not with M2P_F_EARTH_PRESSURE, ensembles, the
+                       tangent and adjoint calls (m2p_create returns M2P_EINVAL for the combination) */
 
 /* thickness convention of m2p_set_state */
 #define M2P_DEPTH_NORMAL 0   /* h measured normal to the bed (the paper's h, Sect. 2.1) */

@@ -192,10 +192,12 @@ Shape make_shape(const KParams& P, int variant, int rows, int slots)
 {
     Shape s{};
     // the smooth-friction option, and earth pressure with the central-upwind
-    // flux or with Mode-II state segments, run on the reference kernel
+    // flux or with Mode-II state segments, and the well-balanced option with
+    // state segments, run on the reference kernel
     const bool ep_ref =
         (P.flags & kFlagEarthPressure) && ((P.flags & kFlagCentralUpwind) || P.nsseg > 0);
-    s.variant = (variant == M2P_VARIANT_REFERENCE || (P.flags & kFlagSmoothFriction) || ep_ref) ? 1 : 2;
+    const bool wb_ref = (P.flags & kFlagWellBalanced) && P.nsseg > 0;
+    s.variant = (variant == M2P_VARIANT_REFERENCE || (P.flags & kFlagSmoothFriction) || ep_ref || wb_ref) ? 1 : 2;
     s.global_addr = variant == M2P_VARIANT_TILED_GLOBAL;
     s.nbx = (P.nx + 63) / 64;
     s.nby = (P.ny + 3) / 4;
@@ -757,7 +759,7 @@ int m2p_set_inflow(m2p_ctx* c, const m2p_inflow* seg, int32_t nseg)
     if (nseg > 0 && (c->kp.flags & M2P_F_EARTH_PRESSURE))
         return fail(M2P_EINVAL, "the earth-pressure option runs Mode-I releases only");
     if (nseg > 0 && (c->kp.flags & M2P_F_WELL_BALANCED))
-        return fail(M2P_EINVAL, "the well-balanced option runs Mode-I releases only");
+        return fail(M2P_EINVAL, "the well-balanced option takes Mode-II inflow as state segments only");
     if (nseg < 0 || nseg > MAX_SEG) return fail(M2P_EINVAL, "0..8 inflow segments supported");
     std::vector<double> tab;
     SegDesc sd[MAX_SEG];
@@ -795,8 +797,6 @@ int m2p_set_inflow_states(m2p_ctx* c, const m2p_inflow_state* seg, int32_t nseg)
     if (!c || (nseg > 0 && !seg)) return fail(M2P_EINVAL, "NULL argument");
     if (nseg > 0 && (c->kp.flags & M2P_F_EARTH_PRESSURE))
         return fail(M2P_EINVAL, "the earth-pressure option runs Mode-I releases only");
-    if (nseg > 0 && (c->kp.flags & M2P_F_WELL_BALANCED))
-        return fail(M2P_EINVAL, "the well-balanced option runs Mode-I releases only");
     if (nseg < 0 || nseg > MAX_SEG) return fail(M2P_EINVAL, "0..8 inflow state segments supported");
     std::vector<double> tab;
     SegDesc sd[MAX_SEG];
@@ -831,6 +831,10 @@ int m2p_set_inflow_states(m2p_ctx* c, const m2p_inflow_state* seg, int32_t nseg)
     }
     K.nsseg = nseg;
     c->tab_state = tab;
+    // the kernel variant depends on whether state segments exist (options
+    // that run them on the reference kernel)
+    refresh_grid(c);
+    if (int rc = ensure_wpart(c)) return rc;
     return upload_tables(c);
 }
 

@@ -234,7 +234,10 @@ __global__ void __launch_bounds__(256) k_stage_ref(KParams P, const T* __restric
                 }
                 const Geo<T>& gM = d == 0 ? gW : gS;
                 const Geo<T>& gP = d == 0 ? gE : gN;
-                const int lo = P.bc[2 * d] == 1, hi = P.bc[2 * d + 1] == 1;
+                // wall faces (not where a state-inflow segment holds the ghost cells)
+                const int kb = d == 0 ? j : i;
+                const bool lo = P.bc[2 * d] == 1 && state_seg_at(P, 2 * d, kb) < 0;
+                const bool hi = P.bc[2 * d + 1] == 1 && state_seg_at(P, 2 * d + 1, kb) < 0;
                 T Hm[NF], Hp[NF], cl[NF], cr[NF], cm[NF];
                 for (int q = 0; q < 4; q++)
                     for (int k = 0; k < NF; k++) w[q][k] = cs[q][k];

@@ -532,6 +532,40 @@ def test_well_balanced_option_fp64(variant):
         assert np.abs(Ug[3] - U0[3]).max() <= 1e-13 * U0[3].max()
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_well_balanced_with_state_inflow(precision):
+    """The well-balanced option with Mode-II inflow as ghost states (the
+    state-inflow problem without its discharge segment: segments on the W wall,
+    the N and the E side), any kernel variant request running the reference
+    kernel: FP64 equal to the oracle to 1e-12 (state, dt, boundary integrals)
+    over 120 steps; FP32 over 60 steps within the FP32 tolerances, volume
+    budget closed (on this two-phase release over rough relief the option's
+    time step collapses within about a second of model time, so the FP32
+    comparison stays at the start)."""
+    import dataclasses
+    prob = _state_inflow_problem()
+    prob = dataclasses.replace(prob, inflows=[],
+                               params=dataclasses.replace(prob.params, flags=I.F_WELL_BALANCED))
+    prob.name = "state-inflow-wb"
+    if precision == "f64":
+        g, o = _compare_steps(prob, 120, 1e-12, variant=2)
+        dg, do = g.diag(), o.diag()
+        for k in ("mass_s", "mass_f", "out_s", "out_f"):
+            assert abs(dg[k] - do[k]) <= 1e-12 * max(abs(do[k]), 1.0), k
+        return
+    g, o = Sim(prob, precision="f32", variant=2), Ora(prob)
+    g.run(60)
+    o.run(60)
+    hg, ho = g.fields()["h"], o.fields()["h"]
+    l1 = np.abs(hg - ho).sum() / ho.sum()
+    d = g.diag()
+    m0 = float(np.sum(prob.h_vert)) * prob.dx * prob.dy
+    bud = abs(d["mass_s"] + d["mass_f"] + d["out_s"] + d["out_f"] - m0) / m0
+    _say(f"[parity] well-balanced state inflow FP32: rel L1 {l1:.3e}, budget {bud:.3e}, "
+         f"t {d['t']:.4f} vs {o.diag()['t']:.4f}")
+    assert l1 <= 1e-3 and bud <= 1e-6
+
+
 def test_well_balanced_with_smooth_friction_fp64():
     """The well-balanced option with the smooth friction of gradient checks
     (a combination the reference kernel runs) equals the oracle to 1e-12 on
@@ -585,7 +619,8 @@ def test_well_balanced_fp32_and_refusals():
     within the FP32 tolerance of the FP64 oracle with its volume kept to 1e-6,
     and a lake at rest that stays at rest to FP32 rounding (velocities below
     1e-5 of the lake's wave speed after 200 steps); the option refuses earth
-    pressure, inflow segments, the tangent and adjoint calls and ensembles."""
+    pressure, discharge-inflow segments, the tangent and adjoint calls and
+    ensembles."""
     import dataclasses
 
     from wb_lake import lake
@@ -617,7 +652,6 @@ def test_well_balanced_fp32_and_refusals():
     z = np.zeros((6, q.ny, q.nx))
     for call in (lambda: Sim(bad, precision="f32"),
                  lambda: g.set_inflow([I.Inflow(I.SIDE_S, 20, 7, t, Q, ph)]),
-                 lambda: g.set_inflow_states([I.InflowState(I.SIDE_S, 20, 7, t, 2.0 + 0 * t, ph, 1.0 + 0 * t)]),
                  lambda: g.adjoint_run(4, 2, np.zeros((q.ny, q.nx))), lambda: g.stage_jvp(z),
                  lambda: g.stage_vjp(z), lambda: Batch([q, q], precision="f32")):
         with pytest.raises(M2PError) as e:
